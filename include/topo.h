@@ -1,0 +1,204 @@
+/*
+ * topo.h -- C ABI of libtopo: the per-iteration hot path of 3D SIMP compliance
+ * minimisation on a structured grid of 8-node trilinear hexahedra (PyTopo3D,
+ * arXiv 2504.05604), implemented with hand-written HIP kernels for gfx950.
+ *
+ * Problem statement (paper, Finite Element Analysis / Optimality Criteria /
+ * Sensitivity Filtering sections): a nelx x nely x nelz grid of unit hexahedra,
+ * element moduli E_e = Emin + rho_e^p (E0 - Emin) (modified SIMP), equilibrium
+ * K(E) u = f with fixed displacements applied by elimination, compliance
+ * c = f^T u, element sensitivities, a cone-weight filter of radius rmin, and an
+ * Optimality Criteria update with move limits under a volume fraction that
+ * excludes passive (obstacle) elements.
+ *
+ * Numbering (the paper leaves it open):
+ *   element e = i + nelx*(j + nely*k),
+ *   node    n = i + (nelx+1)*(j + (nely+1)*k),
+ *   dof       = 3*n + c  (c = 0,1,2 for x,y,z; node-interleaved "AoS").
+ * Local element node order: (0,0,0),(1,0,0),(1,1,0),(0,1,0),(0,0,1),(1,0,1),
+ * (1,1,1),(0,1,1).
+ *
+ * Pointers: arguments named d_* are DEVICE pointers owned by the caller
+ * (contiguous FP64 arrays of the stated length, allocated on the device the
+ * context was created on); h_* are HOST pointers.  topo_setup copies every host
+ * array it is given; the context owns all its device workspaces.
+ *
+ * Streams and threads: every call enqueues its work on the stream given to
+ * topo_setup (NULL = the default stream) and returns after enqueueing, except
+ * calls that write h_* outputs, which synchronise that stream.  A context must
+ * not be used from two threads at once.
+ *
+ * Errors: no call aborts or throws; a non-OK status leaves a message retrievable
+ * with topo_last_error() (thread-local).  Argument validation happens before
+ * any device work.
+ */
+#ifndef TOPO_H
+#define TOPO_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct topo_ctx topo_ctx; /* opaque, library-owned */
+
+typedef enum {
+  TOPO_OK = 0,
+  TOPO_EINVAL = 1,          /* invalid argument or problem definition        */
+  TOPO_ENOMEM = 2,          /* device allocation failed                      */
+  TOPO_EDEVICE = 3,         /* HIP runtime error                             */
+  TOPO_ENOTCONVERGED = 4,   /* solver hit max_iters; outputs hold last iterate */
+  TOPO_EUNSUPPORTED = 5     /* option combination not implemented            */
+} topo_status;
+
+/* filter modes (Sensitivity Filtering section) */
+enum { TOPO_FILTER_DENSITY = 0, TOPO_FILTER_SENSITIVITY = 1 };
+/* filter operations for topo_filter */
+enum {
+  TOPO_FILTER_FWD = 0,  /* out = (H in)/Hs, passive elements reset to 0 (void) / 1 (solid) */
+  TOPO_FILTER_ADJ = 1,  /* out = H (in_D / Hs): in restricted to design elements          */
+  TOPO_FILTER_SENS = 2, /* out = H (aux * in) / (Hs * max(1e-3, aux)); aux = x             */
+  TOPO_FILTER_VOLW = 3  /* out = H (1_D / Hs): filtered volume weights (in, aux unused)    */
+};
+/* internal precision of the operator and preconditioner (vectors stay FP64) */
+enum { TOPO_PREC_FP64 = 0, TOPO_PREC_FP32 = 1, TOPO_PREC_BF16 = 2 };
+/* preconditioner of the conjugate-gradient solve */
+enum { TOPO_PRECOND_JACOBI = 0, TOPO_PRECOND_MG = 1 };
+
+/* Problem definition; all arrays are host arrays copied by topo_setup. */
+typedef struct {
+  int32_t nelx, nely, nelz;   /* elements per axis, each >= 1                        */
+  double E0, Emin;            /* solid and void moduli, E0 > Emin > 0                */
+  double nu;                  /* Poisson ratio, -1 < nu < 0.5                        */
+  double penal;               /* SIMP penalty p >= 1                                 */
+  double rmin;                /* filter radius in element units, > 0                 */
+  double volfrac;             /* volume fraction of the design elements, (0, 1]      */
+  double move;                /* OC move limit, > 0                                  */
+  double eta;                 /* OC damping exponent, > 0                            */
+  int32_t filter;             /* TOPO_FILTER_DENSITY | TOPO_FILTER_SENSITIVITY       */
+  const int8_t *mask;         /* nel entries: 0 design, 1 void, 2 solid; NULL = all design */
+  const int64_t *fixed_dofs;  /* n_fixed constrained dofs (homogeneous), any order   */
+  int64_t n_fixed;
+  const double *f;            /* ndof nodal loads; entries on fixed dofs are ignored */
+} topo_problem;
+
+/* Solver options; topo_default_opts fills every field. */
+typedef struct {
+  int32_t precision;          /* TOPO_PREC_*                                          */
+  int32_t precond;            /* TOPO_PRECOND_*                                       */
+  int32_t mg_levels;          /* 0 = automatic (coarsest <= mg_max_coarse_dof)         */
+  int32_t mg_max_coarse_dof;  /* automatic depth: stop coarsening at or below this     */
+  int32_t cheb_degree;        /* Chebyshev smoother degree per pre/post smoothing      */
+  double rtol;                /* stop when ||r||_2 <= rtol ||f||_2 (free dofs)         */
+  int32_t max_iters;          /* CG iteration cap per solve                           */
+  int32_t warm_start;         /* topo_iterate: start each solve from the last u        */
+  double oc_tol;              /* relative width of the final multiplier bracket        */
+  int32_t check_every;        /* host convergence check every k CG iterations          */
+} topo_opts;
+
+typedef struct {
+  int32_t iters;       /* CG iterations taken                        */
+  int32_t converged;   /* 1 if relres <= rtol                        */
+  double relres;       /* ||f - K u|| / ||f|| (recursive residual)   */
+  double ms;           /* wall time of the solve on the stream       */
+} topo_solve_stats;
+
+typedef struct {
+  double c;            /* compliance f^T u                                      */
+  double volume;       /* design-element sum of the physical density after update */
+  double change;       /* max |x_new - x|                                       */
+  double lambda;       /* volume multiplier                                     */
+  int32_t pcg_iters;   /* CG iterations of this iteration's solve               */
+  int32_t converged;
+  double relres;
+  double ms_total, ms_filter, ms_solve, ms_sens, ms_oc; /* phase times (hipEvents) */
+} topo_iter_stats;
+
+/* Fills *opts with defaults: FP64, MG, automatic depth (coarsest <= 400 dofs),
+ * Chebyshev degree 2, rtol 1e-8, max_iters 1000, warm start, oc_tol 1e-12,
+ * check_every 1. */
+void topo_default_opts(topo_opts *opts);
+
+/* Validates the problem, copies its arrays to the device, builds the element
+ * stiffness matrix (Finite Element Analysis section: precomputed H8 matrix), the
+ * filter stencil and row sums (Sensitivity Filtering section), the multigrid
+ * hierarchy and all workspaces.  hip_stream is a hipStream_t or NULL.
+ * Errors: TOPO_EINVAL (sizes < 1, non-positive rmin/move/eta, volfrac outside
+ * (0,1], Emin <= 0 or >= E0, mask codes outside {0,1,2}, fixed dofs out of
+ * range, fewer than 6 fixed dofs, no design element, NULL f), TOPO_ENOMEM,
+ * TOPO_EDEVICE.  On error *out is NULL. */
+topo_status topo_setup(const topo_problem *problem, const topo_opts *opts, void *hip_stream,
+                       topo_ctx **out);
+
+/* Releases the context and its device memory (NULL is accepted). */
+void topo_destroy(topo_ctx *ctx);
+
+/* Thread-local message of the last non-OK status ("" if none). */
+const char *topo_last_error(void);
+
+/* Sizes of the problem held by ctx (any pointer may be NULL). */
+topo_status topo_sizes(const topo_ctx *ctx, int64_t *nel, int64_t *ndof, int32_t *mg_levels);
+
+/* Matrix-free operator (Finite Element Analysis section, K U = F with the
+ * constraints eliminated): d_y = K(E(d_xphys)) d_u on free dofs with the fixed
+ * entries of d_u taken as zero, and d_y = d_u on fixed dofs (identity rows).
+ * E = Emin + xphys^p (E0 - Emin).  d_xphys: nel, d_u, d_y: ndof (must not alias). */
+topo_status topo_apply_K(topo_ctx *ctx, const double *d_xphys, const double *d_u, double *d_y);
+
+/* Solves K(E(d_xphys)) u = f on the free dofs by preconditioned conjugate
+ * gradients (Finite Element Analysis section: the linear solve of K U = F).
+ * d_u (ndof) holds the initial guess on entry (its fixed entries are zeroed)
+ * and the solution on exit.  Returns TOPO_ENOTCONVERGED if max_iters was hit
+ * (d_u then holds the last iterate).  h_stats may be NULL. */
+topo_status topo_solve(topo_ctx *ctx, const double *d_xphys, double *d_u, topo_solve_stats *h_stats);
+
+/* One application of the solver's preconditioner z = M r for the operator of
+ * d_xphys: the symmetric multigrid V-cycle (TOPO_PRECOND_MG: Chebyshev-Jacobi
+ * smoothing, trilinear transfers, rediscretised coarse levels, exact coarsest
+ * solve) or z = r / diag(K) (TOPO_PRECOND_JACOBI).  This is the inner operator
+ * of topo_solve, exposed so it can be checked on its own.  d_r must be zero on
+ * fixed dofs; d_z receives zeros there.  d_xphys: nel; d_r, d_z: ndof. */
+topo_status topo_apply_precond(topo_ctx *ctx, const double *d_xphys, const double *d_r, double *d_z);
+
+/* Element energies and compliance sensitivities (Optimality Criteria section):
+ * d_ce[e] = u_e^T KE u_e, d_dc[e] = -p xphys_e^(p-1) (E0 - Emin) ce_e (nel each);
+ * *h_compliance = f^T u if h_compliance is not NULL (synchronises). */
+topo_status topo_sensitivity(topo_ctx *ctx, const double *d_xphys, const double *d_u, double *d_ce,
+                             double *d_dc, double *h_compliance);
+
+/* Cone-weight filter (Sensitivity Filtering section), op = TOPO_FILTER_*.
+ * d_in, d_aux, d_out: nel each; d_aux is x for TOPO_FILTER_SENS, else ignored.
+ * d_out must not alias d_in or d_aux. */
+topo_status topo_filter(topo_ctx *ctx, int32_t op, const double *d_in, const double *d_aux,
+                        double *d_out);
+
+/* OC update with move limits (Optimality Criteria section).  For design
+ * elements x_new = clamp(x (max(0,-dc)/(lambda dv))^eta, max(0,x-move),
+ * min(1,x+move)); passive elements keep x.  lambda is chosen so that the volume
+ * measure sum_j dv_j x_new_j (over all elements) equals volfrac * (number of
+ * design elements); dv is therefore the volume weight vector: H(1_D/Hs) for the
+ * density filter (TOPO_FILTER_VOLW), 1 on design and 0 on passive elements for
+ * the sensitivity filter.  The multiplier bracket is narrowed until its relative
+ * width is below oc_tol.  d_x, d_dc, d_dv, d_xnew: nel (d_xnew must not alias).
+ * h_change = max |x_new - x|, h_lambda (either may be NULL; synchronises if not). */
+topo_status topo_oc_update(topo_ctx *ctx, const double *d_x, const double *d_dc, const double *d_dv,
+                           double *d_xnew, double *h_change, double *h_lambda);
+
+/* n_iter SIMP iterations in the order of the Workflow section (filter ->
+ * modulus -> solve -> sensitivities -> filter adjoint -> OC update) on the
+ * design d_x (nel, in/out).  h_stats (n_iter entries) may be NULL.  The last
+ * displacement is kept in the context for the next call's warm start and can be
+ * read with topo_get_displacement. */
+topo_status topo_iterate(topo_ctx *ctx, double *d_x, int32_t n_iter, topo_iter_stats *h_stats);
+
+/* Copies the context's current displacement (ndof) to d_u / physical density
+ * (nel) to d_xphys; either may be NULL. */
+topo_status topo_get_state(topo_ctx *ctx, double *d_u, double *d_xphys);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TOPO_H */

@@ -92,6 +92,47 @@ def apply_K_reduced(E, KE, edof, u, fixed) -> np.ndarray:
     return y
 
 
+def apply_K_rows(E, KE, dims, u, nodes, fixed_mask=None) -> np.ndarray:
+    """Rows of the reduced operator for selected nodes: (len(nodes), 3) array of
+    sum over the elements around node n of E_e (KE v_e) at n's local position,
+    with v = u zeroed on fixed dofs, and u itself on fixed dofs."""
+    nelx, nely, nelz = dims
+    v = u.copy()
+    if fixed_mask is not None:
+        v[fixed_mask] = 0.0
+    out = np.zeros((len(nodes), 3))
+    for r, n in enumerate(np.asarray(nodes)):
+        i = n % (nelx + 1)
+        j = (n // (nelx + 1)) % (nely + 1)
+        k = n // ((nelx + 1) * (nely + 1))
+        for ei in (i - 1, i):
+            for ej in (j - 1, j):
+                for ek in (k - 1, k):
+                    if not (0 <= ei < nelx and 0 <= ej < nely and 0 <= ek < nelz):
+                        continue
+                    e = ei + nelx * (ej + nely * ek)
+                    corner = [i - ei, j - ej, k - ek]
+                    a = int(np.nonzero((CORNERS == corner).all(axis=1))[0][0])
+                    edof = element_dofs_of(e, dims)
+                    out[r] += E[e] * (KE[3 * a:3 * a + 3] @ v[edof])
+        if fixed_mask is not None:
+            for c in range(3):
+                if fixed_mask[3 * n + c]:
+                    out[r, c] = u[3 * n + c]
+    return out
+
+
+def element_dofs_of(e: int, dims) -> np.ndarray:
+    nelx, nely, _ = dims
+    i, j, k = e % nelx, (e // nelx) % nely, e // (nelx * nely)
+    d = []
+    for a in range(8):
+        di, dj, dk = (int(t) for t in CORNERS[a])
+        n = (i + di) + (nelx + 1) * ((j + dj) + (nely + 1) * (k + dk))
+        d += [3 * n, 3 * n + 1, 3 * n + 2]
+    return np.array(d)
+
+
 def compliance(f: np.ndarray, u: np.ndarray) -> float:
     return float(f @ u)
 

@@ -58,6 +58,22 @@ def filter_matrix(nelx: int, nely: int, nelz: int, rmin: float) -> sp.csr_matrix
                          shape=(nel, nel)).tocsr()
 
 
+def filter_rows(nelx, nely, nelz, rmin, elems):
+    """For selected elements: list of (neighbour indices, weights) of their H rows."""
+    offs, wts = filter_offsets(rmin)
+    rows = []
+    for e in np.asarray(elems):
+        i, j, k = e % nelx, (e // nelx) % nely, e // (nelx * nely)
+        idx, w = [], []
+        for (di, dj, dk), wt in zip(offs, wts):
+            ii, jj, kk = i + di, j + dj, k + dk
+            if 0 <= ii < nelx and 0 <= jj < nely and 0 <= kk < nelz:
+                idx.append(ii + nelx * (jj + nely * kk))
+                w.append(wt)
+        rows.append((np.array(idx), np.array(w)))
+    return rows
+
+
 def filter_matrix_bruteforce(nelx: int, nely: int, nelz: int, rmin: float) -> np.ndarray:
     """Dense H from all centroid pairs (tiny grids only)."""
     e = np.arange(nelx * nely * nelz)

@@ -1,0 +1,260 @@
+"""ctypes binding of libtopo (include/topo.h): argument marshalling only.
+
+Every numerical step runs in the HIP library; this module converts Python
+problem descriptions and torch device tensors into the C structures and raw
+pointers the ABI expects, and turns status codes into exceptions.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import List, Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtopo.so")
+
+TOPO_OK, TOPO_EINVAL, TOPO_ENOMEM, TOPO_EDEVICE, TOPO_ENOTCONVERGED, TOPO_EUNSUPPORTED = range(6)
+FILTER_DENSITY, FILTER_SENSITIVITY = 0, 1
+FILTER_FWD, FILTER_ADJ, FILTER_SENS, FILTER_VOLW = 0, 1, 2, 3
+PREC_FP64, PREC_FP32, PREC_BF16 = 0, 1, 2
+PRECOND_JACOBI, PRECOND_MG = 0, 1
+
+EXPORTED = [
+    "topo_default_opts", "topo_setup", "topo_destroy", "topo_last_error", "topo_sizes",
+    "topo_apply_K", "topo_apply_precond", "topo_solve", "topo_sensitivity", "topo_filter", "topo_oc_update",
+    "topo_iterate", "topo_get_state",
+]
+
+
+class TopoError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"[status {status}] {msg}")
+        self.status = status
+
+
+class NotConverged(TopoError):
+    pass
+
+
+class Problem_C(C.Structure):
+    _fields_ = [
+        ("nelx", C.c_int32), ("nely", C.c_int32), ("nelz", C.c_int32),
+        ("E0", C.c_double), ("Emin", C.c_double), ("nu", C.c_double), ("penal", C.c_double),
+        ("rmin", C.c_double), ("volfrac", C.c_double), ("move", C.c_double), ("eta", C.c_double),
+        ("filter", C.c_int32),
+        ("mask", C.POINTER(C.c_int8)),
+        ("fixed_dofs", C.POINTER(C.c_int64)), ("n_fixed", C.c_int64),
+        ("f", C.POINTER(C.c_double)),
+    ]
+
+
+class Opts_C(C.Structure):
+    _fields_ = [
+        ("precision", C.c_int32), ("precond", C.c_int32), ("mg_levels", C.c_int32),
+        ("mg_max_coarse_dof", C.c_int32), ("cheb_degree", C.c_int32), ("rtol", C.c_double),
+        ("max_iters", C.c_int32), ("warm_start", C.c_int32), ("oc_tol", C.c_double),
+        ("check_every", C.c_int32),
+    ]
+
+
+class SolveStats_C(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("converged", C.c_int32), ("relres", C.c_double),
+                ("ms", C.c_double)]
+
+
+class IterStats_C(C.Structure):
+    _fields_ = [
+        ("c", C.c_double), ("volume", C.c_double), ("change", C.c_double), ("lambda_", C.c_double),
+        ("pcg_iters", C.c_int32), ("converged", C.c_int32), ("relres", C.c_double),
+        ("ms_total", C.c_double), ("ms_filter", C.c_double), ("ms_solve", C.c_double),
+        ("ms_sens", C.c_double), ("ms_oc", C.c_double),
+    ]
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Loads libtopo.so; raises if it has not been built (no CPU fallback exists)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with `python -m paper_2504_05604_amd.build`")
+    lib = C.CDLL(path)
+    vp, dp = C.c_void_p, C.c_void_p
+    lib.topo_default_opts.argtypes = [C.POINTER(Opts_C)]
+    lib.topo_default_opts.restype = None
+    lib.topo_setup.argtypes = [C.POINTER(Problem_C), C.POINTER(Opts_C), vp, C.POINTER(vp)]
+    lib.topo_destroy.argtypes = [vp]
+    lib.topo_destroy.restype = None
+    lib.topo_last_error.restype = C.c_char_p
+    lib.topo_sizes.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int32)]
+    lib.topo_apply_K.argtypes = [vp, dp, dp, dp]
+    lib.topo_apply_precond.argtypes = [vp, dp, dp, dp]
+    lib.topo_solve.argtypes = [vp, dp, dp, C.POINTER(SolveStats_C)]
+    lib.topo_sensitivity.argtypes = [vp, dp, dp, dp, dp, C.POINTER(C.c_double)]
+    lib.topo_filter.argtypes = [vp, C.c_int32, dp, dp, dp]
+    lib.topo_oc_update.argtypes = [vp, dp, dp, dp, dp, C.POINTER(C.c_double), C.POINTER(C.c_double)]
+    lib.topo_iterate.argtypes = [vp, dp, C.c_int32, C.POINTER(IterStats_C)]
+    lib.topo_get_state.argtypes = [vp, dp, dp]
+    for name in EXPORTED:
+        if name not in ("topo_default_opts", "topo_destroy", "topo_last_error"):
+            getattr(lib, name).restype = C.c_int
+    _lib = lib
+    return lib
+
+
+def _check(status: int):
+    if status == TOPO_OK:
+        return
+    msg = _lib.topo_last_error().decode()
+    if status == TOPO_ENOTCONVERGED:
+        raise NotConverged(status, msg)
+    raise TopoError(status, msg)
+
+
+def default_opts(**kw) -> Opts_C:
+    lib = load()
+    o = Opts_C()
+    lib.topo_default_opts(C.byref(o))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise KeyError(f"unknown option {k}")
+        setattr(o, k, v)
+    return o
+
+
+def _ptr(t, n: Optional[int] = None, dtype=None):
+    """Raw device pointer of a contiguous CUDA/HIP tensor (None -> NULL)."""
+    if t is None:
+        return None
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("expected a device tensor")
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"expected dtype {dtype}, got {t.dtype}")
+    if n is not None and t.numel() != n:
+        raise ValueError(f"expected {n} elements, got {t.numel()}")
+    return C.c_void_p(t.data_ptr())
+
+
+class Context:
+    """One problem on one device; wraps a topo_ctx."""
+
+    def __init__(self, problem, opts: Optional[Opts_C] = None, stream=None, filter_mode=None):
+        lib = load()
+        self._lib = lib
+        p = problem
+        self.nel = int(p.nelx * p.nely * p.nelz)
+        self.ndof = int(3 * (p.nelx + 1) * (p.nely + 1) * (p.nelz + 1))
+        # keep host arrays alive during setup (setup copies them)
+        self._mask = None if p.mask is None else np.ascontiguousarray(p.mask, dtype=np.int8)
+        self._fixed = np.ascontiguousarray(p.fixed_dofs, dtype=np.int64)
+        self._f = np.ascontiguousarray(p.f, dtype=np.float64)
+        if self._f.size != self.ndof:
+            raise ValueError("load vector has the wrong length")
+        if self._mask is not None and self._mask.size != self.nel:
+            raise ValueError("mask has the wrong length")
+        mode = filter_mode if filter_mode is not None else getattr(p, "filter_mode", "density")
+        pc = Problem_C(
+            p.nelx, p.nely, p.nelz, p.E0, p.Emin, p.nu, p.penal, p.rmin, p.volfrac, p.move, p.eta,
+            FILTER_DENSITY if mode == "density" else FILTER_SENSITIVITY,
+            None if self._mask is None else self._mask.ctypes.data_as(C.POINTER(C.c_int8)),
+            self._fixed.ctypes.data_as(C.POINTER(C.c_int64)), self._fixed.size,
+            self._f.ctypes.data_as(C.POINTER(C.c_double)),
+        )
+        self.opts = opts if opts is not None else default_opts()
+        handle = C.c_void_p()
+        st_ptr = None if stream is None else C.c_void_p(int(stream))
+        _check(lib.topo_setup(C.byref(pc), C.byref(self.opts), st_ptr, C.byref(handle)))
+        self._h = handle
+        lv = C.c_int32()
+        _check(lib.topo_sizes(self._h, None, None, C.byref(lv)))
+        self.mg_levels = lv.value
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.topo_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    # -- entry points ------------------------------------------------------
+    def apply_K(self, xphys, u, y):
+        import torch
+        _check(self._lib.topo_apply_K(self._h, _ptr(xphys, self.nel, torch.float64),
+                                      _ptr(u, self.ndof, torch.float64), _ptr(y, self.ndof, torch.float64)))
+
+    def apply_precond(self, xphys, r, z):
+        import torch
+        _check(self._lib.topo_apply_precond(self._h, _ptr(xphys, self.nel, torch.float64),
+                                            _ptr(r, self.ndof, torch.float64), _ptr(z, self.ndof, torch.float64)))
+
+    def solve(self, xphys, u, raise_on_nonconv=True) -> dict:
+        import torch
+        st = SolveStats_C()
+        status = self._lib.topo_solve(self._h, _ptr(xphys, self.nel, torch.float64),
+                                      _ptr(u, self.ndof, torch.float64), C.byref(st))
+        out = {"iters": st.iters, "converged": bool(st.converged), "relres": st.relres, "ms": st.ms}
+        if status == TOPO_ENOTCONVERGED and not raise_on_nonconv:
+            return out
+        _check(status)
+        return out
+
+    def sensitivity(self, xphys, u, ce, dc, want_compliance=True):
+        import torch
+        c = C.c_double()
+        _check(self._lib.topo_sensitivity(self._h, _ptr(xphys, self.nel, torch.float64),
+                                          _ptr(u, self.ndof, torch.float64), _ptr(ce, self.nel, torch.float64),
+                                          _ptr(dc, self.nel, torch.float64),
+                                          C.byref(c) if want_compliance else None))
+        return c.value if want_compliance else None
+
+    def filter(self, op: int, inp, out, aux=None):
+        import torch
+        _check(self._lib.topo_filter(self._h, op, _ptr(inp, self.nel, torch.float64),
+                                     _ptr(aux, self.nel, torch.float64), _ptr(out, self.nel, torch.float64)))
+
+    def oc_update(self, x, dc, dv, xnew):
+        import torch
+        chg, lam = C.c_double(), C.c_double()
+        _check(self._lib.topo_oc_update(self._h, _ptr(x, self.nel, torch.float64),
+                                        _ptr(dc, self.nel, torch.float64), _ptr(dv, self.nel, torch.float64),
+                                        _ptr(xnew, self.nel, torch.float64), C.byref(chg), C.byref(lam)))
+        return chg.value, lam.value
+
+    def iterate(self, x, n_iter: int, raise_on_nonconv=True) -> List[dict]:
+        import torch
+        stats = (IterStats_C * max(1, n_iter))()
+        status = self._lib.topo_iterate(self._h, _ptr(x, self.nel, torch.float64), n_iter, stats)
+        if not (status == TOPO_ENOTCONVERGED and not raise_on_nonconv):
+            _check(status)
+        out = []
+        for i in range(n_iter):
+            s = stats[i]
+            out.append({"c": s.c, "volume": s.volume, "change": s.change, "lambda": s.lambda_,
+                        "pcg_iters": s.pcg_iters, "converged": bool(s.converged), "relres": s.relres,
+                        "ms_total": s.ms_total, "ms_filter": s.ms_filter, "ms_solve": s.ms_solve,
+                        "ms_sens": s.ms_sens, "ms_oc": s.ms_oc})
+        return out
+
+    def get_state(self, u=None, xphys=None):
+        import torch
+        _check(self._lib.topo_get_state(self._h, _ptr(u, self.ndof, torch.float64),
+                                        _ptr(xphys, self.nel, torch.float64)))

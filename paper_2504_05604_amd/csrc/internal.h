@@ -1,0 +1,175 @@
+// Internal declarations of libtopo (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/topo.h"
+
+namespace topo {
+
+// ---------------------------------------------------------------------------
+// grid geometry
+struct Grid {
+  int nx, ny, nz;  // elements per axis
+  __host__ __device__ int NX() const { return nx + 1; }
+  __host__ __device__ int NY() const { return ny + 1; }
+  __host__ __device__ int NZ() const { return nz + 1; }
+  __host__ __device__ int64_t nel() const { return (int64_t)nx * ny * nz; }
+  __host__ __device__ int64_t nnodes() const { return (int64_t)(nx + 1) * (ny + 1) * (nz + 1); }
+  __host__ __device__ int64_t ndof() const { return 3 * nnodes(); }
+};
+
+// Local node a of an element sits at corner (cx(a), cy(a), cz(a)) of the unit cube.
+__host__ __device__ constexpr int cx(int a) { return (a == 1 || a == 2 || a == 5 || a == 6) ? 1 : 0; }
+__host__ __device__ constexpr int cy(int a) { return (a == 2 || a == 3 || a == 6 || a == 7) ? 1 : 0; }
+__host__ __device__ constexpr int cz(int a) { return a >= 4 ? 1 : 0; }
+__host__ __device__ constexpr int corner_of(int x, int y, int z) {
+  return z * 4 + (y ? (x ? 2 : 3) : (x ? 1 : 0));
+}
+
+// ---------------------------------------------------------------------------
+// deterministic reductions: per-block partials, the last block to finish sums
+// them in a fixed order and writes the result (no floating-point atomics).
+constexpr int kMaxRed = 4;  // values reduced together in one kernel
+
+struct Reducer {
+  double *partials;    // [max_blocks * kMaxRed]
+  unsigned *counter;   // one counter per reduction slot in use
+  int max_blocks;
+};
+
+// ---------------------------------------------------------------------------
+// error state
+void set_error(const char *fmt, ...);
+#define TOPO_HIP(call)                                                           \
+  do {                                                                           \
+    hipError_t e_ = (call);                                                      \
+    if (e_ != hipSuccess) {                                                      \
+      ::topo::set_error("%s failed: %s (%s:%d)", #call, hipGetErrorString(e_),   \
+                        __FILE__, __LINE__);                                     \
+      return TOPO_EDEVICE;                                                       \
+    }                                                                            \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// device scalar block of the CG loop and the OC search
+struct Scalars {
+  double rr, rz, rz_new, pq, ff, alpha, beta, comp;  // CG / compliance
+  double red[8];                                     // scratch results of reductions
+  // OC multiplier search
+  double l1, l2, target, vconst, change, volume, lambda;
+  int oc_done, oc_pass;
+  double oc_lam[64];
+  double oc_vol[64];
+};
+constexpr int kOcCand = 63;  // candidate multipliers evaluated per pass
+
+// ---------------------------------------------------------------------------
+// kernel launchers (kernels_*.hip)
+
+// E_e = Emin + xphys^p (E0 - Emin), times scale
+hipError_t launch_simp_modulus(hipStream_t s, int64_t nel, const double *xphys, double E0,
+                               double Emin, double penal, double scale, double *E);
+// E_c = 2 * mean of the 8 children (missing children count as 0)
+hipError_t launch_coarsen_moduli(hipStream_t s, Grid gf, Grid gc, const double *Ef, double *Ec);
+// diag_i = sum_{e ni i} E_e KE_{li,li}; 1 on fixed dofs
+hipError_t launch_diag(hipStream_t s, Grid g, const double *E, const double *KEdiag,
+                       const uint8_t *fixed, double *diag);
+
+// K.u variants (node-centred, matrix-free, identity rows on fixed dofs); the
+// input vector must be zero on fixed dofs.
+enum KuEpi {
+  KU_STORE = 0,      // y = Au
+  KU_STORE_DOT = 1,  // y = Au, red0 = u.y
+  KU_RESID = 2,      // y = b - Au, red0 = y.y
+  KU_CHEB = 3,       // res -= Au; dout = c1 u + c2 res/diag; x += dout
+  KU_RESUPD = 4,     // res -= Au
+};
+struct KuArgs {
+  Grid g;
+  const double *E;
+  const double *KE;       // 576 entries
+  const double *u;        // input (stencil operand)
+  double *y;              // STORE, STORE_DOT, RESID output
+  const double *b;        // RESID rhs
+  const uint8_t *fixed;   // per node, bit c set if dof c is fixed
+  double *res, *x, *dout; // CHEB / RESUPD
+  const double *diag;
+  double c1, c2;
+};
+hipError_t launch_ku(hipStream_t s, KuEpi epi, const KuArgs &a, const Reducer &red, double *out0);
+
+// vector kernels
+hipError_t launch_zero_fixed(hipStream_t s, int64_t nnodes, const uint8_t *fixed, double *v);
+hipError_t launch_copy_masked(hipStream_t s, int64_t nnodes, const uint8_t *fixed, const double *in,
+                              double *out);
+// out[d] = in[d] on fixed dofs only
+hipError_t launch_copy_fixed(hipStream_t s, int64_t nnodes, const uint8_t *fixed, const double *in,
+                             double *out);
+hipError_t launch_dot(hipStream_t s, int64_t n, const double *a, const double *b, const Reducer &red,
+                      double *out);
+// x += alpha p; r -= alpha q; red = r.r        (alpha = sc->rz / sc->pq)
+hipError_t launch_cg_update_xr(hipStream_t s, int64_t n, Scalars *sc, double *x, double *r,
+                               const double *p, const double *q, const Reducer &red);
+// z = r / diag; red = r.z
+hipError_t launch_jacobi(hipStream_t s, int64_t n, const double *r, const double *diag, double *z,
+                         const Reducer &red, double *out);
+// p = z + beta p, beta = rz_new / rz (0 if first); rz = rz_new
+hipError_t launch_cg_update_p(hipStream_t s, int64_t n, Scalars *sc, const double *z, double *p,
+                              int first);
+// Chebyshev first step from x = 0: d = r/(diag theta); x = d; res = r
+hipError_t launch_cheb_first(hipStream_t s, int64_t n, const double *r, const double *diag,
+                             double inv_theta, double *d, double *x, double *res);
+// d = res/(diag theta); x += d
+hipError_t launch_cheb_start(hipStream_t s, int64_t n, const double *res, const double *diag,
+                             double inv_theta, double *d, double *x);
+
+// multigrid transfers
+hipError_t launch_restrict(hipStream_t s, Grid gf, Grid gc, const double *rf, const uint8_t *fixc,
+                           double *rc);
+hipError_t launch_prolong_add(hipStream_t s, Grid gf, Grid gc, const double *ec,
+                              const uint8_t *fixf, double *xf);
+hipError_t launch_coarse_fixed(hipStream_t s, Grid gf, Grid gc, const uint8_t *fixf, uint8_t *fixc);
+// dense coarsest-level operator, inverse and application
+hipError_t launch_dense_assemble(hipStream_t s, Grid g, const double *E, const double *KE,
+                                 const uint8_t *fixed, double *A);
+hipError_t launch_dense_invert(hipStream_t s, int n, double *A);
+hipError_t launch_dense_matvec(hipStream_t s, int n, const double *A, const double *x, double *y);
+
+// sensitivities: ce = u_e^T KE u_e, dc = -p xphys^(p-1) (E0-Emin) ce
+hipError_t launch_sensitivity(hipStream_t s, Grid g, const double *KE, const double *u,
+                              const double *xphys, double E0, double Emin, double penal, double *ce,
+                              double *dc);
+
+// filter
+struct FilterArgs {
+  Grid g;
+  int noff;
+  const int *off;       // noff x 3 (di, dj, dk)
+  const double *w;      // noff weights
+  const double *Hs;     // nel
+  const double *sD;     // nel: design/Hs
+  const int8_t *mask;   // nel
+};
+hipError_t launch_filter_hs(hipStream_t s, const FilterArgs &f, double *Hs);
+hipError_t launch_filter(hipStream_t s, int op, const FilterArgs &f, const double *in,
+                         const double *aux, double *out);
+hipError_t launch_design_scale(hipStream_t s, int64_t nel, const int8_t *mask, const double *Hs,
+                               double *sD);
+
+// OC update with device-side multisection
+hipError_t launch_oc_prepare(hipStream_t s, int64_t nel, const double *x, const double *dc,
+                             const double *dv, const int8_t *mask, double eta, double target,
+                             double *a, Scalars *sc, const Reducer &red);
+hipError_t launch_oc_pass(hipStream_t s, int64_t nel, const double *x, const double *a,
+                          const double *dv, const int8_t *mask, double move, double eta,
+                          double tol, Scalars *sc, const Reducer &red);
+hipError_t launch_oc_final(hipStream_t s, int64_t nel, const double *x, const double *a,
+                           const double *dv, const int8_t *mask, double move, double eta,
+                           double *xnew, Scalars *sc, const Reducer &red);
+
+}  // namespace topo

@@ -1,0 +1,203 @@
+// Geometric multigrid pieces: trilinear transfers between a grid and the grid of
+// half the resolution (odd fine counts round up: the coarse grid extends half a
+// coarse element past the fine domain), coarse Dirichlet flags, and the dense
+// coarsest-level operator with its explicit inverse.
+#include "internal.h"
+
+namespace topo {
+
+namespace {
+constexpr int kBs = 256;
+inline unsigned nblocks(int64_t n) { return (unsigned)((n + kBs - 1) / kBs); }
+}  // namespace
+
+// r_c = P^T r_f: each coarse node gathers the fine nodes within one fine spacing
+// of its position 2*(I,J,K), weight prod over axes (1 at distance 0, 1/2 at 1).
+__global__ void restrict_kernel(Grid gf, Grid gc, const double *__restrict__ rf,
+                                const uint8_t *__restrict__ fixc, double *__restrict__ rc) {
+  const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= gc.nnodes()) return;
+  const int I = (int)(m % gc.NX());
+  const int J = (int)((m / gc.NX()) % gc.NY());
+  const int K = (int)(m / ((int64_t)gc.NX() * gc.NY()));
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+#pragma unroll
+  for (int dz = -1; dz <= 1; ++dz) {
+    const int k = 2 * K + dz;
+    if (k < 0 || k > gf.nz) continue;
+#pragma unroll
+    for (int dy = -1; dy <= 1; ++dy) {
+      const int j = 2 * J + dy;
+      if (j < 0 || j > gf.ny) continue;
+#pragma unroll
+      for (int dx = -1; dx <= 1; ++dx) {
+        const int i = 2 * I + dx;
+        if (i < 0 || i > gf.nx) continue;
+        const double w = (dx ? 0.5 : 1.0) * (dy ? 0.5 : 1.0) * (dz ? 0.5 : 1.0);
+        const int64_t n = i + (int64_t)gf.NX() * (j + (int64_t)gf.NY() * k);
+        s0 = fma(w, rf[3 * n + 0], s0);
+        s1 = fma(w, rf[3 * n + 1], s1);
+        s2 = fma(w, rf[3 * n + 2], s2);
+      }
+    }
+  }
+  const uint8_t f = fixc[m];
+  rc[3 * m + 0] = (f & 1) ? 0.0 : s0;
+  rc[3 * m + 1] = (f & 2) ? 0.0 : s1;
+  rc[3 * m + 2] = (f & 4) ? 0.0 : s2;
+}
+
+hipError_t launch_restrict(hipStream_t s, Grid gf, Grid gc, const double *rf, const uint8_t *fixc,
+                           double *rc) {
+  restrict_kernel<<<nblocks(gc.nnodes()), kBs, 0, s>>>(gf, gc, rf, fixc, rc);
+  return hipGetLastError();
+}
+
+// x_f += P e_c on free fine dofs (trilinear interpolation of the coarse values).
+__global__ void prolong_add_kernel(Grid gf, Grid gc, const double *__restrict__ ec,
+                                   const uint8_t *__restrict__ fixf, double *__restrict__ xf) {
+  const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= gf.nnodes()) return;
+  const int i = (int)(n % gf.NX());
+  const int j = (int)((n / gf.NX()) % gf.NY());
+  const int k = (int)(n / ((int64_t)gf.NX() * gf.NY()));
+  const int I0 = i >> 1, J0 = j >> 1, K0 = k >> 1;
+  const int ni = (i & 1) ? 2 : 1, nj = (j & 1) ? 2 : 1, nk = (k & 1) ? 2 : 1;
+  const double wi = (i & 1) ? 0.5 : 1.0, wj = (j & 1) ? 0.5 : 1.0, wk = (k & 1) ? 0.5 : 1.0;
+  const double w = wi * wj * wk;
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+  for (int c = 0; c < nk; ++c)
+    for (int b = 0; b < nj; ++b)
+      for (int a = 0; a < ni; ++a) {
+        const int64_t m = (I0 + a) + (int64_t)gc.NX() * ((J0 + b) + (int64_t)gc.NY() * (K0 + c));
+        s0 += ec[3 * m + 0];
+        s1 += ec[3 * m + 1];
+        s2 += ec[3 * m + 2];
+      }
+  const uint8_t f = fixf[n];
+  if (!(f & 1)) xf[3 * n + 0] = fma(w, s0, xf[3 * n + 0]);
+  if (!(f & 2)) xf[3 * n + 1] = fma(w, s1, xf[3 * n + 1]);
+  if (!(f & 4)) xf[3 * n + 2] = fma(w, s2, xf[3 * n + 2]);
+}
+
+hipError_t launch_prolong_add(hipStream_t s, Grid gf, Grid gc, const double *ec,
+                              const uint8_t *fixf, double *xf) {
+  prolong_add_kernel<<<nblocks(gf.nnodes()), kBs, 0, s>>>(gf, gc, ec, fixf, xf);
+  return hipGetLastError();
+}
+
+// coarse dof fixed iff the fine dof at the coincident node (clamped into the
+// fine grid) is fixed
+__global__ void coarse_fixed_kernel(Grid gf, Grid gc, const uint8_t *fixf, uint8_t *fixc) {
+  const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= gc.nnodes()) return;
+  const int I = (int)(m % gc.NX());
+  const int J = (int)((m / gc.NX()) % gc.NY());
+  const int K = (int)(m / ((int64_t)gc.NX() * gc.NY()));
+  const int i = min(2 * I, gf.nx), j = min(2 * J, gf.ny), k = min(2 * K, gf.nz);
+  fixc[m] = fixf[i + (int64_t)gf.NX() * (j + (int64_t)gf.NY() * k)];
+}
+
+hipError_t launch_coarse_fixed(hipStream_t s, Grid gf, Grid gc, const uint8_t *fixf, uint8_t *fixc) {
+  coarse_fixed_kernel<<<nblocks(gc.nnodes()), kBs, 0, s>>>(gf, gc, fixf, fixc);
+  return hipGetLastError();
+}
+
+// Dense n x n operator of a (small) level, row-major; thread per row: the row of
+// dof (node i, component c) collects E_e KE[3 li + c][3 lb + d] over the elements
+// around i.  Fixed rows/columns become identity rows/columns.
+__global__ void dense_assemble_kernel(Grid g, const double *E, const double *KE,
+                                      const uint8_t *fixed, double *A) {
+  const int64_t n = g.ndof();
+  const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (row >= n) return;
+  double *Ar = A + row * n;
+  for (int64_t c = 0; c < n; ++c) Ar[c] = 0.0;
+  const int64_t node = row / 3;
+  const int comp = (int)(row % 3);
+  if ((fixed[node] >> comp) & 1) {
+    Ar[row] = 1.0;
+    return;
+  }
+  const int i = (int)(node % g.NX());
+  const int j = (int)((node / g.NX()) % g.NY());
+  const int k = (int)(node / ((int64_t)g.NX() * g.NY()));
+  for (int e = 0; e < 8; ++e) {
+    const int ex = e & 1, ey = (e >> 1) & 1, ez = e >> 2;
+    const int ei = i - 1 + ex, ej = j - 1 + ey, ek = k - 1 + ez;
+    if (ei < 0 || ei >= g.nx || ej < 0 || ej >= g.ny || ek < 0 || ek >= g.nz) continue;
+    const double Ee = E[ei + (int64_t)g.nx * (ej + (int64_t)g.ny * ek)];
+    const int li = corner_of(1 - ex, 1 - ey, 1 - ez);
+    for (int b = 0; b < 8; ++b) {
+      const int64_t nb = (ei + cx(b)) + (int64_t)g.NX() * ((ej + cy(b)) + (int64_t)g.NY() * (ek + cz(b)));
+      const uint8_t fb = fixed[nb];
+      for (int d = 0; d < 3; ++d) {
+        if ((fb >> d) & 1) continue;
+        Ar[3 * nb + d] += Ee * KE[(3 * li + comp) * 24 + 3 * b + d];
+      }
+    }
+  }
+}
+
+hipError_t launch_dense_assemble(hipStream_t s, Grid g, const double *E, const double *KE,
+                                 const uint8_t *fixed, double *A) {
+  dense_assemble_kernel<<<nblocks(g.ndof()), kBs, 0, s>>>(g, E, KE, fixed, A);
+  return hipGetLastError();
+}
+
+// In-place Gauss-Jordan inversion of an SPD matrix (no pivoting is needed for
+// SPD matrices), one workgroup; pivot row and column are staged in LDS.
+constexpr int kInvThreads = 1024;
+constexpr int kMaxDense = 2048;
+
+__global__ __launch_bounds__(kInvThreads) void dense_invert_kernel(int n, double *A) {
+  __shared__ double col[kMaxDense];
+  __shared__ double rowk[kMaxDense];
+  for (int k = 0; k < n; ++k) {
+    for (int t = threadIdx.x; t < n; t += blockDim.x) {
+      col[t] = A[(int64_t)t * n + k];
+      rowk[t] = A[(int64_t)k * n + t];
+    }
+    __syncthreads();
+    const double inv = 1.0 / col[k];
+    const int64_t nn = (int64_t)n * n;
+    for (int64_t idx = threadIdx.x; idx < nn; idx += blockDim.x) {
+      const int i = (int)(idx / n), j = (int)(idx % n);
+      double v;
+      if (i == k)
+        v = (j == k) ? inv : rowk[j] * inv;
+      else if (j == k)
+        v = -col[i] * inv;
+      else
+        v = A[idx] - col[i] * rowk[j] * inv;
+      A[idx] = v;
+    }
+    __syncthreads();
+  }
+}
+
+hipError_t launch_dense_invert(hipStream_t s, int n, double *A) {
+  if (n > kMaxDense) return hipErrorInvalidValue;
+  dense_invert_kernel<<<1, kInvThreads, 0, s>>>(n, A);
+  return hipGetLastError();
+}
+
+// y = A x, one wave per row
+__global__ void dense_matvec_kernel(int n, const double *A, const double *x, double *y) {
+  const int lane = threadIdx.x & 63;
+  const int row = blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64;
+  if (row >= n) return;
+  double t = 0.0;
+  for (int c = lane; c < n; c += 64) t = fma(A[(int64_t)row * n + c], x[c], t);
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) t += __shfl_down(t, off, 64);
+  if (lane == 0) y[row] = t;
+}
+
+hipError_t launch_dense_matvec(hipStream_t s, int n, const double *A, const double *x, double *y) {
+  const int rows_per_block = kBs / 64;
+  dense_matvec_kernel<<<(unsigned)((n + rows_per_block - 1) / rows_per_block), kBs, 0, s>>>(n, A, x, y);
+  return hipGetLastError();
+}
+
+}  // namespace topo

@@ -1,0 +1,177 @@
+// Vector kernels of the conjugate-gradient loop and the Chebyshev smoother.
+// All reductions are deterministic (block partials summed in a fixed order).
+#include "internal.h"
+#include "reduce_dev.h"
+
+namespace topo {
+
+namespace {
+constexpr int kBs = 256;
+inline unsigned nblocks(int64_t n, int per_thread = 1) {
+  const int64_t m = (n + per_thread - 1) / per_thread;
+  return (unsigned)((m + kBs - 1) / kBs);
+}
+// grid-stride reductions use a bounded grid so partial buffers stay small
+inline unsigned red_blocks(int64_t n, const Reducer &red) {
+  unsigned nb = nblocks(n);
+  return nb > (unsigned)red.max_blocks ? (unsigned)red.max_blocks : nb;
+}
+}  // namespace
+
+__global__ void zero_fixed_kernel(int64_t nnodes, const uint8_t *fixed, double *v) {
+  const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= nnodes) return;
+  const uint8_t f = fixed[n];
+  if (f & 1) v[3 * n + 0] = 0.0;
+  if (f & 2) v[3 * n + 1] = 0.0;
+  if (f & 4) v[3 * n + 2] = 0.0;
+}
+
+hipError_t launch_zero_fixed(hipStream_t s, int64_t nnodes, const uint8_t *fixed, double *v) {
+  zero_fixed_kernel<<<nblocks(nnodes), kBs, 0, s>>>(nnodes, fixed, v);
+  return hipGetLastError();
+}
+
+__global__ void copy_masked_kernel(int64_t nnodes, const uint8_t *fixed, const double *in,
+                                   double *out) {
+  const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= nnodes) return;
+  const uint8_t f = fixed[n];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) out[3 * n + c] = ((f >> c) & 1) ? 0.0 : in[3 * n + c];
+}
+
+hipError_t launch_copy_masked(hipStream_t s, int64_t nnodes, const uint8_t *fixed, const double *in,
+                              double *out) {
+  copy_masked_kernel<<<nblocks(nnodes), kBs, 0, s>>>(nnodes, fixed, in, out);
+  return hipGetLastError();
+}
+
+__global__ void copy_fixed_kernel(int64_t nnodes, const uint8_t *fixed, const double *in,
+                                  double *out) {
+  const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= nnodes) return;
+  const uint8_t f = fixed[n];
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+    if ((f >> c) & 1) out[3 * n + c] = in[3 * n + c];
+}
+
+hipError_t launch_copy_fixed(hipStream_t s, int64_t nnodes, const uint8_t *fixed, const double *in,
+                             double *out) {
+  copy_fixed_kernel<<<nblocks(nnodes), kBs, 0, s>>>(nnodes, fixed, in, out);
+  return hipGetLastError();
+}
+
+__global__ void dot_kernel(int64_t n, const double *a, const double *b, Reducer red, double *out) {
+  double t = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    t = fma(a[i], b[i], t);
+  double v[1] = {t};
+  block_reduce_finalize<1, false>(v, red, out);
+}
+
+hipError_t launch_dot(hipStream_t s, int64_t n, const double *a, const double *b, const Reducer &red,
+                      double *out) {
+  dot_kernel<<<red_blocks(n, red), kBs, 0, s>>>(n, a, b, red, out);
+  return hipGetLastError();
+}
+
+__global__ void cg_update_xr_kernel(int64_t n, Scalars *sc, double *x, double *r, const double *p,
+                                    const double *q, Reducer red) {
+  const double alpha = sc->rz / sc->pq;
+  double t = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    x[i] = fma(alpha, p[i], x[i]);
+    const double ri = fma(-alpha, q[i], r[i]);
+    r[i] = ri;
+    t = fma(ri, ri, t);
+  }
+  double v[1] = {t};
+  block_reduce_finalize<1, false>(v, red, &sc->rr);
+}
+
+hipError_t launch_cg_update_xr(hipStream_t s, int64_t n, Scalars *sc, double *x, double *r,
+                               const double *p, const double *q, const Reducer &red) {
+  cg_update_xr_kernel<<<red_blocks(n, red), kBs, 0, s>>>(n, sc, x, r, p, q, red);
+  return hipGetLastError();
+}
+
+__global__ void jacobi_kernel(int64_t n, const double *r, const double *diag, double *z, Reducer red,
+                              double *out) {
+  double t = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const double zi = r[i] / diag[i];
+    z[i] = zi;
+    t = fma(r[i], zi, t);
+  }
+  double v[1] = {t};
+  block_reduce_finalize<1, false>(v, red, out);
+}
+
+hipError_t launch_jacobi(hipStream_t s, int64_t n, const double *r, const double *diag, double *z,
+                         const Reducer &red, double *out) {
+  jacobi_kernel<<<red_blocks(n, red), kBs, 0, s>>>(n, r, diag, z, red, out);
+  return hipGetLastError();
+}
+
+__global__ void cg_update_p_kernel(int64_t n, Scalars *sc, const double *z, double *p, int first) {
+  const double beta = first ? 0.0 : sc->rz_new / sc->rz;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = first ? z[i] : fma(beta, p[i], z[i]);
+}
+
+// rz <- rz_new once every block has read the old rz (a separate tiny kernel)
+__global__ void cg_shift_rz_kernel(Scalars *sc) {
+  sc->beta = sc->rz_new / sc->rz;
+  sc->rz = sc->rz_new;
+}
+__global__ void cg_first_rz_kernel(Scalars *sc) { sc->rz = sc->rz_new; }
+
+hipError_t launch_cg_update_p(hipStream_t s, int64_t n, Scalars *sc, const double *z, double *p,
+                              int first) {
+  cg_update_p_kernel<<<nblocks(n, 4), kBs, 0, s>>>(n, sc, z, p, first);
+  if (first)
+    cg_first_rz_kernel<<<1, 1, 0, s>>>(sc);
+  else
+    cg_shift_rz_kernel<<<1, 1, 0, s>>>(sc);
+  return hipGetLastError();
+}
+
+__global__ void cheb_first_kernel(int64_t n, const double *r, const double *diag, double inv_theta,
+                                  double *d, double *x, double *res) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double ri = r[i];
+  const double di = ri / diag[i] * inv_theta;
+  d[i] = di;
+  x[i] = di;
+  res[i] = ri;
+}
+
+hipError_t launch_cheb_first(hipStream_t s, int64_t n, const double *r, const double *diag,
+                             double inv_theta, double *d, double *x, double *res) {
+  cheb_first_kernel<<<nblocks(n), kBs, 0, s>>>(n, r, diag, inv_theta, d, x, res);
+  return hipGetLastError();
+}
+
+__global__ void cheb_start_kernel(int64_t n, const double *res, const double *diag,
+                                  double inv_theta, double *d, double *x) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double di = res[i] / diag[i] * inv_theta;
+  d[i] = di;
+  x[i] += di;
+}
+
+hipError_t launch_cheb_start(hipStream_t s, int64_t n, const double *res, const double *diag,
+                             double inv_theta, double *d, double *x) {
+  cheb_start_kernel<<<nblocks(n), kBs, 0, s>>>(n, res, diag, inv_theta, d, x);
+  return hipGetLastError();
+}
+
+}  // namespace topo

@@ -1,0 +1,763 @@
+// Host side of libtopo: argument validation, setup (element stiffness, filter
+// stencil, multigrid hierarchy, workspaces), the conjugate-gradient solve with a
+// multigrid or Jacobi preconditioner, and the SIMP iteration driver.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <vector>
+
+#include "internal.h"
+
+namespace topo {
+
+static thread_local char g_err[512] = "";
+
+void set_error(const char *fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof g_err, fmt, ap);
+  va_end(ap);
+}
+
+// ---------------------------------------------------------------------------
+// H8 element stiffness (Finite Element Analysis section): KE = int B^T D B over
+// the unit cube with a 2x2x2 Gauss rule, isotropic D for E = 1 and Poisson
+// ratio nu, Voigt order xx, yy, zz, xy, yz, zx with engineering shears.
+static void element_stiffness(double nu, double KE[576]) {
+  const double lam = nu / ((1.0 + nu) * (1.0 - 2.0 * nu));
+  const double mu = 1.0 / (2.0 * (1.0 + nu));
+  double D[6][6] = {};
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) D[a][b] = lam + (a == b ? 2.0 * mu : 0.0);
+  D[3][3] = D[4][4] = D[5][5] = mu;
+  const double gp[2] = {0.5 - 0.5 / std::sqrt(3.0), 0.5 + 0.5 / std::sqrt(3.0)};
+  std::fill(KE, KE + 576, 0.0);
+  for (int qa = 0; qa < 2; ++qa)
+    for (int qb = 0; qb < 2; ++qb)
+      for (int qc = 0; qc < 2; ++qc) {
+        const double p[3] = {gp[qa], gp[qb], gp[qc]};
+        double B[6][24] = {};
+        for (int n = 0; n < 8; ++n) {
+          const int c[3] = {cx(n), cy(n), cz(n)};
+          double gr[3];
+          for (int d = 0; d < 3; ++d) {
+            double v = c[d] ? 1.0 : -1.0;
+            for (int o = 0; o < 3; ++o)
+              if (o != d) v *= c[o] ? p[o] : 1.0 - p[o];
+            gr[d] = v;
+          }
+          B[0][3 * n + 0] = gr[0];
+          B[1][3 * n + 1] = gr[1];
+          B[2][3 * n + 2] = gr[2];
+          B[3][3 * n + 0] = gr[1];
+          B[3][3 * n + 1] = gr[0];
+          B[4][3 * n + 1] = gr[2];
+          B[4][3 * n + 2] = gr[1];
+          B[5][3 * n + 0] = gr[2];
+          B[5][3 * n + 2] = gr[0];
+        }
+        double DB[6][24];
+        for (int r = 0; r < 6; ++r)
+          for (int j = 0; j < 24; ++j) {
+            double s = 0.0;
+            for (int k = 0; k < 6; ++k) s += D[r][k] * B[k][j];
+            DB[r][j] = s;
+          }
+        for (int i = 0; i < 24; ++i)
+          for (int j = 0; j < 24; ++j) {
+            double s = 0.0;
+            for (int k = 0; k < 6; ++k) s += B[k][i] * DB[k][j];
+            KE[i * 24 + j] += 0.125 * s;
+          }
+      }
+}
+
+// Largest eigenvalue of a symmetric n x n matrix by cyclic Jacobi rotations.
+static double sym_max_eig(std::vector<double> A, int n) {
+  for (int sweep = 0; sweep < 100; ++sweep) {
+    double off = 0.0;
+    for (int p = 0; p < n; ++p)
+      for (int q = p + 1; q < n; ++q) off += A[p * n + q] * A[p * n + q];
+    if (off < 1e-30) break;
+    for (int p = 0; p < n; ++p)
+      for (int q = p + 1; q < n; ++q) {
+        const double apq = A[p * n + q];
+        if (std::fabs(apq) < 1e-300) continue;
+        const double theta = (A[q * n + q] - A[p * n + p]) / (2.0 * apq);
+        const double t = (theta >= 0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
+        const double c = 1.0 / std::sqrt(t * t + 1.0), s = t * c;
+        for (int k = 0; k < n; ++k) {
+          const double akp = A[k * n + p], akq = A[k * n + q];
+          A[k * n + p] = c * akp - s * akq;
+          A[k * n + q] = s * akp + c * akq;
+        }
+        for (int k = 0; k < n; ++k) {
+          const double apk = A[p * n + k], aqk = A[q * n + k];
+          A[p * n + k] = c * apk - s * aqk;
+          A[q * n + k] = s * apk + c * aqk;
+        }
+      }
+  }
+  double m = A[0];
+  for (int i = 1; i < n; ++i) m = std::max(m, A[i * n + i]);
+  return m;
+}
+
+// ---------------------------------------------------------------------------
+template <typename T>
+static hipError_t dalloc(T **p, size_t count) {
+  *p = nullptr;
+  if (count == 0) count = 1;
+  return hipMalloc((void **)p, count * sizeof(T));
+}
+
+struct Level {
+  Grid g{};
+  double *E = nullptr;       // moduli incl. the 2^level stiffness scale
+  double *diag = nullptr;    // Jacobi diagonal (1 on fixed dofs)
+  uint8_t *fixed = nullptr;  // per node, bit c = dof c fixed
+  double *b = nullptr, *x = nullptr, *res = nullptr, *d0 = nullptr, *d1 = nullptr;
+};
+
+}  // namespace topo
+
+using namespace topo;
+
+struct topo_ctx {
+  topo_problem prob{};
+  topo_opts opts{};
+  hipStream_t stream = nullptr;
+  Grid g{};
+  int64_t nel = 0, ndof = 0, nnodes = 0, n_design = 0;
+  double target = 0.0;
+  // constants
+  double *KE = nullptr, *KEdiag = nullptr;
+  double lam_max = 0.0;
+  // problem data
+  double *f = nullptr;
+  int8_t *mask = nullptr;
+  // filter
+  FilterArgs filt{};
+  int *d_off = nullptr;
+  double *d_w = nullptr, *Hs = nullptr, *sD = nullptr, *volw = nullptr;
+  // multigrid
+  std::vector<Level> lv;
+  double *Ainv = nullptr;
+  int ncoarse = 0;
+  // CG vectors (level-0 b / x double as the V-cycle's rhs / result)
+  double *u = nullptr, *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr;
+  // SIMP work
+  double *xphys = nullptr, *ce = nullptr, *dc = nullptr, *dcf = nullptr, *oc_a = nullptr,
+         *tmp = nullptr, *xnew = nullptr;
+  // reductions and scalars
+  Scalars *sc = nullptr;
+  Scalars *h_sc = nullptr;  // pinned mirror
+  Reducer red{};
+  int have_u = 0;
+  std::vector<void *> allocs;
+
+  template <typename T>
+  hipError_t alloc(T **p_, size_t count) {
+    hipError_t e = dalloc(p_, count);
+    if (e == hipSuccess) allocs.push_back((void *)*p_);
+    return e;
+  }
+  ~topo_ctx() {
+    for (void *a : allocs) (void)hipFree(a);
+    if (h_sc) (void)hipHostFree(h_sc);
+  }
+};
+
+#define TOPO_ALLOC(ptr, count)                                               \
+  do {                                                                       \
+    if (ctx->alloc(&(ptr), (count)) != hipSuccess) {                         \
+      set_error("device allocation of %s (%zu elements) failed", #ptr,       \
+                (size_t)(count));                                            \
+      return TOPO_ENOMEM;                                                    \
+    }                                                                        \
+  } while (0)
+
+extern "C" void topo_default_opts(topo_opts *o) {
+  if (!o) return;
+  o->precision = TOPO_PREC_FP64;
+  o->precond = TOPO_PRECOND_MG;
+  o->mg_levels = 0;
+  o->mg_max_coarse_dof = 400;
+  o->cheb_degree = 2;
+  o->rtol = 1e-8;
+  o->max_iters = 1000;
+  o->warm_start = 1;
+  o->oc_tol = 1e-12;
+  o->check_every = 1;
+}
+
+extern "C" const char *topo_last_error(void) { return g_err; }
+
+static topo_status validate(const topo_problem *P, const topo_opts *O) {
+  if (!P || !O) return set_error("NULL problem or options"), TOPO_EINVAL;
+  if (P->nelx < 1 || P->nely < 1 || P->nelz < 1)
+    return set_error("grid sizes must be >= 1"), TOPO_EINVAL;
+  const int64_t nel = (int64_t)P->nelx * P->nely * P->nelz;
+  const int64_t ndof = 3 * (int64_t)(P->nelx + 1) * (P->nely + 1) * (P->nelz + 1);
+  if (ndof > ((int64_t)1 << 40)) return set_error("grid too large"), TOPO_EINVAL;
+  if (!(P->E0 > 0) || !(P->Emin > 0) || !(P->Emin < P->E0))
+    return set_error("need 0 < Emin < E0"), TOPO_EINVAL;
+  if (!(P->nu > -1.0 && P->nu < 0.5)) return set_error("nu must lie in (-1, 0.5)"), TOPO_EINVAL;
+  if (!(P->penal >= 1.0)) return set_error("penal must be >= 1"), TOPO_EINVAL;
+  if (!(P->rmin > 0.0) || P->rmin > 16.0) return set_error("rmin must lie in (0, 16]"), TOPO_EINVAL;
+  if (!(P->volfrac > 0.0 && P->volfrac <= 1.0)) return set_error("volfrac must lie in (0, 1]"), TOPO_EINVAL;
+  if (!(P->move > 0.0) || !(P->eta > 0.0)) return set_error("move and eta must be > 0"), TOPO_EINVAL;
+  if (P->filter != TOPO_FILTER_DENSITY && P->filter != TOPO_FILTER_SENSITIVITY)
+    return set_error("unknown filter mode %d", P->filter), TOPO_EINVAL;
+  if (!P->f) return set_error("load vector f is NULL"), TOPO_EINVAL;
+  if (P->n_fixed < 6 || !P->fixed_dofs)
+    return set_error("at least 6 fixed dofs are needed to remove rigid-body motion"), TOPO_EINVAL;
+  for (int64_t i = 0; i < P->n_fixed; ++i)
+    if (P->fixed_dofs[i] < 0 || P->fixed_dofs[i] >= ndof)
+      return set_error("fixed dof %lld out of range [0, %lld)", (long long)P->fixed_dofs[i], (long long)ndof), TOPO_EINVAL;
+  int64_t nd = nel;
+  if (P->mask) {
+    nd = 0;
+    for (int64_t e = 0; e < nel; ++e) {
+      if (P->mask[e] < 0 || P->mask[e] > 2)
+        return set_error("mask value %d at element %lld not in {0,1,2}", (int)P->mask[e], (long long)e), TOPO_EINVAL;
+      nd += P->mask[e] == 0;
+    }
+  }
+  if (nd == 0) return set_error("no design element"), TOPO_EINVAL;
+  if (O->precision != TOPO_PREC_FP64 && O->precision != TOPO_PREC_FP32 && O->precision != TOPO_PREC_BF16)
+    return set_error("unknown precision %d", O->precision), TOPO_EINVAL;
+  if (O->precond != TOPO_PRECOND_JACOBI && O->precond != TOPO_PRECOND_MG)
+    return set_error("unknown preconditioner %d", O->precond), TOPO_EINVAL;
+  if (O->cheb_degree < 1 || O->cheb_degree > 16) return set_error("cheb_degree must lie in [1, 16]"), TOPO_EINVAL;
+  if (!(O->rtol > 0.0) || O->max_iters < 1) return set_error("rtol > 0 and max_iters >= 1 required"), TOPO_EINVAL;
+  if (!(O->oc_tol > 0.0)) return set_error("oc_tol must be > 0"), TOPO_EINVAL;
+  if (O->mg_levels < 0 || O->mg_levels > 16) return set_error("mg_levels must lie in [0, 16]"), TOPO_EINVAL;
+  if (O->precision != TOPO_PREC_FP64) return set_error("only FP64 operators are available"), TOPO_EUNSUPPORTED;
+  return TOPO_OK;
+}
+
+static std::vector<Grid> mg_hierarchy(Grid g, const topo_opts &o) {
+  std::vector<Grid> dims{g};
+  const int cap = o.mg_levels > 0 ? o.mg_levels : 16;
+  while ((int)dims.size() < cap) {
+    const Grid c = dims.back();
+    if (o.mg_levels == 0 && c.ndof() <= o.mg_max_coarse_dof) break;
+    if (std::min(c.nx, std::min(c.ny, c.nz)) < 2) break;
+    dims.push_back(Grid{(c.nx + 1) / 2, (c.ny + 1) / 2, (c.nz + 1) / 2});
+  }
+  return dims;
+}
+
+extern "C" topo_status topo_setup(const topo_problem *P, const topo_opts *O, void *hip_stream,
+                                  topo_ctx **out) {
+  if (!out) return set_error("out is NULL"), TOPO_EINVAL;
+  *out = nullptr;
+  topo_opts defaults;
+  topo_default_opts(&defaults);
+  if (!O) O = &defaults;
+  topo_status st = validate(P, O);
+  if (st != TOPO_OK) return st;
+  std::unique_ptr<topo_ctx> c(new topo_ctx());
+  topo_ctx *ctx = c.get();
+  ctx->prob = *P;
+  ctx->prob.mask = nullptr;
+  ctx->prob.fixed_dofs = nullptr;
+  ctx->prob.f = nullptr;
+  ctx->opts = *O;
+  ctx->stream = (hipStream_t)hip_stream;
+  hipStream_t s = ctx->stream;
+  Grid g{P->nelx, P->nely, P->nelz};
+  ctx->g = g;
+  ctx->nel = g.nel();
+  ctx->nnodes = g.nnodes();
+  ctx->ndof = g.ndof();
+
+  // element stiffness and the Jacobi-scaled bound lambda_max(diag(KE)^-1 KE)
+  double KE[576];
+  element_stiffness(P->nu, KE);
+  double KEd[24];
+  for (int i = 0; i < 24; ++i) KEd[i] = KE[i * 24 + i];
+  {
+    std::vector<double> S(576);
+    for (int i = 0; i < 24; ++i)
+      for (int j = 0; j < 24; ++j) S[i * 24 + j] = KE[i * 24 + j] / std::sqrt(KEd[i] * KEd[j]);
+    ctx->lam_max = sym_max_eig(S, 24);
+  }
+  TOPO_ALLOC(ctx->KE, 576);
+  TOPO_ALLOC(ctx->KEdiag, 24);
+  TOPO_HIP(hipMemcpyAsync(ctx->KE, KE, sizeof KE, hipMemcpyHostToDevice, s));
+  TOPO_HIP(hipMemcpyAsync(ctx->KEdiag, KEd, sizeof KEd, hipMemcpyHostToDevice, s));
+
+  // host-side staging of the problem arrays
+  std::vector<int8_t> hmask(ctx->nel, 0);
+  if (P->mask) std::memcpy(hmask.data(), P->mask, ctx->nel);
+  ctx->n_design = std::count(hmask.begin(), hmask.end(), (int8_t)0);
+  ctx->target = P->volfrac * (double)ctx->n_design;
+  std::vector<uint8_t> hfix(ctx->nnodes, 0);
+  for (int64_t i = 0; i < P->n_fixed; ++i) hfix[P->fixed_dofs[i] / 3] |= (uint8_t)(1u << (P->fixed_dofs[i] % 3));
+  std::vector<double> hf(P->f, P->f + ctx->ndof);
+  for (int64_t n = 0; n < ctx->nnodes; ++n)
+    for (int cc = 0; cc < 3; ++cc)
+      if ((hfix[n] >> cc) & 1) hf[3 * n + cc] = 0.0;  // loads on fixed dofs are eliminated
+  double ff = 0.0;
+  for (double v : hf) ff += v * v;
+  if (ff == 0.0) return set_error("load vector is zero on the free dofs"), TOPO_EINVAL;
+
+  TOPO_ALLOC(ctx->f, ctx->ndof);
+  TOPO_ALLOC(ctx->mask, ctx->nel);
+  TOPO_HIP(hipMemcpyAsync(ctx->f, hf.data(), ctx->ndof * sizeof(double), hipMemcpyHostToDevice, s));
+  TOPO_HIP(hipMemcpyAsync(ctx->mask, hmask.data(), ctx->nel, hipMemcpyHostToDevice, s));
+
+  // multigrid hierarchy (level 0 only when Jacobi is used)
+  std::vector<Grid> dims = O->precond == TOPO_PRECOND_MG ? mg_hierarchy(g, *O) : std::vector<Grid>{g};
+  ctx->lv.resize(dims.size());
+  for (size_t l = 0; l < dims.size(); ++l) {
+    Level &L = ctx->lv[l];
+    L.g = dims[l];
+    TOPO_ALLOC(L.E, L.g.nel());
+    TOPO_ALLOC(L.diag, L.g.ndof());
+    TOPO_ALLOC(L.fixed, L.g.nnodes());
+    TOPO_ALLOC(L.res, L.g.ndof());
+    TOPO_ALLOC(L.d0, L.g.ndof());
+    TOPO_ALLOC(L.d1, L.g.ndof());
+    if (l > 0) {
+      TOPO_ALLOC(L.b, L.g.ndof());
+      TOPO_ALLOC(L.x, L.g.ndof());
+    }
+  }
+  TOPO_HIP(hipMemcpyAsync(ctx->lv[0].fixed, hfix.data(), ctx->nnodes, hipMemcpyHostToDevice, s));
+  for (size_t l = 1; l < dims.size(); ++l)
+    TOPO_HIP(launch_coarse_fixed(s, dims[l - 1], dims[l], ctx->lv[l - 1].fixed, ctx->lv[l].fixed));
+  if (dims.size() > 1) {
+    ctx->ncoarse = (int)dims.back().ndof();
+    if (ctx->ncoarse > 2048) return set_error("coarsest level has %d dofs (> 2048); allow more levels", ctx->ncoarse), TOPO_EINVAL;
+    TOPO_ALLOC(ctx->Ainv, (size_t)ctx->ncoarse * ctx->ncoarse);
+  }
+
+  // CG and SIMP vectors
+  TOPO_ALLOC(ctx->u, ctx->ndof);
+  TOPO_ALLOC(ctx->r, ctx->ndof);
+  TOPO_ALLOC(ctx->z, ctx->ndof);
+  TOPO_ALLOC(ctx->p, ctx->ndof);
+  TOPO_ALLOC(ctx->q, ctx->ndof);
+  TOPO_ALLOC(ctx->tmp, ctx->ndof);
+  TOPO_ALLOC(ctx->xphys, ctx->nel);
+  TOPO_ALLOC(ctx->ce, ctx->nel);
+  TOPO_ALLOC(ctx->dc, ctx->nel);
+  TOPO_ALLOC(ctx->dcf, ctx->nel);
+  TOPO_ALLOC(ctx->oc_a, ctx->nel);
+  TOPO_ALLOC(ctx->xnew, ctx->nel);
+  TOPO_HIP(hipMemsetAsync(ctx->u, 0, ctx->ndof * sizeof(double), s));
+  ctx->lv[0].b = ctx->r;
+  ctx->lv[0].x = ctx->z;
+
+  // reductions
+  const int64_t nb_nodes = (ctx->nnodes + 255) / 256;
+  ctx->red.max_blocks = (int)std::max<int64_t>(4096, nb_nodes + 1);
+  TOPO_ALLOC(ctx->red.partials, (size_t)ctx->red.max_blocks * kMaxRed);
+  TOPO_ALLOC(ctx->red.counter, 8);
+  TOPO_HIP(hipMemsetAsync(ctx->red.counter, 0, 8 * sizeof(unsigned), s));
+  TOPO_ALLOC(ctx->sc, 1);
+  TOPO_HIP(hipMemsetAsync(ctx->sc, 0, sizeof(Scalars), s));
+  if (hipHostMalloc((void **)&ctx->h_sc, sizeof(Scalars), hipHostMallocDefault) != hipSuccess) {
+    ctx->h_sc = nullptr;
+    return set_error("pinned host allocation failed"), TOPO_ENOMEM;
+  }
+
+  // filter stencil: offsets with |d| < rmin, weights rmin - |d|
+  std::vector<int> off;
+  std::vector<double> w;
+  const int R = (int)std::ceil(P->rmin) - 1;
+  for (int dk = -R; dk <= R; ++dk)
+    for (int dj = -R; dj <= R; ++dj)
+      for (int di = -R; di <= R; ++di) {
+        const double d = std::sqrt((double)(di * di + dj * dj + dk * dk));
+        if (d < P->rmin) {
+          off.push_back(di);
+          off.push_back(dj);
+          off.push_back(dk);
+          w.push_back(P->rmin - d);
+        }
+      }
+  TOPO_ALLOC(ctx->d_off, off.size());
+  TOPO_ALLOC(ctx->d_w, w.size());
+  TOPO_ALLOC(ctx->Hs, ctx->nel);
+  TOPO_ALLOC(ctx->sD, ctx->nel);
+  TOPO_ALLOC(ctx->volw, ctx->nel);
+  TOPO_HIP(hipMemcpyAsync(ctx->d_off, off.data(), off.size() * sizeof(int), hipMemcpyHostToDevice, s));
+  TOPO_HIP(hipMemcpyAsync(ctx->d_w, w.data(), w.size() * sizeof(double), hipMemcpyHostToDevice, s));
+  ctx->filt = FilterArgs{g, (int)w.size(), ctx->d_off, ctx->d_w, ctx->Hs, ctx->sD, ctx->mask};
+  TOPO_HIP(launch_filter_hs(s, ctx->filt, ctx->Hs));
+  TOPO_HIP(launch_design_scale(s, ctx->nel, ctx->mask, ctx->Hs, ctx->sD));
+  if (P->filter == TOPO_FILTER_DENSITY) {
+    TOPO_HIP(launch_filter(s, TOPO_FILTER_VOLW, ctx->filt, nullptr, nullptr, ctx->volw));
+  } else {
+    std::vector<double> hv(ctx->nel);
+    for (int64_t e = 0; e < ctx->nel; ++e) hv[e] = hmask[e] == 0 ? 1.0 : 0.0;
+    TOPO_HIP(hipMemcpyAsync(ctx->volw, hv.data(), ctx->nel * sizeof(double), hipMemcpyHostToDevice, s));
+    TOPO_HIP(hipStreamSynchronize(s));  // hv goes out of scope
+  }
+  TOPO_HIP(hipStreamSynchronize(s));
+  *out = c.release();
+  return TOPO_OK;
+}
+
+extern "C" void topo_destroy(topo_ctx *ctx) {
+  if (!ctx) return;
+  (void)hipStreamSynchronize(ctx->stream);
+  delete ctx;
+}
+
+extern "C" topo_status topo_sizes(const topo_ctx *ctx, int64_t *nel, int64_t *ndof, int32_t *levels) {
+  if (!ctx) return set_error("ctx is NULL"), TOPO_EINVAL;
+  if (nel) *nel = ctx->nel;
+  if (ndof) *ndof = ctx->ndof;
+  if (levels) *levels = (int32_t)ctx->lv.size();
+  return TOPO_OK;
+}
+
+// ---------------------------------------------------------------------------
+static KuArgs ku_args(topo_ctx *ctx, const Level &L, const double *u) {
+  KuArgs a{};
+  a.g = L.g;
+  a.E = L.E;
+  a.KE = ctx->KE;
+  a.u = u;
+  a.fixed = L.fixed;
+  a.diag = L.diag;
+  return a;
+}
+
+// level-0 modulus from xphys, then the coarse moduli, diagonals and coarse inverse
+static topo_status prepare_operator(topo_ctx *ctx, const double *d_xphys) {
+  hipStream_t s = ctx->stream;
+  const topo_problem &P = ctx->prob;
+  TOPO_HIP(launch_simp_modulus(s, ctx->nel, d_xphys, P.E0, P.Emin, P.penal, 1.0, ctx->lv[0].E));
+  for (size_t l = 0; l < ctx->lv.size(); ++l) {
+    Level &L = ctx->lv[l];
+    if (l > 0) TOPO_HIP(launch_coarsen_moduli(s, ctx->lv[l - 1].g, L.g, ctx->lv[l - 1].E, L.E));
+    TOPO_HIP(launch_diag(s, L.g, L.E, ctx->KEdiag, L.fixed, L.diag));
+  }
+  if (ctx->lv.size() > 1) {
+    const Level &C = ctx->lv.back();
+    TOPO_HIP(launch_dense_assemble(s, C.g, C.E, ctx->KE, C.fixed, ctx->Ainv));
+    TOPO_HIP(launch_dense_invert(s, ctx->ncoarse, ctx->Ainv));
+  }
+  return TOPO_OK;
+}
+
+// Chebyshev smoothing on level L for A x = b.  from_zero: x starts at 0 (pre-
+// smoothing); otherwise x holds the current iterate (post-smoothing).  On exit
+// L.res = b - A x when want_res.
+static topo_status cheb_smooth(topo_ctx *ctx, Level &L, bool from_zero, bool want_res) {
+  hipStream_t s = ctx->stream;
+  const int deg = ctx->opts.cheb_degree;
+  const double hi = ctx->lam_max, lo = hi / 30.0;
+  const double theta = 0.5 * (hi + lo), delta = 0.5 * (hi - lo), sigma = theta / delta;
+  double rho = 1.0 / sigma;
+  const int64_t n = L.g.ndof();
+  double *din = L.d0, *dout = L.d1;
+  if (from_zero) {
+    TOPO_HIP(launch_cheb_first(s, n, L.b, L.diag, 1.0 / theta, din, L.x, L.res));
+  } else {
+    KuArgs a = ku_args(ctx, L, L.x);
+    a.y = L.res;
+    a.b = L.b;
+    TOPO_HIP(launch_ku(s, KU_RESID, a, ctx->red, &ctx->sc->red[0]));
+    TOPO_HIP(launch_cheb_start(s, n, L.res, L.diag, 1.0 / theta, din, L.x));
+  }
+  for (int k = 1; k < deg; ++k) {
+    const double rho_new = 1.0 / (2.0 * sigma - rho);
+    KuArgs a = ku_args(ctx, L, din);
+    a.res = L.res;
+    a.x = L.x;
+    a.dout = dout;
+    a.c1 = rho_new * rho;
+    a.c2 = 2.0 * rho_new / delta;
+    TOPO_HIP(launch_ku(s, KU_CHEB, a, ctx->red, nullptr));
+    std::swap(din, dout);
+    rho = rho_new;
+  }
+  if (want_res) {
+    KuArgs a = ku_args(ctx, L, din);
+    a.res = L.res;
+    TOPO_HIP(launch_ku(s, KU_RESUPD, a, ctx->red, nullptr));
+  }
+  return TOPO_OK;
+}
+
+// z = M r: V-cycle from level l with rhs lv[l].b into lv[l].x
+static topo_status vcycle(topo_ctx *ctx, size_t l) {
+  hipStream_t s = ctx->stream;
+  Level &L = ctx->lv[l];
+  if (l + 1 == ctx->lv.size()) {
+    TOPO_HIP(launch_dense_matvec(s, ctx->ncoarse, ctx->Ainv, L.b, L.x));
+    return TOPO_OK;
+  }
+  topo_status st = cheb_smooth(ctx, L, true, true);
+  if (st != TOPO_OK) return st;
+  Level &C = ctx->lv[l + 1];
+  TOPO_HIP(launch_restrict(s, L.g, C.g, L.res, C.fixed, C.b));
+  st = vcycle(ctx, l + 1);
+  if (st != TOPO_OK) return st;
+  TOPO_HIP(launch_prolong_add(s, L.g, C.g, C.x, L.fixed, L.x));
+  return cheb_smooth(ctx, L, false, false);
+}
+
+// z = M r and sc->rz_new = r.z
+static topo_status precondition(topo_ctx *ctx) {
+  hipStream_t s = ctx->stream;
+  Level &L0 = ctx->lv[0];
+  if (ctx->opts.precond == TOPO_PRECOND_JACOBI || ctx->lv.size() == 1) {
+    TOPO_HIP(launch_jacobi(s, ctx->ndof, ctx->r, L0.diag, ctx->z, ctx->red, &ctx->sc->rz_new));
+    return TOPO_OK;
+  }
+  topo_status st = vcycle(ctx, 0);
+  if (st != TOPO_OK) return st;
+  TOPO_HIP(launch_dot(s, ctx->ndof, ctx->r, ctx->z, ctx->red, &ctx->sc->rz_new));
+  return TOPO_OK;
+}
+
+static topo_status read_scalars(topo_ctx *ctx) {
+  TOPO_HIP(hipMemcpyAsync(ctx->h_sc, ctx->sc, sizeof(Scalars), hipMemcpyDeviceToHost, ctx->stream));
+  TOPO_HIP(hipStreamSynchronize(ctx->stream));
+  return TOPO_OK;
+}
+
+// PCG on the operator prepared by prepare_operator; solution in/out d_u.
+static topo_status pcg(topo_ctx *ctx, double *d_u, topo_solve_stats *stats) {
+  hipStream_t s = ctx->stream;
+  Level &L0 = ctx->lv[0];
+  const int64_t n = ctx->ndof;
+  TOPO_HIP(launch_zero_fixed(s, ctx->nnodes, L0.fixed, d_u));
+  // r = f - K u, rr
+  {
+    KuArgs a = ku_args(ctx, L0, d_u);
+    a.y = ctx->r;
+    a.b = ctx->f;
+    TOPO_HIP(launch_ku(s, KU_RESID, a, ctx->red, &ctx->sc->rr));
+  }
+  TOPO_HIP(launch_dot(s, n, ctx->f, ctx->f, ctx->red, &ctx->sc->ff));
+  topo_status st = read_scalars(ctx);
+  if (st != TOPO_OK) return st;
+  const double fnorm = std::sqrt(ctx->h_sc->ff);
+  double relres = std::sqrt(ctx->h_sc->rr) / fnorm;
+  int it = 0;
+  const int check = std::max(1, ctx->opts.check_every);
+  if (relres > ctx->opts.rtol) {
+    st = precondition(ctx);
+    if (st != TOPO_OK) return st;
+    TOPO_HIP(launch_cg_update_p(s, n, ctx->sc, ctx->z, ctx->p, 1));
+    while (it < ctx->opts.max_iters) {
+      KuArgs a = ku_args(ctx, L0, ctx->p);
+      a.y = ctx->q;
+      TOPO_HIP(launch_ku(s, KU_STORE_DOT, a, ctx->red, &ctx->sc->pq));
+      TOPO_HIP(launch_cg_update_xr(s, n, ctx->sc, d_u, ctx->r, ctx->p, ctx->q, ctx->red));
+      ++it;
+      if (it % check == 0 || it == ctx->opts.max_iters) {
+        st = read_scalars(ctx);
+        if (st != TOPO_OK) return st;
+        relres = std::sqrt(ctx->h_sc->rr) / fnorm;
+        if (!(relres > ctx->opts.rtol) || !std::isfinite(relres)) break;
+      }
+      st = precondition(ctx);
+      if (st != TOPO_OK) return st;
+      TOPO_HIP(launch_cg_update_p(s, n, ctx->sc, ctx->z, ctx->p, 0));
+    }
+  }
+  if (stats) {
+    stats->iters = it;
+    stats->relres = relres;
+    stats->converged = relres <= ctx->opts.rtol;
+  }
+  if (!std::isfinite(relres)) return set_error("CG diverged (non-finite residual)"), TOPO_ENOTCONVERGED;
+  if (relres > ctx->opts.rtol)
+    return set_error("CG reached max_iters=%d with relres %.3e", ctx->opts.max_iters, relres), TOPO_ENOTCONVERGED;
+  return TOPO_OK;
+}
+
+extern "C" topo_status topo_apply_K(topo_ctx *ctx, const double *d_xphys, const double *d_u, double *d_y) {
+  if (!ctx || !d_xphys || !d_u || !d_y) return set_error("NULL argument"), TOPO_EINVAL;
+  if (d_u == d_y) return set_error("d_u and d_y must not alias"), TOPO_EINVAL;
+  hipStream_t s = ctx->stream;
+  const topo_problem &P = ctx->prob;
+  Level &L0 = ctx->lv[0];
+  TOPO_HIP(launch_simp_modulus(s, ctx->nel, d_xphys, P.E0, P.Emin, P.penal, 1.0, L0.E));
+  TOPO_HIP(launch_copy_masked(s, ctx->nnodes, L0.fixed, d_u, ctx->tmp));
+  KuArgs a = ku_args(ctx, L0, ctx->tmp);
+  a.y = d_y;
+  TOPO_HIP(launch_ku(s, KU_STORE, a, ctx->red, nullptr));
+  // identity rows return the caller's u (not the zeroed copy) on fixed dofs
+  TOPO_HIP(launch_copy_fixed(s, ctx->nnodes, L0.fixed, d_u, d_y));
+  return TOPO_OK;
+}
+
+extern "C" topo_status topo_apply_precond(topo_ctx *ctx, const double *d_xphys, const double *d_r,
+                                          double *d_z) {
+  if (!ctx || !d_xphys || !d_r || !d_z) return set_error("NULL argument"), TOPO_EINVAL;
+  if (d_r == d_z) return set_error("d_r and d_z must not alias"), TOPO_EINVAL;
+  hipStream_t s = ctx->stream;
+  topo_status st = prepare_operator(ctx, d_xphys);
+  if (st != TOPO_OK) return st;
+  TOPO_HIP(hipMemcpyAsync(ctx->r, d_r, ctx->ndof * sizeof(double), hipMemcpyDeviceToDevice, s));
+  st = precondition(ctx);
+  if (st != TOPO_OK) return st;
+  TOPO_HIP(hipMemcpyAsync(d_z, ctx->z, ctx->ndof * sizeof(double), hipMemcpyDeviceToDevice, s));
+  return TOPO_OK;
+}
+
+extern "C" topo_status topo_solve(topo_ctx *ctx, const double *d_xphys, double *d_u, topo_solve_stats *st_out) {
+  if (!ctx || !d_xphys || !d_u) return set_error("NULL argument"), TOPO_EINVAL;
+  hipEvent_t e0, e1;
+  TOPO_HIP(hipEventCreate(&e0));
+  TOPO_HIP(hipEventCreate(&e1));
+  TOPO_HIP(hipEventRecord(e0, ctx->stream));
+  topo_status st = prepare_operator(ctx, d_xphys);
+  topo_solve_stats stats{};
+  if (st == TOPO_OK) st = pcg(ctx, d_u, &stats);
+  (void)hipEventRecord(e1, ctx->stream);
+  (void)hipEventSynchronize(e1);
+  float ms = 0.f;
+  (void)hipEventElapsedTime(&ms, e0, e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  stats.ms = ms;
+  if (st_out) *st_out = stats;
+  return st;
+}
+
+extern "C" topo_status topo_sensitivity(topo_ctx *ctx, const double *d_xphys, const double *d_u,
+                                        double *d_ce, double *d_dc, double *h_compliance) {
+  if (!ctx || !d_xphys || !d_u || !d_ce || !d_dc) return set_error("NULL argument"), TOPO_EINVAL;
+  hipStream_t s = ctx->stream;
+  const topo_problem &P = ctx->prob;
+  TOPO_HIP(launch_sensitivity(s, ctx->g, ctx->KE, d_u, d_xphys, P.E0, P.Emin, P.penal, d_ce, d_dc));
+  if (h_compliance) {
+    TOPO_HIP(launch_dot(s, ctx->ndof, ctx->f, d_u, ctx->red, &ctx->sc->comp));
+    topo_status st = read_scalars(ctx);
+    if (st != TOPO_OK) return st;
+    *h_compliance = ctx->h_sc->comp;
+  }
+  return TOPO_OK;
+}
+
+extern "C" topo_status topo_filter(topo_ctx *ctx, int32_t op, const double *d_in, const double *d_aux,
+                                   double *d_out) {
+  if (!ctx || !d_out) return set_error("NULL argument"), TOPO_EINVAL;
+  if (op < TOPO_FILTER_FWD || op > TOPO_FILTER_VOLW) return set_error("unknown filter op %d", op), TOPO_EINVAL;
+  if (op != TOPO_FILTER_VOLW && !d_in) return set_error("d_in is NULL"), TOPO_EINVAL;
+  if (op == TOPO_FILTER_SENS && !d_aux) return set_error("d_aux (x) is NULL"), TOPO_EINVAL;
+  if (d_out == d_in || (d_aux && d_out == d_aux)) return set_error("d_out must not alias an input"), TOPO_EINVAL;
+  TOPO_HIP(launch_filter(ctx->stream, op, ctx->filt, d_in, d_aux, d_out));
+  return TOPO_OK;
+}
+
+static topo_status oc_update(topo_ctx *ctx, const double *d_x, const double *d_dc, const double *d_dv,
+                             double *d_xnew) {
+  hipStream_t s = ctx->stream;
+  const topo_problem &P = ctx->prob;
+  TOPO_HIP(launch_oc_prepare(s, ctx->nel, d_x, d_dc, d_dv, ctx->mask, P.eta, ctx->target, ctx->oc_a,
+                             ctx->sc, ctx->red));
+  // worst case: 1e80 bracket, geometric passes shrink by 64x in log, linear by 64x
+  for (int pass = 0; pass < 16; ++pass)
+    TOPO_HIP(launch_oc_pass(s, ctx->nel, d_x, ctx->oc_a, d_dv, ctx->mask, P.move, P.eta,
+                            ctx->opts.oc_tol, ctx->sc, ctx->red));
+  TOPO_HIP(launch_oc_final(s, ctx->nel, d_x, ctx->oc_a, d_dv, ctx->mask, P.move, P.eta, d_xnew,
+                           ctx->sc, ctx->red));
+  return TOPO_OK;
+}
+
+extern "C" topo_status topo_oc_update(topo_ctx *ctx, const double *d_x, const double *d_dc,
+                                      const double *d_dv, double *d_xnew, double *h_change,
+                                      double *h_lambda) {
+  if (!ctx || !d_x || !d_dc || !d_dv || !d_xnew) return set_error("NULL argument"), TOPO_EINVAL;
+  if (d_xnew == d_x || d_xnew == d_dc || d_xnew == d_dv) return set_error("d_xnew must not alias an input"), TOPO_EINVAL;
+  topo_status st = oc_update(ctx, d_x, d_dc, d_dv, d_xnew);
+  if (st != TOPO_OK) return st;
+  if (h_change || h_lambda) {
+    st = read_scalars(ctx);
+    if (st != TOPO_OK) return st;
+    if (h_change) *h_change = ctx->h_sc->change;
+    if (h_lambda) *h_lambda = ctx->h_sc->lambda;
+  }
+  return TOPO_OK;
+}
+
+extern "C" topo_status topo_iterate(topo_ctx *ctx, double *d_x, int32_t n_iter, topo_iter_stats *h_stats) {
+  if (!ctx || !d_x || n_iter < 0) return set_error("invalid argument"), TOPO_EINVAL;
+  hipStream_t s = ctx->stream;
+  const topo_problem &P = ctx->prob;
+  hipEvent_t ev[6];
+  for (auto &e : ev) TOPO_HIP(hipEventCreate(&e));
+  topo_status result = TOPO_OK;
+  for (int it = 0; it < n_iter; ++it) {
+    (void)hipEventRecord(ev[0], s);
+    // physical density
+    if (P.filter == TOPO_FILTER_DENSITY) {
+      TOPO_HIP(launch_filter(s, TOPO_FILTER_FWD, ctx->filt, d_x, nullptr, ctx->xphys));
+    } else {
+      TOPO_HIP(hipMemcpyAsync(ctx->xphys, d_x, ctx->nel * sizeof(double), hipMemcpyDeviceToDevice, s));
+    }
+    (void)hipEventRecord(ev[1], s);
+    // modulus, operator hierarchy and solve (warm start from the last u)
+    if (!ctx->opts.warm_start || !ctx->have_u) TOPO_HIP(hipMemsetAsync(ctx->u, 0, ctx->ndof * sizeof(double), s));
+    topo_status st = prepare_operator(ctx, ctx->xphys);
+    topo_solve_stats ss{};
+    if (st == TOPO_OK) st = pcg(ctx, ctx->u, &ss);
+    if (st != TOPO_OK && st != TOPO_ENOTCONVERGED) return st;
+    if (st == TOPO_ENOTCONVERGED) result = st;
+    ctx->have_u = 1;
+    (void)hipEventRecord(ev[2], s);
+    // sensitivities and compliance
+    TOPO_HIP(launch_sensitivity(s, ctx->g, ctx->KE, ctx->u, ctx->xphys, P.E0, P.Emin, P.penal, ctx->ce, ctx->dc));
+    TOPO_HIP(launch_dot(s, ctx->ndof, ctx->f, ctx->u, ctx->red, &ctx->sc->comp));
+    (void)hipEventRecord(ev[3], s);
+    // filtered sensitivities and OC update
+    if (P.filter == TOPO_FILTER_DENSITY)
+      TOPO_HIP(launch_filter(s, TOPO_FILTER_ADJ, ctx->filt, ctx->dc, nullptr, ctx->dcf));
+    else
+      TOPO_HIP(launch_filter(s, TOPO_FILTER_SENS, ctx->filt, ctx->dc, d_x, ctx->dcf));
+    (void)hipEventRecord(ev[4], s);
+    st = oc_update(ctx, d_x, ctx->dcf, ctx->volw, ctx->xnew);
+    if (st != TOPO_OK) return st;
+    TOPO_HIP(hipMemcpyAsync(d_x, ctx->xnew, ctx->nel * sizeof(double), hipMemcpyDeviceToDevice, s));
+    (void)hipEventRecord(ev[5], s);
+    if (h_stats) {
+      st = read_scalars(ctx);
+      if (st != TOPO_OK) return st;
+      topo_iter_stats &o = h_stats[it];
+      o.c = ctx->h_sc->comp;
+      o.volume = ctx->h_sc->volume;
+      o.change = ctx->h_sc->change;
+      o.lambda = ctx->h_sc->lambda;
+      o.pcg_iters = ss.iters;
+      o.converged = ss.converged;
+      o.relres = ss.relres;
+      float t[5];
+      for (int k = 0; k < 5; ++k) (void)hipEventElapsedTime(&t[k], ev[k], ev[k + 1]);
+      float tot = 0.f;
+      (void)hipEventElapsedTime(&tot, ev[0], ev[5]);
+      o.ms_total = tot;
+      o.ms_filter = t[0] + t[3];
+      o.ms_solve = t[1];
+      o.ms_sens = t[2];
+      o.ms_oc = t[4];
+    }
+  }
+  TOPO_HIP(hipStreamSynchronize(s));
+  for (auto &e : ev) (void)hipEventDestroy(e);
+  return result;
+}
+
+extern "C" topo_status topo_get_state(topo_ctx *ctx, double *d_u, double *d_xphys) {
+  if (!ctx) return set_error("ctx is NULL"), TOPO_EINVAL;
+  if (d_u) TOPO_HIP(hipMemcpyAsync(d_u, ctx->u, ctx->ndof * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
+  if (d_xphys) TOPO_HIP(hipMemcpyAsync(d_xphys, ctx->xphys, ctx->nel * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
+  return TOPO_OK;
+}

@@ -1,0 +1,90 @@
+"""Host-side checks of the C ABI: the library loads, exports every entry point the
+header declares, and rejects invalid problems before any device work."""
+
+import ctypes as C
+import re
+
+import numpy as np
+import pytest
+
+import synth
+import paper_2504_05604_amd as pkg
+from paper_2504_05604_amd import _lib
+
+
+def declared_functions():
+    text = open("include/topo.h").read()
+    return sorted(set(re.findall(r"\b(topo_[a-z_A-Z]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = pkg.load()
+    names = declared_functions()
+    assert len(names) >= 12
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(names) == set(_lib.EXPORTED)
+
+
+def test_default_opts():
+    o = pkg.default_opts()
+    assert o.precision == pkg.PREC_FP64 and o.precond == pkg.PRECOND_MG
+    assert o.rtol == 1e-8 and o.oc_tol == 1e-12 and o.cheb_degree == 2
+
+
+def setup_status(p, **opt):
+    lib = pkg.load()
+    mask = None if p.mask is None else np.ascontiguousarray(p.mask, np.int8)
+    fixed = np.ascontiguousarray(p.fixed_dofs, np.int64)
+    f = np.ascontiguousarray(p.f, np.float64)
+    pc = _lib.Problem_C(p.nelx, p.nely, p.nelz, p.E0, p.Emin, p.nu, p.penal, p.rmin, p.volfrac,
+                        p.move, p.eta, 0,
+                        None if mask is None else mask.ctypes.data_as(C.POINTER(C.c_int8)),
+                        fixed.ctypes.data_as(C.POINTER(C.c_int64)), fixed.size,
+                        f.ctypes.data_as(C.POINTER(C.c_double)))
+    o = pkg.default_opts(**opt)
+    h = C.c_void_p()
+    st = lib.topo_setup(C.byref(pc), C.byref(o), None, C.byref(h))
+    return st, lib.topo_last_error().decode(), h
+
+
+@pytest.mark.parametrize("field,value,msg", [
+    ("nelx", 0, "grid sizes"), ("rmin", -1.0, "rmin"), ("volfrac", 1.5, "volfrac"),
+    ("Emin", 0.0, "Emin"), ("nu", 0.5, "nu"), ("move", 0.0, "move"), ("penal", 0.5, "penal"),
+])
+def test_setup_rejects_invalid_scalars(field, value, msg):
+    p = synth.config_small()
+    setattr(p, field, value)
+    if field == "nelx":
+        p.f = np.zeros(3 * (1) * (p.nely + 1) * (p.nelz + 1))
+    st, err, h = setup_status(p)
+    assert st == _lib.TOPO_EINVAL and msg in err
+    assert not h.value
+
+
+def test_setup_rejects_bad_mask_and_fixed_dofs():
+    p = synth.config_small()
+    p.mask = np.zeros(p.nel, np.int8)
+    p.mask[3] = 5
+    st, err, _ = setup_status(p)
+    assert st == _lib.TOPO_EINVAL and "mask value" in err
+    p = synth.config_small()
+    p.fixed_dofs = np.array([0, 1, 2, p.ndof], np.int64)
+    st, err, _ = setup_status(p)
+    assert st == _lib.TOPO_EINVAL
+    p = synth.config_small()
+    p.fixed_dofs = p.fixed_dofs[:3]
+    st, err, _ = setup_status(p)
+    assert st == _lib.TOPO_EINVAL and "rigid-body" in err
+    p = synth.config_small()
+    p.mask = np.ones(p.nel, np.int8)
+    st, err, _ = setup_status(p)
+    assert st == _lib.TOPO_EINVAL and "no design element" in err
+
+
+def test_setup_rejects_bad_options():
+    p = synth.config_small()
+    for kw, msg in [({"cheb_degree": 0}, "cheb_degree"), ({"rtol": 0.0}, "rtol"),
+                    ({"precond": 9}, "preconditioner"), ({"precision": 7}, "precision")]:
+        st, err, _ = setup_status(p, **kw)
+        assert st == _lib.TOPO_EINVAL and msg in err, (kw, err)

@@ -1,0 +1,226 @@
+"""GPU parity: every entry point of the C ABI against the CPU FP64 oracle on the
+same seeded inputs (small grids spanning several blocks with ragged tails, plus
+sampled outputs at the 160x80x80 size)."""
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import fem, filt, mg, oc, simp
+from oracle.ke import element_stiffness
+
+torch = pytest.importorskip("torch")
+import paper_2504_05604_amd as topo  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+KE = element_stiffness(0.3)
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to("cuda")
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def ragged_problem(seed=0, dims=(13, 7, 5), rmin=2.0, passive=True):
+    """Odd-sized grid, a clamped face plus a few extra fixed dofs, random passive elements."""
+    q = synth.cantilever(*dims, volfrac=0.3, rmin=rmin, n_iter=5)
+    rng = np.random.default_rng(seed)
+    extra = rng.choice(q.ndof, 7, replace=False)
+    q.fixed_dofs = np.unique(np.concatenate([q.fixed_dofs, extra])).astype(np.int64)
+    q.f = synth.random_vector(seed + 1, q.ndof)
+    if passive:
+        m = np.zeros(q.nel, np.int8)
+        m[rng.random(q.nel) < 0.08] = 1
+        m[rng.random(q.nel) < 0.03] = 2
+        q.mask = m
+    return q
+
+
+def fixed_mask(p):
+    fm = np.zeros(p.ndof, bool)
+    fm[p.fixed_dofs] = True
+    return fm
+
+
+CASES = ["small", "ragged", "ragged_odd"]
+
+
+def make_case(name):
+    if name == "small":
+        return synth.config_small()
+    if name == "ragged":
+        return ragged_problem(1, (13, 7, 5))
+    return ragged_problem(2, (17, 9, 11), rmin=3.0)
+
+
+@pytest.mark.parametrize("case", CASES)
+def test_apply_K_matches_oracle(case):
+    p = make_case(case)
+    x = synth.random_density(3, p.nel, 0.0, 1.0)
+    u = synth.random_vector(4, p.ndof)
+    E = fem.simp_modulus(x, p.E0, p.Emin, p.penal)
+    ref = fem.apply_K_reduced(E, KE, fem.element_dofs(p.nelx, p.nely, p.nelz), u, p.fixed_dofs)
+    with topo.Context(p) as ctx:
+        y = torch.empty(p.ndof, dtype=torch.float64, device="cuda")
+        ctx.apply_K(dev(x), dev(u), y)
+        got = host(y)
+    assert np.abs(got - ref).max() <= 1e-13 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("case", CASES)
+@pytest.mark.parametrize("precond", ["mg", "jacobi"])
+def test_preconditioner_matches_oracle(case, precond):
+    p = make_case(case)
+    x = synth.random_density(5, p.nel, 0.0, 1.0)
+    E = fem.simp_modulus(x, p.E0, p.Emin, p.penal)
+    r = synth.random_vector(6, p.ndof)
+    r[fixed_mask(p)] = 0.0
+    if precond == "mg":
+        V = mg.VCycle(p, E, KE, degree=2, max_coarse_dof=400)
+        ref = V.apply(r)
+        opts = topo.default_opts(precond=topo.PRECOND_MG)
+    else:
+        K = mg.with_identity_rows(fem.assemble(E, KE, fem.element_dofs(p.nelx, p.nely, p.nelz), p.ndof),
+                                  fixed_mask(p))
+        ref = r / K.diagonal()
+        opts = topo.default_opts(precond=topo.PRECOND_JACOBI)
+    with topo.Context(p, opts) as ctx:
+        if precond == "mg":
+            assert ctx.mg_levels == len(V.levels)
+        z = torch.empty(p.ndof, dtype=torch.float64, device="cuda")
+        ctx.apply_precond(dev(x), dev(r), z)
+        got = host(z)
+    assert np.abs(got - ref).max() <= 1e-11 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("case", CASES)
+@pytest.mark.parametrize("precond", ["mg", "jacobi"])
+def test_solve_matches_direct_solve(case, precond):
+    p = make_case(case)
+    x = synth.random_density(7, p.nel, 0.05, 1.0)
+    E = fem.simp_modulus(x, p.E0, p.Emin, p.penal)
+    K = fem.assemble(E, KE, fem.element_dofs(p.nelx, p.nely, p.nelz), p.ndof)
+    f = p.f.copy()
+    f[p.fixed_dofs] = 0.0
+    uref = fem.solve(K, f, p.fixed_dofs)
+    opts = topo.default_opts(rtol=1e-11, max_iters=5000,
+                             precond=topo.PRECOND_MG if precond == "mg" else topo.PRECOND_JACOBI)
+    with topo.Context(p, opts) as ctx:
+        u = torch.zeros(p.ndof, dtype=torch.float64, device="cuda")
+        st = ctx.solve(dev(x), u)
+        got = host(u)
+    assert st["converged"] and st["relres"] <= 1e-11
+    # true residual of the GPU solution, computed by the oracle
+    free = fem.free_dofs(p.ndof, p.fixed_dofs)
+    res = (f - K @ got)[free]
+    assert np.linalg.norm(res) <= 2e-11 * np.linalg.norm(f)
+    assert np.linalg.norm(got - uref) <= 1e-7 * np.linalg.norm(uref)
+    assert abs(f @ got - f @ uref) <= 1e-9 * abs(f @ uref)
+
+
+@pytest.mark.parametrize("case", CASES)
+def test_sensitivity_matches_oracle(case):
+    p = make_case(case)
+    x = synth.random_density(8, p.nel, 0.0, 1.0)
+    u = synth.random_vector(9, p.ndof)
+    u[p.fixed_dofs] = 0.0
+    edof = fem.element_dofs(p.nelx, p.nely, p.nelz)
+    ce_ref = fem.element_energy(KE, edof, u)
+    dc_ref = fem.compliance_sensitivity(x, ce_ref, p.E0, p.Emin, p.penal)
+    f = p.f.copy()
+    f[p.fixed_dofs] = 0.0
+    with topo.Context(p) as ctx:
+        ce = torch.empty(p.nel, dtype=torch.float64, device="cuda")
+        dc = torch.empty(p.nel, dtype=torch.float64, device="cuda")
+        c = ctx.sensitivity(dev(x), dev(u), ce, dc)
+        ce_g, dc_g = host(ce), host(dc)
+    np.testing.assert_allclose(ce_g, ce_ref, rtol=1e-12, atol=1e-14 * np.abs(ce_ref).max())
+    np.testing.assert_allclose(dc_g, dc_ref, rtol=1e-12, atol=1e-14 * np.abs(dc_ref).max())
+    assert abs(c - f @ u) <= 1e-12 * np.abs(f).sum() * np.abs(u).max()
+
+
+@pytest.mark.parametrize("rmin", [1.5, 2.0, 3.0, 4.0])
+@pytest.mark.parametrize("dims", [(11, 7, 6), (20, 10, 4)])
+def test_filter_ops_match_oracle(rmin, dims):
+    p = ragged_problem(11, dims, rmin=rmin)
+    F = filt.Filter(*dims, rmin, p.mask)
+    x = synth.random_density(12, p.nel, 0.0, 1.0)
+    g = synth.random_vector(13, p.nel)
+    refs = {topo.FILTER_FWD: F.forward(x), topo.FILTER_ADJ: F.adjoint(g),
+            topo.FILTER_SENS: F.sensitivity(x, g), topo.FILTER_VOLW: F.volume_weights()}
+    with topo.Context(p) as ctx:
+        out = torch.empty(p.nel, dtype=torch.float64, device="cuda")
+        for op, ref in refs.items():
+            inp = dev(x) if op == topo.FILTER_FWD else dev(g)
+            ctx.filter(op, inp, out, aux=dev(x) if op == topo.FILTER_SENS else None)
+            got = host(out)
+            np.testing.assert_allclose(got, ref, rtol=1e-13, atol=1e-15 * np.abs(ref).max(), err_msg=str(op))
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+@pytest.mark.parametrize("move", [0.2, 0.05])
+def test_oc_update_matches_exact_multiplier(seed, move):
+    p = ragged_problem(20 + seed, (23, 11, 9), rmin=2.0)
+    p.move = move
+    F = filt.Filter(p.nelx, p.nely, p.nelz, p.rmin, p.mask)
+    design = p.mask == 0
+    rng = np.random.default_rng(seed)
+    x = p.initial_design()
+    x[design] = rng.uniform(0.0, 1.0, design.sum())
+    x[design & (rng.random(p.nel) < 0.05)] = 0.0
+    dc = F.adjoint(-rng.exponential(1.0, p.nel) * 10 ** rng.uniform(-3, 2))
+    w = F.volume_weights()
+    target = p.volfrac * design.sum()
+    xref, lam_ref = oc.oc_exact(x, dc, w, w, target, p.move, p.eta, design)
+    with topo.Context(p) as ctx:
+        xn = torch.empty(p.nel, dtype=torch.float64, device="cuda")
+        chg, lam = ctx.oc_update(dev(x), dev(dc), dev(w), xn)
+        got = host(xn)
+    assert abs(lam - lam_ref) <= 1e-10 * lam_ref
+    np.testing.assert_allclose(got, xref, atol=1e-10)
+    assert np.array_equal(got[~design], x[~design])
+    assert abs(chg - np.abs(xref - x).max()) <= 1e-10
+    assert abs(w @ got - target) <= 1e-9 * target
+
+
+def run_gpu_trajectory(p, n_iter, **opt):
+    opts = topo.default_opts(rtol=1e-11, max_iters=5000, **opt)
+    with topo.Context(p, opts) as ctx:
+        x = dev(p.initial_design())
+        stats = ctx.iterate(x, n_iter)
+        return host(x), stats
+
+
+@pytest.mark.parametrize("precond", ["mg", "jacobi"])
+def test_iterate_matches_oracle_trajectory_small_cantilever(precond):
+    p = synth.config_small()
+    xo, hist = simp.SimpOracle(p).trajectory()
+    xg, stats = run_gpu_trajectory(p, p.n_iter,
+                                   precond=topo.PRECOND_MG if precond == "mg" else topo.PRECOND_JACOBI)
+    for h, s in zip(hist, stats):
+        assert s["converged"]
+        assert abs(s["c"] - h["c"]) <= 1e-8 * h["c"]
+        assert abs(s["lambda"] - h["lam"]) <= 1e-7 * h["lam"]
+        assert abs(s["change"] - h["change"]) <= 1e-7
+        assert abs(s["volume"] - h["volume"]) <= 1e-8 * h["volume"]
+    np.testing.assert_allclose(xg, xo, atol=1e-7)
+
+
+@pytest.mark.parametrize("mode", ["density", "sensitivity"])
+def test_iterate_matches_oracle_with_passive_elements(mode):
+    p = ragged_problem(30, (16, 8, 6), rmin=2.0)
+    p.f = np.zeros(p.ndof)
+    p.f[3 * int(p.node_id(16, 0, 3)) + 1] = -1.0
+    p.mask[p.mask == 2] = 0
+    p.filter_mode = mode
+    n = 6
+    xo, hist = simp.SimpOracle(p).trajectory(n)
+    xg, stats = run_gpu_trajectory(p, n)
+    for h, s in zip(hist, stats):
+        assert abs(s["c"] - h["c"]) <= 1e-8 * h["c"], (s["c"], h["c"])
+    np.testing.assert_allclose(xg, xo, atol=1e-7)
+    assert np.all(xg[p.mask == 1] == 0.0)

@@ -154,3 +154,19 @@ def test_sensitivity_matches_finite_differences(mode):
             xm[j] -= h
             fd = (comp(xp) - comp(xm)) / (2 * h)
             assert abs(fd - r["dc"][j]) <= 1e-6 * np.abs(r["dc"]).max(), j
+
+
+def test_sampled_rows_equal_assembled_product():
+    p = synth.config_obstacle(seed=7)
+    p.nelx, p.nely, p.nelz = 9, 5, 4
+    p.mask = None
+    E = np.random.default_rng(2).uniform(0.01, 1, 180)
+    edof = fem.element_dofs(9, 5, 4)
+    ndof = 3 * 10 * 6 * 5
+    u = synth.random_vector(3, ndof)
+    fixed = np.zeros(ndof, bool)
+    fixed[np.random.default_rng(4).choice(ndof, 20, replace=False)] = True
+    y = fem.apply_K_reduced(E, KE, edof, u, np.nonzero(fixed)[0])
+    nodes = np.array([0, 7, 33, 150, 299])
+    np.testing.assert_allclose(fem.apply_K_rows(E, KE, (9, 5, 4), u, nodes, fixed),
+                               y.reshape(-1, 3)[nodes], atol=1e-13)

@@ -77,3 +77,12 @@ def test_sensitivity_filter_of_uniform_field():
     # uniform x and uniform dc: H(x dc)/(Hs x) = dc exactly
     F = filt.Filter(6, 5, 4, 1.5)
     np.testing.assert_allclose(F.sensitivity(np.full(120, 0.5), np.full(120, -2.0)), -2.0, rtol=1e-14)
+
+
+def test_sampled_rows_equal_matrix_rows():
+    H = filt.filter_matrix(8, 6, 5, 2.5)
+    for e, (idx, w) in zip([0, 17, 120, 239], filt.filter_rows(8, 6, 5, 2.5, [0, 17, 120, 239])):
+        row = H.getrow(e).toarray().ravel()
+        ref = np.zeros(240)
+        ref[idx] = w
+        np.testing.assert_allclose(row, ref, atol=0)
