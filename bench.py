@@ -1,0 +1,179 @@
+#!/usr/bin/env python3
+"""Benchmark of the SIMP hot path on one MI355X.
+
+Workload: the 160x80x80 cantilever (1,024,000 hexahedra, 3,168,963 DOF; face x=0
+clamped, unit downward load spread over the bottom edge of the free end),
+volfrac 0.2, rmin 3.0, p = 3, density filter, multigrid-preconditioned CG to a
+relative residual of 1e-8 with warm starts.  A step is one full SIMP iteration
+(filter, moduli and multigrid set-up, solve, sensitivities, filter adjoint, OC
+update).  Prints one JSON line.
+
+python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "ms/SIMP iter @3.1M DOF; PCG iters+time to 1e-8 rel res, learned vs plain MG"
+FP64_VECTOR_PEAK_TFLOPS = 78.6   # MI355X: 256 CU x 2.4 GHz x 128 FP64 flop/clk
+KU_FLOP_PER_ELEMENT = 1152       # dense 24x24 KE times the element vector, 2 flop per MAC
+KU_SOURCE = os.path.join(ROOT, "paper_2504_05604_amd", "csrc", "kernels_ku.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "ku_node_fp64_160x80x80_traffic.json")
+
+
+def ku_traffic_bytes():
+    """HBM bytes per K.u launch from the committed counter runs, if they were
+    taken on the current kernel source (else None)."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    with open(TRAFFIC_FILE) as fh:
+        rec = json.load(fh)
+    sha = hashlib.sha256(open(KU_SOURCE, "rb").read()).hexdigest()
+    if rec.get("kernel_source_sha256") != sha:
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def cpu_baseline(p, ku_equiv_per_iter, budget_s):
+    """Oracle (NumPy FP64, element-by-element) timed on the host: one K.u and one
+    sensitivity evaluation at the full grid, scaled to a SIMP iteration by the
+    number of fine-grid K.u applications the GPU iteration performs."""
+    import numpy as np
+    from oracle import fem
+    from oracle.ke import element_stiffness
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    except Exception:  # pragma: no cover
+        threads = os.cpu_count() or 1
+    KE = element_stiffness(p.nu)
+    edof = fem.element_dofs(p.nelx, p.nely, p.nelz)
+    rng = np.random.default_rng(0)
+    E = fem.simp_modulus(rng.uniform(0, 1, p.nel), p.E0, p.Emin, p.penal)
+    u = rng.standard_normal(p.ndof)
+    t0 = time.perf_counter()
+    reps = 0
+    while True:
+        fem.apply_K(E, KE, edof, u)
+        reps += 1
+        if time.perf_counter() - t0 > min(budget_s, 10.0) or reps >= 3:
+            break
+    t_ku = (time.perf_counter() - t0) / reps
+    t0 = time.perf_counter()
+    fem.element_energy(KE, edof, u)
+    t_sens = time.perf_counter() - t0
+    ms_iter = 1e3 * (t_ku * ku_equiv_per_iter + t_sens)
+    return {
+        "value": round(ms_iter, 1), "unit": "ms/SIMP iteration", "cores": int(threads),
+        "kind": "oracle",
+        "sample": (f"oracle element-by-element K.u at 160x80x80 ({t_ku:.2f} s/call, {reps} calls) "
+                   f"and one sensitivity pass ({t_sens:.2f} s), scaled by the {ku_equiv_per_iter:.1f} "
+                   f"fine-grid K.u-equivalents of the GPU's SIMP iteration"),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=28)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--precond", choices=["mg", "jacobi"], default="mg")
+    ap.add_argument("--cheb-degree", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--ku-reps", type=int, default=100)
+    ap.add_argument("--coarse-dof", type=int, default=140, help="coarsest multigrid level size cap")
+    ap.add_argument("--check-every", type=int, default=4)
+    ap.add_argument("--no-graphs", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build runs on exactly one GPU; --gpus above 1 is not supported "
+              "(the multi-GPU decomposition is described in DESIGN.md, not implemented).",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2504_05604_amd as topo
+    import synth
+
+    p = synth.config_large()
+    opts = topo.default_opts(rtol=1e-8, max_iters=2000, cheb_degree=args.cheb_degree,
+                             mg_max_coarse_dof=args.coarse_dof, check_every=args.check_every,
+                             use_graphs=0 if args.no_graphs else 1,
+                             precond=topo.PRECOND_MG if args.precond == "mg" else topo.PRECOND_JACOBI)
+    ctx = topo.Context(p, opts)
+    x = torch.from_numpy(p.initial_design()).to("cuda")
+    print(f"# setup done: {p.nel} elements, {p.ndof} dof, {ctx.mg_levels} MG levels", file=sys.stderr, flush=True)
+    if args.warmup:
+        ctx.iterate(x, args.warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stats = ctx.iterate(x, args.steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_per_step = 1e3 * (t1 - t0) / args.steps
+    print(f"# timed {args.steps} SIMP iterations: {ms_per_step:.2f} ms each", file=sys.stderr, flush=True)
+
+    pcg = np.array([s["pcg_iters"] for s in stats], dtype=float)
+    solve_ms = np.array([s["ms_solve"] for s in stats])
+    deg = args.cheb_degree
+    # fine-grid K.u applications per CG iteration: the product itself plus 2*deg in
+    # the V-cycle, coarser levels adding 1/8 per level
+    ku_per_cg = 1.0 + (2.0 * deg * 8.0 / 7.0 if args.precond == "mg" else 0.0)
+    ku_equiv = float(pcg.mean() * ku_per_cg + 1.0)
+
+    ku_ms = ctx.time_operator(args.ku_reps)
+    flops = KU_FLOP_PER_ELEMENT * p.nel
+    achieved = flops / (ku_ms * 1e-3) / 1e12
+    roofline = {
+        "kernel": "ku_node_kernel (finest-level K.u, FP64)",
+        "bound": "alu", "achieved": round(achieved, 2), "peak": FP64_VECTOR_PEAK_TFLOPS,
+        "unit": "TFLOP/s", "frac": round(achieved / FP64_VECTOR_PEAK_TFLOPS, 4),
+        "traffic": ku_traffic_bytes(), "ms_per_launch": round(ku_ms, 5),
+    }
+
+    out = {
+        "metric": METRIC,
+        "value": round(ms_per_step, 3),
+        "unit": "ms/SIMP iteration",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": "cantilever-160x80x80 (3,168,963 DOF), volfrac 0.2, rmin 3.0, density filter",
+            "nel": p.nel, "ndof": p.ndof, "precond": args.precond, "mg_levels": ctx.mg_levels,
+            "cheb_degree": deg, "rtol": 1e-8, "warm_start": True, "coarse_dof_cap": args.coarse_dof,
+            "check_every": args.check_every, "graphs": not args.no_graphs,
+            "pcg_iters_mean": round(float(pcg.mean()), 2), "pcg_iters_max": int(pcg.max()),
+            "solve_ms_mean": round(float(solve_ms.mean()), 3),
+            "dof_pcg_iters_per_s": round(float(p.ndof * pcg.sum() / (solve_ms.sum() * 1e-3)), 1),
+            "phase_ms_mean": {k: round(float(np.mean([s[k] for s in stats])), 3)
+                              for k in ("ms_filter", "ms_solve", "ms_sens", "ms_oc")},
+            "compliance_last": stats[-1]["c"],
+            "learned_vs_mg": None,
+        },
+        "roofline": roofline,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(p, ku_equiv, args.cpu_budget)
+    ctx.close()
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -95,7 +95,9 @@ typedef struct {
   int32_t max_iters;          /* CG iteration cap per solve                           */
   int32_t warm_start;         /* topo_iterate: start each solve from the last u        */
   double oc_tol;              /* relative width of the final multiplier bracket        */
-  int32_t check_every;        /* host convergence check every k CG iterations          */
+  int32_t check_every;        /* CG iterations per host convergence check (the device
+                                 stops iterating at convergence within a chunk)         */
+  int32_t use_graphs;         /* replay chunks of CG iterations from a captured HIP graph */
 } topo_opts;
 
 typedef struct {
@@ -116,9 +118,9 @@ typedef struct {
   double ms_total, ms_filter, ms_solve, ms_sens, ms_oc; /* phase times (hipEvents) */
 } topo_iter_stats;
 
-/* Fills *opts with defaults: FP64, MG, automatic depth (coarsest <= 400 dofs),
+/* Fills *opts with defaults: FP64, MG, automatic depth (coarsest <= 140 dofs),
  * Chebyshev degree 2, rtol 1e-8, max_iters 1000, warm start, oc_tol 1e-12,
- * check_every 1. */
+ * check_every 4, use_graphs 1. */
 void topo_default_opts(topo_opts *opts);
 
 /* Validates the problem, copies its arrays to the device, builds the element
@@ -192,6 +194,13 @@ topo_status topo_oc_update(topo_ctx *ctx, const double *d_x, const double *d_dc,
  * displacement is kept in the context for the next call's warm start and can be
  * read with topo_get_displacement. */
 topo_status topo_iterate(topo_ctx *ctx, double *d_x, int32_t n_iter, topo_iter_stats *h_stats);
+
+/* Measurement helper: times `reps` back-to-back launches of the finest-level
+ * matrix-free operator kernel (the conjugate-gradient product q = K p, with the
+ * context's current moduli and displacement as operand) between two hipEvents
+ * on the context's stream; *h_ms_per_launch = elapsed / reps.  Call after
+ * topo_iterate or topo_solve.  Writes only the context's scratch vector. */
+topo_status topo_time_operator(topo_ctx *ctx, int32_t reps, double *h_ms_per_launch);
 
 /* Copies the context's current displacement (ndof) to d_u / physical density
  * (nel) to d_xphys; either may be NULL. */

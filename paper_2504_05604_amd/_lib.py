@@ -25,7 +25,7 @@ PRECOND_JACOBI, PRECOND_MG = 0, 1
 EXPORTED = [
     "topo_default_opts", "topo_setup", "topo_destroy", "topo_last_error", "topo_sizes",
     "topo_apply_K", "topo_apply_precond", "topo_solve", "topo_sensitivity", "topo_filter", "topo_oc_update",
-    "topo_iterate", "topo_get_state",
+    "topo_iterate", "topo_get_state", "topo_time_operator",
 ]
 
 
@@ -56,7 +56,7 @@ class Opts_C(C.Structure):
         ("precision", C.c_int32), ("precond", C.c_int32), ("mg_levels", C.c_int32),
         ("mg_max_coarse_dof", C.c_int32), ("cheb_degree", C.c_int32), ("rtol", C.c_double),
         ("max_iters", C.c_int32), ("warm_start", C.c_int32), ("oc_tol", C.c_double),
-        ("check_every", C.c_int32),
+        ("check_every", C.c_int32), ("use_graphs", C.c_int32),
     ]
 
 
@@ -84,6 +84,10 @@ def load(path: str = LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise ImportError(f"{path} is missing: build it with `python -m paper_2504_05604_amd.build`")
+    # torch brings its own HIP runtime (same soname as the system one); importing
+    # it first makes the dynamic loader resolve libtopo's runtime to that same
+    # copy, so the process has exactly one HIP runtime and one device context.
+    import torch  # noqa: F401
     lib = C.CDLL(path)
     vp, dp = C.c_void_p, C.c_void_p
     lib.topo_default_opts.argtypes = [C.POINTER(Opts_C)]
@@ -101,6 +105,7 @@ def load(path: str = LIB_PATH):
     lib.topo_oc_update.argtypes = [vp, dp, dp, dp, dp, C.POINTER(C.c_double), C.POINTER(C.c_double)]
     lib.topo_iterate.argtypes = [vp, dp, C.c_int32, C.POINTER(IterStats_C)]
     lib.topo_get_state.argtypes = [vp, dp, dp]
+    lib.topo_time_operator.argtypes = [vp, C.c_int32, C.POINTER(C.c_double)]
     for name in EXPORTED:
         if name not in ("topo_default_opts", "topo_destroy", "topo_last_error"):
             getattr(lib, name).restype = C.c_int
@@ -150,6 +155,11 @@ class Context:
     def __init__(self, problem, opts: Optional[Opts_C] = None, stream=None, filter_mode=None):
         lib = load()
         self._lib = lib
+        import torch
+        # the library shares the process's HIP runtime with torch; let torch create
+        # the device context first so both use the same one
+        torch.cuda.init()
+        self.device = torch.cuda.current_device()
         p = problem
         self.nel = int(p.nelx * p.nely * p.nelz)
         self.ndof = int(3 * (p.nelx + 1) * (p.nely + 1) * (p.nelz + 1))
@@ -253,6 +263,12 @@ class Context:
                         "ms_total": s.ms_total, "ms_filter": s.ms_filter, "ms_solve": s.ms_solve,
                         "ms_sens": s.ms_sens, "ms_oc": s.ms_oc})
         return out
+
+    def time_operator(self, reps: int = 50) -> float:
+        """Average ms per launch of the finest-level K.u kernel (hipEvents)."""
+        ms = C.c_double()
+        _check(self._lib.topo_time_operator(self._h, reps, C.byref(ms)))
+        return ms.value
 
     def get_state(self, u=None, xphys=None):
         import torch

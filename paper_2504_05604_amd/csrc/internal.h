@@ -4,9 +4,6 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
-#include <string>
-#include <vector>
-
 #include "../../include/topo.h"
 
 namespace topo {
@@ -32,13 +29,12 @@ __host__ __device__ constexpr int corner_of(int x, int y, int z) {
 }
 
 // ---------------------------------------------------------------------------
-// deterministic reductions: per-block partials, the last block to finish sums
-// them in a fixed order and writes the result (no floating-point atomics).
+// deterministic reductions: each reducing kernel stores one partial per block,
+// a one-block finalize kernel sums them in block order.
 constexpr int kMaxRed = 4;  // values reduced together in one kernel
 
 struct Reducer {
-  double *partials;    // [max_blocks * kMaxRed]
-  unsigned *counter;   // one counter per reduction slot in use
+  double *partials;  // [max_blocks * kMaxRed]
   int max_blocks;
 };
 
@@ -57,19 +53,25 @@ void set_error(const char *fmt, ...);
 
 // ---------------------------------------------------------------------------
 // device scalar block of the CG loop and the OC search
+constexpr int kOcCand = 63;  // candidate multipliers evaluated per pass
 struct Scalars {
   double rr, rz, rz_new, pq, ff, alpha, beta, comp;  // CG / compliance
   double red[8];                                     // scratch results of reductions
   // OC multiplier search
   double l1, l2, target, vconst, change, volume, lambda;
   int oc_done, oc_pass;
+  int cg_done, cg_iters;  // device-side CG convergence state
   double oc_lam[64];
-  double oc_vol[64];
 };
-constexpr int kOcCand = 63;  // candidate multipliers evaluated per pass
+
+struct Kappa;  // ke_code.h
 
 // ---------------------------------------------------------------------------
 // kernel launchers (kernels_*.hip)
+
+// sums nparts partials (slot-major, k-th value at [slot*kMaxRed + k]) into out[0..n)
+hipError_t launch_finalize(hipStream_t s, const Reducer &red, int nparts, int n, bool is_max,
+                           double *out, const int *skip = nullptr);
 
 // E_e = Emin + xphys^p (E0 - Emin), times scale
 hipError_t launch_simp_modulus(hipStream_t s, int64_t nel, const double *xphys, double E0,
@@ -77,22 +79,21 @@ hipError_t launch_simp_modulus(hipStream_t s, int64_t nel, const double *xphys, 
 // E_c = 2 * mean of the 8 children (missing children count as 0)
 hipError_t launch_coarsen_moduli(hipStream_t s, Grid gf, Grid gc, const double *Ef, double *Ec);
 // diag_i = sum_{e ni i} E_e KE_{li,li}; 1 on fixed dofs
-hipError_t launch_diag(hipStream_t s, Grid g, const double *E, const double *KEdiag,
+hipError_t launch_diag(hipStream_t s, Grid g, const double *E, const Kappa &kap,
                        const uint8_t *fixed, double *diag);
 
-// K.u variants (node-centred, matrix-free, identity rows on fixed dofs); the
-// input vector must be zero on fixed dofs.
+// K.u variants (matrix-free, identity rows on fixed dofs); the input vector must
+// be zero on fixed dofs.
 enum KuEpi {
   KU_STORE = 0,      // y = Au
-  KU_STORE_DOT = 1,  // y = Au, red0 = u.y
-  KU_RESID = 2,      // y = b - Au, red0 = y.y
+  KU_STORE_DOT = 1,  // y = Au, out = u.y
+  KU_RESID = 2,      // y = b - Au, out = y.y
   KU_CHEB = 3,       // res -= Au; dout = c1 u + c2 res/diag; x += dout
   KU_RESUPD = 4,     // res -= Au
 };
 struct KuArgs {
   Grid g;
   const double *E;
-  const double *KE;       // 576 entries
   const double *u;        // input (stencil operand)
   double *y;              // STORE, STORE_DOT, RESID output
   const double *b;        // RESID rhs
@@ -100,8 +101,11 @@ struct KuArgs {
   double *res, *x, *dout; // CHEB / RESUPD
   const double *diag;
   double c1, c2;
+  const int *skip;        // device flag: return at once when non-zero (may be NULL)
 };
-hipError_t launch_ku(hipStream_t s, KuEpi epi, const KuArgs &a, const Reducer &red, double *out0);
+// out (device scalar) receives the reduction of STORE_DOT / RESID
+hipError_t launch_ku(hipStream_t s, KuEpi epi, const KuArgs &a, const Kappa &kap, const Reducer &red,
+                     double *out);
 
 // vector kernels
 hipError_t launch_zero_fixed(hipStream_t s, int64_t nnodes, const uint8_t *fixed, double *v);
@@ -111,37 +115,44 @@ hipError_t launch_copy_masked(hipStream_t s, int64_t nnodes, const uint8_t *fixe
 hipError_t launch_copy_fixed(hipStream_t s, int64_t nnodes, const uint8_t *fixed, const double *in,
                              double *out);
 hipError_t launch_dot(hipStream_t s, int64_t n, const double *a, const double *b, const Reducer &red,
-                      double *out);
-// x += alpha p; r -= alpha q; red = r.r        (alpha = sc->rz / sc->pq)
+                      double *out, const int *skip = nullptr);
+// x += alpha p; r -= alpha q; sc->rr = r.r        (alpha = sc->rz / sc->pq)
 hipError_t launch_cg_update_xr(hipStream_t s, int64_t n, Scalars *sc, double *x, double *r,
-                               const double *p, const double *q, const Reducer &red);
-// z = r / diag; red = r.z
+                               const double *p, const double *q, const Reducer &red,
+                               const int *skip = nullptr);
+// device-side convergence test (cg_iters += 1; cg_done once rr <= rtol2 ff or at the cap)
+hipError_t launch_cg_check(hipStream_t s, Scalars *sc, double rtol2, int max_iters);
+// cg_iters = 0; cg_done = (rr <= rtol2 ff)
+hipError_t launch_cg_start(hipStream_t s, Scalars *sc, double rtol2);
+// z = r / diag; out = r.z
 hipError_t launch_jacobi(hipStream_t s, int64_t n, const double *r, const double *diag, double *z,
-                         const Reducer &red, double *out);
+                         const Reducer &red, double *out, const int *skip = nullptr);
 // p = z + beta p, beta = rz_new / rz (0 if first); rz = rz_new
 hipError_t launch_cg_update_p(hipStream_t s, int64_t n, Scalars *sc, const double *z, double *p,
-                              int first);
+                              int first, const int *skip = nullptr);
 // Chebyshev first step from x = 0: d = r/(diag theta); x = d; res = r
 hipError_t launch_cheb_first(hipStream_t s, int64_t n, const double *r, const double *diag,
-                             double inv_theta, double *d, double *x, double *res);
+                             double inv_theta, double *d, double *x, double *res,
+                             const int *skip = nullptr);
 // d = res/(diag theta); x += d
 hipError_t launch_cheb_start(hipStream_t s, int64_t n, const double *res, const double *diag,
-                             double inv_theta, double *d, double *x);
+                             double inv_theta, double *d, double *x, const int *skip = nullptr);
 
 // multigrid transfers
 hipError_t launch_restrict(hipStream_t s, Grid gf, Grid gc, const double *rf, const uint8_t *fixc,
-                           double *rc);
+                           double *rc, const int *skip = nullptr);
 hipError_t launch_prolong_add(hipStream_t s, Grid gf, Grid gc, const double *ec,
-                              const uint8_t *fixf, double *xf);
+                              const uint8_t *fixf, double *xf, const int *skip = nullptr);
 hipError_t launch_coarse_fixed(hipStream_t s, Grid gf, Grid gc, const uint8_t *fixf, uint8_t *fixc);
 // dense coarsest-level operator, inverse and application
-hipError_t launch_dense_assemble(hipStream_t s, Grid g, const double *E, const double *KE,
+hipError_t launch_dense_assemble(hipStream_t s, Grid g, const double *E, const Kappa &kap,
                                  const uint8_t *fixed, double *A);
 hipError_t launch_dense_invert(hipStream_t s, int n, double *A);
-hipError_t launch_dense_matvec(hipStream_t s, int n, const double *A, const double *x, double *y);
+hipError_t launch_dense_matvec(hipStream_t s, int n, const double *A, const double *x, double *y,
+                               const int *skip = nullptr);
 
 // sensitivities: ce = u_e^T KE u_e, dc = -p xphys^(p-1) (E0-Emin) ce
-hipError_t launch_sensitivity(hipStream_t s, Grid g, const double *KE, const double *u,
+hipError_t launch_sensitivity(hipStream_t s, Grid g, const Kappa &kap, const double *u,
                               const double *xphys, double E0, double Emin, double penal, double *ce,
                               double *dc);
 

@@ -3,6 +3,7 @@
 // coarse element past the fine domain), coarse Dirichlet flags, and the dense
 // coarsest-level operator with its explicit inverse.
 #include "internal.h"
+#include "ke_code.h"
 
 namespace topo {
 
@@ -14,7 +15,9 @@ inline unsigned nblocks(int64_t n) { return (unsigned)((n + kBs - 1) / kBs); }
 // r_c = P^T r_f: each coarse node gathers the fine nodes within one fine spacing
 // of its position 2*(I,J,K), weight prod over axes (1 at distance 0, 1/2 at 1).
 __global__ void restrict_kernel(Grid gf, Grid gc, const double *__restrict__ rf,
-                                const uint8_t *__restrict__ fixc, double *__restrict__ rc) {
+                                const uint8_t *__restrict__ fixc, double *__restrict__ rc,
+                                const int *skip) {
+  if (skip && *skip) return;
   const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (m >= gc.nnodes()) return;
   const int I = (int)(m % gc.NX());
@@ -48,14 +51,16 @@ __global__ void restrict_kernel(Grid gf, Grid gc, const double *__restrict__ rf,
 }
 
 hipError_t launch_restrict(hipStream_t s, Grid gf, Grid gc, const double *rf, const uint8_t *fixc,
-                           double *rc) {
-  restrict_kernel<<<nblocks(gc.nnodes()), kBs, 0, s>>>(gf, gc, rf, fixc, rc);
+                           double *rc, const int *skip) {
+  restrict_kernel<<<nblocks(gc.nnodes()), kBs, 0, s>>>(gf, gc, rf, fixc, rc, skip);
   return hipGetLastError();
 }
 
 // x_f += P e_c on free fine dofs (trilinear interpolation of the coarse values).
 __global__ void prolong_add_kernel(Grid gf, Grid gc, const double *__restrict__ ec,
-                                   const uint8_t *__restrict__ fixf, double *__restrict__ xf) {
+                                   const uint8_t *__restrict__ fixf, double *__restrict__ xf,
+                                   const int *skip) {
+  if (skip && *skip) return;
   const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (n >= gf.nnodes()) return;
   const int i = (int)(n % gf.NX());
@@ -81,8 +86,8 @@ __global__ void prolong_add_kernel(Grid gf, Grid gc, const double *__restrict__ 
 }
 
 hipError_t launch_prolong_add(hipStream_t s, Grid gf, Grid gc, const double *ec,
-                              const uint8_t *fixf, double *xf) {
-  prolong_add_kernel<<<nblocks(gf.nnodes()), kBs, 0, s>>>(gf, gc, ec, fixf, xf);
+                              const uint8_t *fixf, double *xf, const int *skip) {
+  prolong_add_kernel<<<nblocks(gf.nnodes()), kBs, 0, s>>>(gf, gc, ec, fixf, xf, skip);
   return hipGetLastError();
 }
 
@@ -106,8 +111,8 @@ hipError_t launch_coarse_fixed(hipStream_t s, Grid gf, Grid gc, const uint8_t *f
 // Dense n x n operator of a (small) level, row-major; thread per row: the row of
 // dof (node i, component c) collects E_e KE[3 li + c][3 lb + d] over the elements
 // around i.  Fixed rows/columns become identity rows/columns.
-__global__ void dense_assemble_kernel(Grid g, const double *E, const double *KE,
-                                      const uint8_t *fixed, double *A) {
+__global__ void dense_assemble_kernel(Grid g, const double *E, Kappa kap, const uint8_t *fixed,
+                                      double *A) {
   const int64_t n = g.ndof();
   const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (row >= n) return;
@@ -122,37 +127,79 @@ __global__ void dense_assemble_kernel(Grid g, const double *E, const double *KE,
   const int i = (int)(node % g.NX());
   const int j = (int)((node / g.NX()) % g.NY());
   const int k = (int)(node / ((int64_t)g.NX() * g.NY()));
+#pragma unroll
   for (int e = 0; e < 8; ++e) {
     const int ex = e & 1, ey = (e >> 1) & 1, ez = e >> 2;
     const int ei = i - 1 + ex, ej = j - 1 + ey, ek = k - 1 + ez;
     if (ei < 0 || ei >= g.nx || ej < 0 || ej >= g.ny || ek < 0 || ek >= g.nz) continue;
     const double Ee = E[ei + (int64_t)g.nx * (ej + (int64_t)g.ny * ek)];
     const int li = corner_of(1 - ex, 1 - ey, 1 - ez);
+#pragma unroll
     for (int b = 0; b < 8; ++b) {
       const int64_t nb = (ei + cx(b)) + (int64_t)g.NX() * ((ej + cy(b)) + (int64_t)g.NY() * (ek + cz(b)));
       const uint8_t fb = fixed[nb];
+#pragma unroll
       for (int d = 0; d < 3; ++d) {
         if ((fb >> d) & 1) continue;
-        Ar[3 * nb + d] += Ee * KE[(3 * li + comp) * 24 + 3 * b + d];
+        const double kv = comp == 0 ? TOPO_KE(kap, 3 * li + 0, 3 * b + d)
+                          : comp == 1 ? TOPO_KE(kap, 3 * li + 1, 3 * b + d)
+                                      : TOPO_KE(kap, 3 * li + 2, 3 * b + d);
+        Ar[3 * nb + d] += Ee * kv;
       }
     }
   }
 }
 
-hipError_t launch_dense_assemble(hipStream_t s, Grid g, const double *E, const double *KE,
+hipError_t launch_dense_assemble(hipStream_t s, Grid g, const double *E, const Kappa &kap,
                                  const uint8_t *fixed, double *A) {
-  dense_assemble_kernel<<<nblocks(g.ndof()), kBs, 0, s>>>(g, E, KE, fixed, A);
+  dense_assemble_kernel<<<nblocks(g.ndof()), kBs, 0, s>>>(g, E, kap, fixed, A);
   return hipGetLastError();
 }
 
 // In-place Gauss-Jordan inversion of an SPD matrix (no pivoting is needed for
-// SPD matrices), one workgroup; pivot row and column are staged in LDS.
+// SPD matrices) by one workgroup.  Small matrices live in LDS for the whole
+// elimination; larger ones stay in global memory and each thread updates its
+// entries in register batches so the loads of a batch are in flight together.
 constexpr int kInvThreads = 1024;
 constexpr int kMaxDense = 2048;
+constexpr int kLdsDense = 140;  // n*n doubles + pivot row/column fit in 160 KB of LDS
+constexpr int kInvBatch = 8;
+
+__device__ __forceinline__ double gj_update(double a, int i, int j, int k, double inv,
+                                            const double *col, const double *rowk) {
+  if (i == k) return (j == k) ? inv : rowk[j] * inv;
+  if (j == k) return -col[i] * inv;
+  return a - col[i] * rowk[j] * inv;
+}
+
+__global__ __launch_bounds__(kInvThreads) void dense_invert_lds_kernel(int n, double *A) {
+  extern __shared__ double lds[];
+  double *M = lds;                     // n*n
+  double *col = lds + n * n;           // n
+  double *rowk = col + n;              // n
+  const int nn = n * n;
+  for (int t = threadIdx.x; t < nn; t += blockDim.x) M[t] = A[t];
+  __syncthreads();
+  for (int k = 0; k < n; ++k) {
+    for (int t = threadIdx.x; t < n; t += blockDim.x) {
+      col[t] = M[t * n + k];
+      rowk[t] = M[k * n + t];
+    }
+    __syncthreads();
+    const double inv = 1.0 / col[k];
+    for (int idx = threadIdx.x; idx < nn; idx += blockDim.x) {
+      const int i = idx / n, j = idx - (idx / n) * n;
+      M[idx] = gj_update(M[idx], i, j, k, inv, col, rowk);
+    }
+    __syncthreads();
+  }
+  for (int t = threadIdx.x; t < nn; t += blockDim.x) A[t] = M[t];
+}
 
 __global__ __launch_bounds__(kInvThreads) void dense_invert_kernel(int n, double *A) {
   __shared__ double col[kMaxDense];
   __shared__ double rowk[kMaxDense];
+  const int64_t nn = (int64_t)n * n;
   for (int k = 0; k < n; ++k) {
     for (int t = threadIdx.x; t < n; t += blockDim.x) {
       col[t] = A[(int64_t)t * n + k];
@@ -160,17 +207,21 @@ __global__ __launch_bounds__(kInvThreads) void dense_invert_kernel(int n, double
     }
     __syncthreads();
     const double inv = 1.0 / col[k];
-    const int64_t nn = (int64_t)n * n;
-    for (int64_t idx = threadIdx.x; idx < nn; idx += blockDim.x) {
-      const int i = (int)(idx / n), j = (int)(idx % n);
-      double v;
-      if (i == k)
-        v = (j == k) ? inv : rowk[j] * inv;
-      else if (j == k)
-        v = -col[i] * inv;
-      else
-        v = A[idx] - col[i] * rowk[j] * inv;
-      A[idx] = v;
+    for (int64_t base = threadIdx.x; base < nn; base += (int64_t)blockDim.x * kInvBatch) {
+      double v[kInvBatch];
+#pragma unroll
+      for (int b = 0; b < kInvBatch; ++b) {
+        const int64_t idx = base + (int64_t)b * blockDim.x;
+        v[b] = idx < nn ? A[idx] : 0.0;
+      }
+#pragma unroll
+      for (int b = 0; b < kInvBatch; ++b) {
+        const int64_t idx = base + (int64_t)b * blockDim.x;
+        if (idx < nn) {
+          const int i = (int)(idx / n), j = (int)(idx % n);
+          A[idx] = gj_update(v[b], i, j, k, inv, col, rowk);
+        }
+      }
     }
     __syncthreads();
   }
@@ -178,12 +229,21 @@ __global__ __launch_bounds__(kInvThreads) void dense_invert_kernel(int n, double
 
 hipError_t launch_dense_invert(hipStream_t s, int n, double *A) {
   if (n > kMaxDense) return hipErrorInvalidValue;
-  dense_invert_kernel<<<1, kInvThreads, 0, s>>>(n, A);
+  if (n <= kLdsDense) {
+    const size_t shm = ((size_t)n * n + 2 * (size_t)n) * sizeof(double);
+    (void)hipFuncSetAttribute((const void *)dense_invert_lds_kernel,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+    dense_invert_lds_kernel<<<1, kInvThreads, shm, s>>>(n, A);
+  } else {
+    dense_invert_kernel<<<1, kInvThreads, 0, s>>>(n, A);
+  }
   return hipGetLastError();
 }
 
 // y = A x, one wave per row
-__global__ void dense_matvec_kernel(int n, const double *A, const double *x, double *y) {
+__global__ void dense_matvec_kernel(int n, const double *A, const double *x, double *y,
+                                    const int *skip) {
+  if (skip && *skip) return;
   const int lane = threadIdx.x & 63;
   const int row = blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64;
   if (row >= n) return;
@@ -194,9 +254,10 @@ __global__ void dense_matvec_kernel(int n, const double *A, const double *x, dou
   if (lane == 0) y[row] = t;
 }
 
-hipError_t launch_dense_matvec(hipStream_t s, int n, const double *A, const double *x, double *y) {
+hipError_t launch_dense_matvec(hipStream_t s, int n, const double *A, const double *x, double *y,
+                               const int *skip) {
   const int rows_per_block = kBs / 64;
-  dense_matvec_kernel<<<(unsigned)((n + rows_per_block - 1) / rows_per_block), kBs, 0, s>>>(n, A, x, y);
+  dense_matvec_kernel<<<(unsigned)((n + rows_per_block - 1) / rows_per_block), kBs, 0, s>>>(n, A, x, y, skip);
   return hipGetLastError();
 }
 

@@ -1,0 +1,209 @@
+// OC design update with move limits (Optimality Criteria section) and a
+// device-side multisection search for the volume multiplier.
+//
+// For design element j, a_j = x_j (max(0,-dc_j)/dv_j)^eta, so the candidate at
+// multiplier lambda is clamp(a_j lambda^-eta, max(0, x_j - move), min(1, x_j + move)).
+// The volume V(lambda) = sum_j dv_j x_new_j is non-increasing in lambda.  Each
+// pass evaluates V at kOcCand multipliers inside the current bracket (geometric
+// spacing while the bracket spans more than a factor 2, linear after) and keeps
+// the sub-interval in which V crosses the target; the bracket shrinks by a
+// factor 64 per pass instead of 2 per bisection step, and the host never waits.
+#include "internal.h"
+#include "reduce_dev.h"
+
+namespace topo {
+
+namespace {
+constexpr int kBs = 256;
+constexpr int kOcStride = 64;  // partial slots per block in a pass
+inline unsigned nblocks(int64_t n) { return (unsigned)((n + kBs - 1) / kBs); }
+}  // namespace
+
+__device__ __forceinline__ double oc_value(double x, double a, double lam_pow, double move) {
+  const double lo = fmax(0.0, x - move), hi = fmin(1.0, x + move);
+  return fmin(hi, fmax(lo, a * lam_pow));
+}
+
+__device__ void oc_make_candidates(Scalars *sc) {
+  const double l1 = sc->l1, l2 = sc->l2;
+  const bool geo = l1 > 0.0 && l2 > 2.0 * l1;
+  for (int c = 0; c < kOcCand; ++c) {
+    const double t = (double)(c + 1) / (double)(kOcCand + 1);
+    sc->oc_lam[c] = geo ? l1 * pow(l2 / l1, t) : l1 + (l2 - l1) * t;
+  }
+}
+
+__global__ void oc_prepare_kernel(int64_t nel, const double *__restrict__ x,
+                                  const double *__restrict__ dc, const double *__restrict__ dv,
+                                  const int8_t *__restrict__ mask, double eta,
+                                  double *__restrict__ a, double *partials) {
+  double cst = 0.0;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nel;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    if (mask[e] == 0) {
+      const double B = fmax(0.0, -dc[e]) / dv[e];
+      a[e] = x[e] * pow(B, eta);
+    } else {
+      a[e] = 0.0;
+      cst = fma(dv[e], x[e], cst);
+    }
+  }
+  double v[1] = {cst};
+  block_reduce_store<1, false>(v, partials, blockIdx.x);
+}
+
+__global__ void oc_init_kernel(Scalars *sc, double target) {
+  sc->target = target;
+  sc->l1 = 1e-40;  // the multiplier is positive; this stands for the lower end 0
+  sc->l2 = 1e40;
+  sc->oc_done = 0;
+  sc->oc_pass = 0;
+  oc_make_candidates(sc);
+}
+
+// Partial volumes of one block for every candidate multiplier.
+__global__ __launch_bounds__(kBs) void oc_pass_kernel(int64_t nel, const double *__restrict__ x,
+                                                      const double *__restrict__ a,
+                                                      const double *__restrict__ dv,
+                                                      const int8_t *__restrict__ mask, double move,
+                                                      double eta, const Scalars *sc,
+                                                      double *partials) {
+  if (sc->oc_done) return;
+  __shared__ double lampow[kOcCand];
+  __shared__ double sh[kOcCand][kBs / 64];
+  for (int c = threadIdx.x; c < kOcCand; c += blockDim.x) lampow[c] = pow(sc->oc_lam[c], -eta);
+  __syncthreads();
+  double part[kOcCand];
+#pragma unroll
+  for (int c = 0; c < kOcCand; ++c) part[c] = 0.0;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nel;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    if (mask[e] != 0) continue;
+    const double xe = x[e], ae = a[e], we = dv[e];
+#pragma unroll
+    for (int c = 0; c < kOcCand; ++c) part[c] = fma(we, oc_value(xe, ae, lampow[c], move), part[c]);
+  }
+  const int lane = threadIdx.x & 63, wid = threadIdx.x / 64;
+#pragma unroll
+  for (int c = 0; c < kOcCand; ++c) {
+    const double t = wave_reduce<false>(part[c]);
+    if (lane == 0) sh[c][wid] = t;
+  }
+  __syncthreads();
+  for (int c = threadIdx.x; c < kOcCand; c += blockDim.x) {
+    double t = 0.0;
+    for (int w = 0; w < (int)(blockDim.x / 64); ++w) t += sh[c][w];
+    partials[(size_t)blockIdx.x * kOcStride + c] = t;
+  }
+}
+
+// Sums the pass partials (fixed order: 4 interleaved lanes per candidate, then
+// a fixed pairwise combine), keeps the crossing sub-interval.
+constexpr int kSelThreads = 256;
+__global__ __launch_bounds__(kSelThreads) void oc_select_kernel(int nparts, double tol, Scalars *sc,
+                                                                const double *partials) {
+  if (sc->oc_done) return;
+  __shared__ double V[kOcCand];
+  const int c = threadIdx.x >> 2, part = threadIdx.x & 3;  // 64 candidates x 4 lanes
+  double t = 0.0;
+  if (c < kOcCand) {
+    int b = part;
+    for (; b + 12 < nparts; b += 16) {
+      const double v0 = partials[(size_t)b * kOcStride + c];
+      const double v1 = partials[(size_t)(b + 4) * kOcStride + c];
+      const double v2 = partials[(size_t)(b + 8) * kOcStride + c];
+      const double v3 = partials[(size_t)(b + 12) * kOcStride + c];
+      t += (v0 + v1) + (v2 + v3);
+    }
+    for (; b < nparts; b += 4) t += partials[(size_t)b * kOcStride + c];
+  }
+  t += __shfl_down(t, 2, 4);
+  t += __shfl_down(t, 1, 4);
+  if (c < kOcCand && part == 0) V[c] = t + sc->vconst;
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  const double target = sc->target;
+  double l1 = sc->l1, l2 = sc->l2;
+  for (int c = 0; c < kOcCand; ++c) {
+    if (V[c] > target) {
+      l1 = sc->oc_lam[c];
+    } else {
+      l2 = sc->oc_lam[c];
+      break;
+    }
+  }
+  sc->l1 = l1;
+  sc->l2 = l2;
+  sc->oc_pass += 1;
+  if ((l2 - l1) / (l1 + l2) < tol || sc->oc_pass >= 64)
+    sc->oc_done = 1;
+  else
+    oc_make_candidates(sc);
+}
+
+__global__ void oc_final_kernel(int64_t nel, const double *__restrict__ x,
+                                const double *__restrict__ a, const double *__restrict__ dv,
+                                const int8_t *__restrict__ mask, double move, double eta,
+                                double *__restrict__ xnew, Scalars *sc, double *partials) {
+  const double lam = 0.5 * (sc->l1 + sc->l2);
+  const double lp = pow(lam, -eta);
+  double chg = 0.0, vol = 0.0;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nel;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const double xe = x[e];
+    const double xn = mask[e] == 0 ? oc_value(xe, a[e], lp, move) : xe;
+    xnew[e] = xn;
+    chg = fmax(chg, fabs(xn - xe));
+    vol = fma(dv[e], xn, vol);
+  }
+  double vm[1] = {chg};
+  block_reduce_store<1, true>(vm, partials, blockIdx.x);
+  double vs[1] = {vol};
+  block_reduce_store<1, false>(vs, partials + 1, blockIdx.x);
+  if (blockIdx.x == 0 && threadIdx.x == 0) sc->lambda = lam;
+}
+
+static unsigned oc_blocks(int64_t nel, int cap) {
+  unsigned nb = nblocks((nel + 3) / 4);
+  if (nb > (unsigned)cap) nb = (unsigned)cap;
+  return nb < 1u ? 1u : nb;
+}
+
+hipError_t launch_oc_prepare(hipStream_t s, int64_t nel, const double *x, const double *dc,
+                             const double *dv, const int8_t *mask, double eta, double target,
+                             double *a, Scalars *sc, const Reducer &red) {
+  const unsigned nb = oc_blocks(nel, 1024);
+  oc_prepare_kernel<<<nb, kBs, 0, s>>>(nel, x, dc, dv, mask, eta, a, red.partials);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  e = launch_finalize(s, red, (int)nb, 1, false, &sc->vconst);
+  if (e != hipSuccess) return e;
+  oc_init_kernel<<<1, 1, 0, s>>>(sc, target);
+  return hipGetLastError();
+}
+
+hipError_t launch_oc_pass(hipStream_t s, int64_t nel, const double *x, const double *a,
+                          const double *dv, const int8_t *mask, double move, double eta,
+                          double tol, Scalars *sc, const Reducer &red) {
+  const unsigned nb = oc_blocks(nel, 256);
+  oc_pass_kernel<<<nb, kBs, 0, s>>>(nel, x, a, dv, mask, move, eta, sc, red.partials);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  oc_select_kernel<<<1, kSelThreads, 0, s>>>((int)nb, tol, sc, red.partials);
+  return hipGetLastError();
+}
+
+hipError_t launch_oc_final(hipStream_t s, int64_t nel, const double *x, const double *a,
+                           const double *dv, const int8_t *mask, double move, double eta,
+                           double *xnew, Scalars *sc, const Reducer &red) {
+  const unsigned nb = oc_blocks(nel, 1024);
+  oc_final_kernel<<<nb, kBs, 0, s>>>(nel, x, a, dv, mask, move, eta, xnew, sc, red.partials);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  e = launch_finalize(s, red, (int)nb, 1, true, &sc->change);
+  if (e != hipSuccess) return e;
+  Reducer r2{red.partials + 1, red.max_blocks};
+  return launch_finalize(s, r2, (int)nb, 1, false, &sc->volume);
+}
+
+}  // namespace topo

@@ -1,5 +1,7 @@
 // Vector kernels of the conjugate-gradient loop and the Chebyshev smoother.
 // All reductions are deterministic (block partials summed in a fixed order).
+// Kernels of the CG loop take a `skip` flag (device int, may be NULL): once the
+// loop has converged every later kernel of a replayed chunk returns at once.
 #include "internal.h"
 #include "reduce_dev.h"
 
@@ -13,9 +15,12 @@ inline unsigned nblocks(int64_t n, int per_thread = 1) {
 }
 // grid-stride reductions use a bounded grid so partial buffers stay small
 inline unsigned red_blocks(int64_t n, const Reducer &red) {
-  unsigned nb = nblocks(n);
+  unsigned nb = nblocks(n, 4);
+  if (nb > 1024u) nb = 1024u;
+  if (nb < 1u) nb = 1u;
   return nb > (unsigned)red.max_blocks ? (unsigned)red.max_blocks : nb;
 }
+__device__ __forceinline__ bool skipped(const int *skip) { return skip != nullptr && *skip != 0; }
 }  // namespace
 
 __global__ void zero_fixed_kernel(int64_t nnodes, const uint8_t *fixed, double *v) {
@@ -63,23 +68,29 @@ hipError_t launch_copy_fixed(hipStream_t s, int64_t nnodes, const uint8_t *fixed
   return hipGetLastError();
 }
 
-__global__ void dot_kernel(int64_t n, const double *a, const double *b, Reducer red, double *out) {
+__global__ void dot_kernel(int64_t n, const double *a, const double *b, double *partials,
+                           const int *skip) {
+  if (skipped(skip)) return;
   double t = 0.0;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x)
     t = fma(a[i], b[i], t);
   double v[1] = {t};
-  block_reduce_finalize<1, false>(v, red, out);
+  block_reduce_store<1, false>(v, partials, blockIdx.x);
 }
 
 hipError_t launch_dot(hipStream_t s, int64_t n, const double *a, const double *b, const Reducer &red,
-                      double *out) {
-  dot_kernel<<<red_blocks(n, red), kBs, 0, s>>>(n, a, b, red, out);
-  return hipGetLastError();
+                      double *out, const int *skip) {
+  const unsigned nb = red_blocks(n, red);
+  dot_kernel<<<nb, kBs, 0, s>>>(n, a, b, red.partials, skip);
+  hipError_t e = hipGetLastError();
+  return e != hipSuccess ? e : launch_finalize(s, red, (int)nb, 1, false, out, skip);
 }
 
-__global__ void cg_update_xr_kernel(int64_t n, Scalars *sc, double *x, double *r, const double *p,
-                                    const double *q, Reducer red) {
+__global__ void cg_update_xr_kernel(int64_t n, const Scalars *sc, double *x, double *r,
+                                    const double *p, const double *q, double *partials,
+                                    const int *skip) {
+  if (skipped(skip)) return;
   const double alpha = sc->rz / sc->pq;
   double t = 0.0;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
@@ -90,17 +101,42 @@ __global__ void cg_update_xr_kernel(int64_t n, Scalars *sc, double *x, double *r
     t = fma(ri, ri, t);
   }
   double v[1] = {t};
-  block_reduce_finalize<1, false>(v, red, &sc->rr);
+  block_reduce_store<1, false>(v, partials, blockIdx.x);
 }
 
 hipError_t launch_cg_update_xr(hipStream_t s, int64_t n, Scalars *sc, double *x, double *r,
-                               const double *p, const double *q, const Reducer &red) {
-  cg_update_xr_kernel<<<red_blocks(n, red), kBs, 0, s>>>(n, sc, x, r, p, q, red);
+                               const double *p, const double *q, const Reducer &red, const int *skip) {
+  const unsigned nb = red_blocks(n, red);
+  cg_update_xr_kernel<<<nb, kBs, 0, s>>>(n, sc, x, r, p, q, red.partials, skip);
+  hipError_t e = hipGetLastError();
+  return e != hipSuccess ? e : launch_finalize(s, red, (int)nb, 1, false, &sc->rr, skip);
+}
+
+// Convergence test on the device: done once rr <= rtol^2 ff or the cap is hit.
+__global__ void cg_check_kernel(Scalars *sc, double rtol2, int max_iters) {
+  if (sc->cg_done) return;
+  sc->cg_iters += 1;
+  if (!(sc->rr > rtol2 * sc->ff) || sc->cg_iters >= max_iters) sc->cg_done = 1;
+}
+
+__global__ void cg_start_kernel(Scalars *sc, double rtol2) {
+  sc->cg_iters = 0;
+  sc->cg_done = !(sc->rr > rtol2 * sc->ff);
+}
+
+hipError_t launch_cg_check(hipStream_t s, Scalars *sc, double rtol2, int max_iters) {
+  cg_check_kernel<<<1, 1, 0, s>>>(sc, rtol2, max_iters);
   return hipGetLastError();
 }
 
-__global__ void jacobi_kernel(int64_t n, const double *r, const double *diag, double *z, Reducer red,
-                              double *out) {
+hipError_t launch_cg_start(hipStream_t s, Scalars *sc, double rtol2) {
+  cg_start_kernel<<<1, 1, 0, s>>>(sc, rtol2);
+  return hipGetLastError();
+}
+
+__global__ void jacobi_kernel(int64_t n, const double *r, const double *diag, double *z,
+                              double *partials, const int *skip) {
+  if (skipped(skip)) return;
   double t = 0.0;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x) {
@@ -109,16 +145,20 @@ __global__ void jacobi_kernel(int64_t n, const double *r, const double *diag, do
     t = fma(r[i], zi, t);
   }
   double v[1] = {t};
-  block_reduce_finalize<1, false>(v, red, out);
+  block_reduce_store<1, false>(v, partials, blockIdx.x);
 }
 
 hipError_t launch_jacobi(hipStream_t s, int64_t n, const double *r, const double *diag, double *z,
-                         const Reducer &red, double *out) {
-  jacobi_kernel<<<red_blocks(n, red), kBs, 0, s>>>(n, r, diag, z, red, out);
-  return hipGetLastError();
+                         const Reducer &red, double *out, const int *skip) {
+  const unsigned nb = red_blocks(n, red);
+  jacobi_kernel<<<nb, kBs, 0, s>>>(n, r, diag, z, red.partials, skip);
+  hipError_t e = hipGetLastError();
+  return e != hipSuccess ? e : launch_finalize(s, red, (int)nb, 1, false, out, skip);
 }
 
-__global__ void cg_update_p_kernel(int64_t n, Scalars *sc, const double *z, double *p, int first) {
+__global__ void cg_update_p_kernel(int64_t n, const Scalars *sc, const double *z, double *p,
+                                   int first, const int *skip) {
+  if (skipped(skip)) return;
   const double beta = first ? 0.0 : sc->rz_new / sc->rz;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x)
@@ -126,24 +166,21 @@ __global__ void cg_update_p_kernel(int64_t n, Scalars *sc, const double *z, doub
 }
 
 // rz <- rz_new once every block has read the old rz (a separate tiny kernel)
-__global__ void cg_shift_rz_kernel(Scalars *sc) {
-  sc->beta = sc->rz_new / sc->rz;
+__global__ void cg_shift_rz_kernel(Scalars *sc, const int *skip) {
+  if (skipped(skip)) return;
   sc->rz = sc->rz_new;
 }
-__global__ void cg_first_rz_kernel(Scalars *sc) { sc->rz = sc->rz_new; }
 
 hipError_t launch_cg_update_p(hipStream_t s, int64_t n, Scalars *sc, const double *z, double *p,
-                              int first) {
-  cg_update_p_kernel<<<nblocks(n, 4), kBs, 0, s>>>(n, sc, z, p, first);
-  if (first)
-    cg_first_rz_kernel<<<1, 1, 0, s>>>(sc);
-  else
-    cg_shift_rz_kernel<<<1, 1, 0, s>>>(sc);
+                              int first, const int *skip) {
+  cg_update_p_kernel<<<nblocks(n, 4), kBs, 0, s>>>(n, sc, z, p, first, skip);
+  cg_shift_rz_kernel<<<1, 1, 0, s>>>(sc, skip);
   return hipGetLastError();
 }
 
 __global__ void cheb_first_kernel(int64_t n, const double *r, const double *diag, double inv_theta,
-                                  double *d, double *x, double *res) {
+                                  double *d, double *x, double *res, const int *skip) {
+  if (skipped(skip)) return;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const double ri = r[i];
@@ -154,13 +191,14 @@ __global__ void cheb_first_kernel(int64_t n, const double *r, const double *diag
 }
 
 hipError_t launch_cheb_first(hipStream_t s, int64_t n, const double *r, const double *diag,
-                             double inv_theta, double *d, double *x, double *res) {
-  cheb_first_kernel<<<nblocks(n), kBs, 0, s>>>(n, r, diag, inv_theta, d, x, res);
+                             double inv_theta, double *d, double *x, double *res, const int *skip) {
+  cheb_first_kernel<<<nblocks(n), kBs, 0, s>>>(n, r, diag, inv_theta, d, x, res, skip);
   return hipGetLastError();
 }
 
 __global__ void cheb_start_kernel(int64_t n, const double *res, const double *diag,
-                                  double inv_theta, double *d, double *x) {
+                                  double inv_theta, double *d, double *x, const int *skip) {
+  if (skipped(skip)) return;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const double di = res[i] / diag[i] * inv_theta;
@@ -169,8 +207,8 @@ __global__ void cheb_start_kernel(int64_t n, const double *res, const double *di
 }
 
 hipError_t launch_cheb_start(hipStream_t s, int64_t n, const double *res, const double *diag,
-                             double inv_theta, double *d, double *x) {
-  cheb_start_kernel<<<nblocks(n), kBs, 0, s>>>(n, res, diag, inv_theta, d, x);
+                             double inv_theta, double *d, double *x, const int *skip) {
+  cheb_start_kernel<<<nblocks(n), kBs, 0, s>>>(n, res, diag, inv_theta, d, x, skip);
   return hipGetLastError();
 }
 

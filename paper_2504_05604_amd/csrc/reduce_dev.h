@@ -1,4 +1,10 @@
-// Device-side deterministic block reductions (header-only, included by kernels).
+// Device-side deterministic reductions (header-only, included by kernels).
+//
+// A reducing kernel writes one partial per block (fixed-order tree inside the
+// block) and a separate one-block finalize kernel sums the partials in block
+// order.  No floating-point atomics and no device-scope fences: on a multi-XCD
+// part a device-scope release fence in every block would write back the whole
+// L2 of that XCD, which costs far more than one extra small launch.
 #pragma once
 
 #include "internal.h"
@@ -19,53 +25,28 @@ __device__ __forceinline__ double wave_reduce(double v) {
   return v;
 }
 
-// Reduces v[0..N) over the block; block results go to red.partials, and the last
-// block to arrive sums them (fixed order) into out[0..N).  Must be called by every
-// thread of the block.  blockDim.x <= 1024.
+// Block-reduces v[0..N) and stores the block's results at
+// partials[slot * kMaxRed + k].  Every thread of the block must call it.
 template <int N, bool MAX>
-__device__ void block_reduce_finalize(double (&v)[N], const Reducer &red, double *out) {
+__device__ void block_reduce_store(double (&v)[N], double *partials, int slot) {
   __shared__ double sh[N][16];
-  __shared__ int is_last;
   const int lane = threadIdx.x & (kWave - 1);
   const int wid = threadIdx.x / kWave;
   const int nw = (blockDim.x + kWave - 1) / kWave;
 #pragma unroll
   for (int k = 0; k < N; ++k) {
-    double t = wave_reduce<MAX>(v[k]);
+    const double t = wave_reduce<MAX>(v[k]);
     if (lane == 0) sh[k][wid] = t;
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
-#pragma unroll
-    for (int k = 0; k < N; ++k) {
-      double t = sh[k][0];
-      for (int w = 1; w < nw; ++w) t = red_op<MAX>(t, sh[k][w]);
-      red.partials[(size_t)blockIdx.x * kMaxRed + k] = t;
-    }
-    __threadfence();
-    unsigned prev = atomicAdd(red.counter, 1u);
-    is_last = (prev == gridDim.x - 1);
+  if (threadIdx.x < N) {
+    const int k = threadIdx.x;
+    double t = sh[k][0];
+    for (int w = 1; w < nw; ++w) t = red_op<MAX>(t, sh[k][w]);
+    partials[(size_t)slot * kMaxRed + k] = t;
   }
-  __syncthreads();
-  if (!is_last) return;
-  __threadfence();
-  const volatile double *P = red.partials;
-#pragma unroll
-  for (int k = 0; k < N; ++k) {
-    double t = MAX ? -INFINITY : 0.0;
-    for (int b = threadIdx.x; b < (int)gridDim.x; b += blockDim.x)
-      t = red_op<MAX>(t, P[(size_t)b * kMaxRed + k]);
-    t = wave_reduce<MAX>(t);
-    __syncthreads();
-    if (lane == 0) sh[k][wid] = t;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      double s = sh[k][0];
-      for (int w = 1; w < nw; ++w) s = red_op<MAX>(s, sh[k][w]);
-      out[k] = s;
-    }
-  }
-  if (threadIdx.x == 0) atomicExch(red.counter, 0u);
 }
+
+__device__ __forceinline__ int linear_block() { return blockIdx.x + gridDim.x * blockIdx.y; }
 
 }  // namespace topo

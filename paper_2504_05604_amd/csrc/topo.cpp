@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "internal.h"
+#include "ke_code.h"
 
 namespace topo {
 
@@ -116,6 +117,8 @@ static hipError_t dalloc(T **p, size_t count) {
   return hipMalloc((void **)p, count * sizeof(T));
 }
 
+constexpr double kChebRatio = 30.0;  // Chebyshev interval [lam_max / ratio, lam_max]
+
 struct Level {
   Grid g{};
   double *E = nullptr;       // moduli incl. the 2^level stiffness scale
@@ -136,7 +139,7 @@ struct topo_ctx {
   int64_t nel = 0, ndof = 0, nnodes = 0, n_design = 0;
   double target = 0.0;
   // constants
-  double *KE = nullptr, *KEdiag = nullptr;
+  Kappa kap{};
   double lam_max = 0.0;
   // problem data
   double *f = nullptr;
@@ -159,6 +162,9 @@ struct topo_ctx {
   Scalars *h_sc = nullptr;  // pinned mirror
   Reducer red{};
   int have_u = 0;
+  hipStream_t cap_stream = nullptr;  // private stream for graph capture
+  hipGraph_t cg_graph = nullptr;
+  hipGraphExec_t cg_exec = nullptr;  // chunk of CG iterations
   std::vector<void *> allocs;
 
   template <typename T>
@@ -168,6 +174,9 @@ struct topo_ctx {
     return e;
   }
   ~topo_ctx() {
+    if (cg_exec) (void)hipGraphExecDestroy(cg_exec);
+    if (cg_graph) (void)hipGraphDestroy(cg_graph);
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
     for (void *a : allocs) (void)hipFree(a);
     if (h_sc) (void)hipHostFree(h_sc);
   }
@@ -175,10 +184,11 @@ struct topo_ctx {
 
 #define TOPO_ALLOC(ptr, count)                                               \
   do {                                                                       \
-    if (ctx->alloc(&(ptr), (count)) != hipSuccess) {                         \
-      set_error("device allocation of %s (%zu elements) failed", #ptr,       \
-                (size_t)(count));                                            \
-      return TOPO_ENOMEM;                                                    \
+    hipError_t ae_ = ctx->alloc(&(ptr), (count));                            \
+    if (ae_ != hipSuccess) {                                                 \
+      set_error("device allocation of %s (%zu elements) failed: %s", #ptr,   \
+                (size_t)(count), hipGetErrorString(ae_));                    \
+      return ae_ == hipErrorOutOfMemory ? TOPO_ENOMEM : TOPO_EDEVICE;        \
     }                                                                        \
   } while (0)
 
@@ -187,13 +197,14 @@ extern "C" void topo_default_opts(topo_opts *o) {
   o->precision = TOPO_PREC_FP64;
   o->precond = TOPO_PRECOND_MG;
   o->mg_levels = 0;
-  o->mg_max_coarse_dof = 400;
+  o->mg_max_coarse_dof = 140;
   o->cheb_degree = 2;
   o->rtol = 1e-8;
   o->max_iters = 1000;
   o->warm_start = 1;
   o->oc_tol = 1e-12;
-  o->check_every = 1;
+  o->check_every = 4;
+  o->use_graphs = 1;
 }
 
 extern "C" const char *topo_last_error(void) { return g_err; }
@@ -263,6 +274,9 @@ extern "C" topo_status topo_setup(const topo_problem *P, const topo_opts *O, voi
   if (!O) O = &defaults;
   topo_status st = validate(P, O);
   if (st != TOPO_OK) return st;
+  int device = 0;
+  TOPO_HIP(hipGetDevice(&device));
+  TOPO_HIP(hipSetDevice(device));
   std::unique_ptr<topo_ctx> c(new topo_ctx());
   topo_ctx *ctx = c.get();
   ctx->prob = *P;
@@ -289,10 +303,14 @@ extern "C" topo_status topo_setup(const topo_problem *P, const topo_opts *O, voi
       for (int j = 0; j < 24; ++j) S[i * 24 + j] = KE[i * 24 + j] / std::sqrt(KEd[i] * KEd[j]);
     ctx->lam_max = sym_max_eig(S, 24);
   }
-  TOPO_ALLOC(ctx->KE, 576);
-  TOPO_ALLOC(ctx->KEdiag, 24);
-  TOPO_HIP(hipMemcpyAsync(ctx->KE, KE, sizeof KE, hipMemcpyHostToDevice, s));
-  TOPO_HIP(hipMemcpyAsync(ctx->KEdiag, KEd, sizeof KEd, hipMemcpyHostToDevice, s));
+  // the kernels use the exact compile-time form of KE; check it against the
+  // quadrature once (they agree to rounding for every nu)
+  ctx->kap = make_kappa(P->nu);
+  for (int I = 0; I < 576; ++I) {
+    const double v = kKeTable.sign[I] * ctx->kap.k[kKeTable.idx[I]];
+    if (std::fabs(v - KE[I]) > 1e-12 * (1.0 + std::fabs(KE[I])))
+      return set_error("internal: element stiffness tables disagree"), TOPO_EINVAL;
+  }
 
   // host-side staging of the problem arrays
   std::vector<int8_t> hmask(ctx->nel, 0);
@@ -354,15 +372,14 @@ extern "C" topo_status topo_setup(const topo_problem *P, const topo_opts *O, voi
   TOPO_ALLOC(ctx->oc_a, ctx->nel);
   TOPO_ALLOC(ctx->xnew, ctx->nel);
   TOPO_HIP(hipMemsetAsync(ctx->u, 0, ctx->ndof * sizeof(double), s));
+  TOPO_HIP(hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
   ctx->lv[0].b = ctx->r;
   ctx->lv[0].x = ctx->z;
 
   // reductions
   const int64_t nb_nodes = (ctx->nnodes + 255) / 256;
-  ctx->red.max_blocks = (int)std::max<int64_t>(4096, nb_nodes + 1);
+  ctx->red.max_blocks = (int)std::max<int64_t>(16384, nb_nodes + 1);
   TOPO_ALLOC(ctx->red.partials, (size_t)ctx->red.max_blocks * kMaxRed);
-  TOPO_ALLOC(ctx->red.counter, 8);
-  TOPO_HIP(hipMemsetAsync(ctx->red.counter, 0, 8 * sizeof(unsigned), s));
   TOPO_ALLOC(ctx->sc, 1);
   TOPO_HIP(hipMemsetAsync(ctx->sc, 0, sizeof(Scalars), s));
   if (hipHostMalloc((void **)&ctx->h_sc, sizeof(Scalars), hipHostMallocDefault) != hipSuccess) {
@@ -427,7 +444,6 @@ static KuArgs ku_args(topo_ctx *ctx, const Level &L, const double *u) {
   KuArgs a{};
   a.g = L.g;
   a.E = L.E;
-  a.KE = ctx->KE;
   a.u = u;
   a.fixed = L.fixed;
   a.diag = L.diag;
@@ -442,11 +458,11 @@ static topo_status prepare_operator(topo_ctx *ctx, const double *d_xphys) {
   for (size_t l = 0; l < ctx->lv.size(); ++l) {
     Level &L = ctx->lv[l];
     if (l > 0) TOPO_HIP(launch_coarsen_moduli(s, ctx->lv[l - 1].g, L.g, ctx->lv[l - 1].E, L.E));
-    TOPO_HIP(launch_diag(s, L.g, L.E, ctx->KEdiag, L.fixed, L.diag));
+    TOPO_HIP(launch_diag(s, L.g, L.E, ctx->kap, L.fixed, L.diag));
   }
   if (ctx->lv.size() > 1) {
     const Level &C = ctx->lv.back();
-    TOPO_HIP(launch_dense_assemble(s, C.g, C.E, ctx->KE, C.fixed, ctx->Ainv));
+    TOPO_HIP(launch_dense_assemble(s, C.g, C.E, ctx->kap, C.fixed, ctx->Ainv));
     TOPO_HIP(launch_dense_invert(s, ctx->ncoarse, ctx->Ainv));
   }
   return TOPO_OK;
@@ -455,22 +471,23 @@ static topo_status prepare_operator(topo_ctx *ctx, const double *d_xphys) {
 // Chebyshev smoothing on level L for A x = b.  from_zero: x starts at 0 (pre-
 // smoothing); otherwise x holds the current iterate (post-smoothing).  On exit
 // L.res = b - A x when want_res.
-static topo_status cheb_smooth(topo_ctx *ctx, Level &L, bool from_zero, bool want_res) {
+static topo_status cheb_smooth(topo_ctx *ctx, Level &L, bool from_zero, bool want_res, const int *skip) {
   hipStream_t s = ctx->stream;
   const int deg = ctx->opts.cheb_degree;
-  const double hi = ctx->lam_max, lo = hi / 30.0;
+  const double hi = ctx->lam_max, lo = hi / kChebRatio;
   const double theta = 0.5 * (hi + lo), delta = 0.5 * (hi - lo), sigma = theta / delta;
   double rho = 1.0 / sigma;
   const int64_t n = L.g.ndof();
   double *din = L.d0, *dout = L.d1;
   if (from_zero) {
-    TOPO_HIP(launch_cheb_first(s, n, L.b, L.diag, 1.0 / theta, din, L.x, L.res));
+    TOPO_HIP(launch_cheb_first(s, n, L.b, L.diag, 1.0 / theta, din, L.x, L.res, skip));
   } else {
     KuArgs a = ku_args(ctx, L, L.x);
     a.y = L.res;
     a.b = L.b;
-    TOPO_HIP(launch_ku(s, KU_RESID, a, ctx->red, &ctx->sc->red[0]));
-    TOPO_HIP(launch_cheb_start(s, n, L.res, L.diag, 1.0 / theta, din, L.x));
+    a.skip = skip;
+    TOPO_HIP(launch_ku(s, KU_RESID, a, ctx->kap, ctx->red, &ctx->sc->red[0]));
+    TOPO_HIP(launch_cheb_start(s, n, L.res, L.diag, 1.0 / theta, din, L.x, skip));
   }
   for (int k = 1; k < deg; ++k) {
     const double rho_new = 1.0 / (2.0 * sigma - rho);
@@ -480,47 +497,49 @@ static topo_status cheb_smooth(topo_ctx *ctx, Level &L, bool from_zero, bool wan
     a.dout = dout;
     a.c1 = rho_new * rho;
     a.c2 = 2.0 * rho_new / delta;
-    TOPO_HIP(launch_ku(s, KU_CHEB, a, ctx->red, nullptr));
+    a.skip = skip;
+    TOPO_HIP(launch_ku(s, KU_CHEB, a, ctx->kap, ctx->red, nullptr));
     std::swap(din, dout);
     rho = rho_new;
   }
   if (want_res) {
     KuArgs a = ku_args(ctx, L, din);
     a.res = L.res;
-    TOPO_HIP(launch_ku(s, KU_RESUPD, a, ctx->red, nullptr));
+    a.skip = skip;
+    TOPO_HIP(launch_ku(s, KU_RESUPD, a, ctx->kap, ctx->red, nullptr));
   }
   return TOPO_OK;
 }
 
 // z = M r: V-cycle from level l with rhs lv[l].b into lv[l].x
-static topo_status vcycle(topo_ctx *ctx, size_t l) {
+static topo_status vcycle(topo_ctx *ctx, size_t l, const int *skip) {
   hipStream_t s = ctx->stream;
   Level &L = ctx->lv[l];
   if (l + 1 == ctx->lv.size()) {
-    TOPO_HIP(launch_dense_matvec(s, ctx->ncoarse, ctx->Ainv, L.b, L.x));
+    TOPO_HIP(launch_dense_matvec(s, ctx->ncoarse, ctx->Ainv, L.b, L.x, skip));
     return TOPO_OK;
   }
-  topo_status st = cheb_smooth(ctx, L, true, true);
+  topo_status st = cheb_smooth(ctx, L, true, true, skip);
   if (st != TOPO_OK) return st;
   Level &C = ctx->lv[l + 1];
-  TOPO_HIP(launch_restrict(s, L.g, C.g, L.res, C.fixed, C.b));
-  st = vcycle(ctx, l + 1);
+  TOPO_HIP(launch_restrict(s, L.g, C.g, L.res, C.fixed, C.b, skip));
+  st = vcycle(ctx, l + 1, skip);
   if (st != TOPO_OK) return st;
-  TOPO_HIP(launch_prolong_add(s, L.g, C.g, C.x, L.fixed, L.x));
-  return cheb_smooth(ctx, L, false, false);
+  TOPO_HIP(launch_prolong_add(s, L.g, C.g, C.x, L.fixed, L.x, skip));
+  return cheb_smooth(ctx, L, false, false, skip);
 }
 
 // z = M r and sc->rz_new = r.z
-static topo_status precondition(topo_ctx *ctx) {
+static topo_status precondition(topo_ctx *ctx, const int *skip) {
   hipStream_t s = ctx->stream;
   Level &L0 = ctx->lv[0];
   if (ctx->opts.precond == TOPO_PRECOND_JACOBI || ctx->lv.size() == 1) {
-    TOPO_HIP(launch_jacobi(s, ctx->ndof, ctx->r, L0.diag, ctx->z, ctx->red, &ctx->sc->rz_new));
+    TOPO_HIP(launch_jacobi(s, ctx->ndof, ctx->r, L0.diag, ctx->z, ctx->red, &ctx->sc->rz_new, skip));
     return TOPO_OK;
   }
-  topo_status st = vcycle(ctx, 0);
+  topo_status st = vcycle(ctx, 0, skip);
   if (st != TOPO_OK) return st;
-  TOPO_HIP(launch_dot(s, ctx->ndof, ctx->r, ctx->z, ctx->red, &ctx->sc->rz_new));
+  TOPO_HIP(launch_dot(s, ctx->ndof, ctx->r, ctx->z, ctx->red, &ctx->sc->rz_new, skip));
   return TOPO_OK;
 }
 
@@ -530,54 +549,96 @@ static topo_status read_scalars(topo_ctx *ctx) {
   return TOPO_OK;
 }
 
-// PCG on the operator prepared by prepare_operator; solution in/out d_u.
-static topo_status pcg(topo_ctx *ctx, double *d_u, topo_solve_stats *stats) {
+// One CG iteration on ctx->u; after convergence (sc->cg_done) every kernel
+// returns immediately, so chunks of iterations can be enqueued (or replayed
+// from a graph) without a host round trip per iteration.
+static topo_status cg_body(topo_ctx *ctx) {
+  hipStream_t s = ctx->stream;
+  const int *skip = &ctx->sc->cg_done;
+  Level &L0 = ctx->lv[0];
+  KuArgs a = ku_args(ctx, L0, ctx->p);
+  a.y = ctx->q;
+  a.skip = skip;
+  TOPO_HIP(launch_ku(s, KU_STORE_DOT, a, ctx->kap, ctx->red, &ctx->sc->pq));
+  TOPO_HIP(launch_cg_update_xr(s, ctx->ndof, ctx->sc, ctx->u, ctx->r, ctx->p, ctx->q, ctx->red, skip));
+  TOPO_HIP(launch_cg_check(s, ctx->sc, ctx->opts.rtol * ctx->opts.rtol, ctx->opts.max_iters));
+  topo_status st = precondition(ctx, skip);
+  if (st != TOPO_OK) return st;
+  TOPO_HIP(launch_cg_update_p(s, ctx->ndof, ctx->sc, ctx->z, ctx->p, 0, skip));
+  return TOPO_OK;
+}
+
+// Enqueues one chunk of check_every CG iterations: the captured graph when graphs
+// are on (captured on first use; every pointer it holds is owned by the context),
+// direct launches otherwise.
+static topo_status cg_chunk(topo_ctx *ctx) {
+  const int chunk = std::max(1, ctx->opts.check_every);
+  if (!ctx->opts.use_graphs) {
+    for (int c = 0; c < chunk; ++c) {
+      topo_status st = cg_body(ctx);
+      if (st != TOPO_OK) return st;
+    }
+    return TOPO_OK;
+  }
+  if (!ctx->cg_exec) {
+    hipStream_t user = ctx->stream;
+    ctx->stream = ctx->cap_stream;
+    TOPO_HIP(hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeRelaxed));
+    topo_status st = TOPO_OK;
+    for (int c = 0; c < chunk && st == TOPO_OK; ++c) st = cg_body(ctx);
+    hipGraph_t graph = nullptr;
+    hipError_t ce = hipStreamEndCapture(ctx->cap_stream, &graph);
+    ctx->stream = user;
+    if (st != TOPO_OK) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return st;
+    }
+    TOPO_HIP(ce);
+    ctx->cg_graph = graph;
+    TOPO_HIP(hipGraphInstantiate(&ctx->cg_exec, graph, nullptr, nullptr, 0));
+  }
+  TOPO_HIP(hipGraphLaunch(ctx->cg_exec, ctx->stream));
+  return TOPO_OK;
+}
+
+// PCG on the operator prepared by prepare_operator; solution in/out ctx->u.
+static topo_status pcg(topo_ctx *ctx, topo_solve_stats *stats) {
   hipStream_t s = ctx->stream;
   Level &L0 = ctx->lv[0];
   const int64_t n = ctx->ndof;
-  TOPO_HIP(launch_zero_fixed(s, ctx->nnodes, L0.fixed, d_u));
+  TOPO_HIP(launch_zero_fixed(s, ctx->nnodes, L0.fixed, ctx->u));
   // r = f - K u, rr
   {
-    KuArgs a = ku_args(ctx, L0, d_u);
+    KuArgs a = ku_args(ctx, L0, ctx->u);
     a.y = ctx->r;
     a.b = ctx->f;
-    TOPO_HIP(launch_ku(s, KU_RESID, a, ctx->red, &ctx->sc->rr));
+    TOPO_HIP(launch_ku(s, KU_RESID, a, ctx->kap, ctx->red, &ctx->sc->rr));
   }
   TOPO_HIP(launch_dot(s, n, ctx->f, ctx->f, ctx->red, &ctx->sc->ff));
-  topo_status st = read_scalars(ctx);
+  const double rtol = ctx->opts.rtol;
+  // iteration count 0; done at once if the initial guess already meets the tolerance
+  TOPO_HIP(launch_cg_start(s, ctx->sc, rtol * rtol));
+  // first direction (skipped on the device when already converged)
+  topo_status st = precondition(ctx, &ctx->sc->cg_done);
   if (st != TOPO_OK) return st;
-  const double fnorm = std::sqrt(ctx->h_sc->ff);
-  double relres = std::sqrt(ctx->h_sc->rr) / fnorm;
-  int it = 0;
-  const int check = std::max(1, ctx->opts.check_every);
-  if (relres > ctx->opts.rtol) {
-    st = precondition(ctx);
+  TOPO_HIP(launch_cg_update_p(s, n, ctx->sc, ctx->z, ctx->p, 1, &ctx->sc->cg_done));
+  st = read_scalars(ctx);
+  if (st != TOPO_OK) return st;
+  while (!ctx->h_sc->cg_done) {
+    st = cg_chunk(ctx);
     if (st != TOPO_OK) return st;
-    TOPO_HIP(launch_cg_update_p(s, n, ctx->sc, ctx->z, ctx->p, 1));
-    while (it < ctx->opts.max_iters) {
-      KuArgs a = ku_args(ctx, L0, ctx->p);
-      a.y = ctx->q;
-      TOPO_HIP(launch_ku(s, KU_STORE_DOT, a, ctx->red, &ctx->sc->pq));
-      TOPO_HIP(launch_cg_update_xr(s, n, ctx->sc, d_u, ctx->r, ctx->p, ctx->q, ctx->red));
-      ++it;
-      if (it % check == 0 || it == ctx->opts.max_iters) {
-        st = read_scalars(ctx);
-        if (st != TOPO_OK) return st;
-        relres = std::sqrt(ctx->h_sc->rr) / fnorm;
-        if (!(relres > ctx->opts.rtol) || !std::isfinite(relres)) break;
-      }
-      st = precondition(ctx);
-      if (st != TOPO_OK) return st;
-      TOPO_HIP(launch_cg_update_p(s, n, ctx->sc, ctx->z, ctx->p, 0));
-    }
+    st = read_scalars(ctx);
+    if (st != TOPO_OK) return st;
   }
+  const double ff = ctx->h_sc->ff;
+  const double relres = std::sqrt(ctx->h_sc->rr / ff);
   if (stats) {
-    stats->iters = it;
+    stats->iters = ctx->h_sc->cg_iters;
     stats->relres = relres;
-    stats->converged = relres <= ctx->opts.rtol;
+    stats->converged = relres <= rtol;
   }
   if (!std::isfinite(relres)) return set_error("CG diverged (non-finite residual)"), TOPO_ENOTCONVERGED;
-  if (relres > ctx->opts.rtol)
+  if (relres > rtol)
     return set_error("CG reached max_iters=%d with relres %.3e", ctx->opts.max_iters, relres), TOPO_ENOTCONVERGED;
   return TOPO_OK;
 }
@@ -592,7 +653,7 @@ extern "C" topo_status topo_apply_K(topo_ctx *ctx, const double *d_xphys, const 
   TOPO_HIP(launch_copy_masked(s, ctx->nnodes, L0.fixed, d_u, ctx->tmp));
   KuArgs a = ku_args(ctx, L0, ctx->tmp);
   a.y = d_y;
-  TOPO_HIP(launch_ku(s, KU_STORE, a, ctx->red, nullptr));
+  TOPO_HIP(launch_ku(s, KU_STORE, a, ctx->kap, ctx->red, nullptr));
   // identity rows return the caller's u (not the zeroed copy) on fixed dofs
   TOPO_HIP(launch_copy_fixed(s, ctx->nnodes, L0.fixed, d_u, d_y));
   return TOPO_OK;
@@ -606,7 +667,7 @@ extern "C" topo_status topo_apply_precond(topo_ctx *ctx, const double *d_xphys, 
   topo_status st = prepare_operator(ctx, d_xphys);
   if (st != TOPO_OK) return st;
   TOPO_HIP(hipMemcpyAsync(ctx->r, d_r, ctx->ndof * sizeof(double), hipMemcpyDeviceToDevice, s));
-  st = precondition(ctx);
+  st = precondition(ctx, nullptr);
   if (st != TOPO_OK) return st;
   TOPO_HIP(hipMemcpyAsync(d_z, ctx->z, ctx->ndof * sizeof(double), hipMemcpyDeviceToDevice, s));
   return TOPO_OK;
@@ -620,7 +681,12 @@ extern "C" topo_status topo_solve(topo_ctx *ctx, const double *d_xphys, double *
   TOPO_HIP(hipEventRecord(e0, ctx->stream));
   topo_status st = prepare_operator(ctx, d_xphys);
   topo_solve_stats stats{};
-  if (st == TOPO_OK) st = pcg(ctx, d_u, &stats);
+  if (st == TOPO_OK) {
+    TOPO_HIP(hipMemcpyAsync(ctx->u, d_u, ctx->ndof * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
+    st = pcg(ctx, &stats);
+    TOPO_HIP(hipMemcpyAsync(d_u, ctx->u, ctx->ndof * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
+    ctx->have_u = 1;
+  }
   (void)hipEventRecord(e1, ctx->stream);
   (void)hipEventSynchronize(e1);
   float ms = 0.f;
@@ -637,7 +703,7 @@ extern "C" topo_status topo_sensitivity(topo_ctx *ctx, const double *d_xphys, co
   if (!ctx || !d_xphys || !d_u || !d_ce || !d_dc) return set_error("NULL argument"), TOPO_EINVAL;
   hipStream_t s = ctx->stream;
   const topo_problem &P = ctx->prob;
-  TOPO_HIP(launch_sensitivity(s, ctx->g, ctx->KE, d_u, d_xphys, P.E0, P.Emin, P.penal, d_ce, d_dc));
+  TOPO_HIP(launch_sensitivity(s, ctx->g, ctx->kap, d_u, d_xphys, P.E0, P.Emin, P.penal, d_ce, d_dc));
   if (h_compliance) {
     TOPO_HIP(launch_dot(s, ctx->ndof, ctx->f, d_u, ctx->red, &ctx->sc->comp));
     topo_status st = read_scalars(ctx);
@@ -709,13 +775,13 @@ extern "C" topo_status topo_iterate(topo_ctx *ctx, double *d_x, int32_t n_iter, 
     if (!ctx->opts.warm_start || !ctx->have_u) TOPO_HIP(hipMemsetAsync(ctx->u, 0, ctx->ndof * sizeof(double), s));
     topo_status st = prepare_operator(ctx, ctx->xphys);
     topo_solve_stats ss{};
-    if (st == TOPO_OK) st = pcg(ctx, ctx->u, &ss);
+    if (st == TOPO_OK) st = pcg(ctx, &ss);
     if (st != TOPO_OK && st != TOPO_ENOTCONVERGED) return st;
     if (st == TOPO_ENOTCONVERGED) result = st;
     ctx->have_u = 1;
     (void)hipEventRecord(ev[2], s);
     // sensitivities and compliance
-    TOPO_HIP(launch_sensitivity(s, ctx->g, ctx->KE, ctx->u, ctx->xphys, P.E0, P.Emin, P.penal, ctx->ce, ctx->dc));
+    TOPO_HIP(launch_sensitivity(s, ctx->g, ctx->kap, ctx->u, ctx->xphys, P.E0, P.Emin, P.penal, ctx->ce, ctx->dc));
     TOPO_HIP(launch_dot(s, ctx->ndof, ctx->f, ctx->u, ctx->red, &ctx->sc->comp));
     (void)hipEventRecord(ev[3], s);
     // filtered sensitivities and OC update
@@ -753,6 +819,28 @@ extern "C" topo_status topo_iterate(topo_ctx *ctx, double *d_x, int32_t n_iter, 
   TOPO_HIP(hipStreamSynchronize(s));
   for (auto &e : ev) (void)hipEventDestroy(e);
   return result;
+}
+
+extern "C" topo_status topo_time_operator(topo_ctx *ctx, int32_t reps, double *h_ms) {
+  if (!ctx || reps < 1 || !h_ms) return set_error("invalid argument"), TOPO_EINVAL;
+  hipStream_t s = ctx->stream;
+  Level &L0 = ctx->lv[0];
+  KuArgs a = ku_args(ctx, L0, ctx->u);
+  a.y = ctx->tmp;
+  hipEvent_t e0, e1;
+  TOPO_HIP(hipEventCreate(&e0));
+  TOPO_HIP(hipEventCreate(&e1));
+  TOPO_HIP(launch_ku(s, KU_STORE_DOT, a, ctx->kap, ctx->red, &ctx->sc->red[0]));  // warm caches
+  TOPO_HIP(hipEventRecord(e0, s));
+  for (int i = 0; i < reps; ++i) TOPO_HIP(launch_ku(s, KU_STORE_DOT, a, ctx->kap, ctx->red, &ctx->sc->red[0]));
+  TOPO_HIP(hipEventRecord(e1, s));
+  TOPO_HIP(hipEventSynchronize(e1));
+  float ms = 0.f;
+  TOPO_HIP(hipEventElapsedTime(&ms, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  *h_ms = (double)ms / reps;
+  return TOPO_OK;
 }
 
 extern "C" topo_status topo_get_state(topo_ctx *ctx, double *d_u, double *d_xphys) {

@@ -72,24 +72,26 @@ def test_apply_K_matches_oracle(case):
 
 
 @pytest.mark.parametrize("case", CASES)
-@pytest.mark.parametrize("precond", ["mg", "jacobi"])
+@pytest.mark.parametrize("precond", ["mg140", "mg400", "mg400deg3", "jacobi"])
 def test_preconditioner_matches_oracle(case, precond):
     p = make_case(case)
     x = synth.random_density(5, p.nel, 0.0, 1.0)
     E = fem.simp_modulus(x, p.E0, p.Emin, p.penal)
     r = synth.random_vector(6, p.ndof)
     r[fixed_mask(p)] = 0.0
-    if precond == "mg":
-        V = mg.VCycle(p, E, KE, degree=2, max_coarse_dof=400)
+    if precond.startswith("mg"):
+        coarse = 140 if precond == "mg140" else 400
+        deg = 3 if precond.endswith("deg3") else 2
+        V = mg.VCycle(p, E, KE, degree=deg, max_coarse_dof=coarse)
         ref = V.apply(r)
-        opts = topo.default_opts(precond=topo.PRECOND_MG)
+        opts = topo.default_opts(precond=topo.PRECOND_MG, mg_max_coarse_dof=coarse, cheb_degree=deg)
     else:
         K = mg.with_identity_rows(fem.assemble(E, KE, fem.element_dofs(p.nelx, p.nely, p.nelz), p.ndof),
                                   fixed_mask(p))
         ref = r / K.diagonal()
         opts = topo.default_opts(precond=topo.PRECOND_JACOBI)
     with topo.Context(p, opts) as ctx:
-        if precond == "mg":
+        if precond.startswith("mg"):
             assert ctx.mg_levels == len(V.levels)
         z = torch.empty(p.ndof, dtype=torch.float64, device="cuda")
         ctx.apply_precond(dev(x), dev(r), z)
@@ -170,12 +172,14 @@ def test_oc_update_matches_exact_multiplier(seed, move):
     design = p.mask == 0
     rng = np.random.default_rng(seed)
     x = p.initial_design()
-    x[design] = rng.uniform(0.0, 1.0, design.sum())
+    # current volume near the target so that the move limits leave it reachable
+    x[design] = rng.uniform(0.0, 2 * p.volfrac, design.sum())
     x[design & (rng.random(p.nel) < 0.05)] = 0.0
     dc = F.adjoint(-rng.exponential(1.0, p.nel) * 10 ** rng.uniform(-3, 2))
     w = F.volume_weights()
     target = p.volfrac * design.sum()
     xref, lam_ref = oc.oc_exact(x, dc, w, w, target, p.move, p.eta, design)
+    assert abs(w @ xref - target) <= 1e-9 * target
     with topo.Context(p) as ctx:
         xn = torch.empty(p.nel, dtype=torch.float64, device="cuda")
         chg, lam = ctx.oc_update(dev(x), dev(dc), dev(w), xn)
@@ -185,6 +189,24 @@ def test_oc_update_matches_exact_multiplier(seed, move):
     assert np.array_equal(got[~design], x[~design])
     assert abs(chg - np.abs(xref - x).max()) <= 1e-10
     assert abs(w @ got - target) <= 1e-9 * target
+
+
+def test_oc_update_unreachable_target_moves_to_bounds():
+    """Volume far above the target with a small move limit: every design element
+    takes its lower bound (the multiplier runs to the top of its bracket)."""
+    p = ragged_problem(40, (15, 9, 7), rmin=1.5)
+    p.move = 0.05
+    F = filt.Filter(p.nelx, p.nely, p.nelz, p.rmin, p.mask)
+    design = p.mask == 0
+    x = p.initial_design()
+    x[design] = np.random.default_rng(1).uniform(0.6, 1.0, design.sum())
+    dc = F.adjoint(-np.random.default_rng(2).exponential(1.0, p.nel))
+    w = F.volume_weights()
+    with topo.Context(p) as ctx:
+        xn = torch.empty(p.nel, dtype=torch.float64, device="cuda")
+        ctx.oc_update(dev(x), dev(dc), dev(w), xn)
+        got = host(xn)
+    np.testing.assert_allclose(got[design], np.maximum(0.0, x[design] - p.move), atol=1e-12)
 
 
 def run_gpu_trajectory(p, n_iter, **opt):
