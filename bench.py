@@ -94,6 +94,8 @@ def main():
     ap.add_argument("--coarse-dof", type=int, default=140, help="coarsest multigrid level size cap")
     ap.add_argument("--check-every", type=int, default=4)
     ap.add_argument("--no-graphs", action="store_true")
+    ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64",
+                    help="precision of the multigrid preconditioner (CG stays FP64)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on exactly one GPU; --gpus above 1 is not supported "
@@ -111,6 +113,7 @@ def main():
     opts = topo.default_opts(rtol=1e-8, max_iters=2000, cheb_degree=args.cheb_degree,
                              mg_max_coarse_dof=args.coarse_dof, check_every=args.check_every,
                              use_graphs=0 if args.no_graphs else 1,
+                             precision=topo.PREC_FP64 if args.precision == "fp64" else topo.PREC_FP32,
                              precond=topo.PRECOND_MG if args.precond == "mg" else topo.PRECOND_JACOBI)
     ctx = topo.Context(p, opts)
     x = torch.from_numpy(p.initial_design()).to("cuda")
@@ -159,6 +162,7 @@ def main():
             "nel": p.nel, "ndof": p.ndof, "precond": args.precond, "mg_levels": ctx.mg_levels,
             "cheb_degree": deg, "rtol": 1e-8, "warm_start": True, "coarse_dof_cap": args.coarse_dof,
             "check_every": args.check_every, "graphs": not args.no_graphs,
+            "preconditioner_precision": args.precision,
             "pcg_iters_mean": round(float(pcg.mean()), 2), "pcg_iters_max": int(pcg.max()),
             "solve_ms_mean": round(float(solve_ms.mean()), 3),
             "dof_pcg_iters_per_s": round(float(p.ndof * pcg.sum() / (solve_ms.sum() * 1e-3)), 1),

@@ -62,7 +62,11 @@ enum {
   TOPO_FILTER_SENS = 2, /* out = H (aux * in) / (Hs * max(1e-3, aux)); aux = x             */
   TOPO_FILTER_VOLW = 3  /* out = H (1_D / Hs): filtered volume weights (in, aux unused)    */
 };
-/* internal precision of the operator and preconditioner (vectors stay FP64) */
+/* precision of the multigrid preconditioner.  FP32: smoothing, transfers and
+ * the coarse solve run in single precision (FP32 accumulation) and the CG
+ * recurrence switches to the flexible (Polak-Ribiere) update; the CG operator,
+ * vectors, inner products and stopping test stay FP64, so the solution meets
+ * the same FP64 residual tolerance.  BF16: reserved (TOPO_EUNSUPPORTED). */
 enum { TOPO_PREC_FP64 = 0, TOPO_PREC_FP32 = 1, TOPO_PREC_BF16 = 2 };
 /* preconditioner of the conjugate-gradient solve */
 enum { TOPO_PRECOND_JACOBI = 0, TOPO_PRECOND_MG = 1 };

@@ -64,48 +64,75 @@ struct Scalars {
   double oc_lam[64];
 };
 
-struct Kappa;  // ke_code.h
+template <typename T>
+struct KappaT;  // ke_code.h
+using Kappa = KappaT<double>;
 
 // ---------------------------------------------------------------------------
 // kernel launchers (kernels_*.hip)
 
-// sums nparts partials (slot-major, k-th value at [slot*kMaxRed + k]) into out[0..n)
-hipError_t launch_finalize(hipStream_t s, const Reducer &red, int nparts, int n, bool is_max,
-                           double *out, const int *skip = nullptr);
+// What a finalize does with the reduced value (see finalize_kernel):
+enum FinMode { FIN_SUM = 0, FIN_MAX = 1, FIN_CG_CHECK = 2, FIN_RZ = 3, FIN_RZ_FLEX = 4 };
+struct Fin {
+  int mode;
+  double *out;      // device result slot(s)
+  Scalars *sc;      // FIN_CG_CHECK / FIN_RZ
+  double rtol2;     // FIN_CG_CHECK
+  int max_iters;    // FIN_CG_CHECK
+};
+inline Fin fin_sum(double *out) { return Fin{FIN_SUM, out, nullptr, 0.0, 0}; }
+inline Fin fin_max(double *out) { return Fin{FIN_MAX, out, nullptr, 0.0, 0}; }
+
+// sums nparts partials (slot-major, k-th value at [slot*kMaxRed + k]) into fin.out[0..n)
+hipError_t launch_finalize(hipStream_t s, const Reducer &red, int nparts, int n, const Fin &fin,
+                           const int *skip = nullptr);
 
 // E_e = Emin + xphys^p (E0 - Emin), times scale
 hipError_t launch_simp_modulus(hipStream_t s, int64_t nel, const double *xphys, double E0,
                                double Emin, double penal, double scale, double *E);
 // E_c = 2 * mean of the 8 children (missing children count as 0)
 hipError_t launch_coarsen_moduli(hipStream_t s, Grid gf, Grid gc, const double *Ef, double *Ec);
-// diag_i = sum_{e ni i} E_e KE_{li,li}; 1 on fixed dofs
+// dinv_i = 1 / sum_{e ni i} E_e KE_{li,li}; 0 on fixed dofs
 hipError_t launch_diag(hipStream_t s, Grid g, const double *E, const Kappa &kap,
-                       const uint8_t *fixed, double *diag);
+                       const uint8_t *fixed, double *dinv);
 
 // K.u variants (matrix-free, identity rows on fixed dofs); the input vector must
 // be zero on fixed dofs.
 enum KuEpi {
-  KU_STORE = 0,      // y = Au
-  KU_STORE_DOT = 1,  // y = Au, out = u.y
-  KU_RESID = 2,      // y = b - Au, out = y.y
-  KU_CHEB = 3,       // res -= Au; dout = c1 u + c2 res/diag; x += dout
-  KU_RESUPD = 4,     // res -= Au
+  KU_STORE = 0,        // y = Au
+  KU_STORE_DOT = 1,    // y = Au, reduce u.y
+  KU_RESID = 2,        // y = b - Au, reduce y.y
+  KU_RES0 = 3,         // operand d0 = b dinv s0: x = d0; res = b - A d0
+  KU_CHEB0 = 4,        // operand d0 = b dinv s0: res = b - A d0; dout = c1 d0 + c2 res dinv; x = d0 + dout
+  KU_CHEB = 5,         // res -= Au; dout = c1 u + c2 res dinv; x += dout      [reduce dot_with.x]
+  KU_CHEB_ADD = 6,     // as KU_CHEB with x += u + dout (u = the pending step)  [reduce dot_with.x]
+  KU_RESUPD = 7,       // res -= Au
+  KU_RESID_START = 8,  // res = b - Au; dout = res dinv s0 (x not updated: the next
+                       // KU_CHEB_ADD adds dout)
 };
-struct KuArgs {
+template <typename T>
+struct KuArgsT {
   Grid g;
-  const double *E;
-  const double *u;        // input (stencil operand)
-  double *y;              // STORE, STORE_DOT, RESID output
-  const double *b;        // RESID rhs
+  const T *E;
+  const T *u;             // stencil operand
+  T *y;                   // STORE, STORE_DOT, RESID output
+  const T *b;             // right-hand side
   const uint8_t *fixed;   // per node, bit c set if dof c is fixed
-  double *res, *x, *dout; // CHEB / RESUPD
-  const double *diag;
-  double c1, c2;
+  T *res, *x, *dout;      // smoother vectors
+  const T *dinv;          // inverse Jacobi diagonal (0 on fixed dofs)
+  T c1, c2, s0;
+  const T *dot_with;      // CHEB / CHEB_ADD: if set, reduce dot_with . x_new
   const int *skip;        // device flag: return at once when non-zero (may be NULL)
 };
-// out (device scalar) receives the reduction of STORE_DOT / RESID
+using KuArgs = KuArgsT<double>;
+// fin receives the reduction of STORE_DOT / RESID / CHEB with dot_with
+// shape: launch shape index (-1 = chosen from the grid size)
 hipError_t launch_ku(hipStream_t s, KuEpi epi, const KuArgs &a, const Kappa &kap, const Reducer &red,
-                     double *out);
+                     const Fin &fin, int shape = -1);
+// single-precision operator (smoothing passes only: no reducing epilogues)
+hipError_t launch_ku(hipStream_t s, KuEpi epi, const KuArgsT<float> &a, const KappaT<float> &kap,
+                     const Reducer &red, const Fin &fin, int shape = -1);
+int ku_shape_for(const Grid &g, KuEpi epi);
 
 // vector kernels
 hipError_t launch_zero_fixed(hipStream_t s, int64_t nnodes, const uint8_t *fixed, double *v);
@@ -115,40 +142,55 @@ hipError_t launch_copy_masked(hipStream_t s, int64_t nnodes, const uint8_t *fixe
 hipError_t launch_copy_fixed(hipStream_t s, int64_t nnodes, const uint8_t *fixed, const double *in,
                              double *out);
 hipError_t launch_dot(hipStream_t s, int64_t n, const double *a, const double *b, const Reducer &red,
-                      double *out, const int *skip = nullptr);
-// x += alpha p; r -= alpha q; sc->rr = r.r        (alpha = sc->rz / sc->pq)
+                      const Fin &fin, const int *skip = nullptr);
+// x += alpha p; r -= alpha q; fin.out = r.r (alpha = sc->rz / sc->pq); with
+// FIN_CG_CHECK the finalize also runs the device-side convergence test
 hipError_t launch_cg_update_xr(hipStream_t s, int64_t n, Scalars *sc, double *x, double *r,
                                const double *p, const double *q, const Reducer &red,
-                               const int *skip = nullptr);
-// device-side convergence test (cg_iters += 1; cg_done once rr <= rtol2 ff or at the cap)
-hipError_t launch_cg_check(hipStream_t s, Scalars *sc, double rtol2, int max_iters);
+                               const Fin &fin, const int *skip = nullptr);
 // cg_iters = 0; cg_done = (rr <= rtol2 ff)
 hipError_t launch_cg_start(hipStream_t s, Scalars *sc, double rtol2);
-// z = r / diag; out = r.z
-hipError_t launch_jacobi(hipStream_t s, int64_t n, const double *r, const double *diag, double *z,
-                         const Reducer &red, double *out, const int *skip = nullptr);
-// p = z + beta p, beta = rz_new / rz (0 if first); rz = rz_new
+// z = r * dinv; fin.out = r.z
+hipError_t launch_jacobi(hipStream_t s, int64_t n, const double *r, const double *dinv, double *z,
+                         const Reducer &red, const Fin &fin, const int *skip = nullptr);
+// p = z + beta p (p = z if first); beta is set by the FIN_RZ finalize of r.z
 hipError_t launch_cg_update_p(hipStream_t s, int64_t n, Scalars *sc, const double *z, double *p,
                               int first, const int *skip = nullptr);
-// Chebyshev first step from x = 0: d = r/(diag theta); x = d; res = r
-hipError_t launch_cheb_first(hipStream_t s, int64_t n, const double *r, const double *diag,
+// Chebyshev first step from x = 0: d = r dinv / theta; x = d; res = r
+hipError_t launch_cheb_first(hipStream_t s, int64_t n, const double *r, const double *dinv,
                              double inv_theta, double *d, double *x, double *res,
                              const int *skip = nullptr);
-// d = res/(diag theta); x += d
-hipError_t launch_cheb_start(hipStream_t s, int64_t n, const double *res, const double *diag,
+// d = res dinv / theta; x += d
+hipError_t launch_cheb_start(hipStream_t s, int64_t n, const double *res, const double *dinv,
                              double inv_theta, double *d, double *x, const int *skip = nullptr);
+hipError_t launch_cheb_first(hipStream_t s, int64_t n, const float *r, const float *dinv,
+                             float inv_theta, float *d, float *x, float *res, const int *skip = nullptr);
+hipError_t launch_cheb_start(hipStream_t s, int64_t n, const float *res, const float *dinv,
+                             float inv_theta, float *d, float *x, const int *skip = nullptr);
+// out = (float) in
+hipError_t launch_convert(hipStream_t s, int64_t n, const double *in, float *out,
+                          const int *skip = nullptr);
+// z = (double) x; fin.out[0] = r.z_new, fin.out[1] = r.z_old (FIN_RZ_FLEX)
+hipError_t launch_widen_dot(hipStream_t s, int64_t n, const float *x, const double *r, double *z,
+                            const Reducer &red, const Fin &fin, const int *skip = nullptr);
 
 // multigrid transfers
 hipError_t launch_restrict(hipStream_t s, Grid gf, Grid gc, const double *rf, const uint8_t *fixc,
                            double *rc, const int *skip = nullptr);
 hipError_t launch_prolong_add(hipStream_t s, Grid gf, Grid gc, const double *ec,
                               const uint8_t *fixf, double *xf, const int *skip = nullptr);
+hipError_t launch_restrict(hipStream_t s, Grid gf, Grid gc, const float *rf, const uint8_t *fixc,
+                           float *rc, const int *skip = nullptr);
+hipError_t launch_prolong_add(hipStream_t s, Grid gf, Grid gc, const float *ec,
+                              const uint8_t *fixf, float *xf, const int *skip = nullptr);
 hipError_t launch_coarse_fixed(hipStream_t s, Grid gf, Grid gc, const uint8_t *fixf, uint8_t *fixc);
 // dense coarsest-level operator, inverse and application
 hipError_t launch_dense_assemble(hipStream_t s, Grid g, const double *E, const Kappa &kap,
                                  const uint8_t *fixed, double *A);
 hipError_t launch_dense_invert(hipStream_t s, int n, double *A);
 hipError_t launch_dense_matvec(hipStream_t s, int n, const double *A, const double *x, double *y,
+                               const int *skip = nullptr);
+hipError_t launch_dense_matvec(hipStream_t s, int n, const float *A, const float *x, float *y,
                                const int *skip = nullptr);
 
 // sensitivities: ce = u_e^T KE u_e, dc = -p xphys^(p-1) (E0-Emin) ce

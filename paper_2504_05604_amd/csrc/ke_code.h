@@ -78,15 +78,22 @@ __host__ __device__ constexpr KeTable make_ke_table() {
 constexpr KeTable kKeTable = make_ke_table();
 static_assert(kKeTable.npairs == 10, "the H8 stiffness has 10 distinct entries up to sign");
 
-struct Kappa {
-  double k[10];
+template <typename T>
+struct KappaT {
+  T k[10];
 };
 
 __host__ __device__ constexpr double ke_sign(int I, int J) { return kKeTable.sign[I * 24 + J]; }
 __host__ __device__ constexpr int ke_idx(int I, int J) { return kKeTable.idx[I * 24 + J]; }
 
-// KE[I][J] for compile-time I, J
-#define TOPO_KE(kap, I, J) (::topo::ke_sign((I), (J)) * (kap).k[::topo::ke_idx((I), (J))])
+// KE[I][J] for compile-time I, J, in the precision of kappa (the sign becomes a
+// negation modifier on the register operand)
+template <typename T>
+__host__ __device__ __forceinline__ T ke_value(const KappaT<T> &k, int I, int J) {
+  const T v = k.k[ke_idx(I, J)];
+  return ke_sign(I, J) > 0 ? v : -v;
+}
+#define TOPO_KE(kap, I, J) (::topo::ke_value((kap), (I), (J)))
 
 inline Kappa make_kappa(double nu) {
   const double lam = nu / ((1.0 + nu) * (1.0 - 2.0 * nu));
@@ -94,6 +101,12 @@ inline Kappa make_kappa(double nu) {
   Kappa k{};
   for (int t = 0; t < 10; ++t) k.k[t] = (kKeTable.pairs[t].a * lam + kKeTable.pairs[t].b * mu) / 216.0;
   return k;
+}
+
+inline KappaT<float> to_float(const Kappa &k) {
+  KappaT<float> f{};
+  for (int t = 0; t < 10; ++t) f.k[t] = (float)k.k[t];
+  return f;
 }
 
 }  // namespace topo

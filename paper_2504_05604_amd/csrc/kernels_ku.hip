@@ -14,6 +14,10 @@
 // node value is loaded once per column instead of once per neighbour, and KE
 // comes from the compile-time sign/index tables with 10 register values.
 //
+// The epilogues fuse the vector updates of the conjugate-gradient loop and of
+// the Chebyshev smoother into the operator pass, and the first smoothing step
+// builds its operand d0 = b dinv / theta on the fly from the right-hand side.
+//
 // Fixed dofs: inputs are required to be zero there (the solver keeps every
 // vector in the subspace of free dofs); outputs get the identity row y = u.
 #include "internal.h"
@@ -22,26 +26,34 @@
 
 namespace topo {
 
-constexpr int kKuBlock = 256;
-constexpr int kKuKZ = 8;  // nodes per thread column
-
 template <int EPI>
-__global__ __launch_bounds__(kKuBlock) void ku_march_kernel(KuArgs a, Kappa kap, double *partials) {
+struct EpiTraits {
+  // operand built as b * dinv * s0 instead of read from u
+  static constexpr bool scaled_operand = EPI == KU_RES0 || EPI == KU_CHEB0;
+};
+
+// Launch shape: KZ nodes per thread column, BS threads per block.  Large grids
+// march KZ = 8 nodes (fewer plane reloads); small grids use short columns and
+// small blocks so the launch still spreads over the 256 CUs.
+template <int EPI, int KZ, int BS, typename T>
+__global__ __launch_bounds__(BS) void ku_march_kernel(KuArgsT<T> a, KappaT<T> kap, double *partials) {
   if (a.skip && *a.skip) return;
   const Grid g = a.g;
   const int NX = g.NX(), NY = g.NY(), NZ = g.NZ();
   const int ncol = NX * NY;
-  const int col = blockIdx.x * kKuBlock + threadIdx.x;
-  const int k0 = blockIdx.y * kKuKZ;
-  const int k1 = min(k0 + kKuKZ, NZ);
+  const int col = blockIdx.x * BS + threadIdx.x;
+  const int k0 = blockIdx.y * KZ;
+  const int k1 = min(k0 + KZ, NZ);
   const bool active = col < ncol;
   const int i = active ? col % NX : 0, j = active ? col / NX : 0;
   const int64_t plane = (int64_t)ncol;
-  const double *__restrict__ u = a.u;
+  constexpr bool kScaled = EpiTraits<EPI>::scaled_operand;
+  const T *__restrict__ u = kScaled ? a.b : a.u;
+  const T *__restrict__ dinv = a.dinv;
   double dotv = 0.0;
   if (active) {
-    double P0[9][3], P1[9][3];
-    auto load_plane = [&](int kp, double(&P)[9][3]) {
+    T P0[9][3], P1[9][3];
+    auto load_plane = [&](int kp, T(&P)[9][3]) {
       const bool okz = kp >= 0 && kp <= g.nz;
 #pragma unroll
       for (int dy = -1; dy <= 1; ++dy)
@@ -51,28 +63,32 @@ __global__ __launch_bounds__(kKuBlock) void ku_march_kernel(KuArgs a, Kappa kap,
           const bool ok = okz && (i + dx >= 0) && (i + dx <= g.nx) && (j + dy >= 0) && (j + dy <= g.ny);
           const int64_t m = (int64_t)kp * plane + (int64_t)(j + dy) * NX + (i + dx);
 #pragma unroll
-          for (int c = 0; c < 3; ++c) P[q][c] = ok ? u[3 * m + c] : 0.0;
+          for (int c = 0; c < 3; ++c) {
+            if constexpr (kScaled)
+              P[q][c] = ok ? u[3 * m + c] * dinv[3 * m + c] * a.s0 : T(0);
+            else
+              P[q][c] = ok ? u[3 * m + c] : T(0);
+          }
         }
     };
-    load_plane(k0 - 1, P0);
-    double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0;  // node (i,j,L): top-face part so far
-    for (int L = k0 - 1; L < k1; ++L) {
-      load_plane(L + 1, P1);
-      double nb0 = 0.0, nb1 = 0.0, nb2 = 0.0;  // node (i,j,L+1)
+    T acc0 = 0, acc1 = 0, acc2 = 0;  // node (i,j,L): top-face part so far
+    // element layer L between node planes L (Pb) and L+1 (Pt)
+    auto layer = [&](const int L, const T(&Pb)[9][3], const T(&Pt)[9][3]) {
+      T nb0 = 0, nb1 = 0, nb2 = 0;  // node (i,j,L+1)
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         const int ex = e & 1, ey = e >> 1;  // element (i-1+ex, j-1+ey, L)
         const int ei = i - 1 + ex, ej = j - 1 + ey;
         const bool eok = ei >= 0 && ei < g.nx && ej >= 0 && ej < g.ny && L >= 0 && L < g.nz;
-        const double Ee = eok ? a.E[ei + (int64_t)g.nx * (ej + (int64_t)g.ny * L)] : 0.0;
+        const T Ee = eok ? a.E[ei + (int64_t)g.nx * (ej + (int64_t)g.ny * L)] : T(0);
         const int lb = corner_of(1 - ex, 1 - ey, 0), lt = corner_of(1 - ex, 1 - ey, 1);
-        double b0 = 0.0, b1 = 0.0, b2 = 0.0, t0 = 0.0, t1 = 0.0, t2 = 0.0;
+        T b0 = 0, b1 = 0, b2 = 0, t0 = 0, t1 = 0, t2 = 0;
 #pragma unroll
         for (int b = 0; b < 8; ++b) {
           const int q = (ex + cx(b)) + 3 * (ey + cy(b));
 #pragma unroll
           for (int d = 0; d < 3; ++d) {
-            const double v = cz(b) ? P1[q][d] : P0[q][d];
+            const T v = cz(b) ? Pt[q][d] : Pb[q][d];
             b0 = fma(TOPO_KE(kap, 3 * lb + 0, 3 * b + d), v, b0);
             b1 = fma(TOPO_KE(kap, 3 * lb + 1, 3 * b + d), v, b1);
             b2 = fma(TOPO_KE(kap, 3 * lb + 2, 3 * b + d), v, b2);
@@ -91,40 +107,58 @@ __global__ __launch_bounds__(kKuBlock) void ku_march_kernel(KuArgs a, Kappa kap,
       if (L >= k0) {  // node (i,j,L) is complete
         const int64_t n = (int64_t)L * plane + col;
         const uint8_t fx = a.fixed[n];
-        const double self[3] = {P0[4][0], P0[4][1], P0[4][2]};
-        const double Au[3] = {acc0, acc1, acc2};
+        const T self[3] = {Pb[4][0], Pb[4][1], Pb[4][2]};
+        const T Au[3] = {acc0, acc1, acc2};
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
           const bool isf = (fx >> c) & 1;
           const int64_t dof = 3 * n + c;
+          const T Ac = isf ? T(0) : Au[c];  // reduced operator: no coupling into fixed rows
           if constexpr (EPI == KU_STORE) {
             a.y[dof] = isf ? self[c] : Au[c];
           } else if constexpr (EPI == KU_STORE_DOT) {
-            const double yv = isf ? self[c] : Au[c];
+            const T yv = isf ? self[c] : Au[c];
             a.y[dof] = yv;
-            dotv = fma(self[c], yv, dotv);
+            dotv = fma((double)self[c], (double)yv, dotv);
           } else if constexpr (EPI == KU_RESID) {
-            const double yv = isf ? 0.0 : a.b[dof] - Au[c];
+            const T yv = isf ? T(0) : a.b[dof] - Au[c];
             a.y[dof] = yv;
-            dotv = fma(yv, yv, dotv);
-          } else if constexpr (EPI == KU_CHEB) {
-            if (!isf) {
-              const double r = a.res[dof] - Au[c];
-              const double dn = a.c1 * self[c] + a.c2 * r / a.diag[dof];
-              a.res[dof] = r;
-              a.dout[dof] = dn;
-              a.x[dof] += dn;
-            } else {
-              a.dout[dof] = 0.0;
-            }
+            dotv = fma((double)yv, (double)yv, dotv);
+          } else if constexpr (EPI == KU_RES0) {  // x = d0, res = b - A d0
+            a.res[dof] = a.b[dof] - Ac;
+            a.x[dof] = self[c];
+          } else if constexpr (EPI == KU_CHEB0) {  // res = b - A d0; d1 = c1 d0 + c2 res dinv; x = d0 + d1
+            const T r = a.b[dof] - Ac;
+            const T dn = a.c1 * self[c] + a.c2 * r * dinv[dof];
+            a.res[dof] = r;
+            a.dout[dof] = dn;
+            a.x[dof] = self[c] + dn;
+          } else if constexpr (EPI == KU_CHEB || EPI == KU_CHEB_ADD) {
+            // dinv is 0 on fixed dofs, where res and the operand stay 0
+            const T r = a.res[dof] - Ac;
+            const T dn = a.c1 * self[c] + a.c2 * r * dinv[dof];
+            const T xn = a.x[dof] + dn + (EPI == KU_CHEB_ADD ? self[c] : 0.0);
+            a.res[dof] = r;
+            a.dout[dof] = dn;
+            a.x[dof] = xn;
+            if (a.dot_with) dotv = fma((double)a.dot_with[dof], (double)xn, dotv);
           } else if constexpr (EPI == KU_RESUPD) {
-            if (!isf) a.res[dof] -= Au[c];
+            a.res[dof] -= Ac;
+          } else if constexpr (EPI == KU_RESID_START) {  // res = b - A x; dout = res dinv s0
+            const T r = a.b[dof] - Ac;
+            a.res[dof] = r;
+            a.dout[dof] = r * dinv[dof] * a.s0;
           }
         }
       }
       acc0 = nb0;
       acc1 = nb1;
       acc2 = nb2;
+    };
+    load_plane(k0 - 1, P0);
+    for (int L = k0 - 1; L < k1; ++L) {
+      load_plane(L + 1, P1);
+      layer(L, P0, P1);
 #pragma unroll
       for (int q = 0; q < 9; ++q) {
         P0[q][0] = P1[q][0];
@@ -136,33 +170,94 @@ __global__ __launch_bounds__(kKuBlock) void ku_march_kernel(KuArgs a, Kappa kap,
   if constexpr (EPI == KU_STORE_DOT || EPI == KU_RESID) {
     double v[1] = {dotv};
     block_reduce_store<1, false>(v, partials, linear_block());
+  } else if constexpr (EPI == KU_CHEB || EPI == KU_CHEB_ADD) {
+    if (a.dot_with) {
+      double v[1] = {dotv};
+      block_reduce_store<1, false>(v, partials, linear_block());
+    }
   }
 }
 
-hipError_t launch_ku(hipStream_t s, KuEpi epi, const KuArgs &a, const Kappa &kap, const Reducer &red,
-                     double *out) {
+template <typename T>
+static bool ku_reduces(KuEpi epi, const KuArgsT<T> &a) {
+  return epi == KU_STORE_DOT || epi == KU_RESID ||
+         ((epi == KU_CHEB || epi == KU_CHEB_ADD) && a.dot_with != nullptr);
+}
+
+template <int KZ, int BS, typename T>
+static hipError_t launch_ku_shape(hipStream_t s, KuEpi epi, const KuArgsT<T> &a, const KappaT<T> &kap,
+                                  const Reducer &red, int *nparts_out) {
   const int ncol = a.g.NX() * a.g.NY();
-  const dim3 grid((unsigned)((ncol + kKuBlock - 1) / kKuBlock), (unsigned)((a.g.NZ() + kKuKZ - 1) / kKuKZ));
+  const dim3 grid((unsigned)((ncol + BS - 1) / BS), (unsigned)((a.g.NZ() + KZ - 1) / KZ));
   const int nparts = (int)(grid.x * grid.y);
-  if ((epi == KU_STORE_DOT || epi == KU_RESID) && nparts > red.max_blocks) return hipErrorInvalidValue;
+  *nparts_out = nparts;
+  if (ku_reduces(epi, a) && nparts > red.max_blocks) return hipErrorInvalidValue;
+#define TOPO_KU_CASE(E) \
+  case E: ku_march_kernel<E, KZ, BS, T><<<grid, BS, 0, s>>>(a, kap, red.partials); break;
   switch (epi) {
-    case KU_STORE: ku_march_kernel<KU_STORE><<<grid, kKuBlock, 0, s>>>(a, kap, red.partials); break;
-    case KU_STORE_DOT: ku_march_kernel<KU_STORE_DOT><<<grid, kKuBlock, 0, s>>>(a, kap, red.partials); break;
-    case KU_RESID: ku_march_kernel<KU_RESID><<<grid, kKuBlock, 0, s>>>(a, kap, red.partials); break;
-    case KU_CHEB: ku_march_kernel<KU_CHEB><<<grid, kKuBlock, 0, s>>>(a, kap, red.partials); break;
-    case KU_RESUPD: ku_march_kernel<KU_RESUPD><<<grid, kKuBlock, 0, s>>>(a, kap, red.partials); break;
+    TOPO_KU_CASE(KU_STORE)
+    TOPO_KU_CASE(KU_STORE_DOT)
+    TOPO_KU_CASE(KU_RESID)
+    TOPO_KU_CASE(KU_RES0)
+    TOPO_KU_CASE(KU_CHEB0)
+    TOPO_KU_CASE(KU_CHEB)
+    TOPO_KU_CASE(KU_CHEB_ADD)
+    TOPO_KU_CASE(KU_RESUPD)
+    TOPO_KU_CASE(KU_RESID_START)
+    default: return hipErrorInvalidValue;
   }
-  hipError_t e = hipGetLastError();
+#undef TOPO_KU_CASE
+  return hipGetLastError();
+}
+
+// Shapes measured on MI355X: 160x80x80 -> KZ 8 with 256 (smoother epilogues) or
+// 128 threads (CG product); 80x40x40 -> KZ 2 x 128; smaller grids -> KZ 1 x 64,
+// where a launch is bound by latency rather than arithmetic.
+int ku_shape_for(const Grid &g, KuEpi epi) {
+  const int64_t nn = g.nnodes();
+  if (nn >= 600000) return epi == KU_STORE_DOT ? 1 : 0;
+  if (nn >= 60000) return 2;
+  return 3;
+}
+
+template <typename T>
+static hipError_t launch_ku_t(hipStream_t s, KuEpi epi, const KuArgsT<T> &a, const KappaT<T> &kap,
+                              const Reducer &red, const Fin &fin, int shape) {
+  if (shape < 0) shape = ku_shape_for(a.g, epi);
+  int nparts = 0;
+  hipError_t e;
+  switch (shape) {
+    case 0: e = launch_ku_shape<8, 256>(s, epi, a, kap, red, &nparts); break;
+    case 1: e = launch_ku_shape<8, 128>(s, epi, a, kap, red, &nparts); break;
+    case 2: e = launch_ku_shape<2, 128>(s, epi, a, kap, red, &nparts); break;
+    case 3: e = launch_ku_shape<1, 64>(s, epi, a, kap, red, &nparts); break;
+    default: return hipErrorInvalidValue;
+  }
   if (e != hipSuccess) return e;
-  if (epi == KU_STORE_DOT || epi == KU_RESID) return launch_finalize(s, red, nparts, 1, false, out, a.skip);
+  if (ku_reduces(epi, a)) return launch_finalize(s, red, nparts, 1, fin, a.skip);
   return hipSuccess;
 }
 
+hipError_t launch_ku(hipStream_t s, KuEpi epi, const KuArgs &a, const Kappa &kap, const Reducer &red,
+                     const Fin &fin, int shape) {
+  return launch_ku_t<double>(s, epi, a, kap, red, fin, shape);
+}
+
+hipError_t launch_ku(hipStream_t s, KuEpi epi, const KuArgsT<float> &a, const KappaT<float> &kap,
+                     const Reducer &red, const Fin &fin, int shape) {
+  if (epi == KU_STORE_DOT || epi == KU_RESID || a.dot_with) return hipErrorInvalidValue;
+  return launch_ku_t<float>(s, epi, a, kap, red, fin, shape);
+}
+
 // ---------------------------------------------------------------------------
-__global__ void finalize_kernel(const double *partials, int nparts, int n, int is_max, double *out,
-                                const int *skip) {
+// Sums the block partials in block order.  Besides writing the sum, a finalize
+// can run the scalar step of the CG loop that consumes it:
+//   FIN_CG_CHECK  (out = rr): count the iteration and raise cg_done at convergence
+//   FIN_RZ        (out = rz_new): beta = rz_new / rz, then rz = rz_new
+__global__ void finalize_kernel(const double *partials, int nparts, int n, Fin fin, const int *skip) {
   if (skip && *skip) return;
   __shared__ double sh[kMaxRed][16];
+  const bool is_max = fin.mode == FIN_MAX;
   const int lane = threadIdx.x & 63, wid = threadIdx.x / 64, nw = blockDim.x / 64;
   for (int k = 0; k < n; ++k) {
     double t = is_max ? -INFINITY : 0.0;
@@ -178,14 +273,31 @@ __global__ void finalize_kernel(const double *partials, int nparts, int n, int i
     const int k = threadIdx.x;
     double t = sh[k][0];
     for (int w = 1; w < nw; ++w) t = is_max ? fmax(t, sh[k][w]) : t + sh[k][w];
-    out[k] = t;
+    fin.out[k] = t;
+    if (k == 0 && fin.mode == FIN_CG_CHECK) {
+      Scalars *sc = fin.sc;
+      sc->cg_iters += 1;
+      if (!(t > fin.rtol2 * sc->ff) || sc->cg_iters >= fin.max_iters) sc->cg_done = 1;
+    } else if (k == 0 && fin.mode == FIN_RZ) {
+      Scalars *sc = fin.sc;
+      sc->beta = t / sc->rz;
+      sc->rz = t;
+    }
+  }
+  __syncthreads();
+  if (fin.mode == FIN_RZ_FLEX && threadIdx.x == 0) {
+    // Polak-Ribiere: beta = r.(z_new - z_old) / rz_old, from the two sums above
+    Scalars *sc = fin.sc;
+    const double rzn = fin.out[0], rzo = fin.out[1];
+    sc->beta = (rzn - rzo) / sc->rz;
+    sc->rz = rzn;
   }
 }
 
-hipError_t launch_finalize(hipStream_t s, const Reducer &red, int nparts, int n, bool is_max,
-                           double *out, const int *skip) {
+hipError_t launch_finalize(hipStream_t s, const Reducer &red, int nparts, int n, const Fin &fin,
+                           const int *skip) {
   if (n > kMaxRed || nparts > red.max_blocks) return hipErrorInvalidValue;
-  finalize_kernel<<<1, 256, 0, s>>>(red.partials, nparts, n, is_max ? 1 : 0, out, skip);
+  finalize_kernel<<<1, 256, 0, s>>>(red.partials, nparts, n, fin, skip);
   return hipGetLastError();
 }
 
@@ -230,8 +342,8 @@ hipError_t launch_coarsen_moduli(hipStream_t s, Grid gf, Grid gc, const double *
   return hipGetLastError();
 }
 
-// diag_(i,c) = sum_{e around i} E_e KE[(3 li + c),(3 li + c)]; 1 on fixed dofs
-__global__ void diag_kernel(Grid g, const double *E, Kappa kap, const uint8_t *fixed, double *diag) {
+// inverse Jacobi diagonal: 1 / sum_{e around i} E_e KE[(3 li + c),(3 li + c)]; 0 on fixed dofs
+__global__ void diag_kernel(Grid g, const double *E, Kappa kap, const uint8_t *fixed, double *dinv) {
   const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (n >= g.nnodes()) return;
   const int i = (int)(n % g.NX());
@@ -250,15 +362,15 @@ __global__ void diag_kernel(Grid g, const double *E, Kappa kap, const uint8_t *f
     d2 += Ee * TOPO_KE(kap, 3 * li + 2, 3 * li + 2);
   }
   const uint8_t fx = fixed[n];
-  diag[3 * n + 0] = (fx & 1) ? 1.0 : d0;
-  diag[3 * n + 1] = (fx & 2) ? 1.0 : d1;
-  diag[3 * n + 2] = (fx & 4) ? 1.0 : d2;
+  dinv[3 * n + 0] = (fx & 1) ? 0.0 : 1.0 / d0;
+  dinv[3 * n + 1] = (fx & 2) ? 0.0 : 1.0 / d1;
+  dinv[3 * n + 2] = (fx & 4) ? 0.0 : 1.0 / d2;
 }
 
 hipError_t launch_diag(hipStream_t s, Grid g, const double *E, const Kappa &kap,
-                       const uint8_t *fixed, double *diag) {
+                       const uint8_t *fixed, double *dinv) {
   const int bs = 256;
-  diag_kernel<<<(unsigned)((g.nnodes() + bs - 1) / bs), bs, 0, s>>>(g, E, kap, fixed, diag);
+  diag_kernel<<<(unsigned)((g.nnodes() + bs - 1) / bs), bs, 0, s>>>(g, E, kap, fixed, dinv);
   return hipGetLastError();
 }
 

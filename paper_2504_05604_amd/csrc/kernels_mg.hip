@@ -14,8 +14,9 @@ inline unsigned nblocks(int64_t n) { return (unsigned)((n + kBs - 1) / kBs); }
 
 // r_c = P^T r_f: each coarse node gathers the fine nodes within one fine spacing
 // of its position 2*(I,J,K), weight prod over axes (1 at distance 0, 1/2 at 1).
-__global__ void restrict_kernel(Grid gf, Grid gc, const double *__restrict__ rf,
-                                const uint8_t *__restrict__ fixc, double *__restrict__ rc,
+template <typename T>
+__global__ void restrict_kernel(Grid gf, Grid gc, const T *__restrict__ rf,
+                                const uint8_t *__restrict__ fixc, T *__restrict__ rc,
                                 const int *skip) {
   if (skip && *skip) return;
   const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -23,7 +24,7 @@ __global__ void restrict_kernel(Grid gf, Grid gc, const double *__restrict__ rf,
   const int I = (int)(m % gc.NX());
   const int J = (int)((m / gc.NX()) % gc.NY());
   const int K = (int)(m / ((int64_t)gc.NX() * gc.NY()));
-  double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+  T s0 = 0, s1 = 0, s2 = 0;
 #pragma unroll
   for (int dz = -1; dz <= 1; ++dz) {
     const int k = 2 * K + dz;
@@ -36,7 +37,7 @@ __global__ void restrict_kernel(Grid gf, Grid gc, const double *__restrict__ rf,
       for (int dx = -1; dx <= 1; ++dx) {
         const int i = 2 * I + dx;
         if (i < 0 || i > gf.nx) continue;
-        const double w = (dx ? 0.5 : 1.0) * (dy ? 0.5 : 1.0) * (dz ? 0.5 : 1.0);
+        const T w = (T)(dx ? 0.5 : 1.0) * (dy ? 0.5 : 1.0) * (dz ? 0.5 : 1.0);
         const int64_t n = i + (int64_t)gf.NX() * (j + (int64_t)gf.NY() * k);
         s0 = fma(w, rf[3 * n + 0], s0);
         s1 = fma(w, rf[3 * n + 1], s1);
@@ -45,20 +46,26 @@ __global__ void restrict_kernel(Grid gf, Grid gc, const double *__restrict__ rf,
     }
   }
   const uint8_t f = fixc[m];
-  rc[3 * m + 0] = (f & 1) ? 0.0 : s0;
-  rc[3 * m + 1] = (f & 2) ? 0.0 : s1;
-  rc[3 * m + 2] = (f & 4) ? 0.0 : s2;
+  rc[3 * m + 0] = (f & 1) ? T(0) : s0;
+  rc[3 * m + 1] = (f & 2) ? T(0) : s1;
+  rc[3 * m + 2] = (f & 4) ? T(0) : s2;
 }
 
 hipError_t launch_restrict(hipStream_t s, Grid gf, Grid gc, const double *rf, const uint8_t *fixc,
                            double *rc, const int *skip) {
-  restrict_kernel<<<nblocks(gc.nnodes()), kBs, 0, s>>>(gf, gc, rf, fixc, rc, skip);
+  restrict_kernel<double><<<nblocks(gc.nnodes()), kBs, 0, s>>>(gf, gc, rf, fixc, rc, skip);
+  return hipGetLastError();
+}
+hipError_t launch_restrict(hipStream_t s, Grid gf, Grid gc, const float *rf, const uint8_t *fixc,
+                           float *rc, const int *skip) {
+  restrict_kernel<float><<<nblocks(gc.nnodes()), kBs, 0, s>>>(gf, gc, rf, fixc, rc, skip);
   return hipGetLastError();
 }
 
 // x_f += P e_c on free fine dofs (trilinear interpolation of the coarse values).
-__global__ void prolong_add_kernel(Grid gf, Grid gc, const double *__restrict__ ec,
-                                   const uint8_t *__restrict__ fixf, double *__restrict__ xf,
+template <typename T>
+__global__ void prolong_add_kernel(Grid gf, Grid gc, const T *__restrict__ ec,
+                                   const uint8_t *__restrict__ fixf, T *__restrict__ xf,
                                    const int *skip) {
   if (skip && *skip) return;
   const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -68,9 +75,9 @@ __global__ void prolong_add_kernel(Grid gf, Grid gc, const double *__restrict__ 
   const int k = (int)(n / ((int64_t)gf.NX() * gf.NY()));
   const int I0 = i >> 1, J0 = j >> 1, K0 = k >> 1;
   const int ni = (i & 1) ? 2 : 1, nj = (j & 1) ? 2 : 1, nk = (k & 1) ? 2 : 1;
-  const double wi = (i & 1) ? 0.5 : 1.0, wj = (j & 1) ? 0.5 : 1.0, wk = (k & 1) ? 0.5 : 1.0;
-  const double w = wi * wj * wk;
-  double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+  const T wi = (i & 1) ? T(0.5) : T(1), wj = (j & 1) ? T(0.5) : T(1), wk = (k & 1) ? T(0.5) : T(1);
+  const T w = wi * wj * wk;
+  T s0 = 0, s1 = 0, s2 = 0;
   for (int c = 0; c < nk; ++c)
     for (int b = 0; b < nj; ++b)
       for (int a = 0; a < ni; ++a) {
@@ -87,7 +94,12 @@ __global__ void prolong_add_kernel(Grid gf, Grid gc, const double *__restrict__ 
 
 hipError_t launch_prolong_add(hipStream_t s, Grid gf, Grid gc, const double *ec,
                               const uint8_t *fixf, double *xf, const int *skip) {
-  prolong_add_kernel<<<nblocks(gf.nnodes()), kBs, 0, s>>>(gf, gc, ec, fixf, xf, skip);
+  prolong_add_kernel<double><<<nblocks(gf.nnodes()), kBs, 0, s>>>(gf, gc, ec, fixf, xf, skip);
+  return hipGetLastError();
+}
+hipError_t launch_prolong_add(hipStream_t s, Grid gf, Grid gc, const float *ec,
+                              const uint8_t *fixf, float *xf, const int *skip) {
+  prolong_add_kernel<float><<<nblocks(gf.nnodes()), kBs, 0, s>>>(gf, gc, ec, fixf, xf, skip);
   return hipGetLastError();
 }
 
@@ -241,13 +253,14 @@ hipError_t launch_dense_invert(hipStream_t s, int n, double *A) {
 }
 
 // y = A x, one wave per row
-__global__ void dense_matvec_kernel(int n, const double *A, const double *x, double *y,
+template <typename T>
+__global__ void dense_matvec_kernel(int n, const T *A, const T *x, T *y,
                                     const int *skip) {
   if (skip && *skip) return;
   const int lane = threadIdx.x & 63;
   const int row = blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64;
   if (row >= n) return;
-  double t = 0.0;
+  T t = 0;
   for (int c = lane; c < n; c += 64) t = fma(A[(int64_t)row * n + c], x[c], t);
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) t += __shfl_down(t, off, 64);
@@ -257,7 +270,13 @@ __global__ void dense_matvec_kernel(int n, const double *A, const double *x, dou
 hipError_t launch_dense_matvec(hipStream_t s, int n, const double *A, const double *x, double *y,
                                const int *skip) {
   const int rows_per_block = kBs / 64;
-  dense_matvec_kernel<<<(unsigned)((n + rows_per_block - 1) / rows_per_block), kBs, 0, s>>>(n, A, x, y, skip);
+  dense_matvec_kernel<double><<<(unsigned)((n + rows_per_block - 1) / rows_per_block), kBs, 0, s>>>(n, A, x, y, skip);
+  return hipGetLastError();
+}
+hipError_t launch_dense_matvec(hipStream_t s, int n, const float *A, const float *x, float *y,
+                               const int *skip) {
+  const int rows_per_block = kBs / 64;
+  dense_matvec_kernel<float><<<(unsigned)((n + rows_per_block - 1) / rows_per_block), kBs, 0, s>>>(n, A, x, y, skip);
   return hipGetLastError();
 }
 

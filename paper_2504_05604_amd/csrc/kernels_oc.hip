@@ -176,7 +176,7 @@ hipError_t launch_oc_prepare(hipStream_t s, int64_t nel, const double *x, const 
   oc_prepare_kernel<<<nb, kBs, 0, s>>>(nel, x, dc, dv, mask, eta, a, red.partials);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  e = launch_finalize(s, red, (int)nb, 1, false, &sc->vconst);
+  e = launch_finalize(s, red, (int)nb, 1, fin_sum(&sc->vconst));
   if (e != hipSuccess) return e;
   oc_init_kernel<<<1, 1, 0, s>>>(sc, target);
   return hipGetLastError();
@@ -200,10 +200,10 @@ hipError_t launch_oc_final(hipStream_t s, int64_t nel, const double *x, const do
   oc_final_kernel<<<nb, kBs, 0, s>>>(nel, x, a, dv, mask, move, eta, xnew, sc, red.partials);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  e = launch_finalize(s, red, (int)nb, 1, true, &sc->change);
+  e = launch_finalize(s, red, (int)nb, 1, fin_max(&sc->change));
   if (e != hipSuccess) return e;
   Reducer r2{red.partials + 1, red.max_blocks};
-  return launch_finalize(s, r2, (int)nb, 1, false, &sc->volume);
+  return launch_finalize(s, r2, (int)nb, 1, fin_sum(&sc->volume));
 }
 
 }  // namespace topo

@@ -80,11 +80,11 @@ __global__ void dot_kernel(int64_t n, const double *a, const double *b, double *
 }
 
 hipError_t launch_dot(hipStream_t s, int64_t n, const double *a, const double *b, const Reducer &red,
-                      double *out, const int *skip) {
+                      const Fin &fin, const int *skip) {
   const unsigned nb = red_blocks(n, red);
   dot_kernel<<<nb, kBs, 0, s>>>(n, a, b, red.partials, skip);
   hipError_t e = hipGetLastError();
-  return e != hipSuccess ? e : launch_finalize(s, red, (int)nb, 1, false, out, skip);
+  return e != hipSuccess ? e : launch_finalize(s, red, (int)nb, 1, fin, skip);
 }
 
 __global__ void cg_update_xr_kernel(int64_t n, const Scalars *sc, double *x, double *r,
@@ -105,18 +105,12 @@ __global__ void cg_update_xr_kernel(int64_t n, const Scalars *sc, double *x, dou
 }
 
 hipError_t launch_cg_update_xr(hipStream_t s, int64_t n, Scalars *sc, double *x, double *r,
-                               const double *p, const double *q, const Reducer &red, const int *skip) {
+                               const double *p, const double *q, const Reducer &red, const Fin &fin,
+                               const int *skip) {
   const unsigned nb = red_blocks(n, red);
   cg_update_xr_kernel<<<nb, kBs, 0, s>>>(n, sc, x, r, p, q, red.partials, skip);
   hipError_t e = hipGetLastError();
-  return e != hipSuccess ? e : launch_finalize(s, red, (int)nb, 1, false, &sc->rr, skip);
-}
-
-// Convergence test on the device: done once rr <= rtol^2 ff or the cap is hit.
-__global__ void cg_check_kernel(Scalars *sc, double rtol2, int max_iters) {
-  if (sc->cg_done) return;
-  sc->cg_iters += 1;
-  if (!(sc->rr > rtol2 * sc->ff) || sc->cg_iters >= max_iters) sc->cg_done = 1;
+  return e != hipSuccess ? e : launch_finalize(s, red, (int)nb, 1, fin, skip);
 }
 
 __global__ void cg_start_kernel(Scalars *sc, double rtol2) {
@@ -124,23 +118,18 @@ __global__ void cg_start_kernel(Scalars *sc, double rtol2) {
   sc->cg_done = !(sc->rr > rtol2 * sc->ff);
 }
 
-hipError_t launch_cg_check(hipStream_t s, Scalars *sc, double rtol2, int max_iters) {
-  cg_check_kernel<<<1, 1, 0, s>>>(sc, rtol2, max_iters);
-  return hipGetLastError();
-}
-
 hipError_t launch_cg_start(hipStream_t s, Scalars *sc, double rtol2) {
   cg_start_kernel<<<1, 1, 0, s>>>(sc, rtol2);
   return hipGetLastError();
 }
 
-__global__ void jacobi_kernel(int64_t n, const double *r, const double *diag, double *z,
+__global__ void jacobi_kernel(int64_t n, const double *r, const double *dinv, double *z,
                               double *partials, const int *skip) {
   if (skipped(skip)) return;
   double t = 0.0;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x) {
-    const double zi = r[i] / diag[i];
+    const double zi = r[i] * dinv[i];
     z[i] = zi;
     t = fma(r[i], zi, t);
   }
@@ -148,68 +137,113 @@ __global__ void jacobi_kernel(int64_t n, const double *r, const double *diag, do
   block_reduce_store<1, false>(v, partials, blockIdx.x);
 }
 
-hipError_t launch_jacobi(hipStream_t s, int64_t n, const double *r, const double *diag, double *z,
-                         const Reducer &red, double *out, const int *skip) {
+hipError_t launch_jacobi(hipStream_t s, int64_t n, const double *r, const double *dinv, double *z,
+                         const Reducer &red, const Fin &fin, const int *skip) {
   const unsigned nb = red_blocks(n, red);
-  jacobi_kernel<<<nb, kBs, 0, s>>>(n, r, diag, z, red.partials, skip);
+  jacobi_kernel<<<nb, kBs, 0, s>>>(n, r, dinv, z, red.partials, skip);
   hipError_t e = hipGetLastError();
-  return e != hipSuccess ? e : launch_finalize(s, red, (int)nb, 1, false, out, skip);
+  return e != hipSuccess ? e : launch_finalize(s, red, (int)nb, 1, fin, skip);
 }
 
 __global__ void cg_update_p_kernel(int64_t n, const Scalars *sc, const double *z, double *p,
                                    int first, const int *skip) {
   if (skipped(skip)) return;
-  const double beta = first ? 0.0 : sc->rz_new / sc->rz;
+  const double beta = first ? 0.0 : sc->beta;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x)
     p[i] = first ? z[i] : fma(beta, p[i], z[i]);
 }
 
-// rz <- rz_new once every block has read the old rz (a separate tiny kernel)
-__global__ void cg_shift_rz_kernel(Scalars *sc, const int *skip) {
-  if (skipped(skip)) return;
-  sc->rz = sc->rz_new;
-}
-
 hipError_t launch_cg_update_p(hipStream_t s, int64_t n, Scalars *sc, const double *z, double *p,
                               int first, const int *skip) {
   cg_update_p_kernel<<<nblocks(n, 4), kBs, 0, s>>>(n, sc, z, p, first, skip);
-  cg_shift_rz_kernel<<<1, 1, 0, s>>>(sc, skip);
   return hipGetLastError();
 }
 
-__global__ void cheb_first_kernel(int64_t n, const double *r, const double *diag, double inv_theta,
-                                  double *d, double *x, double *res, const int *skip) {
+template <typename T>
+__global__ void cheb_first_kernel(int64_t n, const T *r, const T *dinv, T inv_theta, T *d, T *x,
+                                  T *res, const int *skip) {
   if (skipped(skip)) return;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  const double ri = r[i];
-  const double di = ri / diag[i] * inv_theta;
+  const T ri = r[i];
+  const T di = ri * dinv[i] * inv_theta;
   d[i] = di;
   x[i] = di;
   res[i] = ri;
 }
 
-hipError_t launch_cheb_first(hipStream_t s, int64_t n, const double *r, const double *diag,
+hipError_t launch_cheb_first(hipStream_t s, int64_t n, const double *r, const double *dinv,
                              double inv_theta, double *d, double *x, double *res, const int *skip) {
-  cheb_first_kernel<<<nblocks(n), kBs, 0, s>>>(n, r, diag, inv_theta, d, x, res, skip);
+  cheb_first_kernel<double><<<nblocks(n), kBs, 0, s>>>(n, r, dinv, inv_theta, d, x, res, skip);
+  return hipGetLastError();
+}
+hipError_t launch_cheb_first(hipStream_t s, int64_t n, const float *r, const float *dinv,
+                             float inv_theta, float *d, float *x, float *res, const int *skip) {
+  cheb_first_kernel<float><<<nblocks(n), kBs, 0, s>>>(n, r, dinv, inv_theta, d, x, res, skip);
   return hipGetLastError();
 }
 
-__global__ void cheb_start_kernel(int64_t n, const double *res, const double *diag,
-                                  double inv_theta, double *d, double *x, const int *skip) {
+template <typename T>
+__global__ void cheb_start_kernel(int64_t n, const T *res, const T *dinv, T inv_theta, T *d, T *x,
+                                  const int *skip) {
   if (skipped(skip)) return;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  const double di = res[i] / diag[i] * inv_theta;
+  const T di = res[i] * dinv[i] * inv_theta;
   d[i] = di;
   x[i] += di;
 }
 
-hipError_t launch_cheb_start(hipStream_t s, int64_t n, const double *res, const double *diag,
+hipError_t launch_cheb_start(hipStream_t s, int64_t n, const double *res, const double *dinv,
                              double inv_theta, double *d, double *x, const int *skip) {
-  cheb_start_kernel<<<nblocks(n), kBs, 0, s>>>(n, res, diag, inv_theta, d, x, skip);
+  cheb_start_kernel<double><<<nblocks(n), kBs, 0, s>>>(n, res, dinv, inv_theta, d, x, skip);
   return hipGetLastError();
+}
+hipError_t launch_cheb_start(hipStream_t s, int64_t n, const float *res, const float *dinv,
+                             float inv_theta, float *d, float *x, const int *skip) {
+  cheb_start_kernel<float><<<nblocks(n), kBs, 0, s>>>(n, res, dinv, inv_theta, d, x, skip);
+  return hipGetLastError();
+}
+
+// Precision conversions at the boundary of a single-precision preconditioner.
+template <typename S, typename D>
+__global__ void convert_kernel(int64_t n, const S *in, D *out, const int *skip) {
+  if (skipped(skip)) return;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = (D)in[i];
+}
+
+hipError_t launch_convert(hipStream_t s, int64_t n, const double *in, float *out, const int *skip) {
+  convert_kernel<double, float><<<nblocks(n), kBs, 0, s>>>(n, in, out, skip);
+  return hipGetLastError();
+}
+
+// z = (double) x32 together with r.z_new and r.z_old (z_old = the previous
+// content of z), for the flexible (Polak-Ribiere) CG update of a preconditioner
+// that is applied in single precision.
+__global__ void widen_dot_kernel(int64_t n, const float *x, const double *r, double *z,
+                                 double *partials, const int *skip) {
+  if (skipped(skip)) return;
+  double tn = 0.0, to = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const double zo = z[i];
+    const double zi = (double)x[i];
+    z[i] = zi;
+    tn = fma(r[i], zi, tn);
+    to = fma(r[i], zo, to);
+  }
+  double v[2] = {tn, to};
+  block_reduce_store<2, false>(v, partials, blockIdx.x);
+}
+
+hipError_t launch_widen_dot(hipStream_t s, int64_t n, const float *x, const double *r, double *z,
+                            const Reducer &red, const Fin &fin, const int *skip) {
+  const unsigned nb = red_blocks(n, red);
+  widen_dot_kernel<<<nb, kBs, 0, s>>>(n, x, r, z, red.partials, skip);
+  hipError_t e = hipGetLastError();
+  return e != hipSuccess ? e : launch_finalize(s, red, (int)nb, 2, fin, skip);
 }
 
 }  // namespace topo

@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstring>
 #include <memory>
+#include <type_traits>
 #include <vector>
 
 #include "internal.h"
@@ -118,14 +119,43 @@ static hipError_t dalloc(T **p, size_t count) {
 }
 
 constexpr double kChebRatio = 30.0;  // Chebyshev interval [lam_max / ratio, lam_max]
+constexpr int64_t kFuseFirstStepBelow = 400000;  // nodes: fuse the first smoothing step below
+
+// Multigrid level data in one precision.
+template <typename T>
+struct LevelBufs {
+  T *E = nullptr;     // moduli incl. the 2^level stiffness scale
+  T *dinv = nullptr;  // inverse Jacobi diagonal (0 on fixed dofs)
+  T *b = nullptr, *x = nullptr, *res = nullptr, *d0 = nullptr, *d1 = nullptr;
+};
 
 struct Level {
   Grid g{};
   double *E = nullptr;       // moduli incl. the 2^level stiffness scale
-  double *diag = nullptr;    // Jacobi diagonal (1 on fixed dofs)
+  double *dinv = nullptr;    // inverse Jacobi diagonal (0 on fixed dofs)
   uint8_t *fixed = nullptr;  // per node, bit c = dof c fixed
   double *b = nullptr, *x = nullptr, *res = nullptr, *d0 = nullptr, *d1 = nullptr;
+  LevelBufs<float> f32;      // single-precision copy for the mixed-precision preconditioner
 };
+
+template <typename T>
+LevelBufs<T> bufs(Level &L);
+template <>
+LevelBufs<double> bufs<double>(Level &L) {
+  LevelBufs<double> b;
+  b.E = L.E;
+  b.dinv = L.dinv;
+  b.b = L.b;
+  b.x = L.x;
+  b.res = L.res;
+  b.d0 = L.d0;
+  b.d1 = L.d1;
+  return b;
+}
+template <>
+LevelBufs<float> bufs<float>(Level &L) {
+  return L.f32;
+}
 
 }  // namespace topo
 
@@ -151,7 +181,10 @@ struct topo_ctx {
   // multigrid
   std::vector<Level> lv;
   double *Ainv = nullptr;
+  float *Ainv32 = nullptr;
   int ncoarse = 0;
+  bool mixed = false;        // single-precision preconditioner
+  KappaT<float> kap32{};
   // CG vectors (level-0 b / x double as the V-cycle's rhs / result)
   double *u = nullptr, *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr;
   // SIMP work
@@ -249,7 +282,7 @@ static topo_status validate(const topo_problem *P, const topo_opts *O) {
   if (!(O->rtol > 0.0) || O->max_iters < 1) return set_error("rtol > 0 and max_iters >= 1 required"), TOPO_EINVAL;
   if (!(O->oc_tol > 0.0)) return set_error("oc_tol must be > 0"), TOPO_EINVAL;
   if (O->mg_levels < 0 || O->mg_levels > 16) return set_error("mg_levels must lie in [0, 16]"), TOPO_EINVAL;
-  if (O->precision != TOPO_PREC_FP64) return set_error("only FP64 operators are available"), TOPO_EUNSUPPORTED;
+  if (O->precision == TOPO_PREC_BF16) return set_error("the BF16 preconditioner is not available"), TOPO_EUNSUPPORTED;
   return TOPO_OK;
 }
 
@@ -306,6 +339,8 @@ extern "C" topo_status topo_setup(const topo_problem *P, const topo_opts *O, voi
   // the kernels use the exact compile-time form of KE; check it against the
   // quadrature once (they agree to rounding for every nu)
   ctx->kap = make_kappa(P->nu);
+  ctx->kap32 = to_float(ctx->kap);
+  ctx->mixed = O->precision != TOPO_PREC_FP64;
   for (int I = 0; I < 576; ++I) {
     const double v = kKeTable.sign[I] * ctx->kap.k[kKeTable.idx[I]];
     if (std::fabs(v - KE[I]) > 1e-12 * (1.0 + std::fabs(KE[I])))
@@ -339,7 +374,7 @@ extern "C" topo_status topo_setup(const topo_problem *P, const topo_opts *O, voi
     Level &L = ctx->lv[l];
     L.g = dims[l];
     TOPO_ALLOC(L.E, L.g.nel());
-    TOPO_ALLOC(L.diag, L.g.ndof());
+    TOPO_ALLOC(L.dinv, L.g.ndof());
     TOPO_ALLOC(L.fixed, L.g.nnodes());
     TOPO_ALLOC(L.res, L.g.ndof());
     TOPO_ALLOC(L.d0, L.g.ndof());
@@ -347,6 +382,15 @@ extern "C" topo_status topo_setup(const topo_problem *P, const topo_opts *O, voi
     if (l > 0) {
       TOPO_ALLOC(L.b, L.g.ndof());
       TOPO_ALLOC(L.x, L.g.ndof());
+    }
+    if (O->precision != TOPO_PREC_FP64) {
+      TOPO_ALLOC(L.f32.E, L.g.nel());
+      TOPO_ALLOC(L.f32.dinv, L.g.ndof());
+      TOPO_ALLOC(L.f32.b, L.g.ndof());
+      TOPO_ALLOC(L.f32.x, L.g.ndof());
+      TOPO_ALLOC(L.f32.res, L.g.ndof());
+      TOPO_ALLOC(L.f32.d0, L.g.ndof());
+      TOPO_ALLOC(L.f32.d1, L.g.ndof());
     }
   }
   TOPO_HIP(hipMemcpyAsync(ctx->lv[0].fixed, hfix.data(), ctx->nnodes, hipMemcpyHostToDevice, s));
@@ -356,6 +400,7 @@ extern "C" topo_status topo_setup(const topo_problem *P, const topo_opts *O, voi
     ctx->ncoarse = (int)dims.back().ndof();
     if (ctx->ncoarse > 2048) return set_error("coarsest level has %d dofs (> 2048); allow more levels", ctx->ncoarse), TOPO_EINVAL;
     TOPO_ALLOC(ctx->Ainv, (size_t)ctx->ncoarse * ctx->ncoarse);
+    if (O->precision != TOPO_PREC_FP64) TOPO_ALLOC(ctx->Ainv32, (size_t)ctx->ncoarse * ctx->ncoarse);
   }
 
   // CG and SIMP vectors
@@ -372,6 +417,7 @@ extern "C" topo_status topo_setup(const topo_problem *P, const topo_opts *O, voi
   TOPO_ALLOC(ctx->oc_a, ctx->nel);
   TOPO_ALLOC(ctx->xnew, ctx->nel);
   TOPO_HIP(hipMemsetAsync(ctx->u, 0, ctx->ndof * sizeof(double), s));
+  TOPO_HIP(hipMemsetAsync(ctx->z, 0, ctx->ndof * sizeof(double), s));
   TOPO_HIP(hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
   ctx->lv[0].b = ctx->r;
   ctx->lv[0].x = ctx->z;
@@ -446,8 +492,31 @@ static KuArgs ku_args(topo_ctx *ctx, const Level &L, const double *u) {
   a.E = L.E;
   a.u = u;
   a.fixed = L.fixed;
-  a.diag = L.diag;
+  a.dinv = L.dinv;
   return a;
+}
+
+template <typename T>
+static KuArgsT<T> ku_args_t(Level &L, const T *u) {
+  const LevelBufs<T> B = bufs<T>(L);
+  KuArgsT<T> a{};
+  a.g = L.g;
+  a.E = B.E;
+  a.u = u;
+  a.fixed = L.fixed;
+  a.dinv = B.dinv;
+  return a;
+}
+
+template <typename T>
+static const KappaT<T> &kappa_of(const topo_ctx *ctx);
+template <>
+const KappaT<double> &kappa_of<double>(const topo_ctx *ctx) {
+  return ctx->kap;
+}
+template <>
+const KappaT<float> &kappa_of<float>(const topo_ctx *ctx) {
+  return ctx->kap32;
 }
 
 // level-0 modulus from xphys, then the coarse moduli, diagonals and coarse inverse
@@ -458,88 +527,191 @@ static topo_status prepare_operator(topo_ctx *ctx, const double *d_xphys) {
   for (size_t l = 0; l < ctx->lv.size(); ++l) {
     Level &L = ctx->lv[l];
     if (l > 0) TOPO_HIP(launch_coarsen_moduli(s, ctx->lv[l - 1].g, L.g, ctx->lv[l - 1].E, L.E));
-    TOPO_HIP(launch_diag(s, L.g, L.E, ctx->kap, L.fixed, L.diag));
+    TOPO_HIP(launch_diag(s, L.g, L.E, ctx->kap, L.fixed, L.dinv));
   }
   if (ctx->lv.size() > 1) {
     const Level &C = ctx->lv.back();
     TOPO_HIP(launch_dense_assemble(s, C.g, C.E, ctx->kap, C.fixed, ctx->Ainv));
     TOPO_HIP(launch_dense_invert(s, ctx->ncoarse, ctx->Ainv));
   }
+  if (ctx->mixed) {
+    for (Level &L : ctx->lv) {
+      TOPO_HIP(launch_convert(s, L.g.nel(), L.E, L.f32.E));
+      TOPO_HIP(launch_convert(s, L.g.ndof(), L.dinv, L.f32.dinv));
+    }
+    if (ctx->Ainv32)
+      TOPO_HIP(launch_convert(s, (int64_t)ctx->ncoarse * ctx->ncoarse, ctx->Ainv, ctx->Ainv32));
+  }
   return TOPO_OK;
 }
 
-// Chebyshev smoothing on level L for A x = b.  from_zero: x starts at 0 (pre-
-// smoothing); otherwise x holds the current iterate (post-smoothing).  On exit
-// L.res = b - A x when want_res.
-static topo_status cheb_smooth(topo_ctx *ctx, Level &L, bool from_zero, bool want_res, const int *skip) {
+// Chebyshev polynomial smoothing in D^-1 A on [lam_max / kChebRatio, lam_max].
+struct Cheb {
+  double theta, delta, sigma;
+  explicit Cheb(double lam_max) {
+    const double hi = lam_max, lo = hi / kChebRatio;
+    theta = 0.5 * (hi + lo);
+    delta = 0.5 * (hi - lo);
+    sigma = theta / delta;
+  }
+};
+
+// Pre-smoothing from x = 0 (cheb_degree steps); on exit x and res = b - A x.
+// On small grids the first step's operand d0 = b dinv / theta is formed inside
+// the operator pass.
+template <typename T>
+static topo_status pre_smooth(topo_ctx *ctx, Level &L, const int *skip) {
   hipStream_t s = ctx->stream;
   const int deg = ctx->opts.cheb_degree;
-  const double hi = ctx->lam_max, lo = hi / kChebRatio;
-  const double theta = 0.5 * (hi + lo), delta = 0.5 * (hi - lo), sigma = theta / delta;
-  double rho = 1.0 / sigma;
-  const int64_t n = L.g.ndof();
-  double *din = L.d0, *dout = L.d1;
-  if (from_zero) {
-    TOPO_HIP(launch_cheb_first(s, n, L.b, L.diag, 1.0 / theta, din, L.x, L.res, skip));
-  } else {
-    KuArgs a = ku_args(ctx, L, L.x);
-    a.y = L.res;
-    a.b = L.b;
-    a.skip = skip;
-    TOPO_HIP(launch_ku(s, KU_RESID, a, ctx->kap, ctx->red, &ctx->sc->red[0]));
-    TOPO_HIP(launch_cheb_start(s, n, L.res, L.diag, 1.0 / theta, din, L.x, skip));
+  const Cheb ch(ctx->lam_max);
+  const KappaT<T> &kap = kappa_of<T>(ctx);
+  const LevelBufs<T> B = bufs<T>(L);
+  double rho = 1.0 / ch.sigma;
+  T *dcur = B.d0, *dnext = B.d1;
+  KuArgsT<T> a = ku_args_t<T>(L, nullptr);
+  a.b = B.b;
+  a.res = B.res;
+  a.x = B.x;
+  a.s0 = (T)(1.0 / ch.theta);
+  a.skip = skip;
+  if (deg == 1) {
+    TOPO_HIP(launch_ku(s, KU_RES0, a, kap, ctx->red, fin_sum(nullptr)));
+    return TOPO_OK;
   }
-  for (int k = 1; k < deg; ++k) {
-    const double rho_new = 1.0 / (2.0 * sigma - rho);
-    KuArgs a = ku_args(ctx, L, din);
-    a.res = L.res;
-    a.x = L.x;
-    a.dout = dout;
-    a.c1 = rho_new * rho;
-    a.c2 = 2.0 * rho_new / delta;
-    a.skip = skip;
-    TOPO_HIP(launch_ku(s, KU_CHEB, a, ctx->kap, ctx->red, nullptr));
-    std::swap(din, dout);
+  double rho_new = 1.0 / (2.0 * ch.sigma - rho);
+  if (L.g.nnodes() >= kFuseFirstStepBelow) {
+    // large grids: the operator pass is arithmetic bound and forming the operand
+    // on the fly doubles its loads, so the first direction gets its own pass
+    TOPO_HIP(launch_cheb_first(s, L.g.ndof(), B.b, B.dinv, (T)(1.0 / ch.theta), dnext, B.x, B.res, skip));
+    KuArgsT<T> c = ku_args_t<T>(L, dnext);
+    c.res = B.res;
+    c.x = B.x;
+    c.dout = dcur;
+    c.c1 = (T)(rho_new * rho);
+    c.c2 = (T)(2.0 * rho_new / ch.delta);
+    c.skip = skip;
+    TOPO_HIP(launch_ku(s, KU_CHEB, c, kap, ctx->red, fin_sum(nullptr)));
+  } else {
+    a.dout = dcur;
+    a.c1 = (T)(rho_new * rho);
+    a.c2 = (T)(2.0 * rho_new / ch.delta);
+    TOPO_HIP(launch_ku(s, KU_CHEB0, a, kap, ctx->red, fin_sum(nullptr)));
+  }
+  rho = rho_new;
+  for (int k = 2; k < deg; ++k) {
+    rho_new = 1.0 / (2.0 * ch.sigma - rho);
+    KuArgsT<T> c = ku_args_t<T>(L, dcur);
+    c.res = B.res;
+    c.x = B.x;
+    c.dout = dnext;
+    c.c1 = (T)(rho_new * rho);
+    c.c2 = (T)(2.0 * rho_new / ch.delta);
+    c.skip = skip;
+    TOPO_HIP(launch_ku(s, KU_CHEB, c, kap, ctx->red, fin_sum(nullptr)));
+    std::swap(dcur, dnext);
     rho = rho_new;
   }
-  if (want_res) {
-    KuArgs a = ku_args(ctx, L, din);
-    a.res = L.res;
-    a.skip = skip;
-    TOPO_HIP(launch_ku(s, KU_RESUPD, a, ctx->kap, ctx->red, nullptr));
+  KuArgsT<T> r = ku_args_t<T>(L, dcur);
+  r.res = B.res;
+  r.skip = skip;
+  TOPO_HIP(launch_ku(s, KU_RESUPD, r, kap, ctx->red, fin_sum(nullptr)));
+  return TOPO_OK;
+}
+
+// Post-smoothing from the current x (cheb_degree steps).  With dot_with set,
+// the last pass also reduces dot_with . x into fin.
+template <typename T>
+static topo_status post_smooth(topo_ctx *ctx, Level &L, const int *skip, const T *dot_with,
+                               const Fin &fin) {
+  hipStream_t s = ctx->stream;
+  const int deg = ctx->opts.cheb_degree;
+  const Cheb ch(ctx->lam_max);
+  const KappaT<T> &kap = kappa_of<T>(ctx);
+  const LevelBufs<T> B = bufs<T>(L);
+  double rho = 1.0 / ch.sigma;
+  T *dcur = B.d0, *dnext = B.d1;
+  KuArgsT<T> a = ku_args_t<T>(L, B.x);
+  a.b = B.b;
+  a.res = B.res;
+  a.dout = dcur;
+  a.s0 = (T)(1.0 / ch.theta);
+  a.skip = skip;
+  TOPO_HIP(launch_ku(s, KU_RESID_START, a, kap, ctx->red, fin_sum(nullptr)));
+  if (deg == 1) {
+    TOPO_HIP(launch_cheb_start(s, L.g.ndof(), B.res, B.dinv, (T)(1.0 / ch.theta), dnext, B.x, skip));
+    if (dot_with) {
+      if constexpr (std::is_same<T, double>::value)
+        TOPO_HIP(launch_dot(s, L.g.ndof(), dot_with, B.x, ctx->red, fin, skip));
+    }
+    return TOPO_OK;
+  }
+  for (int k = 1; k < deg; ++k) {
+    const double rho_new = 1.0 / (2.0 * ch.sigma - rho);
+    KuArgsT<T> c = ku_args_t<T>(L, dcur);
+    c.res = B.res;
+    c.x = B.x;
+    c.dout = dnext;
+    c.c1 = (T)(rho_new * rho);
+    c.c2 = (T)(2.0 * rho_new / ch.delta);
+    c.dot_with = (k == deg - 1) ? dot_with : nullptr;
+    c.skip = skip;
+    TOPO_HIP(launch_ku(s, k == 1 ? KU_CHEB_ADD : KU_CHEB, c, kap, ctx->red, fin));
+    std::swap(dcur, dnext);
+    rho = rho_new;
   }
   return TOPO_OK;
 }
 
-// z = M r: V-cycle from level l with rhs lv[l].b into lv[l].x
-static topo_status vcycle(topo_ctx *ctx, size_t l, const int *skip) {
-  hipStream_t s = ctx->stream;
-  Level &L = ctx->lv[l];
-  if (l + 1 == ctx->lv.size()) {
-    TOPO_HIP(launch_dense_matvec(s, ctx->ncoarse, ctx->Ainv, L.b, L.x, skip));
-    return TOPO_OK;
-  }
-  topo_status st = cheb_smooth(ctx, L, true, true, skip);
-  if (st != TOPO_OK) return st;
-  Level &C = ctx->lv[l + 1];
-  TOPO_HIP(launch_restrict(s, L.g, C.g, L.res, C.fixed, C.b, skip));
-  st = vcycle(ctx, l + 1, skip);
-  if (st != TOPO_OK) return st;
-  TOPO_HIP(launch_prolong_add(s, L.g, C.g, C.x, L.fixed, L.x, skip));
-  return cheb_smooth(ctx, L, false, false, skip);
+template <typename T>
+static const T *coarse_inverse(const topo_ctx *ctx);
+template <>
+const double *coarse_inverse<double>(const topo_ctx *ctx) {
+  return ctx->Ainv;
+}
+template <>
+const float *coarse_inverse<float>(const topo_ctx *ctx) {
+  return ctx->Ainv32;
 }
 
-// z = M r and sc->rz_new = r.z
+// z = M r: V-cycle from level l with rhs b into x of that level; with dot_fin
+// set (level 0 in double precision) the last smoothing pass reduces r.z into it
+template <typename T>
+static topo_status vcycle(topo_ctx *ctx, size_t l, const int *skip, const Fin *dot_fin) {
+  hipStream_t s = ctx->stream;
+  Level &L = ctx->lv[l];
+  const LevelBufs<T> B = bufs<T>(L);
+  if (l + 1 == ctx->lv.size()) {
+    TOPO_HIP(launch_dense_matvec(s, ctx->ncoarse, coarse_inverse<T>(ctx), B.b, B.x, skip));
+    return TOPO_OK;
+  }
+  topo_status st = pre_smooth<T>(ctx, L, skip);
+  if (st != TOPO_OK) return st;
+  Level &C = ctx->lv[l + 1];
+  const LevelBufs<T> BC = bufs<T>(C);
+  TOPO_HIP(launch_restrict(s, L.g, C.g, B.res, C.fixed, BC.b, skip));
+  st = vcycle<T>(ctx, l + 1, skip, nullptr);
+  if (st != TOPO_OK) return st;
+  TOPO_HIP(launch_prolong_add(s, L.g, C.g, BC.x, L.fixed, B.x, skip));
+  return post_smooth<T>(ctx, L, skip, dot_fin ? B.b : nullptr, dot_fin ? *dot_fin : fin_sum(nullptr));
+}
+
+// z = M r; the r.z finalize sets rz_new, beta = rz_new / rz and rz = rz_new.
+// In mixed precision the whole V-cycle runs in single precision between a
+// narrowing of r and a widening of z (which also forms r.z in double).
 static topo_status precondition(topo_ctx *ctx, const int *skip) {
   hipStream_t s = ctx->stream;
   Level &L0 = ctx->lv[0];
+  const Fin fin{FIN_RZ, &ctx->sc->rz_new, ctx->sc, 0.0, 0};
   if (ctx->opts.precond == TOPO_PRECOND_JACOBI || ctx->lv.size() == 1) {
-    TOPO_HIP(launch_jacobi(s, ctx->ndof, ctx->r, L0.diag, ctx->z, ctx->red, &ctx->sc->rz_new, skip));
+    TOPO_HIP(launch_jacobi(s, ctx->ndof, ctx->r, L0.dinv, ctx->z, ctx->red, fin, skip));
     return TOPO_OK;
   }
-  topo_status st = vcycle(ctx, 0, skip);
+  if (!ctx->mixed) return vcycle<double>(ctx, 0, skip, &fin);
+  TOPO_HIP(launch_convert(s, ctx->ndof, ctx->r, L0.f32.b, skip));
+  topo_status st = vcycle<float>(ctx, 0, skip, nullptr);
   if (st != TOPO_OK) return st;
-  TOPO_HIP(launch_dot(s, ctx->ndof, ctx->r, ctx->z, ctx->red, &ctx->sc->rz_new, skip));
+  const Fin flex{FIN_RZ_FLEX, &ctx->sc->red[0], ctx->sc, 0.0, 0};
+  TOPO_HIP(launch_widen_dot(s, ctx->ndof, L0.f32.x, ctx->r, ctx->z, ctx->red, flex, skip));
   return TOPO_OK;
 }
 
@@ -559,9 +731,9 @@ static topo_status cg_body(topo_ctx *ctx) {
   KuArgs a = ku_args(ctx, L0, ctx->p);
   a.y = ctx->q;
   a.skip = skip;
-  TOPO_HIP(launch_ku(s, KU_STORE_DOT, a, ctx->kap, ctx->red, &ctx->sc->pq));
-  TOPO_HIP(launch_cg_update_xr(s, ctx->ndof, ctx->sc, ctx->u, ctx->r, ctx->p, ctx->q, ctx->red, skip));
-  TOPO_HIP(launch_cg_check(s, ctx->sc, ctx->opts.rtol * ctx->opts.rtol, ctx->opts.max_iters));
+  TOPO_HIP(launch_ku(s, KU_STORE_DOT, a, ctx->kap, ctx->red, fin_sum(&ctx->sc->pq)));
+  const Fin check{FIN_CG_CHECK, &ctx->sc->rr, ctx->sc, ctx->opts.rtol * ctx->opts.rtol, ctx->opts.max_iters};
+  TOPO_HIP(launch_cg_update_xr(s, ctx->ndof, ctx->sc, ctx->u, ctx->r, ctx->p, ctx->q, ctx->red, check, skip));
   topo_status st = precondition(ctx, skip);
   if (st != TOPO_OK) return st;
   TOPO_HIP(launch_cg_update_p(s, ctx->ndof, ctx->sc, ctx->z, ctx->p, 0, skip));
@@ -612,9 +784,9 @@ static topo_status pcg(topo_ctx *ctx, topo_solve_stats *stats) {
     KuArgs a = ku_args(ctx, L0, ctx->u);
     a.y = ctx->r;
     a.b = ctx->f;
-    TOPO_HIP(launch_ku(s, KU_RESID, a, ctx->kap, ctx->red, &ctx->sc->rr));
+    TOPO_HIP(launch_ku(s, KU_RESID, a, ctx->kap, ctx->red, fin_sum(&ctx->sc->rr)));
   }
-  TOPO_HIP(launch_dot(s, n, ctx->f, ctx->f, ctx->red, &ctx->sc->ff));
+  TOPO_HIP(launch_dot(s, n, ctx->f, ctx->f, ctx->red, fin_sum(&ctx->sc->ff)));
   const double rtol = ctx->opts.rtol;
   // iteration count 0; done at once if the initial guess already meets the tolerance
   TOPO_HIP(launch_cg_start(s, ctx->sc, rtol * rtol));
@@ -653,7 +825,7 @@ extern "C" topo_status topo_apply_K(topo_ctx *ctx, const double *d_xphys, const 
   TOPO_HIP(launch_copy_masked(s, ctx->nnodes, L0.fixed, d_u, ctx->tmp));
   KuArgs a = ku_args(ctx, L0, ctx->tmp);
   a.y = d_y;
-  TOPO_HIP(launch_ku(s, KU_STORE, a, ctx->kap, ctx->red, nullptr));
+  TOPO_HIP(launch_ku(s, KU_STORE, a, ctx->kap, ctx->red, fin_sum(nullptr)));
   // identity rows return the caller's u (not the zeroed copy) on fixed dofs
   TOPO_HIP(launch_copy_fixed(s, ctx->nnodes, L0.fixed, d_u, d_y));
   return TOPO_OK;
@@ -705,7 +877,7 @@ extern "C" topo_status topo_sensitivity(topo_ctx *ctx, const double *d_xphys, co
   const topo_problem &P = ctx->prob;
   TOPO_HIP(launch_sensitivity(s, ctx->g, ctx->kap, d_u, d_xphys, P.E0, P.Emin, P.penal, d_ce, d_dc));
   if (h_compliance) {
-    TOPO_HIP(launch_dot(s, ctx->ndof, ctx->f, d_u, ctx->red, &ctx->sc->comp));
+    TOPO_HIP(launch_dot(s, ctx->ndof, ctx->f, d_u, ctx->red, fin_sum(&ctx->sc->comp)));
     topo_status st = read_scalars(ctx);
     if (st != TOPO_OK) return st;
     *h_compliance = ctx->h_sc->comp;
@@ -782,7 +954,7 @@ extern "C" topo_status topo_iterate(topo_ctx *ctx, double *d_x, int32_t n_iter, 
     (void)hipEventRecord(ev[2], s);
     // sensitivities and compliance
     TOPO_HIP(launch_sensitivity(s, ctx->g, ctx->kap, ctx->u, ctx->xphys, P.E0, P.Emin, P.penal, ctx->ce, ctx->dc));
-    TOPO_HIP(launch_dot(s, ctx->ndof, ctx->f, ctx->u, ctx->red, &ctx->sc->comp));
+    TOPO_HIP(launch_dot(s, ctx->ndof, ctx->f, ctx->u, ctx->red, fin_sum(&ctx->sc->comp)));
     (void)hipEventRecord(ev[3], s);
     // filtered sensitivities and OC update
     if (P.filter == TOPO_FILTER_DENSITY)
@@ -830,9 +1002,9 @@ extern "C" topo_status topo_time_operator(topo_ctx *ctx, int32_t reps, double *h
   hipEvent_t e0, e1;
   TOPO_HIP(hipEventCreate(&e0));
   TOPO_HIP(hipEventCreate(&e1));
-  TOPO_HIP(launch_ku(s, KU_STORE_DOT, a, ctx->kap, ctx->red, &ctx->sc->red[0]));  // warm caches
+  TOPO_HIP(launch_ku(s, KU_STORE_DOT, a, ctx->kap, ctx->red, fin_sum(&ctx->sc->red[0])));  // warm caches
   TOPO_HIP(hipEventRecord(e0, s));
-  for (int i = 0; i < reps; ++i) TOPO_HIP(launch_ku(s, KU_STORE_DOT, a, ctx->kap, ctx->red, &ctx->sc->red[0]));
+  for (int i = 0; i < reps; ++i) TOPO_HIP(launch_ku(s, KU_STORE_DOT, a, ctx->kap, ctx->red, fin_sum(&ctx->sc->red[0])));
   TOPO_HIP(hipEventRecord(e1, s));
   TOPO_HIP(hipEventSynchronize(e1));
   float ms = 0.f;
