@@ -20,6 +20,8 @@
 //
 // Fixed dofs: inputs are required to be zero there (the solver keeps every
 // vector in the subspace of free dofs); outputs get the identity row y = u.
+#include <type_traits>
+
 #include "internal.h"
 #include "ke_code.h"
 #include "reduce_dev.h"
@@ -75,34 +77,59 @@ __global__ __launch_bounds__(BS) void ku_march_kernel(KuArgsT<T> a, KappaT<T> ka
     // element layer L between node planes L (Pb) and L+1 (Pt)
     auto layer = [&](const int L, const T(&Pb)[9][3], const T(&Pt)[9][3]) {
       T nb0 = 0, nb1 = 0, nb2 = 0;  // node (i,j,L+1)
+      // bottom-face rows finish node L, top-face rows start node L+1; the first
+      // and last layer of a column need only one of the two (uniform per block)
+      auto faces = [&](auto bot_tag, auto top_tag) {
+        constexpr bool kBot = decltype(bot_tag)::value, kTop = decltype(top_tag)::value;
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int ex = e & 1, ey = e >> 1;  // element (i-1+ex, j-1+ey, L)
-        const int ei = i - 1 + ex, ej = j - 1 + ey;
-        const bool eok = ei >= 0 && ei < g.nx && ej >= 0 && ej < g.ny && L >= 0 && L < g.nz;
-        const T Ee = eok ? a.E[ei + (int64_t)g.nx * (ej + (int64_t)g.ny * L)] : T(0);
-        const int lb = corner_of(1 - ex, 1 - ey, 0), lt = corner_of(1 - ex, 1 - ey, 1);
-        T b0 = 0, b1 = 0, b2 = 0, t0 = 0, t1 = 0, t2 = 0;
+        for (int e = 0; e < 4; ++e) {
+          const int ex = e & 1, ey = e >> 1;  // element (i-1+ex, j-1+ey, L)
+          const int ei = i - 1 + ex, ej = j - 1 + ey;
+          const bool eok = ei >= 0 && ei < g.nx && ej >= 0 && ej < g.ny && L >= 0 && L < g.nz;
+          const T Ee = eok ? a.E[ei + (int64_t)g.nx * (ej + (int64_t)g.ny * L)] : T(0);
+          const int lb = corner_of(1 - ex, 1 - ey, 0), lt = corner_of(1 - ex, 1 - ey, 1);
+          T b0 = 0, b1 = 0, b2 = 0, t0 = 0, t1 = 0, t2 = 0;
 #pragma unroll
-        for (int b = 0; b < 8; ++b) {
-          const int q = (ex + cx(b)) + 3 * (ey + cy(b));
+          for (int b = 0; b < 8; ++b) {
+            const int q = (ex + cx(b)) + 3 * (ey + cy(b));
 #pragma unroll
-          for (int d = 0; d < 3; ++d) {
-            const T v = cz(b) ? Pt[q][d] : Pb[q][d];
-            b0 = fma(TOPO_KE(kap, 3 * lb + 0, 3 * b + d), v, b0);
-            b1 = fma(TOPO_KE(kap, 3 * lb + 1, 3 * b + d), v, b1);
-            b2 = fma(TOPO_KE(kap, 3 * lb + 2, 3 * b + d), v, b2);
-            t0 = fma(TOPO_KE(kap, 3 * lt + 0, 3 * b + d), v, t0);
-            t1 = fma(TOPO_KE(kap, 3 * lt + 1, 3 * b + d), v, t1);
-            t2 = fma(TOPO_KE(kap, 3 * lt + 2, 3 * b + d), v, t2);
+            for (int d = 0; d < 3; ++d) {
+              const T v = cz(b) ? Pt[q][d] : Pb[q][d];
+              if constexpr (kBot) {
+                b0 = fma(TOPO_KE(kap, 3 * lb + 0, 3 * b + d), v, b0);
+                b1 = fma(TOPO_KE(kap, 3 * lb + 1, 3 * b + d), v, b1);
+                b2 = fma(TOPO_KE(kap, 3 * lb + 2, 3 * b + d), v, b2);
+              }
+              if constexpr (kTop) {
+                t0 = fma(TOPO_KE(kap, 3 * lt + 0, 3 * b + d), v, t0);
+                t1 = fma(TOPO_KE(kap, 3 * lt + 1, 3 * b + d), v, t1);
+                t2 = fma(TOPO_KE(kap, 3 * lt + 2, 3 * b + d), v, t2);
+              }
+            }
+          }
+          if constexpr (kBot) {
+            acc0 = fma(Ee, b0, acc0);
+            acc1 = fma(Ee, b1, acc1);
+            acc2 = fma(Ee, b2, acc2);
+          }
+          if constexpr (kTop) {
+            nb0 = fma(Ee, t0, nb0);
+            nb1 = fma(Ee, t1, nb1);
+            nb2 = fma(Ee, t2, nb2);
           }
         }
-        acc0 = fma(Ee, b0, acc0);
-        acc1 = fma(Ee, b1, acc1);
-        acc2 = fma(Ee, b2, acc2);
-        nb0 = fma(Ee, t0, nb0);
-        nb1 = fma(Ee, t1, nb1);
-        nb2 = fma(Ee, t2, nb2);
+      };
+      if constexpr (KZ > 2) {
+        // long columns: one shared code path keeps the register count down; the
+        // unneeded half of the first/last layer is 1/KZ of the work
+        faces(std::true_type{}, std::true_type{});
+      } else {
+        if (L >= k0 && L + 1 < k1)
+          faces(std::true_type{}, std::true_type{});
+        else if (L >= k0)
+          faces(std::true_type{}, std::false_type{});
+        else
+          faces(std::false_type{}, std::true_type{});
       }
       if (L >= k0) {  // node (i,j,L) is complete
         const int64_t n = (int64_t)L * plane + col;
