@@ -68,8 +68,10 @@ enum {
  * vectors, inner products and stopping test stay FP64, so the solution meets
  * the same FP64 residual tolerance.  BF16: reserved (TOPO_EUNSUPPORTED). */
 enum { TOPO_PREC_FP64 = 0, TOPO_PREC_FP32 = 1, TOPO_PREC_BF16 = 2 };
-/* preconditioner of the conjugate-gradient solve */
-enum { TOPO_PRECOND_JACOBI = 0, TOPO_PRECOND_MG = 1 };
+/* preconditioner of the conjugate-gradient solve.  LEARNED: the convolutional
+ * network attached with topo_set_nn (see below), used inside flexible CG with a
+ * restart on the multigrid preconditioner when the safeguard fails. */
+enum { TOPO_PRECOND_JACOBI = 0, TOPO_PRECOND_MG = 1, TOPO_PRECOND_LEARNED = 2 };
 
 /* Problem definition; all arrays are host arrays copied by topo_setup. */
 typedef struct {
@@ -102,13 +104,17 @@ typedef struct {
   int32_t check_every;        /* CG iterations per host convergence check (the device
                                  stops iterating at convergence within a chunk)         */
   int32_t use_graphs;         /* replay chunks of CG iterations from a captured HIP graph */
+  int32_t nn_max_iters;       /* LEARNED: flexible-CG iterations before the solve restarts
+                                 on the multigrid preconditioner                       */
 } topo_opts;
 
 typedef struct {
-  int32_t iters;       /* CG iterations taken                        */
+  int32_t iters;       /* CG iterations taken (all phases)           */
   int32_t converged;   /* 1 if relres <= rtol                        */
   double relres;       /* ||f - K u|| / ||f|| (recursive residual)   */
   double ms;           /* wall time of the solve on the stream       */
+  int32_t fallbacks;   /* LEARNED: restarts on the multigrid preconditioner */
+  int32_t learned_iters; /* LEARNED: iterations taken with the network  */
 } topo_solve_stats;
 
 typedef struct {
@@ -124,7 +130,7 @@ typedef struct {
 
 /* Fills *opts with defaults: FP64, MG, automatic depth (coarsest <= 140 dofs),
  * Chebyshev degree 2, rtol 1e-8, max_iters 1000, warm start, oc_tol 1e-12,
- * check_every 4, use_graphs 1. */
+ * check_every 4, use_graphs 1, nn_max_iters 200. */
 void topo_default_opts(topo_opts *opts);
 
 /* Validates the problem, copies its arrays to the device, builds the element
@@ -209,6 +215,86 @@ topo_status topo_time_operator(topo_ctx *ctx, int32_t reps, double *h_ms_per_lau
 /* Copies the context's current displacement (ndof) to d_u / physical density
  * (nel) to d_xphys; either may be NULL. */
 topo_status topo_get_state(topo_ctx *ctx, double *d_u, double *d_xphys);
+
+/* ------------------------------------------------------------------------
+ * Learned preconditioner.  A three-level convolutional encoder-decoder on the
+ * node grid maps the node density (mean of the adjacent elements' physical
+ * densities) and the residual scaled by its root-mean-square to a correction
+ * z ~ K^{-1} r, rescaled and zeroed on fixed dofs.  Layers (3x3x3 zero-padded
+ * cross-correlations, ReLU after each but the up layers and the head):
+ *   enc0a 4->c0, enc0b c0->c0 (= s0), down1 c0->c1 stride 2, enc1b c1->c1 (= s1),
+ *   down2 c1->c2 stride 2, enc2b c2->c2, up1 = transpose of a stride-2
+ *   convolution c2->c1 (+bias), dec1 on [up1, s1] 2c1->c1, up0 c1->c0 (+bias),
+ *   dec0 on [up0, s0] 2c0->c0, head 1x1x1 c0->3.
+ * Coarse grids have ceil(n/2) nodes per axis.  Parameters are one FP32 blob:
+ * per layer its weight [c_out][c_in][taps] (taps z-major, then y, then x) and
+ * its bias, in the order above; an up layer stores the weight of the stride-2
+ * convolution it transposes, [c_coarse][c_fine][27], and a c_fine bias.  With
+ * (16, 32, 64) channels there are 354611 parameters.  Network arithmetic is
+ * FP32 with FP32 accumulation.
+ *
+ * Network activations are channel-major over a batch: [C][batch][V] with
+ * V = NX*NY*NZ nodes, x fastest (node numbering above).  nodes[3] = (NX, NY, NZ).
+ * Training samples are stored per sample: rho [n][V] (node density), r and
+ * e [n][3V] (dof order), fixed [n][V] (bit c set when dof c of the node is
+ * fixed).  The loss of a sample is ||(y - e/s) m||^2 / ||(e/s) m||^2 with
+ * y = net(rho, r/s), s = rms(r) and m the free dofs; a batch's loss is the mean.
+ */
+typedef struct topo_nn topo_nn;
+
+typedef struct {
+  int32_t epochs;          /* passes over the samples (a fresh shuffle each)      */
+  int32_t batch;           /* samples per Adam step, 1..64                         */
+  double lr, beta1, beta2, eps; /* Adam (Kingma and Ba 2015) with bias correction */
+  uint64_t seed;           /* shuffle seed                                         */
+} topo_train_opts;
+
+typedef struct {
+  int32_t steps;           /* Adam steps taken                                     */
+  double loss_first;       /* mean sample loss over the first epoch                */
+  double loss_last;        /* ... over the last epoch                              */
+  double ms;               /* wall time on the stream                              */
+} topo_train_stats;
+
+/* Creates a network with channels (c0, c1, c2) (NULL = 16, 32, 64) and zero
+ * weights; hip_stream as in topo_setup.  Errors: TOPO_EINVAL, TOPO_ENOMEM. */
+topo_status topo_nn_create(const int32_t channels[3], void *hip_stream, topo_nn **out);
+void topo_nn_destroy(topo_nn *nn);
+topo_status topo_nn_n_params(const topo_nn *nn, int64_t *n);
+/* Copies n = n_params FP32 parameters from the host (layout above) and resets
+ * the Adam moments.  Synchronises. */
+topo_status topo_nn_set_weights(topo_nn *nn, const float *h_blob, int64_t n);
+topo_status topo_nn_get_weights(const topo_nn *nn, float *h_blob, int64_t n);
+/* d_out[3][batch][V] = net(d_in[4][batch][V]) (raw network, no scaling). */
+topo_status topo_nn_forward(topo_nn *nn, const int32_t nodes[3], int32_t batch, const float *d_in,
+                            float *d_out);
+/* Mean loss of the samples h_index[0..batch) (host indices into n_samples) and
+ * its gradient with respect to the parameters (d_grad, n_params; may be NULL).
+ * *h_loss may be NULL.  Synchronises. */
+topo_status topo_nn_loss_grad(topo_nn *nn, const int32_t nodes[3], int64_t n_samples, const float *d_rho,
+                              const float *d_r, const float *d_e, const uint8_t *d_fixed, int32_t batch,
+                              const int32_t *h_index, double *h_loss, float *d_grad);
+/* Fills *opts: 10 epochs, batch 4, lr 1e-3, betas 0.9 / 0.999, eps 1e-8, seed 0. */
+void topo_default_train_opts(topo_train_opts *opts);
+/* Adam training over the stored samples; the last partial batch of an epoch is
+ * dropped.  h_epoch_loss (epochs entries) and h_stats may be NULL.  Synchronises. */
+topo_status topo_nn_train(topo_nn *nn, const int32_t nodes[3], int64_t n_samples, const float *d_rho,
+                          const float *d_r, const float *d_e, const uint8_t *d_fixed,
+                          const topo_train_opts *opts, double *h_epoch_loss, topo_train_stats *h_stats);
+
+/* Attaches nn (NULL detaches) as the network of TOPO_PRECOND_LEARNED for ctx.
+ * The context keeps its own activation buffers; nn must outlive the attachment,
+ * and later topo_nn_set_weights / topo_nn_train calls take effect at once. */
+topo_status topo_set_nn(topo_ctx *ctx, topo_nn *nn);
+
+/* Training pairs from the conjugate-gradient iterates of one density field:
+ * solves K(E(d_xphys)) u* = f to min(rtol, 1e-10) with the multigrid
+ * preconditioner, then for each i restarts from u = 0, takes h_iters[i] >= 0
+ * iterations and stores r_i = f - K u_i and e_i = u* - u_i (= K^{-1} r_i).
+ * Writes d_rho[i][V] (node density), d_r[i][3V], d_e[i][3V] (FP32) and
+ * d_fixed[i][V] for i < n.  Synchronises. */
+topo_status topo_nn_make_pairs(topo_ctx *ctx, const double *d_xphys, int32_t n, const int32_t *h_iters,
+                               float *d_rho, float *d_r, float *d_e, uint8_t *d_fixed);
 
 #ifdef __cplusplus
 }

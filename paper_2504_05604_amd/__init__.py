@@ -6,9 +6,11 @@ the C ABI in ``include/topo.h``); this package is its thin Python binding.
 
 from ._lib import (  # noqa: F401
     Context,
+    Network,
     NotConverged,
     TopoError,
     default_opts,
+    default_train_opts,
     load,
     EXPORTED,
     LIB_PATH,
@@ -23,4 +25,5 @@ from ._lib import (  # noqa: F401
     PREC_BF16,
     PRECOND_JACOBI,
     PRECOND_MG,
+    PRECOND_LEARNED,
 )

@@ -20,13 +20,17 @@ TOPO_OK, TOPO_EINVAL, TOPO_ENOMEM, TOPO_EDEVICE, TOPO_ENOTCONVERGED, TOPO_EUNSUP
 FILTER_DENSITY, FILTER_SENSITIVITY = 0, 1
 FILTER_FWD, FILTER_ADJ, FILTER_SENS, FILTER_VOLW = 0, 1, 2, 3
 PREC_FP64, PREC_FP32, PREC_BF16 = 0, 1, 2
-PRECOND_JACOBI, PRECOND_MG = 0, 1
+PRECOND_JACOBI, PRECOND_MG, PRECOND_LEARNED = 0, 1, 2
 
 EXPORTED = [
     "topo_default_opts", "topo_setup", "topo_destroy", "topo_last_error", "topo_sizes",
     "topo_apply_K", "topo_apply_precond", "topo_solve", "topo_sensitivity", "topo_filter", "topo_oc_update",
     "topo_iterate", "topo_get_state", "topo_time_operator",
+    "topo_nn_create", "topo_nn_destroy", "topo_nn_n_params", "topo_nn_set_weights", "topo_nn_get_weights",
+    "topo_nn_forward", "topo_nn_loss_grad", "topo_default_train_opts", "topo_nn_train", "topo_set_nn",
+    "topo_nn_make_pairs",
 ]
+_VOID = ("topo_default_opts", "topo_destroy", "topo_last_error", "topo_nn_destroy", "topo_default_train_opts")
 
 
 class TopoError(RuntimeError):
@@ -56,12 +60,22 @@ class Opts_C(C.Structure):
         ("precision", C.c_int32), ("precond", C.c_int32), ("mg_levels", C.c_int32),
         ("mg_max_coarse_dof", C.c_int32), ("cheb_degree", C.c_int32), ("rtol", C.c_double),
         ("max_iters", C.c_int32), ("warm_start", C.c_int32), ("oc_tol", C.c_double),
-        ("check_every", C.c_int32), ("use_graphs", C.c_int32),
+        ("check_every", C.c_int32), ("use_graphs", C.c_int32), ("nn_max_iters", C.c_int32),
     ]
 
 
 class SolveStats_C(C.Structure):
     _fields_ = [("iters", C.c_int32), ("converged", C.c_int32), ("relres", C.c_double),
+                ("ms", C.c_double), ("fallbacks", C.c_int32), ("learned_iters", C.c_int32)]
+
+
+class TrainOpts_C(C.Structure):
+    _fields_ = [("epochs", C.c_int32), ("batch", C.c_int32), ("lr", C.c_double), ("beta1", C.c_double),
+                ("beta2", C.c_double), ("eps", C.c_double), ("seed", C.c_uint64)]
+
+
+class TrainStats_C(C.Structure):
+    _fields_ = [("steps", C.c_int32), ("loss_first", C.c_double), ("loss_last", C.c_double),
                 ("ms", C.c_double)]
 
 
@@ -106,8 +120,24 @@ def load(path: str = LIB_PATH):
     lib.topo_iterate.argtypes = [vp, dp, C.c_int32, C.POINTER(IterStats_C)]
     lib.topo_get_state.argtypes = [vp, dp, dp]
     lib.topo_time_operator.argtypes = [vp, C.c_int32, C.POINTER(C.c_double)]
+    i32p, fp = C.POINTER(C.c_int32), C.c_void_p
+    lib.topo_nn_create.argtypes = [i32p, vp, C.POINTER(vp)]
+    lib.topo_nn_destroy.argtypes = [vp]
+    lib.topo_nn_destroy.restype = None
+    lib.topo_nn_n_params.argtypes = [vp, C.POINTER(C.c_int64)]
+    lib.topo_nn_set_weights.argtypes = [vp, C.POINTER(C.c_float), C.c_int64]
+    lib.topo_nn_get_weights.argtypes = [vp, C.POINTER(C.c_float), C.c_int64]
+    lib.topo_nn_forward.argtypes = [vp, i32p, C.c_int32, fp, fp]
+    lib.topo_nn_loss_grad.argtypes = [vp, i32p, C.c_int64, fp, fp, fp, fp, C.c_int32, i32p,
+                                      C.POINTER(C.c_double), fp]
+    lib.topo_default_train_opts.argtypes = [C.POINTER(TrainOpts_C)]
+    lib.topo_default_train_opts.restype = None
+    lib.topo_nn_train.argtypes = [vp, i32p, C.c_int64, fp, fp, fp, fp, C.POINTER(TrainOpts_C),
+                                  C.POINTER(C.c_double), C.POINTER(TrainStats_C)]
+    lib.topo_set_nn.argtypes = [vp, vp]
+    lib.topo_nn_make_pairs.argtypes = [vp, dp, C.c_int32, i32p, fp, fp, fp, fp]
     for name in EXPORTED:
-        if name not in ("topo_default_opts", "topo_destroy", "topo_last_error"):
+        if name not in _VOID:
             getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
@@ -221,7 +251,8 @@ class Context:
         st = SolveStats_C()
         status = self._lib.topo_solve(self._h, _ptr(xphys, self.nel, torch.float64),
                                       _ptr(u, self.ndof, torch.float64), C.byref(st))
-        out = {"iters": st.iters, "converged": bool(st.converged), "relres": st.relres, "ms": st.ms}
+        out = {"iters": st.iters, "converged": bool(st.converged), "relres": st.relres, "ms": st.ms,
+               "fallbacks": st.fallbacks, "learned_iters": st.learned_iters}
         if status == TOPO_ENOTCONVERGED and not raise_on_nonconv:
             return out
         _check(status)
@@ -274,3 +305,107 @@ class Context:
         import torch
         _check(self._lib.topo_get_state(self._h, _ptr(u, self.ndof, torch.float64),
                                         _ptr(xphys, self.nel, torch.float64)))
+
+    def set_nn(self, nn: Optional["Network"]):
+        """Attaches a Network as the learned preconditioner (None detaches)."""
+        _check(self._lib.topo_set_nn(self._h, None if nn is None else nn._h))
+        self._nn = nn  # keep it alive while attached
+
+    def make_pairs(self, xphys, iters, rho, r, e, fixed):
+        """Training pairs (r_k, u* - u_k) from CG iterates k in `iters`."""
+        import torch
+        it = np.ascontiguousarray(iters, dtype=np.int32)
+        n = it.size
+        V = self.ndof // 3
+        _check(self._lib.topo_nn_make_pairs(
+            self._h, _ptr(xphys, self.nel, torch.float64), n, it.ctypes.data_as(C.POINTER(C.c_int32)),
+            _ptr(rho, n * V, torch.float32), _ptr(r, n * 3 * V, torch.float32),
+            _ptr(e, n * 3 * V, torch.float32), _ptr(fixed, n * V, torch.uint8)))
+
+
+def default_train_opts(**kw) -> TrainOpts_C:
+    lib = load()
+    o = TrainOpts_C()
+    lib.topo_default_train_opts(C.byref(o))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise KeyError(f"unknown training option {k}")
+        setattr(o, k, v)
+    return o
+
+
+class Network:
+    """The convolutional preconditioner network; wraps a topo_nn."""
+
+    def __init__(self, channels=(16, 32, 64), stream=None):
+        lib = load()
+        self._lib = lib
+        import torch
+        torch.cuda.init()
+        ch = (C.c_int32 * 3)(*channels)
+        h = C.c_void_p()
+        _check(lib.topo_nn_create(ch, None if stream is None else C.c_void_p(int(stream)), C.byref(h)))
+        self._h = h
+        self.channels = tuple(channels)
+        n = C.c_int64()
+        _check(lib.topo_nn_n_params(self._h, C.byref(n)))
+        self.n_params = n.value
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.topo_nn_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_weights(self, blob):
+        w = np.ascontiguousarray(blob, dtype=np.float32)
+        if w.size != self.n_params:
+            raise ValueError(f"expected {self.n_params} parameters, got {w.size}")
+        _check(self._lib.topo_nn_set_weights(self._h, w.ctypes.data_as(C.POINTER(C.c_float)), w.size))
+
+    def get_weights(self) -> np.ndarray:
+        w = np.empty(self.n_params, dtype=np.float32)
+        _check(self._lib.topo_nn_get_weights(self._h, w.ctypes.data_as(C.POINTER(C.c_float)), w.size))
+        return w
+
+    @staticmethod
+    def _nodes(nodes):
+        return (C.c_int32 * 3)(*[int(v) for v in nodes])
+
+    def forward(self, nodes, batch, x, out):
+        """out[3][batch][V] = net(x[4][batch][V]); nodes = (NX, NY, NZ)."""
+        import torch
+        V = int(np.prod(nodes))
+        _check(self._lib.topo_nn_forward(self._h, self._nodes(nodes), batch, _ptr(x, 4 * batch * V, torch.float32),
+                                         _ptr(out, 3 * batch * V, torch.float32)))
+
+    def loss_grad(self, nodes, rho, r, e, fixed, index, grad=None) -> float:
+        import torch
+        V = int(np.prod(nodes))
+        n = rho.numel() // V
+        idx = np.ascontiguousarray(index, dtype=np.int32)
+        loss = C.c_double()
+        _check(self._lib.topo_nn_loss_grad(
+            self._h, self._nodes(nodes), n, _ptr(rho, n * V, torch.float32), _ptr(r, n * 3 * V, torch.float32),
+            _ptr(e, n * 3 * V, torch.float32), _ptr(fixed, n * V, torch.uint8), idx.size,
+            idx.ctypes.data_as(C.POINTER(C.c_int32)), C.byref(loss),
+            _ptr(grad, self.n_params, torch.float32)))
+        return loss.value
+
+    def train(self, nodes, rho, r, e, fixed, opts: Optional[TrainOpts_C] = None):
+        import torch
+        V = int(np.prod(nodes))
+        n = rho.numel() // V
+        o = opts if opts is not None else default_train_opts()
+        ep = (C.c_double * max(1, o.epochs))()
+        st = TrainStats_C()
+        _check(self._lib.topo_nn_train(
+            self._h, self._nodes(nodes), n, _ptr(rho, n * V, torch.float32), _ptr(r, n * 3 * V, torch.float32),
+            _ptr(e, n * 3 * V, torch.float32), _ptr(fixed, n * V, torch.uint8), C.byref(o), ep, C.byref(st)))
+        return {"steps": st.steps, "loss_first": st.loss_first, "loss_last": st.loss_last, "ms": st.ms,
+                "epoch_loss": [ep[i] for i in range(o.epochs)]}

@@ -61,6 +61,9 @@ struct Scalars {
   double l1, l2, target, vconst, change, volume, lambda;
   int oc_done, oc_pass;
   int cg_done, cg_iters;  // device-side CG convergence state
+  int cg_max;             // iteration cap of the running solve
+  int nn_fallback;        // learned preconditioner failed its safeguard test
+  double rtol2;           // squared relative tolerance of the running solve
   double oc_lam[64];
 };
 
@@ -72,16 +75,22 @@ using Kappa = KappaT<double>;
 // kernel launchers (kernels_*.hip)
 
 // What a finalize does with the reduced value (see finalize_kernel):
-enum FinMode { FIN_SUM = 0, FIN_MAX = 1, FIN_CG_CHECK = 2, FIN_RZ = 3, FIN_RZ_FLEX = 4 };
+//   FIN_CG_CHECK  (out = rr): count the iteration, raise cg_done at convergence
+//                 (rr <= rtol2 ff) or at the iteration cap cg_max
+//   FIN_RZ        (out = rz_new): beta = rz_new / rz, then rz = rz_new
+//   FIN_RZ_FLEX   (out = r.z_new, r.z_old): flexible (Polak-Ribiere) beta
+//   FIN_RZ_SAFE   (out = r.z_new, r.z_old, z.z): as FIN_RZ_FLEX, and when
+//                 r.z_new <= kSafeEps ||r|| ||z|| (or any of them is not finite)
+//                 raise nn_fallback and cg_done
+enum FinMode { FIN_SUM = 0, FIN_MAX = 1, FIN_CG_CHECK = 2, FIN_RZ = 3, FIN_RZ_FLEX = 4, FIN_RZ_SAFE = 5 };
+constexpr double kSafeEps = 1e-6;
 struct Fin {
   int mode;
   double *out;      // device result slot(s)
-  Scalars *sc;      // FIN_CG_CHECK / FIN_RZ
-  double rtol2;     // FIN_CG_CHECK
-  int max_iters;    // FIN_CG_CHECK
+  Scalars *sc;      // all modes but FIN_SUM / FIN_MAX
 };
-inline Fin fin_sum(double *out) { return Fin{FIN_SUM, out, nullptr, 0.0, 0}; }
-inline Fin fin_max(double *out) { return Fin{FIN_MAX, out, nullptr, 0.0, 0}; }
+inline Fin fin_sum(double *out) { return Fin{FIN_SUM, out, nullptr}; }
+inline Fin fin_max(double *out) { return Fin{FIN_MAX, out, nullptr}; }
 
 // sums nparts partials (slot-major, k-th value at [slot*kMaxRed + k]) into fin.out[0..n)
 hipError_t launch_finalize(hipStream_t s, const Reducer &red, int nparts, int n, const Fin &fin,
@@ -148,8 +157,8 @@ hipError_t launch_dot(hipStream_t s, int64_t n, const double *a, const double *b
 hipError_t launch_cg_update_xr(hipStream_t s, int64_t n, Scalars *sc, double *x, double *r,
                                const double *p, const double *q, const Reducer &red,
                                const Fin &fin, const int *skip = nullptr);
-// cg_iters = 0; cg_done = (rr <= rtol2 ff)
-hipError_t launch_cg_start(hipStream_t s, Scalars *sc, double rtol2);
+// cg_iters = 0; rtol2, cg_max stored; nn_fallback = 0; cg_done = (rr <= rtol2 ff)
+hipError_t launch_cg_start(hipStream_t s, Scalars *sc, double rtol2, int max_iters);
 // z = r * dinv; fin.out = r.z
 hipError_t launch_jacobi(hipStream_t s, int64_t n, const double *r, const double *dinv, double *z,
                          const Reducer &red, const Fin &fin, const int *skip = nullptr);

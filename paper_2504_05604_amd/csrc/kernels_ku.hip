@@ -278,9 +278,7 @@ hipError_t launch_ku(hipStream_t s, KuEpi epi, const KuArgsT<float> &a, const Ka
 
 // ---------------------------------------------------------------------------
 // Sums the block partials in block order.  Besides writing the sum, a finalize
-// can run the scalar step of the CG loop that consumes it:
-//   FIN_CG_CHECK  (out = rr): count the iteration and raise cg_done at convergence
-//   FIN_RZ        (out = rz_new): beta = rz_new / rz, then rz = rz_new
+// can run the scalar step of the CG loop that consumes it (FinMode).
 __global__ void finalize_kernel(const double *partials, int nparts, int n, Fin fin, const int *skip) {
   if (skip && *skip) return;
   __shared__ double sh[kMaxRed][16];
@@ -304,7 +302,7 @@ __global__ void finalize_kernel(const double *partials, int nparts, int n, Fin f
     if (k == 0 && fin.mode == FIN_CG_CHECK) {
       Scalars *sc = fin.sc;
       sc->cg_iters += 1;
-      if (!(t > fin.rtol2 * sc->ff) || sc->cg_iters >= fin.max_iters) sc->cg_done = 1;
+      if (!(t > sc->rtol2 * sc->ff) || sc->cg_iters >= sc->cg_max) sc->cg_done = 1;
     } else if (k == 0 && fin.mode == FIN_RZ) {
       Scalars *sc = fin.sc;
       sc->beta = t / sc->rz;
@@ -312,12 +310,20 @@ __global__ void finalize_kernel(const double *partials, int nparts, int n, Fin f
     }
   }
   __syncthreads();
-  if (fin.mode == FIN_RZ_FLEX && threadIdx.x == 0) {
+  if ((fin.mode == FIN_RZ_FLEX || fin.mode == FIN_RZ_SAFE) && threadIdx.x == 0) {
     // Polak-Ribiere: beta = r.(z_new - z_old) / rz_old, from the two sums above
     Scalars *sc = fin.sc;
     const double rzn = fin.out[0], rzo = fin.out[1];
     sc->beta = (rzn - rzo) / sc->rz;
     sc->rz = rzn;
+    if (fin.mode == FIN_RZ_SAFE) {
+      // a preconditioner that is not positive on this residual cannot be used
+      const double zz = fin.out[2], bound = kSafeEps * sqrt(sc->rr * zz);
+      if (!(rzn > bound) || !isfinite(rzn) || !isfinite(zz) || !isfinite(sc->beta)) {
+        sc->nn_fallback = 1;
+        sc->cg_done = 1;
+      }
+    }
   }
 }
 

@@ -113,13 +113,17 @@ hipError_t launch_cg_update_xr(hipStream_t s, int64_t n, Scalars *sc, double *x,
   return e != hipSuccess ? e : launch_finalize(s, red, (int)nb, 1, fin, skip);
 }
 
-__global__ void cg_start_kernel(Scalars *sc, double rtol2) {
+__global__ void cg_start_kernel(Scalars *sc, double rtol2, int max_iters) {
   sc->cg_iters = 0;
-  sc->cg_done = !(sc->rr > rtol2 * sc->ff);
+  sc->rtol2 = rtol2;
+  sc->cg_max = max_iters;
+  sc->nn_fallback = 0;
+  sc->rz = 1.0;  // the first r.z finalize forms a beta that is never used: keep it finite
+  sc->cg_done = !(sc->rr > rtol2 * sc->ff) || max_iters <= 0;
 }
 
-hipError_t launch_cg_start(hipStream_t s, Scalars *sc, double rtol2) {
-  cg_start_kernel<<<1, 1, 0, s>>>(sc, rtol2);
+hipError_t launch_cg_start(hipStream_t s, Scalars *sc, double rtol2, int max_iters) {
+  cg_start_kernel<<<1, 1, 0, s>>>(sc, rtol2, max_iters);
   return hipGetLastError();
 }
 

@@ -14,6 +14,7 @@
 
 #include "internal.h"
 #include "ke_code.h"
+#include "nn.h"
 
 namespace topo {
 
@@ -196,8 +197,13 @@ struct topo_ctx {
   Reducer red{};
   int have_u = 0;
   hipStream_t cap_stream = nullptr;  // private stream for graph capture
-  hipGraph_t cg_graph = nullptr;
-  hipGraphExec_t cg_exec = nullptr;  // chunk of CG iterations
+  hipGraph_t cg_graph[3] = {};
+  hipGraphExec_t cg_exec[3] = {};    // chunk of CG iterations, per preconditioner kind
+  // learned preconditioner
+  topo_nn *nn = nullptr;
+  NnWork nnw;                        // activations (batch 1) on the node grid
+  double *nn_scale = nullptr;        // rms of the residual of the current application
+  double *ustar = nullptr;           // training-pair generation: converged solution
   std::vector<void *> allocs;
 
   template <typename T>
@@ -206,9 +212,17 @@ struct topo_ctx {
     if (e == hipSuccess) allocs.push_back((void *)*p_);
     return e;
   }
+  void drop_graphs() {
+    for (int k = 0; k < 3; ++k) {
+      if (cg_exec[k]) (void)hipGraphExecDestroy(cg_exec[k]);
+      if (cg_graph[k]) (void)hipGraphDestroy(cg_graph[k]);
+      cg_exec[k] = nullptr;
+      cg_graph[k] = nullptr;
+    }
+  }
   ~topo_ctx() {
-    if (cg_exec) (void)hipGraphExecDestroy(cg_exec);
-    if (cg_graph) (void)hipGraphDestroy(cg_graph);
+    drop_graphs();
+    nnw.release();
     if (cap_stream) (void)hipStreamDestroy(cap_stream);
     for (void *a : allocs) (void)hipFree(a);
     if (h_sc) (void)hipHostFree(h_sc);
@@ -238,6 +252,7 @@ extern "C" void topo_default_opts(topo_opts *o) {
   o->oc_tol = 1e-12;
   o->check_every = 4;
   o->use_graphs = 1;
+  o->nn_max_iters = 200;
 }
 
 extern "C" const char *topo_last_error(void) { return g_err; }
@@ -276,8 +291,10 @@ static topo_status validate(const topo_problem *P, const topo_opts *O) {
   if (nd == 0) return set_error("no design element"), TOPO_EINVAL;
   if (O->precision != TOPO_PREC_FP64 && O->precision != TOPO_PREC_FP32 && O->precision != TOPO_PREC_BF16)
     return set_error("unknown precision %d", O->precision), TOPO_EINVAL;
-  if (O->precond != TOPO_PRECOND_JACOBI && O->precond != TOPO_PRECOND_MG)
+  if (O->precond != TOPO_PRECOND_JACOBI && O->precond != TOPO_PRECOND_MG && O->precond != TOPO_PRECOND_LEARNED)
     return set_error("unknown preconditioner %d", O->precond), TOPO_EINVAL;
+  if (O->precond == TOPO_PRECOND_LEARNED && O->nn_max_iters < 1)
+    return set_error("nn_max_iters must be >= 1"), TOPO_EINVAL;
   if (O->cheb_degree < 1 || O->cheb_degree > 16) return set_error("cheb_degree must lie in [1, 16]"), TOPO_EINVAL;
   if (!(O->rtol > 0.0) || O->max_iters < 1) return set_error("rtol > 0 and max_iters >= 1 required"), TOPO_EINVAL;
   if (!(O->oc_tol > 0.0)) return set_error("oc_tol must be > 0"), TOPO_EINVAL;
@@ -368,7 +385,8 @@ extern "C" topo_status topo_setup(const topo_problem *P, const topo_opts *O, voi
   TOPO_HIP(hipMemcpyAsync(ctx->mask, hmask.data(), ctx->nel, hipMemcpyHostToDevice, s));
 
   // multigrid hierarchy (level 0 only when Jacobi is used)
-  std::vector<Grid> dims = O->precond == TOPO_PRECOND_MG ? mg_hierarchy(g, *O) : std::vector<Grid>{g};
+  // (the learned preconditioner keeps the hierarchy for its fallback)
+  std::vector<Grid> dims = O->precond != TOPO_PRECOND_JACOBI ? mg_hierarchy(g, *O) : std::vector<Grid>{g};
   ctx->lv.resize(dims.size());
   for (size_t l = 0; l < dims.size(); ++l) {
     Level &L = ctx->lv[l];
@@ -416,6 +434,7 @@ extern "C" topo_status topo_setup(const topo_problem *P, const topo_opts *O, voi
   TOPO_ALLOC(ctx->dcf, ctx->nel);
   TOPO_ALLOC(ctx->oc_a, ctx->nel);
   TOPO_ALLOC(ctx->xnew, ctx->nel);
+  TOPO_ALLOC(ctx->nn_scale, 1);
   TOPO_HIP(hipMemsetAsync(ctx->u, 0, ctx->ndof * sizeof(double), s));
   TOPO_HIP(hipMemsetAsync(ctx->z, 0, ctx->ndof * sizeof(double), s));
   TOPO_HIP(hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
@@ -542,6 +561,8 @@ static topo_status prepare_operator(topo_ctx *ctx, const double *d_xphys) {
     if (ctx->Ainv32)
       TOPO_HIP(launch_convert(s, (int64_t)ctx->ncoarse * ctx->ncoarse, ctx->Ainv, ctx->Ainv32));
   }
+  // network input channel 0 (node density) is fixed for the whole solve
+  if (ctx->nn) TOPO_HIP(launch_node_density(s, ctx->g, d_xphys, ctx->nnw.x));
   return TOPO_OK;
 }
 
@@ -698,11 +719,25 @@ static topo_status vcycle(topo_ctx *ctx, size_t l, const int *skip, const Fin *d
 // z = M r; the r.z finalize sets rz_new, beta = rz_new / rz and rz = rz_new.
 // In mixed precision the whole V-cycle runs in single precision between a
 // narrowing of r and a widening of z (which also forms r.z in double).
-static topo_status precondition(topo_ctx *ctx, const int *skip) {
+//
+// The learned preconditioner (kind TOPO_PRECOND_LEARNED) maps the residual
+// through the network (its rms comes from rr, formed by the caller) and feeds
+// the flexible update with the safeguard test of FIN_RZ_SAFE.
+static topo_status precondition(topo_ctx *ctx, int kind, const int *skip) {
   hipStream_t s = ctx->stream;
   Level &L0 = ctx->lv[0];
-  const Fin fin{FIN_RZ, &ctx->sc->rz_new, ctx->sc, 0.0, 0};
-  if (ctx->opts.precond == TOPO_PRECOND_JACOBI || ctx->lv.size() == 1) {
+  const Fin fin{FIN_RZ, &ctx->sc->rz_new, ctx->sc};
+  if (kind == TOPO_PRECOND_LEARNED) {
+    NnWork &w = ctx->nnw;
+    const int64_t V = ctx->nnodes;
+    TOPO_HIP(launch_nn_input_resid(s, V, ctx->r, &ctx->sc->rr, ctx->nn_scale, w.x + V, skip));
+    topo_status st = nn_forward(ctx->nn, w, s, skip);
+    if (st != TOPO_OK) return st;
+    const Fin safe{FIN_RZ_SAFE, &ctx->sc->red[0], ctx->sc};
+    TOPO_HIP(launch_nn_output_flex(s, V, w.out, ctx->nn_scale, L0.fixed, ctx->r, ctx->z, ctx->red, safe, skip));
+    return TOPO_OK;
+  }
+  if (kind == TOPO_PRECOND_JACOBI || ctx->lv.size() == 1) {
     TOPO_HIP(launch_jacobi(s, ctx->ndof, ctx->r, L0.dinv, ctx->z, ctx->red, fin, skip));
     return TOPO_OK;
   }
@@ -710,7 +745,7 @@ static topo_status precondition(topo_ctx *ctx, const int *skip) {
   TOPO_HIP(launch_convert(s, ctx->ndof, ctx->r, L0.f32.b, skip));
   topo_status st = vcycle<float>(ctx, 0, skip, nullptr);
   if (st != TOPO_OK) return st;
-  const Fin flex{FIN_RZ_FLEX, &ctx->sc->red[0], ctx->sc, 0.0, 0};
+  const Fin flex{FIN_RZ_FLEX, &ctx->sc->red[0], ctx->sc};
   TOPO_HIP(launch_widen_dot(s, ctx->ndof, L0.f32.x, ctx->r, ctx->z, ctx->red, flex, skip));
   return TOPO_OK;
 }
@@ -724,7 +759,7 @@ static topo_status read_scalars(topo_ctx *ctx) {
 // One CG iteration on ctx->u; after convergence (sc->cg_done) every kernel
 // returns immediately, so chunks of iterations can be enqueued (or replayed
 // from a graph) without a host round trip per iteration.
-static topo_status cg_body(topo_ctx *ctx) {
+static topo_status cg_body(topo_ctx *ctx, int kind) {
   hipStream_t s = ctx->stream;
   const int *skip = &ctx->sc->cg_done;
   Level &L0 = ctx->lv[0];
@@ -732,9 +767,9 @@ static topo_status cg_body(topo_ctx *ctx) {
   a.y = ctx->q;
   a.skip = skip;
   TOPO_HIP(launch_ku(s, KU_STORE_DOT, a, ctx->kap, ctx->red, fin_sum(&ctx->sc->pq)));
-  const Fin check{FIN_CG_CHECK, &ctx->sc->rr, ctx->sc, ctx->opts.rtol * ctx->opts.rtol, ctx->opts.max_iters};
+  const Fin check{FIN_CG_CHECK, &ctx->sc->rr, ctx->sc};
   TOPO_HIP(launch_cg_update_xr(s, ctx->ndof, ctx->sc, ctx->u, ctx->r, ctx->p, ctx->q, ctx->red, check, skip));
-  topo_status st = precondition(ctx, skip);
+  topo_status st = precondition(ctx, kind, skip);
   if (st != TOPO_OK) return st;
   TOPO_HIP(launch_cg_update_p(s, ctx->ndof, ctx->sc, ctx->z, ctx->p, 0, skip));
   return TOPO_OK;
@@ -743,21 +778,21 @@ static topo_status cg_body(topo_ctx *ctx) {
 // Enqueues one chunk of check_every CG iterations: the captured graph when graphs
 // are on (captured on first use; every pointer it holds is owned by the context),
 // direct launches otherwise.
-static topo_status cg_chunk(topo_ctx *ctx) {
+static topo_status cg_chunk(topo_ctx *ctx, int kind) {
   const int chunk = std::max(1, ctx->opts.check_every);
   if (!ctx->opts.use_graphs) {
     for (int c = 0; c < chunk; ++c) {
-      topo_status st = cg_body(ctx);
+      topo_status st = cg_body(ctx, kind);
       if (st != TOPO_OK) return st;
     }
     return TOPO_OK;
   }
-  if (!ctx->cg_exec) {
+  if (!ctx->cg_exec[kind]) {
     hipStream_t user = ctx->stream;
     ctx->stream = ctx->cap_stream;
     TOPO_HIP(hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeRelaxed));
     topo_status st = TOPO_OK;
-    for (int c = 0; c < chunk && st == TOPO_OK; ++c) st = cg_body(ctx);
+    for (int c = 0; c < chunk && st == TOPO_OK; ++c) st = cg_body(ctx, kind);
     hipGraph_t graph = nullptr;
     hipError_t ce = hipStreamEndCapture(ctx->cap_stream, &graph);
     ctx->stream = user;
@@ -766,15 +801,16 @@ static topo_status cg_chunk(topo_ctx *ctx) {
       return st;
     }
     TOPO_HIP(ce);
-    ctx->cg_graph = graph;
-    TOPO_HIP(hipGraphInstantiate(&ctx->cg_exec, graph, nullptr, nullptr, 0));
+    ctx->cg_graph[kind] = graph;
+    TOPO_HIP(hipGraphInstantiate(&ctx->cg_exec[kind], graph, nullptr, nullptr, 0));
   }
-  TOPO_HIP(hipGraphLaunch(ctx->cg_exec, ctx->stream));
+  TOPO_HIP(hipGraphLaunch(ctx->cg_exec[kind], ctx->stream));
   return TOPO_OK;
 }
 
-// PCG on the operator prepared by prepare_operator; solution in/out ctx->u.
-static topo_status pcg(topo_ctx *ctx, topo_solve_stats *stats) {
+// One run of (flexible) PCG with preconditioner `kind` and iteration cap
+// max_iters, from ctx->u; the scalars end in ctx->h_sc.
+static topo_status pcg_run(topo_ctx *ctx, int kind, int max_iters) {
   hipStream_t s = ctx->stream;
   Level &L0 = ctx->lv[0];
   const int64_t n = ctx->ndof;
@@ -789,25 +825,58 @@ static topo_status pcg(topo_ctx *ctx, topo_solve_stats *stats) {
   TOPO_HIP(launch_dot(s, n, ctx->f, ctx->f, ctx->red, fin_sum(&ctx->sc->ff)));
   const double rtol = ctx->opts.rtol;
   // iteration count 0; done at once if the initial guess already meets the tolerance
-  TOPO_HIP(launch_cg_start(s, ctx->sc, rtol * rtol));
+  TOPO_HIP(launch_cg_start(s, ctx->sc, rtol * rtol, max_iters));
+  // the flexible update reads the previous z: start it from zero
+  if (kind == TOPO_PRECOND_LEARNED || ctx->mixed) TOPO_HIP(hipMemsetAsync(ctx->z, 0, n * sizeof(double), s));
   // first direction (skipped on the device when already converged)
-  topo_status st = precondition(ctx, &ctx->sc->cg_done);
+  topo_status st = precondition(ctx, kind, &ctx->sc->cg_done);
   if (st != TOPO_OK) return st;
   TOPO_HIP(launch_cg_update_p(s, n, ctx->sc, ctx->z, ctx->p, 1, &ctx->sc->cg_done));
   st = read_scalars(ctx);
   if (st != TOPO_OK) return st;
   while (!ctx->h_sc->cg_done) {
-    st = cg_chunk(ctx);
+    st = cg_chunk(ctx, kind);
     if (st != TOPO_OK) return st;
     st = read_scalars(ctx);
     if (st != TOPO_OK) return st;
   }
+  return TOPO_OK;
+}
+
+// PCG on the operator prepared by prepare_operator; solution in/out ctx->u.
+// With the learned preconditioner, a failed safeguard test or nn_max_iters
+// iterations without convergence restart the solve from the current iterate
+// with the multigrid (or Jacobi) preconditioner.
+static topo_status pcg(topo_ctx *ctx, topo_solve_stats *stats) {
+  const int base = ctx->lv.size() > 1 ? TOPO_PRECOND_MG : TOPO_PRECOND_JACOBI;
+  int kind = ctx->opts.precond == TOPO_PRECOND_JACOBI ? TOPO_PRECOND_JACOBI : base;
+  int fallbacks = 0, learned = 0, total = 0;
+  const int cap = ctx->opts.max_iters;
+  topo_status st;
+  if (ctx->opts.precond == TOPO_PRECOND_LEARNED) {
+    if (!ctx->nn) return set_error("TOPO_PRECOND_LEARNED needs a network (topo_set_nn)"), TOPO_EINVAL;
+    st = pcg_run(ctx, TOPO_PRECOND_LEARNED, std::min(cap, ctx->opts.nn_max_iters));
+    if (st != TOPO_OK) return st;
+    learned = total = ctx->h_sc->cg_iters;
+    const bool ok = !ctx->h_sc->nn_fallback && std::isfinite(ctx->h_sc->rr) &&
+                    ctx->h_sc->rr <= ctx->opts.rtol * ctx->opts.rtol * ctx->h_sc->ff;
+    if (ok) kind = -1;
+    else ++fallbacks;
+  }
+  if (kind >= 0) {
+    st = pcg_run(ctx, kind, std::max(1, cap - total));
+    if (st != TOPO_OK) return st;
+    total += ctx->h_sc->cg_iters;
+  }
   const double ff = ctx->h_sc->ff;
+  const double rtol = ctx->opts.rtol;
   const double relres = std::sqrt(ctx->h_sc->rr / ff);
   if (stats) {
-    stats->iters = ctx->h_sc->cg_iters;
+    stats->iters = total;
     stats->relres = relres;
     stats->converged = relres <= rtol;
+    stats->fallbacks = fallbacks;
+    stats->learned_iters = learned;
   }
   if (!std::isfinite(relres)) return set_error("CG diverged (non-finite residual)"), TOPO_ENOTCONVERGED;
   if (relres > rtol)
@@ -839,7 +908,15 @@ extern "C" topo_status topo_apply_precond(topo_ctx *ctx, const double *d_xphys, 
   topo_status st = prepare_operator(ctx, d_xphys);
   if (st != TOPO_OK) return st;
   TOPO_HIP(hipMemcpyAsync(ctx->r, d_r, ctx->ndof * sizeof(double), hipMemcpyDeviceToDevice, s));
-  st = precondition(ctx, nullptr);
+  int kind = ctx->opts.precond;
+  if (kind == TOPO_PRECOND_LEARNED) {
+    if (!ctx->nn) return set_error("TOPO_PRECOND_LEARNED needs a network (topo_set_nn)"), TOPO_EINVAL;
+    TOPO_HIP(launch_dot(s, ctx->ndof, ctx->r, ctx->r, ctx->red, fin_sum(&ctx->sc->rr)));
+    TOPO_HIP(hipMemsetAsync(ctx->z, 0, ctx->ndof * sizeof(double), s));
+  } else if (kind == TOPO_PRECOND_MG && ctx->lv.size() == 1) {
+    kind = TOPO_PRECOND_JACOBI;
+  }
+  st = precondition(ctx, kind, nullptr);
   if (st != TOPO_OK) return st;
   TOPO_HIP(hipMemcpyAsync(d_z, ctx->z, ctx->ndof * sizeof(double), hipMemcpyDeviceToDevice, s));
   return TOPO_OK;
@@ -1019,5 +1096,73 @@ extern "C" topo_status topo_get_state(topo_ctx *ctx, double *d_u, double *d_xphy
   if (!ctx) return set_error("ctx is NULL"), TOPO_EINVAL;
   if (d_u) TOPO_HIP(hipMemcpyAsync(d_u, ctx->u, ctx->ndof * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
   if (d_xphys) TOPO_HIP(hipMemcpyAsync(d_xphys, ctx->xphys, ctx->nel * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
+  return TOPO_OK;
+}
+
+extern "C" topo_status topo_set_nn(topo_ctx *ctx, topo_nn *nn) {
+  if (!ctx) return set_error("ctx is NULL"), TOPO_EINVAL;
+  // the captured learned-preconditioner chunk refers to the network's buffers
+  if (ctx->cg_exec[TOPO_PRECOND_LEARNED]) (void)hipGraphExecDestroy(ctx->cg_exec[TOPO_PRECOND_LEARNED]);
+  if (ctx->cg_graph[TOPO_PRECOND_LEARNED]) (void)hipGraphDestroy(ctx->cg_graph[TOPO_PRECOND_LEARNED]);
+  ctx->cg_exec[TOPO_PRECOND_LEARNED] = nullptr;
+  ctx->cg_graph[TOPO_PRECOND_LEARNED] = nullptr;
+  ctx->nn = nullptr;
+  if (!nn) {
+    TOPO_HIP(hipStreamSynchronize(ctx->stream));
+    ctx->nnw.release();
+    return TOPO_OK;
+  }
+  const Dim3 g0{ctx->g.NX(), ctx->g.NY(), ctx->g.NZ()};
+  if (g0.count() > ((int64_t)1 << 30)) return set_error("grid too large for the network"), TOPO_EUNSUPPORTED;
+  topo_status st = nn_prepare(nn, ctx->nnw, g0, 1, false);
+  if (st != TOPO_OK) return st;
+  ctx->nn = nn;
+  return TOPO_OK;
+}
+
+extern "C" topo_status topo_nn_make_pairs(topo_ctx *ctx, const double *d_xphys, int32_t n, const int32_t *h_iters,
+                                          float *d_rho, float *d_r, float *d_e, uint8_t *d_fixed) {
+  if (!ctx || !d_xphys || !h_iters || !d_rho || !d_r || !d_e || !d_fixed) return set_error("NULL argument"), TOPO_EINVAL;
+  if (n < 1) return set_error("n must be >= 1"), TOPO_EINVAL;
+  for (int i = 0; i < n; ++i)
+    if (h_iters[i] < 0) return set_error("iteration counts must be >= 0"), TOPO_EINVAL;
+  hipStream_t s = ctx->stream;
+  if (!ctx->ustar) TOPO_ALLOC(ctx->ustar, ctx->ndof);
+  const int base = ctx->lv.size() > 1 ? TOPO_PRECOND_MG : TOPO_PRECOND_JACOBI;
+  topo_status st = prepare_operator(ctx, d_xphys);
+  if (st != TOPO_OK) return st;
+  // converged solution
+  const double rtol_user = ctx->opts.rtol;
+  ctx->opts.rtol = std::min(rtol_user, 1e-10);
+  TOPO_HIP(hipMemsetAsync(ctx->u, 0, ctx->ndof * sizeof(double), s));
+  st = pcg_run(ctx, base, ctx->opts.max_iters);
+  const double rtol2 = ctx->opts.rtol * ctx->opts.rtol;
+  ctx->opts.rtol = rtol_user;
+  if (st != TOPO_OK) return st;
+  if (!(ctx->h_sc->rr <= rtol2 * ctx->h_sc->ff))
+    return set_error("reference solve did not converge (relres %.3e)", std::sqrt(ctx->h_sc->rr / ctx->h_sc->ff)),
+           TOPO_ENOTCONVERGED;
+  TOPO_HIP(hipMemcpyAsync(ctx->ustar, ctx->u, ctx->ndof * sizeof(double), hipMemcpyDeviceToDevice, s));
+  const int64_t V = ctx->nnodes;
+  TOPO_HIP(launch_node_density(s, ctx->g, d_xphys, d_rho));
+  Level &L0 = ctx->lv[0];
+  for (int i = 0; i < n; ++i) {
+    if (i > 0) TOPO_HIP(hipMemcpyAsync(d_rho + (size_t)i * V, d_rho, V * sizeof(float), hipMemcpyDeviceToDevice, s));
+    TOPO_HIP(hipMemcpyAsync(d_fixed + (size_t)i * V, L0.fixed, V, hipMemcpyDeviceToDevice, s));
+    TOPO_HIP(hipMemsetAsync(ctx->u, 0, ctx->ndof * sizeof(double), s));
+    if (h_iters[i] > 0) {
+      st = pcg_run(ctx, base, h_iters[i]);
+      if (st != TOPO_OK) return st;
+    }
+    // true residual of the iterate, and its error against the converged solution
+    KuArgs a = ku_args(ctx, L0, ctx->u);
+    a.y = ctx->r;
+    a.b = ctx->f;
+    TOPO_HIP(launch_ku(s, KU_RESID, a, ctx->kap, ctx->red, fin_sum(&ctx->sc->red[0])));
+    TOPO_HIP(launch_pair_out(s, ctx->ndof, ctx->r, ctx->ustar, ctx->u, d_r + (size_t)i * 3 * V,
+                             d_e + (size_t)i * 3 * V));
+  }
+  TOPO_HIP(hipStreamSynchronize(s));
+  ctx->have_u = 0;  // the next warm start must not use a truncated iterate
   return TOPO_OK;
 }
