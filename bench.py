@@ -27,7 +27,7 @@ METRIC = "ms/SIMP iter @3.1M DOF; PCG iters+time to 1e-8 rel res, learned vs pla
 FP64_VECTOR_PEAK_TFLOPS = 78.6   # MI355X: 256 CU x 2.4 GHz x 128 FP64 flop/clk
 KU_FLOP_PER_ELEMENT = 1152       # dense 24x24 KE times the element vector, 2 flop per MAC
 KU_SOURCE = os.path.join(ROOT, "paper_2504_05604_amd", "csrc", "kernels_ku.hip")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "ku_node_fp64_160x80x80_traffic.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "ku_march_fp64_160x80x80_traffic.json")
 
 
 def ku_traffic_bytes():
@@ -81,6 +81,97 @@ def cpu_baseline(p, ku_equiv_per_iter, budget_s):
     }
 
 
+def learned_vs_mg(topo, synth, args):
+    """Training of the convolutional preconditioner on the GPU from pairs (r_k, u* - u_k)
+    of multigrid-PCG iterates on random 48x24x24 cantilevers (SIMP densities at
+    iterations 1, 5, 10, 20, 40), then solves to 1e-8 from zero at 96x48x48 on SIMP
+    densities with plain FP64 MG-PCG, the trained and the untrained network in
+    flexible CG (with the multigrid restart safeguard), and Jacobi-PCG."""
+    import numpy as np
+    import torch
+    from synth import networks
+
+    t0 = time.perf_counter()
+    snaps = [1, 5, 10, 20, 40]
+    pair_its = [0, 1, 2, 3, 4, 6, 8, 11, 15, 20]
+    parts = []
+    for s in range(args.learned_seeds):
+        p = synth.random_problem(s, 48)
+        p.volfrac = float(np.random.default_rng(1000 + s).uniform(0.15, 0.4))
+        with topo.Context(p, topo.default_opts()) as ctx:
+            x = torch.from_numpy(p.initial_design()).to("cuda")
+            V, done = p.nnodes, 0
+            for it in snaps:
+                ctx.iterate(x, it - done, raise_on_nonconv=False)
+                done = it
+                xp = torch.empty(p.nel, dtype=torch.float64, device="cuda")
+                ctx.get_state(xphys=xp)
+                n = len(pair_its)
+                bufs = (torch.empty(n * V, dtype=torch.float32, device="cuda"),
+                        torch.empty(n * 3 * V, dtype=torch.float32, device="cuda"),
+                        torch.empty(n * 3 * V, dtype=torch.float32, device="cuda"),
+                        torch.empty(n * V, dtype=torch.uint8, device="cuda"))
+                ctx.make_pairs(xp, pair_its, *bufs)
+                parts.append(bufs)
+    rho, r, e, fx = (torch.cat([b[i] for b in parts]) for i in range(4))
+    n_pairs = len(parts) * len(pair_its)
+    del parts
+    torch.cuda.synchronize()
+    t_data = time.perf_counter() - t0
+    print(f"# learned: {n_pairs} training pairs in {t_data:.1f} s", file=sys.stderr, flush=True)
+
+    w0 = networks.init_weights(seed=0)
+    net = topo.Network()
+    net.set_weights(w0)
+    tr = net.train((49, 25, 25), rho, r, e, fx,
+                   topo.default_train_opts(epochs=args.learned_epochs, batch=8, lr=1e-3, seed=1,
+                                           loss=topo.LOSS_COS))
+    print(f"# learned: trained {tr['steps']} steps, loss {tr['loss_first']:.3f} -> {tr['loss_last']:.3f}",
+          file=sys.stderr, flush=True)
+    del rho, r, e, fx
+    untrained = topo.Network()
+    untrained.set_weights(w0)
+
+    results = []
+    p = synth.random_problem(10001, 96)
+    with topo.Context(p, topo.default_opts()) as ctx:
+        x = torch.from_numpy(p.initial_design()).to("cuda")
+        done = 0
+        for it in (1, 10):
+            ctx.iterate(x, it - done, raise_on_nonconv=False)
+            done = it
+            xp = torch.empty(p.nel, dtype=torch.float64, device="cuda")
+            ctx.get_state(xphys=xp)
+            row = {"simp_iter": it}
+            for name, pc, nn_ in (("mg_fp64", topo.PRECOND_MG, None), ("learned", topo.PRECOND_LEARNED, net),
+                                  ("untrained", topo.PRECOND_LEARNED, untrained),
+                                  ("jacobi", topo.PRECOND_JACOBI, None)):
+                o = topo.default_opts(precond=pc, rtol=1e-8, max_iters=5000, nn_max_iters=500)
+                with topo.Context(p, o) as c2:
+                    if nn_ is not None:
+                        c2.set_nn(nn_)
+                    u = torch.zeros(p.ndof, dtype=torch.float64, device="cuda")
+                    c2.solve(xp, u, raise_on_nonconv=False)  # captures the CG graphs
+                    st = c2.solve(xp, u.zero_(), raise_on_nonconv=False)
+                    rec = {"iters": st["iters"], "ms": round(st["ms"], 3), "relres": st["relres"]}
+                    if pc == topo.PRECOND_LEARNED:
+                        rec.update(learned_iters=st["learned_iters"], fallbacks=st["fallbacks"])
+                    row[name] = rec
+            results.append(row)
+    print(f"# learned: evaluation done ({time.perf_counter() - t0:.1f} s in total)", file=sys.stderr, flush=True)
+    return {
+        "train_workload": f"{args.learned_seeds} random cantilevers 48x24x24 (91,875 DOF), pairs at CG "
+                          f"iterations {pair_its} of SIMP iterations {snaps}",
+        "pairs": n_pairs, "pair_gen_s": round(t_data, 2), "epochs": args.learned_epochs, "batch": 8,
+        "loss": "cosine", "loss_first_epoch": round(tr["loss_first"], 4), "loss_last_epoch": round(tr["loss_last"], 4),
+        "train_s": round(tr["ms"] * 1e-3, 2),
+        "train_samples_per_s": round(tr["steps"] * 8 / (tr["ms"] * 1e-3), 1),
+        "network_precision": "fp32",
+        "eval_workload": "random cantilever 96x48x48 (698,691 DOF), seed 10001, solve from zero to 1e-8",
+        "results": results,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -96,6 +187,9 @@ def main():
     ap.add_argument("--no-graphs", action="store_true")
     ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64",
                     help="precision of the multigrid preconditioner (CG stays FP64)")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-vs-multigrid leg")
+    ap.add_argument("--learned-seeds", type=int, default=16)
+    ap.add_argument("--learned-epochs", type=int, default=8)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on exactly one GPU; --gpus above 1 is not supported "
@@ -140,7 +234,7 @@ def main():
     flops = KU_FLOP_PER_ELEMENT * p.nel
     achieved = flops / (ku_ms * 1e-3) / 1e12
     roofline = {
-        "kernel": "ku_node_kernel (finest-level K.u, FP64)",
+        "kernel": "ku_march_kernel (finest-level K.u with the p.q epilogue, FP64)",
         "bound": "alu", "achieved": round(achieved, 2), "peak": FP64_VECTOR_PEAK_TFLOPS,
         "unit": "TFLOP/s", "frac": round(achieved / FP64_VECTOR_PEAK_TFLOPS, 4),
         "traffic": ku_traffic_bytes(), "ms_per_launch": round(ku_ms, 5),
@@ -173,9 +267,11 @@ def main():
         },
         "roofline": roofline,
     }
+    ctx.close()
+    if not args.no_learned:
+        out["config"]["learned_vs_mg"] = learned_vs_mg(topo, synth, args)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(p, ku_equiv, args.cpu_budget)
-    ctx.close()
     print(json.dumps(out))
 
 

@@ -237,16 +237,22 @@ topo_status topo_get_state(topo_ctx *ctx, double *d_u, double *d_xphys);
  * V = NX*NY*NZ nodes, x fastest (node numbering above).  nodes[3] = (NX, NY, NZ).
  * Training samples are stored per sample: rho [n][V] (node density), r and
  * e [n][3V] (dof order), fixed [n][V] (bit c set when dof c of the node is
- * fixed).  The loss of a sample is ||(y - e/s) m||^2 / ||(e/s) m||^2 with
- * y = net(rho, r/s), s = rms(r) and m the free dofs; a batch's loss is the mean.
+ * fixed).  With y = net(rho, r/s), s = rms(r), t = e/s and m the free dofs,
+ * the loss of a sample is
+ *   TOPO_LOSS_REL:    ||(y - t) m||^2 / ||t m||^2,
+ *   TOPO_LOSS_COS:    1 - (y m).(t m) / (|y m| |t m|)
+ *                     (blind to a positive scaling of y, as flexible CG is);
+ * a batch's loss is the mean over its samples.
  */
 typedef struct topo_nn topo_nn;
+enum { TOPO_LOSS_REL = 0, TOPO_LOSS_COS = 1 };
 
 typedef struct {
   int32_t epochs;          /* passes over the samples (a fresh shuffle each)      */
   int32_t batch;           /* samples per Adam step, 1..64                         */
   double lr, beta1, beta2, eps; /* Adam (Kingma and Ba 2015) with bias correction */
   uint64_t seed;           /* shuffle seed                                         */
+  int32_t loss;            /* TOPO_LOSS_*                                          */
 } topo_train_opts;
 
 typedef struct {
@@ -268,13 +274,14 @@ topo_status topo_nn_get_weights(const topo_nn *nn, float *h_blob, int64_t n);
 /* d_out[3][batch][V] = net(d_in[4][batch][V]) (raw network, no scaling). */
 topo_status topo_nn_forward(topo_nn *nn, const int32_t nodes[3], int32_t batch, const float *d_in,
                             float *d_out);
-/* Mean loss of the samples h_index[0..batch) (host indices into n_samples) and
- * its gradient with respect to the parameters (d_grad, n_params; may be NULL).
- * *h_loss may be NULL.  Synchronises. */
+/* Mean loss (TOPO_LOSS_*) of the samples h_index[0..batch) (host indices into
+ * n_samples) and its gradient with respect to the parameters (d_grad, n_params;
+ * may be NULL).  *h_loss may be NULL.  Synchronises. */
 topo_status topo_nn_loss_grad(topo_nn *nn, const int32_t nodes[3], int64_t n_samples, const float *d_rho,
                               const float *d_r, const float *d_e, const uint8_t *d_fixed, int32_t batch,
-                              const int32_t *h_index, double *h_loss, float *d_grad);
-/* Fills *opts: 10 epochs, batch 4, lr 1e-3, betas 0.9 / 0.999, eps 1e-8, seed 0. */
+                              const int32_t *h_index, int32_t loss_mode, double *h_loss, float *d_grad);
+/* Fills *opts: 10 epochs, batch 4, lr 1e-3, betas 0.9 / 0.999, eps 1e-8, seed 0,
+ * TOPO_LOSS_REL. */
 void topo_default_train_opts(topo_train_opts *opts);
 /* Adam training over the stored samples; the last partial batch of an epoch is
  * dropped.  h_epoch_loss (epochs entries) and h_stats may be NULL.  Synchronises. */

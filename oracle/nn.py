@@ -218,14 +218,32 @@ def apply(params, rho_node, r, fixed_mask):
     return z
 
 
-def loss_and_grad(params, rho_node, r, e, fixed_mask):
-    """Relative squared error of the scaled prediction against e / rms(r)."""
+def loss_and_grad(params, rho_node, r, e, fixed_mask, mode="rel"):
+    """Loss of the scaled prediction y = net(rho, r/s) against t = e/s (s = rms(r)),
+    over the free dofs, and its parameter gradient.
+
+    mode "rel":    ||y - t||^2 / ||t||^2 (relative squared error);
+    mode "cos":    1 - y.t / (|y| |t|) (one minus the cosine of the angle), blind to
+                   a positive scaling of y (so is flexible CG) but not to its sign.
+    """
     x, s = make_input(rho_node, r)
     out, A = forward(params, x, keep=True)
     t = np.moveaxis((e / s).reshape(rho_node.shape + (3,)), -1, 0)
     m = np.moveaxis((~fixed_mask).reshape(rho_node.shape + (3,)), -1, 0).astype(float)
-    diff = (out - t) * m
-    den = float((t * t * m).sum())
-    loss = float((diff * diff).sum()) / den
-    g = backward(params, A, 2.0 * diff / den)
+    tm = t * m
+    den = float((tm * tm).sum())
+    if mode == "rel":
+        diff = (out - t) * m
+        loss = float((diff * diff).sum()) / den
+        dout = 2.0 * diff / den
+    elif mode == "cos":
+        ym = out * m
+        a = float((ym * tm).sum())
+        b = float((ym * ym).sum())
+        q = np.sqrt(b * den)
+        loss = 1.0 - a / q
+        dout = (a / b * ym - tm) / q
+    else:
+        raise ValueError(mode)
+    g = backward(params, A, dout)
     return loss, g

@@ -26,4 +26,6 @@ from ._lib import (  # noqa: F401
     PRECOND_JACOBI,
     PRECOND_MG,
     PRECOND_LEARNED,
+    LOSS_REL,
+    LOSS_COS,
 )

@@ -21,6 +21,7 @@ FILTER_DENSITY, FILTER_SENSITIVITY = 0, 1
 FILTER_FWD, FILTER_ADJ, FILTER_SENS, FILTER_VOLW = 0, 1, 2, 3
 PREC_FP64, PREC_FP32, PREC_BF16 = 0, 1, 2
 PRECOND_JACOBI, PRECOND_MG, PRECOND_LEARNED = 0, 1, 2
+LOSS_REL, LOSS_COS = 0, 1
 
 EXPORTED = [
     "topo_default_opts", "topo_setup", "topo_destroy", "topo_last_error", "topo_sizes",
@@ -71,7 +72,7 @@ class SolveStats_C(C.Structure):
 
 class TrainOpts_C(C.Structure):
     _fields_ = [("epochs", C.c_int32), ("batch", C.c_int32), ("lr", C.c_double), ("beta1", C.c_double),
-                ("beta2", C.c_double), ("eps", C.c_double), ("seed", C.c_uint64)]
+                ("beta2", C.c_double), ("eps", C.c_double), ("seed", C.c_uint64), ("loss", C.c_int32)]
 
 
 class TrainStats_C(C.Structure):
@@ -128,7 +129,7 @@ def load(path: str = LIB_PATH):
     lib.topo_nn_set_weights.argtypes = [vp, C.POINTER(C.c_float), C.c_int64]
     lib.topo_nn_get_weights.argtypes = [vp, C.POINTER(C.c_float), C.c_int64]
     lib.topo_nn_forward.argtypes = [vp, i32p, C.c_int32, fp, fp]
-    lib.topo_nn_loss_grad.argtypes = [vp, i32p, C.c_int64, fp, fp, fp, fp, C.c_int32, i32p,
+    lib.topo_nn_loss_grad.argtypes = [vp, i32p, C.c_int64, fp, fp, fp, fp, C.c_int32, i32p, C.c_int32,
                                       C.POINTER(C.c_double), fp]
     lib.topo_default_train_opts.argtypes = [C.POINTER(TrainOpts_C)]
     lib.topo_default_train_opts.restype = None
@@ -384,18 +385,18 @@ class Network:
         _check(self._lib.topo_nn_forward(self._h, self._nodes(nodes), batch, _ptr(x, 4 * batch * V, torch.float32),
                                          _ptr(out, 3 * batch * V, torch.float32)))
 
-    def loss_grad(self, nodes, rho, r, e, fixed, index, grad=None) -> float:
+    def loss_grad(self, nodes, rho, r, e, fixed, index, grad=None, loss=LOSS_REL) -> float:
         import torch
         V = int(np.prod(nodes))
         n = rho.numel() // V
         idx = np.ascontiguousarray(index, dtype=np.int32)
-        loss = C.c_double()
+        value = C.c_double()
         _check(self._lib.topo_nn_loss_grad(
             self._h, self._nodes(nodes), n, _ptr(rho, n * V, torch.float32), _ptr(r, n * 3 * V, torch.float32),
             _ptr(e, n * 3 * V, torch.float32), _ptr(fixed, n * V, torch.uint8), idx.size,
-            idx.ctypes.data_as(C.POINTER(C.c_int32)), C.byref(loss),
+            idx.ctypes.data_as(C.POINTER(C.c_int32)), loss, C.byref(value),
             _ptr(grad, self.n_params, torch.float32)))
-        return loss.value
+        return value.value
 
     def train(self, nodes, rho, r, e, fixed, opts: Optional[TrainOpts_C] = None):
         import torch

@@ -454,64 +454,90 @@ hipError_t launch_nn_output(hipStream_t s, int64_t V, const float *out, const do
 }
 
 // ---------------------------------------------------------------------------
-// loss: pass 1 writes diff = out - t (0 on fixed dofs) and per-block partial
-// sums (diff.diff, t.t) per sample; pass 2 sums each sample's partials in block
-// order and scales diff by 2 / (den B) (the gradient of the batch mean).
+// loss, two passes.  Pass 1 reduces per sample and per block
+//   mode 0 (relative):  (d.d, t.t) with d = y - t, and writes dout = d;
+//   mode 1 (cosine):    (y.t, y.y, t.t), writes dout = t and zeroes y on fixed dofs;
+// all over the free dofs (fixed entries of dout are 0).  Pass 2 sums each
+// sample's partials in block order, stores the sample loss and turns dout into
+// the gradient of the batch mean:
+//   mode 0: 2 d / (t.t B);  mode 1: (a/b y - t) / (sqrt(b c) B), a = y.t, b = y.y, c = t.t.
 constexpr int kLossBlocks = 64;
 
-__global__ void loss_terms_kernel(int64_t V, int B, const int *idx, const float *out, const float *e,
+__global__ void loss_terms_kernel(int64_t V, int B, int mode, const int *idx, float *out, const float *e,
                                   const uint8_t *fixed, const float *scale, float *dout, double *partials) {
   const int b = blockIdx.y;
   const int64_t p = idx[b];
   const float inv = 1.0f / scale[b];
-  double sd = 0.0, st = 0.0;
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0;
   for (int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; n < V; n += (int64_t)gridDim.x * blockDim.x) {
     const uint8_t f = fixed[p * V + n];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       const int64_t o = ((int64_t)c * B + b) * V + n;
-      float d = 0.0f;
-      if (!((f >> c) & 1)) {
-        const float t = e[(p * V + n) * 3 + c] * inv;
-        d = out[o] - t;
-        sd += (double)d * d;
-        st += (double)t * t;
+      const bool fr = !((f >> c) & 1);
+      const float t = fr ? e[(p * V + n) * 3 + c] * inv : 0.0f;
+      if (mode == 0) {
+        const float d = fr ? out[o] - t : 0.0f;
+        s0 += (double)d * d;
+        s1 += (double)t * t;
+        dout[o] = d;
+      } else {
+        const float y = fr ? out[o] : 0.0f;
+        s0 += (double)y * t;
+        s1 += (double)y * y;
+        s2 += (double)t * t;
+        out[o] = y;
+        dout[o] = t;
       }
-      dout[o] = d;
     }
   }
-  double v[2] = {sd, st};
-  block_reduce_store<2, false>(v, partials, b * kLossBlocks + blockIdx.x);
+  double v[3] = {s0, s1, s2};
+  block_reduce_store<3, false>(v, partials, b * kLossBlocks + blockIdx.x);
 }
 
-__global__ void loss_scale_kernel(int64_t V, int B, const double *partials, float *dout, double *loss) {
+__global__ void loss_scale_kernel(int64_t V, int B, int mode, const double *partials, const float *out,
+                                  float *dout, double *loss) {
   const int b = blockIdx.y;
-  __shared__ double s[2];
+  __shared__ float coef[2];
   if (threadIdx.x == 0) {
-    double sd = 0.0, st = 0.0;
-    for (int q = 0; q < kLossBlocks; ++q) {
-      sd += partials[(size_t)(b * kLossBlocks + q) * kMaxRed + 0];
-      st += partials[(size_t)(b * kLossBlocks + q) * kMaxRed + 1];
+    double s[3] = {0.0, 0.0, 0.0};
+    for (int q = 0; q < kLossBlocks; ++q)
+      for (int k = 0; k < 3; ++k) s[k] += partials[(size_t)(b * kLossBlocks + q) * kMaxRed + k];
+    double l, c0, c1;
+    if (mode == 0) {
+      const double den = s[1] > 0.0 ? s[1] : 1.0;
+      l = s[0] / den;
+      c0 = 2.0 / (den * B);  // dout = c0 d
+      c1 = 0.0;
+    } else {
+      const double a = s[0], yy = s[1] > 0.0 ? s[1] : 1.0, tt = s[2] > 0.0 ? s[2] : 1.0;
+      const double q = sqrt(yy * tt);
+      l = 1.0 - a / q;
+      c0 = 1.0 / (q * B);  // dout = c0 (c1 y - t)
+      c1 = a / yy;
     }
-    s[0] = sd;
-    s[1] = st > 0.0 ? st : 1.0;
-    if (blockIdx.x == 0) loss[b] = sd / s[1];
+    if (blockIdx.x == 0) loss[b] = l;
+    coef[0] = (float)c0;
+    coef[1] = (float)c1;
   }
   __syncthreads();
-  const float gsc = (float)(2.0 / (s[1] * B));
+  const float c0 = coef[0], c1 = coef[1];
   for (int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; n < V; n += (int64_t)gridDim.x * blockDim.x)
 #pragma unroll
-    for (int c = 0; c < 3; ++c) dout[((int64_t)c * B + b) * V + n] *= gsc;
+    for (int c = 0; c < 3; ++c) {
+      const int64_t o = ((int64_t)c * B + b) * V + n;
+      dout[o] = mode == 0 ? c0 * dout[o] : c0 * (c1 * out[o] - dout[o]);
+    }
 }
 
-hipError_t launch_nn_loss(hipStream_t s, int64_t V, int B, const int *idx, const float *out,
+hipError_t launch_nn_loss(hipStream_t s, int mode, int64_t V, int B, const int *idx, float *out,
                           const float *e, const uint8_t *fixed, const float *scale, float *dout,
                           const Reducer &red, double *loss) {
-  if (B * kLossBlocks > red.max_blocks) return hipErrorInvalidValue;
-  loss_terms_kernel<<<dim3(kLossBlocks, B), kBs, 0, s>>>(V, B, idx, out, e, fixed, scale, dout, red.partials);
+  if (B * kLossBlocks > red.max_blocks || (mode != 0 && mode != 1)) return hipErrorInvalidValue;
+  loss_terms_kernel<<<dim3(kLossBlocks, B), kBs, 0, s>>>(V, B, mode, idx, out, e, fixed, scale, dout, red.partials);
   hipError_t err = hipGetLastError();
   if (err != hipSuccess) return err;
-  loss_scale_kernel<<<dim3(kLossBlocks, B), kBs, 0, s>>>(V, B, red.partials, dout, loss);
+  loss_scale_kernel<<<dim3(kLossBlocks, B), kBs, 0, s>>>(V, B, mode, red.partials, out, dout, loss);
   return hipGetLastError();
 }
 

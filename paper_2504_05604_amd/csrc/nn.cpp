@@ -359,23 +359,24 @@ static bool valid_data(const float *rho, const float *r, const float *e, const u
 }
 
 // input, forward, loss and gradient of one batch (indices already on the device)
-static topo_status batch_step(topo_nn *nn, int64_t V, const float *d_rho, const float *d_r, const float *d_e,
-                              const uint8_t *d_fixed, double *d_loss) {
+static topo_status batch_step(topo_nn *nn, int mode, int64_t V, const float *d_rho, const float *d_r,
+                              const float *d_e, const uint8_t *d_fixed, double *d_loss) {
   NnWork &w = nn->work;
   hipStream_t s = nn->stream;
   TOPO_HIP(launch_nn_input_train(s, V, w.B, w.idx, d_rho, d_r, w.scale, w.x));
   topo_status st = nn_forward(nn, w, s, nullptr);
   if (st != TOPO_OK) return st;
-  TOPO_HIP(launch_nn_loss(s, V, w.B, w.idx, w.out, d_e, d_fixed, w.scale, w.dout, nn->red, d_loss));
+  TOPO_HIP(launch_nn_loss(s, mode, V, w.B, w.idx, w.out, d_e, d_fixed, w.scale, w.dout, nn->red, d_loss));
   return nn_backward(nn, w, s);
 }
 
 extern "C" topo_status topo_nn_loss_grad(topo_nn *nn, const int32_t nodes[3], int64_t n_samples,
                                          const float *d_rho, const float *d_r, const float *d_e,
                                          const uint8_t *d_fixed, int32_t batch, const int32_t *h_index,
-                                         double *h_loss, float *d_grad) {
+                                         int32_t loss_mode, double *h_loss, float *d_grad) {
   if (!nn || !valid_data(d_rho, d_r, d_e, d_fixed) || !h_index) return set_error("NULL argument"), TOPO_EINVAL;
   if (batch < 1 || batch > 64 || !valid_nodes(nodes, batch)) return set_error("invalid grid or batch"), TOPO_EINVAL;
+  if (loss_mode != TOPO_LOSS_REL && loss_mode != TOPO_LOSS_COS) return set_error("unknown loss %d", loss_mode), TOPO_EINVAL;
   for (int b = 0; b < batch; ++b)
     if (h_index[b] < 0 || h_index[b] >= n_samples) return set_error("sample index out of range"), TOPO_EINVAL;
   const Dim3 g0{nodes[0], nodes[1], nodes[2]};
@@ -383,7 +384,7 @@ extern "C" topo_status topo_nn_loss_grad(topo_nn *nn, const int32_t nodes[3], in
   if (st != TOPO_OK) return st;
   hipStream_t s = nn->stream;
   TOPO_HIP(hipMemcpyAsync(nn->work.idx, h_index, batch * sizeof(int32_t), hipMemcpyHostToDevice, s));
-  st = batch_step(nn, g0.count(), d_rho, d_r, d_e, d_fixed, nn->work.loss);
+  st = batch_step(nn, loss_mode, g0.count(), d_rho, d_r, d_e, d_fixed, nn->work.loss);
   if (st != TOPO_OK) return st;
   if (d_grad) TOPO_HIP(hipMemcpyAsync(d_grad, nn->G, nn->nparams * sizeof(float), hipMemcpyDeviceToDevice, s));
   std::vector<double> l(batch);
@@ -414,6 +415,7 @@ extern "C" void topo_default_train_opts(topo_train_opts *o) {
   o->beta2 = 0.999;
   o->eps = 1e-8;
   o->seed = 0;
+  o->loss = TOPO_LOSS_REL;
 }
 
 extern "C" topo_status topo_nn_train(topo_nn *nn, const int32_t nodes[3], int64_t n_samples, const float *d_rho,
@@ -422,7 +424,8 @@ extern "C" topo_status topo_nn_train(topo_nn *nn, const int32_t nodes[3], int64_
   if (!nn || !valid_data(d_rho, d_r, d_e, d_fixed) || !opts) return set_error("NULL argument"), TOPO_EINVAL;
   if (!valid_nodes(nodes) || n_samples < 1 || n_samples > (1ll << 30)) return set_error("invalid grid or sample count"), TOPO_EINVAL;
   if (opts->epochs < 0 || opts->batch < 1 || opts->batch > 64 || !(opts->lr > 0.0) || !(opts->beta1 >= 0.0) ||
-      !(opts->beta1 < 1.0) || !(opts->beta2 >= 0.0) || !(opts->beta2 < 1.0) || !(opts->eps > 0.0))
+      !(opts->beta1 < 1.0) || !(opts->beta2 >= 0.0) || !(opts->beta2 < 1.0) || !(opts->eps > 0.0) ||
+      (opts->loss != TOPO_LOSS_REL && opts->loss != TOPO_LOSS_COS))
     return set_error("invalid training options"), TOPO_EINVAL;
   const int B = (int)std::min<int64_t>(opts->batch, n_samples);
   if (!valid_nodes(nodes, B)) return set_error("grid too large for the batch"), TOPO_EINVAL;
@@ -466,7 +469,7 @@ extern "C" topo_status topo_nn_train(topo_nn *nn, const int32_t nodes[3], int64_
     for (int64_t k = 0; k < steps_per_epoch && st == TOPO_OK; ++k) {
       const int64_t step = (int64_t)ep * steps_per_epoch + k;
       w.idx = d_perm + (size_t)ep * n_samples + k * B;
-      st = batch_step(nn, g0.count(), d_rho, d_r, d_e, d_fixed, d_loss + step * B);
+      st = batch_step(nn, opts->loss, g0.count(), d_rho, d_r, d_e, d_fixed, d_loss + step * B);
       if (st != TOPO_OK) break;
       ++nn->adam_step;
       hipError_t he = launch_adam(s, nn->nparams, nn->W, nn->G, nn->m, nn->v, (float)opts->lr, (float)opts->beta1,

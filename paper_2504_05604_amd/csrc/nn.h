@@ -81,9 +81,11 @@ hipError_t launch_nn_output_flex(hipStream_t s, int64_t V, const float *out, con
 // plain output (no reductions): z = scale * out, zero on fixed dofs
 hipError_t launch_nn_output(hipStream_t s, int64_t V, const float *out, const double *scale,
                             const uint8_t *fixed, double *z);
-// per-sample loss ||(out - e/scale) m||^2 / ||(e/scale) m||^2 with m the free dofs;
-// dout = d(mean loss)/d out; loss[b] receives each sample's value
-hipError_t launch_nn_loss(hipStream_t s, int64_t V, int B, const int *idx, const float *out,
+// per-sample loss over the free dofs m of y = out against t = e/scale:
+// mode 0 ||(y - t) m||^2 / ||t m||^2, mode 1 1 - (y m).(t m) / (|y m| |t m|);
+// dout = d(mean loss)/d out; loss[b] receives each sample's value.  Mode 1
+// zeroes out on fixed dofs.
+hipError_t launch_nn_loss(hipStream_t s, int mode, int64_t V, int B, const int *idx, float *out,
                           const float *e, const uint8_t *fixed, const float *scale, float *dout,
                           const Reducer &red, double *loss);
 

@@ -78,8 +78,9 @@ def random_samples(seed, n, nodes):
     return rho, r, e, fixed
 
 
+@pytest.mark.parametrize("mode", ["rel", "cos"])
 @pytest.mark.parametrize("nodes,batch", [((9, 7, 6), 1), ((13, 7, 9), 3)])
-def test_loss_gradient_matches_oracle(nodes, batch):
+def test_loss_gradient_matches_oracle(nodes, batch, mode):
     ch = (16, 32, 64)
     blob = networks.init_weights(ch, seed=3)
     n = batch + 1
@@ -90,14 +91,15 @@ def test_loss_gradient_matches_oracle(nodes, batch):
     grad = torch.empty(net.n_params, dtype=torch.float32, device="cuda")
     bits = np.stack([node_fixed_bits(f) for f in fixed])
     loss = net.loss_grad(nodes, dev(rho.reshape(-1)), dev(r.reshape(-1)), dev(e.reshape(-1)),
-                         dev(bits.reshape(-1), torch.uint8), index, grad)
+                         dev(bits.reshape(-1), torch.uint8), index, grad,
+                         loss=topo.LOSS_REL if mode == "rel" else topo.LOSS_COS)
     g = host(grad)
     P = oracle_params(blob, ch)
     shape = (nodes[2], nodes[1], nodes[0])
     ref_loss, ref_g = 0.0, None
     for i in index:
         l, gi = nn.loss_and_grad(P, rho[i].astype(np.float64).reshape(shape), r[i].astype(np.float64),
-                                 e[i].astype(np.float64), fixed[i])
+                                 e[i].astype(np.float64), fixed[i], mode)
         vec = nn.pack(gi, ch)
         ref_loss += l / batch
         ref_g = vec / batch if ref_g is None else ref_g + vec / batch

@@ -51,7 +51,8 @@ def test_parameter_count():
     assert nn.n_params() == weights + biases == 354611
 
 
-def test_loss_gradient_matches_finite_differences():
+@pytest.mark.parametrize("mode", ["rel", "cos"])
+def test_loss_gradient_matches_finite_differences(mode):
     ch = (2, 4, 6)
     shapes = nn.layer_shapes(ch)
     npar = nn.n_params(ch)
@@ -64,7 +65,7 @@ def test_loss_gradient_matches_finite_differences():
     fixed = np.zeros(r.size, bool)
     fixed[:6] = True
     r[fixed] = 0.0
-    loss, g = nn.loss_and_grad(nn.unpack(blob, ch), rho, r, e, fixed)
+    loss, g = nn.loss_and_grad(nn.unpack(blob, ch), rho, r, e, fixed, mode)
     gvec = np.concatenate([np.concatenate([g[n][0].ravel(), g[n][1].ravel()]) for n, _ in shapes])
     idx = rng.choice(npar, 60, replace=False)
     h = 1e-6
@@ -72,8 +73,8 @@ def test_loss_gradient_matches_finite_differences():
         bp, bm = blob.copy(), blob.copy()
         bp[i] += h
         bm[i] -= h
-        fd = (nn.loss_and_grad(nn.unpack(bp, ch), rho, r, e, fixed)[0]
-              - nn.loss_and_grad(nn.unpack(bm, ch), rho, r, e, fixed)[0]) / (2 * h)
+        fd = (nn.loss_and_grad(nn.unpack(bp, ch), rho, r, e, fixed, mode)[0]
+              - nn.loss_and_grad(nn.unpack(bm, ch), rho, r, e, fixed, mode)[0]) / (2 * h)
         assert abs(fd - gvec[i]) <= 1e-6 * max(1.0, abs(fd)), (i, fd, gvec[i])
 
 
@@ -85,3 +86,23 @@ def test_node_density_averages_adjacent_elements():
     # interior node (1,1,1) touches the 8 elements around it
     E = x.reshape(2, 3, 4)
     assert rho[1, 1, 1] == E[0:2, 0:2, 0:2].mean()
+
+
+def test_cosine_loss_is_blind_to_positive_output_scale():
+    # a network whose head is multiplied by c > 0 has the same loss; by -1, 2 - loss
+    ch = (2, 4, 6)
+    rng = np.random.default_rng(12)
+    blob = 0.3 * rng.standard_normal(nn.n_params(ch))
+    grid = (3, 4, 5)
+    rho = rng.uniform(0, 1, grid)
+    r = rng.standard_normal(3 * int(np.prod(grid)))
+    e = rng.standard_normal(r.size)
+    fixed = np.zeros(r.size, bool)
+    P = nn.unpack(blob, ch)
+    l1 = nn.loss_and_grad(P, rho, r, e, fixed, "cos")[0]
+    Q = dict(P)
+    Q["head"] = (P["head"][0] * 7.0, P["head"][1] * 7.0)
+    l2 = nn.loss_and_grad(Q, rho, r, e, fixed, "cos")[0]
+    Q["head"] = (-P["head"][0], -P["head"][1])
+    l3 = nn.loss_and_grad(Q, rho, r, e, fixed, "cos")[0]
+    assert 0.0 <= l1 <= 2.0 and abs(l1 - l2) < 1e-12 and abs(l1 + l3 - 2.0) < 1e-12
