@@ -172,6 +172,43 @@ def learned_vs_mg(topo, synth, args):
     }
 
 
+def batched(topo, synth, args):
+    """64 independent random problems (grids 24x12x12 .. 96x48x48, seeds 0-63) with the
+    single-precision multigrid preconditioner and autotuned K.u launch shapes:
+    aggregate time of one SIMP iteration of the whole batch, driven concurrently
+    (one stream per problem, 8 host threads) and one problem after another."""
+    import numpy as np
+    import torch
+
+    ps = synth.batch_problems(args.batch_size)
+    opts = topo.default_opts(precision=topo.PREC_FP32, autotune=1)
+    out = {"workload": f"{len(ps)} random cantilevers, seeds 0-{len(ps) - 1}, grids nelx=8*U{{3..12}} x nelx/2 x nelx/2",
+           "precond": "mg, fp32 preconditioner", "autotune": True}
+    for label, threads in (("concurrent", 8), ("sequential", 1)):
+        t0 = time.perf_counter()
+        b = topo.Batch(ps, opts, n_threads=threads)
+        out.setdefault("total_dof", int(sum(b.ndof)))
+        out.setdefault("setup_s", round(time.perf_counter() - t0, 2))
+        xs = [torch.from_numpy(p.initial_design()).to("cuda") for p in ps]
+        b.iterate(xs, args.batch_warmup, raise_on_nonconv=False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = b.iterate(xs, args.batch_steps, raise_on_nonconv=False)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        b.close()
+        iters = sum(s["pcg_iters"] for row in st for s in row)
+        dof_iters = sum(b.ndof[i] * s["pcg_iters"] for i, row in enumerate(st) for s in row)
+        out[label] = {"ms_per_batch_iteration": round(1e3 * dt / args.batch_steps, 2),
+                      "pcg_iters_mean": round(iters / (len(ps) * args.batch_steps), 2),
+                      "dof_pcg_iters_per_s": round(dof_iters / dt, 1)}
+    out["speedup_concurrent_vs_sequential"] = round(
+        out["sequential"]["ms_per_batch_iteration"] / out["concurrent"]["ms_per_batch_iteration"], 2)
+    print(f"# batched: {out['concurrent']['ms_per_batch_iteration']} ms per batch iteration concurrent, "
+          f"{out['sequential']['ms_per_batch_iteration']} sequential", file=sys.stderr, flush=True)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -188,6 +225,10 @@ def main():
     ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64",
                     help="precision of the multigrid preconditioner (CG stays FP64)")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-vs-multigrid leg")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched-problems leg")
+    ap.add_argument("--batch-size", type=int, default=64)
+    ap.add_argument("--batch-steps", type=int, default=5)
+    ap.add_argument("--batch-warmup", type=int, default=2)
     ap.add_argument("--learned-seeds", type=int, default=16)
     ap.add_argument("--learned-epochs", type=int, default=8)
     args = ap.parse_args()
@@ -264,12 +305,15 @@ def main():
                               for k in ("ms_filter", "ms_solve", "ms_sens", "ms_oc")},
             "compliance_last": stats[-1]["c"],
             "learned_vs_mg": None,
+            "batched": None,
         },
         "roofline": roofline,
     }
     ctx.close()
     if not args.no_learned:
         out["config"]["learned_vs_mg"] = learned_vs_mg(topo, synth, args)
+    if not args.no_batch:
+        out["config"]["batched"] = batched(topo, synth, args)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(p, ku_equiv, args.cpu_budget)
     print(json.dumps(out))

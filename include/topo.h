@@ -106,6 +106,8 @@ typedef struct {
   int32_t use_graphs;         /* replay chunks of CG iterations from a captured HIP graph */
   int32_t nn_max_iters;       /* LEARNED: flexible-CG iterations before the solve restarts
                                  on the multigrid preconditioner                       */
+  int32_t autotune;           /* time every K.u launch shape on this problem's grids at
+                                 setup and keep the fastest (else chosen by grid size)   */
 } topo_opts;
 
 typedef struct {
@@ -130,7 +132,7 @@ typedef struct {
 
 /* Fills *opts with defaults: FP64, MG, automatic depth (coarsest <= 140 dofs),
  * Chebyshev degree 2, rtol 1e-8, max_iters 1000, warm start, oc_tol 1e-12,
- * check_every 4, use_graphs 1, nn_max_iters 200. */
+ * check_every 4, use_graphs 1, nn_max_iters 200, autotune 0. */
 void topo_default_opts(topo_opts *opts);
 
 /* Validates the problem, copies its arrays to the device, builds the element
@@ -215,6 +217,26 @@ topo_status topo_time_operator(topo_ctx *ctx, int32_t reps, double *h_ms_per_lau
 /* Copies the context's current displacement (ndof) to d_u / physical density
  * (nel) to d_xphys; either may be NULL. */
 topo_status topo_get_state(topo_ctx *ctx, double *d_u, double *d_xphys);
+
+/* ------------------------------------------------------------------------
+ * Batches of independent problems.  Each problem gets its own context on its
+ * own stream (created by the batch), so kernels of different problems overlap
+ * on the device; topo_iterate_batch drives them from a pool of n_threads host
+ * threads (0 = min(8, n)), largest problems first.  Results of every problem
+ * are those of topo_iterate on a context of its own with the same options.
+ */
+typedef struct topo_batch topo_batch;
+/* Sets up n problems (the array is read during the call only).  Errors as for
+ * topo_setup, with the failing problem's index in the message. */
+topo_status topo_setup_batch(const topo_problem *problems, int32_t n, const topo_opts *opts, int32_t n_threads,
+                             topo_batch **out);
+void topo_destroy_batch(topo_batch *batch);
+/* The context of problem i (owned by the batch), e.g. for topo_get_state. */
+topo_status topo_batch_context(topo_batch *batch, int32_t i, topo_ctx **out);
+/* n_iter SIMP iterations of every problem i on d_x[i] (device, nel_i, in/out);
+ * h_stats (n * n_iter entries, problem-major) may be NULL.  Returns after all
+ * problems are done; TOPO_ENOTCONVERGED if any solve hit max_iters. */
+topo_status topo_iterate_batch(topo_batch *batch, double *const *d_x, int32_t n_iter, topo_iter_stats *h_stats);
 
 /* ------------------------------------------------------------------------
  * Learned preconditioner.  A three-level convolutional encoder-decoder on the

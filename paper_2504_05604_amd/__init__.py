@@ -5,6 +5,7 @@ the C ABI in ``include/topo.h``); this package is its thin Python binding.
 """
 
 from ._lib import (  # noqa: F401
+    Batch,
     Context,
     Network,
     NotConverged,

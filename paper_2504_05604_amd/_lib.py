@@ -29,9 +29,10 @@ EXPORTED = [
     "topo_iterate", "topo_get_state", "topo_time_operator",
     "topo_nn_create", "topo_nn_destroy", "topo_nn_n_params", "topo_nn_set_weights", "topo_nn_get_weights",
     "topo_nn_forward", "topo_nn_loss_grad", "topo_default_train_opts", "topo_nn_train", "topo_set_nn",
-    "topo_nn_make_pairs",
+    "topo_nn_make_pairs", "topo_setup_batch", "topo_destroy_batch", "topo_batch_context", "topo_iterate_batch",
 ]
-_VOID = ("topo_default_opts", "topo_destroy", "topo_last_error", "topo_nn_destroy", "topo_default_train_opts")
+_VOID = ("topo_default_opts", "topo_destroy", "topo_last_error", "topo_nn_destroy", "topo_default_train_opts",
+         "topo_destroy_batch")
 
 
 class TopoError(RuntimeError):
@@ -62,6 +63,7 @@ class Opts_C(C.Structure):
         ("mg_max_coarse_dof", C.c_int32), ("cheb_degree", C.c_int32), ("rtol", C.c_double),
         ("max_iters", C.c_int32), ("warm_start", C.c_int32), ("oc_tol", C.c_double),
         ("check_every", C.c_int32), ("use_graphs", C.c_int32), ("nn_max_iters", C.c_int32),
+        ("autotune", C.c_int32),
     ]
 
 
@@ -137,6 +139,11 @@ def load(path: str = LIB_PATH):
                                   C.POINTER(C.c_double), C.POINTER(TrainStats_C)]
     lib.topo_set_nn.argtypes = [vp, vp]
     lib.topo_nn_make_pairs.argtypes = [vp, dp, C.c_int32, i32p, fp, fp, fp, fp]
+    lib.topo_setup_batch.argtypes = [C.POINTER(Problem_C), C.c_int32, C.POINTER(Opts_C), C.c_int32, C.POINTER(vp)]
+    lib.topo_destroy_batch.argtypes = [vp]
+    lib.topo_destroy_batch.restype = None
+    lib.topo_batch_context.argtypes = [vp, C.c_int32, C.POINTER(vp)]
+    lib.topo_iterate_batch.argtypes = [vp, C.POINTER(vp), C.c_int32, C.POINTER(IterStats_C)]
     for name in EXPORTED:
         if name not in _VOID:
             getattr(lib, name).restype = C.c_int
@@ -180,6 +187,36 @@ def _ptr(t, n: Optional[int] = None, dtype=None):
     return C.c_void_p(t.data_ptr())
 
 
+def _problem_c(p, filter_mode=None):
+    """Problem_C for a problem description, and the host arrays it points to
+    (they must stay alive until setup returns; setup copies them)."""
+    nel = int(p.nelx * p.nely * p.nelz)
+    ndof = int(3 * (p.nelx + 1) * (p.nely + 1) * (p.nelz + 1))
+    mask = None if p.mask is None else np.ascontiguousarray(p.mask, dtype=np.int8)
+    fixed = np.ascontiguousarray(p.fixed_dofs, dtype=np.int64)
+    f = np.ascontiguousarray(p.f, dtype=np.float64)
+    if f.size != ndof:
+        raise ValueError("load vector has the wrong length")
+    if mask is not None and mask.size != nel:
+        raise ValueError("mask has the wrong length")
+    mode = filter_mode if filter_mode is not None else getattr(p, "filter_mode", "density")
+    pc = Problem_C(
+        p.nelx, p.nely, p.nelz, p.E0, p.Emin, p.nu, p.penal, p.rmin, p.volfrac, p.move, p.eta,
+        FILTER_DENSITY if mode == "density" else FILTER_SENSITIVITY,
+        None if mask is None else mask.ctypes.data_as(C.POINTER(C.c_int8)),
+        fixed.ctypes.data_as(C.POINTER(C.c_int64)), fixed.size,
+        f.ctypes.data_as(C.POINTER(C.c_double)),
+    )
+    return pc, (mask, fixed, f)
+
+
+def _iter_stats(s) -> dict:
+    return {"c": s.c, "volume": s.volume, "change": s.change, "lambda": s.lambda_,
+            "pcg_iters": s.pcg_iters, "converged": bool(s.converged), "relres": s.relres,
+            "ms_total": s.ms_total, "ms_filter": s.ms_filter, "ms_solve": s.ms_solve,
+            "ms_sens": s.ms_sens, "ms_oc": s.ms_oc}
+
+
 class Context:
     """One problem on one device; wraps a topo_ctx."""
 
@@ -194,22 +231,7 @@ class Context:
         p = problem
         self.nel = int(p.nelx * p.nely * p.nelz)
         self.ndof = int(3 * (p.nelx + 1) * (p.nely + 1) * (p.nelz + 1))
-        # keep host arrays alive during setup (setup copies them)
-        self._mask = None if p.mask is None else np.ascontiguousarray(p.mask, dtype=np.int8)
-        self._fixed = np.ascontiguousarray(p.fixed_dofs, dtype=np.int64)
-        self._f = np.ascontiguousarray(p.f, dtype=np.float64)
-        if self._f.size != self.ndof:
-            raise ValueError("load vector has the wrong length")
-        if self._mask is not None and self._mask.size != self.nel:
-            raise ValueError("mask has the wrong length")
-        mode = filter_mode if filter_mode is not None else getattr(p, "filter_mode", "density")
-        pc = Problem_C(
-            p.nelx, p.nely, p.nelz, p.E0, p.Emin, p.nu, p.penal, p.rmin, p.volfrac, p.move, p.eta,
-            FILTER_DENSITY if mode == "density" else FILTER_SENSITIVITY,
-            None if self._mask is None else self._mask.ctypes.data_as(C.POINTER(C.c_int8)),
-            self._fixed.ctypes.data_as(C.POINTER(C.c_int64)), self._fixed.size,
-            self._f.ctypes.data_as(C.POINTER(C.c_double)),
-        )
+        pc, self._keep = _problem_c(p, filter_mode)
         self.opts = opts if opts is not None else default_opts()
         handle = C.c_void_p()
         st_ptr = None if stream is None else C.c_void_p(int(stream))
@@ -287,14 +309,7 @@ class Context:
         status = self._lib.topo_iterate(self._h, _ptr(x, self.nel, torch.float64), n_iter, stats)
         if not (status == TOPO_ENOTCONVERGED and not raise_on_nonconv):
             _check(status)
-        out = []
-        for i in range(n_iter):
-            s = stats[i]
-            out.append({"c": s.c, "volume": s.volume, "change": s.change, "lambda": s.lambda_,
-                        "pcg_iters": s.pcg_iters, "converged": bool(s.converged), "relres": s.relres,
-                        "ms_total": s.ms_total, "ms_filter": s.ms_filter, "ms_solve": s.ms_solve,
-                        "ms_sens": s.ms_sens, "ms_oc": s.ms_oc})
-        return out
+        return [_iter_stats(stats[i]) for i in range(n_iter)]
 
     def time_operator(self, reps: int = 50) -> float:
         """Average ms per launch of the finest-level K.u kernel (hipEvents)."""
@@ -410,3 +425,61 @@ class Network:
             _ptr(e, n * 3 * V, torch.float32), _ptr(fixed, n * V, torch.uint8), C.byref(o), ep, C.byref(st)))
         return {"steps": st.steps, "loss_first": st.loss_first, "loss_last": st.loss_last, "ms": st.ms,
                 "epoch_loss": [ep[i] for i in range(o.epochs)]}
+
+
+class Batch:
+    """Independent problems iterated concurrently; wraps a topo_batch."""
+
+    def __init__(self, problems, opts: Optional[Opts_C] = None, n_threads: int = 0):
+        lib = load()
+        self._lib = lib
+        import torch
+        torch.cuda.init()
+        pcs, keep = [], []
+        for p in problems:
+            pc, k = _problem_c(p)
+            pcs.append(pc)
+            keep.append(k)
+        arr = (Problem_C * len(pcs))(*pcs)
+        self.opts = opts if opts is not None else default_opts()
+        h = C.c_void_p()
+        _check(lib.topo_setup_batch(arr, len(pcs), C.byref(self.opts), n_threads, C.byref(h)))
+        self._h = h
+        self.n = len(pcs)
+        self.nel = [int(p.nelx * p.nely * p.nelz) for p in problems]
+        self.ndof = [int(3 * (p.nelx + 1) * (p.nely + 1) * (p.nelz + 1)) for p in problems]
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.topo_destroy_batch(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def iterate(self, xs, n_iter: int, raise_on_nonconv=True) -> List[List[dict]]:
+        import torch
+        if len(xs) != self.n:
+            raise ValueError("one design per problem")
+        ptrs = (C.c_void_p * self.n)(*[_ptr(x, self.nel[i], torch.float64) for i, x in enumerate(xs)])
+        stats = (IterStats_C * max(1, self.n * n_iter))()
+        status = self._lib.topo_iterate_batch(self._h, ptrs, n_iter, stats)
+        if not (status == TOPO_ENOTCONVERGED and not raise_on_nonconv):
+            _check(status)
+        return [[_iter_stats(stats[i * n_iter + k]) for k in range(n_iter)] for i in range(self.n)]
+
+    def get_state(self, i: int, u=None, xphys=None):
+        import torch
+        c = C.c_void_p()
+        _check(self._lib.topo_batch_context(self._h, i, C.byref(c)))
+        _check(self._lib.topo_get_state(c, _ptr(u, self.ndof[i], torch.float64),
+                                        _ptr(xphys, self.nel[i], torch.float64)))

@@ -142,6 +142,7 @@ hipError_t launch_ku(hipStream_t s, KuEpi epi, const KuArgs &a, const Kappa &kap
 hipError_t launch_ku(hipStream_t s, KuEpi epi, const KuArgsT<float> &a, const KappaT<float> &kap,
                      const Reducer &red, const Fin &fin, int shape = -1);
 int ku_shape_for(const Grid &g, KuEpi epi);
+constexpr int kKuShapes = 4;  // launch shapes 0..3 accepted by launch_ku
 
 // vector kernels
 hipError_t launch_zero_fixed(hipStream_t s, int64_t nnodes, const uint8_t *fixed, double *v);

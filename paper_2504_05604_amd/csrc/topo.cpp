@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <functional>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -137,6 +138,7 @@ struct Level {
   uint8_t *fixed = nullptr;  // per node, bit c = dof c fixed
   double *b = nullptr, *x = nullptr, *res = nullptr, *d0 = nullptr, *d1 = nullptr;
   LevelBufs<float> f32;      // single-precision copy for the mixed-precision preconditioner
+  int shape = -1;            // K.u launch shape of the smoothing passes (-1: by grid size)
 };
 
 template <typename T>
@@ -200,6 +202,7 @@ struct topo_ctx {
   hipGraph_t cg_graph[3] = {};
   hipGraphExec_t cg_exec[3] = {};    // chunk of CG iterations, per preconditioner kind
   // learned preconditioner
+  int shape_cg = -1;                 // K.u launch shape of the CG product (-1: by grid size)
   topo_nn *nn = nullptr;
   NnWork nnw;                        // activations (batch 1) on the node grid
   double *nn_scale = nullptr;        // rms of the residual of the current application
@@ -253,6 +256,7 @@ extern "C" void topo_default_opts(topo_opts *o) {
   o->check_every = 4;
   o->use_graphs = 1;
   o->nn_max_iters = 200;
+  o->autotune = 0;
 }
 
 extern "C" const char *topo_last_error(void) { return g_err; }
@@ -314,6 +318,8 @@ static std::vector<Grid> mg_hierarchy(Grid g, const topo_opts &o) {
   }
   return dims;
 }
+
+static topo_status autotune(topo_ctx *ctx);
 
 extern "C" topo_status topo_setup(const topo_problem *P, const topo_opts *O, void *hip_stream,
                                   topo_ctx **out) {
@@ -485,6 +491,10 @@ extern "C" topo_status topo_setup(const topo_problem *P, const topo_opts *O, voi
     TOPO_HIP(hipMemcpyAsync(ctx->volw, hv.data(), ctx->nel * sizeof(double), hipMemcpyHostToDevice, s));
     TOPO_HIP(hipStreamSynchronize(s));  // hv goes out of scope
   }
+  if (O->autotune) {
+    st = autotune(ctx);
+    if (st != TOPO_OK) return st;
+  }
   TOPO_HIP(hipStreamSynchronize(s));
   *out = c.release();
   return TOPO_OK;
@@ -536,6 +546,72 @@ const KappaT<double> &kappa_of<double>(const topo_ctx *ctx) {
 template <>
 const KappaT<float> &kappa_of<float>(const topo_ctx *ctx) {
   return ctx->kap32;
+}
+
+// ---------------------------------------------------------------------------
+// Launch-shape autotuner: times every K.u launch shape (nodes per thread column
+// x threads per block) on this context's grids and keeps the fastest, for the CG
+// product on the finest level and for the smoothing passes on every level.
+static topo_status time_ku_shapes(topo_ctx *ctx, int n_shapes, const std::function<hipError_t(int)> &launch,
+                                  int *best) {
+  hipStream_t s = ctx->stream;
+  hipEvent_t e0, e1;
+  TOPO_HIP(hipEventCreate(&e0));
+  TOPO_HIP(hipEventCreate(&e1));
+  float best_ms = 0.f;
+  *best = -1;
+  for (int shape = 0; shape < n_shapes; ++shape) {
+    TOPO_HIP(launch(shape));  // warm-up
+    TOPO_HIP(hipEventRecord(e0, s));
+    for (int r = 0; r < 3; ++r) TOPO_HIP(launch(shape));
+    TOPO_HIP(hipEventRecord(e1, s));
+    TOPO_HIP(hipEventSynchronize(e1));
+    float ms = 0.f;
+    TOPO_HIP(hipEventElapsedTime(&ms, e0, e1));
+    if (*best < 0 || ms < best_ms) best_ms = ms, *best = shape;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return TOPO_OK;
+}
+
+template <typename T>
+static topo_status tune_smoothing(topo_ctx *ctx, Level &L) {
+  const LevelBufs<T> B = bufs<T>(L);
+  const int64_t nd = L.g.ndof();
+  hipStream_t s = ctx->stream;
+  TOPO_HIP(hipMemsetAsync(B.E, 0, L.g.nel() * sizeof(T), s));
+  for (T *v : {B.dinv, B.b, B.x, B.res, B.d0, B.d1}) TOPO_HIP(hipMemsetAsync(v, 0, nd * sizeof(T), s));
+  KuArgsT<T> c = ku_args_t<T>(L, B.d0);
+  c.res = B.res;
+  c.x = B.x;
+  c.dout = B.d1;
+  c.c1 = (T)0.5;
+  c.c2 = (T)0.5;
+  const KappaT<T> &kap = kappa_of<T>(ctx);
+  return time_ku_shapes(ctx, kKuShapes, [&](int shape) {
+    return launch_ku(s, KU_CHEB, c, kap, ctx->red, fin_sum(nullptr), shape);
+  }, &L.shape);
+}
+
+static topo_status autotune(topo_ctx *ctx) {
+  hipStream_t s = ctx->stream;
+  Level &L0 = ctx->lv[0];
+  const int64_t nd = ctx->ndof;
+  TOPO_HIP(hipMemsetAsync(L0.E, 0, ctx->nel * sizeof(double), s));
+  TOPO_HIP(hipMemsetAsync(ctx->p, 0, nd * sizeof(double), s));
+  KuArgs a = ku_args(ctx, L0, ctx->p);
+  a.y = ctx->q;
+  topo_status st = time_ku_shapes(ctx, kKuShapes, [&](int shape) {
+    return launch_ku(s, KU_STORE_DOT, a, ctx->kap, ctx->red, fin_sum(&ctx->sc->red[0]), shape);
+  }, &ctx->shape_cg);
+  if (st != TOPO_OK) return st;
+  if (ctx->lv.size() < 2) return TOPO_OK;  // Jacobi: no smoothing passes
+  for (Level &L : ctx->lv) {
+    st = ctx->mixed ? tune_smoothing<float>(ctx, L) : tune_smoothing<double>(ctx, L);
+    if (st != TOPO_OK) return st;
+  }
+  return TOPO_OK;
 }
 
 // level-0 modulus from xphys, then the coarse moduli, diagonals and coarse inverse
@@ -596,7 +672,7 @@ static topo_status pre_smooth(topo_ctx *ctx, Level &L, const int *skip) {
   a.s0 = (T)(1.0 / ch.theta);
   a.skip = skip;
   if (deg == 1) {
-    TOPO_HIP(launch_ku(s, KU_RES0, a, kap, ctx->red, fin_sum(nullptr)));
+    TOPO_HIP(launch_ku(s, KU_RES0, a, kap, ctx->red, fin_sum(nullptr), L.shape));
     return TOPO_OK;
   }
   double rho_new = 1.0 / (2.0 * ch.sigma - rho);
@@ -611,12 +687,12 @@ static topo_status pre_smooth(topo_ctx *ctx, Level &L, const int *skip) {
     c.c1 = (T)(rho_new * rho);
     c.c2 = (T)(2.0 * rho_new / ch.delta);
     c.skip = skip;
-    TOPO_HIP(launch_ku(s, KU_CHEB, c, kap, ctx->red, fin_sum(nullptr)));
+    TOPO_HIP(launch_ku(s, KU_CHEB, c, kap, ctx->red, fin_sum(nullptr), L.shape));
   } else {
     a.dout = dcur;
     a.c1 = (T)(rho_new * rho);
     a.c2 = (T)(2.0 * rho_new / ch.delta);
-    TOPO_HIP(launch_ku(s, KU_CHEB0, a, kap, ctx->red, fin_sum(nullptr)));
+    TOPO_HIP(launch_ku(s, KU_CHEB0, a, kap, ctx->red, fin_sum(nullptr), L.shape));
   }
   rho = rho_new;
   for (int k = 2; k < deg; ++k) {
@@ -628,14 +704,14 @@ static topo_status pre_smooth(topo_ctx *ctx, Level &L, const int *skip) {
     c.c1 = (T)(rho_new * rho);
     c.c2 = (T)(2.0 * rho_new / ch.delta);
     c.skip = skip;
-    TOPO_HIP(launch_ku(s, KU_CHEB, c, kap, ctx->red, fin_sum(nullptr)));
+    TOPO_HIP(launch_ku(s, KU_CHEB, c, kap, ctx->red, fin_sum(nullptr), L.shape));
     std::swap(dcur, dnext);
     rho = rho_new;
   }
   KuArgsT<T> r = ku_args_t<T>(L, dcur);
   r.res = B.res;
   r.skip = skip;
-  TOPO_HIP(launch_ku(s, KU_RESUPD, r, kap, ctx->red, fin_sum(nullptr)));
+  TOPO_HIP(launch_ku(s, KU_RESUPD, r, kap, ctx->red, fin_sum(nullptr), L.shape));
   return TOPO_OK;
 }
 
@@ -657,7 +733,7 @@ static topo_status post_smooth(topo_ctx *ctx, Level &L, const int *skip, const T
   a.dout = dcur;
   a.s0 = (T)(1.0 / ch.theta);
   a.skip = skip;
-  TOPO_HIP(launch_ku(s, KU_RESID_START, a, kap, ctx->red, fin_sum(nullptr)));
+  TOPO_HIP(launch_ku(s, KU_RESID_START, a, kap, ctx->red, fin_sum(nullptr), L.shape));
   if (deg == 1) {
     TOPO_HIP(launch_cheb_start(s, L.g.ndof(), B.res, B.dinv, (T)(1.0 / ch.theta), dnext, B.x, skip));
     if (dot_with) {
@@ -676,7 +752,7 @@ static topo_status post_smooth(topo_ctx *ctx, Level &L, const int *skip, const T
     c.c2 = (T)(2.0 * rho_new / ch.delta);
     c.dot_with = (k == deg - 1) ? dot_with : nullptr;
     c.skip = skip;
-    TOPO_HIP(launch_ku(s, k == 1 ? KU_CHEB_ADD : KU_CHEB, c, kap, ctx->red, fin));
+    TOPO_HIP(launch_ku(s, k == 1 ? KU_CHEB_ADD : KU_CHEB, c, kap, ctx->red, fin, L.shape));
     std::swap(dcur, dnext);
     rho = rho_new;
   }
@@ -766,7 +842,7 @@ static topo_status cg_body(topo_ctx *ctx, int kind) {
   KuArgs a = ku_args(ctx, L0, ctx->p);
   a.y = ctx->q;
   a.skip = skip;
-  TOPO_HIP(launch_ku(s, KU_STORE_DOT, a, ctx->kap, ctx->red, fin_sum(&ctx->sc->pq)));
+  TOPO_HIP(launch_ku(s, KU_STORE_DOT, a, ctx->kap, ctx->red, fin_sum(&ctx->sc->pq), ctx->shape_cg));
   const Fin check{FIN_CG_CHECK, &ctx->sc->rr, ctx->sc};
   TOPO_HIP(launch_cg_update_xr(s, ctx->ndof, ctx->sc, ctx->u, ctx->r, ctx->p, ctx->q, ctx->red, check, skip));
   topo_status st = precondition(ctx, kind, skip);

@@ -88,3 +88,29 @@ def test_setup_rejects_bad_options():
                     ({"precond": 9}, "preconditioner"), ({"precision": 7}, "precision")]:
         st, err, _ = setup_status(p, **kw)
         assert st == _lib.TOPO_EINVAL and msg in err, (kw, err)
+
+
+def test_batch_and_network_entry_points_reject_invalid_arguments():
+    lib = pkg.load()
+    h = C.c_void_p()
+    o = pkg.default_opts()
+    st = lib.topo_setup_batch(None, 3, C.byref(o), 0, C.byref(h))
+    assert st == _lib.TOPO_EINVAL and "at least one problem" in lib.topo_last_error().decode()
+    p = synth.config_small()
+    pc, keep = _lib._problem_c(p)
+    arr = (_lib.Problem_C * 1)(pc)
+    st = lib.topo_setup_batch(arr, 1, C.byref(o), 100, C.byref(h))
+    assert st == _lib.TOPO_EINVAL and "n_threads" in lib.topo_last_error().decode()
+    st = lib.topo_iterate_batch(None, None, 1, None)
+    assert st == _lib.TOPO_EINVAL
+    bad = (C.c_int32 * 3)(16, 0, 64)
+    st = lib.topo_nn_create(bad, None, C.byref(h))
+    assert st == _lib.TOPO_EINVAL and "channel" in lib.topo_last_error().decode()
+    assert lib.topo_set_nn(None, None) == _lib.TOPO_EINVAL
+
+
+def test_default_train_opts():
+    t = pkg.default_train_opts()
+    assert (t.epochs, t.batch, t.lr, t.beta1, t.beta2, t.eps, t.loss) == (10, 4, 1e-3, 0.9, 0.999, 1e-8, pkg.LOSS_REL)
+    o = pkg.default_opts()
+    assert o.nn_max_iters == 200 and o.autotune == 0

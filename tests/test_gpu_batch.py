@@ -1,0 +1,61 @@
+"""Batched SIMP iterations: every problem of a batch ends exactly where its own
+single-problem run ends (same kernels, same order on its own stream), and the
+launch-shape autotuner changes nothing but rounding."""
+
+import numpy as np
+import pytest
+
+import synth
+
+torch = pytest.importorskip("torch")
+import paper_2504_05604_amd as topo  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+def problems():
+    out = []
+    for seed, nelx in [(0, 24), (1, 32), (2, 16), (3, 40), (4, 24), (5, 16)]:
+        out.append(synth.random_problem(seed, nelx, n_iter=4))
+    return out
+
+
+def run_single(p, opts, n_iter):
+    with topo.Context(p, opts) as ctx:
+        x = torch.from_numpy(p.initial_design()).to("cuda")
+        st = ctx.iterate(x, n_iter)
+        torch.cuda.synchronize()
+        return x.cpu().numpy(), [s["c"] for s in st]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_batch_equals_single_problem_runs(precision):
+    ps = problems()
+    opts = topo.default_opts(precision=topo.PREC_FP64 if precision == "fp64" else topo.PREC_FP32)
+    n_iter = 4
+    with topo.Batch(ps, opts, n_threads=4) as b:
+        xs = [torch.from_numpy(p.initial_design()).to("cuda") for p in ps]
+        stats = b.iterate(xs, n_iter)
+        torch.cuda.synchronize()
+        got = [x.cpu().numpy() for x in xs]
+    for i, p in enumerate(ps):
+        xr, cr = run_single(p, opts, n_iter)
+        assert np.array_equal(got[i], xr), i
+        assert [s["c"] for s in stats[i]] == cr, i
+
+
+def test_autotuned_shapes_change_only_rounding():
+    """Other launch shapes change reduction orders, hence the CG iterates at the
+    rounding level; solving to 1e-12 keeps the trajectories within 1e-9."""
+    ps = problems()[:3]
+    n_iter = 3
+    base = [run_single(p, topo.default_opts(rtol=1e-12), n_iter) for p in ps]
+    with topo.Batch(ps, topo.default_opts(autotune=1, rtol=1e-12), n_threads=3) as b:
+        xs = [torch.from_numpy(p.initial_design()).to("cuda") for p in ps]
+        stats = b.iterate(xs, n_iter)
+        torch.cuda.synchronize()
+        for i in range(len(ps)):
+            c = np.array([s["c"] for s in stats[i]])
+            cr = np.array(base[i][1])
+            assert np.abs(c - cr).max() <= 1e-9 * np.abs(cr).max(), i
+            assert np.abs(xs[i].cpu().numpy() - base[i][0]).max() <= 1e-7, i
