@@ -252,8 +252,7 @@ topo_status topo_iterate_batch(topo_batch *batch, double *const *d_x, int32_t n_
  * per layer its weight [c_out][c_in][taps] (taps z-major, then y, then x) and
  * its bias, in the order above; an up layer stores the weight of the stride-2
  * convolution it transposes, [c_coarse][c_fine][27], and a c_fine bias.  With
- * (16, 32, 64) channels there are 354611 parameters.  Network arithmetic is
- * FP32 with FP32 accumulation.
+ * (16, 32, 64) channels there are 354611 parameters.
  *
  * Network activations are channel-major over a batch: [C][batch][V] with
  * V = NX*NY*NZ nodes, x fastest (node numbering above).  nodes[3] = (NX, NY, NZ).
@@ -288,6 +287,11 @@ typedef struct {
  * weights; hip_stream as in topo_setup.  Errors: TOPO_EINVAL, TOPO_ENOMEM. */
 topo_status topo_nn_create(const int32_t channels[3], void *hip_stream, topo_nn **out);
 void topo_nn_destroy(topo_nn *nn);
+/* Arithmetic of the network's convolutions (forward, backward and inside the
+ * solver): TOPO_PREC_FP32 (default; FP32 operands and accumulation) or
+ * TOPO_PREC_BF16 (operands rounded to BF16 on the matrix cores, FP32
+ * accumulation; activations, gradients and master weights stay FP32). */
+topo_status topo_nn_set_precision(topo_nn *nn, int32_t precision);
 topo_status topo_nn_n_params(const topo_nn *nn, int64_t *n);
 /* Copies n = n_params FP32 parameters from the host (layout above) and resets
  * the Adam moments.  Synchronises. */

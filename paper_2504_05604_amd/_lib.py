@@ -27,7 +27,7 @@ EXPORTED = [
     "topo_default_opts", "topo_setup", "topo_destroy", "topo_last_error", "topo_sizes",
     "topo_apply_K", "topo_apply_precond", "topo_solve", "topo_sensitivity", "topo_filter", "topo_oc_update",
     "topo_iterate", "topo_get_state", "topo_time_operator",
-    "topo_nn_create", "topo_nn_destroy", "topo_nn_n_params", "topo_nn_set_weights", "topo_nn_get_weights",
+    "topo_nn_create", "topo_nn_destroy", "topo_nn_set_precision", "topo_nn_n_params", "topo_nn_set_weights", "topo_nn_get_weights",
     "topo_nn_forward", "topo_nn_loss_grad", "topo_default_train_opts", "topo_nn_train", "topo_set_nn",
     "topo_nn_make_pairs", "topo_setup_batch", "topo_destroy_batch", "topo_batch_context", "topo_iterate_batch",
 ]
@@ -128,6 +128,7 @@ def load(path: str = LIB_PATH):
     lib.topo_nn_destroy.argtypes = [vp]
     lib.topo_nn_destroy.restype = None
     lib.topo_nn_n_params.argtypes = [vp, C.POINTER(C.c_int64)]
+    lib.topo_nn_set_precision.argtypes = [vp, C.c_int32]
     lib.topo_nn_set_weights.argtypes = [vp, C.POINTER(C.c_float), C.c_int64]
     lib.topo_nn_get_weights.argtypes = [vp, C.POINTER(C.c_float), C.c_int64]
     lib.topo_nn_forward.argtypes = [vp, i32p, C.c_int32, fp, fp]
@@ -353,7 +354,7 @@ def default_train_opts(**kw) -> TrainOpts_C:
 class Network:
     """The convolutional preconditioner network; wraps a topo_nn."""
 
-    def __init__(self, channels=(16, 32, 64), stream=None):
+    def __init__(self, channels=(16, 32, 64), stream=None, precision=PREC_FP32):
         lib = load()
         self._lib = lib
         import torch
@@ -366,6 +367,11 @@ class Network:
         n = C.c_int64()
         _check(lib.topo_nn_n_params(self._h, C.byref(n)))
         self.n_params = n.value
+        self.set_precision(precision)
+
+    def set_precision(self, precision):
+        _check(self._lib.topo_nn_set_precision(self._h, precision))
+        self.precision = precision
 
     def close(self):
         if getattr(self, "_h", None):

@@ -84,6 +84,12 @@ static topo_status prepare_impl(const int c[3], NnWork &w, Dim3 g0, int B, bool 
   return TOPO_OK;
 }
 
+static hipError_t run_gemm(const topo_nn *nn, hipStream_t s, int mode, const GemmArgs &a, float *split,
+                           int64_t cap) {
+  return nn->precision == TOPO_PREC_BF16 ? launch_igemm_bf16(s, mode, a, split, cap)
+                                         : launch_igemm(s, mode, a, split, cap);
+}
+
 static GemmArgs gemm(int M, int N, int K, const float *A, int64_t sam, int64_t sak, const float *src,
                      ConvGeo geo, float *C, const float *bias, bool relu, bool acc, const int *skip) {
   GemmArgs a{};
@@ -112,7 +118,7 @@ static hipError_t conv_fwd(const topo_nn *nn, int L, hipStream_t s, int B, Dim3 
   const int K = l.ci * 27;
   const GemmArgs a = gemm(l.co, (int)(B * go.count()), K, nn->W + l.w_off, K, 1, x, ConvGeo{B, gi, go, stride},
                           y, nn->W + l.b_off, relu, false, skip);
-  return launch_igemm(s, GB_CONV, a, nullptr, 0);
+  return run_gemm(nn, s, GB_CONV, a, nullptr, 0);
 }
 
 // y = conv_2^T(x; layer) + b: x on the coarse grid (co channels), y on gf (ci channels)
@@ -122,7 +128,7 @@ static hipError_t up_fwd(const topo_nn *nn, int L, hipStream_t s, int B, Dim3 gf
   const int K = l.co * 27;
   const GemmArgs a = gemm(l.ci, (int)(B * gf.count()), K, nn->WT + l.w_off, K, 1, x,
                           ConvGeo{B, gf, half_up(gf), 2}, y, nn->W + l.b_off, false, false, skip);
-  return launch_igemm(s, GB_CONVT, a, nullptr, 0);
+  return run_gemm(nn, s, GB_CONVT, a, nullptr, 0);
 }
 
 }  // namespace topo
@@ -164,7 +170,7 @@ topo_status nn_forward(topo_nn *nn, NnWork &w, hipStream_t s, const int *skip) {
   const NnLayer &h = nn->layer[L_HEAD];
   const GemmArgs a = gemm(3, (int)N0, c0, nn->W + h.w_off, c0, 1, w.t0, ConvGeo{B, w.g0, w.g0, 1}, w.out,
                           nn->W + h.b_off, false, false, skip);
-  NN_HIP(launch_igemm(s, GB_PLAIN, a, nullptr, 0));
+  NN_HIP(run_gemm(nn, s, GB_PLAIN, a, nullptr, 0));
   return TOPO_OK;
 }
 
@@ -177,12 +183,12 @@ static topo_status conv_back(topo_nn *nn, NnWork &w, int L, hipStream_t s, Dim3 
   const Dim3 go = stride == 2 ? half_up(gi) : gi;
   const int Ko = (int)(B * go.count()), Ni = (int)(B * gi.count());
   const ConvGeo geo{B, gi, go, stride};
-  NN_HIP(launch_igemm(s, GB_WGRAD, gemm(l.co, l.ci * 27, Ko, dy, Ko, 1, x, geo, nn->G + l.w_off, nullptr, false,
+  NN_HIP(run_gemm(nn, s, GB_WGRAD, gemm(l.co, l.ci * 27, Ko, dy, Ko, 1, x, geo, nn->G + l.w_off, nullptr, false,
                                         false, nullptr),
                       w.split, w.split_cap));
   NN_HIP(launch_bias_grad(s, l.co, Ko, dy, nn->G + l.b_off));
   if (dx)
-    NN_HIP(launch_igemm(s, GB_CONVT, gemm(l.ci, Ni, l.co * 27, nn->WT + l.w_off, l.co * 27, 1, dy, geo, dx,
+    NN_HIP(run_gemm(nn, s, GB_CONVT, gemm(l.ci, Ni, l.co * 27, nn->WT + l.w_off, l.co * 27, 1, dy, geo, dx,
                                           nullptr, false, acc, nullptr),
                         nullptr, 0));
   return TOPO_OK;
@@ -196,11 +202,11 @@ static topo_status up_back(topo_nn *nn, NnWork &w, int L, hipStream_t s, Dim3 gf
   const Dim3 gc = half_up(gf);
   const int Kc = (int)(B * gc.count()), Nf = (int)(B * gf.count());
   const ConvGeo geo{B, gf, gc, 2};
-  NN_HIP(launch_igemm(s, GB_WGRAD, gemm(l.co, l.ci * 27, Kc, xc, Kc, 1, dy, geo, nn->G + l.w_off, nullptr, false,
+  NN_HIP(run_gemm(nn, s, GB_WGRAD, gemm(l.co, l.ci * 27, Kc, xc, Kc, 1, dy, geo, nn->G + l.w_off, nullptr, false,
                                         false, nullptr),
                       w.split, w.split_cap));
   NN_HIP(launch_bias_grad(s, l.ci, Nf, dy, nn->G + l.b_off));
-  NN_HIP(launch_igemm(s, GB_CONV, gemm(l.co, Kc, l.ci * 27, nn->W + l.w_off, l.ci * 27, 1, dy, geo, dxc, nullptr,
+  NN_HIP(run_gemm(nn, s, GB_CONV, gemm(l.co, Kc, l.ci * 27, nn->W + l.w_off, l.ci * 27, 1, dy, geo, dxc, nullptr,
                                        false, false, nullptr),
                       nullptr, 0));
   return TOPO_OK;
@@ -217,11 +223,11 @@ topo_status nn_backward(topo_nn *nn, NnWork &w, hipStream_t s) {
   {
     const NnLayer &h = nn->layer[L_HEAD];
     const ConvGeo geo{B, w.g0, w.g0, 1};
-    NN_HIP(launch_igemm(s, GB_PLAINT, gemm(3, c0, (int)N0, w.dout, N0, 1, w.t0, geo, nn->G + h.w_off, nullptr,
+    NN_HIP(run_gemm(nn, s, GB_PLAINT, gemm(3, c0, (int)N0, w.dout, N0, 1, w.t0, geo, nn->G + h.w_off, nullptr,
                                            false, false, nullptr),
                         w.split, w.split_cap));
     NN_HIP(launch_bias_grad(s, 3, N0, w.dout, nn->G + h.b_off));
-    NN_HIP(launch_igemm(s, GB_PLAIN, gemm(c0, (int)N0, 3, nn->W + h.w_off, 1, c0, w.dout, geo, w.dt0, nullptr,
+    NN_HIP(run_gemm(nn, s, GB_PLAIN, gemm(c0, (int)N0, 3, nn->W + h.w_off, 1, c0, w.dout, geo, w.dt0, nullptr,
                                           false, false, nullptr),
                         nullptr, 0));
   }
@@ -309,6 +315,14 @@ extern "C" topo_status topo_nn_create(const int32_t channels[3], void *hip_strea
 }
 
 extern "C" void topo_nn_destroy(topo_nn *nn) { delete nn; }
+
+extern "C" topo_status topo_nn_set_precision(topo_nn *nn, int32_t precision) {
+  if (!nn) return set_error("NULL argument"), TOPO_EINVAL;
+  if (precision != TOPO_PREC_FP32 && precision != TOPO_PREC_BF16)
+    return set_error("network precision must be TOPO_PREC_FP32 or TOPO_PREC_BF16"), TOPO_EINVAL;
+  nn->precision = precision;
+  return TOPO_OK;
+}
 
 extern "C" topo_status topo_nn_n_params(const topo_nn *nn, int64_t *n) {
   if (!nn || !n) return set_error("NULL argument"), TOPO_EINVAL;

@@ -50,6 +50,8 @@ struct GemmArgs {
 // split_buf (split_cap floats) enables a split reduction over long K (weight
 // gradients); NULL runs unsplit.
 hipError_t launch_igemm(hipStream_t s, int mode, const GemmArgs &a, float *split_buf, int64_t split_cap);
+// the same product with operands rounded to BF16 on the matrix cores (FP32 accumulation)
+hipError_t launch_igemm_bf16(hipStream_t s, int mode, const GemmArgs &a, float *split_buf, int64_t split_cap);
 
 // WT[ci][co*taps + t] = W[co][ci*taps + t]
 hipError_t launch_transpose_w(hipStream_t s, int co, int ci, int taps, const float *W, float *WT);
@@ -128,6 +130,7 @@ struct topo_nn {
   int64_t nparams = 0;
   float *W = nullptr, *WT = nullptr, *G = nullptr, *m = nullptr, *v = nullptr;
   int adam_step = 0;
+  int precision = TOPO_PREC_FP32;  // arithmetic of the convolutions: FP32 or BF16 operands
   topo::Reducer red{};
   topo::NnWork work;  // workspace of the API calls
   std::vector<void *> allocs;

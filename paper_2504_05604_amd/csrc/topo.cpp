@@ -204,6 +204,7 @@ struct topo_ctx {
   // learned preconditioner
   int shape_cg = -1;                 // K.u launch shape of the CG product (-1: by grid size)
   topo_nn *nn = nullptr;
+  int nn_graph_precision = -1;       // network precision the captured learned chunk uses
   NnWork nnw;                        // activations (batch 1) on the node grid
   double *nn_scale = nullptr;        // rms of the residual of the current application
   double *ustar = nullptr;           // training-pair generation: converged solution
@@ -863,7 +864,14 @@ static topo_status cg_chunk(topo_ctx *ctx, int kind) {
     }
     return TOPO_OK;
   }
+  if (kind == TOPO_PRECOND_LEARNED && ctx->cg_exec[kind] && ctx->nn_graph_precision != ctx->nn->precision) {
+    (void)hipGraphExecDestroy(ctx->cg_exec[kind]);
+    (void)hipGraphDestroy(ctx->cg_graph[kind]);
+    ctx->cg_exec[kind] = nullptr;
+    ctx->cg_graph[kind] = nullptr;
+  }
   if (!ctx->cg_exec[kind]) {
+    if (kind == TOPO_PRECOND_LEARNED) ctx->nn_graph_precision = ctx->nn->precision;
     hipStream_t user = ctx->stream;
     ctx->stream = ctx->cap_stream;
     TOPO_HIP(hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeRelaxed));

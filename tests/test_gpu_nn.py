@@ -60,6 +60,32 @@ def test_forward_matches_oracle(ch, nodes, batch):
         assert np.abs(got[:, b] - ref).max() <= 2e-4 * np.abs(ref).max(), b
 
 
+@pytest.mark.parametrize("ch,nodes,batch", [
+    ((16, 32, 64), (9, 7, 6), 1),
+    ((16, 32, 64), (21, 11, 13), 2),
+    ((3, 5, 7), (6, 9, 5), 3),
+])
+def test_bf16_forward_matches_oracle(ch, nodes, batch):
+    """BF16 operands (8-bit mantissa, relative rounding 2^-9) with FP32
+    accumulation: each layer's output carries a relative error of about
+    2^-9 sqrt(#layers); compared at 3e-2 of the output scale."""
+    blob = networks.init_weights(ch, seed=1)
+    x = networks.random_activations(2, 4, batch, nodes)
+    net = topo.Network(ch, precision=topo.PREC_BF16)
+    net.set_weights(blob)
+    V = int(np.prod(nodes))
+    out = torch.empty(3 * batch * V, dtype=torch.float32, device="cuda")
+    net.forward(nodes, batch, dev(x.reshape(-1)), out)
+    got = host(out).reshape(3, batch, nodes[2], nodes[1], nodes[0])
+    P = oracle_params(blob, ch)
+    for b in range(batch):
+        ref = nn.forward(P, x[:, b].astype(np.float64))
+        err = np.abs(got[:, b] - ref).max() / np.abs(ref).max()
+        rel2 = np.linalg.norm(got[:, b] - ref) / np.linalg.norm(ref)
+        print("bf16 forward max err", err, "rel2", rel2)
+        assert err <= 3e-2 and rel2 <= 1e-2, b
+
+
 def node_fixed_bits(fixed_mask_dof):
     m = fixed_mask_dof.reshape(-1, 3)
     return (m[:, 0] * 1 + m[:, 1] * 2 + m[:, 2] * 4).astype(np.uint8)
@@ -108,8 +134,52 @@ def test_loss_gradient_matches_oracle(nodes, batch, mode):
     for name, wshape, nb in networks.layer_shapes(ch):
         k = int(np.prod(wshape)) + nb
         a, b = g[off:off + k], ref_g[off:off + k]
+        print("fp32 grad", mode, name, np.linalg.norm(a - b) / np.linalg.norm(b))
         assert np.linalg.norm(a - b) <= 1e-3 * np.linalg.norm(b), name
         off += k
+
+
+@pytest.mark.parametrize("mode", ["rel", "cos"])
+def test_bf16_loss_gradient_matches_oracle(mode):
+    """BF16 products in every backward GEMM.  The parameter gradients of a
+    random-initialised network are sums with heavy cancellation, so their
+    relative error is the operand rounding (2^-9, 2^15 times FP32's) amplified
+    by the cancellation; the FP32 kernels show about 1e-6 per layer on this case,
+    so BF16 is held to 0.15 per layer in the relative 2-norm, and to a cosine of
+    at least 0.995 between the whole gradient vectors."""
+    ch = (16, 32, 64)
+    nodes, batch = (13, 7, 9), 3
+    blob = networks.init_weights(ch, seed=3)
+    n = batch + 1
+    rho, r, e, fixed = random_samples(4, n, nodes)
+    index = np.arange(1, n)[:batch]
+    net = topo.Network(ch, precision=topo.PREC_BF16)
+    net.set_weights(blob)
+    grad = torch.empty(net.n_params, dtype=torch.float32, device="cuda")
+    bits = np.stack([node_fixed_bits(f) for f in fixed])
+    loss = net.loss_grad(nodes, dev(rho.reshape(-1)), dev(r.reshape(-1)), dev(e.reshape(-1)),
+                         dev(bits.reshape(-1), torch.uint8), index, grad,
+                         loss=topo.LOSS_REL if mode == "rel" else topo.LOSS_COS)
+    g = host(grad)
+    P = oracle_params(blob, ch)
+    shape = (nodes[2], nodes[1], nodes[0])
+    ref_loss, ref_g = 0.0, 0.0
+    for i in index:
+        l, gi = nn.loss_and_grad(P, rho[i].astype(np.float64).reshape(shape), r[i].astype(np.float64),
+                                 e[i].astype(np.float64), fixed[i], mode)
+        ref_loss += l / batch
+        ref_g = ref_g + nn.pack(gi, ch) / batch
+    assert abs(loss - ref_loss) <= 1e-2 * abs(ref_loss)
+    off = 0
+    for name, wshape, nb in networks.layer_shapes(ch):
+        k = int(np.prod(wshape)) + nb
+        a, b = g[off:off + k], ref_g[off:off + k]
+        print("bf16 grad", mode, name, np.linalg.norm(a - b) / np.linalg.norm(b))
+        assert np.linalg.norm(a - b) <= 0.15 * np.linalg.norm(b), name
+        off += k
+    cos = float(g @ ref_g) / (np.linalg.norm(g) * np.linalg.norm(ref_g))
+    print("bf16 grad cosine", mode, cos)
+    assert cos >= 0.995
 
 
 def test_adam_step_matches_oracle_gradient():
