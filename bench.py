@@ -224,6 +224,8 @@ def main():
     ap.add_argument("--no-graphs", action="store_true")
     ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64",
                     help="precision of the multigrid preconditioner (CG stays FP64)")
+    ap.add_argument("--tail-nodes", type=int, default=1024,
+                    help="levels with at most this many nodes run as one single-workgroup launch (0 = off)")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-vs-multigrid leg")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-problems leg")
     ap.add_argument("--batch-size", type=int, default=64)
@@ -247,7 +249,7 @@ def main():
     p = synth.config_large()
     opts = topo.default_opts(rtol=1e-8, max_iters=2000, cheb_degree=args.cheb_degree,
                              mg_max_coarse_dof=args.coarse_dof, check_every=args.check_every,
-                             use_graphs=0 if args.no_graphs else 1,
+                             use_graphs=0 if args.no_graphs else 1, coarse_tail_nodes=args.tail_nodes,
                              precision=topo.PREC_FP64 if args.precision == "fp64" else topo.PREC_FP32,
                              precond=topo.PRECOND_MG if args.precond == "mg" else topo.PRECOND_JACOBI)
     ctx = topo.Context(p, opts)
@@ -297,6 +299,7 @@ def main():
             "nel": p.nel, "ndof": p.ndof, "precond": args.precond, "mg_levels": ctx.mg_levels,
             "cheb_degree": deg, "rtol": 1e-8, "warm_start": True, "coarse_dof_cap": args.coarse_dof,
             "check_every": args.check_every, "graphs": not args.no_graphs,
+            "coarse_tail_nodes": args.tail_nodes,
             "preconditioner_precision": args.precision,
             "pcg_iters_mean": round(float(pcg.mean()), 2), "pcg_iters_max": int(pcg.max()),
             "solve_ms_mean": round(float(solve_ms.mean()), 3),

@@ -108,6 +108,8 @@ typedef struct {
                                  on the multigrid preconditioner                       */
   int32_t autotune;           /* time every K.u launch shape on this problem's grids at
                                  setup and keep the fastest (else chosen by grid size)   */
+  int32_t coarse_tail_nodes;  /* multigrid levels (below the finest) with at most this many
+                                 nodes run as one single-workgroup launch; 0 = off        */
 } topo_opts;
 
 typedef struct {
@@ -132,7 +134,7 @@ typedef struct {
 
 /* Fills *opts with defaults: FP64, MG, automatic depth (coarsest <= 140 dofs),
  * Chebyshev degree 2, rtol 1e-8, max_iters 1000, warm start, oc_tol 1e-12,
- * check_every 4, use_graphs 1, nn_max_iters 200, autotune 0. */
+ * check_every 4, use_graphs 1, nn_max_iters 200, autotune 0, coarse_tail_nodes 1024. */
 void topo_default_opts(topo_opts *opts);
 
 /* Validates the problem, copies its arrays to the device, builds the element

@@ -67,8 +67,11 @@ struct Scalars {
   double oc_lam[64];
 };
 
+// the 10 distinct values of the element matrix (their placement: ke_code.h)
 template <typename T>
-struct KappaT;  // ke_code.h
+struct KappaT {
+  T k[10];
+};
 using Kappa = KappaT<double>;
 
 // ---------------------------------------------------------------------------
@@ -202,6 +205,44 @@ hipError_t launch_dense_matvec(hipStream_t s, int n, const double *A, const doub
                                const int *skip = nullptr);
 hipError_t launch_dense_matvec(hipStream_t s, int n, const float *A, const float *x, float *y,
                                const int *skip = nullptr);
+
+// The coarse end of the V-cycle in one workgroup (kernels_tail.hip): levels
+// L[0] (finest of the tail) .. L[nlev-1] (coarsest, solved with Ainv).
+template <typename T>
+struct TailLevel {
+  Grid g;
+  const T *E;              // moduli incl. the level's stiffness scale
+  const T *dinv;           // inverse Jacobi diagonal (0 on fixed dofs)
+  const uint8_t *fixed;    // per node, bit c = dof c fixed
+  T *b, *x, *res, *d0, *d1;
+};
+constexpr int kTailMaxLevels = 8;
+constexpr int kTailMaxDeg = 17;
+constexpr int kTailThreads = 512;
+template <typename T>
+struct TailArgs {
+  int nlev;
+  TailLevel<T> L[kTailMaxLevels];
+  const T *Ainv;                       // dense inverse of the coarsest operator (ncoarse^2)
+  int ncoarse;
+  KappaT<T> kap;                       // element matrix values (see ke_code.h)
+  int deg;                             // Chebyshev degree per smoothing
+  T s0;                                // 1 / theta
+  T c1[kTailMaxDeg], c2[kTailMaxDeg];  // step k: d_k = c1[k] d_{k-1} + c2[k] D^-1 r
+  const int *skip;
+};
+// LDS bytes of the tail, per level E | dinv | b | x | res | d0 | d1 | fixed
+// (16-byte aligned)
+constexpr size_t kTailMaxLds = 158 * 1024;  // dynamic part; the kernel adds < 1 KB of static LDS
+template <typename T>
+__host__ __device__ inline size_t tail_level_bytes(const Grid &g) {
+  return (size_t)(g.nel() + 6 * g.ndof()) * sizeof(T) + (size_t)((g.nnodes() + 15) / 16) * 16;
+}
+template <typename T>
+hipError_t launch_vcycle_tail_t(hipStream_t s, const TailArgs<T> &a);
+// raises the kernel's dynamic LDS limit (call once before launching)
+template <typename T>
+hipError_t prepare_vcycle_tail_t(size_t smem_bytes);
 
 // sensitivities: ce = u_e^T KE u_e, dc = -p xphys^(p-1) (E0-Emin) ce
 hipError_t launch_sensitivity(hipStream_t s, Grid g, const Kappa &kap, const double *u,

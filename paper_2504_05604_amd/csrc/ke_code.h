@@ -78,11 +78,6 @@ __host__ __device__ constexpr KeTable make_ke_table() {
 constexpr KeTable kKeTable = make_ke_table();
 static_assert(kKeTable.npairs == 10, "the H8 stiffness has 10 distinct entries up to sign");
 
-template <typename T>
-struct KappaT {
-  T k[10];
-};
-
 __host__ __device__ constexpr double ke_sign(int I, int J) { return kKeTable.sign[I * 24 + J]; }
 __host__ __device__ constexpr int ke_idx(int I, int J) { return kKeTable.idx[I * 24 + J]; }
 

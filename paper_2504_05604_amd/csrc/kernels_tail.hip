@@ -1,0 +1,303 @@
+// The coarse end of the multigrid V-cycle in one launch.
+//
+// Below a thousand or so nodes a level's smoothing pass, transfer or dense solve
+// is far too small to fill the device, and launching each of them separately
+// costs more than the work.  Here one workgroup walks the whole tail of the
+// hierarchy (pre-smoothing and restriction down to the coarsest level, the
+// dense solve, prolongation and post-smoothing back up), with a workgroup
+// barrier between passes.  Each pass is the same arithmetic as the
+// corresponding multi-block kernels, written per node: the operator gathers
+// the up to 8 elements around the node and applies the 24 x 24 element matrix
+// to each element's displacement vector.
+#include "internal.h"
+#include "ke_code.h"
+
+namespace topo {
+
+namespace {
+
+// y = (A u) at the three dofs of node (i, j, k), free rows only (every operand
+// is zero on fixed dofs; callers handle fixed rows).  The 3x3x3 neighbourhood
+// of u is gathered into registers once; the element matrix entries are the
+// compile-time sign/index tables applied to kappa (kernel arguments, i.e.
+// scalar registers), so the 576 multiply-adds read no memory.
+template <typename T>
+__device__ __forceinline__ void node_apply(const Grid &g, const T *__restrict__ E, const KappaT<T> &kap,
+                                           const T *__restrict__ u, int i, int j, int k, T y[3]) {
+  T U[27][3];
+#pragma unroll
+  for (int q = 0; q < 27; ++q) {
+    const int ii = i + q % 3 - 1, jj = j + (q / 3) % 3 - 1, kk = k + q / 9 - 1;
+    const bool in = ii >= 0 && ii <= g.nx && jj >= 0 && jj <= g.ny && kk >= 0 && kk <= g.nz;
+    const int64_t m = in ? ii + (int64_t)g.NX() * (jj + (int64_t)g.NY() * kk) : 0;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) U[q][d] = in ? u[3 * m + d] : T(0);
+  }
+  y[0] = y[1] = y[2] = T(0);
+#pragma unroll
+  for (int e8 = 0; e8 < 8; ++e8) {
+    const int ex = e8 & 1, ey = (e8 >> 1) & 1, ez = e8 >> 2;
+    const int ei = i - 1 + ex, ej = j - 1 + ey, ek = k - 1 + ez;
+    if (ei < 0 || ei >= g.nx || ej < 0 || ej >= g.ny || ek < 0 || ek >= g.nz) continue;
+    const int a = corner_of(1 - ex, 1 - ey, 1 - ez);  // this node's corner in the element
+    const T Ee = E[ei + (int64_t)g.nx * (ej + (int64_t)g.ny * ek)];
+    T t[3] = {T(0), T(0), T(0)};
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      // corner b of the element sits at offset (ex-1+cx, ey-1+cy, ez-1+cz) from the node
+      const int q = (ex + cx(b)) + 3 * (ey + cy(b)) + 9 * (ez + cz(b));
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int d = 0; d < 3; ++d) t[c] = fma(TOPO_KE(kap, 3 * a + c, 3 * b + d), U[q][d], t[c]);
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) y[c] = fma(Ee, t[c], y[c]);
+  }
+}
+
+__device__ __forceinline__ void node_ijk(const Grid &g, int n, int &i, int &j, int &k) {
+  i = n % g.NX();
+  j = (n / g.NX()) % g.NY();
+  k = n / (g.NX() * g.NY());
+}
+
+// pre-smoothing from x = 0: on exit x and res = b - A x
+template <typename T>
+__device__ void pre_smooth(const TailArgs<T> &a, const TailLevel<T> &L) {
+  const Grid &g = L.g;
+  const int nn = (int)g.nnodes();
+  for (int d = threadIdx.x; d < 3 * nn; d += blockDim.x) {
+    const T v = L.b[d] * L.dinv[d] * a.s0;
+    L.d0[d] = v;
+    L.x[d] = v;
+    L.res[d] = L.b[d];
+  }
+  __syncthreads();
+  T *dc = L.d0, *dn = L.d1;
+  for (int s = 1; s <= a.deg; ++s) {
+    const bool last = s == a.deg;
+    for (int n = threadIdx.x; n < nn; n += blockDim.x) {
+      int i, j, k;
+      node_ijk(g, n, i, j, k);
+      T y[3];
+      node_apply(g, L.E, a.kap, dc, i, j, k, y);
+      const uint8_t f = L.fixed[n];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const int d = 3 * n + c;
+        const T r = ((f >> c) & 1) ? T(0) : L.res[d] - y[c];
+        L.res[d] = r;
+        if (!last) {
+          const T step = a.c1[s] * dc[d] + a.c2[s] * L.dinv[d] * r;
+          dn[d] = step;
+          L.x[d] += step;
+        }
+      }
+    }
+    __syncthreads();
+    T *t = dc;
+    dc = dn;
+    dn = t;
+  }
+}
+
+// post-smoothing from the current x
+template <typename T>
+__device__ void post_smooth(const TailArgs<T> &a, const TailLevel<T> &L) {
+  const Grid &g = L.g;
+  const int nn = (int)g.nnodes();
+  // res = b - A x; d0 = D^-1 res / theta (added to x together with the next step)
+  for (int n = threadIdx.x; n < nn; n += blockDim.x) {
+    int i, j, k;
+    node_ijk(g, n, i, j, k);
+    T y[3];
+    node_apply(g, L.E, a.kap, L.x, i, j, k, y);
+    const uint8_t f = L.fixed[n];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const int d = 3 * n + c;
+      const T r = ((f >> c) & 1) ? T(0) : L.b[d] - y[c];
+      L.res[d] = r;
+      L.d0[d] = r * L.dinv[d] * a.s0;
+    }
+  }
+  __syncthreads();
+  if (a.deg == 1) {
+    for (int d = threadIdx.x; d < 3 * nn; d += blockDim.x) L.x[d] += L.d0[d];
+    __syncthreads();
+    return;
+  }
+  T *dc = L.d0, *dn = L.d1;
+  for (int s = 1; s < a.deg; ++s) {
+    for (int n = threadIdx.x; n < nn; n += blockDim.x) {
+      int i, j, k;
+      node_ijk(g, n, i, j, k);
+      T y[3];
+      node_apply(g, L.E, a.kap, dc, i, j, k, y);
+      const uint8_t f = L.fixed[n];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const int d = 3 * n + c;
+        const T r = ((f >> c) & 1) ? T(0) : L.res[d] - y[c];
+        L.res[d] = r;
+        const T step = a.c1[s] * dc[d] + a.c2[s] * L.dinv[d] * r;
+        dn[d] = step;
+        L.x[d] += (s == 1) ? dc[d] + step : step;
+      }
+    }
+    __syncthreads();
+    T *t = dc;
+    dc = dn;
+    dn = t;
+  }
+}
+
+template <typename T>
+__device__ void restrict_to(const TailLevel<T> &F, const TailLevel<T> &Cl) {
+  const Grid &gf = F.g, &gc = Cl.g;
+  const int nc = (int)gc.nnodes();
+  for (int m = threadIdx.x; m < nc; m += blockDim.x) {
+    int I, J, K;
+    node_ijk(gc, m, I, J, K);
+    T s0 = 0, s1 = 0, s2 = 0;
+    for (int dz = -1; dz <= 1; ++dz) {
+      const int k = 2 * K + dz;
+      if (k < 0 || k > gf.nz) continue;
+      for (int dy = -1; dy <= 1; ++dy) {
+        const int j = 2 * J + dy;
+        if (j < 0 || j > gf.ny) continue;
+        for (int dx = -1; dx <= 1; ++dx) {
+          const int i = 2 * I + dx;
+          if (i < 0 || i > gf.nx) continue;
+          const T w = (T)(dx ? 0.5 : 1.0) * (dy ? 0.5 : 1.0) * (dz ? 0.5 : 1.0);
+          const int64_t n = i + (int64_t)gf.NX() * (j + (int64_t)gf.NY() * k);
+          s0 = fma(w, F.res[3 * n + 0], s0);
+          s1 = fma(w, F.res[3 * n + 1], s1);
+          s2 = fma(w, F.res[3 * n + 2], s2);
+        }
+      }
+    }
+    const uint8_t f = Cl.fixed[m];
+    Cl.b[3 * m + 0] = (f & 1) ? T(0) : s0;
+    Cl.b[3 * m + 1] = (f & 2) ? T(0) : s1;
+    Cl.b[3 * m + 2] = (f & 4) ? T(0) : s2;
+  }
+  __syncthreads();
+}
+
+template <typename T>
+__device__ void prolong_add(const TailLevel<T> &F, const TailLevel<T> &Cl) {
+  const Grid &gf = F.g, &gc = Cl.g;
+  const int nf = (int)gf.nnodes();
+  for (int n = threadIdx.x; n < nf; n += blockDim.x) {
+    int i, j, k;
+    node_ijk(gf, n, i, j, k);
+    const int I0 = i >> 1, J0 = j >> 1, K0 = k >> 1;
+    const int ni = (i & 1) ? 2 : 1, nj = (j & 1) ? 2 : 1, nk = (k & 1) ? 2 : 1;
+    const T w = ((i & 1) ? T(0.5) : T(1)) * ((j & 1) ? T(0.5) : T(1)) * ((k & 1) ? T(0.5) : T(1));
+    T s0 = 0, s1 = 0, s2 = 0;
+    for (int c = 0; c < nk; ++c)
+      for (int b = 0; b < nj; ++b)
+        for (int a = 0; a < ni; ++a) {
+          const int64_t m = (I0 + a) + (int64_t)gc.NX() * ((J0 + b) + (int64_t)gc.NY() * (K0 + c));
+          s0 += Cl.x[3 * m + 0];
+          s1 += Cl.x[3 * m + 1];
+          s2 += Cl.x[3 * m + 2];
+        }
+    const uint8_t f = F.fixed[n];
+    if (!(f & 1)) F.x[3 * n + 0] = fma(w, s0, F.x[3 * n + 0]);
+    if (!(f & 2)) F.x[3 * n + 1] = fma(w, s1, F.x[3 * n + 1]);
+    if (!(f & 4)) F.x[3 * n + 2] = fma(w, s2, F.x[3 * n + 2]);
+  }
+  __syncthreads();
+}
+
+}  // namespace
+
+// Every vector, modulus and flag of the tail lives in LDS for the whole launch
+// (layout per level: E | dinv | b | x | res | d0 | d1 | fixed); only the first level's right-hand side comes in from global memory
+// and its correction x goes back out.
+template <typename T>
+__global__ __launch_bounds__(kTailThreads) void vcycle_tail_kernel(TailArgs<T> a) {
+  if (a.skip && *a.skip) return;
+  extern __shared__ __attribute__((aligned(16))) unsigned char tail_smem[];
+  // level descriptors pointing into LDS (kept in LDS too: indexed at run time)
+  __shared__ TailLevel<T> L[kTailMaxLevels];
+  if (threadIdx.x == 0) {
+    size_t off = 0;
+    for (int l = 0; l < a.nlev; ++l) {
+      const Grid g = a.L[l].g;
+      const int64_t nd = g.ndof(), ne = g.nel();
+      T *base = reinterpret_cast<T *>(tail_smem + off);
+      TailLevel<T> d;
+      d.g = g;
+      d.E = base;
+      d.dinv = base + ne;
+      d.b = base + ne + nd;
+      d.x = d.b + nd;
+      d.res = d.x + nd;
+      d.d0 = d.res + nd;
+      d.d1 = d.d0 + nd;
+      d.fixed = reinterpret_cast<const uint8_t *>(d.d1 + nd);
+      L[l] = d;
+      off += tail_level_bytes<T>(g);
+    }
+  }
+  __syncthreads();
+  for (int l = 0; l < a.nlev; ++l) {
+    const TailLevel<T> &G = a.L[l];
+    const int64_t nd = G.g.ndof(), ne = G.g.nel(), nn = G.g.nnodes();
+    T *E = const_cast<T *>(L[l].E), *dinv = const_cast<T *>(L[l].dinv);
+    uint8_t *fx = const_cast<uint8_t *>(L[l].fixed);
+    for (int64_t q = threadIdx.x; q < ne; q += blockDim.x) E[q] = G.E[q];
+    for (int64_t q = threadIdx.x; q < nd; q += blockDim.x) dinv[q] = G.dinv[q];
+    for (int64_t q = threadIdx.x; q < nn; q += blockDim.x) fx[q] = G.fixed[q];
+    if (l == 0)
+      for (int64_t q = threadIdx.x; q < nd; q += blockDim.x) L[0].b[q] = G.b[q];
+  }
+  __syncthreads();
+  const int last = a.nlev - 1;
+  for (int l = 0; l < last; ++l) {
+    pre_smooth(a, L[l]);
+    restrict_to(L[l], L[l + 1]);
+  }
+  // coarsest level: x = Ainv b
+  {
+    const TailLevel<T> &C = L[last];
+    for (int r = threadIdx.x; r < a.ncoarse; r += blockDim.x) {
+      T t = 0;
+      for (int c = 0; c < a.ncoarse; ++c) t = fma(a.Ainv[(int64_t)r * a.ncoarse + c], C.b[c], t);
+      C.x[r] = t;
+    }
+    __syncthreads();
+  }
+  for (int l = last - 1; l >= 0; --l) {
+    prolong_add(L[l], L[l + 1]);
+    post_smooth(a, L[l]);
+  }
+  for (int64_t q = threadIdx.x; q < a.L[0].g.ndof(); q += blockDim.x) a.L[0].x[q] = L[0].x[q];
+}
+
+template <typename T>
+hipError_t prepare_vcycle_tail_t(size_t smem_bytes) {
+  return hipFuncSetAttribute((const void *)vcycle_tail_kernel<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)smem_bytes);
+}
+
+template <typename T>
+hipError_t launch_vcycle_tail_t(hipStream_t s, const TailArgs<T> &a) {
+  if (a.nlev < 1 || a.nlev > kTailMaxLevels || a.deg < 1 || a.deg >= kTailMaxDeg) return hipErrorInvalidValue;
+  size_t bytes = 0;
+  for (int l = 0; l < a.nlev; ++l) bytes += tail_level_bytes<T>(a.L[l].g);
+  if (bytes > kTailMaxLds) return hipErrorInvalidValue;
+  vcycle_tail_kernel<T><<<1, kTailThreads, bytes, s>>>(a);
+  return hipGetLastError();
+}
+
+template hipError_t launch_vcycle_tail_t<double>(hipStream_t, const TailArgs<double> &);
+template hipError_t launch_vcycle_tail_t<float>(hipStream_t, const TailArgs<float> &);
+template hipError_t prepare_vcycle_tail_t<double>(size_t);
+template hipError_t prepare_vcycle_tail_t<float>(size_t);
+
+}  // namespace topo

@@ -203,6 +203,7 @@ struct topo_ctx {
   hipGraphExec_t cg_exec[3] = {};    // chunk of CG iterations, per preconditioner kind
   // learned preconditioner
   int shape_cg = -1;                 // K.u launch shape of the CG product (-1: by grid size)
+  size_t tail_start = 0;             // first level of the one-workgroup V-cycle tail (0: none)
   topo_nn *nn = nullptr;
   int nn_graph_precision = -1;       // network precision the captured learned chunk uses
   NnWork nnw;                        // activations (batch 1) on the node grid
@@ -258,6 +259,7 @@ extern "C" void topo_default_opts(topo_opts *o) {
   o->use_graphs = 1;
   o->nn_max_iters = 200;
   o->autotune = 0;
+  o->coarse_tail_nodes = 1024;
 }
 
 extern "C" const char *topo_last_error(void) { return g_err; }
@@ -304,6 +306,7 @@ static topo_status validate(const topo_problem *P, const topo_opts *O) {
   if (!(O->rtol > 0.0) || O->max_iters < 1) return set_error("rtol > 0 and max_iters >= 1 required"), TOPO_EINVAL;
   if (!(O->oc_tol > 0.0)) return set_error("oc_tol must be > 0"), TOPO_EINVAL;
   if (O->mg_levels < 0 || O->mg_levels > 16) return set_error("mg_levels must lie in [0, 16]"), TOPO_EINVAL;
+  if (O->coarse_tail_nodes < 0) return set_error("coarse_tail_nodes must be >= 0"), TOPO_EINVAL;
   if (O->precision == TOPO_PREC_BF16) return set_error("the BF16 preconditioner is not available"), TOPO_EUNSUPPORTED;
   return TOPO_OK;
 }
@@ -447,6 +450,23 @@ extern "C" topo_status topo_setup(const topo_problem *P, const topo_opts *O, voi
   TOPO_HIP(hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
   ctx->lv[0].b = ctx->r;
   ctx->lv[0].x = ctx->z;
+
+  // one-workgroup tail of the V-cycle: the levels below coarse_tail_nodes nodes
+  // (never the finest level, whose last pass also forms r.z)
+  if (dims.size() > 1 && O->coarse_tail_nodes > 0) {
+    const bool fp32 = O->precision != TOPO_PREC_FP64;
+    auto level_bytes = [&](const Grid &g) { return fp32 ? tail_level_bytes<float>(g) : tail_level_bytes<double>(g); };
+    size_t bytes = level_bytes(dims.back());
+    size_t t = dims.size() - 1;
+    while (t > 1 && dims[t - 1].nnodes() <= O->coarse_tail_nodes && bytes + level_bytes(dims[t - 1]) <= kTailMaxLds &&
+           dims.size() - t < (size_t)kTailMaxLevels) {
+      bytes += level_bytes(dims[t - 1]);
+      --t;
+    }
+    if (dims.size() - t >= 2 && bytes <= kTailMaxLds) ctx->tail_start = t;
+    if (ctx->tail_start)
+      TOPO_HIP(fp32 ? prepare_vcycle_tail_t<float>(kTailMaxLds) : prepare_vcycle_tail_t<double>(kTailMaxLds));
+  }
 
   // reductions
   const int64_t nb_nodes = (ctx->nnodes + 255) / 256;
@@ -773,6 +793,34 @@ const float *coarse_inverse<float>(const topo_ctx *ctx) {
 
 // z = M r: V-cycle from level l with rhs b into x of that level; with dot_fin
 // set (level 0 in double precision) the last smoothing pass reduces r.z into it
+// levels tail_start .. coarsest in one launch (same arithmetic as the per-level passes)
+template <typename T>
+static topo_status vcycle_tail(topo_ctx *ctx, const int *skip) {
+  TailArgs<T> a{};
+  a.nlev = (int)(ctx->lv.size() - ctx->tail_start);
+  for (int q = 0; q < a.nlev; ++q) {
+    Level &L = ctx->lv[ctx->tail_start + q];
+    const LevelBufs<T> B = bufs<T>(L);
+    a.L[q] = TailLevel<T>{L.g, B.E, B.dinv, L.fixed, B.b, B.x, B.res, B.d0, B.d1};
+  }
+  a.Ainv = coarse_inverse<T>(ctx);
+  a.ncoarse = ctx->ncoarse;
+  a.kap = kappa_of<T>(ctx);
+  a.deg = ctx->opts.cheb_degree;
+  const Cheb ch(ctx->lam_max);
+  a.s0 = (T)(1.0 / ch.theta);
+  double rho = 1.0 / ch.sigma;
+  for (int k = 1; k < a.deg && k < kTailMaxDeg; ++k) {
+    const double rho_new = 1.0 / (2.0 * ch.sigma - rho);
+    a.c1[k] = (T)(rho_new * rho);
+    a.c2[k] = (T)(2.0 * rho_new / ch.delta);
+    rho = rho_new;
+  }
+  a.skip = skip;
+  TOPO_HIP(launch_vcycle_tail_t<T>(ctx->stream, a));
+  return TOPO_OK;
+}
+
 template <typename T>
 static topo_status vcycle(topo_ctx *ctx, size_t l, const int *skip, const Fin *dot_fin) {
   hipStream_t s = ctx->stream;
@@ -782,6 +830,7 @@ static topo_status vcycle(topo_ctx *ctx, size_t l, const int *skip, const Fin *d
     TOPO_HIP(launch_dense_matvec(s, ctx->ncoarse, coarse_inverse<T>(ctx), B.b, B.x, skip));
     return TOPO_OK;
   }
+  if (ctx->tail_start && l == ctx->tail_start) return vcycle_tail<T>(ctx, skip);
   topo_status st = pre_smooth<T>(ctx, L, skip);
   if (st != TOPO_OK) return st;
   Level &C = ctx->lv[l + 1];

@@ -72,19 +72,25 @@ def test_apply_K_matches_oracle(case):
 
 
 @pytest.mark.parametrize("case", CASES)
-@pytest.mark.parametrize("precond", ["mg140", "mg400", "mg400deg3", "jacobi"])
+@pytest.mark.parametrize("precond", ["mg140", "mg400", "mg400deg3", "mg140deg1", "mg140_notail",
+                                     "mg140_tail4000", "jacobi"])
 def test_preconditioner_matches_oracle(case, precond):
+    """The coarse levels run as one single-workgroup launch below coarse_tail_nodes
+    nodes (default 1024); _notail runs every level with the per-level kernels,
+    _tail4000 moves more levels into the single launch."""
     p = make_case(case)
     x = synth.random_density(5, p.nel, 0.0, 1.0)
     E = fem.simp_modulus(x, p.E0, p.Emin, p.penal)
     r = synth.random_vector(6, p.ndof)
     r[fixed_mask(p)] = 0.0
     if precond.startswith("mg"):
-        coarse = 140 if precond == "mg140" else 400
-        deg = 3 if precond.endswith("deg3") else 2
+        coarse = 140 if precond.startswith("mg140") else 400
+        deg = 3 if precond.endswith("deg3") else (1 if precond.endswith("deg1") else 2)
+        tail = 0 if precond.endswith("notail") else (4000 if precond.endswith("tail4000") else 1024)
         V = mg.VCycle(p, E, KE, degree=deg, max_coarse_dof=coarse)
         ref = V.apply(r)
-        opts = topo.default_opts(precond=topo.PRECOND_MG, mg_max_coarse_dof=coarse, cheb_degree=deg)
+        opts = topo.default_opts(precond=topo.PRECOND_MG, mg_max_coarse_dof=coarse, cheb_degree=deg,
+                                 coarse_tail_nodes=tail)
     else:
         K = mg.with_identity_rows(fem.assemble(E, KE, fem.element_dofs(p.nelx, p.nely, p.nelz), p.ndof),
                                   fixed_mask(p))
