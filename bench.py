@@ -222,8 +222,13 @@ def main():
     ap.add_argument("--coarse-dof", type=int, default=140, help="coarsest multigrid level size cap")
     ap.add_argument("--check-every", type=int, default=4)
     ap.add_argument("--no-graphs", action="store_true")
-    ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64",
+    ap.add_argument("--precision", choices=["fp64", "fp32", "bf16"], default="fp64",
                     help="precision of the multigrid preconditioner (CG stays FP64)")
+    ap.add_argument("--mfma", action="store_true",
+                    help="FP32 preconditioner: smoothing operator passes on the matrix cores")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="after the timed run, copy a buffer of this many MiB 5 times (a plain copy "
+                         "kernel of known traffic for calibrating hardware byte counters)")
     ap.add_argument("--tail-nodes", type=int, default=1024,
                     help="levels with at most this many nodes run as one single-workgroup launch (0 = off)")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-vs-multigrid leg")
@@ -250,7 +255,9 @@ def main():
     opts = topo.default_opts(rtol=1e-8, max_iters=2000, cheb_degree=args.cheb_degree,
                              mg_max_coarse_dof=args.coarse_dof, check_every=args.check_every,
                              use_graphs=0 if args.no_graphs else 1, coarse_tail_nodes=args.tail_nodes,
-                             precision=topo.PREC_FP64 if args.precision == "fp64" else topo.PREC_FP32,
+                             precision={"fp64": topo.PREC_FP64, "fp32": topo.PREC_FP32,
+                                        "bf16": topo.PREC_BF16}[args.precision],
+                             mfma_smoothing=1 if args.mfma else 0,
                              precond=topo.PRECOND_MG if args.precond == "mg" else topo.PRECOND_JACOBI)
     ctx = topo.Context(p, opts)
     x = torch.from_numpy(p.initial_design()).to("cuda")
@@ -301,6 +308,7 @@ def main():
             "check_every": args.check_every, "graphs": not args.no_graphs,
             "coarse_tail_nodes": args.tail_nodes,
             "preconditioner_precision": args.precision,
+            "matrix_core_smoothing": bool(args.mfma or args.precision == "bf16"),
             "pcg_iters_mean": round(float(pcg.mean()), 2), "pcg_iters_max": int(pcg.max()),
             "solve_ms_mean": round(float(solve_ms.mean()), 3),
             "dof_pcg_iters_per_s": round(float(p.ndof * pcg.sum() / (solve_ms.sum() * 1e-3)), 1),
@@ -313,6 +321,14 @@ def main():
         "roofline": roofline,
     }
     ctx.close()
+    if args.copy_probe_mib > 0:
+        n = args.copy_probe_mib * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     if not args.no_learned:
         out["config"]["learned_vs_mg"] = learned_vs_mg(topo, synth, args)
     if not args.no_batch:

@@ -66,7 +66,9 @@ enum {
  * the coarse solve run in single precision (FP32 accumulation) and the CG
  * recurrence switches to the flexible (Polak-Ribiere) update; the CG operator,
  * vectors, inner products and stopping test stay FP64, so the solution meets
- * the same FP64 residual tolerance.  BF16: reserved (TOPO_EUNSUPPORTED). */
+ * the same FP64 residual tolerance.  BF16: as FP32, and every smoothing
+ * operator pass multiplies BF16-rounded element matrix and displacements on the
+ * matrix cores (FP32 accumulation). */
 enum { TOPO_PREC_FP64 = 0, TOPO_PREC_FP32 = 1, TOPO_PREC_BF16 = 2 };
 /* preconditioner of the conjugate-gradient solve.  LEARNED: the convolutional
  * network attached with topo_set_nn (see below), used inside flexible CG with a
@@ -110,6 +112,8 @@ typedef struct {
                                  setup and keep the fastest (else chosen by grid size)   */
   int32_t coarse_tail_nodes;  /* multigrid levels (below the finest) with at most this many
                                  nodes run as one single-workgroup launch; 0 = off        */
+  int32_t mfma_smoothing;     /* FP32 preconditioner: smoothing operator passes on the FP32
+                                 matrix cores (else the vector-unit kernels)              */
 } topo_opts;
 
 typedef struct {
@@ -134,7 +138,8 @@ typedef struct {
 
 /* Fills *opts with defaults: FP64, MG, automatic depth (coarsest <= 140 dofs),
  * Chebyshev degree 2, rtol 1e-8, max_iters 1000, warm start, oc_tol 1e-12,
- * check_every 4, use_graphs 1, nn_max_iters 200, autotune 0, coarse_tail_nodes 1024. */
+ * check_every 4, use_graphs 1, nn_max_iters 200, autotune 0, coarse_tail_nodes 1024,
+ * mfma_smoothing 0. */
 void topo_default_opts(topo_opts *opts);
 
 /* Validates the problem, copies its arrays to the device, builds the element

@@ -135,6 +135,8 @@ struct KuArgsT {
   T c1, c2, s0;
   const T *dot_with;      // CHEB / CHEB_ADD: if set, reduce dot_with . x_new
   const int *skip;        // device flag: return at once when non-zero (may be NULL)
+  const float *ke32;      // matrix-core shapes: KE as FP32 [32][24] (rows 24.. zero)
+  const void *ke16;       // ... and as BF16 [32][32] (zero padded)
 };
 using KuArgs = KuArgsT<double>;
 // fin receives the reduction of STORE_DOT / RESID / CHEB with dot_with
@@ -145,7 +147,12 @@ hipError_t launch_ku(hipStream_t s, KuEpi epi, const KuArgs &a, const Kappa &kap
 hipError_t launch_ku(hipStream_t s, KuEpi epi, const KuArgsT<float> &a, const KappaT<float> &kap,
                      const Reducer &red, const Fin &fin, int shape = -1);
 int ku_shape_for(const Grid &g, KuEpi epi);
-constexpr int kKuShapes = 4;  // launch shapes 0..3 accepted by launch_ku
+// launch shapes: 0..3 vector-unit kernels (FP64 and FP32), 4 the FP32 matrix-core
+// kernel (single precision only), 5 the matrix-core kernel with BF16 operands
+// (single precision only; changes the arithmetic, chosen only in BF16 mode)
+constexpr int kKuShapes = 4;
+constexpr int kKuShapeMfma = 4, kKuShapeMfmaBf16 = 5;
+hipError_t launch_ku_mfma(hipStream_t s, KuEpi epi, const KuArgsT<float> &a, bool bf16);
 
 // vector kernels
 hipError_t launch_zero_fixed(hipStream_t s, int64_t nnodes, const uint8_t *fixed, double *v);

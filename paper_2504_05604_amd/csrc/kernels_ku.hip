@@ -43,8 +43,10 @@ __global__ __launch_bounds__(BS) void ku_march_kernel(KuArgsT<T> a, KappaT<T> ka
   const Grid g = a.g;
   const int NX = g.NX(), NY = g.NY(), NZ = g.NZ();
   const int ncol = NX * NY;
-  const int col = blockIdx.x * BS + threadIdx.x;
-  const int k0 = blockIdx.y * KZ;
+  // tiles: BS columns x KZ node planes, x-major; contiguous runs per XCD
+  const int tile = xcd_tile(linear_block(), gridDim.x * gridDim.y);
+  const int col = (tile % gridDim.x) * BS + threadIdx.x;
+  const int k0 = (tile / gridDim.x) * KZ;
   const int k1 = min(k0 + KZ, NZ);
   const bool active = col < ncol;
   const int i = active ? col % NX : 0, j = active ? col / NX : 0;
@@ -251,6 +253,9 @@ template <typename T>
 static hipError_t launch_ku_t(hipStream_t s, KuEpi epi, const KuArgsT<T> &a, const KappaT<T> &kap,
                               const Reducer &red, const Fin &fin, int shape) {
   if (shape < 0) shape = ku_shape_for(a.g, epi);
+  if constexpr (std::is_same<T, float>::value) {
+    if (shape == kKuShapeMfma || shape == kKuShapeMfmaBf16) return launch_ku_mfma(s, epi, a, shape == kKuShapeMfmaBf16);
+  }
   int nparts = 0;
   hipError_t e;
   switch (shape) {

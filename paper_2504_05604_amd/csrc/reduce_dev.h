@@ -49,4 +49,21 @@ __device__ void block_reduce_store(double (&v)[N], double *partials, int slot) {
 
 __device__ __forceinline__ int linear_block() { return blockIdx.x + gridDim.x * blockIdx.y; }
 
+// The dispatcher hands the workgroups of a launch to the 8 XCDs round-robin by
+// linear id, and each XCD has its own L2.  xcd_tile maps a workgroup to the tile
+// it processes so that every XCD works through runs of kXcdRun consecutive
+// tiles: neighbouring tiles (which read each other's halo) then mostly share
+// an L2, while the runs of different XCDs stay interleaved across the domain
+// (one contiguous slab per XCD measured slower).  The ragged end keeps the
+// plain order.
+constexpr int kXcds = 8;
+constexpr int kXcdRun = 16;
+__device__ __forceinline__ int xcd_tile(int id, int total) {
+  constexpr int span = kXcds * kXcdRun;
+  const int full = (total / span) * span;
+  if (id >= full) return id;
+  const int xcd = id % kXcds, q = id / kXcds;
+  return ((q / kXcdRun) * kXcds + xcd) * kXcdRun + q % kXcdRun;
+}
+
 }  // namespace topo

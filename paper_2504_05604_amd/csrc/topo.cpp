@@ -139,6 +139,8 @@ struct Level {
   double *b = nullptr, *x = nullptr, *res = nullptr, *d0 = nullptr, *d1 = nullptr;
   LevelBufs<float> f32;      // single-precision copy for the mixed-precision preconditioner
   int shape = -1;            // K.u launch shape of the smoothing passes (-1: by grid size)
+  const float *ke32 = nullptr;  // element matrix for the single-precision matrix-core K.u
+  const void *ke16 = nullptr;
 };
 
 template <typename T>
@@ -260,6 +262,7 @@ extern "C" void topo_default_opts(topo_opts *o) {
   o->nn_max_iters = 200;
   o->autotune = 0;
   o->coarse_tail_nodes = 1024;
+  o->mfma_smoothing = 0;
 }
 
 extern "C" const char *topo_last_error(void) { return g_err; }
@@ -307,7 +310,6 @@ static topo_status validate(const topo_problem *P, const topo_opts *O) {
   if (!(O->oc_tol > 0.0)) return set_error("oc_tol must be > 0"), TOPO_EINVAL;
   if (O->mg_levels < 0 || O->mg_levels > 16) return set_error("mg_levels must lie in [0, 16]"), TOPO_EINVAL;
   if (O->coarse_tail_nodes < 0) return set_error("coarse_tail_nodes must be >= 0"), TOPO_EINVAL;
-  if (O->precision == TOPO_PREC_BF16) return set_error("the BF16 preconditioner is not available"), TOPO_EUNSUPPORTED;
   return TOPO_OK;
 }
 
@@ -419,6 +421,36 @@ extern "C" topo_status topo_setup(const topo_problem *P, const topo_opts *O, voi
       TOPO_ALLOC(L.f32.res, L.g.ndof());
       TOPO_ALLOC(L.f32.d0, L.g.ndof());
       TOPO_ALLOC(L.f32.d1, L.g.ndof());
+    }
+  }
+  if (O->precision != TOPO_PREC_FP64) {
+    // element matrix for the single-precision matrix-core K.u: FP32 [32][24] and
+    // BF16 [32][32] (round to nearest even), zero padded
+    std::vector<float> k32(32 * 24, 0.0f);
+    std::vector<uint16_t> k16(32 * 32, 0);
+    for (int r = 0; r < 24; ++r)
+      for (int c = 0; c < 24; ++c) {
+        const float v = (float)KE[r * 24 + c];
+        k32[r * 24 + c] = v;
+        uint32_t bits;
+        std::memcpy(&bits, &v, 4);
+        bits += 0x7FFFu + ((bits >> 16) & 1u);
+        k16[r * 32 + c] = (uint16_t)(bits >> 16);
+      }
+    float *d32 = nullptr;
+    uint16_t *d16 = nullptr;
+    TOPO_ALLOC(d32, k32.size());
+    TOPO_ALLOC(d16, k16.size());
+    TOPO_HIP(hipMemcpyAsync(d32, k32.data(), k32.size() * sizeof(float), hipMemcpyHostToDevice, s));
+    TOPO_HIP(hipMemcpyAsync(d16, k16.data(), k16.size() * sizeof(uint16_t), hipMemcpyHostToDevice, s));
+    TOPO_HIP(hipStreamSynchronize(s));  // host staging goes out of scope
+    for (Level &L : ctx->lv) {
+      L.ke32 = d32;
+      L.ke16 = d16;
+      // BF16 mode: every smoothing pass on the matrix cores with BF16 operands;
+      // FP32 mode: on the FP32 matrix cores when asked to (else by grid size)
+      if (O->precision == TOPO_PREC_BF16) L.shape = kKuShapeMfmaBf16;
+      else if (O->mfma_smoothing) L.shape = kKuShapeMfma;
     }
   }
   TOPO_HIP(hipMemcpyAsync(ctx->lv[0].fixed, hfix.data(), ctx->nnodes, hipMemcpyHostToDevice, s));
@@ -555,6 +587,8 @@ static KuArgsT<T> ku_args_t(Level &L, const T *u) {
   a.u = u;
   a.fixed = L.fixed;
   a.dinv = B.dinv;
+  a.ke32 = L.ke32;
+  a.ke16 = L.ke16;
   return a;
 }
 
@@ -610,7 +644,9 @@ static topo_status tune_smoothing(topo_ctx *ctx, Level &L) {
   c.c1 = (T)0.5;
   c.c2 = (T)0.5;
   const KappaT<T> &kap = kappa_of<T>(ctx);
-  return time_ku_shapes(ctx, kKuShapes, [&](int shape) {
+  // single precision may also take the matrix-core kernel (same arithmetic up to rounding)
+  const int n_shapes = std::is_same<T, float>::value ? kKuShapes + 1 : kKuShapes;
+  return time_ku_shapes(ctx, n_shapes, [&](int shape) {
     return launch_ku(s, KU_CHEB, c, kap, ctx->red, fin_sum(nullptr), shape);
   }, &L.shape);
 }
@@ -628,6 +664,7 @@ static topo_status autotune(topo_ctx *ctx) {
   }, &ctx->shape_cg);
   if (st != TOPO_OK) return st;
   if (ctx->lv.size() < 2) return TOPO_OK;  // Jacobi: no smoothing passes
+  if (ctx->opts.precision == TOPO_PREC_BF16) return TOPO_OK;  // BF16 operands: one fixed kernel
   for (Level &L : ctx->lv) {
     st = ctx->mixed ? tune_smoothing<float>(ctx, L) : tune_smoothing<double>(ctx, L);
     if (st != TOPO_OK) return st;

@@ -1,6 +1,7 @@
 """Single-precision multigrid preconditioner inside FP64 flexible CG: the
 solution meets the same FP64 residual tolerance, and the SIMP trajectory stays
-within stated bounds of the FP64 one."""
+within stated bounds of the FP64 one.  Variants: FP32 on the vector units,
+FP32 on the matrix cores (mfma_smoothing), BF16 operands on the matrix cores."""
 
 import numpy as np
 import pytest
@@ -16,8 +17,16 @@ pytestmark = pytest.mark.gpu
 KE = element_stiffness(0.3)
 
 
+VARIANTS = {
+    "fp32": dict(precision=topo.PREC_FP32),
+    "fp32_mfma": dict(precision=topo.PREC_FP32, mfma_smoothing=1),
+    "bf16": dict(precision=topo.PREC_BF16),
+}
+
+
+@pytest.mark.parametrize("variant", list(VARIANTS))
 @pytest.mark.parametrize("case", ["small", "obstacle"])
-def test_fp32_preconditioned_solve_meets_fp64_tolerance(case):
+def test_low_precision_preconditioned_solve_meets_fp64_tolerance(case, variant):
     p = synth.config_small() if case == "small" else synth.config_obstacle(seed=4)
     x = synth.random_density(3, p.nel, 0.05, 1.0)
     E = fem.simp_modulus(x, p.E0, p.Emin, p.penal)
@@ -25,37 +34,63 @@ def test_fp32_preconditioned_solve_meets_fp64_tolerance(case):
     f[p.fixed_dofs] = 0.0
     edof = fem.element_dofs(p.nelx, p.nely, p.nelz)
     out = {}
-    for prec in (topo.PREC_FP64, topo.PREC_FP32):
-        with topo.Context(p, topo.default_opts(precision=prec, rtol=1e-10, max_iters=3000)) as ctx:
+    for name, kw in (("fp64", {}), (variant, VARIANTS[variant])):
+        with topo.Context(p, topo.default_opts(rtol=1e-10, max_iters=3000, **kw)) as ctx:
             u = torch.zeros(p.ndof, dtype=torch.float64, device="cuda")
             st = ctx.solve(torch.from_numpy(x).cuda(), u)
-            out[prec] = (u.cpu().numpy(), st)
-    for prec, (u, st) in out.items():
+            out[name] = (u.cpu().numpy(), st)
+    for name, (u, st) in out.items():
         assert st["converged"]
         # true FP64 residual of the returned solution, by the oracle's operator
         res = f - fem.apply_K_reduced(E, KE, edof, u, p.fixed_dofs)
-        assert np.linalg.norm(res) <= 3e-10 * np.linalg.norm(f), prec
-    u64, u32 = out[topo.PREC_FP64][0], out[topo.PREC_FP32][0]
-    assert abs(f @ u32 - f @ u64) <= 1e-9 * abs(f @ u64)
-    # the preconditioner in single precision costs at most a few extra iterations
-    assert out[topo.PREC_FP32][1]["iters"] <= out[topo.PREC_FP64][1]["iters"] + 5
+        assert np.linalg.norm(res) <= 3e-10 * np.linalg.norm(f), name
+    u64, ul = out["fp64"][0], out[variant][0]
+    assert abs(f @ ul - f @ u64) <= 1e-9 * abs(f @ u64)
+    # a single-precision preconditioner costs at most a few extra iterations; BF16
+    # operands (relative rounding 2^-9 in the smoother) up to a quarter more
+    extra = 5 if variant != "bf16" else max(5, out["fp64"][1]["iters"] // 4)
+    print(variant, "iterations", out[variant][1]["iters"], "fp64", out["fp64"][1]["iters"])
+    assert out[variant][1]["iters"] <= out["fp64"][1]["iters"] + extra
 
 
-def test_fp32_preconditioner_trajectory_close_to_fp64():
+@pytest.mark.parametrize("variant", list(VARIANTS))
+@pytest.mark.parametrize("case", ["small", "ragged"])
+def test_low_precision_preconditioner_matches_oracle(case, variant):
+    """One V-cycle application against the oracle's FP64 V-cycle: FP32 arithmetic
+    (2^-24 rounding through a few dozen passes) within 1e-4 of the output scale;
+    BF16 operands in the smoothing products (2^-9) within 3e-2."""
+    if case == "small":
+        p = synth.config_small()
+    else:
+        p = synth.cantilever(13, 7, 5, volfrac=0.3, rmin=2.0, n_iter=5)
+    x = synth.random_density(5, p.nel, 0.0, 1.0)
+    E = fem.simp_modulus(x, p.E0, p.Emin, p.penal)
+    fm = np.zeros(p.ndof, bool)
+    fm[p.fixed_dofs] = True
+    r = synth.random_vector(6, p.ndof)
+    r[fm] = 0.0
+    ref = mg.VCycle(p, E, KE, degree=2, max_coarse_dof=140).apply(r)
+    with topo.Context(p, topo.default_opts(**VARIANTS[variant])) as ctx:
+        z = torch.empty(p.ndof, dtype=torch.float64, device="cuda")
+        ctx.apply_precond(torch.from_numpy(x).cuda(), torch.from_numpy(r).cuda(), z)
+        torch.cuda.synchronize()
+        got = z.cpu().numpy()
+    err = np.abs(got - ref).max() / np.abs(ref).max()
+    print(variant, case, "max rel err", err)
+    assert err <= (3e-2 if variant == "bf16" else 1e-4)
+
+
+@pytest.mark.parametrize("variant", list(VARIANTS))
+def test_low_precision_preconditioner_trajectory_close_to_fp64(variant):
+    """The preconditioner does not change the solution beyond the solve tolerance
+    (1e-10), so the SIMP trajectories agree to about that level."""
     p = synth.config_small()
     res = {}
-    for prec in (topo.PREC_FP64, topo.PREC_FP32):
-        with topo.Context(p, topo.default_opts(precision=prec, rtol=1e-10)) as ctx:
+    for name, kw in (("fp64", {}), (variant, VARIANTS[variant])):
+        with topo.Context(p, topo.default_opts(rtol=1e-10, **kw)) as ctx:
             x = torch.from_numpy(p.initial_design()).cuda()
             stats = ctx.iterate(x, p.n_iter)
-            res[prec] = (x.cpu().numpy(), [s["c"] for s in stats])
-    c64, c32 = np.array(res[topo.PREC_FP64][1]), np.array(res[topo.PREC_FP32][1])
-    assert np.max(np.abs(c32 - c64) / c64) <= 1e-8
-    assert np.abs(res[topo.PREC_FP32][0] - res[topo.PREC_FP64][0]).max() <= 1e-6
-
-
-def test_bf16_reports_unsupported():
-    p = synth.config_small()
-    with pytest.raises(topo.TopoError) as e:
-        topo.Context(p, topo.default_opts(precision=topo.PREC_BF16))
-    assert e.value.status == 5
+            res[name] = (x.cpu().numpy(), [s["c"] for s in stats])
+    c64, cl = np.array(res["fp64"][1]), np.array(res[variant][1])
+    assert np.max(np.abs(cl - c64) / c64) <= 1e-8
+    assert np.abs(res[variant][0] - res["fp64"][0]).max() <= 1e-6
