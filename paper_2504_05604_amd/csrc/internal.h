@@ -245,6 +245,12 @@ template <typename T>
 __host__ __device__ inline size_t tail_level_bytes(const Grid &g) {
   return (size_t)(g.nel() + 6 * g.ndof()) * sizeof(T) + (size_t)((g.nnodes() + 15) / 16) * 16;
 }
+// partial sums of the coarsest solve (kColParts per row)
+constexpr int kColParts = 4;
+template <typename T>
+__host__ __device__ inline size_t tail_solve_bytes(int ncoarse) {
+  return (size_t)kColParts * ncoarse * sizeof(T);
+}
 template <typename T>
 hipError_t launch_vcycle_tail_t(hipStream_t s, const TailArgs<T> &a);
 // raises the kernel's dynamic LDS limit (call once before launching)

@@ -222,61 +222,103 @@ template <typename T>
 __global__ __launch_bounds__(kTailThreads) void vcycle_tail_kernel(TailArgs<T> a) {
   if (a.skip && *a.skip) return;
   extern __shared__ __attribute__((aligned(16))) unsigned char tail_smem[];
-  // level descriptors pointing into LDS (kept in LDS too: indexed at run time)
-  __shared__ TailLevel<T> L[kTailMaxLevels];
-  if (threadIdx.x == 0) {
+  // level l's arrays in LDS, rebuilt from the offsets whenever needed (kept in
+  // registers, never stored, so the compiler knows they are LDS addresses)
+  auto lev = [&](int l) {
     size_t off = 0;
-    for (int l = 0; l < a.nlev; ++l) {
-      const Grid g = a.L[l].g;
-      const int64_t nd = g.ndof(), ne = g.nel();
-      T *base = reinterpret_cast<T *>(tail_smem + off);
-      TailLevel<T> d;
-      d.g = g;
-      d.E = base;
-      d.dinv = base + ne;
-      d.b = base + ne + nd;
-      d.x = d.b + nd;
-      d.res = d.x + nd;
-      d.d0 = d.res + nd;
-      d.d1 = d.d0 + nd;
-      d.fixed = reinterpret_cast<const uint8_t *>(d.d1 + nd);
-      L[l] = d;
-      off += tail_level_bytes<T>(g);
+    for (int q = 0; q < l; ++q) off += tail_level_bytes<T>(a.L[q].g);
+    const Grid g = a.L[l].g;
+    const int64_t nd = g.ndof(), ne = g.nel();
+    T *base = reinterpret_cast<T *>(tail_smem + off);
+    TailLevel<T> d;
+    d.g = g;
+    d.E = base;
+    d.dinv = base + ne;
+    d.b = base + ne + nd;
+    d.x = d.b + nd;
+    d.res = d.x + nd;
+    d.d0 = d.res + nd;
+    d.d1 = d.d0 + nd;
+    d.fixed = reinterpret_cast<const uint8_t *>(d.d1 + nd);
+    return d;
+  };
+  // copy-in as one flat loop over every (level, array) segment, so all the
+  // global loads of a thread are independent and in flight together
+  {
+    int64_t total = 0;
+    for (int l = 0; l < a.nlev; ++l) total += a.L[l].g.nel() + a.L[l].g.ndof() + a.L[l].g.nnodes();
+    total += a.L[0].g.ndof();  // right-hand side of the first level
+    for (int64_t q = threadIdx.x; q < total; q += blockDim.x) {
+      int64_t r = q;
+      if (r < a.L[0].g.ndof()) {
+        lev(0).b[r] = a.L[0].b[r];
+        continue;
+      }
+      r -= a.L[0].g.ndof();
+      for (int l = 0; l < a.nlev; ++l) {
+        const TailLevel<T> &G = a.L[l];
+        const int64_t ne = G.g.nel(), nd = G.g.ndof(), nn = G.g.nnodes();
+        if (r < ne) {
+          const_cast<T *>(lev(l).E)[r] = G.E[r];
+          break;
+        }
+        r -= ne;
+        if (r < nd) {
+          const_cast<T *>(lev(l).dinv)[r] = G.dinv[r];
+          break;
+        }
+        r -= nd;
+        if (r < nn) {
+          const_cast<uint8_t *>(lev(l).fixed)[r] = G.fixed[r];
+          break;
+        }
+        r -= nn;
+      }
     }
-  }
-  __syncthreads();
-  for (int l = 0; l < a.nlev; ++l) {
-    const TailLevel<T> &G = a.L[l];
-    const int64_t nd = G.g.ndof(), ne = G.g.nel(), nn = G.g.nnodes();
-    T *E = const_cast<T *>(L[l].E), *dinv = const_cast<T *>(L[l].dinv);
-    uint8_t *fx = const_cast<uint8_t *>(L[l].fixed);
-    for (int64_t q = threadIdx.x; q < ne; q += blockDim.x) E[q] = G.E[q];
-    for (int64_t q = threadIdx.x; q < nd; q += blockDim.x) dinv[q] = G.dinv[q];
-    for (int64_t q = threadIdx.x; q < nn; q += blockDim.x) fx[q] = G.fixed[q];
-    if (l == 0)
-      for (int64_t q = threadIdx.x; q < nd; q += blockDim.x) L[0].b[q] = G.b[q];
   }
   __syncthreads();
   const int last = a.nlev - 1;
   for (int l = 0; l < last; ++l) {
-    pre_smooth(a, L[l]);
-    restrict_to(L[l], L[l + 1]);
+    const TailLevel<T> F = lev(l), Cl = lev(l + 1);
+    pre_smooth(a, F);
+    restrict_to(F, Cl);
   }
-  // coarsest level: x = Ainv b
+  // coarsest level: x = Ainv b.  Each row is split into kColParts contiguous
+  // column chunks, one per thread, so every thread issues all its loads at once;
+  // the partial sums meet in LDS (after the levels' arrays) and are added in a
+  // fixed order.
   {
-    const TailLevel<T> &C = L[last];
-    for (int r = threadIdx.x; r < a.ncoarse; r += blockDim.x) {
-      T t = 0;
-      for (int c = 0; c < a.ncoarse; ++c) t = fma(a.Ainv[(int64_t)r * a.ncoarse + c], C.b[c], t);
-      C.x[r] = t;
+    const TailLevel<T> C = lev(last);
+    size_t pofs = 0;
+    for (int q = 0; q < a.nlev; ++q) pofs += tail_level_bytes<T>(a.L[q].g);
+    T *part = reinterpret_cast<T *>(tail_smem + pofs);
+    const int n = a.ncoarse, chunk = (n + kColParts - 1) / kColParts;
+    for (int t = threadIdx.x; t < kColParts * n; t += blockDim.x) {
+      const int r = t / kColParts, q = t % kColParts;
+      const int c0 = q * chunk, c1 = min(n, c0 + chunk);
+      const T *row = a.Ainv + (int64_t)r * n;
+      T s = 0;
+      for (int c = c0; c < c1; ++c) s = fma(row[c], C.b[c], s);
+      part[t] = s;
+    }
+    __syncthreads();
+    for (int r = threadIdx.x; r < n; r += blockDim.x) {
+      T s = 0;
+#pragma unroll
+      for (int q = 0; q < kColParts; ++q) s += part[kColParts * r + q];
+      C.x[r] = s;
     }
     __syncthreads();
   }
   for (int l = last - 1; l >= 0; --l) {
-    prolong_add(L[l], L[l + 1]);
-    post_smooth(a, L[l]);
+    const TailLevel<T> F = lev(l), Cl = lev(l + 1);
+    prolong_add(F, Cl);
+    post_smooth(a, F);
   }
-  for (int64_t q = threadIdx.x; q < a.L[0].g.ndof(); q += blockDim.x) a.L[0].x[q] = L[0].x[q];
+  {
+    const TailLevel<T> F = lev(0);
+    for (int64_t q = threadIdx.x; q < a.L[0].g.ndof(); q += blockDim.x) a.L[0].x[q] = F.x[q];
+  }
 }
 
 template <typename T>
@@ -288,7 +330,7 @@ hipError_t prepare_vcycle_tail_t(size_t smem_bytes) {
 template <typename T>
 hipError_t launch_vcycle_tail_t(hipStream_t s, const TailArgs<T> &a) {
   if (a.nlev < 1 || a.nlev > kTailMaxLevels || a.deg < 1 || a.deg >= kTailMaxDeg) return hipErrorInvalidValue;
-  size_t bytes = 0;
+  size_t bytes = tail_solve_bytes<T>(a.ncoarse);
   for (int l = 0; l < a.nlev; ++l) bytes += tail_level_bytes<T>(a.L[l].g);
   if (bytes > kTailMaxLds) return hipErrorInvalidValue;
   vcycle_tail_kernel<T><<<1, kTailThreads, bytes, s>>>(a);

@@ -488,7 +488,8 @@ extern "C" topo_status topo_setup(const topo_problem *P, const topo_opts *O, voi
   if (dims.size() > 1 && O->coarse_tail_nodes > 0) {
     const bool fp32 = O->precision != TOPO_PREC_FP64;
     auto level_bytes = [&](const Grid &g) { return fp32 ? tail_level_bytes<float>(g) : tail_level_bytes<double>(g); };
-    size_t bytes = level_bytes(dims.back());
+    const int nco = (int)dims.back().ndof();
+    size_t bytes = level_bytes(dims.back()) + (fp32 ? tail_solve_bytes<float>(nco) : tail_solve_bytes<double>(nco));
     size_t t = dims.size() - 1;
     while (t > 1 && dims[t - 1].nnodes() <= O->coarse_tail_nodes && bytes + level_bytes(dims[t - 1]) <= kTailMaxLds &&
            dims.size() - t < (size_t)kTailMaxLevels) {
