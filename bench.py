@@ -302,6 +302,8 @@ def main():
                          "kernel of known traffic for calibrating hardware byte counters)")
     ap.add_argument("--tail-nodes", type=int, default=1024,
                     help="levels with at most this many nodes run as one single-workgroup launch (0 = off)")
+    ap.add_argument("--warm", type=int, default=3, choices=[0, 1, 2, 3],
+                    help="initial guess of each solve: 0 zero, 1 last solution, 2 extrapolated, 3 projected")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-vs-multigrid leg")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-problems leg")
     ap.add_argument("--no-paper", action="store_true", help="skip the paper's 32x16x16 workload")
@@ -324,7 +326,7 @@ def main():
     import synth
 
     p = synth.config_large()
-    opts = topo.default_opts(rtol=1e-8, max_iters=2000, cheb_degree=args.cheb_degree,
+    opts = topo.default_opts(rtol=1e-8, max_iters=2000, cheb_degree=args.cheb_degree, warm_start=args.warm,
                              mg_max_coarse_dof=args.coarse_dof, check_every=args.check_every,
                              use_graphs=0 if args.no_graphs else 1, coarse_tail_nodes=args.tail_nodes,
                              precision={"fp64": topo.PREC_FP64, "fp32": topo.PREC_FP32,
@@ -376,7 +378,8 @@ def main():
         "config": {
             "workload": "cantilever-160x80x80 (3,168,963 DOF), volfrac 0.2, rmin 3.0, density filter",
             "nel": p.nel, "ndof": p.ndof, "precond": args.precond, "mg_levels": ctx.mg_levels,
-            "cheb_degree": deg, "rtol": 1e-8, "warm_start": True, "coarse_dof_cap": args.coarse_dof,
+            "cheb_degree": deg, "rtol": 1e-8, "warm_start": ["zero", "last", "extrapolated", "projected"][args.warm],
+            "coarse_dof_cap": args.coarse_dof,
             "check_every": args.check_every, "graphs": not args.no_graphs,
             "coarse_tail_nodes": args.tail_nodes,
             "preconditioner_precision": args.precision,

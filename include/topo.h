@@ -101,7 +101,10 @@ typedef struct {
   int32_t cheb_degree;        /* Chebyshev smoother degree per pre/post smoothing      */
   double rtol;                /* stop when ||r||_2 <= rtol ||f||_2 (free dofs)         */
   int32_t max_iters;          /* CG iteration cap per solve                           */
-  int32_t warm_start;         /* topo_iterate: start each solve from the last u        */
+  int32_t warm_start;         /* topo_iterate: 0 start each solve from zero, 1 from the
+                                 last u, 2 from the extrapolation 2 u_k - u_{k-1}, 3 from
+                                 the combination of the last 4 solutions closest to the
+                                 new solution in the new operator's energy norm          */
   double oc_tol;              /* relative width of the final multiplier bracket        */
   int32_t check_every;        /* CG iterations per host convergence check (the device
                                  stops iterating at convergence within a chunk)         */
@@ -137,7 +140,7 @@ typedef struct {
 } topo_iter_stats;
 
 /* Fills *opts with defaults: FP64, MG, automatic depth (coarsest <= 140 dofs),
- * Chebyshev degree 2, rtol 1e-8, max_iters 1000, warm start, oc_tol 1e-12,
+ * Chebyshev degree 2, rtol 1e-8, max_iters 1000, projected warm start (3), oc_tol 1e-12,
  * check_every 4, use_graphs 1, nn_max_iters 200, autotune 0, coarse_tail_nodes 1024,
  * mfma_smoothing 0. */
 void topo_default_opts(topo_opts *opts);

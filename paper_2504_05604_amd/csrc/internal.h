@@ -190,6 +190,10 @@ hipError_t launch_cheb_start(hipStream_t s, int64_t n, const float *res, const f
 // out = (float) in
 hipError_t launch_convert(hipStream_t s, int64_t n, const double *in, float *out,
                           const int *skip = nullptr);
+// u = sum_k alpha_k v_k, 1 <= nv <= 4
+hipError_t launch_combine(hipStream_t s, int64_t n, int nv, const double *const *v, const double *alpha, double *u);
+// u_prev <- u and u <- 2 u - u_prev (previous u_prev)
+hipError_t launch_extrapolate(hipStream_t s, int64_t n, double *u, double *u_prev);
 // z = (double) x; fin.out[0] = r.z_new, fin.out[1] = r.z_old (FIN_RZ_FLEX)
 hipError_t launch_widen_dot(hipStream_t s, int64_t n, const float *x, const double *r, double *z,
                             const Reducer &red, const Fin &fin, const int *skip = nullptr);

@@ -250,4 +250,45 @@ hipError_t launch_widen_dot(hipStream_t s, int64_t n, const float *x, const doub
   return e != hipSuccess ? e : launch_finalize(s, red, (int)nb, 2, fin, skip);
 }
 
+// linear extrapolation of the solution sequence: u_prev <- u, u <- 2 u - u_prev_old
+__global__ void extrapolate_kernel(int64_t n, double *u, double *u_prev) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double cur = u[i], old = u_prev[i];
+  u_prev[i] = cur;
+  u[i] = 2.0 * cur - old;
+}
+
+hipError_t launch_extrapolate(hipStream_t s, int64_t n, double *u, double *u_prev) {
+  extrapolate_kernel<<<nblocks(n), kBs, 0, s>>>(n, u, u_prev);
+  return hipGetLastError();
+}
+
+// u = sum_k alpha_k v_k (up to 4 vectors)
+struct Combo {
+  const double *v[4];
+  double alpha[4];
+  int n;
+};
+
+__global__ void combine_kernel(int64_t n, Combo c, double *u) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double t = 0.0;
+  for (int k = 0; k < c.n; ++k) t = fma(c.alpha[k], c.v[k][i], t);
+  u[i] = t;
+}
+
+hipError_t launch_combine(hipStream_t s, int64_t n, int nv, const double *const *v, const double *alpha, double *u) {
+  if (nv < 1 || nv > 4) return hipErrorInvalidValue;
+  Combo c{};
+  c.n = nv;
+  for (int k = 0; k < nv; ++k) {
+    c.v[k] = v[k];
+    c.alpha[k] = alpha[k];
+  }
+  combine_kernel<<<nblocks(n), kBs, 0, s>>>(n, c, u);
+  return hipGetLastError();
+}
+
 }  // namespace topo

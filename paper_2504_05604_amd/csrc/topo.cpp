@@ -211,6 +211,11 @@ struct topo_ctx {
   NnWork nnw;                        // activations (batch 1) on the node grid
   double *nn_scale = nullptr;        // rms of the residual of the current application
   double *ustar = nullptr;           // training-pair generation: converged solution
+  double *u_prev = nullptr;          // extrapolated warm start: the solution before the last
+  int n_warm = 0;                    // consecutive solutions available for the warm start
+  double *basis[4] = {};             // projected warm start: the last solutions (ring)
+  int nbasis = 0, basis_next = 0;
+  double *gram = nullptr;            // its Gram matrix and right-hand side on the device
   std::vector<void *> allocs;
 
   template <typename T>
@@ -255,7 +260,7 @@ extern "C" void topo_default_opts(topo_opts *o) {
   o->cheb_degree = 2;
   o->rtol = 1e-8;
   o->max_iters = 1000;
-  o->warm_start = 1;
+  o->warm_start = 3;
   o->oc_tol = 1e-12;
   o->check_every = 4;
   o->use_graphs = 1;
@@ -310,6 +315,7 @@ static topo_status validate(const topo_problem *P, const topo_opts *O) {
   if (!(O->oc_tol > 0.0)) return set_error("oc_tol must be > 0"), TOPO_EINVAL;
   if (O->mg_levels < 0 || O->mg_levels > 16) return set_error("mg_levels must lie in [0, 16]"), TOPO_EINVAL;
   if (O->coarse_tail_nodes < 0) return set_error("coarse_tail_nodes must be >= 0"), TOPO_EINVAL;
+  if (O->warm_start < 0 || O->warm_start > 3) return set_error("warm_start must be 0, 1, 2 or 3"), TOPO_EINVAL;
   return TOPO_OK;
 }
 
@@ -602,6 +608,91 @@ const KappaT<double> &kappa_of<double>(const topo_ctx *ctx) {
 template <>
 const KappaT<float> &kappa_of<float>(const topo_ctx *ctx) {
   return ctx->kap32;
+}
+
+// ---------------------------------------------------------------------------
+// Initial guess of a solve from the last few solutions: the combination U alpha
+// of the stored solutions U that is closest to the new solution in the energy
+// norm of the new operator, i.e. (U^T K U) alpha = U^T f.  The small Gram
+// system is solved on the host through its eigen-decomposition (directions with
+// eigenvalues below 1e-12 of the largest, i.e. nearly repeated solutions, are
+// dropped).
+constexpr int kMaxBasis = 4;
+
+// symmetric eigen-decomposition by cyclic Jacobi rotations: A = V diag(w) V^T
+static void sym_eig(std::vector<double> A, int n, std::vector<double> &w, std::vector<double> &V) {
+  V.assign(n * n, 0.0);
+  for (int i = 0; i < n; ++i) V[i * n + i] = 1.0;
+  for (int sweep = 0; sweep < 100; ++sweep) {
+    double off = 0.0, scale = 0.0;
+    for (int p = 0; p < n; ++p) {
+      scale += A[p * n + p] * A[p * n + p];
+      for (int q = p + 1; q < n; ++q) off += A[p * n + q] * A[p * n + q];
+    }
+    if (off <= 1e-30 * scale) break;
+    for (int p = 0; p < n; ++p)
+      for (int q = p + 1; q < n; ++q) {
+        const double apq = A[p * n + q];
+        if (std::fabs(apq) < 1e-300) continue;
+        const double theta = (A[q * n + q] - A[p * n + p]) / (2.0 * apq);
+        const double t = (theta >= 0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
+        const double c = 1.0 / std::sqrt(t * t + 1.0), sn = t * c;
+        for (int k = 0; k < n; ++k) {
+          const double akp = A[k * n + p], akq = A[k * n + q];
+          A[k * n + p] = c * akp - sn * akq;
+          A[k * n + q] = sn * akp + c * akq;
+        }
+        for (int k = 0; k < n; ++k) {
+          const double apk = A[p * n + k], aqk = A[q * n + k];
+          A[p * n + k] = c * apk - sn * aqk;
+          A[q * n + k] = sn * apk + c * aqk;
+        }
+        for (int k = 0; k < n; ++k) {
+          const double vkp = V[k * n + p], vkq = V[k * n + q];
+          V[k * n + p] = c * vkp - sn * vkq;
+          V[k * n + q] = sn * vkp + c * vkq;
+        }
+      }
+  }
+  w.resize(n);
+  for (int i = 0; i < n; ++i) w[i] = A[i * n + i];
+}
+
+static topo_status projected_start(topo_ctx *ctx) {
+  hipStream_t s = ctx->stream;
+  const int nb = ctx->nbasis;
+  Level &L0 = ctx->lv[0];
+  // Gram matrix G_ij = u_i . K u_j (upper triangle) and g_i = u_i . f
+  for (int j = 0; j < nb; ++j) {
+    KuArgs a = ku_args(ctx, L0, ctx->basis[j]);
+    a.y = ctx->tmp;
+    TOPO_HIP(launch_ku(s, KU_STORE, a, ctx->kap, ctx->red, fin_sum(nullptr)));
+    for (int i = 0; i <= j; ++i)
+      TOPO_HIP(launch_dot(s, ctx->ndof, ctx->basis[i], ctx->tmp, ctx->red, fin_sum(&ctx->gram[i * kMaxBasis + j])));
+    TOPO_HIP(launch_dot(s, ctx->ndof, ctx->basis[j], ctx->f, ctx->red, fin_sum(&ctx->gram[kMaxBasis * kMaxBasis + j])));
+  }
+  double h[kMaxBasis * kMaxBasis + kMaxBasis];
+  TOPO_HIP(hipMemcpyAsync(h, ctx->gram, sizeof(h), hipMemcpyDeviceToHost, s));
+  TOPO_HIP(hipStreamSynchronize(s));
+  std::vector<double> G(nb * nb), w, V;
+  for (int i = 0; i < nb; ++i)
+    for (int j = i; j < nb; ++j) G[i * nb + j] = G[j * nb + i] = h[i * kMaxBasis + j];
+  sym_eig(G, nb, w, V);
+  double wmax = 0.0;
+  for (double v : w) wmax = std::max(wmax, v);
+  double alpha[kMaxBasis] = {0.0, 0.0, 0.0, 0.0};
+  for (int k = 0; k < nb; ++k) {
+    if (!(w[k] > 1e-12 * wmax)) continue;
+    double qg = 0.0;
+    for (int i = 0; i < nb; ++i) qg += V[i * nb + k] * h[kMaxBasis * kMaxBasis + i];
+    for (int i = 0; i < nb; ++i) alpha[i] += V[i * nb + k] * qg / w[k];
+  }
+  for (int i = 0; i < nb; ++i)
+    if (!std::isfinite(alpha[i])) return TOPO_OK;  // keep the plain warm start
+  const double *vs[kMaxBasis];
+  for (int i = 0; i < nb; ++i) vs[i] = ctx->basis[i];
+  TOPO_HIP(launch_combine(s, ctx->ndof, nb, vs, alpha, ctx->u));
+  return TOPO_OK;
 }
 
 // ---------------------------------------------------------------------------
@@ -1106,6 +1197,8 @@ extern "C" topo_status topo_solve(topo_ctx *ctx, const double *d_xphys, double *
     st = pcg(ctx, &stats);
     TOPO_HIP(hipMemcpyAsync(d_u, ctx->u, ctx->ndof * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
     ctx->have_u = 1;
+    ctx->n_warm = 0;  // a caller's solve starts a new sequence for the extrapolated
+    ctx->nbasis = 0;  // and the projected warm starts
   }
   (void)hipEventRecord(e1, ctx->stream);
   (void)hipEventSynchronize(e1);
@@ -1192,13 +1285,32 @@ extern "C" topo_status topo_iterate(topo_ctx *ctx, double *d_x, int32_t n_iter, 
     }
     (void)hipEventRecord(ev[1], s);
     // modulus, operator hierarchy and solve (warm start from the last u)
-    if (!ctx->opts.warm_start || !ctx->have_u) TOPO_HIP(hipMemsetAsync(ctx->u, 0, ctx->ndof * sizeof(double), s));
+    if (!ctx->opts.warm_start || !ctx->have_u) {
+      TOPO_HIP(hipMemsetAsync(ctx->u, 0, ctx->ndof * sizeof(double), s));
+      ctx->n_warm = 0;
+      ctx->nbasis = 0;
+    } else if (ctx->opts.warm_start == 2) {
+      // extrapolated start 2 u_k - u_{k-1} once two solutions are known
+      if (!ctx->u_prev) TOPO_ALLOC(ctx->u_prev, ctx->ndof);
+      if (ctx->n_warm >= 2) TOPO_HIP(launch_extrapolate(s, ctx->ndof, ctx->u, ctx->u_prev));
+      else TOPO_HIP(hipMemcpyAsync(ctx->u_prev, ctx->u, ctx->ndof * sizeof(double), hipMemcpyDeviceToDevice, s));
+    }
     topo_status st = prepare_operator(ctx, ctx->xphys);
+    if (st == TOPO_OK && ctx->opts.warm_start == 3 && ctx->nbasis > 0) st = projected_start(ctx);
     topo_solve_stats ss{};
     if (st == TOPO_OK) st = pcg(ctx, &ss);
     if (st != TOPO_OK && st != TOPO_ENOTCONVERGED) return st;
     if (st == TOPO_ENOTCONVERGED) result = st;
     ctx->have_u = 1;
+    ++ctx->n_warm;
+    if (ctx->opts.warm_start == 3) {
+      if (!ctx->gram) TOPO_ALLOC(ctx->gram, kMaxBasis * kMaxBasis + kMaxBasis);
+      double *&slot = ctx->basis[ctx->basis_next];
+      if (!slot) TOPO_ALLOC(slot, ctx->ndof);
+      TOPO_HIP(hipMemcpyAsync(slot, ctx->u, ctx->ndof * sizeof(double), hipMemcpyDeviceToDevice, s));
+      ctx->basis_next = (ctx->basis_next + 1) % kMaxBasis;
+      ctx->nbasis = std::min(ctx->nbasis + 1, kMaxBasis);
+    }
     (void)hipEventRecord(ev[2], s);
     // sensitivities and compliance
     TOPO_HIP(launch_sensitivity(s, ctx->g, ctx->kap, ctx->u, ctx->xphys, P.E0, P.Emin, P.penal, ctx->ce, ctx->dc));

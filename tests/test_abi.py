@@ -29,7 +29,7 @@ def test_library_exports_every_declared_symbol():
 def test_default_opts():
     o = pkg.default_opts()
     assert o.precision == pkg.PREC_FP64 and o.precond == pkg.PRECOND_MG
-    assert o.rtol == 1e-8 and o.oc_tol == 1e-12 and o.cheb_degree == 2
+    assert o.rtol == 1e-8 and o.oc_tol == 1e-12 and o.cheb_degree == 2 and o.warm_start == 3
 
 
 def setup_status(p, **opt):

@@ -252,3 +252,19 @@ def test_iterate_matches_oracle_with_passive_elements(mode):
         assert abs(s["c"] - h["c"]) <= 1e-8 * h["c"], (s["c"], h["c"])
     np.testing.assert_allclose(xg, xo, atol=1e-7)
     assert np.all(xg[p.mask == 1] == 0.0)
+
+
+@pytest.mark.parametrize("warm", [0, 1, 2, 3])
+def test_warm_start_modes_give_the_same_trajectory(warm):
+    """Zero, last, extrapolated and energy-projected initial guesses change only
+    the CG iteration counts: the trajectory matches the oracle's (direct
+    solves) to the solve tolerance."""
+    p = synth.config_small()
+    n_iter = 6
+    ref = simp.SimpOracle(p).trajectory(n_iter)[1]
+    with topo.Context(p, topo.default_opts(rtol=1e-10, warm_start=warm)) as ctx:
+        x = dev(p.initial_design())
+        st = ctx.iterate(x, n_iter)
+    for k in range(n_iter):
+        assert abs(st[k]["c"] - ref[k]["c"]) <= 1e-8 * abs(ref[k]["c"]), (warm, k)
+    print("warm", warm, "iterations", [s["pcg_iters"] for s in st])
