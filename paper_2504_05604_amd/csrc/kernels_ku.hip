@@ -185,7 +185,13 @@ __global__ __launch_bounds__(BS) void ku_march_kernel(KuArgsT<T> a, KappaT<T> ka
       acc2 = nb2;
     };
     load_plane(k0 - 1, P0);
-    for (int L = k0 - 1; L < k1; ++L) {
+    // fully unrolled over the KZ + 1 layers (the last column of the grid may be
+    // shorter): straight-line code lets the compiler rename the plane registers
+    // instead of copying them and issue the next plane's loads early
+#pragma unroll
+    for (int q = 0; q <= KZ; ++q) {
+      const int L = k0 - 1 + q;
+      if (L >= k1) break;
       load_plane(L + 1, P1);
       layer(L, P0, P1);
 #pragma unroll
