@@ -304,6 +304,7 @@ def main():
                     help="levels with at most this many nodes run as one single-workgroup launch (0 = off)")
     ap.add_argument("--warm", type=int, default=3, choices=[0, 1, 2, 3],
                     help="initial guess of each solve: 0 zero, 1 last solution, 2 extrapolated, 3 projected")
+    ap.add_argument("--autotune", action="store_true", help="time every K.u launch shape at set-up")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-vs-multigrid leg")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-problems leg")
     ap.add_argument("--no-paper", action="store_true", help="skip the paper's 32x16x16 workload")
@@ -331,7 +332,7 @@ def main():
                              use_graphs=0 if args.no_graphs else 1, coarse_tail_nodes=args.tail_nodes,
                              precision={"fp64": topo.PREC_FP64, "fp32": topo.PREC_FP32,
                                         "bf16": topo.PREC_BF16}[args.precision],
-                             mfma_smoothing=1 if args.mfma else 0,
+                             mfma_smoothing=1 if args.mfma else 0, autotune=1 if args.autotune else 0,
                              precond=topo.PRECOND_MG if args.precond == "mg" else topo.PRECOND_JACOBI)
     ctx = topo.Context(p, opts)
     x = torch.from_numpy(p.initial_design()).to("cuda")
@@ -381,7 +382,7 @@ def main():
             "cheb_degree": deg, "rtol": 1e-8, "warm_start": ["zero", "last", "extrapolated", "projected"][args.warm],
             "coarse_dof_cap": args.coarse_dof,
             "check_every": args.check_every, "graphs": not args.no_graphs,
-            "coarse_tail_nodes": args.tail_nodes,
+            "coarse_tail_nodes": args.tail_nodes, "autotune": bool(args.autotune),
             "preconditioner_precision": args.precision,
             "matrix_core_smoothing": bool(args.mfma or args.precision == "bf16"),
             "pcg_iters_mean": round(float(pcg.mean()), 2), "pcg_iters_max": int(pcg.max()),

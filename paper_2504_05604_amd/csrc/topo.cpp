@@ -508,8 +508,11 @@ extern "C" topo_status topo_setup(const topo_problem *P, const topo_opts *O, voi
   }
 
   // reductions
+  // enough partials for every K.u launch shape (the smallest, 64 threads per
+  // one-node column, has a block per 64 columns per node plane) and the vector kernels
   const int64_t nb_nodes = (ctx->nnodes + 255) / 256;
-  ctx->red.max_blocks = (int)std::max<int64_t>(16384, nb_nodes + 1);
+  const int64_t nb_ku = ((int64_t)g.NX() * g.NY() + 63) / 64 * g.NZ();
+  ctx->red.max_blocks = (int)std::max<int64_t>({16384, nb_nodes + 1, nb_ku + 1});
   TOPO_ALLOC(ctx->red.partials, (size_t)ctx->red.max_blocks * kMaxRed);
   TOPO_ALLOC(ctx->sc, 1);
   TOPO_HIP(hipMemsetAsync(ctx->sc, 0, sizeof(Scalars), s));
