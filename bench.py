@@ -305,6 +305,9 @@ def main():
     ap.add_argument("--warm", type=int, default=3, choices=[0, 1, 2, 3],
                     help="initial guess of each solve: 0 zero, 1 last solution, 2 extrapolated, 3 projected")
     ap.add_argument("--autotune", action="store_true", help="time every K.u launch shape at set-up")
+    ap.add_argument("--ku-kernel", choices=["auto", "node", "element"], default="auto",
+                    help="K.u kernel: node columns or element columns in the sum/difference basis")
+    ap.add_argument("--ku-shape", type=int, default=-1, help="one K.u launch shape for every level (-1: by grid size)")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-vs-multigrid leg")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-problems leg")
     ap.add_argument("--no-paper", action="store_true", help="skip the paper's 32x16x16 workload")
@@ -333,6 +336,9 @@ def main():
                              precision={"fp64": topo.PREC_FP64, "fp32": topo.PREC_FP32,
                                         "bf16": topo.PREC_BF16}[args.precision],
                              mfma_smoothing=1 if args.mfma else 0, autotune=1 if args.autotune else 0,
+                             ku_kernel={"auto": topo.KU_AUTO, "node": topo.KU_NODE,
+                                        "element": topo.KU_ELEMENT}[args.ku_kernel],
+                             ku_shape=args.ku_shape,
                              precond=topo.PRECOND_MG if args.precond == "mg" else topo.PRECOND_JACOBI)
     ctx = topo.Context(p, opts)
     x = torch.from_numpy(p.initial_design()).to("cuda")
@@ -383,6 +389,7 @@ def main():
             "coarse_dof_cap": args.coarse_dof,
             "check_every": args.check_every, "graphs": not args.no_graphs,
             "coarse_tail_nodes": args.tail_nodes, "autotune": bool(args.autotune),
+            "ku_kernel": args.ku_kernel, "ku_shape": args.ku_shape,
             "preconditioner_precision": args.precision,
             "matrix_core_smoothing": bool(args.mfma or args.precision == "bf16"),
             "pcg_iters_mean": round(float(pcg.mean()), 2), "pcg_iters_max": int(pcg.max()),

@@ -70,6 +70,13 @@ enum {
  * operator pass multiplies BF16-rounded element matrix and displacements on the
  * matrix cores (FP32 accumulation). */
 enum { TOPO_PREC_FP64 = 0, TOPO_PREC_FP32 = 1, TOPO_PREC_BF16 = 2 };
+/* K.u kernels (Finite Element Analysis section: y = sum_e E_e KE u_e, never assembled).
+ * NODE: one thread per node column applies the 24 x 24 element matrix rows of
+ * the 8 elements around each node.  ELEMENT: one thread per element column works
+ * in the per-axis sum/difference basis of the element's corners, where KE splits
+ * into eight 3 x 3 parity blocks (21 multiply-adds per element), and neighbouring
+ * threads add their corner contributions through LDS.  AUTO: ELEMENT. */
+enum { TOPO_KU_AUTO = 0, TOPO_KU_NODE = 1, TOPO_KU_ELEMENT = 2 };
 /* preconditioner of the conjugate-gradient solve.  LEARNED: the convolutional
  * network attached with topo_set_nn (see below), used inside flexible CG with a
  * restart on the multigrid preconditioner when the safeguard fails. */
@@ -117,6 +124,16 @@ typedef struct {
                                  nodes run as one single-workgroup launch; 0 = off        */
   int32_t mfma_smoothing;     /* FP32 preconditioner: smoothing operator passes on the FP32
                                  matrix cores (else the vector-unit kernels)              */
+  int32_t ku_kernel;          /* TOPO_KU_*: which matrix-free K.u kernel the solver runs;
+                                 every choice computes the same product up to rounding    */
+  int32_t ku_shape;           /* -1: launch shapes by grid size (or autotuned); else one
+                                 launch shape for every level and the CG product:
+                                 0..3 node-column kernel, nodes per thread column x
+                                 threads = 8x256, 8x128, 2x128, 1x64; 6..12 element-column
+                                 kernel, node planes per slab x tile = 8x32x8, 8x16x16,
+                                 4x16x8 (next plane loaded ahead), 2x8x8 (ahead), 1x8x8,
+                                 8x32x8 (ahead), 8x16x16 (ahead); 4 and 5, the matrix-core
+                                 kernels, are chosen through precision / mfma_smoothing  */
 } topo_opts;
 
 typedef struct {

@@ -27,6 +27,9 @@ from ._lib import (  # noqa: F401
     PRECOND_JACOBI,
     PRECOND_MG,
     PRECOND_LEARNED,
+    KU_AUTO,
+    KU_NODE,
+    KU_ELEMENT,
     LOSS_REL,
     LOSS_COS,
 )

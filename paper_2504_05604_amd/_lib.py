@@ -21,6 +21,7 @@ FILTER_DENSITY, FILTER_SENSITIVITY = 0, 1
 FILTER_FWD, FILTER_ADJ, FILTER_SENS, FILTER_VOLW = 0, 1, 2, 3
 PREC_FP64, PREC_FP32, PREC_BF16 = 0, 1, 2
 PRECOND_JACOBI, PRECOND_MG, PRECOND_LEARNED = 0, 1, 2
+KU_AUTO, KU_NODE, KU_ELEMENT = 0, 1, 2
 LOSS_REL, LOSS_COS = 0, 1
 
 EXPORTED = [
@@ -64,6 +65,7 @@ class Opts_C(C.Structure):
         ("max_iters", C.c_int32), ("warm_start", C.c_int32), ("oc_tol", C.c_double),
         ("check_every", C.c_int32), ("use_graphs", C.c_int32), ("nn_max_iters", C.c_int32),
         ("autotune", C.c_int32), ("coarse_tail_nodes", C.c_int32), ("mfma_smoothing", C.c_int32),
+        ("ku_kernel", C.c_int32), ("ku_shape", C.c_int32),
     ]
 
 

@@ -1,6 +1,8 @@
 // Internal declarations of libtopo (not part of the ABI).
 #pragma once
 
+#include <vector>
+
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -73,6 +75,12 @@ struct KappaT {
   T k[10];
 };
 using Kappa = KappaT<double>;
+// the element matrix's 8 distinct entries in the sum/difference basis of the
+// element's corners, in the form the kernels apply them (see ke_code.h)
+template <typename T>
+struct HadaW {
+  T w[8];
+};
 
 // ---------------------------------------------------------------------------
 // kernel launchers (kernels_*.hip)
@@ -117,6 +125,7 @@ enum KuEpi {
   KU_RES0 = 3,         // operand d0 = b dinv s0: x = d0; res = b - A d0
   KU_CHEB0 = 4,        // operand d0 = b dinv s0: res = b - A d0; dout = c1 d0 + c2 res dinv; x = d0 + dout
   KU_CHEB = 5,         // res -= Au; dout = c1 u + c2 res dinv; x += dout      [reduce dot_with.x]
+                       // (dout = NULL: the last step, only x is stored)
   KU_CHEB_ADD = 6,     // as KU_CHEB with x += u + dout (u = the pending step)  [reduce dot_with.x]
   KU_RESUPD = 7,       // res -= Au
   KU_RESID_START = 8,  // res = b - Au; dout = res dinv s0 (x not updated: the next
@@ -146,13 +155,25 @@ hipError_t launch_ku(hipStream_t s, KuEpi epi, const KuArgs &a, const Kappa &kap
 // single-precision operator (smoothing passes only: no reducing epilogues)
 hipError_t launch_ku(hipStream_t s, KuEpi epi, const KuArgsT<float> &a, const KappaT<float> &kap,
                      const Reducer &red, const Fin &fin, int shape = -1);
-int ku_shape_for(const Grid &g, KuEpi epi);
-// launch shapes: 0..3 vector-unit kernels (FP64 and FP32), 4 the FP32 matrix-core
-// kernel (single precision only), 5 the matrix-core kernel with BF16 operands
-// (single precision only; changes the arithmetic, chosen only in BF16 mode)
+// launch shape by grid size within a K.u kernel family (TOPO_KU_*)
+int ku_shape_for(const Grid &g, KuEpi epi, int family);
+// launch shapes: 0..3 the node-column vector kernel (FP64 and FP32), 4 the FP32
+// matrix-core kernel (single precision only), 5 the matrix-core kernel with BF16
+// operands (single precision only; changes the arithmetic, chosen only in BF16
+// mode), 6..10 the element-column kernel in the sum/difference basis
 constexpr int kKuShapes = 4;
 constexpr int kKuShapeMfma = 4, kKuShapeMfmaBf16 = 5;
+constexpr int kKuShapeHada = 6, kKuShapesHada = 7;
 hipError_t launch_ku_mfma(hipStream_t s, KuEpi epi, const KuArgsT<float> &a, bool bf16);
+template <typename T>
+hipError_t launch_ku_hada(hipStream_t s, KuEpi epi, const KuArgsT<T> &a, const KappaT<T> &kap,
+                          const Reducer &red, int which, int *nparts);
+// most block partials any K.u launch shape writes on this grid
+int64_t ku_max_blocks(const Grid &g);
+int64_t ku_hada_max_blocks(const Grid &g);
+// shapes the autotuner times within a K.u kernel family (TOPO_KU_*; with AUTO,
+// single precision adds the FP32 matrix-core kernel)
+std::vector<int> ku_tunable_shapes(bool single, int family);
 
 // vector kernels
 hipError_t launch_zero_fixed(hipStream_t s, int64_t nnodes, const uint8_t *fixed, double *v);
@@ -236,7 +257,7 @@ struct TailArgs {
   TailLevel<T> L[kTailMaxLevels];
   const T *Ainv;                       // dense inverse of the coarsest operator (ncoarse^2)
   int ncoarse;
-  KappaT<T> kap;                       // element matrix values (see ke_code.h)
+  HadaW<T> hw;                         // element matrix, sum/difference basis (see ke_code.h)
   int deg;                             // Chebyshev degree per smoothing
   T s0;                                // 1 / theta
   T c1[kTailMaxDeg], c2[kTailMaxDeg];  // step k: d_k = c1[k] d_{k-1} + c2[k] D^-1 r
@@ -248,6 +269,12 @@ constexpr size_t kTailMaxLds = 158 * 1024;  // dynamic part; the kernel adds < 1
 template <typename T>
 __host__ __device__ inline size_t tail_level_bytes(const Grid &g) {
   return (size_t)(g.nel() + 6 * g.ndof()) * sizeof(T) + (size_t)((g.nnodes() + 15) / 16) * 16;
+}
+// per-element products of one operator pass (24 values per element), sized by
+// the finest (largest) level of the tail, after the levels and the solve partials
+template <typename T>
+__host__ __device__ inline size_t tail_scratch_bytes(const Grid &finest) {
+  return (size_t)24 * finest.nel() * sizeof(T);
 }
 // partial sums of the coarsest solve (kColParts per row)
 constexpr int kColParts = 4;

@@ -20,19 +20,15 @@
 //
 // Fixed dofs: inputs are required to be zero there (the solver keeps every
 // vector in the subspace of free dofs); outputs get the identity row y = u.
+#include <algorithm>
 #include <type_traits>
 
 #include "internal.h"
 #include "ke_code.h"
+#include "ku_epilogue.h"
 #include "reduce_dev.h"
 
 namespace topo {
-
-template <int EPI>
-struct EpiTraits {
-  // operand built as b * dinv * s0 instead of read from u
-  static constexpr bool scaled_operand = EPI == KU_RES0 || EPI == KU_CHEB0;
-};
 
 // Launch shape: KZ nodes per thread column, BS threads per block.  Large grids
 // march KZ = 8 nodes (fewer plane reloads); small grids use short columns and
@@ -135,50 +131,9 @@ __global__ __launch_bounds__(BS) void ku_march_kernel(KuArgsT<T> a, KappaT<T> ka
       }
       if (L >= k0) {  // node (i,j,L) is complete
         const int64_t n = (int64_t)L * plane + col;
-        const uint8_t fx = a.fixed[n];
         const T self[3] = {Pb[4][0], Pb[4][1], Pb[4][2]};
         const T Au[3] = {acc0, acc1, acc2};
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-          const bool isf = (fx >> c) & 1;
-          const int64_t dof = 3 * n + c;
-          const T Ac = isf ? T(0) : Au[c];  // reduced operator: no coupling into fixed rows
-          if constexpr (EPI == KU_STORE) {
-            a.y[dof] = isf ? self[c] : Au[c];
-          } else if constexpr (EPI == KU_STORE_DOT) {
-            const T yv = isf ? self[c] : Au[c];
-            a.y[dof] = yv;
-            dotv = fma((double)self[c], (double)yv, dotv);
-          } else if constexpr (EPI == KU_RESID) {
-            const T yv = isf ? T(0) : a.b[dof] - Au[c];
-            a.y[dof] = yv;
-            dotv = fma((double)yv, (double)yv, dotv);
-          } else if constexpr (EPI == KU_RES0) {  // x = d0, res = b - A d0
-            a.res[dof] = a.b[dof] - Ac;
-            a.x[dof] = self[c];
-          } else if constexpr (EPI == KU_CHEB0) {  // res = b - A d0; d1 = c1 d0 + c2 res dinv; x = d0 + d1
-            const T r = a.b[dof] - Ac;
-            const T dn = a.c1 * self[c] + a.c2 * r * dinv[dof];
-            a.res[dof] = r;
-            a.dout[dof] = dn;
-            a.x[dof] = self[c] + dn;
-          } else if constexpr (EPI == KU_CHEB || EPI == KU_CHEB_ADD) {
-            // dinv is 0 on fixed dofs, where res and the operand stay 0
-            const T r = a.res[dof] - Ac;
-            const T dn = a.c1 * self[c] + a.c2 * r * dinv[dof];
-            const T xn = a.x[dof] + dn + (EPI == KU_CHEB_ADD ? self[c] : 0.0);
-            a.res[dof] = r;
-            a.dout[dof] = dn;
-            a.x[dof] = xn;
-            if (a.dot_with) dotv = fma((double)a.dot_with[dof], (double)xn, dotv);
-          } else if constexpr (EPI == KU_RESUPD) {
-            a.res[dof] -= Ac;
-          } else if constexpr (EPI == KU_RESID_START) {  // res = b - A x; dout = res dinv s0
-            const T r = a.b[dof] - Ac;
-            a.res[dof] = r;
-            a.dout[dof] = r * dinv[dof] * a.s0;
-          }
-        }
+        ku_node_epilogue<EPI>(a, n, self, Au, dinv, dotv);
       }
       acc0 = nb0;
       acc1 = nb1;
@@ -202,21 +157,7 @@ __global__ __launch_bounds__(BS) void ku_march_kernel(KuArgsT<T> a, KappaT<T> ka
       }
     }
   }
-  if constexpr (EPI == KU_STORE_DOT || EPI == KU_RESID) {
-    double v[1] = {dotv};
-    block_reduce_store<1, false>(v, partials, linear_block());
-  } else if constexpr (EPI == KU_CHEB || EPI == KU_CHEB_ADD) {
-    if (a.dot_with) {
-      double v[1] = {dotv};
-      block_reduce_store<1, false>(v, partials, linear_block());
-    }
-  }
-}
-
-template <typename T>
-static bool ku_reduces(KuEpi epi, const KuArgsT<T> &a) {
-  return epi == KU_STORE_DOT || epi == KU_RESID ||
-         ((epi == KU_CHEB || epi == KU_CHEB_ADD) && a.dot_with != nullptr);
+  ku_block_reduce<EPI>(a, dotv, partials);
 }
 
 template <int KZ, int BS, typename T>
@@ -245,25 +186,58 @@ static hipError_t launch_ku_shape(hipStream_t s, KuEpi epi, const KuArgsT<T> &a,
   return hipGetLastError();
 }
 
-// Shapes measured on MI355X: 160x80x80 -> KZ 8 with 256 (smoother epilogues) or
-// 128 threads (CG product); 80x40x40 -> KZ 2 x 128; smaller grids -> KZ 1 x 64,
-// where a launch is bound by latency rather than arithmetic.
-int ku_shape_for(const Grid &g, KuEpi epi) {
+// Node-column shapes measured on MI355X: 160x80x80 -> KZ 8 with 256 (smoother
+// epilogues) or 128 threads (CG product); 80x40x40 -> KZ 2 x 128; smaller grids ->
+// KZ 1 x 64, where a launch is bound by latency rather than arithmetic.
+// Element-column shapes measured on MI355X (CG product): 160x80x80 -> 32 x 8
+// tiles of 8 planes, 24 us; 80x40x40 and 40x20x20 -> 8 x 8 tiles of 2 planes with
+// the next plane loaded ahead, 10 and 6.5 us; smaller grids -> 8 x 8 tiles of
+// one plane (latency bound, about 6 us).
+int ku_shape_for(const Grid &g, KuEpi epi, int family) {
   const int64_t nn = g.nnodes();
-  if (nn >= 600000) return epi == KU_STORE_DOT ? 1 : 0;
-  if (nn >= 60000) return 2;
-  return 3;
+  if (family == TOPO_KU_NODE) {
+    if (nn >= 600000) return epi == KU_STORE_DOT ? 1 : 0;
+    if (nn >= 60000) return 2;
+    return 3;
+  }
+  if (nn >= 600000) return kKuShapeHada + 0;
+  if (nn >= 8000) return kKuShapeHada + 3;
+  return kKuShapeHada + 4;
+}
+
+int64_t ku_max_blocks(const Grid &g) {
+  const int64_t ncol = (int64_t)g.NX() * g.NY(), nz = g.NZ();
+  // node-column shapes: KZ x BS = 8 x 256, 8 x 128, 2 x 128, 1 x 64
+  int64_t m = std::max<int64_t>({(ncol + 255) / 256 * ((nz + 7) / 8), (ncol + 127) / 128 * ((nz + 7) / 8),
+                                 (ncol + 127) / 128 * ((nz + 1) / 2), (ncol + 63) / 64 * nz});
+  return std::max(m, ku_hada_max_blocks(g));
+}
+
+std::vector<int> ku_tunable_shapes(bool single, int family) {
+  std::vector<int> v;
+  if (family != TOPO_KU_ELEMENT)
+    for (int i = 0; i < kKuShapes; ++i) v.push_back(i);
+  if (single && family == TOPO_KU_AUTO) v.push_back(kKuShapeMfma);
+  if (family != TOPO_KU_NODE)
+    for (int i = 0; i < kKuShapesHada; ++i) v.push_back(kKuShapeHada + i);
+  return v;
 }
 
 template <typename T>
 static hipError_t launch_ku_t(hipStream_t s, KuEpi epi, const KuArgsT<T> &a, const KappaT<T> &kap,
                               const Reducer &red, const Fin &fin, int shape) {
-  if (shape < 0) shape = ku_shape_for(a.g, epi);
+  if (shape < 0) shape = ku_shape_for(a.g, epi, TOPO_KU_AUTO);
   if constexpr (std::is_same<T, float>::value) {
     if (shape == kKuShapeMfma || shape == kKuShapeMfmaBf16) return launch_ku_mfma(s, epi, a, shape == kKuShapeMfmaBf16);
   }
   int nparts = 0;
   hipError_t e;
+  if (shape >= kKuShapeHada && shape < kKuShapeHada + kKuShapesHada) {
+    e = launch_ku_hada<T>(s, epi, a, kap, red, shape - kKuShapeHada, &nparts);
+    if (e != hipSuccess) return e;
+    if (ku_reduces(epi, a)) return launch_finalize(s, red, nparts, 1, fin, a.skip);
+    return hipSuccess;
+  }
   switch (shape) {
     case 0: e = launch_ku_shape<8, 256>(s, epi, a, kap, red, &nparts); break;
     case 1: e = launch_ku_shape<8, 128>(s, epi, a, kap, red, &nparts); break;

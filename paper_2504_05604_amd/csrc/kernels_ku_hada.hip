@@ -1,0 +1,278 @@
+// Element-column stiffness operator: y = K u with K = sum_e E_e KE (the Finite
+// Element Analysis section), computed element by element in the per-axis
+// sum/difference basis of the element's corners, where KE splits into eight
+// parity blocks with 8 distinct entries (ke_code.h).  Per element that is
+//   h = H u_e        (sum/difference passes: additions only),
+//   g = E_e M h      (21 multiply-adds with the E-scaled block entries),
+//   y_e = H^T g      (sum/difference passes),
+// instead of the 576 multiply-adds of the 24 x 24 element mat-vec.
+//
+// Work decomposition: a block owns a tile of (TX-1) x (TY-1) node columns and a
+// slab of KZ node planes.  Its TX x TY threads each own one element column
+// (i0-1+tx, j0-1+ty) and march up through its element layers.  A node plane is
+// transformed in x and y once, when it is loaded; the z pass then forms the
+// element's modes from the planes below and above.  Node plane L collects the
+// top face of element layer L-1 and the bottom face of layer L, which are added
+// while still in the xy basis and transformed back once per plane.  The four
+// element columns around a node column hand their corner contributions over
+// through LDS and are summed in a fixed order (deterministic, no atomics); the
+// thread whose element has the node as its (+x, +y) corner finishes the node
+// with the fused epilogue.  The tile's last row and column of threads compute
+// halo elements only.
+//
+// Fixed dofs: inputs are required to be zero there; see ku_epilogue.h.
+#include <algorithm>
+
+#include "internal.h"
+#include "ke_code.h"
+#include "ku_epilogue.h"
+#include "reduce_dev.h"
+
+namespace topo {
+
+template <int EPI, int KZ, int TX, int TY, bool PF, typename T>
+__global__ __launch_bounds__(TX * TY) void ku_hada_kernel(KuArgsT<T> a, HadaW<T> hw, int tiles_x,
+                                                         int tiles_xy, double *partials) {
+  if (a.skip && *a.skip) return;
+  constexpr int NT = TX * TY;
+  // corner contributions (0,0), (1,0), (0,1) of every thread's element column,
+  // double-buffered over node planes so one barrier per plane suffices
+  __shared__ T xch[2][3][3][NT];
+  const Grid g = a.g;
+  const int NX = g.NX(), NY = g.NY(), NZ = g.NZ();
+  const int64_t plane = (int64_t)NX * NY;
+  const int tile = xcd_tile(linear_block(), gridDim.x * gridDim.y);
+  const int txy = tile % tiles_xy, slab = tile / tiles_xy;
+  const int tid = threadIdx.x, tx = tid % TX, ty = tid / TX;
+  const int ie = (txy % tiles_x) * (TX - 1) - 1 + tx;
+  const int je = (txy / tiles_x) * (TY - 1) - 1 + ty;
+  const int k0 = slab * KZ, k1 = min(k0 + KZ, NZ);
+  const bool elem_xy = ie >= 0 && ie < g.nx && je >= 0 && je < g.ny;
+  const bool owner = tx < TX - 1 && ty < TY - 1 && ie + 1 <= g.nx && je + 1 <= g.ny;
+  constexpr bool kScaled = EpiTraits<EPI>::scaled_operand;
+  const T *__restrict__ u = kScaled ? a.b : a.u;
+  const T *__restrict__ dinv = a.dinv;
+
+  // Per-lane parts of the addresses, clamped into the grid, so every load is
+  // unconditional and in bounds: corner q of the element column sits at node
+  // column off[q] of every plane.  A clamped corner or plane only feeds elements
+  // outside the grid, whose modulus is taken as 0, so its (finite) values add
+  // exact zeros and need no masking.
+  uint32_t off[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int ci = min(max(ie + (q & 1), 0), g.nx), cj = min(max(je + (q >> 1), 0), g.ny);
+    off[q] = 3u * (uint32_t)(cj * NX + ci);
+  }
+  const uint32_t eoff = (uint32_t)(min(max(je, 0), g.ny - 1) * g.nx + min(max(ie, 0), g.nx - 1));
+  const uint32_t own = (uint32_t)((je + 1) * NX + (ie + 1));  // the owned node column (owners only)
+
+  // the operand at the element column's 4 corners on node plane kp
+  auto load_raw = [&](int kp, T(&v)[3][4]) {
+    const int64_t pbase = 3 * (int64_t)min(max(kp, 0), g.nz) * plane;  // uniform
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const T *__restrict__ up = u + pbase + off[q];
+      const T *__restrict__ dp = dinv + pbase + off[q];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        if constexpr (kScaled)
+          v[c][q] = up[c] * dp[c] * a.s0;
+        else
+          v[c][q] = up[c];
+      }
+    }
+  };
+  // x/y modes of a plane; self gets the operand at corner (1, 1), the node this
+  // thread may own
+  auto modes = [&](const T(&v)[3][4], T(&m)[3][4], T(&self)[3]) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      self[c] = v[c][3];
+      xy_pass(v[c], m[c]);
+    }
+  };
+
+  // modulus of element layer L of this column (0 outside the grid)
+  auto load_E = [&](int L) {
+    const T *__restrict__ Ep = a.E + (int64_t)min(max(L, 0), g.nz - 1) * g.nx * g.ny;  // uniform
+    const T Eraw = Ep[eoff];
+    return (elem_xy && L >= 0 && L < g.nz) ? Eraw : T(0);
+  };
+
+  // Memory order within a layer (vector loads retire in issue order, so a wait
+  // for one load waits for every older one): first the epilogue inputs of node
+  // plane L, then (PF) the next plane and modulus, which stay in flight through
+  // this layer's arithmetic and barrier (the barrier waits for LDS traffic only).
+  double dotv = 0.0;
+  T Pb[3][4], selfb[3];  // node plane L (xy modes) and the operand at the owned node
+  T ytp[3][4];           // top face of element layer L-1 (xy modes)
+  T nxt[3][4];           // PF: node plane L+1 and the modulus of layer L, one layer ahead
+  T Enxt = T(0);
+  {
+    T v[3][4];
+    load_raw(k0 - 1, v);
+    modes(v, Pb, selfb);
+  }
+  if constexpr (PF) {
+    load_raw(k0, nxt);
+    Enxt = load_E(k0 - 1);
+  }
+#pragma unroll
+  for (int q = 0; q <= KZ; ++q) {
+    const int L = k0 - 1 + q;  // element layer between node planes L and L+1
+    if (L >= k1) break;
+    const int64_t nL = (int64_t)L * plane + own;
+    EpiIn<T> in;
+    if (q > 0 && owner) ku_epi_load<EPI>(a, nL, dinv, in);
+    T Pt[3][4], selft[3];
+    T Ee;
+    if constexpr (PF) {
+      T cur[3][4];
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) cur[c][r] = nxt[c][r];
+      Ee = Enxt;
+      if (q < KZ && L + 1 < k1) {
+        load_raw(L + 2, nxt);
+        Enxt = load_E(L + 1);
+      }
+      modes(cur, Pt, selft);
+    } else {
+      T v[3][4];
+      load_raw(L + 1, v);
+      Ee = load_E(L);
+      modes(v, Pt, selft);
+    }
+    T w[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) w[k] = Ee * hw.w[k];
+    // element modes h[c][s], s = q + 4 z (h[c][0], the rigid translations, is not needed)
+    T h[3][8];
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        h[c][r] = Pb[c][r] + Pt[c][r];
+        h[c][r + 4] = Pb[c][r] - Pt[c][r];
+      }
+    T gm[3][8];
+    hada_blocks(w, h, gm);
+    // back in z: bottom face (node plane L) and top face (node plane L+1), xy modes
+    if (q > 0) {  // node plane L is owned by this slab
+      T cn[3][4];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        T acc[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc[r] = ytp[c][r] + (gm[c][r] + gm[c][r + 4]);
+        xy_pass(acc, cn[c]);
+      }
+      T(&buf)[3][3][NT] = xch[q & 1];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        buf[0][c][tid] = cn[c][0];
+        buf[1][c][tid] = cn[c][1];
+        buf[2][c][tid] = cn[c][2];
+      }
+      __syncthreads();
+      if (owner) {
+        // elements (ie, je), (ie+1, je), (ie, je+1), (ie+1, je+1) around node (ie+1, je+1)
+        T Au[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+          Au[c] = ((cn[c][3] + buf[2][c][tid + 1]) + buf[1][c][tid + TX]) + buf[0][c][tid + TX + 1];
+        ku_epi_finish<EPI>(a, nL, in, selfb, Au, dotv);
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        ytp[c][r] = gm[c][r] - gm[c][r + 4];
+        Pb[c][r] = Pt[c][r];
+      }
+      selfb[c] = selft[c];
+    }
+  }
+  ku_block_reduce<EPI>(a, dotv, partials);
+}
+
+template <int KZ, int TX, int TY>
+struct HadaShape {
+  static int tiles_x(const Grid &g) { return (g.NX() + TX - 2) / (TX - 1); }
+  static int tiles_y(const Grid &g) { return (g.NY() + TY - 2) / (TY - 1); }
+  static int64_t blocks(const Grid &g) {
+    return (int64_t)tiles_x(g) * tiles_y(g) * ((g.NZ() + KZ - 1) / KZ);
+  }
+};
+
+template <int KZ, int TX, int TY, bool PF, typename T>
+static hipError_t launch_hada_shape(hipStream_t s, KuEpi epi, const KuArgsT<T> &a, const KappaT<T> &kap,
+                                    const Reducer &red, int *nparts_out) {
+  using S = HadaShape<KZ, TX, TY>;
+  const int tx = S::tiles_x(a.g), txy = tx * S::tiles_y(a.g);
+  const int64_t nb = S::blocks(a.g);
+  if (nb > INT32_MAX) return hipErrorInvalidValue;
+  *nparts_out = (int)nb;
+  if (ku_reduces(epi, a) && nb > red.max_blocks) return hipErrorInvalidValue;
+  const HadaW<T> hw = hada_work(kap);
+  const dim3 grid((unsigned)nb);
+#define TOPO_KU_CASE(E) \
+  case E: ku_hada_kernel<E, KZ, TX, TY, PF, T><<<grid, TX * TY, 0, s>>>(a, hw, tx, txy, red.partials); break;
+  switch (epi) {
+    TOPO_KU_CASE(KU_STORE)
+    TOPO_KU_CASE(KU_STORE_DOT)
+    TOPO_KU_CASE(KU_RESID)
+    TOPO_KU_CASE(KU_RES0)
+    TOPO_KU_CASE(KU_CHEB0)
+    TOPO_KU_CASE(KU_CHEB)
+    TOPO_KU_CASE(KU_CHEB_ADD)
+    TOPO_KU_CASE(KU_RESUPD)
+    TOPO_KU_CASE(KU_RESID_START)
+    default: return hipErrorInvalidValue;
+  }
+#undef TOPO_KU_CASE
+  return hipGetLastError();
+}
+
+// element-column shapes (index relative to kKuShapeHada): KZ x TX x TY, and
+// whether the next node plane is loaded one layer ahead.  Every shape runs the
+// same arithmetic in the same order (a node always sums its four element
+// columns in the same order), so they give bit-identical results.
+#define TOPO_HADA_SHAPES(X) \
+  X(0, 8, 32, 8, false)     \
+  X(1, 8, 16, 16, false)    \
+  X(2, 4, 16, 8, true)      \
+  X(3, 2, 8, 8, true)       \
+  X(4, 1, 8, 8, false)      \
+  X(5, 8, 32, 8, true)      \
+  X(6, 8, 16, 16, true)
+
+template <typename T>
+hipError_t launch_ku_hada(hipStream_t s, KuEpi epi, const KuArgsT<T> &a, const KappaT<T> &kap,
+                          const Reducer &red, int which, int *nparts) {
+  switch (which) {
+#define TOPO_HADA_LAUNCH(I, KZ, TX, TY, PF) \
+  case I: return launch_hada_shape<KZ, TX, TY, PF>(s, epi, a, kap, red, nparts);
+    TOPO_HADA_SHAPES(TOPO_HADA_LAUNCH)
+#undef TOPO_HADA_LAUNCH
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template hipError_t launch_ku_hada<double>(hipStream_t, KuEpi, const KuArgsT<double> &,
+                                           const KappaT<double> &, const Reducer &, int, int *);
+template hipError_t launch_ku_hada<float>(hipStream_t, KuEpi, const KuArgsT<float> &,
+                                          const KappaT<float> &, const Reducer &, int, int *);
+
+int64_t ku_hada_max_blocks(const Grid &g) {
+  int64_t m = 0;
+#define TOPO_HADA_BLOCKS(I, KZ, TX, TY, PF) m = std::max<int64_t>(m, HadaShape<KZ, TX, TY>::blocks(g));
+  TOPO_HADA_SHAPES(TOPO_HADA_BLOCKS)
+#undef TOPO_HADA_BLOCKS
+  return m;
+}
+
+}  // namespace topo

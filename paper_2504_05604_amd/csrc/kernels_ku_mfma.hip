@@ -211,8 +211,10 @@ __global__ __launch_bounds__(256) void ku_mfma_kernel(KuArgsT<float> a, const fl
             const float r = a.res[dof] - Ac;
             const float dn = a.c1 * self[c] + a.c2 * r * a.dinv[dof];
             const float xn = a.x[dof] + dn + (EPI == KU_CHEB_ADD ? self[c] : 0.0f);
-            a.res[dof] = r;
-            a.dout[dof] = dn;
+            if (a.dout) {  // not the last step: its residual and direction are still needed
+              a.res[dof] = r;
+              a.dout[dof] = dn;
+            }
             a.x[dof] = xn;
             if (a.dot_with) dotv = fma((double)a.dot_with[dof], (double)xn, dotv);
           } else if constexpr (EPI == KU_RESUPD) {

@@ -5,10 +5,11 @@
 // costs more than the work.  Here one workgroup walks the whole tail of the
 // hierarchy (pre-smoothing and restriction down to the coarsest level, the
 // dense solve, prolongation and post-smoothing back up), with a workgroup
-// barrier between passes.  Each pass is the same arithmetic as the
-// corresponding multi-block kernels, written per node: the operator gathers
-// the up to 8 elements around the node and applies the 24 x 24 element matrix
-// to each element's displacement vector.
+// barrier between passes.  An operator pass runs in two phases: one thread per
+// element forms the element's product in the sum/difference basis of its
+// corners (ke_code.h) into an LDS scratch array, then one thread per node adds
+// the products of the up to 8 elements around it in a fixed order and applies
+// the pass's vector update.
 #include "internal.h"
 #include "ke_code.h"
 
@@ -16,43 +17,79 @@ namespace topo {
 
 namespace {
 
-// y = (A u) at the three dofs of node (i, j, k), free rows only (every operand
-// is zero on fixed dofs; callers handle fixed rows).  The 3x3x3 neighbourhood
-// of u is gathered into registers once; the element matrix entries are the
-// compile-time sign/index tables applied to kappa (kernel arguments, i.e.
-// scalar registers), so the 576 multiply-adds read no memory.
+// Phase 1 of an operator pass: every element's product E_e KE u_e, stored per
+// corner q = dx + 2 dy + 4 dz and component c at scr[(3 q + c) ne + e].  The
+// caller synchronises before phase 2 reads it.
 template <typename T>
-__device__ __forceinline__ void node_apply(const Grid &g, const T *__restrict__ E, const KappaT<T> &kap,
-                                           const T *__restrict__ u, int i, int j, int k, T y[3]) {
-  T U[27][3];
+__device__ void element_products(const Grid &g, const T *__restrict__ E, const HadaW<T> &hw,
+                                 const T *__restrict__ u, T *__restrict__ scr) {
+  const int ne = (int)g.nel(), NX = g.NX(), NY = g.NY();
+  for (int e = threadIdx.x; e < ne; e += blockDim.x) {
+    const int i = e % g.nx, j = (e / g.nx) % g.ny, k = e / (g.nx * g.ny);
+    const int n0 = i + NX * (j + NY * k);
+    T Pb[3][4], Pt[3][4];
 #pragma unroll
-  for (int q = 0; q < 27; ++q) {
-    const int ii = i + q % 3 - 1, jj = j + (q / 3) % 3 - 1, kk = k + q / 9 - 1;
-    const bool in = ii >= 0 && ii <= g.nx && jj >= 0 && jj <= g.ny && kk >= 0 && kk <= g.nz;
-    const int64_t m = in ? ii + (int64_t)g.NX() * (jj + (int64_t)g.NY() * kk) : 0;
+    for (int c = 0; c < 3; ++c) {
+      T vb[4], vt[4];
 #pragma unroll
-    for (int d = 0; d < 3; ++d) U[q][d] = in ? u[3 * m + d] : T(0);
+      for (int q = 0; q < 4; ++q) {
+        const int n = n0 + (q & 1) + NX * (q >> 1);
+        vb[q] = u[3 * n + c];
+        vt[q] = u[3 * (n + NX * NY) + c];
+      }
+      xy_pass(vb, Pb[c]);
+      xy_pass(vt, Pt[c]);
+    }
+    T h[3][8];
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        h[c][r] = Pb[c][r] + Pt[c][r];
+        h[c][r + 4] = Pb[c][r] - Pt[c][r];
+      }
+    const T Ee = E[e];
+    T w[8];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) w[t] = Ee * hw.w[t];
+    T gm[3][8];
+    hada_blocks(w, h, gm);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      T yb[4], yt[4], ob[4], ot[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        yb[r] = gm[c][r] + gm[c][r + 4];
+        yt[r] = gm[c][r] - gm[c][r + 4];
+      }
+      xy_pass(yb, ob);
+      xy_pass(yt, ot);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        scr[(3 * q + c) * ne + e] = ob[q];
+        scr[(3 * (q + 4) + c) * ne + e] = ot[q];
+      }
+    }
   }
+}
+
+// Phase 2: (A u) at the three dofs of node (i, j, k), free rows only (every
+// operand is zero on fixed dofs; callers handle fixed rows), the elements
+// around the node added in a fixed order.
+template <typename T>
+__device__ __forceinline__ void node_product(const Grid &g, const T *__restrict__ scr, int i, int j, int k,
+                                             T y[3]) {
+  const int ne = (int)g.nel();
   y[0] = y[1] = y[2] = T(0);
 #pragma unroll
   for (int e8 = 0; e8 < 8; ++e8) {
     const int ex = e8 & 1, ey = (e8 >> 1) & 1, ez = e8 >> 2;
     const int ei = i - 1 + ex, ej = j - 1 + ey, ek = k - 1 + ez;
     if (ei < 0 || ei >= g.nx || ej < 0 || ej >= g.ny || ek < 0 || ek >= g.nz) continue;
-    const int a = corner_of(1 - ex, 1 - ey, 1 - ez);  // this node's corner in the element
-    const T Ee = E[ei + (int64_t)g.nx * (ej + (int64_t)g.ny * ek)];
-    T t[3] = {T(0), T(0), T(0)};
+    const int e = ei + g.nx * (ej + g.ny * ek);
+    const int q = (1 - ex) + 2 * (1 - ey) + 4 * (1 - ez);  // this node's corner in the element
 #pragma unroll
-    for (int b = 0; b < 8; ++b) {
-      // corner b of the element sits at offset (ex-1+cx, ey-1+cy, ez-1+cz) from the node
-      const int q = (ex + cx(b)) + 3 * (ey + cy(b)) + 9 * (ez + cz(b));
-#pragma unroll
-      for (int c = 0; c < 3; ++c)
-#pragma unroll
-        for (int d = 0; d < 3; ++d) t[c] = fma(TOPO_KE(kap, 3 * a + c, 3 * b + d), U[q][d], t[c]);
-    }
-#pragma unroll
-    for (int c = 0; c < 3; ++c) y[c] = fma(Ee, t[c], y[c]);
+    for (int c = 0; c < 3; ++c) y[c] += scr[(3 * q + c) * ne + e];
   }
 }
 
@@ -64,7 +101,7 @@ __device__ __forceinline__ void node_ijk(const Grid &g, int n, int &i, int &j, i
 
 // pre-smoothing from x = 0: on exit x and res = b - A x
 template <typename T>
-__device__ void pre_smooth(const TailArgs<T> &a, const TailLevel<T> &L) {
+__device__ void pre_smooth(const TailArgs<T> &a, const TailLevel<T> &L, T *scr) {
   const Grid &g = L.g;
   const int nn = (int)g.nnodes();
   for (int d = threadIdx.x; d < 3 * nn; d += blockDim.x) {
@@ -77,11 +114,13 @@ __device__ void pre_smooth(const TailArgs<T> &a, const TailLevel<T> &L) {
   T *dc = L.d0, *dn = L.d1;
   for (int s = 1; s <= a.deg; ++s) {
     const bool last = s == a.deg;
+    element_products(g, L.E, a.hw, dc, scr);
+    __syncthreads();
     for (int n = threadIdx.x; n < nn; n += blockDim.x) {
       int i, j, k;
       node_ijk(g, n, i, j, k);
       T y[3];
-      node_apply(g, L.E, a.kap, dc, i, j, k, y);
+      node_product(g, scr, i, j, k, y);
       const uint8_t f = L.fixed[n];
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
@@ -104,15 +143,17 @@ __device__ void pre_smooth(const TailArgs<T> &a, const TailLevel<T> &L) {
 
 // post-smoothing from the current x
 template <typename T>
-__device__ void post_smooth(const TailArgs<T> &a, const TailLevel<T> &L) {
+__device__ void post_smooth(const TailArgs<T> &a, const TailLevel<T> &L, T *scr) {
   const Grid &g = L.g;
   const int nn = (int)g.nnodes();
   // res = b - A x; d0 = D^-1 res / theta (added to x together with the next step)
+  element_products(g, L.E, a.hw, L.x, scr);
+  __syncthreads();
   for (int n = threadIdx.x; n < nn; n += blockDim.x) {
     int i, j, k;
     node_ijk(g, n, i, j, k);
     T y[3];
-    node_apply(g, L.E, a.kap, L.x, i, j, k, y);
+    node_product(g, scr, i, j, k, y);
     const uint8_t f = L.fixed[n];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
@@ -130,11 +171,13 @@ __device__ void post_smooth(const TailArgs<T> &a, const TailLevel<T> &L) {
   }
   T *dc = L.d0, *dn = L.d1;
   for (int s = 1; s < a.deg; ++s) {
+    element_products(g, L.E, a.hw, dc, scr);
+    __syncthreads();
     for (int n = threadIdx.x; n < nn; n += blockDim.x) {
       int i, j, k;
       node_ijk(g, n, i, j, k);
       T y[3];
-      node_apply(g, L.E, a.kap, dc, i, j, k, y);
+      node_product(g, scr, i, j, k, y);
       const uint8_t f = L.fixed[n];
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
@@ -277,10 +320,16 @@ __global__ __launch_bounds__(kTailThreads) void vcycle_tail_kernel(TailArgs<T> a
     }
   }
   __syncthreads();
+  // element scratch after the levels and the solve partials
+  auto scratch = [&]() {
+    size_t ofs = tail_solve_bytes<T>(a.ncoarse);
+    for (int q = 0; q < a.nlev; ++q) ofs += tail_level_bytes<T>(a.L[q].g);
+    return reinterpret_cast<T *>(tail_smem + ofs);
+  };
   const int last = a.nlev - 1;
   for (int l = 0; l < last; ++l) {
     const TailLevel<T> F = lev(l), Cl = lev(l + 1);
-    pre_smooth(a, F);
+    pre_smooth(a, F, scratch());
     restrict_to(F, Cl);
   }
   // coarsest level: x = Ainv b.  Each row is split into kColParts contiguous
@@ -313,7 +362,7 @@ __global__ __launch_bounds__(kTailThreads) void vcycle_tail_kernel(TailArgs<T> a
   for (int l = last - 1; l >= 0; --l) {
     const TailLevel<T> F = lev(l), Cl = lev(l + 1);
     prolong_add(F, Cl);
-    post_smooth(a, F);
+    post_smooth(a, F, scratch());
   }
   {
     const TailLevel<T> F = lev(0);
@@ -330,7 +379,7 @@ hipError_t prepare_vcycle_tail_t(size_t smem_bytes) {
 template <typename T>
 hipError_t launch_vcycle_tail_t(hipStream_t s, const TailArgs<T> &a) {
   if (a.nlev < 1 || a.nlev > kTailMaxLevels || a.deg < 1 || a.deg >= kTailMaxDeg) return hipErrorInvalidValue;
-  size_t bytes = tail_solve_bytes<T>(a.ncoarse);
+  size_t bytes = tail_solve_bytes<T>(a.ncoarse) + tail_scratch_bytes<T>(a.L[0].g);
   for (int l = 0; l < a.nlev; ++l) bytes += tail_level_bytes<T>(a.L[l].g);
   if (bytes > kTailMaxLds) return hipErrorInvalidValue;
   vcycle_tail_kernel<T><<<1, kTailThreads, bytes, s>>>(a);

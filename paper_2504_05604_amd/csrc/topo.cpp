@@ -121,7 +121,10 @@ static hipError_t dalloc(T **p, size_t count) {
 }
 
 constexpr double kChebRatio = 30.0;  // Chebyshev interval [lam_max / ratio, lam_max]
-constexpr int64_t kFuseFirstStepBelow = 400000;  // nodes: fuse the first smoothing step below
+// node-column kernel: fuse the first smoothing step into the operator pass below
+// this many nodes (above, that kernel is arithmetic bound and forming the operand
+// on the fly doubles its loads); the element-column kernel always fuses it
+constexpr int64_t kFuseFirstStepBelow = 400000;
 
 // Multigrid level data in one precision.
 template <typename T>
@@ -268,6 +271,8 @@ extern "C" void topo_default_opts(topo_opts *o) {
   o->autotune = 0;
   o->coarse_tail_nodes = 1024;
   o->mfma_smoothing = 0;
+  o->ku_kernel = TOPO_KU_AUTO;
+  o->ku_shape = -1;
 }
 
 extern "C" const char *topo_last_error(void) { return g_err; }
@@ -316,6 +321,12 @@ static topo_status validate(const topo_problem *P, const topo_opts *O) {
   if (O->mg_levels < 0 || O->mg_levels > 16) return set_error("mg_levels must lie in [0, 16]"), TOPO_EINVAL;
   if (O->coarse_tail_nodes < 0) return set_error("coarse_tail_nodes must be >= 0"), TOPO_EINVAL;
   if (O->warm_start < 0 || O->warm_start > 3) return set_error("warm_start must be 0, 1, 2 or 3"), TOPO_EINVAL;
+  if (O->ku_kernel != TOPO_KU_AUTO && O->ku_kernel != TOPO_KU_NODE && O->ku_kernel != TOPO_KU_ELEMENT)
+    return set_error("unknown ku_kernel %d", O->ku_kernel), TOPO_EINVAL;
+  if (!(O->ku_shape == -1 || (O->ku_shape >= 0 && O->ku_shape < kKuShapes) ||
+        (O->ku_shape >= kKuShapeHada && O->ku_shape < kKuShapeHada + kKuShapesHada)))
+    return set_error("ku_shape must be -1, 0..%d or %d..%d", kKuShapes - 1, kKuShapeHada,
+                     kKuShapeHada + kKuShapesHada - 1), TOPO_EINVAL;
   return TOPO_OK;
 }
 
@@ -497,7 +508,10 @@ extern "C" topo_status topo_setup(const topo_problem *P, const topo_opts *O, voi
     const int nco = (int)dims.back().ndof();
     size_t bytes = level_bytes(dims.back()) + (fp32 ? tail_solve_bytes<float>(nco) : tail_solve_bytes<double>(nco));
     size_t t = dims.size() - 1;
-    while (t > 1 && dims[t - 1].nnodes() <= O->coarse_tail_nodes && bytes + level_bytes(dims[t - 1]) <= kTailMaxLds &&
+    // the element scratch is sized by the finest tail level, the one being added
+    auto scratch_bytes = [&](const Grid &g) { return fp32 ? tail_scratch_bytes<float>(g) : tail_scratch_bytes<double>(g); };
+    while (t > 1 && dims[t - 1].nnodes() <= O->coarse_tail_nodes &&
+           bytes + level_bytes(dims[t - 1]) + scratch_bytes(dims[t - 1]) <= kTailMaxLds &&
            dims.size() - t < (size_t)kTailMaxLevels) {
       bytes += level_bytes(dims[t - 1]);
       --t;
@@ -508,10 +522,10 @@ extern "C" topo_status topo_setup(const topo_problem *P, const topo_opts *O, voi
   }
 
   // reductions
-  // enough partials for every K.u launch shape (the smallest, 64 threads per
-  // one-node column, has a block per 64 columns per node plane) and the vector kernels
+  // enough partials for every K.u launch shape on the finest grid and for the vector kernels
   const int64_t nb_nodes = (ctx->nnodes + 255) / 256;
-  const int64_t nb_ku = ((int64_t)g.NX() * g.NY() + 63) / 64 * g.NZ();
+  const int64_t nb_ku = ku_max_blocks(g);
+  if (nb_ku >= INT32_MAX) return set_error("grid too large for the K.u launch shapes"), TOPO_EINVAL;
   ctx->red.max_blocks = (int)std::max<int64_t>({16384, nb_nodes + 1, nb_ku + 1});
   TOPO_ALLOC(ctx->red.partials, (size_t)ctx->red.max_blocks * kMaxRed);
   TOPO_ALLOC(ctx->sc, 1);
@@ -554,6 +568,11 @@ extern "C" topo_status topo_setup(const topo_problem *P, const topo_opts *O, voi
     TOPO_HIP(hipMemcpyAsync(ctx->volw, hv.data(), ctx->nel * sizeof(double), hipMemcpyHostToDevice, s));
     TOPO_HIP(hipStreamSynchronize(s));  // hv goes out of scope
   }
+  // launch shapes by grid size within the chosen K.u kernel (the matrix-core
+  // modes above keep theirs); the autotuner may replace them
+  for (Level &L : ctx->lv)
+    if (L.shape < 0) L.shape = O->ku_shape >= 0 ? O->ku_shape : ku_shape_for(L.g, KU_CHEB, O->ku_kernel);
+  ctx->shape_cg = O->ku_shape >= 0 ? O->ku_shape : ku_shape_for(g, KU_STORE_DOT, O->ku_kernel);
   if (O->autotune) {
     st = autotune(ctx);
     if (st != TOPO_OK) return st;
@@ -702,15 +721,15 @@ static topo_status projected_start(topo_ctx *ctx) {
 // Launch-shape autotuner: times every K.u launch shape (nodes per thread column
 // x threads per block) on this context's grids and keeps the fastest, for the CG
 // product on the finest level and for the smoothing passes on every level.
-static topo_status time_ku_shapes(topo_ctx *ctx, int n_shapes, const std::function<hipError_t(int)> &launch,
-                                  int *best) {
+static topo_status time_ku_shapes(topo_ctx *ctx, const std::vector<int> &shapes,
+                                  const std::function<hipError_t(int)> &launch, int *best) {
   hipStream_t s = ctx->stream;
   hipEvent_t e0, e1;
   TOPO_HIP(hipEventCreate(&e0));
   TOPO_HIP(hipEventCreate(&e1));
   float best_ms = 0.f;
   *best = -1;
-  for (int shape = 0; shape < n_shapes; ++shape) {
+  for (int shape : shapes) {
     TOPO_HIP(launch(shape));  // warm-up
     TOPO_HIP(hipEventRecord(e0, s));
     for (int r = 0; r < 3; ++r) TOPO_HIP(launch(shape));
@@ -740,8 +759,7 @@ static topo_status tune_smoothing(topo_ctx *ctx, Level &L) {
   c.c2 = (T)0.5;
   const KappaT<T> &kap = kappa_of<T>(ctx);
   // single precision may also take the matrix-core kernel (same arithmetic up to rounding)
-  const int n_shapes = std::is_same<T, float>::value ? kKuShapes + 1 : kKuShapes;
-  return time_ku_shapes(ctx, n_shapes, [&](int shape) {
+  return time_ku_shapes(ctx, ku_tunable_shapes(std::is_same<T, float>::value, ctx->opts.ku_kernel), [&](int shape) {
     return launch_ku(s, KU_CHEB, c, kap, ctx->red, fin_sum(nullptr), shape);
   }, &L.shape);
 }
@@ -754,7 +772,7 @@ static topo_status autotune(topo_ctx *ctx) {
   TOPO_HIP(hipMemsetAsync(ctx->p, 0, nd * sizeof(double), s));
   KuArgs a = ku_args(ctx, L0, ctx->p);
   a.y = ctx->q;
-  topo_status st = time_ku_shapes(ctx, kKuShapes, [&](int shape) {
+  topo_status st = time_ku_shapes(ctx, ku_tunable_shapes(false, ctx->opts.ku_kernel), [&](int shape) {
     return launch_ku(s, KU_STORE_DOT, a, ctx->kap, ctx->red, fin_sum(&ctx->sc->red[0]), shape);
   }, &ctx->shape_cg);
   if (st != TOPO_OK) return st;
@@ -829,9 +847,9 @@ static topo_status pre_smooth(topo_ctx *ctx, Level &L, const int *skip) {
     return TOPO_OK;
   }
   double rho_new = 1.0 / (2.0 * ch.sigma - rho);
-  if (L.g.nnodes() >= kFuseFirstStepBelow) {
-    // large grids: the operator pass is arithmetic bound and forming the operand
-    // on the fly doubles its loads, so the first direction gets its own pass
+  const bool element_kernel = L.shape >= kKuShapeHada && L.shape < kKuShapeHada + kKuShapesHada;
+  if (L.g.nnodes() >= kFuseFirstStepBelow && !element_kernel) {
+    // large grids, node-column kernel: the first direction gets its own pass
     TOPO_HIP(launch_cheb_first(s, L.g.ndof(), B.b, B.dinv, (T)(1.0 / ch.theta), dnext, B.x, B.res, skip));
     KuArgsT<T> c = ku_args_t<T>(L, dnext);
     c.res = B.res;
@@ -904,6 +922,7 @@ static topo_status post_smooth(topo_ctx *ctx, Level &L, const int *skip, const T
     c.c1 = (T)(rho_new * rho);
     c.c2 = (T)(2.0 * rho_new / ch.delta);
     c.dot_with = (k == deg - 1) ? dot_with : nullptr;
+    if (k == deg - 1) c.dout = nullptr;  // last step: only x is needed afterwards
     c.skip = skip;
     TOPO_HIP(launch_ku(s, k == 1 ? KU_CHEB_ADD : KU_CHEB, c, kap, ctx->red, fin, L.shape));
     std::swap(dcur, dnext);
@@ -937,7 +956,7 @@ static topo_status vcycle_tail(topo_ctx *ctx, const int *skip) {
   }
   a.Ainv = coarse_inverse<T>(ctx);
   a.ncoarse = ctx->ncoarse;
-  a.kap = kappa_of<T>(ctx);
+  a.hw = hada_work(kappa_of<T>(ctx));
   a.deg = ctx->opts.cheb_degree;
   const Cheb ch(ctx->lam_max);
   a.s0 = (T)(1.0 / ch.theta);
@@ -1159,7 +1178,7 @@ extern "C" topo_status topo_apply_K(topo_ctx *ctx, const double *d_xphys, const 
   TOPO_HIP(launch_copy_masked(s, ctx->nnodes, L0.fixed, d_u, ctx->tmp));
   KuArgs a = ku_args(ctx, L0, ctx->tmp);
   a.y = d_y;
-  TOPO_HIP(launch_ku(s, KU_STORE, a, ctx->kap, ctx->red, fin_sum(nullptr)));
+  TOPO_HIP(launch_ku(s, KU_STORE, a, ctx->kap, ctx->red, fin_sum(nullptr), ctx->shape_cg));
   // identity rows return the caller's u (not the zeroed copy) on fixed dofs
   TOPO_HIP(launch_copy_fixed(s, ctx->nnodes, L0.fixed, d_u, d_y));
   return TOPO_OK;
@@ -1365,9 +1384,10 @@ extern "C" topo_status topo_time_operator(topo_ctx *ctx, int32_t reps, double *h
   hipEvent_t e0, e1;
   TOPO_HIP(hipEventCreate(&e0));
   TOPO_HIP(hipEventCreate(&e1));
-  TOPO_HIP(launch_ku(s, KU_STORE_DOT, a, ctx->kap, ctx->red, fin_sum(&ctx->sc->red[0])));  // warm caches
+  TOPO_HIP(launch_ku(s, KU_STORE_DOT, a, ctx->kap, ctx->red, fin_sum(&ctx->sc->red[0]), ctx->shape_cg));  // warm caches
   TOPO_HIP(hipEventRecord(e0, s));
-  for (int i = 0; i < reps; ++i) TOPO_HIP(launch_ku(s, KU_STORE_DOT, a, ctx->kap, ctx->red, fin_sum(&ctx->sc->red[0])));
+  for (int i = 0; i < reps; ++i)
+    TOPO_HIP(launch_ku(s, KU_STORE_DOT, a, ctx->kap, ctx->red, fin_sum(&ctx->sc->red[0]), ctx->shape_cg));
   TOPO_HIP(hipEventRecord(e1, s));
   TOPO_HIP(hipEventSynchronize(e1));
   float ms = 0.f;

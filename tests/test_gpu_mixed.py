@@ -1,7 +1,8 @@
 """Single-precision multigrid preconditioner inside FP64 flexible CG: the
 solution meets the same FP64 residual tolerance, and the SIMP trajectory stays
-within stated bounds of the FP64 one.  Variants: FP32 on the vector units,
-FP32 on the matrix cores (mfma_smoothing), BF16 operands on the matrix cores."""
+within stated bounds of the FP64 one.  Variants: FP32 on the vector units (both
+K.u kernels), FP32 on the matrix cores (mfma_smoothing), BF16 operands on the
+matrix cores."""
 
 import numpy as np
 import pytest
@@ -19,6 +20,7 @@ KE = element_stiffness(0.3)
 
 VARIANTS = {
     "fp32": dict(precision=topo.PREC_FP32),
+    "fp32_node": dict(precision=topo.PREC_FP32, ku_kernel=topo.KU_NODE),
     "fp32_mfma": dict(precision=topo.PREC_FP32, mfma_smoothing=1),
     "bf16": dict(precision=topo.PREC_BF16),
 }

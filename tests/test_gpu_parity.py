@@ -47,6 +47,9 @@ def fixed_mask(p):
 
 
 CASES = ["small", "ragged", "ragged_odd"]
+# the two K.u kernels: element columns in the sum/difference basis (the default)
+# and node columns applying the element-matrix rows
+KERNELS = {"element": 2, "node": 1}
 
 
 def make_case(name):
@@ -57,24 +60,26 @@ def make_case(name):
     return ragged_problem(2, (17, 9, 11), rmin=3.0)
 
 
+@pytest.mark.parametrize("kernel", list(KERNELS))
 @pytest.mark.parametrize("case", CASES)
-def test_apply_K_matches_oracle(case):
+def test_apply_K_matches_oracle(case, kernel):
     p = make_case(case)
     x = synth.random_density(3, p.nel, 0.0, 1.0)
     u = synth.random_vector(4, p.ndof)
     E = fem.simp_modulus(x, p.E0, p.Emin, p.penal)
     ref = fem.apply_K_reduced(E, KE, fem.element_dofs(p.nelx, p.nely, p.nelz), u, p.fixed_dofs)
-    with topo.Context(p) as ctx:
+    with topo.Context(p, topo.default_opts(ku_kernel=KERNELS[kernel])) as ctx:
         y = torch.empty(p.ndof, dtype=torch.float64, device="cuda")
         ctx.apply_K(dev(x), dev(u), y)
         got = host(y)
     assert np.abs(got - ref).max() <= 1e-13 * np.abs(ref).max()
 
 
+@pytest.mark.parametrize("kernel", list(KERNELS))
 @pytest.mark.parametrize("case", CASES)
 @pytest.mark.parametrize("precond", ["mg140", "mg400", "mg400deg3", "mg140deg1", "mg140_notail",
                                      "mg140_tail4000", "jacobi"])
-def test_preconditioner_matches_oracle(case, precond):
+def test_preconditioner_matches_oracle(case, precond, kernel):
     """The coarse levels run as one single-workgroup launch below coarse_tail_nodes
     nodes (default 1024); _notail runs every level with the per-level kernels,
     _tail4000 moves more levels into the single launch."""
@@ -90,12 +95,12 @@ def test_preconditioner_matches_oracle(case, precond):
         V = mg.VCycle(p, E, KE, degree=deg, max_coarse_dof=coarse)
         ref = V.apply(r)
         opts = topo.default_opts(precond=topo.PRECOND_MG, mg_max_coarse_dof=coarse, cheb_degree=deg,
-                                 coarse_tail_nodes=tail)
+                                 coarse_tail_nodes=tail, ku_kernel=KERNELS[kernel])
     else:
         K = mg.with_identity_rows(fem.assemble(E, KE, fem.element_dofs(p.nelx, p.nely, p.nelz), p.ndof),
                                   fixed_mask(p))
         ref = r / K.diagonal()
-        opts = topo.default_opts(precond=topo.PRECOND_JACOBI)
+        opts = topo.default_opts(precond=topo.PRECOND_JACOBI, ku_kernel=KERNELS[kernel])
     with topo.Context(p, opts) as ctx:
         if precond.startswith("mg"):
             assert ctx.mg_levels == len(V.levels)
@@ -105,9 +110,10 @@ def test_preconditioner_matches_oracle(case, precond):
     assert np.abs(got - ref).max() <= 1e-11 * np.abs(ref).max()
 
 
+@pytest.mark.parametrize("kernel", list(KERNELS))
 @pytest.mark.parametrize("case", CASES)
 @pytest.mark.parametrize("precond", ["mg", "jacobi"])
-def test_solve_matches_direct_solve(case, precond):
+def test_solve_matches_direct_solve(case, precond, kernel):
     p = make_case(case)
     x = synth.random_density(7, p.nel, 0.05, 1.0)
     E = fem.simp_modulus(x, p.E0, p.Emin, p.penal)
@@ -115,7 +121,7 @@ def test_solve_matches_direct_solve(case, precond):
     f = p.f.copy()
     f[p.fixed_dofs] = 0.0
     uref = fem.solve(K, f, p.fixed_dofs)
-    opts = topo.default_opts(rtol=1e-11, max_iters=5000,
+    opts = topo.default_opts(rtol=1e-11, max_iters=5000, ku_kernel=KERNELS[kernel],
                              precond=topo.PRECOND_MG if precond == "mg" else topo.PRECOND_JACOBI)
     with topo.Context(p, opts) as ctx:
         u = torch.zeros(p.ndof, dtype=torch.float64, device="cuda")
