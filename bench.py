@@ -24,9 +24,16 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "ms/SIMP iter @3.1M DOF; PCG iters+time to 1e-8 rel res, learned vs plain MG"
-FP64_VECTOR_PEAK_TFLOPS = 78.6   # MI355X: 256 CU x 2.4 GHz x 128 FP64 flop/clk
-KU_FLOP_PER_ELEMENT = 1152       # dense 24x24 KE times the element vector, 2 flop per MAC
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "ku_march_fp64_160x80x80_traffic.json")
+HBM_PEAK_GBS = 8000.0             # MI355X HBM3E, published
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "ku_element_fp64_160x80x80_traffic.json")
+
+
+def ku_algorithmic_bytes(p):
+    """Bytes a K.u launch with the p.q epilogue must move: u read and y written
+    (8 B per dof each), the element moduli read (8 B per element) and the
+    fixed-dof flags read (1 B per node)."""
+    nnodes = (p.nelx + 1) * (p.nely + 1) * (p.nelz + 1)
+    return 2 * 8 * p.ndof + 8 * p.nel + nnodes
 
 
 def ku_traffic_bytes():
@@ -362,13 +369,15 @@ def main():
     ku_equiv = float(pcg.mean() * ku_per_cg + 1.0)
 
     ku_ms = ctx.time_operator(args.ku_reps)
-    flops = KU_FLOP_PER_ELEMENT * p.nel
-    achieved = flops / (ku_ms * 1e-3) / 1e12
+    kernel = {"node": "ku_march_kernel (node columns", "element": "ku_hada_kernel (element columns",
+              "auto": "ku_hada_kernel (element columns"}[args.ku_kernel]
+    achieved = ku_algorithmic_bytes(p) / (ku_ms * 1e-3) / 1e9
     roofline = {
-        "kernel": "ku_march_kernel (finest-level K.u with the p.q epilogue, FP64)",
-        "bound": "alu", "achieved": round(achieved, 2), "peak": FP64_VECTOR_PEAK_TFLOPS,
-        "unit": "TFLOP/s", "frac": round(achieved / FP64_VECTOR_PEAK_TFLOPS, 4),
-        "traffic": ku_traffic_bytes(), "ms_per_launch": round(ku_ms, 5),
+        "kernel": kernel + ", finest-level K.u with the p.q epilogue, FP64)",
+        "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+        "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+        "traffic": ku_traffic_bytes() if args.ku_kernel != "node" and args.ku_shape < 0 else None,
+        "algorithmic_bytes": ku_algorithmic_bytes(p), "ms_per_launch": round(ku_ms, 5),
     }
 
     out = {

@@ -30,8 +30,11 @@
 
 namespace topo {
 
+// Without the one-layer-ahead loads: at least 3 waves per SIMD (at most 168
+// VGPRs), so a 160x80x80 launch runs in one round (3 blocks of 256 threads per
+// CU); with them the register budget is left to the compiler.
 template <int EPI, int KZ, int TX, int TY, bool PF, typename T>
-__global__ __launch_bounds__(TX * TY) void ku_hada_kernel(KuArgsT<T> a, HadaW<T> hw, int tiles_x,
+__global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(PF ? 1 : 3))) void ku_hada_kernel(KuArgsT<T> a, HadaW<T> hw, int tiles_x,
                                                          int tiles_xy, double *partials) {
   if (a.skip && *a.skip) return;
   constexpr int NT = TX * TY;
@@ -67,8 +70,9 @@ __global__ __launch_bounds__(TX * TY) void ku_hada_kernel(KuArgsT<T> a, HadaW<T>
   const uint32_t eoff = (uint32_t)(min(max(je, 0), g.ny - 1) * g.nx + min(max(ie, 0), g.nx - 1));
   const uint32_t own = (uint32_t)((je + 1) * NX + (ie + 1));  // the owned node column (owners only)
 
-  // the operand at the element column's 4 corners on node plane kp
-  auto load_raw = [&](int kp, T(&v)[3][4]) {
+  // the operand at the element column's 4 corners on node plane kp; the scaled
+  // epilogues also keep b and dinv of corner (1, 1) for their own update
+  auto load_raw = [&](int kp, T(&v)[3][4], T(&bd)[2][3]) {
     const int64_t pbase = 3 * (int64_t)min(max(kp, 0), g.nz) * plane;  // uniform
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
@@ -76,10 +80,16 @@ __global__ __launch_bounds__(TX * TY) void ku_hada_kernel(KuArgsT<T> a, HadaW<T>
       const T *__restrict__ dp = dinv + pbase + off[q];
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        if constexpr (kScaled)
-          v[c][q] = up[c] * dp[c] * a.s0;
-        else
+        if constexpr (kScaled) {
+          const T bv = up[c], dv = dp[c];
+          v[c][q] = bv * dv * a.s0;
+          if (q == 3) {
+            bd[0][c] = bv;
+            bd[1][c] = dv;
+          }
+        } else {
           v[c][q] = up[c];
+        }
       }
     }
   };
@@ -106,16 +116,18 @@ __global__ __launch_bounds__(TX * TY) void ku_hada_kernel(KuArgsT<T> a, HadaW<T>
   // this layer's arithmetic and barrier (the barrier waits for LDS traffic only).
   double dotv = 0.0;
   T Pb[3][4], selfb[3];  // node plane L (xy modes) and the operand at the owned node
+  T bdb[2][3];           // scaled epilogues: b and dinv at the owned node of plane L
   T ytp[3][4];           // top face of element layer L-1 (xy modes)
   T nxt[3][4];           // PF: node plane L+1 and the modulus of layer L, one layer ahead
+  T bdn[2][3];
   T Enxt = T(0);
   {
     T v[3][4];
-    load_raw(k0 - 1, v);
+    load_raw(k0 - 1, v, bdb);
     modes(v, Pb, selfb);
   }
   if constexpr (PF) {
-    load_raw(k0, nxt);
+    load_raw(k0, nxt, bdn);
     Enxt = load_E(k0 - 1);
   }
 #pragma unroll
@@ -124,24 +136,36 @@ __global__ __launch_bounds__(TX * TY) void ku_hada_kernel(KuArgsT<T> a, HadaW<T>
     if (L >= k1) break;
     const int64_t nL = (int64_t)L * plane + own;
     EpiIn<T> in;
-    if (q > 0 && owner) ku_epi_load<EPI>(a, nL, dinv, in);
-    T Pt[3][4], selft[3];
+    if (q > 0 && owner) {
+      ku_epi_load<EPI, kScaled>(a, nL, dinv, in);
+      if constexpr (kScaled) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          in.b[c] = bdb[0][c];
+          in.d[c] = bdb[1][c];
+        }
+      }
+    }
+    T Pt[3][4], selft[3], bdt[2][3];
     T Ee;
     if constexpr (PF) {
       T cur[3][4];
 #pragma unroll
-      for (int c = 0; c < 3; ++c)
+      for (int c = 0; c < 3; ++c) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) cur[c][r] = nxt[c][r];
+        bdt[0][c] = bdn[0][c];
+        bdt[1][c] = bdn[1][c];
+      }
       Ee = Enxt;
       if (q < KZ && L + 1 < k1) {
-        load_raw(L + 2, nxt);
+        load_raw(L + 2, nxt, bdn);
         Enxt = load_E(L + 1);
       }
       modes(cur, Pt, selft);
     } else {
       T v[3][4];
-      load_raw(L + 1, v);
+      load_raw(L + 1, v, bdt);
       Ee = load_E(L);
       modes(v, Pt, selft);
     }
@@ -194,6 +218,8 @@ __global__ __launch_bounds__(TX * TY) void ku_hada_kernel(KuArgsT<T> a, HadaW<T>
         Pb[c][r] = Pt[c][r];
       }
       selfb[c] = selft[c];
+      bdb[0][c] = bdt[0][c];
+      bdb[1][c] = bdt[1][c];
     }
   }
   ku_block_reduce<EPI>(a, dotv, partials);

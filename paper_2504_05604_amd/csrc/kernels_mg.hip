@@ -14,91 +14,114 @@ inline unsigned nblocks(int64_t n) { return (unsigned)((n + kBs - 1) / kBs); }
 
 // r_c = P^T r_f: each coarse node gathers the fine nodes within one fine spacing
 // of its position 2*(I,J,K), weight prod over axes (1 at distance 0, 1/2 at 1).
+// Branch-free: a neighbour outside the fine grid is read at a clamped (valid)
+// index with weight 0, which adds an exact zero.
 template <typename T>
 __global__ void restrict_kernel(Grid gf, Grid gc, const T *__restrict__ rf,
                                 const uint8_t *__restrict__ fixc, T *__restrict__ rc,
                                 const int *skip) {
   if (skip && *skip) return;
-  const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (m >= gc.nnodes()) return;
-  const int I = (int)(m % gc.NX());
-  const int J = (int)((m / gc.NX()) % gc.NY());
-  const int K = (int)(m / ((int64_t)gc.NX() * gc.NY()));
+  const int m = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+  if (m >= (int)gc.nnodes()) return;
+  const int NXc = gc.NX(), NYc = gc.NY(), NXf = gf.NX(), NYf = gf.NY();
+  const int I = m % NXc, J = (m / NXc) % NYc, K = m / (NXc * NYc);
+  int xi[3], yj[3], zk[3];
+  T wx[3], wy[3], wz[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const T wd = d == 1 ? T(1) : T(0.5);
+    const int i = 2 * I + d - 1, j = 2 * J + d - 1, k = 2 * K + d - 1;
+    xi[d] = min(max(i, 0), gf.nx);
+    yj[d] = min(max(j, 0), gf.ny);
+    zk[d] = min(max(k, 0), gf.nz);
+    wx[d] = (i >= 0 && i <= gf.nx) ? wd : T(0);
+    wy[d] = (j >= 0 && j <= gf.ny) ? wd : T(0);
+    wz[d] = (k >= 0 && k <= gf.nz) ? wd : T(0);
+  }
   T s0 = 0, s1 = 0, s2 = 0;
 #pragma unroll
-  for (int dz = -1; dz <= 1; ++dz) {
-    const int k = 2 * K + dz;
-    if (k < 0 || k > gf.nz) continue;
+  for (int dz = 0; dz < 3; ++dz)
 #pragma unroll
-    for (int dy = -1; dy <= 1; ++dy) {
-      const int j = 2 * J + dy;
-      if (j < 0 || j > gf.ny) continue;
+    for (int dy = 0; dy < 3; ++dy) {
+      const T *__restrict__ row = rf + 3 * ((int64_t)(zk[dz] * NYf + yj[dy]) * NXf);
 #pragma unroll
-      for (int dx = -1; dx <= 1; ++dx) {
-        const int i = 2 * I + dx;
-        if (i < 0 || i > gf.nx) continue;
-        const T w = (T)(dx ? 0.5 : 1.0) * (dy ? 0.5 : 1.0) * (dz ? 0.5 : 1.0);
-        const int64_t n = i + (int64_t)gf.NX() * (j + (int64_t)gf.NY() * k);
-        s0 = fma(w, rf[3 * n + 0], s0);
-        s1 = fma(w, rf[3 * n + 1], s1);
-        s2 = fma(w, rf[3 * n + 2], s2);
+      for (int dx = 0; dx < 3; ++dx) {
+        const T w = wx[dx] * (wy[dy] * wz[dz]);
+        const T *__restrict__ v = row + 3 * xi[dx];
+        s0 = fma(w, v[0], s0);
+        s1 = fma(w, v[1], s1);
+        s2 = fma(w, v[2], s2);
       }
     }
-  }
   const uint8_t f = fixc[m];
-  rc[3 * m + 0] = (f & 1) ? T(0) : s0;
-  rc[3 * m + 1] = (f & 2) ? T(0) : s1;
-  rc[3 * m + 2] = (f & 4) ? T(0) : s2;
+  rc[3 * (int64_t)m + 0] = (f & 1) ? T(0) : s0;
+  rc[3 * (int64_t)m + 1] = (f & 2) ? T(0) : s1;
+  rc[3 * (int64_t)m + 2] = (f & 4) ? T(0) : s2;
 }
 
 hipError_t launch_restrict(hipStream_t s, Grid gf, Grid gc, const double *rf, const uint8_t *fixc,
                            double *rc, const int *skip) {
+  if (gf.nnodes() >= INT32_MAX) return hipErrorInvalidValue;
   restrict_kernel<double><<<nblocks(gc.nnodes()), kBs, 0, s>>>(gf, gc, rf, fixc, rc, skip);
   return hipGetLastError();
 }
 hipError_t launch_restrict(hipStream_t s, Grid gf, Grid gc, const float *rf, const uint8_t *fixc,
                            float *rc, const int *skip) {
+  if (gf.nnodes() >= INT32_MAX) return hipErrorInvalidValue;
   restrict_kernel<float><<<nblocks(gc.nnodes()), kBs, 0, s>>>(gf, gc, rf, fixc, rc, skip);
   return hipGetLastError();
 }
 
-// x_f += P e_c on free fine dofs (trilinear interpolation of the coarse values).
+// x_f += P e_c on free fine dofs (trilinear interpolation of the coarse values):
+// a fine node on an odd index of an axis sits between two coarse nodes (weight
+// 1/2 each), on an even one on a coarse node (weight 1).  Branch-free: the 8
+// candidate coarse values are always read (clamped), the unused ones with a 0
+// multiplier, which adds an exact zero to the sum.
 template <typename T>
 __global__ void prolong_add_kernel(Grid gf, Grid gc, const T *__restrict__ ec,
                                    const uint8_t *__restrict__ fixf, T *__restrict__ xf,
                                    const int *skip) {
   if (skip && *skip) return;
-  const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (n >= gf.nnodes()) return;
-  const int i = (int)(n % gf.NX());
-  const int j = (int)((n / gf.NX()) % gf.NY());
-  const int k = (int)(n / ((int64_t)gf.NX() * gf.NY()));
+  const int n = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+  if (n >= (int)gf.nnodes()) return;
+  const int NXf = gf.NX(), NYf = gf.NY(), NXc = gc.NX(), NYc = gc.NY();
+  const int i = n % NXf, j = (n / NXf) % NYf, k = n / (NXf * NYf);
   const int I0 = i >> 1, J0 = j >> 1, K0 = k >> 1;
-  const int ni = (i & 1) ? 2 : 1, nj = (j & 1) ? 2 : 1, nk = (k & 1) ? 2 : 1;
-  const T wi = (i & 1) ? T(0.5) : T(1), wj = (j & 1) ? T(0.5) : T(1), wk = (k & 1) ? T(0.5) : T(1);
-  const T w = wi * wj * wk;
+  const int I1 = min(I0 + 1, gc.nx), J1 = min(J0 + 1, gc.ny), K1 = min(K0 + 1, gc.nz);
+  const T ia = (i & 1) ? T(1) : T(0), jb = (j & 1) ? T(1) : T(0), kc = (k & 1) ? T(1) : T(0);
+  const T w = ((i & 1) ? T(0.5) : T(1)) * ((j & 1) ? T(0.5) : T(1)) * ((k & 1) ? T(0.5) : T(1));
   T s0 = 0, s1 = 0, s2 = 0;
-  for (int c = 0; c < nk; ++c)
-    for (int b = 0; b < nj; ++b)
-      for (int a = 0; a < ni; ++a) {
-        const int64_t m = (I0 + a) + (int64_t)gc.NX() * ((J0 + b) + (int64_t)gc.NY() * (K0 + c));
-        s0 += ec[3 * m + 0];
-        s1 += ec[3 * m + 1];
-        s2 += ec[3 * m + 2];
+#pragma unroll
+  for (int c = 0; c < 2; ++c)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      const T inc_cb = (c ? kc : T(1)) * (b ? jb : T(1));
+      const T *__restrict__ row = ec + 3 * ((int64_t)((c ? K1 : K0) * NYc + (b ? J1 : J0)) * NXc);
+#pragma unroll
+      for (int a = 0; a < 2; ++a) {
+        const T inc = inc_cb * (a ? ia : T(1));
+        const T *__restrict__ v = row + 3 * (a ? I1 : I0);
+        s0 = fma(inc, v[0], s0);
+        s1 = fma(inc, v[1], s1);
+        s2 = fma(inc, v[2], s2);
       }
+    }
   const uint8_t f = fixf[n];
-  if (!(f & 1)) xf[3 * n + 0] = fma(w, s0, xf[3 * n + 0]);
-  if (!(f & 2)) xf[3 * n + 1] = fma(w, s1, xf[3 * n + 1]);
-  if (!(f & 4)) xf[3 * n + 2] = fma(w, s2, xf[3 * n + 2]);
+  T *__restrict__ xn = xf + 3 * (int64_t)n;
+  if (!(f & 1)) xn[0] = fma(w, s0, xn[0]);
+  if (!(f & 2)) xn[1] = fma(w, s1, xn[1]);
+  if (!(f & 4)) xn[2] = fma(w, s2, xn[2]);
 }
 
 hipError_t launch_prolong_add(hipStream_t s, Grid gf, Grid gc, const double *ec,
                               const uint8_t *fixf, double *xf, const int *skip) {
+  if (gf.nnodes() >= INT32_MAX) return hipErrorInvalidValue;
   prolong_add_kernel<double><<<nblocks(gf.nnodes()), kBs, 0, s>>>(gf, gc, ec, fixf, xf, skip);
   return hipGetLastError();
 }
 hipError_t launch_prolong_add(hipStream_t s, Grid gf, Grid gc, const float *ec,
                               const uint8_t *fixf, float *xf, const int *skip) {
+  if (gf.nnodes() >= INT32_MAX) return hipErrorInvalidValue;
   prolong_add_kernel<float><<<nblocks(gf.nnodes()), kBs, 0, s>>>(gf, gc, ec, fixf, xf, skip);
   return hipGetLastError();
 }

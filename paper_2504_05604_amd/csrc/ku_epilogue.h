@@ -30,13 +30,15 @@ struct EpiIn {
   T b[3], r[3], d[3], x[3], w[3];  // rhs, residual, inverse diagonal, iterate, dot_with
 };
 
-template <int EPI, typename T>
+// HAVE_BD: the caller already holds b and dinv at the node (the scaled
+// epilogues read them to form their operand) and fills them in itself.
+template <int EPI, bool HAVE_BD = false, typename T>
 __device__ __forceinline__ void ku_epi_load(const KuArgsT<T> &a, int64_t n, const T *__restrict__ dinv,
                                             EpiIn<T> &in) {
   in.fx = a.fixed[n];
-  constexpr bool kB = EPI == KU_RESID || EPI == KU_RES0 || EPI == KU_CHEB0 || EPI == KU_RESID_START;
+  constexpr bool kB = !HAVE_BD && (EPI == KU_RESID || EPI == KU_RES0 || EPI == KU_CHEB0 || EPI == KU_RESID_START);
   constexpr bool kR = EPI == KU_CHEB || EPI == KU_CHEB_ADD || EPI == KU_RESUPD;
-  constexpr bool kD = EPI == KU_CHEB0 || EPI == KU_CHEB || EPI == KU_CHEB_ADD || EPI == KU_RESID_START;
+  constexpr bool kD = !HAVE_BD && (EPI == KU_CHEB0 || EPI == KU_CHEB || EPI == KU_CHEB_ADD || EPI == KU_RESID_START);
   constexpr bool kX = EPI == KU_CHEB || EPI == KU_CHEB_ADD;
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
