@@ -307,7 +307,7 @@ def main():
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="after the timed run, copy a buffer of this many MiB 5 times (a plain copy "
                          "kernel of known traffic for calibrating hardware byte counters)")
-    ap.add_argument("--tail-nodes", type=int, default=1024,
+    ap.add_argument("--tail-nodes", type=int, default=0,
                     help="levels with at most this many nodes run as one single-workgroup launch (0 = off)")
     ap.add_argument("--warm", type=int, default=3, choices=[0, 1, 2, 3],
                     help="initial guess of each solve: 0 zero, 1 last solution, 2 extrapolated, 3 projected")

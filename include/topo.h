@@ -158,8 +158,8 @@ typedef struct {
 
 /* Fills *opts with defaults: FP64, MG, automatic depth (coarsest <= 140 dofs),
  * Chebyshev degree 2, rtol 1e-8, max_iters 1000, projected warm start (3), oc_tol 1e-12,
- * check_every 4, use_graphs 1, nn_max_iters 200, autotune 0, coarse_tail_nodes 1024,
- * mfma_smoothing 0. */
+ * check_every 4, use_graphs 1, nn_max_iters 200, autotune 0, coarse_tail_nodes 0,
+ * mfma_smoothing 0, ku_kernel TOPO_KU_AUTO, ku_shape -1. */
 void topo_default_opts(topo_opts *opts);
 
 /* Validates the problem, copies its arrays to the device, builds the element

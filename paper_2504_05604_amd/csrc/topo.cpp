@@ -269,7 +269,7 @@ extern "C" void topo_default_opts(topo_opts *o) {
   o->use_graphs = 1;
   o->nn_max_iters = 200;
   o->autotune = 0;
-  o->coarse_tail_nodes = 1024;
+  o->coarse_tail_nodes = 0;  // per-level launches measured faster with the element-column kernel
   o->mfma_smoothing = 0;
   o->ku_kernel = TOPO_KU_AUTO;
   o->ku_shape = -1;

@@ -30,6 +30,7 @@ def test_default_opts():
     o = pkg.default_opts()
     assert o.precision == pkg.PREC_FP64 and o.precond == pkg.PRECOND_MG
     assert o.rtol == 1e-8 and o.oc_tol == 1e-12 and o.cheb_degree == 2 and o.warm_start == 3
+    assert o.ku_kernel == pkg.KU_AUTO and o.ku_shape == -1 and o.coarse_tail_nodes == 0
 
 
 def setup_status(p, **opt):
@@ -85,7 +86,10 @@ def test_setup_rejects_bad_mask_and_fixed_dofs():
 def test_setup_rejects_bad_options():
     p = synth.config_small()
     for kw, msg in [({"cheb_degree": 0}, "cheb_degree"), ({"rtol": 0.0}, "rtol"),
-                    ({"precond": 9}, "preconditioner"), ({"precision": 7}, "precision")]:
+                    ({"precond": 9}, "preconditioner"), ({"precision": 7}, "precision"),
+                    ({"ku_kernel": 3}, "ku_kernel"), ({"ku_shape": 4}, "ku_shape"),
+                    ({"ku_shape": 5}, "ku_shape"), ({"ku_shape": 13}, "ku_shape"),
+                    ({"ku_shape": -2}, "ku_shape")]:
         st, err, _ = setup_status(p, **kw)
         assert st == _lib.TOPO_EINVAL and msg in err, (kw, err)
 

@@ -77,12 +77,11 @@ def test_apply_K_matches_oracle(case, kernel):
 
 @pytest.mark.parametrize("kernel", list(KERNELS))
 @pytest.mark.parametrize("case", CASES)
-@pytest.mark.parametrize("precond", ["mg140", "mg400", "mg400deg3", "mg140deg1", "mg140_notail",
+@pytest.mark.parametrize("precond", ["mg140", "mg400", "mg400deg3", "mg140deg1", "mg140_tail1024",
                                      "mg140_tail4000", "jacobi"])
 def test_preconditioner_matches_oracle(case, precond, kernel):
-    """The coarse levels run as one single-workgroup launch below coarse_tail_nodes
-    nodes (default 1024); _notail runs every level with the per-level kernels,
-    _tail4000 moves more levels into the single launch."""
+    """By default every level runs the per-level kernels; _tail1024 and _tail4000
+    run the levels below that many nodes as one single-workgroup launch."""
     p = make_case(case)
     x = synth.random_density(5, p.nel, 0.0, 1.0)
     E = fem.simp_modulus(x, p.E0, p.Emin, p.penal)
@@ -91,7 +90,7 @@ def test_preconditioner_matches_oracle(case, precond, kernel):
     if precond.startswith("mg"):
         coarse = 140 if precond.startswith("mg140") else 400
         deg = 3 if precond.endswith("deg3") else (1 if precond.endswith("deg1") else 2)
-        tail = 0 if precond.endswith("notail") else (4000 if precond.endswith("tail4000") else 1024)
+        tail = 4000 if precond.endswith("tail4000") else (1024 if precond.endswith("tail1024") else 0)
         V = mg.VCycle(p, E, KE, degree=deg, max_coarse_dof=coarse)
         ref = V.apply(r)
         opts = topo.default_opts(precond=topo.PRECOND_MG, mg_max_coarse_dof=coarse, cheb_degree=deg,
