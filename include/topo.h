@@ -156,7 +156,7 @@ typedef struct {
   double ms_total, ms_filter, ms_solve, ms_sens, ms_oc; /* phase times (hipEvents) */
 } topo_iter_stats;
 
-/* Fills *opts with defaults: FP64, MG, automatic depth (coarsest <= 140 dofs),
+/* Fills *opts with defaults: FP64, MG, automatic depth (coarsest <= 1500 dofs),
  * Chebyshev degree 2, rtol 1e-8, max_iters 1000, projected warm start (3), oc_tol 1e-12,
  * check_every 4, use_graphs 1, nn_max_iters 200, autotune 0, coarse_tail_nodes 0,
  * mfma_smoothing 0, ku_kernel TOPO_KU_AUTO, ku_shape -1. */

@@ -232,10 +232,13 @@ hipError_t launch_coarse_fixed(hipStream_t s, Grid gf, Grid gc, const uint8_t *f
 // dense coarsest-level operator, inverse and application
 hipError_t launch_dense_assemble(hipStream_t s, Grid g, const double *E, const Kappa &kap,
                                  const uint8_t *fixed, double *A);
-hipError_t launch_dense_invert(hipStream_t s, int n, double *A);
+// in-place inverse of an SPD n x n matrix; work: dense_invert_work(n) doubles
+// (none for small n)
+size_t dense_invert_work(int n);
+hipError_t launch_dense_invert(hipStream_t s, int n, double *A, double *work);
 hipError_t launch_dense_matvec(hipStream_t s, int n, const double *A, const double *x, double *y,
                                const int *skip = nullptr);
-hipError_t launch_dense_matvec(hipStream_t s, int n, const float *A, const float *x, float *y,
+hipError_t launch_dense_matvec(hipStream_t s, int n, const double *A, const float *x, float *y,
                                const int *skip = nullptr);
 
 // The coarse end of the V-cycle in one workgroup (kernels_tail.hip): levels
@@ -255,7 +258,7 @@ template <typename T>
 struct TailArgs {
   int nlev;
   TailLevel<T> L[kTailMaxLevels];
-  const T *Ainv;                       // dense inverse of the coarsest operator (ncoarse^2)
+  const double *Ainv;                  // dense inverse of the coarsest operator (ncoarse^2, FP64)
   int ncoarse;
   HadaW<T> hw;                         // element matrix, sum/difference basis (see ke_code.h)
   int deg;                             // Chebyshev degree per smoothing
@@ -268,7 +271,7 @@ struct TailArgs {
 constexpr size_t kTailMaxLds = 158 * 1024;  // dynamic part; the kernel adds < 1 KB of static LDS
 template <typename T>
 __host__ __device__ inline size_t tail_level_bytes(const Grid &g) {
-  return (size_t)(g.nel() + 6 * g.ndof()) * sizeof(T) + (size_t)((g.nnodes() + 15) / 16) * 16;
+  return ((size_t)(g.nel() + 6 * g.ndof()) * sizeof(T) + 15) / 16 * 16 + (size_t)((g.nnodes() + 15) / 16) * 16;
 }
 // per-element products of one operator pass (24 values per element), sized by
 // the finest (largest) level of the tail, after the levels and the solve partials
@@ -280,7 +283,7 @@ __host__ __device__ inline size_t tail_scratch_bytes(const Grid &finest) {
 constexpr int kColParts = 4;
 template <typename T>
 __host__ __device__ inline size_t tail_solve_bytes(int ncoarse) {
-  return (size_t)kColParts * ncoarse * sizeof(T);
+  return (size_t)kColParts * ncoarse * sizeof(double);  // FP64 in every precision
 }
 template <typename T>
 hipError_t launch_vcycle_tail_t(hipStream_t s, const TailArgs<T> &a);

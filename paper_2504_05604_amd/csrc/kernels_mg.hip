@@ -2,6 +2,8 @@
 // half the resolution (odd fine counts round up: the coarse grid extends half a
 // coarse element past the fine domain), coarse Dirichlet flags, and the dense
 // coarsest-level operator with its explicit inverse.
+#include <algorithm>
+
 #include "internal.h"
 #include "ke_code.h"
 
@@ -143,16 +145,20 @@ hipError_t launch_coarse_fixed(hipStream_t s, Grid gf, Grid gc, const uint8_t *f
   return hipGetLastError();
 }
 
-// Dense n x n operator of a (small) level, row-major; thread per row: the row of
-// dof (node i, component c) collects E_e KE[3 li + c][3 lb + d] over the elements
-// around i.  Fixed rows/columns become identity rows/columns.
+// Dense n x n operator of a (small) level, row-major, on a zeroed matrix; thread
+// per row: the row of dof (node i, component c) collects E_e KE[3 li + c][3 lb + d]
+// over the elements around i.  Fixed rows/columns become identity rows/columns.
+__global__ void zero_kernel(int64_t n, double *A) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n) A[t] = 0.0;
+}
+
 __global__ void dense_assemble_kernel(Grid g, const double *E, Kappa kap, const uint8_t *fixed,
                                       double *A) {
   const int64_t n = g.ndof();
   const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (row >= n) return;
   double *Ar = A + row * n;
-  for (int64_t c = 0; c < n; ++c) Ar[c] = 0.0;
   const int64_t node = row / 3;
   const int comp = (int)(row % 3);
   if ((fixed[node] >> comp) & 1) {
@@ -187,18 +193,23 @@ __global__ void dense_assemble_kernel(Grid g, const double *E, Kappa kap, const 
 
 hipError_t launch_dense_assemble(hipStream_t s, Grid g, const double *E, const Kappa &kap,
                                  const uint8_t *fixed, double *A) {
+  zero_kernel<<<nblocks(g.ndof() * g.ndof()), kBs, 0, s>>>(g.ndof() * g.ndof(), A);
   dense_assemble_kernel<<<nblocks(g.ndof()), kBs, 0, s>>>(g, E, kap, fixed, A);
   return hipGetLastError();
 }
 
 // In-place Gauss-Jordan inversion of an SPD matrix (no pivoting is needed for
-// SPD matrices) by one workgroup.  Small matrices live in LDS for the whole
-// elimination; larger ones stay in global memory and each thread updates its
-// entries in register batches so the loads of a batch are in flight together.
+// SPD matrices).  Up to kLdsDense rows one workgroup eliminates the whole matrix
+// in LDS.  Larger matrices use the blocked form over panels of kGjNb columns K:
+//   P = A_KK^-1                                  (one workgroup, in LDS)
+//   C = A_iK for i outside K (saved), A_Kj <- P A_Kj for j outside K
+//   A_ij <- A_ij - C_i A_Kj,  A_iK <- -C_i P,  A_KK <- P
+// (the scalar elimination step applied to blocks), three launches per panel.
 constexpr int kInvThreads = 1024;
 constexpr int kMaxDense = 2048;
 constexpr int kLdsDense = 140;  // n*n doubles + pivot row/column fit in 160 KB of LDS
-constexpr int kInvBatch = 8;
+constexpr int kGjNb = 64;       // panel width of the blocked elimination
+constexpr int kGjQ = 32;        // inner-dimension chunk staged in LDS by the tile kernels
 
 __device__ __forceinline__ double gj_update(double a, int i, int j, int k, double inv,
                                             const double *col, const double *rowk) {
@@ -207,87 +218,226 @@ __device__ __forceinline__ double gj_update(double a, int i, int j, int k, doubl
   return a - col[i] * rowk[j] * inv;
 }
 
-__global__ __launch_bounds__(kInvThreads) void dense_invert_lds_kernel(int n, double *A) {
-  extern __shared__ double lds[];
-  double *M = lds;                     // n*n
-  double *col = lds + n * n;           // n
-  double *rowk = col + n;              // n
-  const int nn = n * n;
-  for (int t = threadIdx.x; t < nn; t += blockDim.x) M[t] = A[t];
-  __syncthreads();
-  for (int k = 0; k < n; ++k) {
-    for (int t = threadIdx.x; t < n; t += blockDim.x) {
-      col[t] = M[t * n + k];
-      rowk[t] = M[k * n + t];
+// Gauss-Jordan on the m x m row-major matrix M in LDS by the whole workgroup
+// (col and rowk: m doubles of LDS each)
+__device__ void gj_invert_lds(int m, double *M, double *col, double *rowk) {
+  const int mm = m * m;
+  for (int k = 0; k < m; ++k) {
+    for (int t = threadIdx.x; t < m; t += blockDim.x) {
+      col[t] = M[t * m + k];
+      rowk[t] = M[k * m + t];
     }
     __syncthreads();
     const double inv = 1.0 / col[k];
-    for (int idx = threadIdx.x; idx < nn; idx += blockDim.x) {
-      const int i = idx / n, j = idx - (idx / n) * n;
+    for (int idx = threadIdx.x; idx < mm; idx += blockDim.x) {
+      const int i = idx / m, j = idx - (idx / m) * m;
       M[idx] = gj_update(M[idx], i, j, k, inv, col, rowk);
     }
     __syncthreads();
   }
+}
+
+__global__ __launch_bounds__(kInvThreads) void dense_invert_lds_kernel(int n, double *A) {
+  extern __shared__ double lds[];
+  double *M = lds;            // n*n
+  double *col = lds + n * n;  // n
+  double *rowk = col + n;     // n
+  const int nn = n * n;
+  for (int t = threadIdx.x; t < nn; t += blockDim.x) M[t] = A[t];
+  __syncthreads();
+  gj_invert_lds(n, M, col, rowk);
   for (int t = threadIdx.x; t < nn; t += blockDim.x) A[t] = M[t];
 }
 
-__global__ __launch_bounds__(kInvThreads) void dense_invert_kernel(int n, double *A) {
-  __shared__ double col[kMaxDense];
-  __shared__ double rowk[kMaxDense];
-  const int64_t nn = (int64_t)n * n;
-  for (int k = 0; k < n; ++k) {
-    for (int t = threadIdx.x; t < n; t += blockDim.x) {
-      col[t] = A[(int64_t)t * n + k];
-      rowk[t] = A[(int64_t)k * n + t];
-    }
-    __syncthreads();
-    const double inv = 1.0 / col[k];
-    for (int64_t base = threadIdx.x; base < nn; base += (int64_t)blockDim.x * kInvBatch) {
-      double v[kInvBatch];
+// P = A_KK^-1 for the panel K = [k0, k0 + kb): 1024 threads, thread (ty, tx) owns
+// entries (ty + 16 a, tx) of the block padded to kGjNb x kGjNb with the identity.
+// The threads that update column k+1 and row k+1 also publish them for the next
+// step (double-buffered), so each elimination step takes one barrier.
+__global__ __launch_bounds__(1024) void gj_panel_inv_kernel(int n, const double *A, int k0, int kb,
+                                                            double *P) {
+  __shared__ double M[kGjNb][kGjNb + 1];
+  __shared__ double col[2][kGjNb], rowk[2][kGjNb];
+  const int tx = threadIdx.x % kGjNb, ty = threadIdx.x / kGjNb;  // 16 row groups
 #pragma unroll
-      for (int b = 0; b < kInvBatch; ++b) {
-        const int64_t idx = base + (int64_t)b * blockDim.x;
-        v[b] = idx < nn ? A[idx] : 0.0;
-      }
+  for (int a = 0; a < 4; ++a) {
+    const int r = ty + 16 * a;
+    const double v = (r < kb && tx < kb) ? A[(int64_t)(k0 + r) * n + k0 + tx] : (r == tx ? 1.0 : 0.0);
+    M[r][tx] = v;
+    if (tx == 0) col[0][r] = v;
+    if (r == 0) rowk[0][tx] = v;
+  }
+  __syncthreads();
+  for (int k = 0; k < kb; ++k) {
+    const int cur = k & 1, nxt = cur ^ 1;
+    const double inv = 1.0 / col[cur][k];
+    const double rk = rowk[cur][tx];
 #pragma unroll
-      for (int b = 0; b < kInvBatch; ++b) {
-        const int64_t idx = base + (int64_t)b * blockDim.x;
-        if (idx < nn) {
-          const int i = (int)(idx / n), j = (int)(idx % n);
-          A[idx] = gj_update(v[b], i, j, k, inv, col, rowk);
-        }
-      }
+    for (int a = 0; a < 4; ++a) {
+      const int r = ty + 16 * a;
+      const double cr = col[cur][r];
+      const double upd = M[r][tx] - cr * rk * inv;
+      const double v = r == k ? (tx == k ? inv : rk * inv) : (tx == k ? -cr * inv : upd);
+      M[r][tx] = v;
+      if (tx == k + 1) col[nxt][r] = v;
+      if (r == k + 1) rowk[nxt][tx] = v;
     }
     __syncthreads();
   }
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    const int r = ty + 16 * a;
+    if (r < kb && tx < kb) P[r * kb + tx] = M[r][tx];
+  }
 }
 
-hipError_t launch_dense_invert(hipStream_t s, int n, double *A) {
-  if (n > kMaxDense) return hipErrorInvalidValue;
+// Blocks 0..nt-1: A_Kj <- P A_Kj on column tile j (the panel's own tile skipped);
+// one block reads its whole kb x kGjNb input before writing it back.
+// Blocks nt..2nt-1: C_i = A_iK on row tile i (rows outside K), C row-major n x kb.
+// The two roles touch disjoint parts of A.
+__global__ __launch_bounds__(256) void gj_panel_rows_kernel(int n, double *A, int k0, int kb,
+                                                            const double *P, double *C) {
+  const int nt = (n + kGjNb - 1) / kGjNb, kt = k0 / kGjNb;
+  const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
+  if ((int)blockIdx.x >= nt) {
+    const int it = blockIdx.x - nt;
+    if (it == kt) return;
+    const int i0 = it * kGjNb, rows = min(kGjNb, n - i0);
+    for (int t = threadIdx.x; t < rows * kb; t += blockDim.x) {
+      const int r = t / kb, q = t % kb;
+      C[(int64_t)(i0 + r) * kb + q] = A[(int64_t)(i0 + r) * n + k0 + q];
+    }
+    return;
+  }
+  const int jt = blockIdx.x;
+  if (jt == kt) return;
+  const int j0 = jt * kGjNb, cols = min(kGjNb, n - j0);
+  __shared__ double Ps[kGjNb][kGjQ + 1];
+  __shared__ double Bs[kGjQ][kGjNb];
+  double acc[4][4] = {};
+  for (int q0 = 0; q0 < kb; q0 += kGjQ) {
+    for (int t = threadIdx.x; t < kGjNb * kGjQ; t += blockDim.x) {
+      const int r = t / kGjQ, q = t % kGjQ;
+      Ps[r][q] = (r < kb && q0 + q < kb) ? P[r * kb + q0 + q] : 0.0;
+      const int qb = t / kGjNb, c = t % kGjNb;
+      Bs[qb][c] = (q0 + qb < kb && c < cols) ? A[(int64_t)(k0 + q0 + qb) * n + j0 + c] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll 8
+    for (int q = 0; q < kGjQ; ++q)
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = fma(Ps[ty + 16 * a][q], Bs[q][tx + 16 * b], acc[a][b]);
+    __syncthreads();
+  }
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const int r = ty + 16 * a, c = tx + 16 * b;
+      if (r < kb && c < cols) A[(int64_t)(k0 + r) * n + j0 + c] = acc[a][b];
+    }
+}
+
+// Tile (i, j) of kGjNb x kGjNb: A_ij <- A_ij - C_i A_Kj (j outside K), A_iK <- -C_i P,
+// A_KK <- P; the panel's rows are otherwise final already.
+__global__ __launch_bounds__(256) void gj_update_kernel(int n, double *A, int k0, int kb,
+                                                        const double *P, const double *C) {
+  const int kt = k0 / kGjNb, it = blockIdx.y, jt = blockIdx.x;
+  const int i0 = it * kGjNb, j0 = jt * kGjNb;
+  const int rows = min(kGjNb, n - i0), cols = min(kGjNb, n - j0);
+  if (it == kt) {
+    if (jt == kt)
+      for (int t = threadIdx.x; t < kb * kb; t += blockDim.x)
+        A[(int64_t)(k0 + t / kb) * n + k0 + t % kb] = P[t];
+    return;
+  }
+  const bool panel = jt == kt;
+  const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
+  __shared__ double Cs[kGjNb][kGjQ + 1];
+  __shared__ double Bs[kGjQ][kGjNb];
+  double acc[4][4] = {};
+  for (int q0 = 0; q0 < kb; q0 += kGjQ) {
+    for (int t = threadIdx.x; t < kGjNb * kGjQ; t += blockDim.x) {
+      const int r = t / kGjQ, q = t % kGjQ;
+      Cs[r][q] = (r < rows && q0 + q < kb) ? C[(int64_t)(i0 + r) * kb + q0 + q] : 0.0;
+      const int qb = t / kGjNb, c = t % kGjNb;
+      double bv = 0.0;
+      if (q0 + qb < kb && c < cols)
+        bv = panel ? P[(q0 + qb) * kb + c] : A[(int64_t)(k0 + q0 + qb) * n + j0 + c];
+      Bs[qb][c] = bv;
+    }
+    __syncthreads();
+#pragma unroll 8
+    for (int q = 0; q < kGjQ; ++q)
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = fma(Cs[ty + 16 * a][q], Bs[q][tx + 16 * b], acc[a][b]);
+    __syncthreads();
+  }
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const int r = ty + 16 * a, c = tx + 16 * b;
+      if (r < rows && c < cols) {
+        double *dst = A + (int64_t)(i0 + r) * n + j0 + c;
+        *dst = panel ? -acc[a][b] : *dst - acc[a][b];
+      }
+    }
+}
+
+size_t dense_invert_work(int n) {
+  return n <= kLdsDense ? 0 : (size_t)kGjNb * kGjNb + (size_t)n * kGjNb;
+}
+
+hipError_t launch_dense_invert(hipStream_t s, int n, double *A, double *work) {
+  if (n < 1 || n > kMaxDense) return hipErrorInvalidValue;
   if (n <= kLdsDense) {
     const size_t shm = ((size_t)n * n + 2 * (size_t)n) * sizeof(double);
     (void)hipFuncSetAttribute((const void *)dense_invert_lds_kernel,
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
     dense_invert_lds_kernel<<<1, kInvThreads, shm, s>>>(n, A);
-  } else {
-    dense_invert_kernel<<<1, kInvThreads, 0, s>>>(n, A);
+    return hipGetLastError();
+  }
+  if (!work) return hipErrorInvalidValue;
+  double *P = work, *C = work + kGjNb * kGjNb;
+  const int nt = (n + kGjNb - 1) / kGjNb;
+  for (int k0 = 0; k0 < n; k0 += kGjNb) {
+    const int kb = std::min(kGjNb, n - k0);
+    gj_panel_inv_kernel<<<1, 1024, 0, s>>>(n, A, k0, kb, P);
+    gj_panel_rows_kernel<<<2 * nt, 256, 0, s>>>(n, A, k0, kb, P, C);
+    gj_update_kernel<<<dim3(nt, nt), 256, 0, s>>>(n, A, k0, kb, P, C);
   }
   return hipGetLastError();
 }
 
-// y = A x, one wave per row
+// y = A x, one wave per row; A is the FP64 inverse in every precision (the
+// products and the row sum run in FP64, single-precision vectors are widened and
+// the result rounded once): the coarse operator is ill-conditioned, and an FP32
+// copy of its inverse loses percents of accuracy at a thousand dofs
 template <typename T>
-__global__ void dense_matvec_kernel(int n, const T *A, const T *x, T *y,
-                                    const int *skip) {
+__global__ void dense_matvec_kernel(int n, const double *A, const T *x, T *y, const int *skip) {
   if (skip && *skip) return;
   const int lane = threadIdx.x & 63;
   const int row = blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64;
   if (row >= n) return;
-  T t = 0;
-  for (int c = lane; c < n; c += 64) t = fma(A[(int64_t)row * n + c], x[c], t);
+  // four independent partial sums per lane so the row's loads overlap
+  const double *Ar = A + (int64_t)row * n;
+  double t0 = 0, t1 = 0, t2 = 0, t3 = 0;
+  int c = lane;
+  for (; c + 192 < n; c += 256) {
+    t0 = fma(Ar[c], (double)x[c], t0);
+    t1 = fma(Ar[c + 64], (double)x[c + 64], t1);
+    t2 = fma(Ar[c + 128], (double)x[c + 128], t2);
+    t3 = fma(Ar[c + 192], (double)x[c + 192], t3);
+  }
+  for (; c < n; c += 64) t0 = fma(Ar[c], (double)x[c], t0);
+  double t = (t0 + t1) + (t2 + t3);
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) t += __shfl_down(t, off, 64);
-  if (lane == 0) y[row] = t;
+  if (lane == 0) y[row] = (T)t;
 }
 
 hipError_t launch_dense_matvec(hipStream_t s, int n, const double *A, const double *x, double *y,
@@ -296,7 +446,7 @@ hipError_t launch_dense_matvec(hipStream_t s, int n, const double *A, const doub
   dense_matvec_kernel<double><<<(unsigned)((n + rows_per_block - 1) / rows_per_block), kBs, 0, s>>>(n, A, x, y, skip);
   return hipGetLastError();
 }
-hipError_t launch_dense_matvec(hipStream_t s, int n, const float *A, const float *x, float *y,
+hipError_t launch_dense_matvec(hipStream_t s, int n, const double *A, const float *x, float *y,
                                const int *skip) {
   const int rows_per_block = kBs / 64;
   dense_matvec_kernel<float><<<(unsigned)((n + rows_per_block - 1) / rows_per_block), kBs, 0, s>>>(n, A, x, y, skip);

@@ -340,22 +340,22 @@ __global__ __launch_bounds__(kTailThreads) void vcycle_tail_kernel(TailArgs<T> a
     const TailLevel<T> C = lev(last);
     size_t pofs = 0;
     for (int q = 0; q < a.nlev; ++q) pofs += tail_level_bytes<T>(a.L[q].g);
-    T *part = reinterpret_cast<T *>(tail_smem + pofs);
+    double *part = reinterpret_cast<double *>(tail_smem + pofs);  // FP64 in every precision
     const int n = a.ncoarse, chunk = (n + kColParts - 1) / kColParts;
     for (int t = threadIdx.x; t < kColParts * n; t += blockDim.x) {
       const int r = t / kColParts, q = t % kColParts;
       const int c0 = q * chunk, c1 = min(n, c0 + chunk);
-      const T *row = a.Ainv + (int64_t)r * n;
-      T s = 0;
-      for (int c = c0; c < c1; ++c) s = fma(row[c], C.b[c], s);
+      const double *row = a.Ainv + (int64_t)r * n;
+      double s = 0;
+      for (int c = c0; c < c1; ++c) s = fma(row[c], (double)C.b[c], s);
       part[t] = s;
     }
     __syncthreads();
     for (int r = threadIdx.x; r < n; r += blockDim.x) {
-      T s = 0;
+      double s = 0;
 #pragma unroll
       for (int q = 0; q < kColParts; ++q) s += part[kColParts * r + q];
-      C.x[r] = s;
+      C.x[r] = (T)s;
     }
     __syncthreads();
   }

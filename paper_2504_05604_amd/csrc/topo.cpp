@@ -189,7 +189,7 @@ struct topo_ctx {
   // multigrid
   std::vector<Level> lv;
   double *Ainv = nullptr;
-  float *Ainv32 = nullptr;
+  double *Awork = nullptr;  // blocked inversion workspace (larger coarsest levels)
   int ncoarse = 0;
   bool mixed = false;        // single-precision preconditioner
   KappaT<float> kap32{};
@@ -259,7 +259,7 @@ extern "C" void topo_default_opts(topo_opts *o) {
   o->precision = TOPO_PREC_FP64;
   o->precond = TOPO_PRECOND_MG;
   o->mg_levels = 0;
-  o->mg_max_coarse_dof = 140;
+  o->mg_max_coarse_dof = 1500;
   o->cheb_degree = 2;
   o->rtol = 1e-8;
   o->max_iters = 1000;
@@ -477,7 +477,7 @@ extern "C" topo_status topo_setup(const topo_problem *P, const topo_opts *O, voi
     ctx->ncoarse = (int)dims.back().ndof();
     if (ctx->ncoarse > 2048) return set_error("coarsest level has %d dofs (> 2048); allow more levels", ctx->ncoarse), TOPO_EINVAL;
     TOPO_ALLOC(ctx->Ainv, (size_t)ctx->ncoarse * ctx->ncoarse);
-    if (O->precision != TOPO_PREC_FP64) TOPO_ALLOC(ctx->Ainv32, (size_t)ctx->ncoarse * ctx->ncoarse);
+    if (dense_invert_work(ctx->ncoarse)) TOPO_ALLOC(ctx->Awork, dense_invert_work(ctx->ncoarse));
   }
 
   // CG and SIMP vectors
@@ -798,15 +798,13 @@ static topo_status prepare_operator(topo_ctx *ctx, const double *d_xphys) {
   if (ctx->lv.size() > 1) {
     const Level &C = ctx->lv.back();
     TOPO_HIP(launch_dense_assemble(s, C.g, C.E, ctx->kap, C.fixed, ctx->Ainv));
-    TOPO_HIP(launch_dense_invert(s, ctx->ncoarse, ctx->Ainv));
+    TOPO_HIP(launch_dense_invert(s, ctx->ncoarse, ctx->Ainv, ctx->Awork));
   }
   if (ctx->mixed) {
     for (Level &L : ctx->lv) {
       TOPO_HIP(launch_convert(s, L.g.nel(), L.E, L.f32.E));
       TOPO_HIP(launch_convert(s, L.g.ndof(), L.dinv, L.f32.dinv));
     }
-    if (ctx->Ainv32)
-      TOPO_HIP(launch_convert(s, (int64_t)ctx->ncoarse * ctx->ncoarse, ctx->Ainv, ctx->Ainv32));
   }
   // network input channel 0 (node density) is fixed for the whole solve
   if (ctx->nn) TOPO_HIP(launch_node_density(s, ctx->g, d_xphys, ctx->nnw.x));
@@ -931,17 +929,6 @@ static topo_status post_smooth(topo_ctx *ctx, Level &L, const int *skip, const T
   return TOPO_OK;
 }
 
-template <typename T>
-static const T *coarse_inverse(const topo_ctx *ctx);
-template <>
-const double *coarse_inverse<double>(const topo_ctx *ctx) {
-  return ctx->Ainv;
-}
-template <>
-const float *coarse_inverse<float>(const topo_ctx *ctx) {
-  return ctx->Ainv32;
-}
-
 // z = M r: V-cycle from level l with rhs b into x of that level; with dot_fin
 // set (level 0 in double precision) the last smoothing pass reduces r.z into it
 // levels tail_start .. coarsest in one launch (same arithmetic as the per-level passes)
@@ -954,7 +941,7 @@ static topo_status vcycle_tail(topo_ctx *ctx, const int *skip) {
     const LevelBufs<T> B = bufs<T>(L);
     a.L[q] = TailLevel<T>{L.g, B.E, B.dinv, L.fixed, B.b, B.x, B.res, B.d0, B.d1};
   }
-  a.Ainv = coarse_inverse<T>(ctx);
+  a.Ainv = ctx->Ainv;
   a.ncoarse = ctx->ncoarse;
   a.hw = hada_work(kappa_of<T>(ctx));
   a.deg = ctx->opts.cheb_degree;
@@ -978,7 +965,7 @@ static topo_status vcycle(topo_ctx *ctx, size_t l, const int *skip, const Fin *d
   Level &L = ctx->lv[l];
   const LevelBufs<T> B = bufs<T>(L);
   if (l + 1 == ctx->lv.size()) {
-    TOPO_HIP(launch_dense_matvec(s, ctx->ncoarse, coarse_inverse<T>(ctx), B.b, B.x, skip));
+    TOPO_HIP(launch_dense_matvec(s, ctx->ncoarse, ctx->Ainv, B.b, B.x, skip));
     return TOPO_OK;
   }
   if (ctx->tail_start && l == ctx->tail_start) return vcycle_tail<T>(ctx, skip);

@@ -78,7 +78,7 @@ def test_apply_K_matches_oracle(case, kernel):
 @pytest.mark.parametrize("kernel", list(KERNELS))
 @pytest.mark.parametrize("case", CASES)
 @pytest.mark.parametrize("precond", ["mg140", "mg400", "mg400deg3", "mg140deg1", "mg140_tail1024",
-                                     "mg140_tail4000", "jacobi"])
+                                     "mg140_tail4000", "mg1500", "jacobi"])
 def test_preconditioner_matches_oracle(case, precond, kernel):
     """By default every level runs the per-level kernels; _tail1024 and _tail4000
     run the levels below that many nodes as one single-workgroup launch."""
@@ -88,7 +88,7 @@ def test_preconditioner_matches_oracle(case, precond, kernel):
     r = synth.random_vector(6, p.ndof)
     r[fixed_mask(p)] = 0.0
     if precond.startswith("mg"):
-        coarse = 140 if precond.startswith("mg140") else 400
+        coarse = int(precond[2:].split("_")[0].split("deg")[0])
         deg = 3 if precond.endswith("deg3") else (1 if precond.endswith("deg1") else 2)
         tail = 4000 if precond.endswith("tail4000") else (1024 if precond.endswith("tail1024") else 0)
         V = mg.VCycle(p, E, KE, degree=deg, max_coarse_dof=coarse)
@@ -107,6 +107,25 @@ def test_preconditioner_matches_oracle(case, precond, kernel):
         ctx.apply_precond(dev(x), dev(r), z)
         got = host(z)
     assert np.abs(got - ref).max() <= 1e-11 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("dims", [(32, 16, 16), (40, 20, 20)])
+def test_preconditioner_with_large_coarsest_level_matches_oracle(dims):
+    """Coarsest levels of 675 and 1188 dofs: the blocked Gauss-Jordan inverse
+    (64-column panels, ragged last panel) against the oracle's exact coarse solve."""
+    p = synth.cantilever(*dims, volfrac=0.3, rmin=1.5, n_iter=1)
+    x = synth.random_density(5, p.nel, 0.0, 1.0)
+    E = fem.simp_modulus(x, p.E0, p.Emin, p.penal)
+    r = synth.random_vector(6, p.ndof)
+    r[fixed_mask(p)] = 0.0
+    V = mg.VCycle(p, E, KE, degree=2, max_coarse_dof=1500)
+    ref = V.apply(r)
+    with topo.Context(p, topo.default_opts(mg_max_coarse_dof=1500)) as ctx:
+        assert ctx.mg_levels == len(V.levels)
+        z = torch.empty(p.ndof, dtype=torch.float64, device="cuda")
+        ctx.apply_precond(dev(x), dev(r), z)
+        got = host(z)
+    assert np.abs(got - ref).max() <= 1e-10 * np.abs(ref).max()
 
 
 @pytest.mark.parametrize("kernel", list(KERNELS))
