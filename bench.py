@@ -315,6 +315,8 @@ def main():
     ap.add_argument("--ku-kernel", choices=["auto", "node", "element"], default="auto",
                     help="K.u kernel: node columns or element columns in the sum/difference basis")
     ap.add_argument("--ku-shape", type=int, default=-1, help="one K.u launch shape for every level (-1: by grid size)")
+    ap.add_argument("--coarse-refresh", type=int, default=1,
+                    help="recompute the coarsest level's dense inverse every this many SIMP iterations")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-vs-multigrid leg")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-problems leg")
     ap.add_argument("--no-paper", action="store_true", help="skip the paper's 32x16x16 workload")
@@ -345,7 +347,7 @@ def main():
                              mfma_smoothing=1 if args.mfma else 0, autotune=1 if args.autotune else 0,
                              ku_kernel={"auto": topo.KU_AUTO, "node": topo.KU_NODE,
                                         "element": topo.KU_ELEMENT}[args.ku_kernel],
-                             ku_shape=args.ku_shape,
+                             ku_shape=args.ku_shape, coarse_refresh=args.coarse_refresh,
                              precond=topo.PRECOND_MG if args.precond == "mg" else topo.PRECOND_JACOBI)
     ctx = topo.Context(p, opts)
     x = torch.from_numpy(p.initial_design()).to("cuda")
@@ -398,7 +400,7 @@ def main():
             "coarse_dof_cap": args.coarse_dof,
             "check_every": args.check_every, "graphs": not args.no_graphs,
             "coarse_tail_nodes": args.tail_nodes, "autotune": bool(args.autotune),
-            "ku_kernel": args.ku_kernel, "ku_shape": args.ku_shape,
+            "ku_kernel": args.ku_kernel, "ku_shape": args.ku_shape, "coarse_refresh": args.coarse_refresh,
             "preconditioner_precision": args.precision,
             "matrix_core_smoothing": bool(args.mfma or args.precision == "bf16"),
             "pcg_iters_mean": round(float(pcg.mean()), 2), "pcg_iters_max": int(pcg.max()),

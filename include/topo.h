@@ -134,6 +134,11 @@ typedef struct {
                                  4x16x8 (next plane loaded ahead), 2x8x8 (ahead), 1x8x8,
                                  8x32x8 (ahead), 8x16x16 (ahead); 4 and 5, the matrix-core
                                  kernels, are chosen through precision / mfma_smoothing  */
+  int32_t coarse_refresh;     /* topo_iterate: recompute the coarsest level's dense inverse
+                                 every this many SIMP iterations (1 = every iteration); in
+                                 between the last one (an SPD matrix, so the V-cycle stays
+                                 a valid preconditioner) serves; other entry points always
+                                 recompute it                                            */
 } topo_opts;
 
 typedef struct {
@@ -159,7 +164,7 @@ typedef struct {
 /* Fills *opts with defaults: FP64, MG, automatic depth (coarsest <= 1500 dofs),
  * Chebyshev degree 2, rtol 1e-8, max_iters 1000, projected warm start (3), oc_tol 1e-12,
  * check_every 4, use_graphs 1, nn_max_iters 200, autotune 0, coarse_tail_nodes 0,
- * mfma_smoothing 0, ku_kernel TOPO_KU_AUTO, ku_shape -1. */
+ * mfma_smoothing 0, ku_kernel TOPO_KU_AUTO, ku_shape -1, coarse_refresh 1. */
 void topo_default_opts(topo_opts *opts);
 
 /* Validates the problem, copies its arrays to the device, builds the element

@@ -65,7 +65,7 @@ class Opts_C(C.Structure):
         ("max_iters", C.c_int32), ("warm_start", C.c_int32), ("oc_tol", C.c_double),
         ("check_every", C.c_int32), ("use_graphs", C.c_int32), ("nn_max_iters", C.c_int32),
         ("autotune", C.c_int32), ("coarse_tail_nodes", C.c_int32), ("mfma_smoothing", C.c_int32),
-        ("ku_kernel", C.c_int32), ("ku_shape", C.c_int32),
+        ("ku_kernel", C.c_int32), ("ku_shape", C.c_int32), ("coarse_refresh", C.c_int32),
     ]
 
 

@@ -190,6 +190,7 @@ struct topo_ctx {
   std::vector<Level> lv;
   double *Ainv = nullptr;
   double *Awork = nullptr;  // blocked inversion workspace (larger coarsest levels)
+  int coarse_due = 0;       // SIMP iterations until the coarse inverse is recomputed
   int ncoarse = 0;
   bool mixed = false;        // single-precision preconditioner
   KappaT<float> kap32{};
@@ -273,6 +274,7 @@ extern "C" void topo_default_opts(topo_opts *o) {
   o->mfma_smoothing = 0;
   o->ku_kernel = TOPO_KU_AUTO;
   o->ku_shape = -1;
+  o->coarse_refresh = 1;
 }
 
 extern "C" const char *topo_last_error(void) { return g_err; }
@@ -321,6 +323,7 @@ static topo_status validate(const topo_problem *P, const topo_opts *O) {
   if (O->mg_levels < 0 || O->mg_levels > 16) return set_error("mg_levels must lie in [0, 16]"), TOPO_EINVAL;
   if (O->coarse_tail_nodes < 0) return set_error("coarse_tail_nodes must be >= 0"), TOPO_EINVAL;
   if (O->warm_start < 0 || O->warm_start > 3) return set_error("warm_start must be 0, 1, 2 or 3"), TOPO_EINVAL;
+  if (O->coarse_refresh < 1) return set_error("coarse_refresh must be >= 1"), TOPO_EINVAL;
   if (O->ku_kernel != TOPO_KU_AUTO && O->ku_kernel != TOPO_KU_NODE && O->ku_kernel != TOPO_KU_ELEMENT)
     return set_error("unknown ku_kernel %d", O->ku_kernel), TOPO_EINVAL;
   if (!(O->ku_shape == -1 || (O->ku_shape >= 0 && O->ku_shape < kKuShapes) ||
@@ -785,8 +788,9 @@ static topo_status autotune(topo_ctx *ctx) {
   return TOPO_OK;
 }
 
-// level-0 modulus from xphys, then the coarse moduli, diagonals and coarse inverse
-static topo_status prepare_operator(topo_ctx *ctx, const double *d_xphys) {
+// level-0 modulus from xphys, then the coarse moduli, diagonals and (unless the
+// previous one is kept) the coarse inverse
+static topo_status prepare_operator(topo_ctx *ctx, const double *d_xphys, bool refresh_coarse = true) {
   hipStream_t s = ctx->stream;
   const topo_problem &P = ctx->prob;
   TOPO_HIP(launch_simp_modulus(s, ctx->nel, d_xphys, P.E0, P.Emin, P.penal, 1.0, ctx->lv[0].E));
@@ -795,11 +799,13 @@ static topo_status prepare_operator(topo_ctx *ctx, const double *d_xphys) {
     if (l > 0) TOPO_HIP(launch_coarsen_moduli(s, ctx->lv[l - 1].g, L.g, ctx->lv[l - 1].E, L.E));
     TOPO_HIP(launch_diag(s, L.g, L.E, ctx->kap, L.fixed, L.dinv));
   }
-  if (ctx->lv.size() > 1) {
+  if (ctx->lv.size() > 1 && refresh_coarse) {
     const Level &C = ctx->lv.back();
     TOPO_HIP(launch_dense_assemble(s, C.g, C.E, ctx->kap, C.fixed, ctx->Ainv));
     TOPO_HIP(launch_dense_invert(s, ctx->ncoarse, ctx->Ainv, ctx->Awork));
   }
+  // a direct call leaves a fresh inverse; the SIMP loop counts from here
+  ctx->coarse_due = refresh_coarse ? ctx->opts.coarse_refresh : ctx->coarse_due;
   if (ctx->mixed) {
     for (Level &L : ctx->lv) {
       TOPO_HIP(launch_convert(s, L.g.nel(), L.E, L.f32.E));
@@ -1304,7 +1310,11 @@ extern "C" topo_status topo_iterate(topo_ctx *ctx, double *d_x, int32_t n_iter, 
       if (ctx->n_warm >= 2) TOPO_HIP(launch_extrapolate(s, ctx->ndof, ctx->u, ctx->u_prev));
       else TOPO_HIP(hipMemcpyAsync(ctx->u_prev, ctx->u, ctx->ndof * sizeof(double), hipMemcpyDeviceToDevice, s));
     }
-    topo_status st = prepare_operator(ctx, ctx->xphys);
+    // the coarse inverse is recomputed every coarse_refresh SIMP iterations; in
+    // between the previous one (still SPD) preconditions the coarsest level
+    const bool refresh = ctx->coarse_due <= 0;
+    topo_status st = prepare_operator(ctx, ctx->xphys, refresh);
+    --ctx->coarse_due;
     if (st == TOPO_OK && ctx->opts.warm_start == 3 && ctx->nbasis > 0) st = projected_start(ctx);
     topo_solve_stats ss{};
     if (st == TOPO_OK) st = pcg(ctx, &ss);

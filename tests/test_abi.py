@@ -31,6 +31,7 @@ def test_default_opts():
     assert o.precision == pkg.PREC_FP64 and o.precond == pkg.PRECOND_MG
     assert o.rtol == 1e-8 and o.oc_tol == 1e-12 and o.cheb_degree == 2 and o.warm_start == 3
     assert o.ku_kernel == pkg.KU_AUTO and o.ku_shape == -1 and o.coarse_tail_nodes == 0
+    assert o.mg_max_coarse_dof == 1500 and o.coarse_refresh == 1
 
 
 def setup_status(p, **opt):
@@ -89,7 +90,7 @@ def test_setup_rejects_bad_options():
                     ({"precond": 9}, "preconditioner"), ({"precision": 7}, "precision"),
                     ({"ku_kernel": 3}, "ku_kernel"), ({"ku_shape": 4}, "ku_shape"),
                     ({"ku_shape": 5}, "ku_shape"), ({"ku_shape": 13}, "ku_shape"),
-                    ({"ku_shape": -2}, "ku_shape")]:
+                    ({"ku_shape": -2}, "ku_shape"), ({"coarse_refresh": 0}, "coarse_refresh")]:
         st, err, _ = setup_status(p, **kw)
         assert st == _lib.TOPO_EINVAL and msg in err, (kw, err)
 
