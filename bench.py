@@ -29,7 +29,7 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "ku_element_fp64_160x80x80_traffic
 
 
 def ku_algorithmic_bytes(p):
-    """Bytes a K.u launch with the p.q epilogue must move: u read and y written
+    """Bytes a K.u launch (y = K u) must move: u read and y written
     (8 B per dof each), the element moduli read (8 B per element) and the
     fixed-dof flags read (1 B per node)."""
     nnodes = (p.nelx + 1) * (p.nely + 1) * (p.nelz + 1)
@@ -375,7 +375,7 @@ def main():
               "auto": "ku_hada_kernel (element columns"}[args.ku_kernel]
     achieved = ku_algorithmic_bytes(p) / (ku_ms * 1e-3) / 1e9
     roofline = {
-        "kernel": kernel + ", finest-level K.u with the p.q epilogue, FP64)",
+        "kernel": kernel + ", finest-level K.u, y = K u, FP64)",
         "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
         "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
         "traffic": ku_traffic_bytes() if args.ku_kernel != "node" and args.ku_shape < 0 else None,

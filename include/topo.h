@@ -240,10 +240,12 @@ topo_status topo_oc_update(topo_ctx *ctx, const double *d_x, const double *d_dc,
 topo_status topo_iterate(topo_ctx *ctx, double *d_x, int32_t n_iter, topo_iter_stats *h_stats);
 
 /* Measurement helper: times `reps` back-to-back launches of the finest-level
- * matrix-free operator kernel (the conjugate-gradient product q = K p, with the
- * context's current moduli and displacement as operand) between two hipEvents
- * on the context's stream; *h_ms_per_launch = elapsed / reps.  Call after
- * topo_iterate or topo_solve.  Writes only the context's scratch vector. */
+ * matrix-free operator kernel (y = K u in the launch shape of the
+ * conjugate-gradient product, with the context's current moduli and
+ * displacement as operand; no reduction, so no other kernel runs between the
+ * events) between two hipEvents on the context's stream; *h_ms_per_launch =
+ * elapsed / reps.  Call after topo_iterate or topo_solve.  Writes only the
+ * context's scratch vector. */
 topo_status topo_time_operator(topo_ctx *ctx, int32_t reps, double *h_ms_per_launch);
 
 /* Copies the context's current displacement (ndof) to d_u / physical density

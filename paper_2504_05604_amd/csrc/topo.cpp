@@ -1381,10 +1381,12 @@ extern "C" topo_status topo_time_operator(topo_ctx *ctx, int32_t reps, double *h
   hipEvent_t e0, e1;
   TOPO_HIP(hipEventCreate(&e0));
   TOPO_HIP(hipEventCreate(&e1));
-  TOPO_HIP(launch_ku(s, KU_STORE_DOT, a, ctx->kap, ctx->red, fin_sum(&ctx->sc->red[0]), ctx->shape_cg));  // warm caches
+  // the plain product (no dot product, hence no finalize launch between the
+  // events), in the CG product's launch shape
+  TOPO_HIP(launch_ku(s, KU_STORE, a, ctx->kap, ctx->red, fin_sum(nullptr), ctx->shape_cg));  // warm caches
   TOPO_HIP(hipEventRecord(e0, s));
   for (int i = 0; i < reps; ++i)
-    TOPO_HIP(launch_ku(s, KU_STORE_DOT, a, ctx->kap, ctx->red, fin_sum(&ctx->sc->red[0]), ctx->shape_cg));
+    TOPO_HIP(launch_ku(s, KU_STORE, a, ctx->kap, ctx->red, fin_sum(nullptr), ctx->shape_cg));
   TOPO_HIP(hipEventRecord(e1, s));
   TOPO_HIP(hipEventSynchronize(e1));
   float ms = 0.f;
