@@ -3,10 +3,12 @@
 
 Workload: the 160x80x80 cantilever (1,024,000 hexahedra, 3,168,963 DOF; face x=0
 clamped, unit downward load spread over the bottom edge of the free end),
-volfrac 0.2, rmin 3.0, p = 3, density filter, multigrid-preconditioned CG to a
-relative residual of 1e-8 with warm starts.  A step is one full SIMP iteration
-(filter, moduli and multigrid set-up, solve, sensitivities, filter adjoint, OC
-update).  Prints one JSON line.
+volfrac 0.2, rmin 3.0, p = 3, density filter, CG to an FP64 relative residual
+of 1e-8 with warm starts, preconditioned by a multigrid V-cycle in FP32 (FP64
+with --precision fp64); a lockstep FP64 run reports the mixed path's compliance
+and displacement error.  A step is one full SIMP iteration (filter, moduli and
+multigrid set-up, solve, sensitivities, filter adjoint, OC update).  Prints one
+JSON line.
 
 python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -250,6 +252,33 @@ def learned_vs_mg(topo, synth, args):
     }
 
 
+def lockstep_fp64_error(topo, p, opts, mixed_stats, mixed_ctx):
+    """The same SIMP iterations with the FP64 preconditioner from the same initial
+    design: largest relative compliance difference over the iterations and the
+    relative displacement difference after the last one."""
+    import numpy as np
+    import torch
+
+    from paper_2504_05604_amd._lib import Opts_C
+    opts64 = Opts_C.from_buffer_copy(opts)
+    opts64.precision = topo.PREC_FP64
+    opts64.mfma_smoothing = 0
+    n = len(mixed_stats)
+    with topo.Context(p, opts64) as ctx64:
+        x64 = torch.from_numpy(p.initial_design()).to("cuda")
+        st64 = ctx64.iterate(x64, n, raise_on_nonconv=False)
+        u64 = torch.empty(p.ndof, dtype=torch.float64, device="cuda")
+        ctx64.get_state(u=u64)
+    u32 = torch.empty(p.ndof, dtype=torch.float64, device="cuda")
+    mixed_ctx.get_state(u=u32)
+    c_err = max(abs(a["c"] - b["c"]) / abs(b["c"]) for a, b in zip(mixed_stats, st64))
+    u_err = float(torch.linalg.vector_norm(u32 - u64) / torch.linalg.vector_norm(u64))
+    print(f"# FP64 lockstep: max rel compliance difference {c_err:.2e}, rel displacement difference {u_err:.2e}",
+          file=sys.stderr, flush=True)
+    return {"iterations": n, "compliance_max_rel_diff": float(c_err), "displacement_rel_diff": u_err,
+            "fp64_pcg_iters_mean": round(float(np.mean([s["pcg_iters"] for s in st64])), 2)}
+
+
 def batched(topo, synth, args):
     """64 independent random problems (grids 24x12x12 .. 96x48x48, seeds 0-63) with the
     single-precision multigrid preconditioner and autotuned K.u launch shapes:
@@ -300,8 +329,10 @@ def main():
     ap.add_argument("--coarse-dof", type=int, default=1500, help="coarsest multigrid level size cap")
     ap.add_argument("--check-every", type=int, default=4)
     ap.add_argument("--no-graphs", action="store_true")
-    ap.add_argument("--precision", choices=["fp64", "fp32", "bf16"], default="fp64",
+    ap.add_argument("--precision", choices=["fp64", "fp32", "bf16"], default="fp32",
                     help="precision of the multigrid preconditioner (CG stays FP64)")
+    ap.add_argument("--no-fp64-reference", action="store_true",
+                    help="skip the lockstep FP64 run that measures the mixed-precision error")
     ap.add_argument("--mfma", action="store_true",
                     help="FP32 preconditioner: smoothing operator passes on the matrix cores")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -352,8 +383,7 @@ def main():
     ctx = topo.Context(p, opts)
     x = torch.from_numpy(p.initial_design()).to("cuda")
     print(f"# setup done: {p.nel} elements, {p.ndof} dof, {ctx.mg_levels} MG levels", file=sys.stderr, flush=True)
-    if args.warmup:
-        ctx.iterate(x, args.warmup, raise_on_nonconv=False)
+    warm_stats = ctx.iterate(x, args.warmup, raise_on_nonconv=False) if args.warmup else []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     stats = ctx.iterate(x, args.steps, raise_on_nonconv=False)
@@ -361,6 +391,9 @@ def main():
     t1 = time.perf_counter()
     ms_per_step = 1e3 * (t1 - t0) / args.steps
     print(f"# timed {args.steps} SIMP iterations: {ms_per_step:.2f} ms each", file=sys.stderr, flush=True)
+    fp64_reference = None
+    if args.precision != "fp64" and not args.no_fp64_reference:
+        fp64_reference = lockstep_fp64_error(topo, p, opts, warm_stats + stats, ctx)
 
     pcg = np.array([s["pcg_iters"] for s in stats], dtype=float)
     solve_ms = np.array([s["ms_solve"] for s in stats])
@@ -391,7 +424,7 @@ def main():
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": {"fp64": "f64", "fp32": "f64/f32", "bf16": "f64/bf16"}[args.precision],
         "data": "synthetic",
         "config": {
             "workload": "cantilever-160x80x80 (3,168,963 DOF), volfrac 0.2, rmin 3.0, density filter",
@@ -402,6 +435,7 @@ def main():
             "coarse_tail_nodes": args.tail_nodes, "autotune": bool(args.autotune),
             "ku_kernel": args.ku_kernel, "ku_shape": args.ku_shape, "coarse_refresh": args.coarse_refresh,
             "preconditioner_precision": args.precision,
+            "error_vs_fp64": fp64_reference,
             "matrix_core_smoothing": bool(args.mfma or args.precision == "bf16"),
             "pcg_iters_mean": round(float(pcg.mean()), 2), "pcg_iters_max": int(pcg.max()),
             "solves_converged": int(sum(1 for s in stats if s["converged"])),
