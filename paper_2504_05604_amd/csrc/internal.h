@@ -188,7 +188,7 @@ hipError_t launch_dot(hipStream_t s, int64_t n, const double *a, const double *b
 // FIN_CG_CHECK the finalize also runs the device-side convergence test
 hipError_t launch_cg_update_xr(hipStream_t s, int64_t n, Scalars *sc, double *x, double *r,
                                const double *p, const double *q, const Reducer &red,
-                               const Fin &fin, const int *skip = nullptr);
+                               const Fin &fin, const int *skip = nullptr, float *r32 = nullptr);
 // cg_iters = 0; rtol2, cg_max stored; nn_fallback = 0; cg_done = (rr <= rtol2 ff)
 hipError_t launch_cg_start(hipStream_t s, Scalars *sc, double rtol2, int max_iters);
 // z = r * dinv; fin.out = r.z

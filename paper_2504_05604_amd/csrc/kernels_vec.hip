@@ -87,8 +87,10 @@ hipError_t launch_dot(hipStream_t s, int64_t n, const double *a, const double *b
   return e != hipSuccess ? e : launch_finalize(s, red, (int)nb, 1, fin, skip);
 }
 
+// r32 (optional): the new residual rounded to FP32 as well, the right-hand side
+// of a single-precision preconditioner
 __global__ void cg_update_xr_kernel(int64_t n, const Scalars *sc, double *x, double *r,
-                                    const double *p, const double *q, double *partials,
+                                    const double *p, const double *q, float *r32, double *partials,
                                     const int *skip) {
   if (skipped(skip)) return;
   const double alpha = sc->rz / sc->pq;
@@ -98,6 +100,7 @@ __global__ void cg_update_xr_kernel(int64_t n, const Scalars *sc, double *x, dou
     x[i] = fma(alpha, p[i], x[i]);
     const double ri = fma(-alpha, q[i], r[i]);
     r[i] = ri;
+    if (r32) r32[i] = (float)ri;
     t = fma(ri, ri, t);
   }
   double v[1] = {t};
@@ -106,9 +109,9 @@ __global__ void cg_update_xr_kernel(int64_t n, const Scalars *sc, double *x, dou
 
 hipError_t launch_cg_update_xr(hipStream_t s, int64_t n, Scalars *sc, double *x, double *r,
                                const double *p, const double *q, const Reducer &red, const Fin &fin,
-                               const int *skip) {
+                               const int *skip, float *r32) {
   const unsigned nb = red_blocks(n, red);
-  cg_update_xr_kernel<<<nb, kBs, 0, s>>>(n, sc, x, r, p, q, red.partials, skip);
+  cg_update_xr_kernel<<<nb, kBs, 0, s>>>(n, sc, x, r, p, q, r32, red.partials, skip);
   hipError_t e = hipGetLastError();
   return e != hipSuccess ? e : launch_finalize(s, red, (int)nb, 1, fin, skip);
 }

@@ -993,7 +993,7 @@ static topo_status vcycle(topo_ctx *ctx, size_t l, const int *skip, const Fin *d
 // The learned preconditioner (kind TOPO_PRECOND_LEARNED) maps the residual
 // through the network (its rms comes from rr, formed by the caller) and feeds
 // the flexible update with the safeguard test of FIN_RZ_SAFE.
-static topo_status precondition(topo_ctx *ctx, int kind, const int *skip) {
+static topo_status precondition(topo_ctx *ctx, int kind, const int *skip, bool have_r32 = false) {
   hipStream_t s = ctx->stream;
   Level &L0 = ctx->lv[0];
   const Fin fin{FIN_RZ, &ctx->sc->rz_new, ctx->sc};
@@ -1012,7 +1012,7 @@ static topo_status precondition(topo_ctx *ctx, int kind, const int *skip) {
     return TOPO_OK;
   }
   if (!ctx->mixed) return vcycle<double>(ctx, 0, skip, &fin);
-  TOPO_HIP(launch_convert(s, ctx->ndof, ctx->r, L0.f32.b, skip));
+  if (!have_r32) TOPO_HIP(launch_convert(s, ctx->ndof, ctx->r, L0.f32.b, skip));
   topo_status st = vcycle<float>(ctx, 0, skip, nullptr);
   if (st != TOPO_OK) return st;
   const Fin flex{FIN_RZ_FLEX, &ctx->sc->red[0], ctx->sc};
@@ -1038,8 +1038,11 @@ static topo_status cg_body(topo_ctx *ctx, int kind) {
   a.skip = skip;
   TOPO_HIP(launch_ku(s, KU_STORE_DOT, a, ctx->kap, ctx->red, fin_sum(&ctx->sc->pq), ctx->shape_cg));
   const Fin check{FIN_CG_CHECK, &ctx->sc->rr, ctx->sc};
-  TOPO_HIP(launch_cg_update_xr(s, ctx->ndof, ctx->sc, ctx->u, ctx->r, ctx->p, ctx->q, ctx->red, check, skip));
-  topo_status st = precondition(ctx, kind, skip);
+  // a single-precision multigrid preconditioner takes the residual in FP32, written
+  // by the same pass
+  float *r32 = (ctx->mixed && kind == TOPO_PRECOND_MG && ctx->lv.size() > 1) ? L0.f32.b : nullptr;
+  TOPO_HIP(launch_cg_update_xr(s, ctx->ndof, ctx->sc, ctx->u, ctx->r, ctx->p, ctx->q, ctx->red, check, skip, r32));
+  topo_status st = precondition(ctx, kind, skip, r32 != nullptr);
   if (st != TOPO_OK) return st;
   TOPO_HIP(launch_cg_update_p(s, ctx->ndof, ctx->sc, ctx->z, ctx->p, 0, skip));
   return TOPO_OK;
