@@ -106,6 +106,7 @@ typedef struct {
   int32_t mg_levels;          /* 0 = automatic (coarsest <= mg_max_coarse_dof)         */
   int32_t mg_max_coarse_dof;  /* automatic depth: stop coarsening at or below this     */
   int32_t cheb_degree;        /* Chebyshev smoother degree per pre/post smoothing      */
+  int32_t cheb_degree_coarse; /* the same below the finest level (0: cheb_degree)        */
   double rtol;                /* stop when ||r||_2 <= rtol ||f||_2 (free dofs)         */
   int32_t max_iters;          /* CG iteration cap per solve                           */
   int32_t warm_start;         /* topo_iterate: 0 start each solve from zero, 1 from the
@@ -162,7 +163,8 @@ typedef struct {
 } topo_iter_stats;
 
 /* Fills *opts with defaults: FP64, MG, automatic depth (coarsest <= 1500 dofs),
- * Chebyshev degree 2, rtol 1e-8, max_iters 1000, projected warm start (3), oc_tol 1e-12,
+ * Chebyshev degree 1 on the finest level and 4 below (cheb_degree_coarse),
+ * rtol 1e-8, max_iters 1000, projected warm start (3), oc_tol 1e-12,
  * check_every 4, use_graphs 1, nn_max_iters 200, autotune 0, coarse_tail_nodes 0,
  * mfma_smoothing 0, ku_kernel TOPO_KU_AUTO, ku_shape -1, coarse_refresh 1. */
 void topo_default_opts(topo_opts *opts);

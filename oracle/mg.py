@@ -101,7 +101,9 @@ class Level:
 class VCycle:
     """Symmetric V-cycle M ~ A^-1 of the reduced operator with identity rows."""
 
-    def __init__(self, p, E, KE, degree=2, max_coarse_dof=800, levels=None):
+    def __init__(self, p, E, KE, degree=2, max_coarse_dof=800, levels=None, coarse_degree=None):
+        """degree: Chebyshev steps per pre/post smoothing on the finest level;
+        coarse_degree: the same on the coarser levels (None: degree)."""
         dims = hierarchy(p.nelx, p.nely, p.nelz, max_coarse_dof)
         if levels is not None:
             dims = dims[:levels]
@@ -110,6 +112,7 @@ class VCycle:
         d = np.diag(KE)
         self.lam_max = float(np.linalg.eigvalsh(KE / np.sqrt(np.outer(d, d))).max())
         self.degree = degree
+        self.coarse_degree = degree if coarse_degree is None else coarse_degree
         self.levels, self.P = [], []
         Ecur, fcur = E, fixed
         for l, dl in enumerate(dims):
@@ -123,7 +126,7 @@ class VCycle:
                 Ecur, fcur = coarse_moduli(Ecur, dl, dc), fc
         self.coarse = sla.cho_factor(self.levels[-1].A.toarray())
 
-    def smooth(self, lv: Level, b, x):
+    def smooth(self, lv: Level, b, x, degree):
         """Chebyshev smoothing of A x = b from x (degree steps)."""
         hi = self.lam_max
         lo = hi / CHEB_RATIO
@@ -133,7 +136,7 @@ class VCycle:
         r = b - lv.A @ x
         dvec = (r / lv.diag) / theta
         x = x + dvec
-        for _ in range(self.degree - 1):
+        for _ in range(degree - 1):
             r = r - lv.A @ dvec
             rho_new = 1.0 / (2.0 * sigma - rho)
             dvec = rho_new * rho * dvec + (2.0 * rho_new / delta) * (r / lv.diag)
@@ -145,11 +148,12 @@ class VCycle:
         lv = self.levels[l]
         if l == len(self.levels) - 1:
             return sla.cho_solve(self.coarse, r)
-        x = self.smooth(lv, r, np.zeros_like(r))
+        deg = self.degree if l == 0 else self.coarse_degree
+        x = self.smooth(lv, r, np.zeros_like(r), deg)
         res = r - lv.A @ x
         ec = self.apply(self.P[l].T @ res, l + 1)
         x = x + self.P[l] @ ec
-        return self.smooth(lv, r, x)
+        return self.smooth(lv, r, x, deg)
 
 
 def pcg(A, b, M=None, x0=None, rtol=1e-10, max_iter=2000):

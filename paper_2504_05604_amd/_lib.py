@@ -61,7 +61,7 @@ class Problem_C(C.Structure):
 class Opts_C(C.Structure):
     _fields_ = [
         ("precision", C.c_int32), ("precond", C.c_int32), ("mg_levels", C.c_int32),
-        ("mg_max_coarse_dof", C.c_int32), ("cheb_degree", C.c_int32), ("rtol", C.c_double),
+        ("mg_max_coarse_dof", C.c_int32), ("cheb_degree", C.c_int32), ("cheb_degree_coarse", C.c_int32), ("rtol", C.c_double),
         ("max_iters", C.c_int32), ("warm_start", C.c_int32), ("oc_tol", C.c_double),
         ("check_every", C.c_int32), ("use_graphs", C.c_int32), ("nn_max_iters", C.c_int32),
         ("autotune", C.c_int32), ("coarse_tail_nodes", C.c_int32), ("mfma_smoothing", C.c_int32),

@@ -261,7 +261,10 @@ extern "C" void topo_default_opts(topo_opts *o) {
   o->precond = TOPO_PRECOND_MG;
   o->mg_levels = 0;
   o->mg_max_coarse_dof = 1500;
-  o->cheb_degree = 2;
+  // measured at 160x80x80: one step on the finest level and four below give the
+  // fewest V-cycle launches for the iteration count
+  o->cheb_degree = 1;
+  o->cheb_degree_coarse = 4;
   o->rtol = 1e-8;
   o->max_iters = 1000;
   o->warm_start = 3;
@@ -318,6 +321,8 @@ static topo_status validate(const topo_problem *P, const topo_opts *O) {
   if (O->precond == TOPO_PRECOND_LEARNED && O->nn_max_iters < 1)
     return set_error("nn_max_iters must be >= 1"), TOPO_EINVAL;
   if (O->cheb_degree < 1 || O->cheb_degree > 16) return set_error("cheb_degree must lie in [1, 16]"), TOPO_EINVAL;
+  if (O->cheb_degree_coarse < 0 || O->cheb_degree_coarse > 16)
+    return set_error("cheb_degree_coarse must lie in [0, 16]"), TOPO_EINVAL;
   if (!(O->rtol > 0.0) || O->max_iters < 1) return set_error("rtol > 0 and max_iters >= 1 required"), TOPO_EINVAL;
   if (!(O->oc_tol > 0.0)) return set_error("oc_tol must be > 0"), TOPO_EINVAL;
   if (O->mg_levels < 0 || O->mg_levels > 16) return set_error("mg_levels must lie in [0, 16]"), TOPO_EINVAL;
@@ -828,13 +833,20 @@ struct Cheb {
   }
 };
 
+// Chebyshev degree of a level: cheb_degree on the finest, cheb_degree_coarse
+// (when set) below it
+static int level_degree(const topo_ctx *ctx, const Level &L) {
+  const bool finest = &L == &ctx->lv[0];
+  return (finest || ctx->opts.cheb_degree_coarse == 0) ? ctx->opts.cheb_degree : ctx->opts.cheb_degree_coarse;
+}
+
 // Pre-smoothing from x = 0 (cheb_degree steps); on exit x and res = b - A x.
 // On small grids the first step's operand d0 = b dinv / theta is formed inside
 // the operator pass.
 template <typename T>
 static topo_status pre_smooth(topo_ctx *ctx, Level &L, const int *skip) {
   hipStream_t s = ctx->stream;
-  const int deg = ctx->opts.cheb_degree;
+  const int deg = level_degree(ctx, L);
   const Cheb ch(ctx->lam_max);
   const KappaT<T> &kap = kappa_of<T>(ctx);
   const LevelBufs<T> B = bufs<T>(L);
@@ -896,7 +908,7 @@ template <typename T>
 static topo_status post_smooth(topo_ctx *ctx, Level &L, const int *skip, const T *dot_with,
                                const Fin &fin) {
   hipStream_t s = ctx->stream;
-  const int deg = ctx->opts.cheb_degree;
+  const int deg = level_degree(ctx, L);
   const Cheb ch(ctx->lam_max);
   const KappaT<T> &kap = kappa_of<T>(ctx);
   const LevelBufs<T> B = bufs<T>(L);
@@ -950,7 +962,7 @@ static topo_status vcycle_tail(topo_ctx *ctx, const int *skip) {
   a.Ainv = ctx->Ainv;
   a.ncoarse = ctx->ncoarse;
   a.hw = hada_work(kappa_of<T>(ctx));
-  a.deg = ctx->opts.cheb_degree;
+  a.deg = ctx->opts.cheb_degree_coarse ? ctx->opts.cheb_degree_coarse : ctx->opts.cheb_degree;  // never the finest level
   const Cheb ch(ctx->lam_max);
   a.s0 = (T)(1.0 / ch.theta);
   double rho = 1.0 / ch.sigma;

@@ -29,7 +29,8 @@ def test_library_exports_every_declared_symbol():
 def test_default_opts():
     o = pkg.default_opts()
     assert o.precision == pkg.PREC_FP64 and o.precond == pkg.PRECOND_MG
-    assert o.rtol == 1e-8 and o.oc_tol == 1e-12 and o.cheb_degree == 2 and o.warm_start == 3
+    assert o.rtol == 1e-8 and o.oc_tol == 1e-12 and o.warm_start == 3
+    assert o.cheb_degree == 1 and o.cheb_degree_coarse == 4
     assert o.ku_kernel == pkg.KU_AUTO and o.ku_shape == -1 and o.coarse_tail_nodes == 0
     assert o.mg_max_coarse_dof == 1500 and o.coarse_refresh == 1
 
@@ -90,7 +91,8 @@ def test_setup_rejects_bad_options():
                     ({"precond": 9}, "preconditioner"), ({"precision": 7}, "precision"),
                     ({"ku_kernel": 3}, "ku_kernel"), ({"ku_shape": 4}, "ku_shape"),
                     ({"ku_shape": 5}, "ku_shape"), ({"ku_shape": 13}, "ku_shape"),
-                    ({"ku_shape": -2}, "ku_shape"), ({"coarse_refresh": 0}, "coarse_refresh")]:
+                    ({"ku_shape": -2}, "ku_shape"), ({"coarse_refresh": 0}, "coarse_refresh"),
+                    ({"cheb_degree_coarse": -1}, "cheb_degree_coarse"), ({"cheb_degree_coarse": 17}, "cheb_degree_coarse")]:
         st, err, _ = setup_status(p, **kw)
         assert st == _lib.TOPO_EINVAL and msg in err, (kw, err)
 

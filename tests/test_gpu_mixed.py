@@ -72,8 +72,10 @@ def test_low_precision_preconditioner_matches_oracle(case, variant, cap):
     fm[p.fixed_dofs] = True
     r = synth.random_vector(6, p.ndof)
     r[fm] = 0.0
-    ref = mg.VCycle(p, E, KE, degree=2, max_coarse_dof=cap).apply(r)
-    with topo.Context(p, topo.default_opts(mg_max_coarse_dof=cap, **VARIANTS[variant])) as ctx:
+    # the default smoother degrees: one step on the finest level, four below
+    ref = mg.VCycle(p, E, KE, degree=1, coarse_degree=4, max_coarse_dof=cap).apply(r)
+    with topo.Context(p, topo.default_opts(mg_max_coarse_dof=cap, cheb_degree=1, cheb_degree_coarse=4,
+                                           **VARIANTS[variant])) as ctx:
         z = torch.empty(p.ndof, dtype=torch.float64, device="cuda")
         ctx.apply_precond(torch.from_numpy(x).cuda(), torch.from_numpy(r).cuda(), z)
         torch.cuda.synchronize()

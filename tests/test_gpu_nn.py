@@ -339,7 +339,8 @@ def test_training_pairs_match_oracle_iterates():
     p = synth.random_problem(3, 16, boxes=1)
     x = synth.random_density(11, p.nel, 0.2, 1.0)
     iters = np.array([0, 1, 2, 5], np.int32)
-    opts = topo.default_opts(precond=topo.PRECOND_MG, mg_max_coarse_dof=140)  # as the oracle's V-cycle below
+    # the same hierarchy and smoother as the oracle's V-cycle below
+    opts = topo.default_opts(precond=topo.PRECOND_MG, mg_max_coarse_dof=140, cheb_degree=2, cheb_degree_coarse=2)
     V = p.nnodes
     n = iters.size
     rho = torch.empty(n * V, dtype=torch.float32, device="cuda")

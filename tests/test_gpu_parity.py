@@ -77,10 +77,18 @@ def test_apply_K_matches_oracle(case, kernel):
     assert np.abs(got - ref).max() <= 1e-13 * np.abs(ref).max()
 
 
+# multigrid variants: coarse-level cap, Chebyshev degree on the finest and the
+# coarser levels, single-workgroup tail below this many nodes
+MG_VARIANTS = {
+    "mg140": (140, 2, 2, 0), "mg400": (400, 2, 2, 0), "mg400deg3": (400, 3, 3, 0),
+    "mg140deg1": (140, 1, 1, 0), "mg140_tail1024": (140, 2, 2, 1024), "mg140_tail4000": (140, 2, 2, 4000),
+    "mg1500": (1500, 2, 2, 0), "mg1500d1c4": (1500, 1, 4, 0), "mg140d1c4_tail1024": (140, 1, 4, 1024),
+}
+
+
 @pytest.mark.parametrize("kernel", list(KERNELS))
 @pytest.mark.parametrize("case", CASES)
-@pytest.mark.parametrize("precond", ["mg140", "mg400", "mg400deg3", "mg140deg1", "mg140_tail1024",
-                                     "mg140_tail4000", "mg1500", "jacobi"])
+@pytest.mark.parametrize("precond", list(MG_VARIANTS) + ["jacobi"])
 def test_preconditioner_matches_oracle(case, precond, kernel):
     """By default every level runs the per-level kernels; _tail1024 and _tail4000
     run the levels below that many nodes as one single-workgroup launch."""
@@ -90,13 +98,11 @@ def test_preconditioner_matches_oracle(case, precond, kernel):
     r = synth.random_vector(6, p.ndof)
     r[fixed_mask(p)] = 0.0
     if precond.startswith("mg"):
-        coarse = int(precond[2:].split("_")[0].split("deg")[0])
-        deg = 3 if precond.endswith("deg3") else (1 if precond.endswith("deg1") else 2)
-        tail = 4000 if precond.endswith("tail4000") else (1024 if precond.endswith("tail1024") else 0)
-        V = mg.VCycle(p, E, KE, degree=deg, max_coarse_dof=coarse)
+        coarse, deg, degc, tail = MG_VARIANTS[precond]
+        V = mg.VCycle(p, E, KE, degree=deg, coarse_degree=degc, max_coarse_dof=coarse)
         ref = V.apply(r)
         opts = topo.default_opts(precond=topo.PRECOND_MG, mg_max_coarse_dof=coarse, cheb_degree=deg,
-                                 coarse_tail_nodes=tail, ku_kernel=KERNELS[kernel])
+                                 cheb_degree_coarse=degc, coarse_tail_nodes=tail, ku_kernel=KERNELS[kernel])
     else:
         K = mg.with_identity_rows(fem.assemble(E, KE, fem.element_dofs(p.nelx, p.nely, p.nelz), p.ndof),
                                   fixed_mask(p))
@@ -111,8 +117,9 @@ def test_preconditioner_matches_oracle(case, precond, kernel):
     assert np.abs(got - ref).max() <= 1e-11 * np.abs(ref).max()
 
 
+@pytest.mark.parametrize("degrees", [(2, 2), (1, 4)])
 @pytest.mark.parametrize("dims", [(32, 16, 16), (40, 20, 20)])
-def test_preconditioner_with_large_coarsest_level_matches_oracle(dims):
+def test_preconditioner_with_large_coarsest_level_matches_oracle(dims, degrees):
     """Coarsest levels of 675 and 1188 dofs: the blocked Gauss-Jordan inverse
     (64-column panels, ragged last panel) against the oracle's exact coarse solve."""
     p = synth.cantilever(*dims, volfrac=0.3, rmin=1.5, n_iter=1)
@@ -120,9 +127,10 @@ def test_preconditioner_with_large_coarsest_level_matches_oracle(dims):
     E = fem.simp_modulus(x, p.E0, p.Emin, p.penal)
     r = synth.random_vector(6, p.ndof)
     r[fixed_mask(p)] = 0.0
-    V = mg.VCycle(p, E, KE, degree=2, max_coarse_dof=1500)
+    V = mg.VCycle(p, E, KE, degree=degrees[0], coarse_degree=degrees[1], max_coarse_dof=1500)
     ref = V.apply(r)
-    with topo.Context(p, topo.default_opts(mg_max_coarse_dof=1500)) as ctx:
+    with topo.Context(p, topo.default_opts(mg_max_coarse_dof=1500, cheb_degree=degrees[0],
+                                           cheb_degree_coarse=degrees[1])) as ctx:
         assert ctx.mg_levels == len(V.levels)
         z = torch.empty(p.ndof, dtype=torch.float64, device="cuda")
         ctx.apply_precond(dev(x), dev(r), z)

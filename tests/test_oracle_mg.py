@@ -46,15 +46,20 @@ def test_coarse_moduli_of_odd_grid_count_missing_children_as_zero():
     np.testing.assert_allclose(Ec, [1.0, 0.5])
 
 
-def setup_vcycle(seed=0):
+def setup_vcycle(seed=0, degrees=(2, None)):
     p = synth.cantilever(12, 6, 6, volfrac=0.3, rmin=1.5, n_iter=1)
     x = synth.random_density(seed, p.nel, 0.0, 1.0)
     E = fem.simp_modulus(x, p.E0, p.Emin, p.penal)
-    return p, E, mg.VCycle(p, E, KE, degree=2, max_coarse_dof=300)
+    return p, E, mg.VCycle(p, E, KE, degree=degrees[0], coarse_degree=degrees[1], max_coarse_dof=300)
 
 
-def test_vcycle_is_symmetric():
-    p, E, V = setup_vcycle()
+# (finest-level degree, coarser-level degree); None: the same on every level
+DEGREES = [(2, None), (1, 4), (3, 1)]
+
+
+@pytest.mark.parametrize("degrees", DEGREES)
+def test_vcycle_is_symmetric(degrees):
+    p, E, V = setup_vcycle(degrees=degrees)
     assert len(V.levels) >= 3
     fixed = V.levels[0].fixed
     a = synth.random_vector(1, p.ndof)
@@ -65,8 +70,9 @@ def test_vcycle_is_symmetric():
     assert a @ Ma > 0
 
 
-def test_mg_pcg_matches_direct_solve():
-    p, E, V = setup_vcycle(3)
+@pytest.mark.parametrize("degrees", DEGREES)
+def test_mg_pcg_matches_direct_solve(degrees):
+    p, E, V = setup_vcycle(3, degrees)
     A = V.levels[0].A
     b = p.f.copy()
     x, it, rr = mg.pcg(A, b, V.apply, rtol=1e-12)
