@@ -249,44 +249,48 @@ __global__ __launch_bounds__(kInvThreads) void dense_invert_lds_kernel(int n, do
   for (int t = threadIdx.x; t < nn; t += blockDim.x) A[t] = M[t];
 }
 
-// P = A_KK^-1 for the panel K = [k0, k0 + kb): 1024 threads, thread (ty, tx) owns
-// entries (ty + 16 a, tx) of the block padded to kGjNb x kGjNb with the identity.
-// The threads that update column k+1 and row k+1 also publish them for the next
-// step (double-buffered), so each elimination step takes one barrier.
-__global__ __launch_bounds__(1024) void gj_panel_inv_kernel(int n, const double *A, int k0, int kb,
-                                                            double *P) {
-  __shared__ double M[kGjNb][kGjNb + 1];
-  __shared__ double col[2][kGjNb], rowk[2][kGjNb];
-  const int tx = threadIdx.x % kGjNb, ty = threadIdx.x / kGjNb;  // 16 row groups
+// a double from lane `lane` of the wave (two 32-bit register reads)
+__device__ __forceinline__ double read_lane_f64(double v, int lane) {
+  const long long bits = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)bits, lane);
+  const int hi = __builtin_amdgcn_readlane((int)(bits >> 32), lane);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// P = A_KK^-1 for the panel K = [k0, k0 + kb), the block padded to kGjNb x kGjNb
+// with the identity.  Four waves; lane c of wave w holds column c of rows
+// 16 w .. 16 w + 15 in registers.  Step k: the wave holding row k publishes it
+// through LDS (double-buffered, one four-wave barrier per step), and every lane
+// reads the pivot column entries of its own rows from lane k of its own wave.
+__global__ __launch_bounds__(256) void gj_panel_inv_kernel(int n, const double *A, int k0, int kb,
+                                                           double *P) {
+  __shared__ double piv[2][kGjNb];
+  const int c = threadIdx.x % kGjNb, w = threadIdx.x / kGjNb;
+  double M[16];
 #pragma unroll
-  for (int a = 0; a < 4; ++a) {
-    const int r = ty + 16 * a;
-    const double v = (r < kb && tx < kb) ? A[(int64_t)(k0 + r) * n + k0 + tx] : (r == tx ? 1.0 : 0.0);
-    M[r][tx] = v;
-    if (tx == 0) col[0][r] = v;
-    if (r == 0) rowk[0][tx] = v;
+  for (int i = 0; i < 16; ++i) {
+    const int r = 16 * w + i;
+    M[i] = (r < kb && c < kb) ? A[(int64_t)(k0 + r) * n + k0 + c] : (r == c ? 1.0 : 0.0);
   }
-  __syncthreads();
-  for (int k = 0; k < kb; ++k) {
-    const int cur = k & 1, nxt = cur ^ 1;
-    const double inv = 1.0 / col[cur][k];
-    const double rk = rowk[cur][tx];
 #pragma unroll
-    for (int a = 0; a < 4; ++a) {
-      const int r = ty + 16 * a;
-      const double cr = col[cur][r];
-      const double upd = M[r][tx] - cr * rk * inv;
-      const double v = r == k ? (tx == k ? inv : rk * inv) : (tx == k ? -cr * inv : upd);
-      M[r][tx] = v;
-      if (tx == k + 1) col[nxt][r] = v;
-      if (r == k + 1) rowk[nxt][tx] = v;
-    }
+  for (int k = 0; k < kGjNb; ++k) {
+    double *pv = piv[k & 1];
+    if (w == k / 16) pv[c] = M[k % 16];
     __syncthreads();
+    const double pk = pv[c];  // M[k][c]
+    const double inv = 1.0 / pv[k];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      const int r = 16 * w + i;
+      const double ck = read_lane_f64(M[i], k);  // M[r][k]
+      const double upd = M[i] - ck * pk * inv;
+      M[i] = r == k ? (c == k ? inv : pk * inv) : (c == k ? -ck * inv : upd);
+    }
   }
 #pragma unroll
-  for (int a = 0; a < 4; ++a) {
-    const int r = ty + 16 * a;
-    if (r < kb && tx < kb) P[r * kb + tx] = M[r][tx];
+  for (int i = 0; i < 16; ++i) {
+    const int r = 16 * w + i;
+    if (r < kb && c < kb) P[r * kb + c] = M[i];
   }
 }
 
@@ -406,7 +410,7 @@ hipError_t launch_dense_invert(hipStream_t s, int n, double *A, double *work) {
   const int nt = (n + kGjNb - 1) / kGjNb;
   for (int k0 = 0; k0 < n; k0 += kGjNb) {
     const int kb = std::min(kGjNb, n - k0);
-    gj_panel_inv_kernel<<<1, 1024, 0, s>>>(n, A, k0, kb, P);
+    gj_panel_inv_kernel<<<1, 256, 0, s>>>(n, A, k0, kb, P);
     gj_panel_rows_kernel<<<2 * nt, 256, 0, s>>>(n, A, k0, kb, P, C);
     gj_update_kernel<<<dim3(nt, nt), 256, 0, s>>>(n, A, k0, kb, P, C);
   }
