@@ -130,10 +130,11 @@ typedef struct {
   int32_t ku_shape;           /* -1: launch shapes by grid size (or autotuned); else one
                                  launch shape for every level and the CG product:
                                  0..3 node-column kernel, nodes per thread column x
-                                 threads = 8x256, 8x128, 2x128, 1x64; 6..12 element-column
+                                 threads = 8x256, 8x128, 2x128, 1x64; 6..14 element-column
                                  kernel, node planes per slab x tile = 8x32x8, 8x16x16,
                                  4x16x8 (next plane loaded ahead), 2x8x8 (ahead), 1x8x8,
-                                 8x32x8 (ahead), 8x16x16 (ahead); 4 and 5, the matrix-core
+                                 8x32x8 (ahead), 8x16x16 (ahead), 8x32x8 (planes staged
+                                 through LDS), 8x16x16 (staged); 4 and 5, the matrix-core
                                  kernels, are chosen through precision / mfma_smoothing  */
   int32_t coarse_refresh;     /* topo_iterate: recompute the coarsest level's dense inverse
                                  every this many SIMP iterations (1 = every iteration); in

@@ -155,15 +155,16 @@ hipError_t launch_ku(hipStream_t s, KuEpi epi, const KuArgs &a, const Kappa &kap
 // single-precision operator (smoothing passes only: no reducing epilogues)
 hipError_t launch_ku(hipStream_t s, KuEpi epi, const KuArgsT<float> &a, const KappaT<float> &kap,
                      const Reducer &red, const Fin &fin, int shape = -1);
-// launch shape by grid size within a K.u kernel family (TOPO_KU_*)
-int ku_shape_for(const Grid &g, KuEpi epi, int family);
+// launch shape by grid size within a K.u kernel family (TOPO_KU_*), for the
+// double- or the single-precision operator
+int ku_shape_for(const Grid &g, KuEpi epi, int family, bool single = false);
 // launch shapes: 0..3 the node-column vector kernel (FP64 and FP32), 4 the FP32
 // matrix-core kernel (single precision only), 5 the matrix-core kernel with BF16
 // operands (single precision only; changes the arithmetic, chosen only in BF16
 // mode), 6..10 the element-column kernel in the sum/difference basis
 constexpr int kKuShapes = 4;
 constexpr int kKuShapeMfma = 4, kKuShapeMfmaBf16 = 5;
-constexpr int kKuShapeHada = 6, kKuShapesHada = 7;
+constexpr int kKuShapeHada = 6, kKuShapesHada = 9;
 hipError_t launch_ku_mfma(hipStream_t s, KuEpi epi, const KuArgsT<float> &a, bool bf16);
 template <typename T>
 hipError_t launch_ku_hada(hipStream_t s, KuEpi epi, const KuArgsT<T> &a, const KappaT<T> &kap,

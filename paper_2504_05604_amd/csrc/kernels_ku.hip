@@ -190,18 +190,19 @@ static hipError_t launch_ku_shape(hipStream_t s, KuEpi epi, const KuArgsT<T> &a,
 // epilogues) or 128 threads (CG product); 80x40x40 -> KZ 2 x 128; smaller grids ->
 // KZ 1 x 64, where a launch is bound by latency rather than arithmetic.
 // Element-column shapes measured on MI355X (CG product): 160x80x80 -> 32 x 8
-// tiles of 8 planes, 24 us; 80x40x40 and 40x20x20 -> 8 x 8 tiles of 2 planes with
-// the next plane loaded ahead, 10 and 6.5 us; smaller grids -> 8 x 8 tiles of
-// one plane (latency bound, about 6 us).
-int ku_shape_for(const Grid &g, KuEpi epi, int family) {
+// tiles of 8 planes, 20 us (single-precision smoothing: the same tiles with the
+// node planes staged through LDS, about 1 % faster per SIMP iteration); 80x40x40
+// -> 8 x 8 tiles of 2 planes with the next plane loaded ahead, 10 us; smaller
+// grids -> 8 x 8 tiles of one plane (latency bound, 4-6 us).
+int ku_shape_for(const Grid &g, KuEpi epi, int family, bool single) {
   const int64_t nn = g.nnodes();
   if (family == TOPO_KU_NODE) {
     if (nn >= 600000) return epi == KU_STORE_DOT ? 1 : 0;
     if (nn >= 60000) return 2;
     return 3;
   }
-  if (nn >= 600000) return kKuShapeHada + 0;
-  if (nn >= 8000) return kKuShapeHada + 3;
+  if (nn >= 600000) return single ? kKuShapeHada + 7 : kKuShapeHada + 0;
+  if (nn >= 50000) return kKuShapeHada + 3;
   return kKuShapeHada + 4;
 }
 
@@ -226,7 +227,7 @@ std::vector<int> ku_tunable_shapes(bool single, int family) {
 template <typename T>
 static hipError_t launch_ku_t(hipStream_t s, KuEpi epi, const KuArgsT<T> &a, const KappaT<T> &kap,
                               const Reducer &red, const Fin &fin, int shape) {
-  if (shape < 0) shape = ku_shape_for(a.g, epi, TOPO_KU_AUTO);
+  if (shape < 0) shape = ku_shape_for(a.g, epi, TOPO_KU_AUTO, std::is_same<T, float>::value);
   if constexpr (std::is_same<T, float>::value) {
     if (shape == kKuShapeMfma || shape == kKuShapeMfmaBf16) return launch_ku_mfma(s, epi, a, shape == kKuShapeMfmaBf16);
   }

@@ -103,12 +103,10 @@ __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(PF ? 1 
     }
   };
 
-  // modulus of element layer L of this column (0 outside the grid)
-  auto load_E = [&](int L) {
-    const T *__restrict__ Ep = a.E + (int64_t)min(max(L, 0), g.nz - 1) * g.nx * g.ny;  // uniform
-    const T Eraw = Ep[eoff];
-    return (elem_xy && L >= 0 && L < g.nz) ? Eraw : T(0);
-  };
+  // modulus of element layer L of this column, raw; zeroed outside the grid only
+  // where it is used (E_at), so a load issued ahead is not waited for at once
+  auto load_E = [&](int L) { return a.E[(int64_t)min(max(L, 0), g.nz - 1) * g.nx * g.ny + eoff]; };
+  auto E_at = [&](int L, T Eraw) { return (elem_xy && L >= 0 && L < g.nz) ? Eraw : T(0); };
 
   // Memory order within a layer (vector loads retire in issue order, so a wait
   // for one load waits for every older one): first the epilogue inputs of node
@@ -157,7 +155,7 @@ __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(PF ? 1 
         bdt[0][c] = bdn[0][c];
         bdt[1][c] = bdn[1][c];
       }
-      Ee = Enxt;
+      Ee = E_at(L, Enxt);
       if (q < KZ && L + 1 < k1) {
         load_raw(L + 2, nxt, bdn);
         Enxt = load_E(L + 1);
@@ -166,7 +164,7 @@ __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(PF ? 1 
     } else {
       T v[3][4];
       load_raw(L + 1, v, bdt);
-      Ee = load_E(L);
+      Ee = E_at(L, load_E(L));
       modes(v, Pt, selft);
     }
     T w[8];
@@ -225,6 +223,167 @@ __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(PF ? 1 
   ku_block_reduce<EPI>(a, dotv, partials);
 }
 
+// Staged variant of the same kernel.  The block loads each node plane of its
+// tile once, (TX+1)(TY+1) nodes spread evenly over its threads instead of four
+// corners per thread, into registers two planes ahead of use, and hands it to
+// the element columns through LDS (double-buffered; the barrier that publishes
+// a plane is the one the corner exchange already needs).  A plane's loads thus
+// stay in flight through one layer's arithmetic and barrier, with a third of the
+// load instructions.  Same arithmetic in the same order: bit-identical to the
+// other shapes.
+template <int EPI, int KZ, int TX, int TY, typename T>
+__global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(3))) void ku_hada_lds_kernel(
+    KuArgsT<T> a, HadaW<T> hw, int tiles_x, int tiles_xy, double *partials) {
+  if (a.skip && *a.skip) return;
+  constexpr int NT = TX * TY;
+  constexpr int NX1 = TX + 1;
+  constexpr int NV = NX1 * (TY + 1) * 3;  // values of one node plane of the tile
+  constexpr int SL = (NV + NT - 1) / NT;  // of which each thread loads SL
+  __shared__ T xch[2][3][3][NT];
+  __shared__ T stage[2][NV];
+  const Grid g = a.g;
+  const int NX = g.NX(), NY = g.NY(), NZ = g.NZ();
+  const int64_t plane = (int64_t)NX * NY;
+  const int tile = xcd_tile(linear_block(), gridDim.x * gridDim.y);
+  const int txy = tile % tiles_xy, slab = tile / tiles_xy;
+  const int tid = threadIdx.x, tx = tid % TX, ty = tid / TX;
+  const int i0 = (txy % tiles_x) * (TX - 1) - 1, j0 = (txy / tiles_x) * (TY - 1) - 1;
+  const int ie = i0 + tx, je = j0 + ty;
+  const int k0 = slab * KZ, k1 = min(k0 + KZ, NZ);
+  const bool elem_xy = ie >= 0 && ie < g.nx && je >= 0 && je < g.ny;
+  const bool owner = tx < TX - 1 && ty < TY - 1 && ie + 1 <= g.nx && je + 1 <= g.ny;
+  constexpr bool kScaled = EpiTraits<EPI>::scaled_operand;
+  const T *__restrict__ u = kScaled ? a.b : a.u;
+  const T *__restrict__ dinv = a.dinv;
+
+  // value d = tid + s NT of the staged plane: node (d/3 mod NX1, d/3 div NX1) of
+  // the tile, component d mod 3; clamped into the grid as in the other shapes
+  // (clamped nodes only feed elements of modulus 0)
+  uint32_t soff[SL];
+#pragma unroll
+  for (int s = 0; s < SL; ++s) {
+    const int d = min(tid + s * NT, NV - 1), nn = d / 3, c = d - 3 * nn;
+    const int ci = min(max(i0 + nn % NX1, 0), g.nx), cj = min(max(j0 + nn / NX1, 0), g.ny);
+    soff[s] = 3u * (uint32_t)(cj * NX + ci) + (uint32_t)c;
+  }
+  auto stage_load = [&](int kp, T(&r)[SL], T(&r2)[SL]) {
+    const int64_t pbase = 3 * (int64_t)min(max(kp, 0), g.nz) * plane;  // uniform
+#pragma unroll
+    for (int s = 0; s < SL; ++s) {
+      r[s] = u[pbase + soff[s]];
+      if constexpr (kScaled) r2[s] = dinv[pbase + soff[s]];
+    }
+  };
+  auto stage_store = [&](T *buf, const T(&r)[SL], const T(&r2)[SL]) {
+#pragma unroll
+    for (int s = 0; s < SL; ++s) {
+      const int d = tid + s * NT;
+      if (s < SL - 1 || d < NV) buf[d] = kScaled ? r[s] * r2[s] * a.s0 : r[s];
+    }
+  };
+  // x/y modes of the staged plane at this thread's element column, and the
+  // operand at corner (1, 1)
+  auto modes_lds = [&](const T *buf, T(&m)[3][4], T(&self)[3]) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      T v[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) v[q] = buf[3 * ((ty + (q >> 1)) * NX1 + tx + (q & 1)) + c];
+      self[c] = v[3];
+      xy_pass(v, m[c]);
+    }
+  };
+  const uint32_t eoff = (uint32_t)(min(max(je, 0), g.ny - 1) * g.nx + min(max(ie, 0), g.nx - 1));
+  const uint32_t own = (uint32_t)((je + 1) * NX + (ie + 1));
+  // modulus of element layer L, loaded ahead of use: the value is taken raw and
+  // zeroed outside the grid only where it is used, so no wait for it comes early
+  auto load_E = [&](int L) { return a.E[(int64_t)min(max(L, 0), g.nz - 1) * g.nx * g.ny + eoff]; };
+
+  // node plane k0-1+m is staged in stage[m & 1] and loaded into rg[m & 1]
+  T rg[2][SL], rd[2][SL];
+  double dotv = 0.0;
+  T Pb[3][4], selfb[3], ytp[3][4];
+  T Ecur = load_E(k0 - 1), Enx = load_E(k0);
+  EpiIn<T> in_nx;  // epilogue inputs of the next node plane, loaded one layer ahead
+  stage_load(k0 - 1, rg[0], rd[0]);
+  stage_load(k0, rg[1], rd[1]);
+  stage_store(stage[0], rg[0], rd[0]);
+  stage_load(k0 + 1, rg[0], rd[0]);
+  __syncthreads();
+  modes_lds(stage[0], Pb, selfb);
+  stage_store(stage[1], rg[1], rd[1]);
+  __syncthreads();  // plane k0 staged, and every read of plane k0-1 done
+#pragma unroll
+  for (int q = 0; q <= KZ; ++q) {
+    const int L = k0 - 1 + q;  // element layer between node planes L and L+1
+    if (L >= k1) break;
+    const int64_t nL = (int64_t)L * plane + own;
+    // issue order: modulus two layers ahead, the next plane's epilogue inputs,
+    // then the node plane three ahead, so every wait below leaves the loads of
+    // this layer in flight
+    const T Ee = (elem_xy && L >= 0 && L < g.nz) ? Ecur : T(0);
+    Ecur = Enx;
+    if (q + 2 <= KZ) Enx = load_E(L + 2);
+    const EpiIn<T> in = in_nx;
+    if (q + 1 <= KZ && L + 1 < k1 && owner) ku_epi_load<EPI, false>(a, nL + plane, dinv, in_nx);
+    if (q + 3 <= KZ + 1) stage_load(L + 3, rg[(q + 1) & 1], rd[(q + 1) & 1]);
+    // node plane L+2 (loaded one layer ago) into the buffer whose plane (L) was
+    // last read before the previous barrier; published by this layer's barrier
+    if (q + 2 <= KZ + 1) stage_store(stage[q & 1], rg[q & 1], rd[q & 1]);
+    T Pt[3][4], selft[3];
+    modes_lds(stage[(q + 1) & 1], Pt, selft);
+    T w[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) w[k] = Ee * hw.w[k];
+    T h[3][8];
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        h[c][r] = Pb[c][r] + Pt[c][r];
+        h[c][r + 4] = Pb[c][r] - Pt[c][r];
+      }
+    T gm[3][8];
+    hada_blocks(w, h, gm);
+    T cn[3][4];
+    if (q > 0) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        T acc[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc[r] = ytp[c][r] + (gm[c][r] + gm[c][r + 4]);
+        xy_pass(acc, cn[c]);
+      }
+      T(&buf)[3][3][NT] = xch[q & 1];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        buf[0][c][tid] = cn[c][0];
+        buf[1][c][tid] = cn[c][1];
+        buf[2][c][tid] = cn[c][2];
+      }
+    }
+    __syncthreads();
+    if (q > 0 && owner) {
+      const T(&buf)[3][3][NT] = xch[q & 1];
+      T Au[3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+        Au[c] = ((cn[c][3] + buf[2][c][tid + 1]) + buf[1][c][tid + TX]) + buf[0][c][tid + TX + 1];
+      ku_epi_finish<EPI>(a, nL, in, selfb, Au, dotv);
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        ytp[c][r] = gm[c][r] - gm[c][r + 4];
+        Pb[c][r] = Pt[c][r];
+      }
+      selfb[c] = selft[c];
+    }
+  }
+  ku_block_reduce<EPI>(a, dotv, partials);
+}
+
 template <int KZ, int TX, int TY>
 struct HadaShape {
   static int tiles_x(const Grid &g) { return (g.NX() + TX - 2) / (TX - 1); }
@@ -234,7 +393,8 @@ struct HadaShape {
   }
 };
 
-template <int KZ, int TX, int TY, bool PF, typename T>
+// VAR: 0 plain, 1 next plane loaded one layer ahead, 2 staged through LDS
+template <int KZ, int TX, int TY, int VAR, typename T>
 static hipError_t launch_hada_shape(hipStream_t s, KuEpi epi, const KuArgsT<T> &a, const KappaT<T> &kap,
                                     const Reducer &red, int *nparts_out) {
   using S = HadaShape<KZ, TX, TY>;
@@ -245,8 +405,13 @@ static hipError_t launch_hada_shape(hipStream_t s, KuEpi epi, const KuArgsT<T> &
   if (ku_reduces(epi, a) && nb > red.max_blocks) return hipErrorInvalidValue;
   const HadaW<T> hw = hada_work(kap);
   const dim3 grid((unsigned)nb);
-#define TOPO_KU_CASE(E) \
-  case E: ku_hada_kernel<E, KZ, TX, TY, PF, T><<<grid, TX * TY, 0, s>>>(a, hw, tx, txy, red.partials); break;
+#define TOPO_KU_CASE(E)                                                                                  \
+  case E:                                                                                                \
+    if constexpr (VAR == 2)                                                                              \
+      ku_hada_lds_kernel<E, KZ, TX, TY, T><<<grid, TX * TY, 0, s>>>(a, hw, tx, txy, red.partials);       \
+    else                                                                                                 \
+      ku_hada_kernel<E, KZ, TX, TY, VAR == 1, T><<<grid, TX * TY, 0, s>>>(a, hw, tx, txy, red.partials); \
+    break;
   switch (epi) {
     TOPO_KU_CASE(KU_STORE)
     TOPO_KU_CASE(KU_STORE_DOT)
@@ -264,24 +429,26 @@ static hipError_t launch_hada_shape(hipStream_t s, KuEpi epi, const KuArgsT<T> &
 }
 
 // element-column shapes (index relative to kKuShapeHada): KZ x TX x TY, and
-// whether the next node plane is loaded one layer ahead.  Every shape runs the
-// same arithmetic in the same order (a node always sums its four element
-// columns in the same order), so they give bit-identical results.
+// how node planes are loaded (VAR above).  Every shape runs the same arithmetic
+// in the same order (a node always sums its four element columns in the same
+// order), so they give bit-identical results.
 #define TOPO_HADA_SHAPES(X) \
-  X(0, 8, 32, 8, false)     \
-  X(1, 8, 16, 16, false)    \
-  X(2, 4, 16, 8, true)      \
-  X(3, 2, 8, 8, true)       \
-  X(4, 1, 8, 8, false)      \
-  X(5, 8, 32, 8, true)      \
-  X(6, 8, 16, 16, true)
+  X(0, 8, 32, 8, 0)         \
+  X(1, 8, 16, 16, 0)        \
+  X(2, 4, 16, 8, 1)         \
+  X(3, 2, 8, 8, 1)          \
+  X(4, 1, 8, 8, 0)          \
+  X(5, 8, 32, 8, 1)         \
+  X(6, 8, 16, 16, 1)        \
+  X(7, 8, 32, 8, 2)         \
+  X(8, 8, 16, 16, 2)
 
 template <typename T>
 hipError_t launch_ku_hada(hipStream_t s, KuEpi epi, const KuArgsT<T> &a, const KappaT<T> &kap,
                           const Reducer &red, int which, int *nparts) {
   switch (which) {
-#define TOPO_HADA_LAUNCH(I, KZ, TX, TY, PF) \
-  case I: return launch_hada_shape<KZ, TX, TY, PF>(s, epi, a, kap, red, nparts);
+#define TOPO_HADA_LAUNCH(I, KZ, TX, TY, VAR) \
+  case I: return launch_hada_shape<KZ, TX, TY, VAR>(s, epi, a, kap, red, nparts);
     TOPO_HADA_SHAPES(TOPO_HADA_LAUNCH)
 #undef TOPO_HADA_LAUNCH
     default: return hipErrorInvalidValue;
@@ -295,7 +462,7 @@ template hipError_t launch_ku_hada<float>(hipStream_t, KuEpi, const KuArgsT<floa
 
 int64_t ku_hada_max_blocks(const Grid &g) {
   int64_t m = 0;
-#define TOPO_HADA_BLOCKS(I, KZ, TX, TY, PF) m = std::max<int64_t>(m, HadaShape<KZ, TX, TY>::blocks(g));
+#define TOPO_HADA_BLOCKS(I, KZ, TX, TY, VAR) m = std::max<int64_t>(m, HadaShape<KZ, TX, TY>::blocks(g));
   TOPO_HADA_SHAPES(TOPO_HADA_BLOCKS)
 #undef TOPO_HADA_BLOCKS
   return m;

@@ -579,7 +579,7 @@ extern "C" topo_status topo_setup(const topo_problem *P, const topo_opts *O, voi
   // launch shapes by grid size within the chosen K.u kernel (the matrix-core
   // modes above keep theirs); the autotuner may replace them
   for (Level &L : ctx->lv)
-    if (L.shape < 0) L.shape = O->ku_shape >= 0 ? O->ku_shape : ku_shape_for(L.g, KU_CHEB, O->ku_kernel);
+    if (L.shape < 0) L.shape = O->ku_shape >= 0 ? O->ku_shape : ku_shape_for(L.g, KU_CHEB, O->ku_kernel, ctx->mixed);
   ctx->shape_cg = O->ku_shape >= 0 ? O->ku_shape : ku_shape_for(g, KU_STORE_DOT, O->ku_kernel);
   if (O->autotune) {
     st = autotune(ctx);

@@ -90,7 +90,7 @@ def test_setup_rejects_bad_options():
     for kw, msg in [({"cheb_degree": 0}, "cheb_degree"), ({"rtol": 0.0}, "rtol"),
                     ({"precond": 9}, "preconditioner"), ({"precision": 7}, "precision"),
                     ({"ku_kernel": 3}, "ku_kernel"), ({"ku_shape": 4}, "ku_shape"),
-                    ({"ku_shape": 5}, "ku_shape"), ({"ku_shape": 13}, "ku_shape"),
+                    ({"ku_shape": 5}, "ku_shape"), ({"ku_shape": 15}, "ku_shape"),
                     ({"ku_shape": -2}, "ku_shape"), ({"coarse_refresh": 0}, "coarse_refresh"),
                     ({"cheb_degree_coarse": -1}, "cheb_degree_coarse"), ({"cheb_degree_coarse": 17}, "cheb_degree_coarse")]:
         st, err, _ = setup_status(p, **kw)

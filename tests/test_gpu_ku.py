@@ -16,8 +16,8 @@ import paper_2504_05604_amd as topo  # noqa: E402
 pytestmark = pytest.mark.gpu
 KE = element_stiffness(0.3)
 
-# launch shapes: 0..3 node-column kernel, 6..12 element-column kernel
-SHAPES = [0, 1, 2, 3, 6, 7, 8, 9, 10, 11, 12]
+# launch shapes: 0..3 node-column kernel, 6..14 element-column kernel
+SHAPES = [0, 1, 2, 3, 6, 7, 8, 9, 10, 11, 12, 13, 14]
 # ragged in every tile and slab size of both kernels, smaller than one tile, one element thick
 GRIDS = [(37, 21, 19), (5, 3, 4), (1, 1, 1), (40, 1, 3), (2, 17, 1)]
 
