@@ -195,8 +195,11 @@ hipError_t launch_cg_start(hipStream_t s, Scalars *sc, double rtol2, int max_ite
 // z = r * dinv; fin.out = r.z
 hipError_t launch_jacobi(hipStream_t s, int64_t n, const double *r, const double *dinv, double *z,
                          const Reducer &red, const Fin &fin, const int *skip = nullptr);
-// p = z + beta p (p = z if first); beta is set by the FIN_RZ finalize of r.z
+// p = z + beta p (p = z if first); beta is set by the FIN_RZ finalize of r.z;
+// z in double or (single-precision preconditioner) in single precision
 hipError_t launch_cg_update_p(hipStream_t s, int64_t n, Scalars *sc, const double *z, double *p,
+                              int first, const int *skip = nullptr);
+hipError_t launch_cg_update_p(hipStream_t s, int64_t n, Scalars *sc, const float *z, double *p,
                               int first, const int *skip = nullptr);
 // Chebyshev first step from x = 0: d = r dinv / theta; x = d; res = r
 hipError_t launch_cheb_first(hipStream_t s, int64_t n, const double *r, const double *dinv,
@@ -209,16 +212,20 @@ hipError_t launch_cheb_first(hipStream_t s, int64_t n, const float *r, const flo
                              float inv_theta, float *d, float *x, float *res, const int *skip = nullptr);
 hipError_t launch_cheb_start(hipStream_t s, int64_t n, const float *res, const float *dinv,
                              float inv_theta, float *d, float *x, const int *skip = nullptr);
-// out = (float) in
+// out = (float) in, and out = (double) in
 hipError_t launch_convert(hipStream_t s, int64_t n, const double *in, float *out,
+                          const int *skip = nullptr);
+hipError_t launch_convert(hipStream_t s, int64_t n, const float *in, double *out,
                           const int *skip = nullptr);
 // u = sum_k alpha_k v_k, 1 <= nv <= 4
 hipError_t launch_combine(hipStream_t s, int64_t n, int nv, const double *const *v, const double *alpha, double *u);
 // u_prev <- u and u <- 2 u - u_prev (previous u_prev)
 hipError_t launch_extrapolate(hipStream_t s, int64_t n, double *u, double *u_prev);
-// z = (double) x; fin.out[0] = r.z_new, fin.out[1] = r.z_old (FIN_RZ_FLEX)
-hipError_t launch_widen_dot(hipStream_t s, int64_t n, const float *x, const double *r, double *z,
-                            const Reducer &red, const Fin &fin, const int *skip = nullptr);
+// z_new = x (+ res dinv inv_theta when res is given); fin.out[0] = r.z_new,
+// fin.out[1] = r.z_old with z_old the previous content of z; z = z_new (FIN_RZ_FLEX)
+hipError_t launch_flex_dot(hipStream_t s, int64_t n, const float *res, const float *dinv, float inv_theta,
+                           const float *x, const double *r, float *z, const Reducer &red, const Fin &fin,
+                           const int *skip = nullptr);
 
 // multigrid transfers
 hipError_t launch_restrict(hipStream_t s, Grid gf, Grid gc, const double *rf, const uint8_t *fixc,

@@ -152,18 +152,28 @@ hipError_t launch_jacobi(hipStream_t s, int64_t n, const double *r, const double
   return e != hipSuccess ? e : launch_finalize(s, red, (int)nb, 1, fin, skip);
 }
 
-__global__ void cg_update_p_kernel(int64_t n, const Scalars *sc, const double *z, double *p,
-                                   int first, const int *skip) {
+// p = z + beta p; z in double, or in single precision (the output of a
+// single-precision preconditioner, widened exactly)
+template <typename Z>
+__global__ void cg_update_p_kernel(int64_t n, const Scalars *sc, const Z *z, double *p, int first,
+                                   const int *skip) {
   if (skipped(skip)) return;
   const double beta = first ? 0.0 : sc->beta;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x)
-    p[i] = first ? z[i] : fma(beta, p[i], z[i]);
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const double zi = (double)z[i];
+    p[i] = first ? zi : fma(beta, p[i], zi);
+  }
 }
 
 hipError_t launch_cg_update_p(hipStream_t s, int64_t n, Scalars *sc, const double *z, double *p,
                               int first, const int *skip) {
-  cg_update_p_kernel<<<nblocks(n, 4), kBs, 0, s>>>(n, sc, z, p, first, skip);
+  cg_update_p_kernel<double><<<nblocks(n, 4), kBs, 0, s>>>(n, sc, z, p, first, skip);
+  return hipGetLastError();
+}
+hipError_t launch_cg_update_p(hipStream_t s, int64_t n, Scalars *sc, const float *z, double *p,
+                              int first, const int *skip) {
+  cg_update_p_kernel<float><<<nblocks(n, 4), kBs, 0, s>>>(n, sc, z, p, first, skip);
   return hipGetLastError();
 }
 
@@ -225,30 +235,40 @@ hipError_t launch_convert(hipStream_t s, int64_t n, const double *in, float *out
   convert_kernel<double, float><<<nblocks(n), kBs, 0, s>>>(n, in, out, skip);
   return hipGetLastError();
 }
+hipError_t launch_convert(hipStream_t s, int64_t n, const float *in, double *out, const int *skip) {
+  convert_kernel<float, double><<<nblocks(n), kBs, 0, s>>>(n, in, out, skip);
+  return hipGetLastError();
+}
 
-// z = (double) x32 together with r.z_new and r.z_old (z_old = the previous
-// content of z), for the flexible (Polak-Ribiere) CG update of a preconditioner
-// that is applied in single precision.
-__global__ void widen_dot_kernel(int64_t n, const float *x, const double *r, double *z,
-                                 double *partials, const int *skip) {
+// The end of a single-precision preconditioner inside flexible (Polak-Ribiere)
+// CG: the new z (kept in single precision; CG widens it exactly where it reads
+// it) replaces the previous one in z, and the pass forms r.z_new and r.z_old in
+// double.  With res and dinv given, the new z is first the finest level's last
+// Chebyshev update x + res dinv / theta (degree-1 smoothing), in the same
+// single-precision arithmetic as that update on its own.
+__global__ void flex_dot_kernel(int64_t n, const float *res, const float *dinv, float inv_theta,
+                                const float *x, const double *r, float *z, double *partials,
+                                const int *skip) {
   if (skipped(skip)) return;
   double tn = 0.0, to = 0.0;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x) {
-    const double zo = z[i];
-    const double zi = (double)x[i];
-    z[i] = zi;
-    tn = fma(r[i], zi, tn);
-    to = fma(r[i], zo, to);
+    float zf = x[i];
+    if (res) zf += res[i] * dinv[i] * inv_theta;
+    const double zo = (double)z[i], zn = (double)zf, ri = r[i];
+    z[i] = zf;
+    tn = fma(ri, zn, tn);
+    to = fma(ri, zo, to);
   }
   double v[2] = {tn, to};
   block_reduce_store<2, false>(v, partials, blockIdx.x);
 }
 
-hipError_t launch_widen_dot(hipStream_t s, int64_t n, const float *x, const double *r, double *z,
-                            const Reducer &red, const Fin &fin, const int *skip) {
+hipError_t launch_flex_dot(hipStream_t s, int64_t n, const float *res, const float *dinv, float inv_theta,
+                           const float *x, const double *r, float *z, const Reducer &red, const Fin &fin,
+                           const int *skip) {
   const unsigned nb = red_blocks(n, red);
-  widen_dot_kernel<<<nb, kBs, 0, s>>>(n, x, r, z, red.partials, skip);
+  flex_dot_kernel<<<nb, kBs, 0, s>>>(n, res, dinv, inv_theta, x, r, z, red.partials, skip);
   hipError_t e = hipGetLastError();
   return e != hipSuccess ? e : launch_finalize(s, red, (int)nb, 2, fin, skip);
 }

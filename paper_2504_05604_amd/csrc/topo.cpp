@@ -196,6 +196,7 @@ struct topo_ctx {
   KappaT<float> kap32{};
   // CG vectors (level-0 b / x double as the V-cycle's rhs / result)
   double *u = nullptr, *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr;
+  float *z32 = nullptr;      // z of the single-precision multigrid preconditioner
   // SIMP work
   double *xphys = nullptr, *ce = nullptr, *dc = nullptr, *dcf = nullptr, *oc_a = nullptr,
          *tmp = nullptr, *xnew = nullptr;
@@ -504,6 +505,10 @@ extern "C" topo_status topo_setup(const topo_problem *P, const topo_opts *O, voi
   TOPO_ALLOC(ctx->nn_scale, 1);
   TOPO_HIP(hipMemsetAsync(ctx->u, 0, ctx->ndof * sizeof(double), s));
   TOPO_HIP(hipMemsetAsync(ctx->z, 0, ctx->ndof * sizeof(double), s));
+  if (ctx->mixed) {
+    TOPO_ALLOC(ctx->z32, ctx->ndof);
+    TOPO_HIP(hipMemsetAsync(ctx->z32, 0, ctx->ndof * sizeof(float), s));
+  }
   TOPO_HIP(hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
   ctx->lv[0].b = ctx->r;
   ctx->lv[0].x = ctx->z;
@@ -902,11 +907,21 @@ static topo_status pre_smooth(topo_ctx *ctx, Level &L, const int *skip) {
   return TOPO_OK;
 }
 
+// Where the finest level of a single-precision V-cycle hands its result to
+// flexible CG: z (single precision, holding the previous z), r and the finalize.
+struct FlexOut {
+  float *z;
+  const double *r;
+  Fin fin;
+};
+
 // Post-smoothing from the current x (cheb_degree steps).  With dot_with set,
-// the last pass also reduces dot_with . x into fin.
+// the last pass also reduces dot_with . x into fin; with flex set (single
+// precision, finest level) the result goes to flex->z with the flexible-CG dot
+// products, fused into the last update when the degree is 1.
 template <typename T>
 static topo_status post_smooth(topo_ctx *ctx, Level &L, const int *skip, const T *dot_with,
-                               const Fin &fin) {
+                               const Fin &fin, const FlexOut *flex = nullptr) {
   hipStream_t s = ctx->stream;
   const int deg = level_degree(ctx, L);
   const Cheb ch(ctx->lam_max);
@@ -922,6 +937,13 @@ static topo_status post_smooth(topo_ctx *ctx, Level &L, const int *skip, const T
   a.skip = skip;
   TOPO_HIP(launch_ku(s, KU_RESID_START, a, kap, ctx->red, fin_sum(nullptr), L.shape));
   if (deg == 1) {
+    if constexpr (std::is_same<T, float>::value) {
+      if (flex) {
+        TOPO_HIP(launch_flex_dot(s, L.g.ndof(), B.res, B.dinv, (T)(1.0 / ch.theta), B.x, flex->r, flex->z,
+                                 ctx->red, flex->fin, skip));
+        return TOPO_OK;
+      }
+    }
     TOPO_HIP(launch_cheb_start(s, L.g.ndof(), B.res, B.dinv, (T)(1.0 / ch.theta), dnext, B.x, skip));
     if (dot_with) {
       if constexpr (std::is_same<T, double>::value)
@@ -943,6 +965,11 @@ static topo_status post_smooth(topo_ctx *ctx, Level &L, const int *skip, const T
     TOPO_HIP(launch_ku(s, k == 1 ? KU_CHEB_ADD : KU_CHEB, c, kap, ctx->red, fin, L.shape));
     std::swap(dcur, dnext);
     rho = rho_new;
+  }
+  if constexpr (std::is_same<T, float>::value) {
+    if (flex)
+      TOPO_HIP(launch_flex_dot(s, L.g.ndof(), nullptr, nullptr, 0.f, B.x, flex->r, flex->z, ctx->red, flex->fin,
+                               skip));
   }
   return TOPO_OK;
 }
@@ -978,7 +1005,8 @@ static topo_status vcycle_tail(topo_ctx *ctx, const int *skip) {
 }
 
 template <typename T>
-static topo_status vcycle(topo_ctx *ctx, size_t l, const int *skip, const Fin *dot_fin) {
+static topo_status vcycle(topo_ctx *ctx, size_t l, const int *skip, const Fin *dot_fin,
+                          const FlexOut *flex = nullptr) {
   hipStream_t s = ctx->stream;
   Level &L = ctx->lv[l];
   const LevelBufs<T> B = bufs<T>(L);
@@ -995,12 +1023,14 @@ static topo_status vcycle(topo_ctx *ctx, size_t l, const int *skip, const Fin *d
   st = vcycle<T>(ctx, l + 1, skip, nullptr);
   if (st != TOPO_OK) return st;
   TOPO_HIP(launch_prolong_add(s, L.g, C.g, BC.x, L.fixed, B.x, skip));
-  return post_smooth<T>(ctx, L, skip, dot_fin ? B.b : nullptr, dot_fin ? *dot_fin : fin_sum(nullptr));
+  return post_smooth<T>(ctx, L, skip, dot_fin ? B.b : nullptr, dot_fin ? *dot_fin : fin_sum(nullptr), flex);
 }
 
 // z = M r; the r.z finalize sets rz_new, beta = rz_new / rz and rz = rz_new.
-// In mixed precision the whole V-cycle runs in single precision between a
-// narrowing of r and a widening of z (which also forms r.z in double).
+// In mixed precision the whole V-cycle runs in single precision after a
+// narrowing of r, and its result stays in single precision in ctx->z32 (CG
+// widens it exactly where it reads it); its last pass forms r.z_new and r.z_old
+// in double for the flexible update.
 //
 // The learned preconditioner (kind TOPO_PRECOND_LEARNED) maps the residual
 // through the network (its rms comes from rr, formed by the caller) and feeds
@@ -1025,11 +1055,18 @@ static topo_status precondition(topo_ctx *ctx, int kind, const int *skip, bool h
   }
   if (!ctx->mixed) return vcycle<double>(ctx, 0, skip, &fin);
   if (!have_r32) TOPO_HIP(launch_convert(s, ctx->ndof, ctx->r, L0.f32.b, skip));
-  topo_status st = vcycle<float>(ctx, 0, skip, nullptr);
-  if (st != TOPO_OK) return st;
-  const Fin flex{FIN_RZ_FLEX, &ctx->sc->red[0], ctx->sc};
-  TOPO_HIP(launch_widen_dot(s, ctx->ndof, L0.f32.x, ctx->r, ctx->z, ctx->red, flex, skip));
-  return TOPO_OK;
+  const FlexOut flex{ctx->z32, ctx->r, Fin{FIN_RZ_FLEX, &ctx->sc->red[0], ctx->sc}};
+  return vcycle<float>(ctx, 0, skip, nullptr, &flex);
+}
+
+// whether the preconditioner of this kind leaves z in ctx->z32 (else ctx->z)
+static bool z_single(const topo_ctx *ctx, int kind) {
+  return ctx->mixed && kind == TOPO_PRECOND_MG && ctx->lv.size() > 1;
+}
+
+static hipError_t update_p(topo_ctx *ctx, int kind, int first, const int *skip) {
+  return z_single(ctx, kind) ? launch_cg_update_p(ctx->stream, ctx->ndof, ctx->sc, ctx->z32, ctx->p, first, skip)
+                             : launch_cg_update_p(ctx->stream, ctx->ndof, ctx->sc, ctx->z, ctx->p, first, skip);
 }
 
 static topo_status read_scalars(topo_ctx *ctx) {
@@ -1052,11 +1089,11 @@ static topo_status cg_body(topo_ctx *ctx, int kind) {
   const Fin check{FIN_CG_CHECK, &ctx->sc->rr, ctx->sc};
   // a single-precision multigrid preconditioner takes the residual in FP32, written
   // by the same pass
-  float *r32 = (ctx->mixed && kind == TOPO_PRECOND_MG && ctx->lv.size() > 1) ? L0.f32.b : nullptr;
+  float *r32 = z_single(ctx, kind) ? L0.f32.b : nullptr;
   TOPO_HIP(launch_cg_update_xr(s, ctx->ndof, ctx->sc, ctx->u, ctx->r, ctx->p, ctx->q, ctx->red, check, skip, r32));
   topo_status st = precondition(ctx, kind, skip, r32 != nullptr);
   if (st != TOPO_OK) return st;
-  TOPO_HIP(launch_cg_update_p(s, ctx->ndof, ctx->sc, ctx->z, ctx->p, 0, skip));
+  TOPO_HIP(update_p(ctx, kind, 0, skip));
   return TOPO_OK;
 }
 
@@ -1119,11 +1156,12 @@ static topo_status pcg_run(topo_ctx *ctx, int kind, int max_iters) {
   // iteration count 0; done at once if the initial guess already meets the tolerance
   TOPO_HIP(launch_cg_start(s, ctx->sc, rtol * rtol, max_iters));
   // the flexible update reads the previous z: start it from zero
-  if (kind == TOPO_PRECOND_LEARNED || ctx->mixed) TOPO_HIP(hipMemsetAsync(ctx->z, 0, n * sizeof(double), s));
+  if (z_single(ctx, kind)) TOPO_HIP(hipMemsetAsync(ctx->z32, 0, n * sizeof(float), s));
+  else if (kind == TOPO_PRECOND_LEARNED || ctx->mixed) TOPO_HIP(hipMemsetAsync(ctx->z, 0, n * sizeof(double), s));
   // first direction (skipped on the device when already converged)
   topo_status st = precondition(ctx, kind, &ctx->sc->cg_done);
   if (st != TOPO_OK) return st;
-  TOPO_HIP(launch_cg_update_p(s, n, ctx->sc, ctx->z, ctx->p, 1, &ctx->sc->cg_done));
+  TOPO_HIP(update_p(ctx, kind, 1, &ctx->sc->cg_done));
   st = read_scalars(ctx);
   if (st != TOPO_OK) return st;
   while (!ctx->h_sc->cg_done) {
@@ -1210,7 +1248,8 @@ extern "C" topo_status topo_apply_precond(topo_ctx *ctx, const double *d_xphys, 
   }
   st = precondition(ctx, kind, nullptr);
   if (st != TOPO_OK) return st;
-  TOPO_HIP(hipMemcpyAsync(d_z, ctx->z, ctx->ndof * sizeof(double), hipMemcpyDeviceToDevice, s));
+  if (z_single(ctx, kind)) TOPO_HIP(launch_convert(s, ctx->ndof, ctx->z32, d_z));
+  else TOPO_HIP(hipMemcpyAsync(d_z, ctx->z, ctx->ndof * sizeof(double), hipMemcpyDeviceToDevice, s));
   return TOPO_OK;
 }
 
