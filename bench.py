@@ -349,8 +349,9 @@ def main():
     ap.add_argument("--ku-kernel", choices=["auto", "node", "element"], default="auto",
                     help="K.u kernel: node columns or element columns in the sum/difference basis")
     ap.add_argument("--ku-shape", type=int, default=-1, help="one K.u launch shape for every level (-1: by grid size)")
-    ap.add_argument("--coarse-refresh", type=int, default=1,
-                    help="recompute the coarsest level's dense inverse every this many SIMP iterations")
+    ap.add_argument("--coarse-refresh", type=int, default=2,
+                    help="recompute the coarsest level's dense inverse every this many SIMP iterations "
+                         "(in between the previous one, still SPD, preconditions)")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-vs-multigrid leg")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-problems leg")
     ap.add_argument("--no-paper", action="store_true", help="skip the paper's 32x16x16 workload")
