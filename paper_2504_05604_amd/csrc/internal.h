@@ -129,7 +129,7 @@ enum KuEpi {
   KU_CHEB_ADD = 6,     // as KU_CHEB with x += u + dout (u = the pending step)  [reduce dot_with.x]
   KU_RESUPD = 7,       // res -= Au
   KU_RESID_START = 8,  // res = b - Au; dout = res dinv s0 (x not updated: the next
-                       // KU_CHEB_ADD adds dout)
+                       // KU_CHEB_ADD adds dout; dout null: not stored)
 };
 template <typename T>
 struct KuArgsT {

@@ -222,7 +222,7 @@ __global__ __launch_bounds__(256) void ku_mfma_kernel(KuArgsT<float> a, const fl
           } else if constexpr (EPI == KU_RESID_START) {
             const float r = a.b[dof] - Ac;
             a.res[dof] = r;
-            a.dout[dof] = r * a.dinv[dof] * a.s0;
+            if (a.dout) a.dout[dof] = r * a.dinv[dof] * a.s0;
           }
         }
       }

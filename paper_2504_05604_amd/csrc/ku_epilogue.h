@@ -45,7 +45,10 @@ __device__ __forceinline__ void ku_epi_load(const KuArgsT<T> &a, int64_t n, cons
     const int64_t dof = 3 * n + c;
     if constexpr (kB) in.b[c] = a.b[dof];
     if constexpr (kR) in.r[c] = a.res[dof];
-    if constexpr (kD) in.d[c] = dinv[dof];
+    if constexpr (kD) {
+      // the residual start reads dinv only for the direction it stores
+      if (EPI != KU_RESID_START || a.dout) in.d[c] = dinv[dof];
+    }
     if constexpr (kX) in.x[c] = a.x[dof];
   }
   if constexpr (kX) {
@@ -99,10 +102,10 @@ __device__ __forceinline__ void ku_epi_finish(const KuArgsT<T> &a, int64_t n, co
       if (a.dot_with) dotv = fma((double)in.w[c], (double)xn, dotv);
     } else if constexpr (EPI == KU_RESUPD) {
       a.res[dof] = in.r[c] - Ac;
-    } else if constexpr (EPI == KU_RESID_START) {  // res = b - A x; dout = res dinv s0
+    } else if constexpr (EPI == KU_RESID_START) {  // res = b - A x; dout = res dinv s0 (unless null)
       const T r = in.b[c] - Ac;
       a.res[dof] = r;
-      a.dout[dof] = r * in.d[c] * a.s0;
+      if (a.dout) a.dout[dof] = r * in.d[c] * a.s0;
     }
   }
 }

@@ -935,6 +935,10 @@ static topo_status post_smooth(topo_ctx *ctx, Level &L, const int *skip, const T
   a.dout = dcur;
   a.s0 = (T)(1.0 / ch.theta);
   a.skip = skip;
+  // degree 1 into flex_dot: it forms the direction from res itself
+  bool fused_last = false;
+  if constexpr (std::is_same<T, float>::value) fused_last = deg == 1 && flex;
+  if (fused_last) a.dout = nullptr;
   TOPO_HIP(launch_ku(s, KU_RESID_START, a, kap, ctx->red, fin_sum(nullptr), L.shape));
   if (deg == 1) {
     if constexpr (std::is_same<T, float>::value) {

@@ -1,8 +1,8 @@
 """Single-precision multigrid preconditioner inside FP64 flexible CG: the
 solution meets the same FP64 residual tolerance, and the SIMP trajectory stays
 within stated bounds of the FP64 one.  Variants: FP32 on the vector units (both
-K.u kernels), FP32 on the matrix cores (mfma_smoothing), BF16 operands on the
-matrix cores."""
+K.u kernels, the element-column one also with its LDS-staged shapes), FP32 on
+the matrix cores (mfma_smoothing), BF16 operands on the matrix cores."""
 
 import numpy as np
 import pytest
@@ -20,6 +20,10 @@ KE = element_stiffness(0.3)
 
 VARIANTS = {
     "fp32": dict(precision=topo.PREC_FP32),
+    # every level and the CG product on the element-column shapes whose node
+    # planes are staged through LDS (the finest-level default on large grids)
+    "fp32_staged": dict(precision=topo.PREC_FP32, ku_shape=13),
+    "fp32_staged16": dict(precision=topo.PREC_FP32, ku_shape=14),
     "fp32_node": dict(precision=topo.PREC_FP32, ku_kernel=topo.KU_NODE),
     "fp32_mfma": dict(precision=topo.PREC_FP32, mfma_smoothing=1),
     "bf16": dict(precision=topo.PREC_BF16),
