@@ -108,11 +108,14 @@ __global__ void prolong_add_kernel(Grid gf, Grid gc, const T *__restrict__ ec,
         s2 = fma(inc, v[2], s2);
       }
     }
+  // the node's x read with the other loads and written back whole (a fixed dof
+  // keeps its value): no load-wait-store round trip per component at the end
   const uint8_t f = fixf[n];
   T *__restrict__ xn = xf + 3 * (int64_t)n;
-  if (!(f & 1)) xn[0] = fma(w, s0, xn[0]);
-  if (!(f & 2)) xn[1] = fma(w, s1, xn[1]);
-  if (!(f & 4)) xn[2] = fma(w, s2, xn[2]);
+  const T x0 = xn[0], x1 = xn[1], x2 = xn[2];
+  xn[0] = (f & 1) ? x0 : fma(w, s0, x0);
+  xn[1] = (f & 2) ? x1 : fma(w, s1, x1);
+  xn[2] = (f & 4) ? x2 : fma(w, s2, x2);
 }
 
 hipError_t launch_prolong_add(hipStream_t s, Grid gf, Grid gc, const double *ec,
