@@ -227,10 +227,11 @@ __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(PF ? 1 
 // tile once, (TX+1)(TY+1) nodes spread evenly over its threads instead of four
 // corners per thread, into registers two planes ahead of use, and hands it to
 // the element columns through LDS (double-buffered; the barrier that publishes
-// a plane is the one the corner exchange already needs).  A plane's loads thus
-// stay in flight through one layer's arithmetic and barrier, with a third of the
-// load instructions.  Same arithmetic in the same order: bit-identical to the
-// other shapes.
+// a plane is the one the corner exchange already needs); the moduli are loaded
+// two layers and the epilogue inputs one layer ahead as well.  A plane's loads
+// thus stay in flight through one layer's arithmetic and barrier, with a third
+// of the load instructions.  Same arithmetic in the same order: bit-identical to
+// the other shapes.
 template <int EPI, int KZ, int TX, int TY, typename T>
 __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(3))) void ku_hada_lds_kernel(
     KuArgsT<T> a, HadaW<T> hw, int tiles_x, int tiles_xy, double *partials) {
