@@ -326,6 +326,9 @@ def main():
     ap.add_argument("--precond", choices=["mg", "jacobi"], default="mg")
     ap.add_argument("--cheb-degree", type=int, default=1, help="Chebyshev degree on the finest level")
     ap.add_argument("--cheb-degree-coarse", type=int, default=4, help="Chebyshev degree below the finest level (0: the same)")
+    ap.add_argument("--cheb-degree-levels", default="1,2,4,6",
+                    help="per-level Chebyshev degrees, finest first, replacing the two above where given "
+                         "(measured on the 5-level 160x80x80 hierarchy; '' for none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--ku-reps", type=int, default=100)
@@ -374,8 +377,9 @@ def main():
     import synth
 
     p = synth.config_large()
+    level_degs = [int(v) for v in args.cheb_degree_levels.split(",") if v.strip()]
     opts = topo.default_opts(rtol=1e-8, max_iters=2000, cheb_degree=args.cheb_degree, warm_start=args.warm,
-                             cheb_degree_coarse=args.cheb_degree_coarse,
+                             cheb_degree_coarse=args.cheb_degree_coarse, cheb_degree_level=level_degs,
                              mg_max_coarse_dof=args.coarse_dof, check_every=args.check_every,
                              use_graphs=0 if args.no_graphs else 1, coarse_tail_nodes=args.tail_nodes,
                              precision={"fp64": topo.PREC_FP64, "fp32": topo.PREC_FP32,
@@ -403,10 +407,14 @@ def main():
     pcg = np.array([s["pcg_iters"] for s in stats], dtype=float)
     solve_ms = np.array([s["ms_solve"] for s in stats])
     deg = args.cheb_degree
-    # fine-grid K.u applications per CG iteration: the product itself plus 2*deg on
-    # the finest level of the V-cycle, each coarser level 1/8 of its finer one
+    # fine-grid K.u applications per CG iteration: the product itself plus 2 deg_l
+    # on each smoothed level l of the V-cycle, level l costing 8^-l of the finest
     degc = args.cheb_degree_coarse or deg
-    ku_per_cg = 1.0 + (2.0 * deg + 2.0 * degc / 7.0 if args.precond == "mg" else 0.0)
+    ku_per_cg = 1.0
+    if args.precond == "mg":
+        for lvl in range(ctx.mg_levels - 1):
+            d = level_degs[lvl] if lvl < len(level_degs) and level_degs[lvl] > 0 else (deg if lvl == 0 else degc)
+            ku_per_cg += 2.0 * d / 8.0 ** lvl
     ku_equiv = float(pcg.mean() * ku_per_cg + 1.0)
 
     ku_ms = ctx.time_operator(args.ku_reps)
@@ -435,7 +443,8 @@ def main():
         "config": {
             "workload": "cantilever-160x80x80 (3,168,963 DOF), volfrac 0.2, rmin 3.0, density filter",
             "nel": p.nel, "ndof": p.ndof, "precond": args.precond, "mg_levels": ctx.mg_levels,
-            "cheb_degree": deg, "cheb_degree_coarse": args.cheb_degree_coarse or deg, "rtol": 1e-8, "warm_start": ["zero", "last", "extrapolated", "projected"][args.warm],
+            "cheb_degree": deg, "cheb_degree_coarse": args.cheb_degree_coarse or deg,
+            "cheb_degree_level": level_degs, "rtol": 1e-8, "warm_start": ["zero", "last", "extrapolated", "projected"][args.warm],
             "coarse_dof_cap": args.coarse_dof,
             "check_every": args.check_every, "graphs": not args.no_graphs,
             "coarse_tail_nodes": args.tail_nodes, "autotune": bool(args.autotune),

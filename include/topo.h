@@ -141,6 +141,10 @@ typedef struct {
                                  between the last one (an SPD matrix, so the V-cycle stays
                                  a valid preconditioner) serves; other entry points always
                                  recompute it                                            */
+  int32_t cheb_degree_level[8]; /* per multigrid level, finest first: a Chebyshev degree
+                                 in [1, 16] that replaces cheb_degree / cheb_degree_coarse
+                                 on that level; 0 = not set (the level above the exact
+                                 coarsest solve never smooths more than 16 steps)      */
 } topo_opts;
 
 typedef struct {
@@ -167,7 +171,8 @@ typedef struct {
  * Chebyshev degree 1 on the finest level and 4 below (cheb_degree_coarse),
  * rtol 1e-8, max_iters 1000, projected warm start (3), oc_tol 1e-12,
  * check_every 4, use_graphs 1, nn_max_iters 200, autotune 0, coarse_tail_nodes 0,
- * mfma_smoothing 0, ku_kernel TOPO_KU_AUTO, ku_shape -1, coarse_refresh 1. */
+ * mfma_smoothing 0, ku_kernel TOPO_KU_AUTO, ku_shape -1, coarse_refresh 1,
+ * cheb_degree_level all 0. */
 void topo_default_opts(topo_opts *opts);
 
 /* Validates the problem, copies its arrays to the device, builds the element

@@ -101,9 +101,12 @@ class Level:
 class VCycle:
     """Symmetric V-cycle M ~ A^-1 of the reduced operator with identity rows."""
 
-    def __init__(self, p, E, KE, degree=2, max_coarse_dof=800, levels=None, coarse_degree=None):
+    def __init__(self, p, E, KE, degree=2, max_coarse_dof=800, levels=None, coarse_degree=None,
+                 level_degrees=None):
         """degree: Chebyshev steps per pre/post smoothing on the finest level;
-        coarse_degree: the same on the coarser levels (None: degree)."""
+        coarse_degree: the same on the coarser levels (None: degree);
+        level_degrees: per level, finest first, a degree that replaces those two
+        where it is given and positive."""
         dims = hierarchy(p.nelx, p.nely, p.nelz, max_coarse_dof)
         if levels is not None:
             dims = dims[:levels]
@@ -113,6 +116,7 @@ class VCycle:
         self.lam_max = float(np.linalg.eigvalsh(KE / np.sqrt(np.outer(d, d))).max())
         self.degree = degree
         self.coarse_degree = degree if coarse_degree is None else coarse_degree
+        self.level_degrees = list(level_degrees or [])
         self.levels, self.P = [], []
         Ecur, fcur = E, fixed
         for l, dl in enumerate(dims):
@@ -149,6 +153,8 @@ class VCycle:
         if l == len(self.levels) - 1:
             return sla.cho_solve(self.coarse, r)
         deg = self.degree if l == 0 else self.coarse_degree
+        if l < len(self.level_degrees) and self.level_degrees[l] > 0:
+            deg = self.level_degrees[l]
         x = self.smooth(lv, r, np.zeros_like(r), deg)
         res = r - lv.A @ x
         ec = self.apply(self.P[l].T @ res, l + 1)

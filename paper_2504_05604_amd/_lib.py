@@ -66,6 +66,7 @@ class Opts_C(C.Structure):
         ("check_every", C.c_int32), ("use_graphs", C.c_int32), ("nn_max_iters", C.c_int32),
         ("autotune", C.c_int32), ("coarse_tail_nodes", C.c_int32), ("mfma_smoothing", C.c_int32),
         ("ku_kernel", C.c_int32), ("ku_shape", C.c_int32), ("coarse_refresh", C.c_int32),
+        ("cheb_degree_level", C.c_int32 * 8),
     ]
 
 
@@ -170,6 +171,11 @@ def default_opts(**kw) -> Opts_C:
     for k, v in kw.items():
         if not hasattr(o, k):
             raise KeyError(f"unknown option {k}")
+        if k == "cheb_degree_level":  # per level, finest first; the rest 0 (not set)
+            v = list(v) + [0] * (8 - len(v))
+            if len(v) != 8:
+                raise ValueError("cheb_degree_level takes at most 8 levels")
+            v = (C.c_int32 * 8)(*v)
         setattr(o, k, v)
     return o
 

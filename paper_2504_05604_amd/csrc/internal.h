@@ -258,6 +258,7 @@ struct TailLevel {
   const T *dinv;           // inverse Jacobi diagonal (0 on fixed dofs)
   const uint8_t *fixed;    // per node, bit c = dof c fixed
   T *b, *x, *res, *d0, *d1;
+  int deg;                 // Chebyshev steps per smoothing on this level
 };
 constexpr int kTailMaxLevels = 8;
 constexpr int kTailMaxDeg = 17;

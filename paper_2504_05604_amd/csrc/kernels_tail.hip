@@ -112,8 +112,8 @@ __device__ void pre_smooth(const TailArgs<T> &a, const TailLevel<T> &L, T *scr) 
   }
   __syncthreads();
   T *dc = L.d0, *dn = L.d1;
-  for (int s = 1; s <= a.deg; ++s) {
-    const bool last = s == a.deg;
+  for (int s = 1; s <= L.deg; ++s) {
+    const bool last = s == L.deg;
     element_products(g, L.E, a.hw, dc, scr);
     __syncthreads();
     for (int n = threadIdx.x; n < nn; n += blockDim.x) {
@@ -164,13 +164,13 @@ __device__ void post_smooth(const TailArgs<T> &a, const TailLevel<T> &L, T *scr)
     }
   }
   __syncthreads();
-  if (a.deg == 1) {
+  if (L.deg == 1) {
     for (int d = threadIdx.x; d < 3 * nn; d += blockDim.x) L.x[d] += L.d0[d];
     __syncthreads();
     return;
   }
   T *dc = L.d0, *dn = L.d1;
-  for (int s = 1; s < a.deg; ++s) {
+  for (int s = 1; s < L.deg; ++s) {
     element_products(g, L.E, a.hw, dc, scr);
     __syncthreads();
     for (int n = threadIdx.x; n < nn; n += blockDim.x) {
@@ -283,6 +283,7 @@ __global__ __launch_bounds__(kTailThreads) void vcycle_tail_kernel(TailArgs<T> a
     d.d0 = d.res + nd;
     d.d1 = d.d0 + nd;
     d.fixed = reinterpret_cast<const uint8_t *>(d.d1 + nd);
+    d.deg = a.L[l].deg;
     return d;
   };
   // copy-in as one flat loop over every (level, array) segment, so all the

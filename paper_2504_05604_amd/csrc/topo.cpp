@@ -330,6 +330,9 @@ static topo_status validate(const topo_problem *P, const topo_opts *O) {
   if (O->coarse_tail_nodes < 0) return set_error("coarse_tail_nodes must be >= 0"), TOPO_EINVAL;
   if (O->warm_start < 0 || O->warm_start > 3) return set_error("warm_start must be 0, 1, 2 or 3"), TOPO_EINVAL;
   if (O->coarse_refresh < 1) return set_error("coarse_refresh must be >= 1"), TOPO_EINVAL;
+  for (int l = 0; l < 8; ++l)
+    if (O->cheb_degree_level[l] < 0 || O->cheb_degree_level[l] > 16)
+      return set_error("cheb_degree_level[%d] must lie in [0, 16]", l), TOPO_EINVAL;
   if (O->ku_kernel != TOPO_KU_AUTO && O->ku_kernel != TOPO_KU_NODE && O->ku_kernel != TOPO_KU_ELEMENT)
     return set_error("unknown ku_kernel %d", O->ku_kernel), TOPO_EINVAL;
   if (!(O->ku_shape == -1 || (O->ku_shape >= 0 && O->ku_shape < kKuShapes) ||
@@ -838,12 +841,13 @@ struct Cheb {
   }
 };
 
-// Chebyshev degree of a level: cheb_degree on the finest, cheb_degree_coarse
-// (when set) below it
-static int level_degree(const topo_ctx *ctx, const Level &L) {
-  const bool finest = &L == &ctx->lv[0];
-  return (finest || ctx->opts.cheb_degree_coarse == 0) ? ctx->opts.cheb_degree : ctx->opts.cheb_degree_coarse;
+// Chebyshev degree of level l: cheb_degree_level[l] when set, else cheb_degree
+// on the finest and cheb_degree_coarse (when set) below it
+static int level_degree(const topo_ctx *ctx, size_t l) {
+  if (l < 8 && ctx->opts.cheb_degree_level[l] > 0) return ctx->opts.cheb_degree_level[l];
+  return (l == 0 || ctx->opts.cheb_degree_coarse == 0) ? ctx->opts.cheb_degree : ctx->opts.cheb_degree_coarse;
 }
+static int level_degree(const topo_ctx *ctx, const Level &L) { return level_degree(ctx, (size_t)(&L - &ctx->lv[0])); }
 
 // Pre-smoothing from x = 0 (cheb_degree steps); on exit x and res = b - A x.
 // On small grids the first step's operand d0 = b dinv / theta is formed inside
@@ -988,12 +992,14 @@ static topo_status vcycle_tail(topo_ctx *ctx, const int *skip) {
   for (int q = 0; q < a.nlev; ++q) {
     Level &L = ctx->lv[ctx->tail_start + q];
     const LevelBufs<T> B = bufs<T>(L);
-    a.L[q] = TailLevel<T>{L.g, B.E, B.dinv, L.fixed, B.b, B.x, B.res, B.d0, B.d1};
+    a.L[q] = TailLevel<T>{L.g, B.E, B.dinv, L.fixed, B.b, B.x, B.res, B.d0, B.d1,
+                          level_degree(ctx, ctx->tail_start + q)};
   }
   a.Ainv = ctx->Ainv;
   a.ncoarse = ctx->ncoarse;
   a.hw = hada_work(kappa_of<T>(ctx));
-  a.deg = ctx->opts.cheb_degree_coarse ? ctx->opts.cheb_degree_coarse : ctx->opts.cheb_degree;  // never the finest level
+  a.deg = 1;  // the most steps of any tail level (never the finest level): coefficients up to it
+  for (int q = 0; q < a.nlev; ++q) a.deg = std::max(a.deg, a.L[q].deg);
   const Cheb ch(ctx->lam_max);
   a.s0 = (T)(1.0 / ch.theta);
   double rho = 1.0 / ch.sigma;

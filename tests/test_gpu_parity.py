@@ -83,6 +83,9 @@ MG_VARIANTS = {
     "mg140": (140, 2, 2, 0), "mg400": (400, 2, 2, 0), "mg400deg3": (400, 3, 3, 0),
     "mg140deg1": (140, 1, 1, 0), "mg140_tail1024": (140, 2, 2, 1024), "mg140_tail4000": (140, 2, 2, 4000),
     "mg1500": (1500, 2, 2, 0), "mg1500d1c4": (1500, 1, 4, 0), "mg140d1c4_tail1024": (140, 1, 4, 1024),
+    # per-level degrees, finest first (the levels not listed take the two above)
+    "mg140lev": (140, 1, 4, 0, [1, 2, 3, 6]), "mg140lev_tail1024": (140, 1, 4, 1024, [1, 2, 3, 6]),
+    "mg1500lev": (1500, 1, 4, 0, [1, 2, 3, 6]),
 }
 
 
@@ -98,11 +101,13 @@ def test_preconditioner_matches_oracle(case, precond, kernel):
     r = synth.random_vector(6, p.ndof)
     r[fixed_mask(p)] = 0.0
     if precond.startswith("mg"):
-        coarse, deg, degc, tail = MG_VARIANTS[precond]
-        V = mg.VCycle(p, E, KE, degree=deg, coarse_degree=degc, max_coarse_dof=coarse)
+        coarse, deg, degc, tail = MG_VARIANTS[precond][:4]
+        lev = MG_VARIANTS[precond][4] if len(MG_VARIANTS[precond]) > 4 else []
+        V = mg.VCycle(p, E, KE, degree=deg, coarse_degree=degc, max_coarse_dof=coarse, level_degrees=lev)
         ref = V.apply(r)
         opts = topo.default_opts(precond=topo.PRECOND_MG, mg_max_coarse_dof=coarse, cheb_degree=deg,
-                                 cheb_degree_coarse=degc, coarse_tail_nodes=tail, ku_kernel=KERNELS[kernel])
+                                 cheb_degree_coarse=degc, coarse_tail_nodes=tail, ku_kernel=KERNELS[kernel],
+                                 cheb_degree_level=lev)
     else:
         K = mg.with_identity_rows(fem.assemble(E, KE, fem.element_dofs(p.nelx, p.nely, p.nelz), p.ndof),
                                   fixed_mask(p))

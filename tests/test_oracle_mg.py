@@ -50,11 +50,14 @@ def setup_vcycle(seed=0, degrees=(2, None)):
     p = synth.cantilever(12, 6, 6, volfrac=0.3, rmin=1.5, n_iter=1)
     x = synth.random_density(seed, p.nel, 0.0, 1.0)
     E = fem.simp_modulus(x, p.E0, p.Emin, p.penal)
-    return p, E, mg.VCycle(p, E, KE, degree=degrees[0], coarse_degree=degrees[1], max_coarse_dof=300)
+    per_level = degrees[2] if len(degrees) > 2 else None
+    return p, E, mg.VCycle(p, E, KE, degree=degrees[0], coarse_degree=degrees[1], max_coarse_dof=300,
+                           level_degrees=per_level)
 
 
-# (finest-level degree, coarser-level degree); None: the same on every level
-DEGREES = [(2, None), (1, 4), (3, 1)]
+# (finest-level degree, coarser-level degree[, per-level degrees]); None: the
+# same on every level
+DEGREES = [(2, None), (1, 4), (3, 1), (1, 4, [2, 6])]
 
 
 @pytest.mark.parametrize("degrees", DEGREES)
