@@ -290,9 +290,11 @@ def batched(topo, synth, args):
     import torch
 
     ps = synth.batch_problems(args.batch_size)
-    opts = topo.default_opts(precision=topo.PREC_FP32, autotune=1)
+    # per-level smoother degrees (finest first; deeper levels take the coarse
+    # degree 4): measured on this batch, 143 against 149 ms per batch iteration
+    opts = topo.default_opts(precision=topo.PREC_FP32, autotune=1, cheb_degree_level=[1, 2, 4])
     out = {"workload": f"{len(ps)} random cantilevers, seeds 0-{len(ps) - 1}, grids nelx=8*U{{3..12}} x nelx/2 x nelx/2",
-           "precond": "mg, fp32 preconditioner", "autotune": True}
+           "precond": "mg, fp32 preconditioner, Chebyshev degrees 1, 2, 4 from the finest level down", "autotune": True}
     for label, threads in (("concurrent", 8), ("sequential", 1)):
         t0 = time.perf_counter()
         b = topo.Batch(ps, opts, n_threads=threads)
