@@ -24,6 +24,8 @@ VARIANTS = {
     # planes are staged through LDS (the finest-level default on large grids)
     "fp32_staged": dict(precision=topo.PREC_FP32, ku_shape=13),
     "fp32_staged16": dict(precision=topo.PREC_FP32, ku_shape=14),
+    # per-level smoother degrees, finest first (the benchmark's setting)
+    "fp32_levels": dict(precision=topo.PREC_FP32, cheb_degree_level=[1, 2, 4, 6]),
     "fp32_node": dict(precision=topo.PREC_FP32, ku_kernel=topo.KU_NODE),
     "fp32_mfma": dict(precision=topo.PREC_FP32, mfma_smoothing=1),
     "bf16": dict(precision=topo.PREC_BF16),
@@ -77,7 +79,8 @@ def test_low_precision_preconditioner_matches_oracle(case, variant, cap):
     r = synth.random_vector(6, p.ndof)
     r[fm] = 0.0
     # the default smoother degrees: one step on the finest level, four below
-    ref = mg.VCycle(p, E, KE, degree=1, coarse_degree=4, max_coarse_dof=cap).apply(r)
+    ref = mg.VCycle(p, E, KE, degree=1, coarse_degree=4, max_coarse_dof=cap,
+                    level_degrees=VARIANTS[variant].get("cheb_degree_level")).apply(r)
     with topo.Context(p, topo.default_opts(mg_max_coarse_dof=cap, cheb_degree=1, cheb_degree_coarse=4,
                                            **VARIANTS[variant])) as ctx:
         z = torch.empty(p.ndof, dtype=torch.float64, device="cuda")
