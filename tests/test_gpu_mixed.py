@@ -92,6 +92,32 @@ def test_low_precision_preconditioner_matches_oracle(case, variant, cap):
     assert err <= (3e-2 if variant == "bf16" else 1e-4)
 
 
+@pytest.mark.parametrize("variant", ["fp32", "fp32_levels", "bf16"])
+def test_low_precision_preconditioner_on_five_levels_matches_oracle(variant):
+    """33x17x17 at a 140-dof cap: 5 levels, so the per-level degrees 1, 2, 4, 6
+    each smooth a level of their own."""
+    p = synth.cantilever(33, 17, 17, volfrac=0.3, rmin=1.5, n_iter=1)
+    x = synth.random_density(5, p.nel, 0.0, 1.0)
+    E = fem.simp_modulus(x, p.E0, p.Emin, p.penal)
+    fm = np.zeros(p.ndof, bool)
+    fm[p.fixed_dofs] = True
+    r = synth.random_vector(6, p.ndof)
+    r[fm] = 0.0
+    lev = VARIANTS[variant].get("cheb_degree_level")
+    V = mg.VCycle(p, E, KE, degree=1, coarse_degree=4, max_coarse_dof=140, level_degrees=lev)
+    assert len(V.levels) == 5
+    ref = V.apply(r)
+    with topo.Context(p, topo.default_opts(mg_max_coarse_dof=140, cheb_degree=1, cheb_degree_coarse=4,
+                                           **VARIANTS[variant])) as ctx:
+        z = torch.empty(p.ndof, dtype=torch.float64, device="cuda")
+        ctx.apply_precond(torch.from_numpy(x).cuda(), torch.from_numpy(r).cuda(), z)
+        torch.cuda.synchronize()
+        got = z.cpu().numpy()
+    err = np.abs(got - ref).max() / np.abs(ref).max()
+    print(variant, "5 levels, max rel err", err)
+    assert err <= (3e-2 if variant == "bf16" else 1e-4)
+
+
 @pytest.mark.parametrize("variant", list(VARIANTS))
 def test_low_precision_preconditioner_trajectory_close_to_fp64(variant):
     """The preconditioner does not change the solution beyond the solve tolerance

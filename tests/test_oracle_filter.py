@@ -86,3 +86,14 @@ def test_sampled_rows_equal_matrix_rows():
         ref = np.zeros(240)
         ref[idx] = w
         np.testing.assert_allclose(row, ref, atol=0)
+
+
+def test_sensitivity_filter_hand_worked_case():
+    """Non-uniform field with one element below gamma, against the values worked
+    by hand in tests/golden/filter_sensitivity_3x1x1.txt.  Fails if the x
+    weighting, the max(gamma, x) guard or the Hs normalisation is dropped."""
+    rows = np.loadtxt("tests/golden/filter_sensitivity_3x1x1.txt")
+    x, dc, hs, want = rows[:, 1], rows[:, 2], rows[:, 3], rows[:, 4]
+    F = filt.Filter(3, 1, 1, 1.5)
+    np.testing.assert_allclose(F.Hs, hs, rtol=1e-15)
+    np.testing.assert_allclose(F.sensitivity(x, dc), want, rtol=1e-14)

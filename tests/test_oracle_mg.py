@@ -95,3 +95,58 @@ def test_coarse_fixed_inherits_clamped_face(n):
     nodes = np.arange(fc.size // 3)
     on_face = nodes % (4 * n + 1) == 0
     assert np.all(fc.reshape(-1, 3)[on_face]) and not np.any(fc.reshape(-1, 3)[~on_face])
+
+
+@pytest.mark.parametrize("k", [1, 2, 3, 4, 5, 6])
+def test_chebyshev_smoother_error_is_the_scaled_chebyshev_polynomial(k):
+    """With a diagonal operator D^-1 A = diag(mu), k Chebyshev steps from x = 0
+    leave the error e_k = T_k((theta - mu)/delta) / T_k(theta/delta) e_0
+    (Chebyshev semi-iteration on [lo, hi], theta/delta the interval's centre and
+    half-width).  T_k comes from numpy's Chebyshev basis, not from the smoother's
+    three-term recurrence."""
+    from types import SimpleNamespace
+
+    from numpy.polynomial import chebyshev as C
+
+    _, _, V = setup_vcycle()
+    hi = V.lam_max
+    lo = hi / mg.CHEB_RATIO
+    theta, delta = 0.5 * (hi + lo), 0.5 * (hi - lo)
+    rng = np.random.default_rng(k)
+    mu = np.concatenate([[lo, hi, theta, 0.5 * lo], rng.uniform(1e-3 * hi, hi, 60)])
+    d = rng.uniform(0.5, 4.0, mu.size)
+    lv = SimpleNamespace(A=sp.diags(mu * d), diag=d)
+    b = rng.standard_normal(mu.size)
+    e0 = b / (mu * d)
+    Tk = C.Chebyshev.basis(k)
+    want = Tk((theta - mu) / delta) / Tk(theta / delta) * e0
+    got = e0 - V.smooth(lv, b, np.zeros_like(b), k)
+    np.testing.assert_allclose(got, want, rtol=0, atol=1e-14 * np.abs(e0).max())
+
+
+def test_per_level_degrees_reach_each_level():
+    """VCycle(level_degrees=[a, b]) on three levels is the V-cycle with degree a on
+    the finest level and b on the middle one, composed here by hand from smooth(),
+    the transfers and the coarsest Cholesky solve; it differs from [a, a]."""
+    import scipy.linalg as sla
+
+    p, _, _ = setup_vcycle()
+    E = fem.simp_modulus(synth.random_density(9, p.nel, 0.3, 1.0), p.E0, p.Emin, p.penal)
+    a, b = 1, 5
+    V = mg.VCycle(p, E, KE, degree=3, coarse_degree=3, max_coarse_dof=300, level_degrees=[a, b])
+    assert len(V.levels) == 3
+    L0, L1, _ = V.levels
+    r = synth.random_vector(4, p.ndof)
+    r[L0.fixed] = 0.0
+
+    x0 = V.smooth(L0, r, np.zeros_like(r), a)
+    r1 = V.P[0].T @ (r - L0.A @ x0)
+    x1 = V.smooth(L1, r1, np.zeros_like(r1), b)
+    x1 = x1 + V.P[1] @ sla.cho_solve(V.coarse, V.P[1].T @ (r1 - L1.A @ x1))
+    x1 = V.smooth(L1, r1, x1, b)
+    x0 = V.smooth(L0, r, x0 + V.P[0] @ x1, a)
+
+    got = V.apply(r)
+    np.testing.assert_allclose(got, x0, rtol=0, atol=1e-13 * np.abs(x0).max())
+    other = mg.VCycle(p, E, KE, degree=3, coarse_degree=3, max_coarse_dof=300, level_degrees=[a, a]).apply(r)
+    assert np.abs(other - got).max() > 1e-3 * np.abs(got).max()
