@@ -55,6 +55,13 @@ typedef enum {
 
 /* filter modes (Sensitivity Filtering section) */
 enum { TOPO_FILTER_DENSITY = 0, TOPO_FILTER_SENSITIVITY = 1 };
+/* volume target of the OC update (Optimality Criteria section; the paper does
+ * not say how obstacle elements count).  DESIGN: the design-element sum of the
+ * physical density equals volfrac * (number of design elements), passive
+ * elements outside both sides.  ALL: the sum over every element (fixed-solid
+ * elements count 1, fixed-void 0) equals volfrac * nel, i.e. the design-element
+ * sum equals volfrac * nel - (number of fixed-solid elements). */
+enum { TOPO_VOL_DESIGN = 0, TOPO_VOL_ALL = 1 };
 /* filter operations for topo_filter */
 enum {
   TOPO_FILTER_FWD = 0,  /* out = (H in)/Hs, passive elements reset to 0 (void) / 1 (solid) */
@@ -93,6 +100,7 @@ typedef struct {
   double move;                /* OC move limit, > 0                                  */
   double eta;                 /* OC damping exponent, > 0                            */
   int32_t filter;             /* TOPO_FILTER_DENSITY | TOPO_FILTER_SENSITIVITY       */
+  int32_t vol_mode;           /* TOPO_VOL_DESIGN (0) | TOPO_VOL_ALL (1)               */
   const int8_t *mask;         /* nel entries: 0 design, 1 void, 2 solid; NULL = all design */
   const int64_t *fixed_dofs;  /* n_fixed constrained dofs (homogeneous), any order   */
   int64_t n_fixed;
@@ -165,6 +173,9 @@ typedef struct {
   int32_t converged;
   double relres;
   double ms_total, ms_filter, ms_solve, ms_sens, ms_oc; /* phase times (hipEvents) */
+  int32_t fallbacks;   /* LEARNED: restarts of this iteration's solve on the multigrid
+                          preconditioner (a safeguard event, not an error)         */
+  int32_t learned_iters; /* LEARNED: CG iterations of this solve taken with the network */
 } topo_iter_stats;
 
 /* Fills *opts with defaults: FP64, MG, automatic depth (coarsest <= 1500 dofs),
@@ -180,8 +191,10 @@ void topo_default_opts(topo_opts *opts);
  * filter stencil and row sums (Sensitivity Filtering section), the multigrid
  * hierarchy and all workspaces.  hip_stream is a hipStream_t or NULL.
  * Errors: TOPO_EINVAL (sizes < 1, non-positive rmin/move/eta, volfrac outside
- * (0,1], Emin <= 0 or >= E0, mask codes outside {0,1,2}, fixed dofs out of
- * range, fewer than 6 fixed dofs, no design element, NULL f), TOPO_ENOMEM,
+ * (0,1], Emin <= 0 or >= E0, mask codes outside {0,1,2}, unknown vol_mode, a
+ * TOPO_VOL_ALL target not above zero (the fixed-solid elements alone exceed
+ * volfrac * nel), fixed dofs out of range, fewer than 6 fixed dofs, no design
+ * element, NULL f), TOPO_ENOMEM,
  * TOPO_EDEVICE.  On error *out is NULL. */
 topo_status topo_setup(const topo_problem *problem, const topo_opts *opts, void *hip_stream,
                        topo_ctx **out);
@@ -231,8 +244,9 @@ topo_status topo_filter(topo_ctx *ctx, int32_t op, const double *d_in, const dou
 /* OC update with move limits (Optimality Criteria section).  For design
  * elements x_new = clamp(x (max(0,-dc)/(lambda dv))^eta, max(0,x-move),
  * min(1,x+move)); passive elements keep x.  lambda is chosen so that the volume
- * measure sum_j dv_j x_new_j (over all elements) equals volfrac * (number of
- * design elements); dv is therefore the volume weight vector: H(1_D/Hs) for the
+ * measure sum_j dv_j x_new_j (over all elements) equals the problem's target
+ * (TOPO_VOL_DESIGN: volfrac * (number of design elements); TOPO_VOL_ALL:
+ * volfrac * nel - (number of fixed-solid elements)); dv is therefore the volume weight vector: H(1_D/Hs) for the
  * density filter (TOPO_FILTER_VOLW), 1 on design and 0 on passive elements for
  * the sensitivity filter.  The multiplier bracket is narrowed until its relative
  * width is below oc_tol.  d_x, d_dc, d_dv, d_xnew: nel (d_xnew must not alias).

@@ -7,6 +7,8 @@ Density-filter mode (the default):
   K(E) u = f; c = f^T u; dc = -p xPhys^(p-1)(E0 - Emin) u_e^T KE u_e;
   dc~ = H (dc_D / Hs); dv~ = w^D; the OC multiplier makes the design-element sum
   of filter(x_new) equal to volfrac * (number of design elements).
+  With ``vol_mode == "all"`` the sum runs over every element instead (passive
+  solids at 1, voids at 0) and equals volfrac * nel.
 Sensitivity-filter mode (the filter the paper's text describes):
   xPhys = x; dc~ = H(x dc)/(Hs max(1e-3, x)); dv = 1; volume = sum of x over
   design elements.
@@ -30,7 +32,12 @@ class SimpOracle:
         self.filter = filt.Filter(p.nelx, p.nely, p.nelz, p.rmin, self.mask)
         self.design = self.mask == 0
         self.n_design = int(self.design.sum())
-        self.target = p.volfrac * self.n_design
+        if getattr(p, "vol_mode", "design") == "all":
+            # every element counts (fixed solids as 1, fixed voids as 0) against
+            # volfrac * nel; the design elements carry what the solids leave
+            self.target = p.volfrac * p.nel - int((self.mask == 2).sum())
+        else:
+            self.target = p.volfrac * self.n_design
         if p.filter_mode == "density":
             self.w = self.filter.volume_weights()
         else:

@@ -17,6 +17,8 @@ from ._lib import (  # noqa: F401
     LIB_PATH,
     FILTER_DENSITY,
     FILTER_SENSITIVITY,
+    VOL_DESIGN,
+    VOL_ALL,
     FILTER_FWD,
     FILTER_ADJ,
     FILTER_SENS,

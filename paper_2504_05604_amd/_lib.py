@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libtopo.so")
 
 TOPO_OK, TOPO_EINVAL, TOPO_ENOMEM, TOPO_EDEVICE, TOPO_ENOTCONVERGED, TOPO_EUNSUPPORTED = range(6)
 FILTER_DENSITY, FILTER_SENSITIVITY = 0, 1
+VOL_DESIGN, VOL_ALL = 0, 1
 FILTER_FWD, FILTER_ADJ, FILTER_SENS, FILTER_VOLW = 0, 1, 2, 3
 PREC_FP64, PREC_FP32, PREC_BF16 = 0, 1, 2
 PRECOND_JACOBI, PRECOND_MG, PRECOND_LEARNED = 0, 1, 2
@@ -51,7 +52,7 @@ class Problem_C(C.Structure):
         ("nelx", C.c_int32), ("nely", C.c_int32), ("nelz", C.c_int32),
         ("E0", C.c_double), ("Emin", C.c_double), ("nu", C.c_double), ("penal", C.c_double),
         ("rmin", C.c_double), ("volfrac", C.c_double), ("move", C.c_double), ("eta", C.c_double),
-        ("filter", C.c_int32),
+        ("filter", C.c_int32), ("vol_mode", C.c_int32),
         ("mask", C.POINTER(C.c_int8)),
         ("fixed_dofs", C.POINTER(C.c_int64)), ("n_fixed", C.c_int64),
         ("f", C.POINTER(C.c_double)),
@@ -91,6 +92,7 @@ class IterStats_C(C.Structure):
         ("pcg_iters", C.c_int32), ("converged", C.c_int32), ("relres", C.c_double),
         ("ms_total", C.c_double), ("ms_filter", C.c_double), ("ms_solve", C.c_double),
         ("ms_sens", C.c_double), ("ms_oc", C.c_double),
+        ("fallbacks", C.c_int32), ("learned_iters", C.c_int32),
     ]
 
 
@@ -212,6 +214,7 @@ def _problem_c(p, filter_mode=None):
     pc = Problem_C(
         p.nelx, p.nely, p.nelz, p.E0, p.Emin, p.nu, p.penal, p.rmin, p.volfrac, p.move, p.eta,
         FILTER_DENSITY if mode == "density" else FILTER_SENSITIVITY,
+        VOL_ALL if getattr(p, "vol_mode", "design") == "all" else VOL_DESIGN,
         None if mask is None else mask.ctypes.data_as(C.POINTER(C.c_int8)),
         fixed.ctypes.data_as(C.POINTER(C.c_int64)), fixed.size,
         f.ctypes.data_as(C.POINTER(C.c_double)),
@@ -223,7 +226,8 @@ def _iter_stats(s) -> dict:
     return {"c": s.c, "volume": s.volume, "change": s.change, "lambda": s.lambda_,
             "pcg_iters": s.pcg_iters, "converged": bool(s.converged), "relres": s.relres,
             "ms_total": s.ms_total, "ms_filter": s.ms_filter, "ms_solve": s.ms_solve,
-            "ms_sens": s.ms_sens, "ms_oc": s.ms_oc}
+            "ms_sens": s.ms_sens, "ms_oc": s.ms_oc, "fallbacks": s.fallbacks,
+            "learned_iters": s.learned_iters}
 
 
 class Context:

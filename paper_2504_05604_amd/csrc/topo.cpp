@@ -299,6 +299,8 @@ static topo_status validate(const topo_problem *P, const topo_opts *O) {
   if (!(P->move > 0.0) || !(P->eta > 0.0)) return set_error("move and eta must be > 0"), TOPO_EINVAL;
   if (P->filter != TOPO_FILTER_DENSITY && P->filter != TOPO_FILTER_SENSITIVITY)
     return set_error("unknown filter mode %d", P->filter), TOPO_EINVAL;
+  if (P->vol_mode != TOPO_VOL_DESIGN && P->vol_mode != TOPO_VOL_ALL)
+    return set_error("unknown vol_mode %d", P->vol_mode), TOPO_EINVAL;
   if (!P->f) return set_error("load vector f is NULL"), TOPO_EINVAL;
   if (P->n_fixed < 6 || !P->fixed_dofs)
     return set_error("at least 6 fixed dofs are needed to remove rigid-body motion"), TOPO_EINVAL;
@@ -315,6 +317,13 @@ static topo_status validate(const topo_problem *P, const topo_opts *O) {
     }
   }
   if (nd == 0) return set_error("no design element"), TOPO_EINVAL;
+  if (P->vol_mode == TOPO_VOL_ALL) {
+    int64_t ns = 0;
+    if (P->mask)
+      for (int64_t e = 0; e < nel; ++e) ns += P->mask[e] == 2;
+    if (!(P->volfrac * (double)nel - (double)ns > 0.0))
+      return set_error("volfrac * nel must exceed the number of fixed-solid elements"), TOPO_EINVAL;
+  }
   if (O->precision != TOPO_PREC_FP64 && O->precision != TOPO_PREC_FP32 && O->precision != TOPO_PREC_BF16)
     return set_error("unknown precision %d", O->precision), TOPO_EINVAL;
   if (O->precond != TOPO_PRECOND_JACOBI && O->precond != TOPO_PRECOND_MG && O->precond != TOPO_PRECOND_LEARNED)
@@ -409,7 +418,11 @@ extern "C" topo_status topo_setup(const topo_problem *P, const topo_opts *O, voi
   std::vector<int8_t> hmask(ctx->nel, 0);
   if (P->mask) std::memcpy(hmask.data(), P->mask, ctx->nel);
   ctx->n_design = std::count(hmask.begin(), hmask.end(), (int8_t)0);
-  ctx->target = P->volfrac * (double)ctx->n_design;
+  // volume target of the design-element sum
+  if (P->vol_mode == TOPO_VOL_ALL)
+    ctx->target = P->volfrac * (double)ctx->nel - (double)std::count(hmask.begin(), hmask.end(), (int8_t)2);
+  else
+    ctx->target = P->volfrac * (double)ctx->n_design;
   std::vector<uint8_t> hfix(ctx->nnodes, 0);
   for (int64_t i = 0; i < P->n_fixed; ++i) hfix[P->fixed_dofs[i] / 3] |= (uint8_t)(1u << (P->fixed_dofs[i] % 3));
   std::vector<double> hf(P->f, P->f + ctx->ndof);
@@ -1420,6 +1433,8 @@ extern "C" topo_status topo_iterate(topo_ctx *ctx, double *d_x, int32_t n_iter, 
       o.pcg_iters = ss.iters;
       o.converged = ss.converged;
       o.relres = ss.relres;
+      o.fallbacks = ss.fallbacks;
+      o.learned_iters = ss.learned_iters;
       float t[5];
       for (int k = 0; k < 5; ++k) (void)hipEventElapsedTime(&t[k], ev[k], ev[k + 1]);
       float tot = 0.f;

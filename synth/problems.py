@@ -35,6 +35,7 @@ class Problem:
     f: Optional[np.ndarray] = None
     n_iter: int = 10
     filter_mode: str = "density"  # "density" | "sensitivity"
+    vol_mode: str = "design"  # volume target over "design" elements or "all" elements
     name: str = ""
     seed: int = 0
 

@@ -35,13 +35,13 @@ def test_default_opts():
     assert o.mg_max_coarse_dof == 1500 and o.coarse_refresh == 1
 
 
-def setup_status(p, **opt):
+def setup_status(p, vol_mode=0, **opt):
     lib = pkg.load()
     mask = None if p.mask is None else np.ascontiguousarray(p.mask, np.int8)
     fixed = np.ascontiguousarray(p.fixed_dofs, np.int64)
     f = np.ascontiguousarray(p.f, np.float64)
     pc = _lib.Problem_C(p.nelx, p.nely, p.nelz, p.E0, p.Emin, p.nu, p.penal, p.rmin, p.volfrac,
-                        p.move, p.eta, 0,
+                        p.move, p.eta, 0, vol_mode,
                         None if mask is None else mask.ctypes.data_as(C.POINTER(C.c_int8)),
                         fixed.ctypes.data_as(C.POINTER(C.c_int64)), fixed.size,
                         f.ctypes.data_as(C.POINTER(C.c_double)))
@@ -83,6 +83,18 @@ def test_setup_rejects_bad_mask_and_fixed_dofs():
     p.mask = np.ones(p.nel, np.int8)
     st, err, _ = setup_status(p)
     assert st == _lib.TOPO_EINVAL and "no design element" in err
+
+
+def test_setup_rejects_bad_volume_modes():
+    p = synth.config_small()
+    st, err, _ = setup_status(p, vol_mode=2)
+    assert st == _lib.TOPO_EINVAL and "vol_mode" in err
+    # fixed solids alone above volfrac * nel leave the design elements no volume
+    p.mask = np.zeros(p.nel, np.int8)
+    p.mask[: int(0.5 * p.nel)] = 2
+    p.volfrac = 0.4
+    st, err, _ = setup_status(p, vol_mode=1)
+    assert st == _lib.TOPO_EINVAL and "fixed-solid" in err
 
 
 def test_setup_rejects_bad_options():

@@ -231,11 +231,16 @@ def test_filter_ops_match_oracle(rmin, dims):
             np.testing.assert_allclose(got, ref, rtol=1e-13, atol=1e-15 * np.abs(ref).max(), err_msg=str(op))
 
 
+@pytest.mark.parametrize("vol_mode", ["design", "all"])
 @pytest.mark.parametrize("seed", [0, 1, 2])
 @pytest.mark.parametrize("move", [0.2, 0.05])
-def test_oc_update_matches_exact_multiplier(seed, move):
+def test_oc_update_matches_exact_multiplier(seed, move, vol_mode):
+    """The multiplier and design against the oracle's exact breakpoint root, with
+    the volume target over design elements or over all elements (fixed solids
+    counted at 1)."""
     p = ragged_problem(20 + seed, (23, 11, 9), rmin=2.0)
     p.move = move
+    p.vol_mode = vol_mode
     F = filt.Filter(p.nelx, p.nely, p.nelz, p.rmin, p.mask)
     design = p.mask == 0
     rng = np.random.default_rng(seed)
@@ -245,7 +250,9 @@ def test_oc_update_matches_exact_multiplier(seed, move):
     x[design & (rng.random(p.nel) < 0.05)] = 0.0
     dc = F.adjoint(-rng.exponential(1.0, p.nel) * 10 ** rng.uniform(-3, 2))
     w = F.volume_weights()
-    target = p.volfrac * design.sum()
+    target = simp.SimpOracle(p).target
+    if vol_mode == "all":
+        assert target == p.volfrac * p.nel - (p.mask == 2).sum()
     xref, lam_ref = oc.oc_exact(x, dc, w, w, target, p.move, p.eta, design)
     assert abs(w @ xref - target) <= 1e-9 * target
     with topo.Context(p) as ctx:
@@ -314,6 +321,25 @@ def test_iterate_matches_oracle_with_passive_elements(mode):
         assert abs(s["c"] - h["c"]) <= 1e-8 * h["c"], (s["c"], h["c"])
     np.testing.assert_allclose(xg, xo, atol=1e-7)
     assert np.all(xg[p.mask == 1] == 0.0)
+
+
+def test_iterate_matches_oracle_with_volume_over_all_elements():
+    """vol_mode "all" with fixed-solid and fixed-void elements: the trajectory
+    matches the oracle's, and the physical density summed over every element
+    meets volfrac * nel."""
+    p = ragged_problem(31, (16, 8, 6), rmin=2.0)
+    p.f = np.zeros(p.ndof)
+    p.f[3 * int(p.node_id(16, 0, 3)) + 1] = -1.0
+    p.vol_mode = "all"
+    assert (p.mask == 2).sum() > 0
+    n = 4
+    o = simp.SimpOracle(p)
+    xo, hist = o.trajectory(n)
+    xg, stats = run_gpu_trajectory(p, n)
+    for h, s in zip(hist, stats):
+        assert abs(s["c"] - h["c"]) <= 1e-8 * h["c"], (s["c"], h["c"])
+    np.testing.assert_allclose(xg, xo, atol=1e-7)
+    assert abs(o.physical(xg).sum() - p.volfrac * p.nel) <= 1e-7 * p.nel
 
 
 @pytest.mark.parametrize("warm", [0, 1, 2, 3])

@@ -49,3 +49,22 @@ def test_bisection_and_exact_multiplier_give_same_step():
     a = o.step(x, lam_mode="exact")
     b = o.step(x, lam_mode="bisection", oc_tol=1e-13)
     np.testing.assert_allclose(a["x_new"], b["x_new"], atol=1e-10)
+
+
+def test_volume_over_all_elements_counts_fixed_solids():
+    """vol_mode "all": the physical density summed over every element, fixed
+    solids included at 1, meets volfrac * nel after each update."""
+    p = synth.cantilever(12, 6, 4, volfrac=0.3, rmin=1.5, n_iter=3)
+    p.mask[(np.arange(p.nel) % 12) == 6] = 1
+    p.mask[[5, 40, 41]] = 2
+    p.vol_mode = "all"
+    o = simp.SimpOracle(p)
+    x = p.initial_design()
+    for _ in range(3):
+        r = o.step(x)
+        x = r["x_new"]
+        assert abs(o.physical(x).sum() - p.volfrac * p.nel) < 1e-8
+    # and the default counts design elements only, against a different target
+    p.vol_mode = "design"
+    r = simp.SimpOracle(p).step(p.initial_design())
+    assert abs(r["volume"] - p.volfrac * (p.mask == 0).sum()) < 1e-8
