@@ -314,7 +314,13 @@ struct FilterArgs {
   const double *Hs;     // nel
   const double *sD;     // nel: design/Hs
   const int8_t *mask;   // nel
+  // tiled stencil (reach R = ceil(rmin) - 1 in 1..kFilterTiledMaxR): the weight
+  // of an offset d depends on |d|^2 only; wsq[q] = max(0, rmin - sqrt(q)) for
+  // q < (R+1)^2 (offsets with |d|^2 >= (R+1)^2 > rmin^2 never contribute)
+  int R;
+  double wsq[16];
 };
+constexpr int kFilterTiledMaxR = 3;
 hipError_t launch_filter_hs(hipStream_t s, const FilterArgs &f, double *Hs);
 hipError_t launch_filter(hipStream_t s, int op, const FilterArgs &f, const double *in,
                          const double *aux, double *out);

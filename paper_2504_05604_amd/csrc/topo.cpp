@@ -586,7 +586,11 @@ extern "C" topo_status topo_setup(const topo_problem *P, const topo_opts *O, voi
   TOPO_ALLOC(ctx->volw, ctx->nel);
   TOPO_HIP(hipMemcpyAsync(ctx->d_off, off.data(), off.size() * sizeof(int), hipMemcpyHostToDevice, s));
   TOPO_HIP(hipMemcpyAsync(ctx->d_w, w.data(), w.size() * sizeof(double), hipMemcpyHostToDevice, s));
-  ctx->filt = FilterArgs{g, (int)w.size(), ctx->d_off, ctx->d_w, ctx->Hs, ctx->sD, ctx->mask};
+  ctx->filt = FilterArgs{g, (int)w.size(), ctx->d_off, ctx->d_w, ctx->Hs, ctx->sD, ctx->mask, R, {}};
+  for (int q = 0; q < 16; ++q) {
+    const double d = std::sqrt((double)q);  // the same weight expression as the offset list's
+    ctx->filt.wsq[q] = d < P->rmin ? P->rmin - d : 0.0;
+  }
   TOPO_HIP(launch_filter_hs(s, ctx->filt, ctx->Hs));
   TOPO_HIP(launch_design_scale(s, ctx->nel, ctx->mask, ctx->Hs, ctx->sD));
   if (P->filter == TOPO_FILTER_DENSITY) {

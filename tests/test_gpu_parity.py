@@ -213,22 +213,53 @@ def test_sensitivity_matches_oracle(case):
     assert abs(c - f @ u) <= 1e-12 * np.abs(f).sum() * np.abs(u).max()
 
 
-@pytest.mark.parametrize("rmin", [1.5, 2.0, 3.0, 4.0])
-@pytest.mark.parametrize("dims", [(11, 7, 6), (20, 10, 4)])
+@pytest.mark.parametrize("rmin", [1.0, 1.5, 2.0, 2.5, 3.0, 4.0, 5.0])
+@pytest.mark.parametrize("dims", [(11, 7, 6), (20, 10, 4), (37, 19, 13)])
 def test_filter_ops_match_oracle(rmin, dims):
+    """Every filter operation against the oracle's sparse H.  Reaches 1-3
+    (rmin 1.5-4) run the LDS-tiled stencil (37x19x13: several tiles per axis with
+    ragged ends), rmin 1 and 5 the offset-list kernel.  The GPU sums a stencil in
+    another order than the sparse product: with sign-mixed inputs (ADJ, SENS on a
+    random vector) the rounding error is bounded by n eps (H|v|)_e for n stencil
+    points, which is the tolerance besides 1e-13 relative."""
     p = ragged_problem(11, dims, rmin=rmin)
     F = filt.Filter(*dims, rmin, p.mask)
+    npts = len(filt.filter_offsets(rmin)[0])
     x = synth.random_density(12, p.nel, 0.0, 1.0)
     g = synth.random_vector(13, p.nel)
-    refs = {topo.FILTER_FWD: F.forward(x), topo.FILTER_ADJ: F.adjoint(g),
-            topo.FILTER_SENS: F.sensitivity(x, g), topo.FILTER_VOLW: F.volume_weights()}
+    refs = {topo.FILTER_FWD: (F.forward(x), 0.0), topo.FILTER_ADJ: (F.adjoint(g), F.adjoint(np.abs(g))),
+            topo.FILTER_SENS: (F.sensitivity(x, g), F.sensitivity(x, np.abs(g))),
+            topo.FILTER_VOLW: (F.volume_weights(), 0.0)}
     with topo.Context(p) as ctx:
         out = torch.empty(p.nel, dtype=torch.float64, device="cuda")
-        for op, ref in refs.items():
+        for op, (ref, mag) in refs.items():
             inp = dev(x) if op == topo.FILTER_FWD else dev(g)
             ctx.filter(op, inp, out, aux=dev(x) if op == topo.FILTER_SENS else None)
             got = host(out)
-            np.testing.assert_allclose(got, ref, rtol=1e-13, atol=1e-15 * np.abs(ref).max(), err_msg=str(op))
+            tol = 1e-13 * np.abs(ref) + 1e-15 * np.abs(ref).max() + 2 * npts * 2.2e-16 * mag
+            assert np.all(np.abs(got - ref) <= tol), (op, np.max(np.abs(got - ref) - tol))
+
+
+@pytest.mark.parametrize("rmin", [2.0, 3.0, 4.0])
+def test_filter_deep_tiles_match_oracle(rmin):
+    """A grid large enough for the 8-element-deep tiles of the stencil kernel,
+    ragged in every axis (100 = 3x32 + 4, 70 = 8x8 + 6, 61 = 7x8 + 5)."""
+    dims = (100, 70, 61)
+    p = ragged_problem(14, dims, rmin=rmin)
+    F = filt.Filter(*dims, rmin, p.mask)
+    npts = len(filt.filter_offsets(rmin)[0])
+    x = synth.random_density(15, p.nel, 0.0, 1.0)
+    g = synth.random_vector(16, p.nel)
+    refs = {topo.FILTER_FWD: (F.forward(x), 0.0), topo.FILTER_ADJ: (F.adjoint(g), F.adjoint(np.abs(g))),
+            topo.FILTER_SENS: (F.sensitivity(x, g), F.sensitivity(x, np.abs(g)))}
+    with topo.Context(p, topo.default_opts(precond=topo.PRECOND_JACOBI)) as ctx:
+        out = torch.empty(p.nel, dtype=torch.float64, device="cuda")
+        for op, (ref, mag) in refs.items():
+            inp = dev(x) if op == topo.FILTER_FWD else dev(g)
+            ctx.filter(op, inp, out, aux=dev(x) if op == topo.FILTER_SENS else None)
+            got = host(out)
+            tol = 1e-13 * np.abs(ref) + 1e-15 * np.abs(ref).max() + 2 * npts * 2.2e-16 * mag
+            assert np.all(np.abs(got - ref) <= tol), (op, np.max(np.abs(got - ref) - tol))
 
 
 @pytest.mark.parametrize("vol_mode", ["design", "all"])
