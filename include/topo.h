@@ -254,6 +254,27 @@ topo_status topo_filter(topo_ctx *ctx, int32_t op, const double *d_in, const dou
 topo_status topo_oc_update(topo_ctx *ctx, const double *d_x, const double *d_dc, const double *d_dv,
                            double *d_xnew, double *h_change, double *h_lambda);
 
+/* The OC update of topo_oc_update without a context, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation): this call allocates nothing.  Its search
+ * state and partial sums live in one fixed array of the library per GPU (about
+ * 130 KB, held until the process ends; its size does not depend on nel), so
+ * calls that overlap on one GPU (concurrent streams or threads) race and must
+ * be serialised by the caller; each call fully rewrites the state it reads.
+ * Arguments: nel >= 1 elements; d_x, d_dc, d_dv, d_xnew (nel FP64 each) and
+ * d_mask (nel int8: 0 design, 1 void, 2 solid) on the current device, d_xnew
+ * not aliasing an input; move, eta, oc_tol > 0; target > 0 is the volume the
+ * sum of d_dv * x_new over all elements must meet (volfrac * number of design
+ * elements for the density filter, plus the passive elements' d_dv * x).  The
+ * update is the one topo_oc_update computes with the same inputs (same kernels
+ * and order of summation).  d_result (device, 3 FP64: max |x_new - x|, the
+ * volume sum_j dv_j x_new_j and lambda) may be NULL.  Enqueued on hip_stream
+ * (NULL = default stream); returns without synchronising.  Errors: TOPO_EINVAL
+ * (validation, before any device work), TOPO_EDEVICE. */
+topo_status topo_oc_update_noalloc(int64_t nel, const double *d_x, const double *d_dc, const double *d_dv,
+                                   const int8_t *d_mask, double move, double eta, double target,
+                                   double oc_tol, void *hip_stream, double *d_xnew, double *d_result);
+
 /* n_iter SIMP iterations in the order of the Workflow section (filter ->
  * modulus -> solve -> sensitivities -> filter adjoint -> OC update) on the
  * design d_x (nel, in/out).  h_stats (n_iter entries) may be NULL.  The last

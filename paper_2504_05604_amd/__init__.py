@@ -12,6 +12,7 @@ from ._lib import (  # noqa: F401
     TopoError,
     default_opts,
     default_train_opts,
+    oc_update_noalloc,
     load,
     EXPORTED,
     LIB_PATH,

@@ -32,6 +32,7 @@ EXPORTED = [
     "topo_nn_create", "topo_nn_destroy", "topo_nn_set_precision", "topo_nn_n_params", "topo_nn_set_weights", "topo_nn_get_weights",
     "topo_nn_forward", "topo_nn_loss_grad", "topo_default_train_opts", "topo_nn_train", "topo_set_nn",
     "topo_nn_make_pairs", "topo_setup_batch", "topo_destroy_batch", "topo_batch_context", "topo_iterate_batch",
+    "topo_oc_update_noalloc",
 ]
 _VOID = ("topo_default_opts", "topo_destroy", "topo_last_error", "topo_nn_destroy", "topo_default_train_opts",
          "topo_destroy_batch")
@@ -150,6 +151,8 @@ def load(path: str = LIB_PATH):
     lib.topo_destroy_batch.restype = None
     lib.topo_batch_context.argtypes = [vp, C.c_int32, C.POINTER(vp)]
     lib.topo_iterate_batch.argtypes = [vp, C.POINTER(vp), C.c_int32, C.POINTER(IterStats_C)]
+    lib.topo_oc_update_noalloc.argtypes = [C.c_int64, dp, dp, dp, dp, C.c_double, C.c_double, C.c_double,
+                                           C.c_double, vp, dp, dp]
     for name in EXPORTED:
         if name not in _VOID:
             getattr(lib, name).restype = C.c_int
@@ -350,6 +353,20 @@ class Context:
             self._h, _ptr(xphys, self.nel, torch.float64), n, it.ctypes.data_as(C.POINTER(C.c_int32)),
             _ptr(rho, n * V, torch.float32), _ptr(r, n * 3 * V, torch.float32),
             _ptr(e, n * 3 * V, torch.float32), _ptr(fixed, n * V, torch.uint8)))
+
+
+def oc_update_noalloc(x, dc, dv, mask, move, eta, target, oc_tol, xnew, result=None, stream=None):
+    """topo_oc_update_noalloc: the OC update without a context or any allocation
+    (device tensors: x, dc, dv, xnew FP64 and mask int8 of nel entries; result,
+    if given, 3 FP64 entries receiving max |x_new - x|, the volume and lambda)."""
+    import torch
+    lib = load()
+    nel = x.numel()
+    _check(lib.topo_oc_update_noalloc(
+        nel, _ptr(x, nel, torch.float64), _ptr(dc, nel, torch.float64), _ptr(dv, nel, torch.float64),
+        _ptr(mask, nel, torch.int8), move, eta, target, oc_tol,
+        None if stream is None else C.c_void_p(int(stream)), _ptr(xnew, nel, torch.float64),
+        _ptr(result, 3, torch.float64)))
 
 
 def default_train_opts(**kw) -> TrainOpts_C:

@@ -327,15 +327,23 @@ hipError_t launch_filter(hipStream_t s, int op, const FilterArgs &f, const doubl
 hipError_t launch_design_scale(hipStream_t s, int64_t nel, const int8_t *mask, const double *Hs,
                                double *sD);
 
-// OC update with device-side multisection
+// OC update with device-side multisection.  a (nel) holds the per-element
+// coefficients x (max(0,-dc)/dv)^eta between the passes; with a == nullptr
+// every pass recomputes them from x, dc and dv (the same bits).  Partials: the
+// pass kernels use kOcPassBlocks x kOcStride slots, the prepare and final
+// reductions kOcReduceBlocks x kMaxRed.
+constexpr int kOcPassBlocks = 256, kOcReduceBlocks = 1024, kOcStride = 64;
+constexpr int kOcPartials = kOcPassBlocks * kOcStride > kOcReduceBlocks * kMaxRed
+                                ? kOcPassBlocks * kOcStride : kOcReduceBlocks * kMaxRed;
+constexpr int kOcPasses = 16;  // multisection passes (a 1e80 bracket shrinks below 1e-12)
 hipError_t launch_oc_prepare(hipStream_t s, int64_t nel, const double *x, const double *dc,
                              const double *dv, const int8_t *mask, double eta, double target,
                              double *a, Scalars *sc, const Reducer &red);
 hipError_t launch_oc_pass(hipStream_t s, int64_t nel, const double *x, const double *a,
-                          const double *dv, const int8_t *mask, double move, double eta,
-                          double tol, Scalars *sc, const Reducer &red);
+                          const double *dc, const double *dv, const int8_t *mask, double move,
+                          double eta, double tol, Scalars *sc, const Reducer &red);
 hipError_t launch_oc_final(hipStream_t s, int64_t nel, const double *x, const double *a,
-                           const double *dv, const int8_t *mask, double move, double eta,
-                           double *xnew, Scalars *sc, const Reducer &red);
+                           const double *dc, const double *dv, const int8_t *mask, double move,
+                           double eta, double *xnew, Scalars *sc, const Reducer &red);
 
 }  // namespace topo

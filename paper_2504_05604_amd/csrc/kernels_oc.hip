@@ -15,13 +15,27 @@ namespace topo {
 
 namespace {
 constexpr int kBs = 256;
-constexpr int kOcStride = 64;  // partial slots per block in a pass
+static_assert(kOcStride >= kOcCand, "one partial slot per candidate");
 inline unsigned nblocks(int64_t n) { return (unsigned)((n + kBs - 1) / kBs); }
 }  // namespace
 
 __device__ __forceinline__ double oc_value(double x, double a, double lam_pow, double move) {
   const double lo = fmax(0.0, x - move), hi = fmin(1.0, x + move);
   return fmin(hi, fmax(lo, a * lam_pow));
+}
+
+// a_e of a design element: read from the array the prepare pass stored, or
+// (kStored false, for callers without a per-element workspace) recomputed from
+// x, dc and dv by the same expression, so both give the same bits
+__device__ __forceinline__ double oc_coef(double x, double dc, double dv, double eta) {
+  const double B = fmax(0.0, -dc) / dv;
+  return x * pow(B, eta);
+}
+template <bool kStored>
+__device__ __forceinline__ double oc_a_of(const double *__restrict__ a, const double *__restrict__ dc,
+                                          const double *__restrict__ dv, double x, double eta, int64_t e) {
+  if constexpr (kStored) return a[e];
+  else return oc_coef(x, dc[e], dv[e], eta);
 }
 
 __device__ void oc_make_candidates(Scalars *sc) {
@@ -41,10 +55,9 @@ __global__ void oc_prepare_kernel(int64_t nel, const double *__restrict__ x,
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nel;
        e += (int64_t)gridDim.x * blockDim.x) {
     if (mask[e] == 0) {
-      const double B = fmax(0.0, -dc[e]) / dv[e];
-      a[e] = x[e] * pow(B, eta);
+      if (a) a[e] = oc_coef(x[e], dc[e], dv[e], eta);
     } else {
-      a[e] = 0.0;
+      if (a) a[e] = 0.0;
       cst = fma(dv[e], x[e], cst);
     }
   }
@@ -62,8 +75,10 @@ __global__ void oc_init_kernel(Scalars *sc, double target) {
 }
 
 // Partial volumes of one block for every candidate multiplier.
+template <bool kStored>
 __global__ __launch_bounds__(kBs) void oc_pass_kernel(int64_t nel, const double *__restrict__ x,
                                                       const double *__restrict__ a,
+                                                      const double *__restrict__ dc,
                                                       const double *__restrict__ dv,
                                                       const int8_t *__restrict__ mask, double move,
                                                       double eta, const Scalars *sc,
@@ -79,7 +94,7 @@ __global__ __launch_bounds__(kBs) void oc_pass_kernel(int64_t nel, const double 
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nel;
        e += (int64_t)gridDim.x * blockDim.x) {
     if (mask[e] != 0) continue;
-    const double xe = x[e], ae = a[e], we = dv[e];
+    const double xe = x[e], ae = oc_a_of<kStored>(a, dc, dv, xe, eta, e), we = dv[e];
 #pragma unroll
     for (int c = 0; c < kOcCand; ++c) part[c] = fma(we, oc_value(xe, ae, lampow[c], move), part[c]);
   }
@@ -141,17 +156,19 @@ __global__ __launch_bounds__(kSelThreads) void oc_select_kernel(int nparts, doub
     oc_make_candidates(sc);
 }
 
+template <bool kStored>
 __global__ void oc_final_kernel(int64_t nel, const double *__restrict__ x,
-                                const double *__restrict__ a, const double *__restrict__ dv,
-                                const int8_t *__restrict__ mask, double move, double eta,
-                                double *__restrict__ xnew, Scalars *sc, double *partials) {
+                                const double *__restrict__ a, const double *__restrict__ dc,
+                                const double *__restrict__ dv, const int8_t *__restrict__ mask,
+                                double move, double eta, double *__restrict__ xnew, Scalars *sc,
+                                double *partials) {
   const double lam = 0.5 * (sc->l1 + sc->l2);
   const double lp = pow(lam, -eta);
   double chg = 0.0, vol = 0.0;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nel;
        e += (int64_t)gridDim.x * blockDim.x) {
     const double xe = x[e];
-    const double xn = mask[e] == 0 ? oc_value(xe, a[e], lp, move) : xe;
+    const double xn = mask[e] == 0 ? oc_value(xe, oc_a_of<kStored>(a, dc, dv, xe, eta, e), lp, move) : xe;
     xnew[e] = xn;
     chg = fmax(chg, fabs(xn - xe));
     vol = fma(dv[e], xn, vol);
@@ -172,7 +189,7 @@ static unsigned oc_blocks(int64_t nel, int cap) {
 hipError_t launch_oc_prepare(hipStream_t s, int64_t nel, const double *x, const double *dc,
                              const double *dv, const int8_t *mask, double eta, double target,
                              double *a, Scalars *sc, const Reducer &red) {
-  const unsigned nb = oc_blocks(nel, 1024);
+  const unsigned nb = oc_blocks(nel, kOcReduceBlocks);
   oc_prepare_kernel<<<nb, kBs, 0, s>>>(nel, x, dc, dv, mask, eta, a, red.partials);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
@@ -183,10 +200,13 @@ hipError_t launch_oc_prepare(hipStream_t s, int64_t nel, const double *x, const 
 }
 
 hipError_t launch_oc_pass(hipStream_t s, int64_t nel, const double *x, const double *a,
-                          const double *dv, const int8_t *mask, double move, double eta,
-                          double tol, Scalars *sc, const Reducer &red) {
-  const unsigned nb = oc_blocks(nel, 256);
-  oc_pass_kernel<<<nb, kBs, 0, s>>>(nel, x, a, dv, mask, move, eta, sc, red.partials);
+                          const double *dc, const double *dv, const int8_t *mask, double move,
+                          double eta, double tol, Scalars *sc, const Reducer &red) {
+  const unsigned nb = oc_blocks(nel, kOcPassBlocks);
+  if (a)
+    oc_pass_kernel<true><<<nb, kBs, 0, s>>>(nel, x, a, dc, dv, mask, move, eta, sc, red.partials);
+  else
+    oc_pass_kernel<false><<<nb, kBs, 0, s>>>(nel, x, a, dc, dv, mask, move, eta, sc, red.partials);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   oc_select_kernel<<<1, kSelThreads, 0, s>>>((int)nb, tol, sc, red.partials);
@@ -194,10 +214,13 @@ hipError_t launch_oc_pass(hipStream_t s, int64_t nel, const double *x, const dou
 }
 
 hipError_t launch_oc_final(hipStream_t s, int64_t nel, const double *x, const double *a,
-                           const double *dv, const int8_t *mask, double move, double eta,
-                           double *xnew, Scalars *sc, const Reducer &red) {
-  const unsigned nb = oc_blocks(nel, 1024);
-  oc_final_kernel<<<nb, kBs, 0, s>>>(nel, x, a, dv, mask, move, eta, xnew, sc, red.partials);
+                           const double *dc, const double *dv, const int8_t *mask, double move,
+                           double eta, double *xnew, Scalars *sc, const Reducer &red) {
+  const unsigned nb = oc_blocks(nel, kOcReduceBlocks);
+  if (a)
+    oc_final_kernel<true><<<nb, kBs, 0, s>>>(nel, x, a, dc, dv, mask, move, eta, xnew, sc, red.partials);
+  else
+    oc_final_kernel<false><<<nb, kBs, 0, s>>>(nel, x, a, dc, dv, mask, move, eta, xnew, sc, red.partials);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   e = launch_finalize(s, red, (int)nb, 1, fin_max(&sc->change));

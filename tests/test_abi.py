@@ -133,3 +133,22 @@ def test_default_train_opts():
     assert (t.epochs, t.batch, t.lr, t.beta1, t.beta2, t.eps, t.loss) == (10, 4, 1e-3, 0.9, 0.999, 1e-8, pkg.LOSS_REL)
     o = pkg.default_opts()
     assert o.nn_max_iters == 200 and o.autotune == 0
+
+
+def test_noalloc_oc_update_validates_before_device_work():
+    lib = pkg.load()
+    fake = C.c_void_p(0x1000)  # never dereferenced: validation fails first
+    args = [fake, fake, fake, fake, 0.2, 0.5, 10.0, 1e-12, None, C.c_void_p(0x2000), None]
+    assert lib.topo_oc_update_noalloc(0, *args) == _lib.TOPO_EINVAL
+    assert "nel" in lib.topo_last_error().decode()
+    bad = list(args)
+    bad[4] = 0.0
+    assert lib.topo_oc_update_noalloc(10, *bad) == _lib.TOPO_EINVAL
+    bad = list(args)
+    bad[6] = -1.0
+    assert lib.topo_oc_update_noalloc(10, *bad) == _lib.TOPO_EINVAL
+    assert "target" in lib.topo_last_error().decode()
+    bad = list(args)
+    bad[9] = fake  # d_xnew aliasing d_x
+    assert lib.topo_oc_update_noalloc(10, *bad) == _lib.TOPO_EINVAL
+    assert lib.topo_oc_update_noalloc(10, None, *args[1:]) == _lib.TOPO_EINVAL
