@@ -296,6 +296,41 @@ topo_status topo_time_operator(topo_ctx *ctx, int32_t reps, double *h_ms_per_lau
 topo_status topo_get_state(topo_ctx *ctx, double *d_u, double *d_xphys);
 
 /* ------------------------------------------------------------------------
+ * Before and after the loop (Workflow and Key Features section: STL design
+ * domains in, the optimised design out as an STL mesh).  Element (i, j, k)
+ * occupies [o + h i, o + h (i+1)] x ... with origin o (h_origin: 3 doubles on
+ * the host, NULL = 0) and element size h > 0.
+ */
+
+/* Binary STL of the thresholded design: every face between an element with
+ * d_xphys > threshold and an element at or below it (or outside the grid) as
+ * two triangles with the outward unit normal, counter-clockwise seen from
+ * outside; elements in numbering order, faces in the order -x, +x, -y, +y, -z,
+ * +z.  The mesh is closed and encloses exactly the solid elements.  Writes
+ * *h_ntri (the triangle count); if d_stl is not NULL also the whole file image
+ * into d_stl (device, stl_bytes >= 84 + 50 ntri: 80-byte header, uint32 count,
+ * 50-byte triangle records).  Calling with d_stl NULL first gives the size.
+ * d_xphys: nel FP64 (device).  Allocates temporary device memory; synchronises
+ * hip_stream.  Errors: TOPO_EINVAL (sizes, NULL arguments, buffer too small,
+ * more than 2^32 - 1 triangles), TOPO_ENOMEM, TOPO_EDEVICE. */
+topo_status topo_surface_stl(int32_t nelx, int32_t nely, int32_t nelz, const double *d_xphys, double threshold,
+                             const double *h_origin, double h, void *hip_stream, uint8_t *d_stl,
+                             int64_t stl_bytes, int64_t *h_ntri);
+
+/* Element mask from a closed triangle mesh (an STL design domain or obstacle):
+ * d_mask[e] = code_inside where the element's centroid lies inside the mesh
+ * (odd number of crossings of the ray from the centroid along +z), else
+ * code_outside; e.g. a domain gives 0 (design) inside and 1 (void) outside for
+ * topo_problem.mask.  d_tri: ntri x 3 vertices x (x, y, z) float32 (device), in
+ * any orientation.  *h_bad_columns (may be NULL) counts the element columns
+ * whose vertical line crossed the mesh an odd number of times (or more than 128
+ * times): zero for a closed mesh.  Allocates temporary device memory;
+ * synchronises hip_stream.  Errors: TOPO_EINVAL, TOPO_ENOMEM, TOPO_EDEVICE. */
+topo_status topo_voxelize(const float *d_tri, int64_t ntri, int32_t nelx, int32_t nely, int32_t nelz,
+                          const double *h_origin, double h, int8_t code_inside, int8_t code_outside,
+                          void *hip_stream, int8_t *d_mask, int64_t *h_bad_columns);
+
+/* ------------------------------------------------------------------------
  * Batches of independent problems.  Each problem gets its own context on its
  * own stream (created by the batch), so kernels of different problems overlap
  * on the device; topo_iterate_batch drives them from a pool of n_threads host

@@ -13,6 +13,10 @@ from ._lib import (  # noqa: F401
     default_opts,
     default_train_opts,
     oc_update_noalloc,
+    surface_stl,
+    write_stl,
+    read_stl,
+    voxelize,
     load,
     EXPORTED,
     LIB_PATH,

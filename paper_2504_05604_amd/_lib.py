@@ -32,7 +32,7 @@ EXPORTED = [
     "topo_nn_create", "topo_nn_destroy", "topo_nn_set_precision", "topo_nn_n_params", "topo_nn_set_weights", "topo_nn_get_weights",
     "topo_nn_forward", "topo_nn_loss_grad", "topo_default_train_opts", "topo_nn_train", "topo_set_nn",
     "topo_nn_make_pairs", "topo_setup_batch", "topo_destroy_batch", "topo_batch_context", "topo_iterate_batch",
-    "topo_oc_update_noalloc",
+    "topo_oc_update_noalloc", "topo_surface_stl", "topo_voxelize",
 ]
 _VOID = ("topo_default_opts", "topo_destroy", "topo_last_error", "topo_nn_destroy", "topo_default_train_opts",
          "topo_destroy_batch")
@@ -151,6 +151,10 @@ def load(path: str = LIB_PATH):
     lib.topo_destroy_batch.restype = None
     lib.topo_batch_context.argtypes = [vp, C.c_int32, C.POINTER(vp)]
     lib.topo_iterate_batch.argtypes = [vp, C.POINTER(vp), C.c_int32, C.POINTER(IterStats_C)]
+    lib.topo_surface_stl.argtypes = [C.c_int32, C.c_int32, C.c_int32, dp, C.c_double, C.POINTER(C.c_double),
+                                     C.c_double, vp, dp, C.c_int64, C.POINTER(C.c_int64)]
+    lib.topo_voxelize.argtypes = [dp, C.c_int64, C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_double),
+                                  C.c_double, C.c_int8, C.c_int8, vp, dp, C.POINTER(C.c_int64)]
     lib.topo_oc_update_noalloc.argtypes = [C.c_int64, dp, dp, dp, dp, C.c_double, C.c_double, C.c_double,
                                            C.c_double, vp, dp, dp]
     for name in EXPORTED:
@@ -367,6 +371,66 @@ def oc_update_noalloc(x, dc, dv, mask, move, eta, target, oc_tol, xnew, result=N
         _ptr(mask, nel, torch.int8), move, eta, target, oc_tol,
         None if stream is None else C.c_void_p(int(stream)), _ptr(xnew, nel, torch.float64),
         _ptr(result, 3, torch.float64)))
+
+
+def _origin(origin):
+    return None if origin is None else (C.c_double * 3)(*[float(v) for v in origin])
+
+
+def surface_stl(dims, xphys, threshold=0.5, origin=None, h=1.0, stream=None):
+    """topo_surface_stl: the binary STL image (a uint8 device tensor) of the
+    thresholded design's voxel surface, and its triangle count."""
+    import torch
+    lib = load()
+    nx, ny, nz = (int(v) for v in dims)
+    nel = nx * ny * nz
+    st = None if stream is None else C.c_void_p(int(stream))
+    ntri = C.c_int64()
+    _check(lib.topo_surface_stl(nx, ny, nz, _ptr(xphys, nel, torch.float64), threshold, _origin(origin), h, st,
+                                None, 0, C.byref(ntri)))
+    buf = torch.empty(84 + 50 * ntri.value, dtype=torch.uint8, device=xphys.device)
+    _check(lib.topo_surface_stl(nx, ny, nz, _ptr(xphys, nel, torch.float64), threshold, _origin(origin), h, st,
+                                _ptr(buf), buf.numel(), C.byref(ntri)))
+    return buf, ntri.value
+
+
+def write_stl(path, dims, xphys, threshold=0.5, origin=None, h=1.0):
+    """Writes the binary STL of the thresholded design to a file (the image is
+    built on the device by topo_surface_stl)."""
+    buf, n = surface_stl(dims, xphys, threshold, origin, h)
+    with open(path, "wb") as fh:
+        fh.write(buf.cpu().numpy().tobytes())
+    return n
+
+
+def read_stl(path):
+    """Triangles (n, 3, 3) float32 of a binary STL file (file parsing only)."""
+    raw = open(path, "rb").read()
+    if len(raw) < 84:
+        raise ValueError("not a binary STL file")
+    n = int(np.frombuffer(raw, dtype="<u4", count=1, offset=80)[0])
+    if len(raw) < 84 + 50 * n:
+        raise ValueError("truncated binary STL file")
+    rec = np.dtype([("normal", "<f4", 3), ("v", "<f4", (3, 3)), ("attr", "<u2")])
+    return np.ascontiguousarray(np.frombuffer(raw, dtype=rec, count=n, offset=84)["v"])
+
+
+def voxelize(tri, dims, origin=None, h=1.0, code_inside=0, code_outside=1, stream=None):
+    """topo_voxelize: int8 device mask of the elements whose centroid lies inside
+    the closed mesh `tri` ((n, 3, 3) float32, host or device), and the number of
+    element columns that saw an open mesh."""
+    import torch
+    lib = load()
+    nx, ny, nz = (int(v) for v in dims)
+    t = torch.as_tensor(np.ascontiguousarray(tri, dtype=np.float32)) if not isinstance(tri, torch.Tensor) else tri
+    t = t.to("cuda").contiguous()
+    mask = torch.empty(nx * ny * nz, dtype=torch.int8, device="cuda")
+    bad = C.c_int64()
+    ntri = t.numel() // 9
+    _check(lib.topo_voxelize(_ptr(t, 9 * ntri, torch.float32) if ntri else None, ntri, nx, ny, nz,
+                             _origin(origin), h, code_inside, code_outside,
+                             None if stream is None else C.c_void_p(int(stream)), _ptr(mask), C.byref(bad)))
+    return mask, bad.value
 
 
 def default_train_opts(**kw) -> TrainOpts_C:

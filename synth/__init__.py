@@ -29,3 +29,4 @@ from .problems import (  # noqa: F401
     random_vector,
     random_density,
 )
+from .meshes import box_mesh, sphere_mesh, random_voxels  # noqa: F401,E402
