@@ -276,21 +276,39 @@ hipError_t launch_relu_back(hipStream_t s, int64_t n, const float *Y, float *dY)
   return hipGetLastError();
 }
 
-// one block per channel; fixed-order tree over a strided partial sum
-__global__ void bias_grad_kernel(int64_t N, const float *dY, float *db) {
-  const int c = blockIdx.x;
+// Bias gradient in two fixed-order stages: blocks (channel c, slice p) sum a
+// contiguous slice of channel c's row into partials[c * P + p], then one thread
+// per channel adds its P partials in order.
+__global__ void bias_grad_part_kernel(int64_t N, int P, const float *dY, double *partials) {
+  const int c = blockIdx.y, p = blockIdx.x;
+  const int64_t len = (N + P - 1) / P, i0 = (int64_t)p * len, i1 = min(N, i0 + len);
   double t = 0.0;
-  for (int64_t i = threadIdx.x; i < N; i += blockDim.x) t += dY[(int64_t)c * N + i];
+  for (int64_t i = i0 + threadIdx.x; i < i1; i += blockDim.x) t += dY[(int64_t)c * N + i];
   __shared__ double part[kMaxRed];
   double v[1] = {t};
   block_reduce_store<1, false>(v, part, 0);
   __syncthreads();
-  if (threadIdx.x == 0) db[c] = (float)part[0];
+  if (threadIdx.x == 0) partials[(int64_t)c * P + p] = part[0];
 }
 
-hipError_t launch_bias_grad(hipStream_t s, int C, int64_t N, const float *dY, float *db) {
+__global__ void bias_grad_sum_kernel(int C, int P, const double *partials, float *db) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= C) return;
+  double t = 0.0;
+  for (int p = 0; p < P; ++p) t += partials[(int64_t)c * P + p];
+  db[c] = (float)t;
+}
+
+hipError_t launch_bias_grad(hipStream_t s, int C, int64_t N, const float *dY, float *db, const Reducer &red) {
   if (!db) return hipSuccess;
-  bias_grad_kernel<<<C, kBs, 0, s>>>(N, dY, db);
+  const int64_t cap = (int64_t)red.max_blocks * kMaxRed;
+  int P = (int)std::min<int64_t>({64, (N + 4095) / 4096, cap / std::max(1, C)});
+  if (P < 1) P = 1;
+  if ((int64_t)P * C > cap) return hipErrorInvalidValue;
+  bias_grad_part_kernel<<<dim3((unsigned)P, (unsigned)C), kBs, 0, s>>>(N, P, dY, red.partials);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  bias_grad_sum_kernel<<<(C + 255) / 256, 256, 0, s>>>(C, P, red.partials, db);
   return hipGetLastError();
 }
 

@@ -86,8 +86,20 @@ static topo_status prepare_impl(const int c[3], NnWork &w, Dim3 g0, int B, bool 
 
 static hipError_t run_gemm(const topo_nn *nn, hipStream_t s, int mode, const GemmArgs &a, float *split,
                            int64_t cap) {
-  return nn->precision == TOPO_PREC_BF16 ? launch_igemm_bf16(s, mode, a, split, cap)
-                                         : launch_igemm(s, mode, a, split, cap);
+  if (nn->precision != TOPO_PREC_BF16) return launch_igemm(s, mode, a, split, cap);
+  if (conv_bf16_supported(mode, a)) return launch_conv_bf16(s, mode, a);
+  return launch_igemm_bf16(s, mode, a, split, cap);
+}
+
+// attaches the BF16 weight pack of layer L in orientation o (0: A = W, 1: A = WT)
+static GemmArgs with_pack(const topo_nn *nn, int L, int o, GemmArgs a) {
+  if (nn->pack && nn->pk_mp[L][o] > 0) {
+    a.wpack = nn->pack + nn->pk_off[L][o];
+    a.wp_mp = nn->pk_mp[L][o];
+    a.wp_cp = nn->pk_cp[L][o];
+    a.wp_cc = nn->pk_cc[L][o];
+  }
+  return a;
 }
 
 static GemmArgs gemm(int M, int N, int K, const float *A, int64_t sam, int64_t sak, const float *src,
@@ -118,7 +130,7 @@ static hipError_t conv_fwd(const topo_nn *nn, int L, hipStream_t s, int B, Dim3 
   const int K = l.ci * 27;
   const GemmArgs a = gemm(l.co, (int)(B * go.count()), K, nn->W + l.w_off, K, 1, x, ConvGeo{B, gi, go, stride},
                           y, nn->W + l.b_off, relu, false, skip);
-  return run_gemm(nn, s, GB_CONV, a, nullptr, 0);
+  return run_gemm(nn, s, GB_CONV, with_pack(nn, L, 0, a), nullptr, 0);
 }
 
 // y = conv_2^T(x; layer) + b: x on the coarse grid (co channels), y on gf (ci channels)
@@ -128,7 +140,7 @@ static hipError_t up_fwd(const topo_nn *nn, int L, hipStream_t s, int B, Dim3 gf
   const int K = l.co * 27;
   const GemmArgs a = gemm(l.ci, (int)(B * gf.count()), K, nn->WT + l.w_off, K, 1, x,
                           ConvGeo{B, gf, half_up(gf), 2}, y, nn->W + l.b_off, false, false, skip);
-  return run_gemm(nn, s, GB_CONVT, a, nullptr, 0);
+  return run_gemm(nn, s, GB_CONVT, with_pack(nn, L, 1, a), nullptr, 0);
 }
 
 }  // namespace topo
@@ -148,6 +160,13 @@ topo_status nn_refresh(topo_nn *nn, hipStream_t s) {
   for (int L = 0; L < L_COUNT; ++L) {
     const NnLayer &l = nn->layer[L];
     NN_HIP(launch_transpose_w(s, l.co, l.ci, l.taps, nn->W + l.w_off, nn->WT + l.w_off));
+    for (int o = 0; o < 2; ++o) {
+      if (!nn->pack || nn->pk_mp[L][o] == 0) continue;
+      const int M = o ? l.ci : l.co, Kch = o ? l.co : l.ci;
+      const float *A = o ? nn->WT + l.w_off : nn->W + l.w_off;
+      NN_HIP(launch_pack_bf16(s, A, (int64_t)Kch * 27, 1, M, Kch, nn->pk_mp[L][o], nn->pk_cp[L][o],
+                              nn->pack + nn->pk_off[L][o]));
+    }
   }
   return TOPO_OK;
 }
@@ -186,11 +205,12 @@ static topo_status conv_back(topo_nn *nn, NnWork &w, int L, hipStream_t s, Dim3 
   NN_HIP(run_gemm(nn, s, GB_WGRAD, gemm(l.co, l.ci * 27, Ko, dy, Ko, 1, x, geo, nn->G + l.w_off, nullptr, false,
                                         false, nullptr),
                       w.split, w.split_cap));
-  NN_HIP(launch_bias_grad(s, l.co, Ko, dy, nn->G + l.b_off));
+  NN_HIP(launch_bias_grad(s, l.co, Ko, dy, nn->G + l.b_off, nn->red));
   if (dx)
-    NN_HIP(run_gemm(nn, s, GB_CONVT, gemm(l.ci, Ni, l.co * 27, nn->WT + l.w_off, l.co * 27, 1, dy, geo, dx,
-                                          nullptr, false, acc, nullptr),
-                        nullptr, 0));
+    NN_HIP(run_gemm(nn, s, GB_CONVT,
+                    with_pack(nn, L, 1, gemm(l.ci, Ni, l.co * 27, nn->WT + l.w_off, l.co * 27, 1, dy, geo, dx,
+                                             nullptr, false, acc, nullptr)),
+                    nullptr, 0));
   return TOPO_OK;
 }
 
@@ -205,10 +225,11 @@ static topo_status up_back(topo_nn *nn, NnWork &w, int L, hipStream_t s, Dim3 gf
   NN_HIP(run_gemm(nn, s, GB_WGRAD, gemm(l.co, l.ci * 27, Kc, xc, Kc, 1, dy, geo, nn->G + l.w_off, nullptr, false,
                                         false, nullptr),
                       w.split, w.split_cap));
-  NN_HIP(launch_bias_grad(s, l.ci, Nf, dy, nn->G + l.b_off));
-  NN_HIP(run_gemm(nn, s, GB_CONV, gemm(l.co, Kc, l.ci * 27, nn->W + l.w_off, l.ci * 27, 1, dy, geo, dxc, nullptr,
-                                       false, false, nullptr),
-                      nullptr, 0));
+  NN_HIP(launch_bias_grad(s, l.ci, Nf, dy, nn->G + l.b_off, nn->red));
+  NN_HIP(run_gemm(nn, s, GB_CONV,
+                  with_pack(nn, L, 0, gemm(l.co, Kc, l.ci * 27, nn->W + l.w_off, l.ci * 27, 1, dy, geo, dxc,
+                                           nullptr, false, false, nullptr)),
+                  nullptr, 0));
   return TOPO_OK;
 }
 
@@ -226,7 +247,7 @@ topo_status nn_backward(topo_nn *nn, NnWork &w, hipStream_t s) {
     NN_HIP(run_gemm(nn, s, GB_PLAINT, gemm(3, c0, (int)N0, w.dout, N0, 1, w.t0, geo, nn->G + h.w_off, nullptr,
                                            false, false, nullptr),
                         w.split, w.split_cap));
-    NN_HIP(launch_bias_grad(s, 3, N0, w.dout, nn->G + h.b_off));
+    NN_HIP(launch_bias_grad(s, 3, N0, w.dout, nn->G + h.b_off, nn->red));
     NN_HIP(run_gemm(nn, s, GB_PLAIN, gemm(c0, (int)N0, 3, nn->W + h.w_off, 1, c0, w.dout, geo, w.dt0, nullptr,
                                           false, false, nullptr),
                         nullptr, 0));
@@ -299,6 +320,26 @@ extern "C" topo_status topo_nn_create(const int32_t channels[3], void *hip_strea
   for (float **b : bufs) {
     if ((e = walloc(nn->allocs, b, off)) != hipSuccess) break;
     if ((e = hipMemsetAsync(*b, 0, off * sizeof(float), nn->stream)) != hipSuccess) break;
+  }
+  // BF16 weight packs (layers with at most 64 rows in an orientation)
+  if (e == hipSuccess) {
+    int64_t poff = 0;
+    for (int L = 0; L < L_COUNT; ++L) {
+      const NnLayer &l = nn->layer[L];
+      if (l.taps != 27) continue;
+      for (int o = 0; o < 2; ++o) {
+        const int M = o ? l.ci : l.co, Kch = o ? l.co : l.ci;
+        if (M > 64) continue;
+        const int cc = Kch <= 16 ? 16 : 32;
+        nn->pk_mp[L][o] = M <= 16 ? 16 : (M <= 32 ? 32 : 64);
+        nn->pk_cc[L][o] = cc;
+        nn->pk_cp[L][o] = (Kch + cc - 1) / cc * cc;
+        nn->pk_off[L][o] = poff;
+        poff += (int64_t)nn->pk_mp[L][o] * 27 * nn->pk_cp[L][o];
+      }
+    }
+    e = walloc(nn->allocs, &nn->pack, poff);
+    if (e == hipSuccess) e = hipMemsetAsync(nn->pack, 0, (size_t)std::max<int64_t>(poff, 1) * 2, nn->stream);
   }
   if (e == hipSuccess) {
     nn->red.max_blocks = 64 * 64;

@@ -46,6 +46,10 @@ struct GemmArgs {
   int relu;
   int accumulate;
   const int *skip;    // device flag: return at once when non-zero (may be NULL)
+  // BF16 direct-convolution path (GB_CONV / GB_CONVT): A packed as
+  // [wp_mp rows][27 taps][wp_cp channels] BF16, channels in chunks of wp_cc
+  const void *wpack;
+  int wp_mp, wp_cp, wp_cc;
 };
 // split_buf (split_cap floats) enables a split reduction over long K (weight
 // gradients); NULL runs unsplit.
@@ -53,12 +57,20 @@ hipError_t launch_igemm(hipStream_t s, int mode, const GemmArgs &a, float *split
 // the same product with operands rounded to BF16 on the matrix cores (FP32 accumulation)
 hipError_t launch_igemm_bf16(hipStream_t s, int mode, const GemmArgs &a, float *split_buf, int64_t split_cap);
 
+// Wp[m][t][c] = A(m, c*27 + t) as BF16 (zero for m >= M, c >= Kch), Mp x 27 x Cp
+hipError_t launch_pack_bf16(hipStream_t s, const float *A, int64_t sam, int64_t sak, int M, int Kch, int Mp, int Cp,
+                            void *Wp);
+// direct 3x3x3 convolution on the matrix cores (kernels_nn_conv.hip) for the
+// GB_CONV / GB_CONVT modes when a.wpack is set and the shape is supported
+bool conv_bf16_supported(int mode, const GemmArgs &a);
+hipError_t launch_conv_bf16(hipStream_t s, int mode, const GemmArgs &a);
+
 // WT[ci][co*taps + t] = W[co][ci*taps + t]
 hipError_t launch_transpose_w(hipStream_t s, int co, int ci, int taps, const float *W, float *WT);
 // dY *= (Y > 0)
 hipError_t launch_relu_back(hipStream_t s, int64_t n, const float *Y, float *dY);
 // db[c] = sum_n dY[c][n]  (db may be NULL: nothing)
-hipError_t launch_bias_grad(hipStream_t s, int C, int64_t N, const float *dY, float *db);
+hipError_t launch_bias_grad(hipStream_t s, int C, int64_t N, const float *dY, float *db, const Reducer &red);
 hipError_t launch_adam(hipStream_t s, int64_t n, float *w, const float *g, float *m, float *v, float lr,
                        float b1, float b2, float eps, int step);
 
@@ -129,6 +141,12 @@ struct topo_nn {
   topo::NnLayer layer[topo::L_COUNT];
   int64_t nparams = 0;
   float *W = nullptr, *WT = nullptr, *G = nullptr, *m = nullptr, *v = nullptr;
+  // BF16 packs of the 3x3x3 weights for the direct-convolution kernels, per
+  // layer in two orientations: [0] rows = output channels of the stored
+  // convolution (A = W), [1] rows = its input channels (A = WT); refreshed with WT
+  uint16_t *pack = nullptr;
+  int64_t pk_off[topo::L_COUNT][2] = {};
+  int pk_mp[topo::L_COUNT][2] = {}, pk_cp[topo::L_COUNT][2] = {}, pk_cc[topo::L_COUNT][2] = {};
   int adam_step = 0;
   int precision = TOPO_PREC_FP32;  // arithmetic of the convolutions: FP32 or BF16 operands
   topo::Reducer red{};
