@@ -324,94 +324,132 @@ def paper_benchmark_oracle(budget_s):
 
 
 def learned_vs_mg(topo, synth, args):
-    """Training of the convolutional preconditioner on the GPU from pairs (r_k, u* - u_k)
-    of multigrid-PCG iterates on random 48x24x24 cantilevers (SIMP densities at
-    iterations 1, 5, 10, 20, 40), then solves to 1e-8 from zero at 96x48x48 on SIMP
-    densities with plain FP64 MG-PCG, the trained and the untrained network in
-    flexible CG (with the multigrid restart safeguard), and Jacobi-PCG."""
+    """The learned preconditioner at the scale of its workload: pairs (r_k, u* - u_k)
+    of multigrid-PCG iterates k = 0..19 on random 48x24x24 cantilevers (random
+    clamped face, load node and direction, passive boxes, volfrac U[0.15, 0.4],
+    rmin U[1.5, 3.0]) at SIMP iterations 1, 5, 10, 20 and 40 of their own
+    trajectories; the network trained on the GPU (cosine loss, Adam); then, on
+    96x48x48 problems from held-out seeds at the same SIMP iterations, solves to
+    1e-8 from zero with plain FP64 MG-PCG, the trained network in flexible CG
+    (multigrid restart safeguard), the same network untrained, and Jacobi-PCG,
+    plus the held-out loss of the trained and the untrained network."""
     import numpy as np
     import torch
     from synth import networks
 
+    prec = topo.PREC_BF16 if args.learned_precision == "bf16" else topo.PREC_FP32
     t0 = time.perf_counter()
     snaps = [1, 5, 10, 20, 40]
-    pair_its = [0, 1, 2, 3, 4, 6, 8, 11, 15, 20]
-    parts = []
-    for s in range(args.learned_seeds):
-        p = synth.random_problem(s, 48)
-        p.volfrac = float(np.random.default_rng(1000 + s).uniform(0.15, 0.4))
-        # pairs from the degree-2 V-cycle: measured, its iterates train the network
-        # to a lower loss than those of the default degrees
-        with topo.Context(p, topo.default_opts(cheb_degree=2, cheb_degree_coarse=2)) as ctx:
-            x = torch.from_numpy(p.initial_design()).to("cuda")
-            V, done = p.nnodes, 0
-            for it in snaps:
-                ctx.iterate(x, it - done, raise_on_nonconv=False)
-                done = it
-                xp = torch.empty(p.nel, dtype=torch.float64, device="cuda")
-                ctx.get_state(xphys=xp)
-                n = len(pair_its)
-                bufs = (torch.empty(n * V, dtype=torch.float32, device="cuda"),
-                        torch.empty(n * 3 * V, dtype=torch.float32, device="cuda"),
-                        torch.empty(n * 3 * V, dtype=torch.float32, device="cuda"),
-                        torch.empty(n * V, dtype=torch.uint8, device="cuda"))
-                ctx.make_pairs(xp, pair_its, *bufs)
-                parts.append(bufs)
-    rho, r, e, fx = (torch.cat([b[i] for b in parts]) for i in range(4))
-    n_pairs = len(parts) * len(pair_its)
-    del parts
+    pair_its = list(range(20))
+
+    def pairs_of(seeds, nelx, its, degree_opts):
+        """(rho, r, e, fixed) device tensors, pairs in seed, snapshot, iteration order."""
+        probs = []
+        for sd in seeds:
+            p = synth.random_problem(sd, nelx)
+            p.volfrac = float(np.random.default_rng(1000 + sd).uniform(0.15, 0.4))
+            probs.append(p)
+        V, n = probs[0].nnodes, len(its)
+        total = len(probs) * len(snaps) * n
+        bufs = (torch.empty(total * V, dtype=torch.float32, device="cuda"),
+                torch.empty(total * 3 * V, dtype=torch.float32, device="cuda"),
+                torch.empty(total * 3 * V, dtype=torch.float32, device="cuda"),
+                torch.empty(total * V, dtype=torch.uint8, device="cuda"))
+        k = 0
+        for p in probs:
+            with topo.Context(p, topo.default_opts(**degree_opts)) as ctx:
+                x = torch.from_numpy(p.initial_design()).to("cuda")
+                done = 0
+                for it in snaps:
+                    ctx.iterate(x, it - done, raise_on_nonconv=False)
+                    done = it
+                    xp = torch.empty(p.nel, dtype=torch.float64, device="cuda")
+                    ctx.get_state(xphys=xp)
+                    ctx.make_pairs(xp, its, bufs[0][k * V:(k + n) * V], bufs[1][3 * k * V:3 * (k + n) * V],
+                                   bufs[2][3 * k * V:3 * (k + n) * V], bufs[3][k * V:(k + n) * V])
+                    k += n
+        return bufs, total
+
+    # pairs from the degree-2 V-cycle: measured, its iterates train the network
+    # to a lower loss than those of the default degrees
+    train, n_pairs = pairs_of(range(args.learned_seeds), 48, pair_its, dict(cheb_degree=2, cheb_degree_coarse=2))
     torch.cuda.synchronize()
     t_data = time.perf_counter() - t0
     print(f"# learned: {n_pairs} training pairs in {t_data:.1f} s", file=sys.stderr, flush=True)
 
     w0 = networks.init_weights(seed=0)
-    net = topo.Network()
+    net = topo.Network(precision=prec)
     net.set_weights(w0)
-    tr = net.train((49, 25, 25), rho, r, e, fx,
-                   topo.default_train_opts(epochs=args.learned_epochs, batch=8, lr=1e-3, seed=1,
-                                           loss=topo.LOSS_COS))
-    print(f"# learned: trained {tr['steps']} steps, loss {tr['loss_first']:.3f} -> {tr['loss_last']:.3f}",
-          file=sys.stderr, flush=True)
-    del rho, r, e, fx
-    untrained = topo.Network()
+    tr = net.train((49, 25, 25), *train,
+                   topo.default_train_opts(epochs=args.learned_epochs, batch=8, lr=1e-3, seed=1, loss=topo.LOSS_COS))
+    print(f"# learned: trained {tr['steps']} steps in {tr['ms'] * 1e-3:.1f} s, loss {tr['loss_first']:.3f} -> "
+          f"{tr['loss_last']:.3f}", file=sys.stderr, flush=True)
+    del train
+    torch.cuda.empty_cache()
+    untrained = topo.Network(precision=prec)
     untrained.set_weights(w0)
 
+    # held-out loss on pairs of the evaluation problems (96x48x48)
+    eval_seeds = list(range(10000, 10000 + args.learned_eval_seeds))
+    held, n_held = pairs_of(eval_seeds, 96, [0, 2, 5, 10], dict(cheb_degree=2, cheb_degree_coarse=2))
+    nodes96 = (97, 49, 49)
+    held_loss = {}
+    for name, nw in (("trained", net), ("untrained", untrained)):
+        vals = [nw.loss_grad(nodes96, *held, list(range(b, min(n_held, b + 8))), None, loss=topo.LOSS_COS)
+                * (min(n_held, b + 8) - b) for b in range(0, n_held, 8)]
+        held_loss[name] = round(float(sum(vals) / n_held), 4)
+    del held
+    torch.cuda.empty_cache()
+    print(f"# learned: held-out loss trained {held_loss['trained']}, untrained {held_loss['untrained']}",
+          file=sys.stderr, flush=True)
+
     results = []
-    p = synth.random_problem(10001, 96)
-    with topo.Context(p, topo.default_opts()) as ctx:
-        x = torch.from_numpy(p.initial_design()).to("cuda")
-        done = 0
-        for it in (1, 10):
-            ctx.iterate(x, it - done, raise_on_nonconv=False)
-            done = it
-            xp = torch.empty(p.nel, dtype=torch.float64, device="cuda")
-            ctx.get_state(xphys=xp)
-            row = {"simp_iter": it}
-            for name, pc, nn_ in (("mg_fp64", topo.PRECOND_MG, None), ("learned", topo.PRECOND_LEARNED, net),
-                                  ("untrained", topo.PRECOND_LEARNED, untrained),
-                                  ("jacobi", topo.PRECOND_JACOBI, None)):
-                o = topo.default_opts(precond=pc, rtol=1e-8, max_iters=5000, nn_max_iters=500)
-                with topo.Context(p, o) as c2:
-                    if nn_ is not None:
-                        c2.set_nn(nn_)
-                    u = torch.zeros(p.ndof, dtype=torch.float64, device="cuda")
-                    c2.solve(xp, u, raise_on_nonconv=False)  # captures the CG graphs
-                    st = c2.solve(xp, u.zero_(), raise_on_nonconv=False)
-                    rec = {"iters": st["iters"], "ms": round(st["ms"], 3), "relres": st["relres"]}
-                    if pc == topo.PRECOND_LEARNED:
-                        rec.update(learned_iters=st["learned_iters"], fallbacks=st["fallbacks"])
-                    row[name] = rec
-            results.append(row)
-    print(f"# learned: evaluation done ({time.perf_counter() - t0:.1f} s in total)", file=sys.stderr, flush=True)
+    for sd in eval_seeds:
+        p = synth.random_problem(sd, 96)
+        p.volfrac = float(np.random.default_rng(1000 + sd).uniform(0.15, 0.4))
+        with topo.Context(p, topo.default_opts()) as ctx:
+            x = torch.from_numpy(p.initial_design()).to("cuda")
+            done = 0
+            for it in snaps:
+                ctx.iterate(x, it - done, raise_on_nonconv=False)
+                done = it
+                xp = torch.empty(p.nel, dtype=torch.float64, device="cuda")
+                ctx.get_state(xphys=xp)
+                row = {"seed": sd, "simp_iter": it}
+                for name, pc, nn_ in (("mg_fp64", topo.PRECOND_MG, None),
+                                      ("learned", topo.PRECOND_LEARNED, net),
+                                      ("untrained", topo.PRECOND_LEARNED, untrained),
+                                      ("jacobi", topo.PRECOND_JACOBI, None)):
+                    o = topo.default_opts(precond=pc, rtol=1e-8, max_iters=5000, nn_max_iters=500)
+                    with topo.Context(p, o) as c2:
+                        if nn_ is not None:
+                            c2.set_nn(nn_)
+                        u = torch.zeros(p.ndof, dtype=torch.float64, device="cuda")
+                        c2.solve(xp, u, raise_on_nonconv=False)  # captures the CG graphs
+                        st = c2.solve(xp, u.zero_(), raise_on_nonconv=False)
+                        rec = {"iters": st["iters"], "ms": round(st["ms"], 3), "relres": st["relres"]}
+                        if pc == topo.PRECOND_LEARNED:
+                            rec.update(learned_iters=st["learned_iters"], fallbacks=st["fallbacks"])
+                        row[name] = rec
+                results.append(row)
+    summary = {k: round(float(np.mean([r[k]["ms"] for r in results])), 3)
+               for k in ("mg_fp64", "learned", "untrained", "jacobi")}
+    summary["learned_beats_mg"] = sum(1 for r in results if r["learned"]["ms"] < r["mg_fp64"]["ms"])
+    summary["solves"] = len(results)
+    print(f"# learned: evaluation done ({time.perf_counter() - t0:.1f} s in total), mean ms {summary}",
+          file=sys.stderr, flush=True)
     return {
         "train_workload": f"{args.learned_seeds} random cantilevers 48x24x24 (91,875 DOF), pairs at CG "
-                          f"iterations {pair_its} of SIMP iterations {snaps} (V-cycle of degree 2)",
+                          f"iterations 0-19 of SIMP iterations {snaps} (V-cycle of degree 2)",
         "pairs": n_pairs, "pair_gen_s": round(t_data, 2), "epochs": args.learned_epochs, "batch": 8,
         "loss": "cosine", "loss_first_epoch": round(tr["loss_first"], 4), "loss_last_epoch": round(tr["loss_last"], 4),
         "train_s": round(tr["ms"] * 1e-3, 2),
         "train_samples_per_s": round(tr["steps"] * 8 / (tr["ms"] * 1e-3), 1),
-        "network_precision": "fp32",
-        "eval_workload": "random cantilever 96x48x48 (698,691 DOF), seed 10001, solve from zero to 1e-8",
+        "network_precision": args.learned_precision,
+        "held_out_loss": held_loss, "held_out_pairs": n_held,
+        "eval_workload": f"random cantilevers 96x48x48 (698,691 DOF), held-out seeds {eval_seeds}, SIMP "
+                         f"iterations {snaps}, solve from zero to 1e-8",
+        "mean_ms": summary,
         "results": results,
     }
 
@@ -528,8 +566,11 @@ def main():
     ap.add_argument("--batch-size", type=int, default=64)
     ap.add_argument("--batch-steps", type=int, default=5)
     ap.add_argument("--batch-warmup", type=int, default=2)
-    ap.add_argument("--learned-seeds", type=int, default=16)
-    ap.add_argument("--learned-epochs", type=int, default=8)
+    ap.add_argument("--learned-seeds", type=int, default=200,
+                    help="random 48x24x24 training problems (100 pairs each)")
+    ap.add_argument("--learned-epochs", type=int, default=3)
+    ap.add_argument("--learned-eval-seeds", type=int, default=2, help="held-out 96x48x48 problems")
+    ap.add_argument("--learned-precision", choices=["bf16", "fp32"], default="bf16")
     args = ap.parse_args()
     if args.record_oracle_iteration:
         import synth
