@@ -454,6 +454,50 @@ def learned_vs_mg(topo, synth, args):
     }
 
 
+def nn_timing(topo):
+    """Times the network alone: forward at 97x49x49 nodes (the 96x48x48
+    evaluation grid) and a training step's loss and gradient at 49x25x25 nodes
+    (batch 8), BF16 and FP32, with hipEvents around 5 calls each."""
+    import numpy as np
+    import torch
+    from synth import networks
+
+    blob = networks.init_weights(seed=0)
+    out = {}
+    for prec, name in ((topo.PREC_BF16, "bf16"), (topo.PREC_FP32, "fp32")):
+        net = topo.Network(precision=prec)
+        net.set_weights(blob)
+        nodes = (97, 49, 49)
+        V = int(np.prod(nodes))
+        g = torch.Generator(device="cuda").manual_seed(0)
+        x = torch.randn(4 * V, dtype=torch.float32, device="cuda", generator=g)
+        y = torch.empty(3 * V, dtype=torch.float32, device="cuda")
+        for _ in range(2):
+            net.forward(nodes, 1, x, y)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(5):
+            net.forward(nodes, 1, x, y)
+        b.record()
+        torch.cuda.synchronize()
+        out[f"{name}_forward_97x49x49_ms"] = round(a.elapsed_time(b) / 5, 3)
+        nodes, n = (49, 25, 25), 8
+        V = int(np.prod(nodes))
+        rho = torch.rand(n * V, device="cuda", generator=g)
+        r = torch.randn(n * 3 * V, device="cuda", generator=g)
+        e = torch.randn(n * 3 * V, device="cuda", generator=g)
+        fx = torch.zeros(n * V, dtype=torch.uint8, device="cuda")
+        grad = torch.empty(net.n_params, dtype=torch.float32, device="cuda")
+        for _ in range(2):
+            net.loss_grad(nodes, rho, r, e, fx, list(range(n)), grad, loss=topo.LOSS_COS)
+        t0 = time.perf_counter()
+        for _ in range(5):
+            net.loss_grad(nodes, rho, r, e, fx, list(range(n)), grad, loss=topo.LOSS_COS)
+        torch.cuda.synchronize()
+        out[f"{name}_loss_grad_49x25x25_b8_ms"] = round((time.perf_counter() - t0) / 5 * 1e3, 3)
+    return out
+
+
 def lockstep_fp64_error(topo, p, opts, mixed_stats, mixed_ctx):
     """The same SIMP iterations with the FP64 preconditioner from the same initial
     design: largest relative compliance difference over the iterations and the
@@ -532,6 +576,8 @@ def main():
                     help="per-level Chebyshev degrees, finest first, replacing the two above where given "
                          "(measured on the 5-level 160x80x80 hierarchy; '' for none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--nn-timing", action="store_true",
+                    help="time the network's forward and loss gradient alone and exit")
     ap.add_argument("--record-oracle-iteration", action="store_true",
                     help="time one complete oracle SIMP iteration at 160x80x80 on the host (minutes), "
                          "write its record under profiles/ and exit (no GPU work)")
@@ -572,6 +618,10 @@ def main():
     ap.add_argument("--learned-eval-seeds", type=int, default=2, help="held-out 96x48x48 problems")
     ap.add_argument("--learned-precision", choices=["bf16", "fp32"], default="bf16")
     args = ap.parse_args()
+    if args.nn_timing:
+        import paper_2504_05604_amd as topo
+        print(json.dumps({"nn_timing": nn_timing(topo)}))
+        return
     if args.record_oracle_iteration:
         import synth
         record_oracle_iteration(synth.config_large())
