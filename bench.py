@@ -544,14 +544,18 @@ def batched(topo, synth, args):
         b = topo.Batch(ps, opts, n_threads=threads)
         out.setdefault("total_dof", int(sum(b.ndof)))
         out.setdefault("setup_s", round(time.perf_counter() - t0, 2))
+        print(f"# batched {label}: set up {len(ps)} problems", file=sys.stderr, flush=True)
         xs = [torch.from_numpy(p.initial_design()).to("cuda") for p in ps]
         b.iterate(xs, args.batch_warmup, raise_on_nonconv=False)
         torch.cuda.synchronize()
+        print(f"# batched {label}: warm-up done", file=sys.stderr, flush=True)
         t0 = time.perf_counter()
         st = b.iterate(xs, args.batch_steps, raise_on_nonconv=False)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
+        print(f"# batched {label}: timed iterations done", file=sys.stderr, flush=True)
         b.close()
+        print(f"# batched {label}: closed", file=sys.stderr, flush=True)
         iters = sum(s["pcg_iters"] for row in st for s in row)
         dof_iters = sum(b.ndof[i] * s["pcg_iters"] for i, row in enumerate(st) for s in row)
         out[label] = {"ms_per_batch_iteration": round(1e3 * dt / args.batch_steps, 2),

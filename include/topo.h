@@ -153,6 +153,12 @@ typedef struct {
                                  in [1, 16] that replaces cheb_degree / cheb_degree_coarse
                                  on that level; 0 = not set (the level above the exact
                                  coarsest solve never smooths more than 16 steps)      */
+  int32_t group_launch;       /* topo_iterate_batch: problems with equal grids (multigrid
+                                 preconditioner in FP64 or FP32 on the element-column
+                                 kernel) are solved together, up to 8 per group, every CG
+                                 pass one launch for the whole group (results identical to
+                                 solving each alone with the group's launch shapes);
+                                 0 = every problem on its own stream                  */
 } topo_opts;
 
 typedef struct {
@@ -183,7 +189,7 @@ typedef struct {
  * rtol 1e-8, max_iters 1000, projected warm start (3), oc_tol 1e-12,
  * check_every 4, use_graphs 1, nn_max_iters 200, autotune 0, coarse_tail_nodes 0,
  * mfma_smoothing 0, ku_kernel TOPO_KU_AUTO, ku_shape -1, coarse_refresh 1,
- * cheb_degree_level all 0. */
+ * cheb_degree_level all 0, group_launch 1. */
 void topo_default_opts(topo_opts *opts);
 
 /* Validates the problem, copies its arrays to the device, builds the element

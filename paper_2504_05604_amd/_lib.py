@@ -68,7 +68,7 @@ class Opts_C(C.Structure):
         ("check_every", C.c_int32), ("use_graphs", C.c_int32), ("nn_max_iters", C.c_int32),
         ("autotune", C.c_int32), ("coarse_tail_nodes", C.c_int32), ("mfma_smoothing", C.c_int32),
         ("ku_kernel", C.c_int32), ("ku_shape", C.c_int32), ("coarse_refresh", C.c_int32),
-        ("cheb_degree_level", C.c_int32 * 8),
+        ("cheb_degree_level", C.c_int32 * 8), ("group_launch", C.c_int32),
     ]
 
 

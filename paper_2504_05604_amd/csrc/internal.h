@@ -1,6 +1,7 @@
 // Internal declarations of libtopo (not part of the ABI).
 #pragma once
 
+#include <string>
 #include <vector>
 
 #include <hip/hip_runtime.h>
@@ -169,6 +170,9 @@ hipError_t launch_ku_mfma(hipStream_t s, KuEpi epi, const KuArgsT<float> &a, boo
 template <typename T>
 hipError_t launch_ku_hada(hipStream_t s, KuEpi epi, const KuArgsT<T> &a, const KappaT<T> &kap,
                           const Reducer &red, int which, int *nparts);
+template <typename T>
+hipError_t launch_ku_hada_group(hipStream_t s, KuEpi epi, int G, const KuArgsT<T> *a, const KappaT<T> &kap,
+                                const Reducer *red, int which, int *nparts);
 // most block partials any K.u launch shape writes on this grid
 int64_t ku_max_blocks(const Grid &g);
 int64_t ku_hada_max_blocks(const Grid &g);
@@ -294,8 +298,102 @@ template <typename T>
 __host__ __device__ inline size_t tail_solve_bytes(int ncoarse) {
   return (size_t)kColParts * ncoarse * sizeof(double);  // FP64 in every precision
 }
+// ---------------------------------------------------------------------------
+// Grouped launches (kernels_*.hip): the problems of a group have identical
+// grids and launch shapes, so one launch serves all of them -- the kernel takes
+// a table of per-problem arguments by value and blockIdx.z picks the entry.
+// Each problem's blocks do exactly what its own launch would (same partial
+// sums, same order), so results are bit-identical to one launch per problem.
+constexpr int kMaxGroup = 8;
+template <class A>
+struct GroupTab {
+  A v[kMaxGroup];
+};
+template <typename T>
+hipError_t launch_ku_group(hipStream_t s, KuEpi epi, int G, const KuArgsT<T> *a, const KappaT<T> &kap,
+                           const Reducer *red, const Fin *fin, int shape);
+// finalize of G reductions of nparts partials each (partials of red[i], skip[i])
+hipError_t launch_finalize_group(hipStream_t s, int G, const Reducer *red, int nparts, int n, const Fin *fin,
+                                 const int *const *skip);
+struct XrArgs {
+  Scalars *sc;
+  double *x, *r;
+  const double *p, *q;
+  float *r32;
+  const int *skip;
+};
+hipError_t launch_cg_update_xr_group(hipStream_t s, int G, int64_t n, const XrArgs *a, const Reducer *red,
+                                     const Fin *fin);
+struct PArgs {
+  const Scalars *sc;
+  const void *z;  // double, or float when zsingle
+  double *p;
+  const int *skip;
+};
+hipError_t launch_cg_update_p_group(hipStream_t s, int G, int64_t n, bool zsingle, const PArgs *a, int first);
+struct FlexArgs {
+  const float *res, *dinv, *x;
+  const double *r;
+  float *z;
+  const int *skip;
+};
+hipError_t launch_flex_dot_group(hipStream_t s, int G, int64_t n, float inv_theta, const FlexArgs *a,
+                                 const Reducer *red, const Fin *fin);
+template <typename T>
+struct ChebStartArgs {
+  const T *res, *dinv;
+  T *d, *x;
+  const int *skip;
+};
+template <typename T>
+hipError_t launch_cheb_start_group(hipStream_t s, int G, int64_t n, T inv_theta, const ChebStartArgs<T> *a);
+struct DotArgs {
+  const double *a, *b;
+  const int *skip;
+};
+hipError_t launch_dot_group(hipStream_t s, int G, int64_t n, const DotArgs *a, const Reducer *red, const Fin *fin);
+template <typename T>
+struct TransferArgs {
+  const T *in;
+  const uint8_t *fixed;  // fixed flags of the output level
+  T *out;
+  const int *skip;
+};
+template <typename T>
+hipError_t launch_restrict_group(hipStream_t s, int G, Grid gf, Grid gc, const TransferArgs<T> *a);
+template <typename T>
+hipError_t launch_prolong_add_group(hipStream_t s, int G, Grid gf, Grid gc, const TransferArgs<T> *a);
+template <typename T>
+struct MatvecArgs {
+  const double *A;
+  const T *x;
+  T *y;
+  const int *skip;
+};
+template <typename T>
+hipError_t launch_dense_matvec_group(hipStream_t s, int G, int n, const MatvecArgs<T> *a);
+
 template <typename T>
 hipError_t launch_vcycle_tail_t(hipStream_t s, const TailArgs<T> &a);
+
+// Grouped CG over contexts (topo.cpp), used by the batch: the members share the
+// group's stream; key "" = the context cannot be grouped.
+struct Group {
+  std::vector<topo_ctx *> c;
+  hipStream_t s = nullptr;
+  int n() const { return (int)c.size(); }
+};
+std::string group_key(const topo_ctx *ctx);
+void group_adopt_shapes(topo_ctx *dst, const topo_ctx *src);
+void ctx_set_stream(topo_ctx *ctx, hipStream_t s);
+Grid ctx_grid(const topo_ctx *ctx);
+// graph/exec: the captured chunk of grouped CG iterations (made on first use,
+// owned by the caller, kept together as the single-context path keeps its own)
+topo_status group_pcg(Group &G, hipGraph_t *graph, hipGraphExec_t *exec, hipStream_t cap_stream,
+                      topo_solve_stats *stats);
+topo_status iterate_pre(topo_ctx *ctx, double *d_x, hipEvent_t *ev);
+topo_status iterate_post(topo_ctx *ctx, double *d_x, const topo_solve_stats &ss, hipEvent_t *ev,
+                         topo_iter_stats *o);
 // raises the kernel's dynamic LDS limit (call once before launching)
 template <typename T>
 hipError_t prepare_vcycle_tail_t(size_t smem_bytes);

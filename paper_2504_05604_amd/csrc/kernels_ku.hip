@@ -262,10 +262,38 @@ hipError_t launch_ku(hipStream_t s, KuEpi epi, const KuArgsT<float> &a, const Ka
   return launch_ku_t<float>(s, epi, a, kap, red, fin, shape);
 }
 
+// Grouped K.u (element-column shapes only): one launch for G problems of the
+// same grid, each reducing into its own partials and finalize.
+template <typename T>
+hipError_t launch_ku_group(hipStream_t s, KuEpi epi, int G, const KuArgsT<T> *a, const KappaT<T> &kap,
+                           const Reducer *red, const Fin *fin, int shape) {
+  if (G < 1 || G > kMaxGroup) return hipErrorInvalidValue;
+  if (shape < kKuShapeHada || shape >= kKuShapeHada + kKuShapesHada) return hipErrorInvalidValue;
+  if constexpr (std::is_same<T, float>::value) {
+    if (epi == KU_STORE_DOT || epi == KU_RESID) return hipErrorInvalidValue;
+  }
+  int nparts = 0;
+  hipError_t e = launch_ku_hada_group<T>(s, epi, G, a, kap, red, shape - kKuShapeHada, &nparts);
+  if (e != hipSuccess) return e;
+  if (!ku_reduces(epi, a[0])) return hipSuccess;
+  Fin f[kMaxGroup];
+  const int *sk[kMaxGroup];
+  for (int i = 0; i < G; ++i) {
+    f[i] = fin[i];
+    sk[i] = a[i].skip;
+  }
+  return launch_finalize_group(s, G, red, nparts, 1, f, sk);
+}
+template hipError_t launch_ku_group<double>(hipStream_t, KuEpi, int, const KuArgsT<double> *, const KappaT<double> &,
+                                            const Reducer *, const Fin *, int);
+template hipError_t launch_ku_group<float>(hipStream_t, KuEpi, int, const KuArgsT<float> *, const KappaT<float> &,
+                                           const Reducer *, const Fin *, int);
+
 // ---------------------------------------------------------------------------
 // Sums the block partials in block order.  Besides writing the sum, a finalize
 // can run the scalar step of the CG loop that consumes it (FinMode).
-__global__ void finalize_kernel(const double *partials, int nparts, int n, Fin fin, const int *skip) {
+__device__ __forceinline__ void finalize_body(const double *partials, int nparts, int n, const Fin &fin,
+                                              const int *skip) {
   if (skip && *skip) return;
   __shared__ double sh[kMaxRed][16];
   const bool is_max = fin.mode == FIN_MAX;
@@ -311,6 +339,31 @@ __global__ void finalize_kernel(const double *partials, int nparts, int n, Fin f
       }
     }
   }
+}
+
+__global__ void finalize_kernel(const double *partials, int nparts, int n, Fin fin, const int *skip) {
+  finalize_body(partials, nparts, n, fin, skip);
+}
+// one block per problem of a group
+__global__ void finalize_group_kernel(int nparts, int n, GroupTab<double *> part, GroupTab<Fin> fin,
+                                      GroupTab<const int *> skip) {
+  finalize_body(part.v[blockIdx.x], nparts, n, fin.v[blockIdx.x], skip.v[blockIdx.x]);
+}
+
+hipError_t launch_finalize_group(hipStream_t s, int G, const Reducer *red, int nparts, int n, const Fin *fin,
+                                 const int *const *skip) {
+  if (G < 1 || G > kMaxGroup || n > kMaxRed) return hipErrorInvalidValue;
+  GroupTab<double *> p{};
+  GroupTab<Fin> f{};
+  GroupTab<const int *> k{};
+  for (int i = 0; i < G; ++i) {
+    if (nparts > red[i].max_blocks) return hipErrorInvalidValue;
+    p.v[i] = red[i].partials;
+    f.v[i] = fin[i];
+    k.v[i] = skip[i];
+  }
+  finalize_group_kernel<<<G, 256, 0, s>>>(nparts, n, p, f, k);
+  return hipGetLastError();
 }
 
 hipError_t launch_finalize(hipStream_t s, const Reducer &red, int nparts, int n, const Fin &fin,

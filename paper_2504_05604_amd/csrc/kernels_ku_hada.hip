@@ -34,8 +34,8 @@ namespace topo {
 // VGPRs), so a 160x80x80 launch runs in one round (3 blocks of 256 threads per
 // CU); with them the register budget is left to the compiler.
 template <int EPI, int KZ, int TX, int TY, bool PF, typename T>
-__global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(PF ? 1 : 3))) void ku_hada_kernel(KuArgsT<T> a, HadaW<T> hw, int tiles_x,
-                                                         int tiles_xy, double *partials) {
+__device__ __forceinline__ void ku_hada_body(const KuArgsT<T> &a, const HadaW<T> &hw, int tiles_x, int tiles_xy,
+                                             double *partials) {
   if (a.skip && *a.skip) return;
   constexpr int NT = TX * TY;
   // corner contributions (0,0), (1,0), (0,1) of every thread's element column,
@@ -233,8 +233,8 @@ __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(PF ? 1 
 // of the load instructions.  Same arithmetic in the same order: bit-identical to
 // the other shapes.
 template <int EPI, int KZ, int TX, int TY, typename T>
-__global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(3))) void ku_hada_lds_kernel(
-    KuArgsT<T> a, HadaW<T> hw, int tiles_x, int tiles_xy, double *partials) {
+__device__ __forceinline__ void ku_hada_lds_body(const KuArgsT<T> &a, const HadaW<T> &hw, int tiles_x,
+                                                 int tiles_xy, double *partials) {
   if (a.skip && *a.skip) return;
   constexpr int NT = TX * TY;
   constexpr int NX1 = TX + 1;
@@ -385,6 +385,29 @@ __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(3))) vo
   ku_block_reduce<EPI>(a, dotv, partials);
 }
 
+// Kernels: one problem per launch, or a group of problems of the same grid
+// (blockIdx.z picks the problem's arguments and partials).
+template <int EPI, int KZ, int TX, int TY, bool PF, typename T>
+__global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(PF ? 1 : 3))) void ku_hada_kernel(
+    KuArgsT<T> a, HadaW<T> hw, int tiles_x, int tiles_xy, double *partials) {
+  ku_hada_body<EPI, KZ, TX, TY, PF, T>(a, hw, tiles_x, tiles_xy, partials);
+}
+template <int EPI, int KZ, int TX, int TY, bool PF, typename T>
+__global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(PF ? 1 : 3))) void ku_hada_group_kernel(
+    GroupTab<KuArgsT<T>> t, GroupTab<double *> part, HadaW<T> hw, int tiles_x, int tiles_xy) {
+  ku_hada_body<EPI, KZ, TX, TY, PF, T>(t.v[blockIdx.z], hw, tiles_x, tiles_xy, part.v[blockIdx.z]);
+}
+template <int EPI, int KZ, int TX, int TY, typename T>
+__global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(3))) void ku_hada_lds_kernel(
+    KuArgsT<T> a, HadaW<T> hw, int tiles_x, int tiles_xy, double *partials) {
+  ku_hada_lds_body<EPI, KZ, TX, TY, T>(a, hw, tiles_x, tiles_xy, partials);
+}
+template <int EPI, int KZ, int TX, int TY, typename T>
+__global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(3))) void ku_hada_lds_group_kernel(
+    GroupTab<KuArgsT<T>> t, GroupTab<double *> part, HadaW<T> hw, int tiles_x, int tiles_xy) {
+  ku_hada_lds_body<EPI, KZ, TX, TY, T>(t.v[blockIdx.z], hw, tiles_x, tiles_xy, part.v[blockIdx.z]);
+}
+
 template <int KZ, int TX, int TY>
 struct HadaShape {
   static int tiles_x(const Grid &g) { return (g.NX() + TX - 2) / (TX - 1); }
@@ -429,6 +452,45 @@ static hipError_t launch_hada_shape(hipStream_t s, KuEpi epi, const KuArgsT<T> &
   return hipGetLastError();
 }
 
+template <int KZ, int TX, int TY, int VAR, typename T>
+static hipError_t launch_hada_shape_group(hipStream_t s, KuEpi epi, int G, const KuArgsT<T> *a,
+                                          const KappaT<T> &kap, const Reducer *red, int *nparts_out) {
+  using S = HadaShape<KZ, TX, TY>;
+  const int tx = S::tiles_x(a[0].g), txy = tx * S::tiles_y(a[0].g);
+  const int64_t nb = S::blocks(a[0].g);
+  if (nb > INT32_MAX) return hipErrorInvalidValue;
+  *nparts_out = (int)nb;
+  GroupTab<KuArgsT<T>> t{};
+  GroupTab<double *> part{};
+  for (int i = 0; i < G; ++i) {
+    if (a[i].g.nx != a[0].g.nx || a[i].g.ny != a[0].g.ny || a[i].g.nz != a[0].g.nz) return hipErrorInvalidValue;
+    if (ku_reduces(epi, a[i]) && nb > red[i].max_blocks) return hipErrorInvalidValue;
+    t.v[i] = a[i];
+    part.v[i] = red[i].partials;
+  }
+  const HadaW<T> hw = hada_work(kap);
+  const dim3 grid((unsigned)nb, 1, (unsigned)G);
+#define TOPO_KU_CASE(E)                                                                             \
+  case E:                                                                                           \
+    if constexpr (VAR == 2)                                                                         \
+      ku_hada_lds_group_kernel<E, KZ, TX, TY, T><<<grid, TX * TY, 0, s>>>(t, part, hw, tx, txy);    \
+    else                                                                                            \
+      ku_hada_group_kernel<E, KZ, TX, TY, VAR == 1, T><<<grid, TX * TY, 0, s>>>(t, part, hw, tx, txy); \
+    break;
+  switch (epi) {
+    TOPO_KU_CASE(KU_STORE_DOT)
+    TOPO_KU_CASE(KU_RES0)
+    TOPO_KU_CASE(KU_CHEB0)
+    TOPO_KU_CASE(KU_CHEB)
+    TOPO_KU_CASE(KU_CHEB_ADD)
+    TOPO_KU_CASE(KU_RESUPD)
+    TOPO_KU_CASE(KU_RESID_START)
+    default: return hipErrorInvalidValue;
+  }
+#undef TOPO_KU_CASE
+  return hipGetLastError();
+}
+
 // element-column shapes (index relative to kKuShapeHada): KZ x TX x TY, and
 // how node planes are loaded (VAR above).  Every shape runs the same arithmetic
 // in the same order (a node always sums its four element columns in the same
@@ -460,6 +522,23 @@ template hipError_t launch_ku_hada<double>(hipStream_t, KuEpi, const KuArgsT<dou
                                            const KappaT<double> &, const Reducer &, int, int *);
 template hipError_t launch_ku_hada<float>(hipStream_t, KuEpi, const KuArgsT<float> &,
                                           const KappaT<float> &, const Reducer &, int, int *);
+
+template <typename T>
+hipError_t launch_ku_hada_group(hipStream_t s, KuEpi epi, int G, const KuArgsT<T> *a, const KappaT<T> &kap,
+                                const Reducer *red, int which, int *nparts) {
+  switch (which) {
+#define TOPO_HADA_LAUNCH(I, KZ, TX, TY, VAR) \
+  case I: return launch_hada_shape_group<KZ, TX, TY, VAR>(s, epi, G, a, kap, red, nparts);
+    TOPO_HADA_SHAPES(TOPO_HADA_LAUNCH)
+#undef TOPO_HADA_LAUNCH
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template hipError_t launch_ku_hada_group<double>(hipStream_t, KuEpi, int, const KuArgsT<double> *,
+                                                 const KappaT<double> &, const Reducer *, int, int *);
+template hipError_t launch_ku_hada_group<float>(hipStream_t, KuEpi, int, const KuArgsT<float> *,
+                                                const KappaT<float> &, const Reducer *, int, int *);
 
 int64_t ku_hada_max_blocks(const Grid &g) {
   int64_t m = 0;

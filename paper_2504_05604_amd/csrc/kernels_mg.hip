@@ -19,9 +19,9 @@ inline unsigned nblocks(int64_t n) { return (unsigned)((n + kBs - 1) / kBs); }
 // Branch-free: a neighbour outside the fine grid is read at a clamped (valid)
 // index with weight 0, which adds an exact zero.
 template <typename T>
-__global__ void restrict_kernel(Grid gf, Grid gc, const T *__restrict__ rf,
-                                const uint8_t *__restrict__ fixc, T *__restrict__ rc,
-                                const int *skip) {
+__device__ __forceinline__ void restrict_body(const Grid &gf, const Grid &gc, const T *__restrict__ rf,
+                                              const uint8_t *__restrict__ fixc, T *__restrict__ rc,
+                                              const int *skip) {
   if (skip && *skip) return;
   const int m = (int)(blockIdx.x * blockDim.x + threadIdx.x);
   if (m >= (int)gc.nnodes()) return;
@@ -61,6 +61,17 @@ __global__ void restrict_kernel(Grid gf, Grid gc, const T *__restrict__ rf,
   rc[3 * (int64_t)m + 2] = (f & 4) ? T(0) : s2;
 }
 
+template <typename T>
+__global__ void restrict_kernel(Grid gf, Grid gc, const T *__restrict__ rf, const uint8_t *__restrict__ fixc,
+                                T *__restrict__ rc, const int *skip) {
+  restrict_body<T>(gf, gc, rf, fixc, rc, skip);
+}
+template <typename T>
+__global__ void restrict_group_kernel(Grid gf, Grid gc, GroupTab<TransferArgs<T>> t) {
+  const TransferArgs<T> &a = t.v[blockIdx.z];
+  restrict_body<T>(gf, gc, a.in, a.fixed, a.out, a.skip);
+}
+
 hipError_t launch_restrict(hipStream_t s, Grid gf, Grid gc, const double *rf, const uint8_t *fixc,
                            double *rc, const int *skip) {
   if (gf.nnodes() >= INT32_MAX) return hipErrorInvalidValue;
@@ -80,9 +91,9 @@ hipError_t launch_restrict(hipStream_t s, Grid gf, Grid gc, const float *rf, con
 // candidate coarse values are always read (clamped), the unused ones with a 0
 // multiplier, which adds an exact zero to the sum.
 template <typename T>
-__global__ void prolong_add_kernel(Grid gf, Grid gc, const T *__restrict__ ec,
-                                   const uint8_t *__restrict__ fixf, T *__restrict__ xf,
-                                   const int *skip) {
+__device__ __forceinline__ void prolong_add_body(const Grid &gf, const Grid &gc, const T *__restrict__ ec,
+                                                 const uint8_t *__restrict__ fixf, T *__restrict__ xf,
+                                                 const int *skip) {
   if (skip && *skip) return;
   const int n = (int)(blockIdx.x * blockDim.x + threadIdx.x);
   if (n >= (int)gf.nnodes()) return;
@@ -116,6 +127,17 @@ __global__ void prolong_add_kernel(Grid gf, Grid gc, const T *__restrict__ ec,
   xn[0] = (f & 1) ? x0 : fma(w, s0, x0);
   xn[1] = (f & 2) ? x1 : fma(w, s1, x1);
   xn[2] = (f & 4) ? x2 : fma(w, s2, x2);
+}
+
+template <typename T>
+__global__ void prolong_add_kernel(Grid gf, Grid gc, const T *__restrict__ ec, const uint8_t *__restrict__ fixf,
+                                   T *__restrict__ xf, const int *skip) {
+  prolong_add_body<T>(gf, gc, ec, fixf, xf, skip);
+}
+template <typename T>
+__global__ void prolong_add_group_kernel(Grid gf, Grid gc, GroupTab<TransferArgs<T>> t) {
+  const TransferArgs<T> &a = t.v[blockIdx.z];
+  prolong_add_body<T>(gf, gc, a.in, a.fixed, a.out, a.skip);
 }
 
 hipError_t launch_prolong_add(hipStream_t s, Grid gf, Grid gc, const double *ec,
@@ -425,7 +447,7 @@ hipError_t launch_dense_invert(hipStream_t s, int n, double *A, double *work) {
 // the result rounded once): the coarse operator is ill-conditioned, and an FP32
 // copy of its inverse loses percents of accuracy at a thousand dofs
 template <typename T>
-__global__ void dense_matvec_kernel(int n, const double *A, const T *x, T *y, const int *skip) {
+__device__ __forceinline__ void dense_matvec_body(int n, const double *A, const T *x, T *y, const int *skip) {
   if (skip && *skip) return;
   const int lane = threadIdx.x & 63;
   const int row = blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64;
@@ -447,6 +469,16 @@ __global__ void dense_matvec_kernel(int n, const double *A, const T *x, T *y, co
   if (lane == 0) y[row] = (T)t;
 }
 
+template <typename T>
+__global__ void dense_matvec_kernel(int n, const double *A, const T *x, T *y, const int *skip) {
+  dense_matvec_body<T>(n, A, x, y, skip);
+}
+template <typename T>
+__global__ void dense_matvec_group_kernel(int n, GroupTab<MatvecArgs<T>> t) {
+  const MatvecArgs<T> &a = t.v[blockIdx.z];
+  dense_matvec_body<T>(n, a.A, a.x, a.y, a.skip);
+}
+
 hipError_t launch_dense_matvec(hipStream_t s, int n, const double *A, const double *x, double *y,
                                const int *skip) {
   const int rows_per_block = kBs / 64;
@@ -459,5 +491,38 @@ hipError_t launch_dense_matvec(hipStream_t s, int n, const double *A, const floa
   dense_matvec_kernel<float><<<(unsigned)((n + rows_per_block - 1) / rows_per_block), kBs, 0, s>>>(n, A, x, y, skip);
   return hipGetLastError();
 }
+
+// grouped launchers: one launch for G problems of the same grids
+template <typename T>
+hipError_t launch_restrict_group(hipStream_t s, int G, Grid gf, Grid gc, const TransferArgs<T> *a) {
+  if (G < 1 || G > kMaxGroup || gf.nnodes() >= INT32_MAX) return hipErrorInvalidValue;
+  GroupTab<TransferArgs<T>> t{};
+  for (int i = 0; i < G; ++i) t.v[i] = a[i];
+  restrict_group_kernel<T><<<dim3(nblocks(gc.nnodes()), 1, G), kBs, 0, s>>>(gf, gc, t);
+  return hipGetLastError();
+}
+template <typename T>
+hipError_t launch_prolong_add_group(hipStream_t s, int G, Grid gf, Grid gc, const TransferArgs<T> *a) {
+  if (G < 1 || G > kMaxGroup || gf.nnodes() >= INT32_MAX) return hipErrorInvalidValue;
+  GroupTab<TransferArgs<T>> t{};
+  for (int i = 0; i < G; ++i) t.v[i] = a[i];
+  prolong_add_group_kernel<T><<<dim3(nblocks(gf.nnodes()), 1, G), kBs, 0, s>>>(gf, gc, t);
+  return hipGetLastError();
+}
+template <typename T>
+hipError_t launch_dense_matvec_group(hipStream_t s, int G, int n, const MatvecArgs<T> *a) {
+  if (G < 1 || G > kMaxGroup) return hipErrorInvalidValue;
+  GroupTab<MatvecArgs<T>> t{};
+  for (int i = 0; i < G; ++i) t.v[i] = a[i];
+  const int rows_per_block = kBs / 64;
+  dense_matvec_group_kernel<T><<<dim3((unsigned)((n + rows_per_block - 1) / rows_per_block), 1, G), kBs, 0, s>>>(n, t);
+  return hipGetLastError();
+}
+template hipError_t launch_restrict_group<double>(hipStream_t, int, Grid, Grid, const TransferArgs<double> *);
+template hipError_t launch_restrict_group<float>(hipStream_t, int, Grid, Grid, const TransferArgs<float> *);
+template hipError_t launch_prolong_add_group<double>(hipStream_t, int, Grid, Grid, const TransferArgs<double> *);
+template hipError_t launch_prolong_add_group<float>(hipStream_t, int, Grid, Grid, const TransferArgs<float> *);
+template hipError_t launch_dense_matvec_group<double>(hipStream_t, int, int, const MatvecArgs<double> *);
+template hipError_t launch_dense_matvec_group<float>(hipStream_t, int, int, const MatvecArgs<float> *);
 
 }  // namespace topo

@@ -68,8 +68,8 @@ hipError_t launch_copy_fixed(hipStream_t s, int64_t nnodes, const uint8_t *fixed
   return hipGetLastError();
 }
 
-__global__ void dot_kernel(int64_t n, const double *a, const double *b, double *partials,
-                           const int *skip) {
+__device__ __forceinline__ void dot_body(int64_t n, const double *a, const double *b, double *partials,
+                                         const int *skip) {
   if (skipped(skip)) return;
   double t = 0.0;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
@@ -77,6 +77,14 @@ __global__ void dot_kernel(int64_t n, const double *a, const double *b, double *
     t = fma(a[i], b[i], t);
   double v[1] = {t};
   block_reduce_store<1, false>(v, partials, blockIdx.x);
+}
+
+__global__ void dot_kernel(int64_t n, const double *a, const double *b, double *partials, const int *skip) {
+  dot_body(n, a, b, partials, skip);
+}
+__global__ void dot_group_kernel(int64_t n, GroupTab<DotArgs> t, GroupTab<double *> part) {
+  const DotArgs &a = t.v[blockIdx.z];
+  dot_body(n, a.a, a.b, part.v[blockIdx.z], a.skip);
 }
 
 hipError_t launch_dot(hipStream_t s, int64_t n, const double *a, const double *b, const Reducer &red,
@@ -89,9 +97,9 @@ hipError_t launch_dot(hipStream_t s, int64_t n, const double *a, const double *b
 
 // r32 (optional): the new residual rounded to FP32 as well, the right-hand side
 // of a single-precision preconditioner
-__global__ void cg_update_xr_kernel(int64_t n, const Scalars *sc, double *x, double *r,
-                                    const double *p, const double *q, float *r32, double *partials,
-                                    const int *skip) {
+__device__ __forceinline__ void cg_update_xr_body(int64_t n, const Scalars *sc, double *x, double *r,
+                                                  const double *p, const double *q, float *r32,
+                                                  double *partials, const int *skip) {
   if (skipped(skip)) return;
   const double alpha = sc->rz / sc->pq;
   double t = 0.0;
@@ -105,6 +113,15 @@ __global__ void cg_update_xr_kernel(int64_t n, const Scalars *sc, double *x, dou
   }
   double v[1] = {t};
   block_reduce_store<1, false>(v, partials, blockIdx.x);
+}
+
+__global__ void cg_update_xr_kernel(int64_t n, const Scalars *sc, double *x, double *r, const double *p,
+                                    const double *q, float *r32, double *partials, const int *skip) {
+  cg_update_xr_body(n, sc, x, r, p, q, r32, partials, skip);
+}
+__global__ void cg_update_xr_group_kernel(int64_t n, GroupTab<XrArgs> t, GroupTab<double *> part) {
+  const XrArgs &a = t.v[blockIdx.z];
+  cg_update_xr_body(n, a.sc, a.x, a.r, a.p, a.q, a.r32, part.v[blockIdx.z], a.skip);
 }
 
 hipError_t launch_cg_update_xr(hipStream_t s, int64_t n, Scalars *sc, double *x, double *r,
@@ -155,8 +172,8 @@ hipError_t launch_jacobi(hipStream_t s, int64_t n, const double *r, const double
 // p = z + beta p; z in double, or in single precision (the output of a
 // single-precision preconditioner, widened exactly)
 template <typename Z>
-__global__ void cg_update_p_kernel(int64_t n, const Scalars *sc, const Z *z, double *p, int first,
-                                   const int *skip) {
+__device__ __forceinline__ void cg_update_p_body(int64_t n, const Scalars *sc, const Z *z, double *p, int first,
+                                                 const int *skip) {
   if (skipped(skip)) return;
   const double beta = first ? 0.0 : sc->beta;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
@@ -164,6 +181,17 @@ __global__ void cg_update_p_kernel(int64_t n, const Scalars *sc, const Z *z, dou
     const double zi = (double)z[i];
     p[i] = first ? zi : fma(beta, p[i], zi);
   }
+}
+
+template <typename Z>
+__global__ void cg_update_p_kernel(int64_t n, const Scalars *sc, const Z *z, double *p, int first,
+                                   const int *skip) {
+  cg_update_p_body<Z>(n, sc, z, p, first, skip);
+}
+template <typename Z>
+__global__ void cg_update_p_group_kernel(int64_t n, GroupTab<PArgs> t, int first) {
+  const PArgs &a = t.v[blockIdx.z];
+  cg_update_p_body<Z>(n, a.sc, static_cast<const Z *>(a.z), a.p, first, a.skip);
 }
 
 hipError_t launch_cg_update_p(hipStream_t s, int64_t n, Scalars *sc, const double *z, double *p,
@@ -202,14 +230,25 @@ hipError_t launch_cheb_first(hipStream_t s, int64_t n, const float *r, const flo
 }
 
 template <typename T>
-__global__ void cheb_start_kernel(int64_t n, const T *res, const T *dinv, T inv_theta, T *d, T *x,
-                                  const int *skip) {
+__device__ __forceinline__ void cheb_start_body(int64_t n, const T *res, const T *dinv, T inv_theta, T *d, T *x,
+                                                const int *skip) {
   if (skipped(skip)) return;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const T di = res[i] * dinv[i] * inv_theta;
   d[i] = di;
   x[i] += di;
+}
+
+template <typename T>
+__global__ void cheb_start_kernel(int64_t n, const T *res, const T *dinv, T inv_theta, T *d, T *x,
+                                  const int *skip) {
+  cheb_start_body<T>(n, res, dinv, inv_theta, d, x, skip);
+}
+template <typename T>
+__global__ void cheb_start_group_kernel(int64_t n, T inv_theta, GroupTab<ChebStartArgs<T>> t) {
+  const ChebStartArgs<T> &a = t.v[blockIdx.z];
+  cheb_start_body<T>(n, a.res, a.dinv, inv_theta, a.d, a.x, a.skip);
 }
 
 hipError_t launch_cheb_start(hipStream_t s, int64_t n, const double *res, const double *dinv,
@@ -246,9 +285,9 @@ hipError_t launch_convert(hipStream_t s, int64_t n, const float *in, double *out
 // double.  With res and dinv given, the new z is first the finest level's last
 // Chebyshev update x + res dinv / theta (degree-1 smoothing), in the same
 // single-precision arithmetic as that update on its own.
-__global__ void flex_dot_kernel(int64_t n, const float *res, const float *dinv, float inv_theta,
-                                const float *x, const double *r, float *z, double *partials,
-                                const int *skip) {
+__device__ __forceinline__ void flex_dot_body(int64_t n, const float *res, const float *dinv, float inv_theta,
+                                              const float *x, const double *r, float *z, double *partials,
+                                              const int *skip) {
   if (skipped(skip)) return;
   double tn = 0.0, to = 0.0;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
@@ -262,6 +301,15 @@ __global__ void flex_dot_kernel(int64_t n, const float *res, const float *dinv, 
   }
   double v[2] = {tn, to};
   block_reduce_store<2, false>(v, partials, blockIdx.x);
+}
+
+__global__ void flex_dot_kernel(int64_t n, const float *res, const float *dinv, float inv_theta, const float *x,
+                                const double *r, float *z, double *partials, const int *skip) {
+  flex_dot_body(n, res, dinv, inv_theta, x, r, z, partials, skip);
+}
+__global__ void flex_dot_group_kernel(int64_t n, float inv_theta, GroupTab<FlexArgs> t, GroupTab<double *> part) {
+  const FlexArgs &a = t.v[blockIdx.z];
+  flex_dot_body(n, a.res, a.dinv, inv_theta, a.x, a.r, a.z, part.v[blockIdx.z], a.skip);
 }
 
 hipError_t launch_flex_dot(hipStream_t s, int64_t n, const float *res, const float *dinv, float inv_theta,
@@ -313,5 +361,78 @@ hipError_t launch_combine(hipStream_t s, int64_t n, int nv, const double *const 
   combine_kernel<<<nblocks(n), kBs, 0, s>>>(n, c, u);
   return hipGetLastError();
 }
+
+// ---------------------------------------------------------------------------
+// grouped launchers (one launch for G problems of equal size; see internal.h)
+namespace {
+template <class A>
+GroupTab<A> group_tab(int G, const A *a) {
+  GroupTab<A> t{};
+  for (int i = 0; i < G; ++i) t.v[i] = a[i];
+  return t;
+}
+GroupTab<double *> group_partials(int G, const Reducer *red) {
+  GroupTab<double *> t{};
+  for (int i = 0; i < G; ++i) t.v[i] = red[i].partials;
+  return t;
+}
+template <class A>
+GroupTab<const int *> group_skips(int G, const A *a) {
+  GroupTab<const int *> t{};
+  for (int i = 0; i < G; ++i) t.v[i] = a[i].skip;
+  return t;
+}
+bool group_ok(int G) { return G >= 1 && G <= kMaxGroup; }
+}  // namespace
+
+hipError_t launch_dot_group(hipStream_t s, int G, int64_t n, const DotArgs *a, const Reducer *red, const Fin *fin) {
+  if (!group_ok(G)) return hipErrorInvalidValue;
+  const unsigned nb = red_blocks(n, red[0]);
+  dot_group_kernel<<<dim3(nb, 1, G), kBs, 0, s>>>(n, group_tab(G, a), group_partials(G, red));
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const GroupTab<const int *> sk = group_skips(G, a);
+  return launch_finalize_group(s, G, red, (int)nb, 1, fin, sk.v);
+}
+
+hipError_t launch_cg_update_xr_group(hipStream_t s, int G, int64_t n, const XrArgs *a, const Reducer *red,
+                                     const Fin *fin) {
+  if (!group_ok(G)) return hipErrorInvalidValue;
+  const unsigned nb = red_blocks(n, red[0]);
+  cg_update_xr_group_kernel<<<dim3(nb, 1, G), kBs, 0, s>>>(n, group_tab(G, a), group_partials(G, red));
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const GroupTab<const int *> sk = group_skips(G, a);
+  return launch_finalize_group(s, G, red, (int)nb, 1, fin, sk.v);
+}
+
+hipError_t launch_cg_update_p_group(hipStream_t s, int G, int64_t n, bool zsingle, const PArgs *a, int first) {
+  if (!group_ok(G)) return hipErrorInvalidValue;
+  if (zsingle)
+    cg_update_p_group_kernel<float><<<dim3(nblocks(n, 4), 1, G), kBs, 0, s>>>(n, group_tab(G, a), first);
+  else
+    cg_update_p_group_kernel<double><<<dim3(nblocks(n, 4), 1, G), kBs, 0, s>>>(n, group_tab(G, a), first);
+  return hipGetLastError();
+}
+
+hipError_t launch_flex_dot_group(hipStream_t s, int G, int64_t n, float inv_theta, const FlexArgs *a,
+                                 const Reducer *red, const Fin *fin) {
+  if (!group_ok(G)) return hipErrorInvalidValue;
+  const unsigned nb = red_blocks(n, red[0]);
+  flex_dot_group_kernel<<<dim3(nb, 1, G), kBs, 0, s>>>(n, inv_theta, group_tab(G, a), group_partials(G, red));
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const GroupTab<const int *> sk = group_skips(G, a);
+  return launch_finalize_group(s, G, red, (int)nb, 2, fin, sk.v);
+}
+
+template <typename T>
+hipError_t launch_cheb_start_group(hipStream_t s, int G, int64_t n, T inv_theta, const ChebStartArgs<T> *a) {
+  if (!group_ok(G)) return hipErrorInvalidValue;
+  cheb_start_group_kernel<T><<<dim3(nblocks(n), 1, G), kBs, 0, s>>>(n, inv_theta, group_tab(G, a));
+  return hipGetLastError();
+}
+template hipError_t launch_cheb_start_group<double>(hipStream_t, int, int64_t, double, const ChebStartArgs<double> *);
+template hipError_t launch_cheb_start_group<float>(hipStream_t, int, int64_t, float, const ChebStartArgs<float> *);
 
 }  // namespace topo

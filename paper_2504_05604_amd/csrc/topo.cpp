@@ -10,6 +10,7 @@
 #include <cstdio>
 #include <cstring>
 #include <memory>
+#include <string>
 #include <type_traits>
 #include <vector>
 
@@ -279,6 +280,8 @@ extern "C" void topo_default_opts(topo_opts *o) {
   o->ku_kernel = TOPO_KU_AUTO;
   o->ku_shape = -1;
   o->coarse_refresh = 1;
+  for (int l = 0; l < 8; ++l) o->cheb_degree_level[l] = 0;
+  o->group_launch = 1;
 }
 
 extern "C" const char *topo_last_error(void) { return g_err; }
@@ -339,6 +342,7 @@ static topo_status validate(const topo_problem *P, const topo_opts *O) {
   if (O->coarse_tail_nodes < 0) return set_error("coarse_tail_nodes must be >= 0"), TOPO_EINVAL;
   if (O->warm_start < 0 || O->warm_start > 3) return set_error("warm_start must be 0, 1, 2 or 3"), TOPO_EINVAL;
   if (O->coarse_refresh < 1) return set_error("coarse_refresh must be >= 1"), TOPO_EINVAL;
+  if (O->group_launch != 0 && O->group_launch != 1) return set_error("group_launch must be 0 or 1"), TOPO_EINVAL;
   for (int l = 0; l < 8; ++l)
     if (O->cheb_degree_level[l] < 0 || O->cheb_degree_level[l] > 16)
       return set_error("cheb_degree_level[%d] must lie in [0, 16]", l), TOPO_EINVAL;
@@ -1241,6 +1245,384 @@ static topo_status pcg(topo_ctx *ctx, topo_solve_stats *stats) {
   return TOPO_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Grouped CG: the contexts of a group (at most kMaxGroup, built with the same
+// options on grids of the same size, so their hierarchies, launch shapes and
+// smoother polynomials coincide) share one stream, and every pass of their CG
+// iterations -- the operator product, the vector updates, every smoothing
+// pass, transfer and coarse solve of the V-cycle, every finalize -- is one
+// launch for all of them.  Each problem's blocks compute exactly what its own
+// launch computes (same partials, same order), so the results are
+// bit-identical to solving each problem alone; a converged problem's blocks
+// return at once (its cg_done flag).
+namespace topo {
+
+// whether a context can take part in grouped CG, and the key that must match
+std::string group_key(const topo_ctx *ctx) {
+  const topo_opts &o = ctx->opts;
+  if (o.precond != TOPO_PRECOND_MG || ctx->lv.size() < 2 || ctx->tail_start != 0) return "";
+  if (o.precision == TOPO_PREC_BF16 || o.mfma_smoothing) return "";
+  const bool is_hada = [&] {
+    auto el = [](int sh) { return sh >= kKuShapeHada && sh < kKuShapeHada + kKuShapesHada; };
+    if (!el(ctx->shape_cg)) return false;
+    for (const Level &L : ctx->lv)
+      if (!el(L.shape)) return false;
+    return true;
+  }();
+  if (!is_hada) return "";
+  std::string k = std::to_string(ctx->prob.nu) + "|" + std::to_string(ctx->mixed) + "|" + std::to_string(ctx->shape_cg);
+  for (size_t l = 0; l < ctx->lv.size(); ++l) {
+    const Level &L = ctx->lv[l];
+    k += "|" + std::to_string(L.g.nx) + "x" + std::to_string(L.g.ny) + "x" + std::to_string(L.g.nz) + "s" +
+         std::to_string(L.shape) + "d" + std::to_string(level_degree(ctx, l));
+  }
+  return k;
+}
+
+// the launch shapes of src (same grids) for dst: every shape computes the same
+// products, so this changes at most the rounding of reductions
+void group_adopt_shapes(topo_ctx *dst, const topo_ctx *src) {
+  if (dst->lv.size() != src->lv.size()) return;
+  dst->shape_cg = src->shape_cg;
+  for (size_t l = 0; l < dst->lv.size(); ++l) dst->lv[l].shape = src->lv[l].shape;
+}
+void ctx_set_stream(topo_ctx *ctx, hipStream_t s) { ctx->stream = s; }
+Grid ctx_grid(const topo_ctx *ctx) { return ctx->g; }
+
+static std::vector<Reducer> group_reds(const Group &G) {
+  std::vector<Reducer> r;
+  for (topo_ctx *c : G.c) r.push_back(c->red);
+  return r;
+}
+
+template <typename T>
+static topo_status group_pre_smooth(const Group &G, size_t l) {
+  const int n = G.n();
+  topo_ctx *c0 = G.c[0];
+  const int deg = level_degree(c0, l);
+  const Cheb ch(c0->lam_max);
+  const KappaT<T> &kap = kappa_of<T>(c0);
+  const std::vector<Reducer> red = group_reds(G);
+  const std::vector<Fin> fin(n, fin_sum(nullptr));
+  const int shape = c0->lv[l].shape;
+  std::vector<KuArgsT<T>> a(n);
+  std::vector<T *> dcur(n), dnext(n);
+  for (int i = 0; i < n; ++i) {
+    Level &L = G.c[i]->lv[l];
+    const LevelBufs<T> B = bufs<T>(L);
+    dcur[i] = B.d0;
+    dnext[i] = B.d1;
+    a[i] = ku_args_t<T>(L, nullptr);
+    a[i].b = B.b;
+    a[i].res = B.res;
+    a[i].x = B.x;
+    a[i].s0 = (T)(1.0 / ch.theta);
+    a[i].skip = &G.c[i]->sc->cg_done;
+  }
+  if (deg == 1) {
+    TOPO_HIP(launch_ku_group<T>(G.s, KU_RES0, n, a.data(), kap, red.data(), fin.data(), shape));
+    return TOPO_OK;
+  }
+  double rho = 1.0 / ch.sigma;
+  double rho_new = 1.0 / (2.0 * ch.sigma - rho);
+  for (int i = 0; i < n; ++i) {
+    a[i].dout = dcur[i];
+    a[i].c1 = (T)(rho_new * rho);
+    a[i].c2 = (T)(2.0 * rho_new / ch.delta);
+  }
+  TOPO_HIP(launch_ku_group<T>(G.s, KU_CHEB0, n, a.data(), kap, red.data(), fin.data(), shape));
+  rho = rho_new;
+  for (int k = 2; k < deg; ++k) {
+    rho_new = 1.0 / (2.0 * ch.sigma - rho);
+    for (int i = 0; i < n; ++i) {
+      Level &L = G.c[i]->lv[l];
+      const LevelBufs<T> B = bufs<T>(L);
+      KuArgsT<T> c = ku_args_t<T>(L, dcur[i]);
+      c.res = B.res;
+      c.x = B.x;
+      c.dout = dnext[i];
+      c.c1 = (T)(rho_new * rho);
+      c.c2 = (T)(2.0 * rho_new / ch.delta);
+      c.skip = &G.c[i]->sc->cg_done;
+      a[i] = c;
+      std::swap(dcur[i], dnext[i]);
+    }
+    TOPO_HIP(launch_ku_group<T>(G.s, KU_CHEB, n, a.data(), kap, red.data(), fin.data(), shape));
+    rho = rho_new;
+  }
+  for (int i = 0; i < n; ++i) {
+    Level &L = G.c[i]->lv[l];
+    KuArgsT<T> r = ku_args_t<T>(L, dcur[i]);
+    r.res = bufs<T>(L).res;
+    r.skip = &G.c[i]->sc->cg_done;
+    a[i] = r;
+  }
+  TOPO_HIP(launch_ku_group<T>(G.s, KU_RESUPD, n, a.data(), kap, red.data(), fin.data(), shape));
+  return TOPO_OK;
+}
+
+// post-smoothing; on the finest level the result goes to CG: in single
+// precision through flex_dot into z32 (flexible update), in double with the
+// r.z reduction of the last pass (FIN_RZ)
+template <typename T>
+static topo_status group_post_smooth(const Group &G, size_t l, bool finest) {
+  const int n = G.n();
+  topo_ctx *c0 = G.c[0];
+  const int deg = level_degree(c0, l);
+  const Cheb ch(c0->lam_max);
+  const KappaT<T> &kap = kappa_of<T>(c0);
+  const std::vector<Reducer> red = group_reds(G);
+  constexpr bool single = std::is_same<T, float>::value;
+  std::vector<Fin> fin(n, fin_sum(nullptr));
+  if (finest && !single)
+    for (int i = 0; i < n; ++i) fin[i] = Fin{FIN_RZ, &G.c[i]->sc->rz_new, G.c[i]->sc};
+  std::vector<Fin> flexfin(n);
+  for (int i = 0; i < n; ++i) flexfin[i] = Fin{FIN_RZ_FLEX, &G.c[i]->sc->red[0], G.c[i]->sc};
+  const int shape = c0->lv[l].shape;
+  std::vector<KuArgsT<T>> a(n);
+  std::vector<T *> dcur(n), dnext(n);
+  const bool fused_last = single && deg == 1 && finest;
+  for (int i = 0; i < n; ++i) {
+    Level &L = G.c[i]->lv[l];
+    const LevelBufs<T> B = bufs<T>(L);
+    dcur[i] = B.d0;
+    dnext[i] = B.d1;
+    a[i] = ku_args_t<T>(L, B.x);
+    a[i].b = B.b;
+    a[i].res = B.res;
+    a[i].dout = fused_last ? nullptr : dcur[i];
+    a[i].s0 = (T)(1.0 / ch.theta);
+    a[i].skip = &G.c[i]->sc->cg_done;
+  }
+  TOPO_HIP(launch_ku_group<T>(G.s, KU_RESID_START, n, a.data(), kap, red.data(), fin.data(), shape));
+  const int64_t nd = c0->lv[l].g.ndof();
+  if (deg == 1) {
+    if constexpr (single) {
+      if (finest) {
+        std::vector<FlexArgs> f(n);
+        for (int i = 0; i < n; ++i) {
+          const LevelBufs<float> B = bufs<float>(G.c[i]->lv[l]);
+          f[i] = FlexArgs{B.res, B.dinv, B.x, G.c[i]->r, G.c[i]->z32, &G.c[i]->sc->cg_done};
+        }
+        TOPO_HIP(launch_flex_dot_group(G.s, n, nd, (float)(1.0 / ch.theta), f.data(), red.data(), flexfin.data()));
+        return TOPO_OK;
+      }
+    }
+    std::vector<ChebStartArgs<T>> cs(n);
+    for (int i = 0; i < n; ++i) {
+      const LevelBufs<T> B = bufs<T>(G.c[i]->lv[l]);
+      cs[i] = ChebStartArgs<T>{B.res, B.dinv, dnext[i], B.x, &G.c[i]->sc->cg_done};
+    }
+    TOPO_HIP(launch_cheb_start_group<T>(G.s, n, nd, (T)(1.0 / ch.theta), cs.data()));
+    if constexpr (!single) {
+      if (finest) {
+        std::vector<DotArgs> d(n);
+        for (int i = 0; i < n; ++i)
+          d[i] = DotArgs{G.c[i]->lv[l].b, G.c[i]->lv[l].x, &G.c[i]->sc->cg_done};
+        TOPO_HIP(launch_dot_group(G.s, n, nd, d.data(), red.data(), fin.data()));
+      }
+    }
+    return TOPO_OK;
+  }
+  double rho = 1.0 / ch.sigma;
+  for (int k = 1; k < deg; ++k) {
+    const double rho_new = 1.0 / (2.0 * ch.sigma - rho);
+    for (int i = 0; i < n; ++i) {
+      Level &L = G.c[i]->lv[l];
+      const LevelBufs<T> B = bufs<T>(L);
+      KuArgsT<T> c = ku_args_t<T>(L, dcur[i]);
+      c.res = B.res;
+      c.x = B.x;
+      c.dout = dnext[i];
+      c.c1 = (T)(rho_new * rho);
+      c.c2 = (T)(2.0 * rho_new / ch.delta);
+      c.dot_with = (k == deg - 1 && finest && !single) ? (const T *)B.b : nullptr;
+      if (k == deg - 1) c.dout = nullptr;
+      c.skip = &G.c[i]->sc->cg_done;
+      a[i] = c;
+      std::swap(dcur[i], dnext[i]);
+    }
+    TOPO_HIP(launch_ku_group<T>(G.s, k == 1 ? KU_CHEB_ADD : KU_CHEB, n, a.data(), kap, red.data(), fin.data(),
+                                shape));
+    rho = rho_new;
+  }
+  if constexpr (single) {
+    if (finest) {
+      std::vector<FlexArgs> f(n);
+      for (int i = 0; i < n; ++i) {
+        const LevelBufs<float> B = bufs<float>(G.c[i]->lv[l]);
+        f[i] = FlexArgs{nullptr, nullptr, B.x, G.c[i]->r, G.c[i]->z32, &G.c[i]->sc->cg_done};
+      }
+      TOPO_HIP(launch_flex_dot_group(G.s, n, nd, 0.f, f.data(), red.data(), flexfin.data()));
+    }
+  }
+  return TOPO_OK;
+}
+
+template <typename T>
+static topo_status group_vcycle(const Group &G, size_t l) {
+  const int n = G.n();
+  topo_ctx *c0 = G.c[0];
+  if (l + 1 == c0->lv.size()) {
+    std::vector<MatvecArgs<T>> m(n);
+    for (int i = 0; i < n; ++i) {
+      const LevelBufs<T> B = bufs<T>(G.c[i]->lv[l]);
+      m[i] = MatvecArgs<T>{G.c[i]->Ainv, B.b, B.x, &G.c[i]->sc->cg_done};
+    }
+    TOPO_HIP(launch_dense_matvec_group<T>(G.s, n, c0->ncoarse, m.data()));
+    return TOPO_OK;
+  }
+  topo_status st = group_pre_smooth<T>(G, l);
+  if (st != TOPO_OK) return st;
+  std::vector<TransferArgs<T>> t(n);
+  for (int i = 0; i < n; ++i) {
+    Level &L = G.c[i]->lv[l], &C = G.c[i]->lv[l + 1];
+    t[i] = TransferArgs<T>{bufs<T>(L).res, C.fixed, bufs<T>(C).b, &G.c[i]->sc->cg_done};
+  }
+  TOPO_HIP(launch_restrict_group<T>(G.s, n, c0->lv[l].g, c0->lv[l + 1].g, t.data()));
+  st = group_vcycle<T>(G, l + 1);
+  if (st != TOPO_OK) return st;
+  for (int i = 0; i < n; ++i) {
+    Level &L = G.c[i]->lv[l], &C = G.c[i]->lv[l + 1];
+    t[i] = TransferArgs<T>{bufs<T>(C).x, L.fixed, bufs<T>(L).x, &G.c[i]->sc->cg_done};
+  }
+  TOPO_HIP(launch_prolong_add_group<T>(G.s, n, c0->lv[l].g, c0->lv[l + 1].g, t.data()));
+  return group_post_smooth<T>(G, l, l == 0);
+}
+
+static topo_status group_update_p(const Group &G, int first) {
+  const int n = G.n();
+  const bool zs = G.c[0]->mixed;
+  std::vector<PArgs> a(n);
+  for (int i = 0; i < n; ++i)
+    a[i] = PArgs{G.c[i]->sc, zs ? (const void *)G.c[i]->z32 : (const void *)G.c[i]->z, G.c[i]->p,
+                 &G.c[i]->sc->cg_done};
+  TOPO_HIP(launch_cg_update_p_group(G.s, n, G.c[0]->ndof, zs, a.data(), first));
+  return TOPO_OK;
+}
+
+static topo_status group_precondition(const Group &G) {
+  return G.c[0]->mixed ? group_vcycle<float>(G, 0) : group_vcycle<double>(G, 0);
+}
+
+// one CG iteration of every problem of the group (the multigrid preconditioner)
+static topo_status group_cg_body(const Group &G) {
+  const int n = G.n();
+  topo_ctx *c0 = G.c[0];
+  const std::vector<Reducer> red = group_reds(G);
+  std::vector<KuArgs> a(n);
+  std::vector<Fin> fpq(n), fchk(n);
+  std::vector<XrArgs> xr(n);
+  for (int i = 0; i < n; ++i) {
+    topo_ctx *c = G.c[i];
+    a[i] = ku_args(c, c->lv[0], c->p);
+    a[i].y = c->q;
+    a[i].skip = &c->sc->cg_done;
+    fpq[i] = fin_sum(&c->sc->pq);
+    fchk[i] = Fin{FIN_CG_CHECK, &c->sc->rr, c->sc};
+    xr[i] = XrArgs{c->sc, c->u, c->r, c->p, c->q, c->mixed ? c->lv[0].f32.b : nullptr, &c->sc->cg_done};
+  }
+  TOPO_HIP(launch_ku_group<double>(G.s, KU_STORE_DOT, n, a.data(), c0->kap, red.data(), fpq.data(), c0->shape_cg));
+  TOPO_HIP(launch_cg_update_xr_group(G.s, n, c0->ndof, xr.data(), red.data(), fchk.data()));
+  topo_status st = group_precondition(G);
+  if (st != TOPO_OK) return st;
+  return group_update_p(G, 0);
+}
+
+// the scalars of every problem of the group into their pinned mirrors, one wait
+static topo_status group_read_scalars(const Group &G) {
+  for (topo_ctx *c : G.c)
+    TOPO_HIP(hipMemcpyAsync(c->h_sc, c->sc, sizeof(Scalars), hipMemcpyDeviceToHost, G.s));
+  TOPO_HIP(hipStreamSynchronize(G.s));
+  return TOPO_OK;
+}
+
+// Multigrid-preconditioned (flexible in mixed precision) CG of every problem
+// of the group from its own u, to its own tolerance: the per-problem set-up,
+// then grouped chunks of check_every iterations (captured once as a graph when
+// the contexts use graphs) until every problem has converged.
+topo_status group_pcg(Group &G, hipGraph_t *graph_out, hipGraphExec_t *exec, hipStream_t cap_stream,
+                      topo_solve_stats *stats) {
+  const int n = G.n();
+  for (topo_ctx *c : G.c) {
+    if (c->stream != G.s) return set_error("grouped CG: the contexts must use the group's stream"), TOPO_EINVAL;
+    const int64_t nd = c->ndof;
+    Level &L0 = c->lv[0];
+    TOPO_HIP(launch_zero_fixed(G.s, c->nnodes, L0.fixed, c->u));
+    KuArgs a = ku_args(c, L0, c->u);
+    a.y = c->r;
+    a.b = c->f;
+    TOPO_HIP(launch_ku(G.s, KU_RESID, a, c->kap, c->red, fin_sum(&c->sc->rr)));
+    TOPO_HIP(launch_dot(G.s, nd, c->f, c->f, c->red, fin_sum(&c->sc->ff)));
+    TOPO_HIP(launch_cg_start(G.s, c->sc, c->opts.rtol * c->opts.rtol, c->opts.max_iters));
+    if (c->mixed) {
+      TOPO_HIP(hipMemsetAsync(c->z32, 0, nd * sizeof(float), G.s));
+      TOPO_HIP(launch_convert(G.s, nd, c->r, L0.f32.b, &c->sc->cg_done));
+    }
+  }
+  topo_status st = group_precondition(G);
+  if (st != TOPO_OK) return st;
+  st = group_update_p(G, 1);
+  if (st != TOPO_OK) return st;
+  const int chunk = std::max(1, G.c[0]->opts.check_every);
+  const bool graphs = G.c[0]->opts.use_graphs && graph_out != nullptr && exec != nullptr && cap_stream != nullptr;
+  if (graphs && !*exec) {
+    Group cap = G;
+    cap.s = cap_stream;
+    TOPO_HIP(hipStreamBeginCapture(cap_stream, hipStreamCaptureModeRelaxed));
+    for (int k = 0; k < chunk && st == TOPO_OK; ++k) st = group_cg_body(cap);
+    hipGraph_t graph = nullptr;
+    const hipError_t ce = hipStreamEndCapture(cap_stream, &graph);
+    if (st != TOPO_OK) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return st;
+    }
+    TOPO_HIP(ce);
+    const hipError_t ie = hipGraphInstantiate(exec, graph, nullptr, nullptr, 0);
+    if (ie != hipSuccess) {
+      (void)hipGraphDestroy(graph);
+      *exec = nullptr;
+      TOPO_HIP(ie);
+    }
+    *graph_out = graph;
+  }
+  st = group_read_scalars(G);
+  if (st != TOPO_OK) return st;
+  for (;;) {
+    bool all = true;
+    for (topo_ctx *c : G.c) all = all && c->h_sc->cg_done;
+    if (all) break;
+    if (graphs) {
+      TOPO_HIP(hipGraphLaunch(*exec, G.s));
+    } else {
+      for (int k = 0; k < chunk; ++k) {
+        st = group_cg_body(G);
+        if (st != TOPO_OK) return st;
+      }
+    }
+    st = group_read_scalars(G);
+    if (st != TOPO_OK) return st;
+  }
+  topo_status result = TOPO_OK;
+  for (int i = 0; i < n; ++i) {
+    topo_ctx *c = G.c[i];
+    const double relres = std::sqrt(c->h_sc->rr / c->h_sc->ff);
+    if (stats) {
+      stats[i] = topo_solve_stats{};
+      stats[i].iters = c->h_sc->cg_iters;
+      stats[i].relres = relres;
+      stats[i].converged = relres <= c->opts.rtol;
+    }
+    if (!(relres <= c->opts.rtol)) {
+      set_error("CG of a grouped problem reached max_iters=%d with relres %.3e", c->opts.max_iters, relres);
+      result = TOPO_ENOTCONVERGED;
+    }
+  }
+  return result;
+}
+
+}  // namespace topo
+
 extern "C" topo_status topo_apply_K(topo_ctx *ctx, const double *d_xphys, const double *d_u, double *d_y) {
   if (!ctx || !d_xphys || !d_u || !d_y) return set_error("NULL argument"), TOPO_EINVAL;
   if (d_u == d_y) return set_error("d_u and d_y must not alias"), TOPO_EINVAL;
@@ -1364,93 +1746,113 @@ extern "C" topo_status topo_oc_update(topo_ctx *ctx, const double *d_x, const do
   return TOPO_OK;
 }
 
-extern "C" topo_status topo_iterate(topo_ctx *ctx, double *d_x, int32_t n_iter, topo_iter_stats *h_stats) {
-  if (!ctx || !d_x || n_iter < 0) return set_error("invalid argument"), TOPO_EINVAL;
+// One SIMP iteration in three parts (the solve in between), so that a batch
+// can solve the problems of a group together: iterate_pre runs the filter and
+// the operator set-up and forms the initial guess, iterate_post the
+// sensitivities, the filter adjoint and the OC update, and fills the stats.
+// ev: 6 events (phase boundaries).
+namespace topo {
+topo_status iterate_pre(topo_ctx *ctx, double *d_x, hipEvent_t *ev) {
   hipStream_t s = ctx->stream;
   const topo_problem &P = ctx->prob;
+  (void)hipEventRecord(ev[0], s);
+  // physical density
+  if (P.filter == TOPO_FILTER_DENSITY) {
+    TOPO_HIP(launch_filter(s, TOPO_FILTER_FWD, ctx->filt, d_x, nullptr, ctx->xphys));
+  } else {
+    TOPO_HIP(hipMemcpyAsync(ctx->xphys, d_x, ctx->nel * sizeof(double), hipMemcpyDeviceToDevice, s));
+  }
+  (void)hipEventRecord(ev[1], s);
+  // modulus, operator hierarchy and the initial guess (warm start from the last u)
+  if (!ctx->opts.warm_start || !ctx->have_u) {
+    TOPO_HIP(hipMemsetAsync(ctx->u, 0, ctx->ndof * sizeof(double), s));
+    ctx->n_warm = 0;
+    ctx->nbasis = 0;
+  } else if (ctx->opts.warm_start == 2) {
+    // extrapolated start 2 u_k - u_{k-1} once two solutions are known
+    if (!ctx->u_prev) TOPO_ALLOC(ctx->u_prev, ctx->ndof);
+    if (ctx->n_warm >= 2) TOPO_HIP(launch_extrapolate(s, ctx->ndof, ctx->u, ctx->u_prev));
+    else TOPO_HIP(hipMemcpyAsync(ctx->u_prev, ctx->u, ctx->ndof * sizeof(double), hipMemcpyDeviceToDevice, s));
+  }
+  // the coarse inverse is recomputed every coarse_refresh SIMP iterations; in
+  // between the previous one (still SPD) preconditions the coarsest level
+  const bool refresh = ctx->coarse_due <= 0;
+  topo_status st = prepare_operator(ctx, ctx->xphys, refresh);
+  --ctx->coarse_due;
+  if (st == TOPO_OK && ctx->opts.warm_start == 3 && ctx->nbasis > 0) st = projected_start(ctx);
+  return st;
+}
+
+topo_status iterate_post(topo_ctx *ctx, double *d_x, const topo_solve_stats &ss, hipEvent_t *ev,
+                         topo_iter_stats *o) {
+  hipStream_t s = ctx->stream;
+  const topo_problem &P = ctx->prob;
+  ctx->have_u = 1;
+  ++ctx->n_warm;
+  if (ctx->opts.warm_start == 3) {
+    if (!ctx->gram) TOPO_ALLOC(ctx->gram, kMaxBasis * kMaxBasis + kMaxBasis);
+    double *&slot = ctx->basis[ctx->basis_next];
+    if (!slot) TOPO_ALLOC(slot, ctx->ndof);
+    TOPO_HIP(hipMemcpyAsync(slot, ctx->u, ctx->ndof * sizeof(double), hipMemcpyDeviceToDevice, s));
+    ctx->basis_next = (ctx->basis_next + 1) % kMaxBasis;
+    ctx->nbasis = std::min(ctx->nbasis + 1, kMaxBasis);
+  }
+  (void)hipEventRecord(ev[2], s);
+  // sensitivities and compliance
+  TOPO_HIP(launch_sensitivity(s, ctx->g, ctx->kap, ctx->u, ctx->xphys, P.E0, P.Emin, P.penal, ctx->ce, ctx->dc));
+  TOPO_HIP(launch_dot(s, ctx->ndof, ctx->f, ctx->u, ctx->red, fin_sum(&ctx->sc->comp)));
+  (void)hipEventRecord(ev[3], s);
+  // filtered sensitivities and OC update
+  if (P.filter == TOPO_FILTER_DENSITY)
+    TOPO_HIP(launch_filter(s, TOPO_FILTER_ADJ, ctx->filt, ctx->dc, nullptr, ctx->dcf));
+  else
+    TOPO_HIP(launch_filter(s, TOPO_FILTER_SENS, ctx->filt, ctx->dc, d_x, ctx->dcf));
+  (void)hipEventRecord(ev[4], s);
+  topo_status st = oc_update(ctx, d_x, ctx->dcf, ctx->volw, ctx->xnew);
+  if (st != TOPO_OK) return st;
+  TOPO_HIP(hipMemcpyAsync(d_x, ctx->xnew, ctx->nel * sizeof(double), hipMemcpyDeviceToDevice, s));
+  (void)hipEventRecord(ev[5], s);
+  if (o) {
+    st = read_scalars(ctx);
+    if (st != TOPO_OK) return st;
+    o->c = ctx->h_sc->comp;
+    o->volume = ctx->h_sc->volume;
+    o->change = ctx->h_sc->change;
+    o->lambda = ctx->h_sc->lambda;
+    o->pcg_iters = ss.iters;
+    o->converged = ss.converged;
+    o->relres = ss.relres;
+    o->fallbacks = ss.fallbacks;
+    o->learned_iters = ss.learned_iters;
+    float t[5];
+    for (int k = 0; k < 5; ++k) (void)hipEventElapsedTime(&t[k], ev[k], ev[k + 1]);
+    float tot = 0.f;
+    (void)hipEventElapsedTime(&tot, ev[0], ev[5]);
+    o->ms_total = tot;
+    o->ms_filter = t[0] + t[3];
+    o->ms_solve = t[1];
+    o->ms_sens = t[2];
+    o->ms_oc = t[4];
+  }
+  return TOPO_OK;
+}
+}  // namespace topo
+
+extern "C" topo_status topo_iterate(topo_ctx *ctx, double *d_x, int32_t n_iter, topo_iter_stats *h_stats) {
+  if (!ctx || !d_x || n_iter < 0) return set_error("invalid argument"), TOPO_EINVAL;
   hipEvent_t ev[6];
   for (auto &e : ev) TOPO_HIP(hipEventCreate(&e));
   topo_status result = TOPO_OK;
   for (int it = 0; it < n_iter; ++it) {
-    (void)hipEventRecord(ev[0], s);
-    // physical density
-    if (P.filter == TOPO_FILTER_DENSITY) {
-      TOPO_HIP(launch_filter(s, TOPO_FILTER_FWD, ctx->filt, d_x, nullptr, ctx->xphys));
-    } else {
-      TOPO_HIP(hipMemcpyAsync(ctx->xphys, d_x, ctx->nel * sizeof(double), hipMemcpyDeviceToDevice, s));
-    }
-    (void)hipEventRecord(ev[1], s);
-    // modulus, operator hierarchy and solve (warm start from the last u)
-    if (!ctx->opts.warm_start || !ctx->have_u) {
-      TOPO_HIP(hipMemsetAsync(ctx->u, 0, ctx->ndof * sizeof(double), s));
-      ctx->n_warm = 0;
-      ctx->nbasis = 0;
-    } else if (ctx->opts.warm_start == 2) {
-      // extrapolated start 2 u_k - u_{k-1} once two solutions are known
-      if (!ctx->u_prev) TOPO_ALLOC(ctx->u_prev, ctx->ndof);
-      if (ctx->n_warm >= 2) TOPO_HIP(launch_extrapolate(s, ctx->ndof, ctx->u, ctx->u_prev));
-      else TOPO_HIP(hipMemcpyAsync(ctx->u_prev, ctx->u, ctx->ndof * sizeof(double), hipMemcpyDeviceToDevice, s));
-    }
-    // the coarse inverse is recomputed every coarse_refresh SIMP iterations; in
-    // between the previous one (still SPD) preconditions the coarsest level
-    const bool refresh = ctx->coarse_due <= 0;
-    topo_status st = prepare_operator(ctx, ctx->xphys, refresh);
-    --ctx->coarse_due;
-    if (st == TOPO_OK && ctx->opts.warm_start == 3 && ctx->nbasis > 0) st = projected_start(ctx);
+    topo_status st = iterate_pre(ctx, d_x, ev);
     topo_solve_stats ss{};
     if (st == TOPO_OK) st = pcg(ctx, &ss);
     if (st != TOPO_OK && st != TOPO_ENOTCONVERGED) return st;
     if (st == TOPO_ENOTCONVERGED) result = st;
-    ctx->have_u = 1;
-    ++ctx->n_warm;
-    if (ctx->opts.warm_start == 3) {
-      if (!ctx->gram) TOPO_ALLOC(ctx->gram, kMaxBasis * kMaxBasis + kMaxBasis);
-      double *&slot = ctx->basis[ctx->basis_next];
-      if (!slot) TOPO_ALLOC(slot, ctx->ndof);
-      TOPO_HIP(hipMemcpyAsync(slot, ctx->u, ctx->ndof * sizeof(double), hipMemcpyDeviceToDevice, s));
-      ctx->basis_next = (ctx->basis_next + 1) % kMaxBasis;
-      ctx->nbasis = std::min(ctx->nbasis + 1, kMaxBasis);
-    }
-    (void)hipEventRecord(ev[2], s);
-    // sensitivities and compliance
-    TOPO_HIP(launch_sensitivity(s, ctx->g, ctx->kap, ctx->u, ctx->xphys, P.E0, P.Emin, P.penal, ctx->ce, ctx->dc));
-    TOPO_HIP(launch_dot(s, ctx->ndof, ctx->f, ctx->u, ctx->red, fin_sum(&ctx->sc->comp)));
-    (void)hipEventRecord(ev[3], s);
-    // filtered sensitivities and OC update
-    if (P.filter == TOPO_FILTER_DENSITY)
-      TOPO_HIP(launch_filter(s, TOPO_FILTER_ADJ, ctx->filt, ctx->dc, nullptr, ctx->dcf));
-    else
-      TOPO_HIP(launch_filter(s, TOPO_FILTER_SENS, ctx->filt, ctx->dc, d_x, ctx->dcf));
-    (void)hipEventRecord(ev[4], s);
-    st = oc_update(ctx, d_x, ctx->dcf, ctx->volw, ctx->xnew);
+    st = iterate_post(ctx, d_x, ss, ev, h_stats ? &h_stats[it] : nullptr);
     if (st != TOPO_OK) return st;
-    TOPO_HIP(hipMemcpyAsync(d_x, ctx->xnew, ctx->nel * sizeof(double), hipMemcpyDeviceToDevice, s));
-    (void)hipEventRecord(ev[5], s);
-    if (h_stats) {
-      st = read_scalars(ctx);
-      if (st != TOPO_OK) return st;
-      topo_iter_stats &o = h_stats[it];
-      o.c = ctx->h_sc->comp;
-      o.volume = ctx->h_sc->volume;
-      o.change = ctx->h_sc->change;
-      o.lambda = ctx->h_sc->lambda;
-      o.pcg_iters = ss.iters;
-      o.converged = ss.converged;
-      o.relres = ss.relres;
-      o.fallbacks = ss.fallbacks;
-      o.learned_iters = ss.learned_iters;
-      float t[5];
-      for (int k = 0; k < 5; ++k) (void)hipEventElapsedTime(&t[k], ev[k], ev[k + 1]);
-      float tot = 0.f;
-      (void)hipEventElapsedTime(&tot, ev[0], ev[5]);
-      o.ms_total = tot;
-      o.ms_filter = t[0] + t[3];
-      o.ms_solve = t[1];
-      o.ms_sens = t[2];
-      o.ms_oc = t[4];
-    }
   }
-  TOPO_HIP(hipStreamSynchronize(s));
+  TOPO_HIP(hipStreamSynchronize(ctx->stream));
   for (auto &e : ev) (void)hipEventDestroy(e);
   return result;
 }

@@ -33,6 +33,7 @@ def test_default_opts():
     assert o.cheb_degree == 1 and o.cheb_degree_coarse == 4
     assert o.ku_kernel == pkg.KU_AUTO and o.ku_shape == -1 and o.coarse_tail_nodes == 0
     assert o.mg_max_coarse_dof == 1500 and o.coarse_refresh == 1
+    assert o.group_launch == 1 and list(o.cheb_degree_level) == [0] * 8
 
 
 def setup_status(p, vol_mode=0, **opt):
@@ -104,7 +105,8 @@ def test_setup_rejects_bad_options():
                     ({"ku_kernel": 3}, "ku_kernel"), ({"ku_shape": 4}, "ku_shape"),
                     ({"ku_shape": 5}, "ku_shape"), ({"ku_shape": 15}, "ku_shape"),
                     ({"ku_shape": -2}, "ku_shape"), ({"coarse_refresh": 0}, "coarse_refresh"),
-                    ({"cheb_degree_coarse": -1}, "cheb_degree_coarse"), ({"cheb_degree_coarse": 17}, "cheb_degree_coarse")]:
+                    ({"cheb_degree_coarse": -1}, "cheb_degree_coarse"), ({"cheb_degree_coarse": 17}, "cheb_degree_coarse"),
+                    ({"group_launch": 2}, "group_launch"), ({"group_launch": -1}, "group_launch")]:
         st, err, _ = setup_status(p, **kw)
         assert st == _lib.TOPO_EINVAL and msg in err, (kw, err)
 

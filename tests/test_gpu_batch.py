@@ -59,3 +59,24 @@ def test_autotuned_shapes_change_only_rounding():
             cr = np.array(base[i][1])
             assert np.abs(c - cr).max() <= 1e-9 * np.abs(cr).max(), i
             assert np.abs(xs[i].cpu().numpy() - base[i][0]).max() <= 1e-7, i
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_grouped_launches_equal_separate_streams(precision):
+    """Ten problems on one grid (a group of 8 and one of 2) plus two of another
+    size: with grouped launches every problem ends bit for bit where it ends on
+    its own stream (group_launch 0); the CG iteration counts agree too."""
+    ps = [synth.random_problem(100 + s, 16, n_iter=3) for s in range(10)]
+    ps += [synth.random_problem(200 + s, 24, n_iter=3) for s in range(2)]
+    prec = topo.PREC_FP64 if precision == "fp64" else topo.PREC_FP32
+    res = {}
+    for grouped in (0, 1):
+        with topo.Batch(ps, topo.default_opts(precision=prec, group_launch=grouped), n_threads=4) as b:
+            xs = [torch.from_numpy(p.initial_design()).to("cuda") for p in ps]
+            st = b.iterate(xs, 3)
+            torch.cuda.synchronize()
+            res[grouped] = ([x.cpu().numpy() for x in xs], st)
+    for i in range(len(ps)):
+        assert np.array_equal(res[0][0][i], res[1][0][i]), i
+        assert [s["c"] for s in res[0][1][i]] == [s["c"] for s in res[1][1][i]], i
+        assert [s["pcg_iters"] for s in res[0][1][i]] == [s["pcg_iters"] for s in res[1][1][i]], i
