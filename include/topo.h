@@ -127,8 +127,12 @@ typedef struct {
   int32_t use_graphs;         /* replay chunks of CG iterations from a captured HIP graph */
   int32_t nn_max_iters;       /* LEARNED: flexible-CG iterations before the solve restarts
                                  on the multigrid preconditioner                       */
-  int32_t autotune;           /* time every K.u launch shape on this problem's grids at
-                                 setup and keep the fastest (else chosen by grid size)   */
+  int32_t autotune;           /* 1: at setup, take the K.u launch shapes found earlier in
+                                 this process for the same grids, precision and kernel
+                                 family, else time every shape on this problem's grids
+                                 and keep (and remember) the fastest; 2: always time
+                                 afresh and replace what is remembered; 0: shapes by
+                                 grid size                                              */
   int32_t coarse_tail_nodes;  /* multigrid levels (below the finest) with at most this many
                                  nodes run as one single-workgroup launch; 0 = off        */
   int32_t mfma_smoothing;     /* FP32 preconditioner: smoothing operator passes on the FP32
@@ -296,6 +300,10 @@ topo_status topo_iterate(topo_ctx *ctx, double *d_x, int32_t n_iter, topo_iter_s
  * elapsed / reps.  Call after topo_iterate or topo_solve.  Writes only the
  * context's scratch vector. */
 topo_status topo_time_operator(topo_ctx *ctx, int32_t reps, double *h_ms_per_launch);
+
+/* Forgets every launch shape the autotuner (topo_opts.autotune 1) remembers in
+ * this process; contexts already set up keep theirs.  Thread-safe. */
+void topo_clear_tuning_cache(void);
 
 /* Copies the context's current displacement (ndof) to d_u / physical density
  * (nel) to d_xphys; either may be NULL. */

@@ -32,10 +32,10 @@ EXPORTED = [
     "topo_nn_create", "topo_nn_destroy", "topo_nn_set_precision", "topo_nn_n_params", "topo_nn_set_weights", "topo_nn_get_weights",
     "topo_nn_forward", "topo_nn_loss_grad", "topo_default_train_opts", "topo_nn_train", "topo_set_nn",
     "topo_nn_make_pairs", "topo_setup_batch", "topo_destroy_batch", "topo_batch_context", "topo_iterate_batch",
-    "topo_oc_update_noalloc", "topo_surface_stl", "topo_voxelize",
+    "topo_oc_update_noalloc", "topo_surface_stl", "topo_voxelize", "topo_clear_tuning_cache",
 ]
 _VOID = ("topo_default_opts", "topo_destroy", "topo_last_error", "topo_nn_destroy", "topo_default_train_opts",
-         "topo_destroy_batch")
+         "topo_destroy_batch", "topo_clear_tuning_cache")
 
 
 class TopoError(RuntimeError):
@@ -157,6 +157,8 @@ def load(path: str = LIB_PATH):
                                   C.c_double, C.c_int8, C.c_int8, vp, dp, C.POINTER(C.c_int64)]
     lib.topo_oc_update_noalloc.argtypes = [C.c_int64, dp, dp, dp, dp, C.c_double, C.c_double, C.c_double,
                                            C.c_double, vp, dp, dp]
+    lib.topo_clear_tuning_cache.argtypes = []
+    lib.topo_clear_tuning_cache.restype = None
     for name in EXPORTED:
         if name not in _VOID:
             getattr(lib, name).restype = C.c_int

@@ -5,6 +5,8 @@
 
 #include <algorithm>
 #include <functional>
+#include <map>
+#include <mutex>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -343,6 +345,7 @@ static topo_status validate(const topo_problem *P, const topo_opts *O) {
   if (O->warm_start < 0 || O->warm_start > 3) return set_error("warm_start must be 0, 1, 2 or 3"), TOPO_EINVAL;
   if (O->coarse_refresh < 1) return set_error("coarse_refresh must be >= 1"), TOPO_EINVAL;
   if (O->group_launch != 0 && O->group_launch != 1) return set_error("group_launch must be 0 or 1"), TOPO_EINVAL;
+  if (O->autotune < 0 || O->autotune > 2) return set_error("autotune must be 0, 1 or 2"), TOPO_EINVAL;
   for (int l = 0; l < 8; ++l)
     if (O->cheb_degree_level[l] < 0 || O->cheb_degree_level[l] > 16)
       return set_error("cheb_degree_level[%d] must lie in [0, 16]", l), TOPO_EINVAL;
@@ -801,7 +804,60 @@ static topo_status tune_smoothing(topo_ctx *ctx, Level &L) {
   }, &L.shape);
 }
 
+// Shapes found by the autotuner, per device and per tuning problem (grids of
+// every level, operator precision, kernel family): later contexts with the same
+// key take them without timing (autotune 1); autotune 2 times again and
+// replaces the entry.  Any entry is a valid choice, as every shape computes the
+// same products.
+namespace {
+struct TunedShapes {
+  int shape_cg = -1;
+  std::vector<int> level;
+};
+std::mutex g_tune_mu;
+std::map<std::string, TunedShapes> g_tune_cache;
+}  // namespace
+
+static std::string tune_key(const topo_ctx *ctx) {
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  std::string k = std::to_string(dev) + "|" + std::to_string(ctx->opts.precision) + "|" +
+                  std::to_string(ctx->mixed) + "|" + std::to_string(ctx->opts.ku_kernel) + "|" +
+                  std::to_string(ctx->lv.size());
+  for (const Level &L : ctx->lv)
+    k += "|" + std::to_string(L.g.nx) + "x" + std::to_string(L.g.ny) + "x" + std::to_string(L.g.nz);
+  return k;
+}
+
+static topo_status autotune_timed(topo_ctx *ctx);
+
 static topo_status autotune(topo_ctx *ctx) {
+  const std::string key = tune_key(ctx);
+  if (ctx->opts.autotune == 1) {
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    auto it = g_tune_cache.find(key);
+    if (it != g_tune_cache.end() && it->second.level.size() == ctx->lv.size()) {
+      ctx->shape_cg = it->second.shape_cg;
+      for (size_t l = 0; l < ctx->lv.size(); ++l) ctx->lv[l].shape = it->second.level[l];
+      return TOPO_OK;
+    }
+  }
+  topo_status st = autotune_timed(ctx);
+  if (st != TOPO_OK) return st;
+  TunedShapes t;
+  t.shape_cg = ctx->shape_cg;
+  for (const Level &L : ctx->lv) t.level.push_back(L.shape);
+  std::lock_guard<std::mutex> g(g_tune_mu);
+  g_tune_cache[key] = t;
+  return TOPO_OK;
+}
+
+extern "C" void topo_clear_tuning_cache(void) {
+  std::lock_guard<std::mutex> g(g_tune_mu);
+  g_tune_cache.clear();
+}
+
+static topo_status autotune_timed(topo_ctx *ctx) {
   hipStream_t s = ctx->stream;
   Level &L0 = ctx->lv[0];
   const int64_t nd = ctx->ndof;

@@ -106,7 +106,8 @@ def test_setup_rejects_bad_options():
                     ({"ku_shape": 5}, "ku_shape"), ({"ku_shape": 15}, "ku_shape"),
                     ({"ku_shape": -2}, "ku_shape"), ({"coarse_refresh": 0}, "coarse_refresh"),
                     ({"cheb_degree_coarse": -1}, "cheb_degree_coarse"), ({"cheb_degree_coarse": 17}, "cheb_degree_coarse"),
-                    ({"group_launch": 2}, "group_launch"), ({"group_launch": -1}, "group_launch")]:
+                    ({"group_launch": 2}, "group_launch"), ({"group_launch": -1}, "group_launch"),
+                    ({"autotune": 3}, "autotune"), ({"autotune": -1}, "autotune")]:
         st, err, _ = setup_status(p, **kw)
         assert st == _lib.TOPO_EINVAL and msg in err, (kw, err)
 

@@ -80,3 +80,18 @@ def test_grouped_launches_equal_separate_streams(precision):
         assert np.array_equal(res[0][0][i], res[1][0][i]), i
         assert [s["c"] for s in res[0][1][i]] == [s["c"] for s in res[1][1][i]], i
         assert [s["pcg_iters"] for s in res[0][1][i]] == [s["pcg_iters"] for s in res[1][1][i]], i
+
+
+def test_autotuner_remembers_shapes_per_grid():
+    """After the cache is cleared, the first context on a grid times the launch
+    shapes; a second context on the same grid takes the remembered shapes, so
+    the two runs agree bit for bit (fresh timings could pick other shapes,
+    which would change the rounding)."""
+    lib = topo.load()
+    lib.topo_clear_tuning_cache()
+    p = synth.random_problem(7, 32, n_iter=3)
+    opts = topo.default_opts(precision=topo.PREC_FP32, autotune=1)
+    a = run_single(p, opts, 3)
+    b = run_single(p, opts, 3)
+    assert np.array_equal(a[0], b[0]) and a[1] == b[1]
+    lib.topo_clear_tuning_cache()
