@@ -194,17 +194,23 @@ static topo_status iterate_group(topo_batch *b, Unit &u, double *const *d_x, int
   for (auto &e : ev)
     if (hipEventCreate(&e) != hipSuccess) return set_error("event creation failed"), TOPO_EDEVICE;
   std::vector<topo_solve_stats> ss(m);
+  std::vector<double *> x(m);
+  std::vector<topo_iter_stats *> o(m);
+  for (int k = 0; k < m; ++k) x[k] = d_x[u.members[k]];
   topo_status result = TOPO_OK, st = TOPO_OK;
   for (int it = 0; it < n_iter && st == TOPO_OK; ++it) {
-    for (int k = 0; k < m && st == TOPO_OK; ++k) st = iterate_pre(G.c[k], d_x[u.members[k]], &ev[6 * k]);
+    // members in lockstep (the normal case) share every launch of the
+    // iteration; otherwise only the CG iterations
+    const bool shared = group_lockstep(G);
+    for (int k = 0; k < m; ++k) o[k] = h_stats ? h_stats + (size_t)u.members[k] * n_iter + it : nullptr;
+    if (shared) st = group_pre(G, x.data(), ev.data());
+    for (int k = 0; k < m && st == TOPO_OK && !shared; ++k) st = iterate_pre(G.c[k], x[k], &ev[6 * k]);
     if (st != TOPO_OK) break;
     st = group_pcg(G, &u.graph, &u.exec, u.cap, ss.data());
     if (st == TOPO_ENOTCONVERGED) result = st, st = TOPO_OK;
     if (st != TOPO_OK) break;
-    for (int k = 0; k < m && st == TOPO_OK; ++k) {
-      const int i = u.members[k];
-      st = iterate_post(G.c[k], d_x[i], ss[k], &ev[6 * k], h_stats ? h_stats + (size_t)i * n_iter + it : nullptr);
-    }
+    if (shared) st = group_post(G, x.data(), ss.data(), ev.data(), o.data());
+    for (int k = 0; k < m && st == TOPO_OK && !shared; ++k) st = iterate_post(G.c[k], x[k], ss[k], &ev[6 * k], o[k]);
   }
   if (st == TOPO_OK && hipStreamSynchronize(u.stream) != hipSuccess) {
     set_error("stream synchronisation failed");

@@ -223,6 +223,20 @@ hipError_t launch_convert(hipStream_t s, int64_t n, const float *in, double *out
                           const int *skip = nullptr);
 // u = sum_k alpha_k v_k, 1 <= nv <= 4
 hipError_t launch_combine(hipStream_t s, int64_t n, int nv, const double *const *v, const double *alpha, double *u);
+// u = sum_k alpha_k v_k over the first n of up to 4 vectors
+struct Combo {
+  const double *v[4];
+  double alpha[4];
+  int n;
+};
+// nv <= kMaxRed dot products a_k . b in one pass; fin.out[k] = a_k . b, each
+// bit-identical to launch_dot of the same pair
+struct MultiDotArgs {
+  const double *a[kMaxRed];
+  const double *b;
+  int nv;
+};
+hipError_t launch_multi_dot(hipStream_t s, int64_t n, const MultiDotArgs &m, const Reducer &red, const Fin &fin);
 // u_prev <- u and u <- 2 u - u_prev (previous u_prev)
 hipError_t launch_extrapolate(hipStream_t s, int64_t n, double *u, double *u_prev);
 // z_new = x (+ res dinv inv_theta when res is given); fin.out[0] = r.z_new,
@@ -373,6 +387,52 @@ struct MatvecArgs {
 template <typename T>
 hipError_t launch_dense_matvec_group(hipStream_t s, int G, int n, const MatvecArgs<T> *a);
 
+hipError_t launch_zero_fixed_group(hipStream_t s, int G, int64_t nnodes, const uint8_t *const *fixed,
+                                   double *const *v);
+struct CgStartArgs {
+  Scalars *sc;
+  double rtol2;
+  int max_iters;
+};
+hipError_t launch_cg_start_group(hipStream_t s, int G, const CgStartArgs *a);
+struct ConvertArgs {
+  const double *in;
+  float *out;
+  const int *skip;
+};
+hipError_t launch_convert_group(hipStream_t s, int G, int64_t n, const ConvertArgs *a);
+hipError_t launch_extrapolate_group(hipStream_t s, int G, int64_t n, double *const *u, double *const *u_prev);
+hipError_t launch_combine_group(hipStream_t s, int G, int64_t n, const Combo *c, double *const *u);
+hipError_t launch_multi_dot_group(hipStream_t s, int G, int64_t n, const MultiDotArgs *m, const Reducer *red,
+                                  const Fin *fin);
+// dst[i] <- src[i] (bytes, a multiple of 4); src == NULL: dst[i] <- 0
+hipError_t launch_copy_group(hipStream_t s, int G, int64_t bytes, const void *const *src, void *const *dst);
+
+struct ModulusArgs {
+  const double *xphys;
+  double E0, Emin, penal;
+  double *E;
+};
+hipError_t launch_simp_modulus_group(hipStream_t s, int G, int64_t nel, const ModulusArgs *a);
+hipError_t launch_coarsen_moduli_group(hipStream_t s, int G, Grid gf, Grid gc, const double *const *Ef,
+                                       double *const *Ec);
+struct DiagArgs {
+  const double *E;
+  Kappa kap;
+  const uint8_t *fixed;
+  double *dinv;
+};
+hipError_t launch_diag_group(hipStream_t s, int G, Grid g, const DiagArgs *a);
+struct AssembleArgs {
+  const double *E;
+  Kappa kap;
+  const uint8_t *fixed;
+  double *A;
+};
+hipError_t launch_dense_assemble_group(hipStream_t s, int G, Grid g, const AssembleArgs *a);
+// G in-place inversions of n x n SPD matrices A[i] (work[i]: dense_invert_work(n) doubles)
+hipError_t launch_dense_invert_group(hipStream_t s, int G, int n, double *const *A, double *const *work);
+
 template <typename T>
 hipError_t launch_vcycle_tail_t(hipStream_t s, const TailArgs<T> &a);
 
@@ -394,6 +454,14 @@ topo_status group_pcg(Group &G, hipGraph_t *graph, hipGraphExec_t *exec, hipStre
 topo_status iterate_pre(topo_ctx *ctx, double *d_x, hipEvent_t *ev);
 topo_status iterate_post(topo_ctx *ctx, double *d_x, const topo_solve_stats &ss, hipEvent_t *ev,
                          topo_iter_stats *o);
+void fill_stats(const topo_ctx *ctx, const topo_solve_stats &ss, hipEvent_t *ev, topo_iter_stats *o);
+// iterate_pre / iterate_post of every member of a group, one launch per step
+// for the whole group (ev: 6 events of the group; o[i] may be NULL); only for
+// groups in lockstep (group_lockstep)
+bool group_lockstep(const Group &G);
+topo_status group_pre(const Group &G, double *const *d_x, hipEvent_t *ev);
+topo_status group_post(const Group &G, double *const *d_x, const topo_solve_stats *ss, hipEvent_t *ev,
+                       topo_iter_stats *const *o);
 // raises the kernel's dynamic LDS limit (call once before launching)
 template <typename T>
 hipError_t prepare_vcycle_tail_t(size_t smem_bytes);
@@ -424,6 +492,21 @@ hipError_t launch_filter(hipStream_t s, int op, const FilterArgs &f, const doubl
                          const double *aux, double *out);
 hipError_t launch_design_scale(hipStream_t s, int64_t nel, const int8_t *mask, const double *Hs,
                                double *sD);
+// grouped filter (FWD, ADJ or SENS) of G problems on one grid with the same
+// stencil reach; every problem gets exactly its own launch's result
+struct FilterCall {
+  FilterArgs f;
+  const double *in, *aux;
+  double *out;
+};
+hipError_t launch_filter_group(hipStream_t s, int op, int G, const FilterCall *c);
+struct SensArgs {
+  Kappa kap;
+  const double *u, *xphys;
+  double E0, Emin, penal;
+  double *ce, *dc;
+};
+hipError_t launch_sensitivity_group(hipStream_t s, int G, Grid g, const SensArgs *a);
 
 // OC update with device-side multisection.  a (nel) holds the per-element
 // coefficients x (max(0,-dc)/dv)^eta between the passes; with a == nullptr
@@ -443,5 +526,15 @@ hipError_t launch_oc_pass(hipStream_t s, int64_t nel, const double *x, const dou
 hipError_t launch_oc_final(hipStream_t s, int64_t nel, const double *x, const double *a,
                            const double *dc, const double *dv, const int8_t *mask, double move,
                            double eta, double *xnew, Scalars *sc, const Reducer &red);
+// prepare, kOcPasses passes and the final update of G problems with nel
+// elements each, every launch shared by the group (a: stored coefficients)
+struct OcArgs {
+  const double *x, *dc, *dv;
+  const int8_t *mask;
+  double move, eta, tol, target;
+  double *a, *xnew;
+  Scalars *sc;
+};
+hipError_t launch_oc_update_group(hipStream_t s, int G, int64_t nel, const OcArgs *o, const Reducer *red);
 
 }  // namespace topo

@@ -1,5 +1,6 @@
 // Cone-weight filter as a 3D stencil (Sensitivity Filtering section) and the
 // element sensitivities (Optimality Criteria section).
+#include "group_host.h"
 #include "internal.h"
 #include "ke_code.h"
 #include "reduce_dev.h"
@@ -20,9 +21,8 @@ enum FiltOp { F_FWD = TOPO_FILTER_FWD, F_ADJ = TOPO_FILTER_ADJ, F_SENS = TOPO_FI
               F_VOLW = TOPO_FILTER_VOLW, F_HS = 100 };
 
 template <int OP>
-__global__ __launch_bounds__(kBs) void filter_kernel(FilterArgs f, const double *__restrict__ in,
-                                                     const double *__restrict__ aux,
-                                                     double *__restrict__ out) {
+__device__ __forceinline__ void filter_body(const FilterArgs &f, const double *__restrict__ in,
+                                            const double *__restrict__ aux, double *__restrict__ out) {
   const Grid g = f.g;
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= g.nel()) return;
@@ -50,6 +50,17 @@ __global__ __launch_bounds__(kBs) void filter_kernel(FilterArgs f, const double 
   } else {
     out[e] = acc;
   }
+}
+template <int OP>
+__global__ __launch_bounds__(kBs) void filter_kernel(FilterArgs f, const double *__restrict__ in,
+                                                     const double *__restrict__ aux,
+                                                     double *__restrict__ out) {
+  filter_body<OP>(f, in, aux, out);
+}
+template <int OP>
+__global__ __launch_bounds__(kBs) void filter_group_kernel(GroupTab<FilterCall> t) {
+  const FilterCall &c = t.v[blockIdx.z];
+  filter_body<OP>(c.f, c.in, c.aux, c.out);
 }
 
 // ---------------------------------------------------------------------------
@@ -80,9 +91,8 @@ __device__ __forceinline__ double filter_operand(const FilterArgs &f, const doub
 }  // namespace
 
 template <int OP, int R, int KZ>
-__global__ __launch_bounds__(kFx *kFy) void filter_tile_kernel(FilterArgs f, const double *__restrict__ in,
-                                                               const double *__restrict__ aux,
-                                                               double *__restrict__ out) {
+__device__ __forceinline__ void filter_tile_body(const FilterArgs &f, const double *__restrict__ in,
+                                                 const double *__restrict__ aux, double *__restrict__ out) {
   constexpr int NTH = kFx * kFy;
   constexpr int LX = kFx + 2 * R, LY = kFy + 2 * R, LZ = KZ + 2 * R, NT = LX * LY * LZ;
   __shared__ double v[LZ][LY][LX];
@@ -170,12 +180,27 @@ __global__ __launch_bounds__(kFx *kFy) void filter_tile_kernel(FilterArgs f, con
     }
   }
 }
+template <int OP, int R, int KZ>
+__global__ __launch_bounds__(kFx *kFy) void filter_tile_kernel(FilterArgs f, const double *__restrict__ in,
+                                                               const double *__restrict__ aux,
+                                                               double *__restrict__ out) {
+  filter_tile_body<OP, R, KZ>(f, in, aux, out);
+}
+template <int OP, int R, int KZ>
+__global__ __launch_bounds__(kFx *kFy) void filter_tile_group_kernel(GroupTab<FilterCall> t) {
+  const FilterCall &c = t.v[blockIdx.z];
+  filter_tile_body<OP, R, KZ>(c.f, c.in, c.aux, c.out);
+}
 
 namespace {
+// G == 0: one problem (f, in, aux, out); else the group table t
 template <int OP, int R, int KZ>
 hipError_t launch_tiled_rk(hipStream_t s, const FilterArgs &f, const double *in, const double *aux, double *out,
-                           int64_t tiles) {
-  filter_tile_kernel<OP, R, KZ><<<(unsigned)tiles, kFx * kFy, 0, s>>>(f, in, aux, out);
+                           int64_t tiles, int G = 0, const GroupTab<FilterCall> *t = nullptr) {
+  if (G == 0)
+    filter_tile_kernel<OP, R, KZ><<<(unsigned)tiles, kFx * kFy, 0, s>>>(f, in, aux, out);
+  else
+    filter_tile_group_kernel<OP, R, KZ><<<dim3((unsigned)tiles, 1, G), kFx * kFy, 0, s>>>(*t);
   return hipGetLastError();
 }
 
@@ -184,27 +209,51 @@ hipError_t launch_tiled_rk(hipStream_t s, const FilterArgs &f, const double *in,
 // depth 4), else 2 deep for more tiles on small grids (96x48x48: 11 against
 // 14 us)
 template <int OP, int R>
-hipError_t launch_tiled_r(hipStream_t s, const FilterArgs &f, const double *in, const double *aux, double *out) {
+hipError_t launch_tiled_r(hipStream_t s, const FilterArgs &f, const double *in, const double *aux, double *out,
+                          int G = 0, const GroupTab<FilterCall> *t = nullptr) {
   const Grid g = f.g;
   const int64_t txy = (int64_t)((g.nx + kFx - 1) / kFx) * ((g.ny + kFy - 1) / kFy);
   const int64_t t8 = txy * ((g.nz + 7) / 8), t2 = txy * ((g.nz + 1) / 2);
   if (t2 > INT32_MAX) return hipErrorInvalidValue;
-  if (t8 >= 256) return launch_tiled_rk<OP, R, 8>(s, f, in, aux, out, t8);
-  return launch_tiled_rk<OP, R, 2>(s, f, in, aux, out, t2);
+  if (t8 >= 256) return launch_tiled_rk<OP, R, 8>(s, f, in, aux, out, t8, G, t);
+  return launch_tiled_rk<OP, R, 2>(s, f, in, aux, out, t2, G, t);
 }
 
 template <int OP>
-hipError_t launch_op(hipStream_t s, const FilterArgs &f, const double *in, const double *aux, double *out) {
+hipError_t launch_op(hipStream_t s, const FilterArgs &f, const double *in, const double *aux, double *out,
+                     int G = 0, const GroupTab<FilterCall> *t = nullptr) {
   switch (f.R) {
-    case 1: return launch_tiled_r<OP, 1>(s, f, in, aux, out);
-    case 2: return launch_tiled_r<OP, 2>(s, f, in, aux, out);
-    case 3: return launch_tiled_r<OP, 3>(s, f, in, aux, out);
+    case 1: return launch_tiled_r<OP, 1>(s, f, in, aux, out, G, t);
+    case 2: return launch_tiled_r<OP, 2>(s, f, in, aux, out, G, t);
+    case 3: return launch_tiled_r<OP, 3>(s, f, in, aux, out, G, t);
     default:
-      filter_kernel<OP><<<nblocks(f.g.nel()), kBs, 0, s>>>(f, in, aux, out);
+      if (G == 0)
+        filter_kernel<OP><<<nblocks(f.g.nel()), kBs, 0, s>>>(f, in, aux, out);
+      else
+        filter_group_kernel<OP><<<dim3(nblocks(f.g.nel()), 1, G), kBs, 0, s>>>(*t);
       return hipGetLastError();
   }
 }
 }  // namespace
+
+hipError_t launch_filter_group(hipStream_t s, int op, int G, const FilterCall *c) {
+  if (!group_ok(G)) return hipErrorInvalidValue;
+  for (int i = 0; i < G; ++i) {
+    const Grid &g = c[i].f.g, &g0 = c[0].f.g;
+    if (g.nx != g0.nx || g.ny != g0.ny || g.nz != g0.nz) return hipErrorInvalidValue;
+    const bool tiled = c[i].f.R >= 1 && c[i].f.R <= kFilterTiledMaxR;
+    const bool tiled0 = c[0].f.R >= 1 && c[0].f.R <= kFilterTiledMaxR;
+    if (tiled != tiled0 || (tiled && c[i].f.R != c[0].f.R)) return hipErrorInvalidValue;
+  }
+  const GroupTab<FilterCall> t = group_tab(G, c);
+  const FilterCall &c0 = c[0];
+  switch (op) {
+    case TOPO_FILTER_FWD: return launch_op<F_FWD>(s, c0.f, c0.in, c0.aux, c0.out, G, &t);
+    case TOPO_FILTER_ADJ: return launch_op<F_ADJ>(s, c0.f, c0.in, c0.aux, c0.out, G, &t);
+    case TOPO_FILTER_SENS: return launch_op<F_SENS>(s, c0.f, c0.in, c0.aux, c0.out, G, &t);
+    default: return hipErrorInvalidValue;
+  }
+}
 
 hipError_t launch_filter_hs(hipStream_t s, const FilterArgs &f, double *Hs) {
   return launch_op<F_HS>(s, f, nullptr, nullptr, Hs);
@@ -236,12 +285,10 @@ hipError_t launch_design_scale(hipStream_t s, int64_t nel, const int8_t *mask, c
 // ---------------------------------------------------------------------------
 // Sensitivities (Optimality Criteria section): ce_e = u_e^T KE u_e and
 // dc_e = -p xphys^(p-1) (E0 - Emin) ce_e; thread per element.
-__global__ __launch_bounds__(kBs) void sensitivity_kernel(Grid g, Kappa kap,
-                                                          const double *__restrict__ u,
-                                                          const double *__restrict__ xphys,
-                                                          double E0, double Emin, double penal,
-                                                          double *__restrict__ ce,
-                                                          double *__restrict__ dc) {
+__device__ __forceinline__ void sensitivity_body(Grid g, const Kappa &kap, const double *__restrict__ u,
+                                                 const double *__restrict__ xphys, double E0, double Emin,
+                                                 double penal, double *__restrict__ ce,
+                                                 double *__restrict__ dc) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= g.nel()) return;
   const int i = (int)(e % g.nx);
@@ -267,11 +314,29 @@ __global__ __launch_bounds__(kBs) void sensitivity_kernel(Grid g, Kappa kap,
   const double xp1 = (penal == 3.0) ? x * x : pow(x, penal - 1.0);
   dc[e] = -penal * xp1 * (E0 - Emin) * s;
 }
+__global__ __launch_bounds__(kBs) void sensitivity_kernel(Grid g, Kappa kap,
+                                                          const double *__restrict__ u,
+                                                          const double *__restrict__ xphys,
+                                                          double E0, double Emin, double penal,
+                                                          double *__restrict__ ce,
+                                                          double *__restrict__ dc) {
+  sensitivity_body(g, kap, u, xphys, E0, Emin, penal, ce, dc);
+}
+__global__ __launch_bounds__(kBs) void sensitivity_group_kernel(Grid g, GroupTab<SensArgs> t) {
+  const SensArgs &a = t.v[blockIdx.z];
+  sensitivity_body(g, a.kap, a.u, a.xphys, a.E0, a.Emin, a.penal, a.ce, a.dc);
+}
 
 hipError_t launch_sensitivity(hipStream_t s, Grid g, const Kappa &kap, const double *u,
                               const double *xphys, double E0, double Emin, double penal, double *ce,
                               double *dc) {
   sensitivity_kernel<<<nblocks(g.nel()), kBs, 0, s>>>(g, kap, u, xphys, E0, Emin, penal, ce, dc);
+  return hipGetLastError();
+}
+
+hipError_t launch_sensitivity_group(hipStream_t s, int G, Grid g, const SensArgs *a) {
+  if (!group_ok(G)) return hipErrorInvalidValue;
+  sensitivity_group_kernel<<<dim3(nblocks(g.nel()), 1, G), kBs, 0, s>>>(g, group_tab(G, a));
   return hipGetLastError();
 }
 

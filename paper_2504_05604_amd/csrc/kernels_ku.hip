@@ -23,6 +23,7 @@
 #include <algorithm>
 #include <type_traits>
 
+#include "group_host.h"
 #include "internal.h"
 #include "ke_code.h"
 #include "ku_epilogue.h"
@@ -374,13 +375,21 @@ hipError_t launch_finalize(hipStream_t s, const Reducer &red, int nparts, int n,
 }
 
 // ---------------------------------------------------------------------------
-__global__ void simp_modulus_kernel(int64_t nel, const double *xphys, double E0, double Emin,
-                                    double penal, double scale, double *E) {
+__device__ __forceinline__ void simp_modulus_body(int64_t nel, const double *xphys, double E0, double Emin,
+                                                  double penal, double scale, double *E) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= nel) return;
   const double x = xphys[e];
   const double xp = (penal == 3.0) ? x * x * x : pow(x, penal);
   E[e] = scale * (Emin + xp * (E0 - Emin));
+}
+__global__ void simp_modulus_kernel(int64_t nel, const double *xphys, double E0, double Emin,
+                                    double penal, double scale, double *E) {
+  simp_modulus_body(nel, xphys, E0, Emin, penal, scale, E);
+}
+__global__ void simp_modulus_group_kernel(int64_t nel, GroupTab<ModulusArgs> t) {
+  const ModulusArgs &a = t.v[blockIdx.z];
+  simp_modulus_body(nel, a.xphys, a.E0, a.Emin, a.penal, 1.0, a.E);
 }
 
 hipError_t launch_simp_modulus(hipStream_t s, int64_t nel, const double *xphys, double E0,
@@ -393,7 +402,7 @@ hipError_t launch_simp_modulus(hipStream_t s, int64_t nel, const double *xphys, 
 
 // Coarse modulus = 2 * mean of the 8 fine children (missing children are 0):
 // the factor 2 is the stiffness scaling of an element of twice the edge length.
-__global__ void coarsen_moduli_kernel(Grid gf, Grid gc, const double *Ef, double *Ec) {
+__device__ __forceinline__ void coarsen_moduli_body(Grid gf, Grid gc, const double *Ef, double *Ec) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= gc.nel()) return;
   const int I = (int)(e % gc.nx);
@@ -407,6 +416,12 @@ __global__ void coarsen_moduli_kernel(Grid gf, Grid gc, const double *Ef, double
   }
   Ec[e] = 0.25 * s;
 }
+__global__ void coarsen_moduli_kernel(Grid gf, Grid gc, const double *Ef, double *Ec) {
+  coarsen_moduli_body(gf, gc, Ef, Ec);
+}
+__global__ void coarsen_moduli_group_kernel(Grid gf, Grid gc, GroupTab<const double *> Ef, GroupTab<double *> Ec) {
+  coarsen_moduli_body(gf, gc, Ef.v[blockIdx.z], Ec.v[blockIdx.z]);
+}
 
 hipError_t launch_coarsen_moduli(hipStream_t s, Grid gf, Grid gc, const double *Ef, double *Ec) {
   const int bs = 256;
@@ -415,7 +430,8 @@ hipError_t launch_coarsen_moduli(hipStream_t s, Grid gf, Grid gc, const double *
 }
 
 // inverse Jacobi diagonal: 1 / sum_{e around i} E_e KE[(3 li + c),(3 li + c)]; 0 on fixed dofs
-__global__ void diag_kernel(Grid g, const double *E, Kappa kap, const uint8_t *fixed, double *dinv) {
+__device__ __forceinline__ void diag_body(Grid g, const double *E, const Kappa &kap, const uint8_t *fixed,
+                                          double *dinv) {
   const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (n >= g.nnodes()) return;
   const int i = (int)(n % g.NX());
@@ -438,11 +454,41 @@ __global__ void diag_kernel(Grid g, const double *E, Kappa kap, const uint8_t *f
   dinv[3 * n + 1] = (fx & 2) ? 0.0 : 1.0 / d1;
   dinv[3 * n + 2] = (fx & 4) ? 0.0 : 1.0 / d2;
 }
+__global__ void diag_kernel(Grid g, const double *E, Kappa kap, const uint8_t *fixed, double *dinv) {
+  diag_body(g, E, kap, fixed, dinv);
+}
+__global__ void diag_group_kernel(Grid g, GroupTab<DiagArgs> t) {
+  const DiagArgs &a = t.v[blockIdx.z];
+  diag_body(g, a.E, a.kap, a.fixed, a.dinv);
+}
 
 hipError_t launch_diag(hipStream_t s, Grid g, const double *E, const Kappa &kap,
                        const uint8_t *fixed, double *dinv) {
   const int bs = 256;
   diag_kernel<<<(unsigned)((g.nnodes() + bs - 1) / bs), bs, 0, s>>>(g, E, kap, fixed, dinv);
+  return hipGetLastError();
+}
+
+
+// grouped operator set-up (problems of equal grids)
+hipError_t launch_simp_modulus_group(hipStream_t s, int G, int64_t nel, const ModulusArgs *a) {
+  if (!group_ok(G)) return hipErrorInvalidValue;
+  const int bs = 256;
+  simp_modulus_group_kernel<<<dim3((unsigned)((nel + bs - 1) / bs), 1, G), bs, 0, s>>>(nel, group_tab(G, a));
+  return hipGetLastError();
+}
+hipError_t launch_coarsen_moduli_group(hipStream_t s, int G, Grid gf, Grid gc, const double *const *Ef,
+                                       double *const *Ec) {
+  if (!group_ok(G)) return hipErrorInvalidValue;
+  const int bs = 256;
+  coarsen_moduli_group_kernel<<<dim3((unsigned)((gc.nel() + bs - 1) / bs), 1, G), bs, 0, s>>>(
+      gf, gc, group_tab(G, Ef), group_tab(G, Ec));
+  return hipGetLastError();
+}
+hipError_t launch_diag_group(hipStream_t s, int G, Grid g, const DiagArgs *a) {
+  if (!group_ok(G)) return hipErrorInvalidValue;
+  const int bs = 256;
+  diag_group_kernel<<<dim3((unsigned)((g.nnodes() + bs - 1) / bs), 1, G), bs, 0, s>>>(g, group_tab(G, a));
   return hipGetLastError();
 }
 

@@ -478,7 +478,9 @@ static hipError_t launch_hada_shape_group(hipStream_t s, KuEpi epi, int G, const
       ku_hada_group_kernel<E, KZ, TX, TY, VAR == 1, T><<<grid, TX * TY, 0, s>>>(t, part, hw, tx, txy); \
     break;
   switch (epi) {
+    TOPO_KU_CASE(KU_STORE)
     TOPO_KU_CASE(KU_STORE_DOT)
+    TOPO_KU_CASE(KU_RESID)
     TOPO_KU_CASE(KU_RES0)
     TOPO_KU_CASE(KU_CHEB0)
     TOPO_KU_CASE(KU_CHEB)

@@ -4,6 +4,7 @@
 // coarsest-level operator with its explicit inverse.
 #include <algorithm>
 
+#include "group_host.h"
 #include "internal.h"
 #include "ke_code.h"
 
@@ -177,9 +178,13 @@ __global__ void zero_kernel(int64_t n, double *A) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t < n) A[t] = 0.0;
 }
+__global__ void zero_group_kernel(int64_t n, GroupTab<AssembleArgs> t) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) t.v[blockIdx.z].A[i] = 0.0;
+}
 
-__global__ void dense_assemble_kernel(Grid g, const double *E, Kappa kap, const uint8_t *fixed,
-                                      double *A) {
+__device__ __forceinline__ void dense_assemble_body(Grid g, const double *E, const Kappa &kap,
+                                                    const uint8_t *fixed, double *A) {
   const int64_t n = g.ndof();
   const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (row >= n) return;
@@ -215,11 +220,27 @@ __global__ void dense_assemble_kernel(Grid g, const double *E, Kappa kap, const 
     }
   }
 }
+__global__ void dense_assemble_kernel(Grid g, const double *E, Kappa kap, const uint8_t *fixed,
+                                      double *A) {
+  dense_assemble_body(g, E, kap, fixed, A);
+}
+__global__ void dense_assemble_group_kernel(Grid g, GroupTab<AssembleArgs> t) {
+  const AssembleArgs &a = t.v[blockIdx.z];
+  dense_assemble_body(g, a.E, a.kap, a.fixed, a.A);
+}
 
 hipError_t launch_dense_assemble(hipStream_t s, Grid g, const double *E, const Kappa &kap,
                                  const uint8_t *fixed, double *A) {
   zero_kernel<<<nblocks(g.ndof() * g.ndof()), kBs, 0, s>>>(g.ndof() * g.ndof(), A);
   dense_assemble_kernel<<<nblocks(g.ndof()), kBs, 0, s>>>(g, E, kap, fixed, A);
+  return hipGetLastError();
+}
+
+hipError_t launch_dense_assemble_group(hipStream_t s, int G, Grid g, const AssembleArgs *a) {
+  if (!group_ok(G)) return hipErrorInvalidValue;
+  const GroupTab<AssembleArgs> t = group_tab(G, a);
+  zero_group_kernel<<<dim3(nblocks(g.ndof() * g.ndof()), 1, G), kBs, 0, s>>>(g.ndof() * g.ndof(), t);
+  dense_assemble_group_kernel<<<dim3(nblocks(g.ndof()), 1, G), kBs, 0, s>>>(g, t);
   return hipGetLastError();
 }
 
@@ -262,7 +283,7 @@ __device__ void gj_invert_lds(int m, double *M, double *col, double *rowk) {
   }
 }
 
-__global__ __launch_bounds__(kInvThreads) void dense_invert_lds_kernel(int n, double *A) {
+__device__ __forceinline__ void dense_invert_lds_body(int n, double *A) {
   extern __shared__ double lds[];
   double *M = lds;            // n*n
   double *col = lds + n * n;  // n
@@ -272,6 +293,13 @@ __global__ __launch_bounds__(kInvThreads) void dense_invert_lds_kernel(int n, do
   __syncthreads();
   gj_invert_lds(n, M, col, rowk);
   for (int t = threadIdx.x; t < nn; t += blockDim.x) A[t] = M[t];
+}
+__global__ __launch_bounds__(kInvThreads) void dense_invert_lds_kernel(int n, double *A) {
+  dense_invert_lds_body(n, A);
+}
+// one workgroup per matrix of the group
+__global__ __launch_bounds__(kInvThreads) void dense_invert_lds_group_kernel(int n, GroupTab<double *> A) {
+  dense_invert_lds_body(n, A.v[blockIdx.z]);
 }
 
 // a double from lane `lane` of the wave (two 32-bit register reads)
@@ -287,8 +315,7 @@ __device__ __forceinline__ double read_lane_f64(double v, int lane) {
 // 16 w .. 16 w + 15 in registers.  Step k: the wave holding row k publishes it
 // through LDS (double-buffered, one four-wave barrier per step), and every lane
 // reads the pivot column entries of its own rows from lane k of its own wave.
-__global__ __launch_bounds__(256) void gj_panel_inv_kernel(int n, const double *A, int k0, int kb,
-                                                           double *P) {
+__device__ __forceinline__ void gj_panel_inv_body(int n, const double *A, int k0, int kb, double *P) {
   __shared__ double piv[2][kGjNb];
   const int c = threadIdx.x % kGjNb, w = threadIdx.x / kGjNb;
   double M[16];
@@ -318,13 +345,20 @@ __global__ __launch_bounds__(256) void gj_panel_inv_kernel(int n, const double *
     if (r < kb && c < kb) P[r * kb + c] = M[i];
   }
 }
+__global__ __launch_bounds__(256) void gj_panel_inv_kernel(int n, const double *A, int k0, int kb,
+                                                           double *P) {
+  gj_panel_inv_body(n, A, k0, kb, P);
+}
+__global__ __launch_bounds__(256) void gj_panel_inv_group_kernel(int n, GroupTab<double *> A, int k0, int kb,
+                                                                 GroupTab<double *> W) {
+  gj_panel_inv_body(n, A.v[blockIdx.z], k0, kb, W.v[blockIdx.z]);
+}
 
 // Blocks 0..nt-1: A_Kj <- P A_Kj on column tile j (the panel's own tile skipped);
 // one block reads its whole kb x kGjNb input before writing it back.
 // Blocks nt..2nt-1: C_i = A_iK on row tile i (rows outside K), C row-major n x kb.
 // The two roles touch disjoint parts of A.
-__global__ __launch_bounds__(256) void gj_panel_rows_kernel(int n, double *A, int k0, int kb,
-                                                            const double *P, double *C) {
+__device__ __forceinline__ void gj_panel_rows_body(int n, double *A, int k0, int kb, const double *P, double *C) {
   const int nt = (n + kGjNb - 1) / kGjNb, kt = k0 / kGjNb;
   const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
   if ((int)blockIdx.x >= nt) {
@@ -367,11 +401,20 @@ __global__ __launch_bounds__(256) void gj_panel_rows_kernel(int n, double *A, in
       if (r < kb && c < cols) A[(int64_t)(k0 + r) * n + j0 + c] = acc[a][b];
     }
 }
+__global__ __launch_bounds__(256) void gj_panel_rows_kernel(int n, double *A, int k0, int kb,
+                                                            const double *P, double *C) {
+  gj_panel_rows_body(n, A, k0, kb, P, C);
+}
+__global__ __launch_bounds__(256) void gj_panel_rows_group_kernel(int n, GroupTab<double *> A, int k0, int kb,
+                                                                  GroupTab<double *> W) {
+  double *P = W.v[blockIdx.z];
+  gj_panel_rows_body(n, A.v[blockIdx.z], k0, kb, P, P + kGjNb * kGjNb);
+}
 
 // Tile (i, j) of kGjNb x kGjNb: A_ij <- A_ij - C_i A_Kj (j outside K), A_iK <- -C_i P,
 // A_KK <- P; the panel's rows are otherwise final already.
-__global__ __launch_bounds__(256) void gj_update_kernel(int n, double *A, int k0, int kb,
-                                                        const double *P, const double *C) {
+__device__ __forceinline__ void gj_update_body(int n, double *A, int k0, int kb, const double *P,
+                                               const double *C) {
   const int kt = k0 / kGjNb, it = blockIdx.y, jt = blockIdx.x;
   const int i0 = it * kGjNb, j0 = jt * kGjNb;
   const int rows = min(kGjNb, n - i0), cols = min(kGjNb, n - j0);
@@ -416,6 +459,15 @@ __global__ __launch_bounds__(256) void gj_update_kernel(int n, double *A, int k0
       }
     }
 }
+__global__ __launch_bounds__(256) void gj_update_kernel(int n, double *A, int k0, int kb,
+                                                        const double *P, const double *C) {
+  gj_update_body(n, A, k0, kb, P, C);
+}
+__global__ __launch_bounds__(256) void gj_update_group_kernel(int n, GroupTab<double *> A, int k0, int kb,
+                                                              GroupTab<double *> W) {
+  const double *P = W.v[blockIdx.z];
+  gj_update_body(n, A.v[blockIdx.z], k0, kb, P, P + kGjNb * kGjNb);
+}
 
 size_t dense_invert_work(int n) {
   return n <= kLdsDense ? 0 : (size_t)kGjNb * kGjNb + (size_t)n * kGjNb;
@@ -438,6 +490,29 @@ hipError_t launch_dense_invert(hipStream_t s, int n, double *A, double *work) {
     gj_panel_inv_kernel<<<1, 256, 0, s>>>(n, A, k0, kb, P);
     gj_panel_rows_kernel<<<2 * nt, 256, 0, s>>>(n, A, k0, kb, P, C);
     gj_update_kernel<<<dim3(nt, nt), 256, 0, s>>>(n, A, k0, kb, P, C);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_dense_invert_group(hipStream_t s, int G, int n, double *const *A, double *const *work) {
+  if (!group_ok(G) || n < 1 || n > kMaxDense) return hipErrorInvalidValue;
+  const GroupTab<double *> a = group_tab(G, A);
+  if (n <= kLdsDense) {
+    const size_t shm = ((size_t)n * n + 2 * (size_t)n) * sizeof(double);
+    (void)hipFuncSetAttribute((const void *)dense_invert_lds_group_kernel,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+    dense_invert_lds_group_kernel<<<dim3(1, 1, G), kInvThreads, shm, s>>>(n, a);
+    return hipGetLastError();
+  }
+  for (int i = 0; i < G; ++i)
+    if (!work[i]) return hipErrorInvalidValue;
+  const GroupTab<double *> w = group_tab(G, work);
+  const int nt = (n + kGjNb - 1) / kGjNb;
+  for (int k0 = 0; k0 < n; k0 += kGjNb) {
+    const int kb = std::min(kGjNb, n - k0);
+    gj_panel_inv_group_kernel<<<dim3(1, 1, G), 256, 0, s>>>(n, a, k0, kb, w);
+    gj_panel_rows_group_kernel<<<dim3(2 * nt, 1, G), 256, 0, s>>>(n, a, k0, kb, w);
+    gj_update_group_kernel<<<dim3(nt, nt, G), 256, 0, s>>>(n, a, k0, kb, w);
   }
   return hipGetLastError();
 }

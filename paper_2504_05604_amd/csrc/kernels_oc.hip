@@ -8,6 +8,7 @@
 // spacing while the bracket spans more than a factor 2, linear after) and keeps
 // the sub-interval in which V crosses the target; the bracket shrinks by a
 // factor 64 per pass instead of 2 per bisection step, and the host never waits.
+#include "group_host.h"
 #include "internal.h"
 #include "reduce_dev.h"
 
@@ -47,10 +48,10 @@ __device__ void oc_make_candidates(Scalars *sc) {
   }
 }
 
-__global__ void oc_prepare_kernel(int64_t nel, const double *__restrict__ x,
-                                  const double *__restrict__ dc, const double *__restrict__ dv,
-                                  const int8_t *__restrict__ mask, double eta,
-                                  double *__restrict__ a, double *partials) {
+__device__ __forceinline__ void oc_prepare_body(int64_t nel, const double *__restrict__ x,
+                                                const double *__restrict__ dc, const double *__restrict__ dv,
+                                                const int8_t *__restrict__ mask, double eta,
+                                                double *__restrict__ a, double *partials) {
   double cst = 0.0;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nel;
        e += (int64_t)gridDim.x * blockDim.x) {
@@ -64,8 +65,18 @@ __global__ void oc_prepare_kernel(int64_t nel, const double *__restrict__ x,
   double v[1] = {cst};
   block_reduce_store<1, false>(v, partials, blockIdx.x);
 }
+__global__ void oc_prepare_kernel(int64_t nel, const double *__restrict__ x,
+                                  const double *__restrict__ dc, const double *__restrict__ dv,
+                                  const int8_t *__restrict__ mask, double eta,
+                                  double *__restrict__ a, double *partials) {
+  oc_prepare_body(nel, x, dc, dv, mask, eta, a, partials);
+}
+__global__ void oc_prepare_group_kernel(int64_t nel, GroupTab<OcArgs> t, GroupTab<double *> part) {
+  const OcArgs &o = t.v[blockIdx.z];
+  oc_prepare_body(nel, o.x, o.dc, o.dv, o.mask, o.eta, o.a, part.v[blockIdx.z]);
+}
 
-__global__ void oc_init_kernel(Scalars *sc, double target) {
+__device__ __forceinline__ void oc_init_body(Scalars *sc, double target) {
   sc->target = target;
   sc->l1 = 1e-40;  // the multiplier is positive; this stands for the lower end 0
   sc->l2 = 1e40;
@@ -73,16 +84,19 @@ __global__ void oc_init_kernel(Scalars *sc, double target) {
   sc->oc_pass = 0;
   oc_make_candidates(sc);
 }
+__global__ void oc_init_kernel(Scalars *sc, double target) { oc_init_body(sc, target); }
+// one thread per problem
+__global__ void oc_init_group_kernel(GroupTab<OcArgs> t) {
+  const OcArgs &o = t.v[threadIdx.x];
+  oc_init_body(o.sc, o.target);
+}
 
 // Partial volumes of one block for every candidate multiplier.
 template <bool kStored>
-__global__ __launch_bounds__(kBs) void oc_pass_kernel(int64_t nel, const double *__restrict__ x,
-                                                      const double *__restrict__ a,
-                                                      const double *__restrict__ dc,
-                                                      const double *__restrict__ dv,
-                                                      const int8_t *__restrict__ mask, double move,
-                                                      double eta, const Scalars *sc,
-                                                      double *partials) {
+__device__ __forceinline__ void oc_pass_body(int64_t nel, const double *__restrict__ x,
+                                             const double *__restrict__ a, const double *__restrict__ dc,
+                                             const double *__restrict__ dv, const int8_t *__restrict__ mask,
+                                             double move, double eta, const Scalars *sc, double *partials) {
   if (sc->oc_done) return;
   __shared__ double lampow[kOcCand];
   __shared__ double sh[kOcCand][kBs / 64];
@@ -111,12 +125,26 @@ __global__ __launch_bounds__(kBs) void oc_pass_kernel(int64_t nel, const double 
     partials[(size_t)blockIdx.x * kOcStride + c] = t;
   }
 }
+template <bool kStored>
+__global__ __launch_bounds__(kBs) void oc_pass_kernel(int64_t nel, const double *__restrict__ x,
+                                                      const double *__restrict__ a,
+                                                      const double *__restrict__ dc,
+                                                      const double *__restrict__ dv,
+                                                      const int8_t *__restrict__ mask, double move,
+                                                      double eta, const Scalars *sc,
+                                                      double *partials) {
+  oc_pass_body<kStored>(nel, x, a, dc, dv, mask, move, eta, sc, partials);
+}
+__global__ __launch_bounds__(kBs) void oc_pass_group_kernel(int64_t nel, GroupTab<OcArgs> t,
+                                                            GroupTab<double *> part) {
+  const OcArgs &o = t.v[blockIdx.z];
+  oc_pass_body<true>(nel, o.x, o.a, o.dc, o.dv, o.mask, o.move, o.eta, o.sc, part.v[blockIdx.z]);
+}
 
 // Sums the pass partials (fixed order: 4 interleaved lanes per candidate, then
 // a fixed pairwise combine), keeps the crossing sub-interval.
 constexpr int kSelThreads = 256;
-__global__ __launch_bounds__(kSelThreads) void oc_select_kernel(int nparts, double tol, Scalars *sc,
-                                                                const double *partials) {
+__device__ __forceinline__ void oc_select_body(int nparts, double tol, Scalars *sc, const double *partials) {
   if (sc->oc_done) return;
   __shared__ double V[kOcCand];
   const int c = threadIdx.x >> 2, part = threadIdx.x & 3;  // 64 candidates x 4 lanes
@@ -155,13 +183,23 @@ __global__ __launch_bounds__(kSelThreads) void oc_select_kernel(int nparts, doub
   else
     oc_make_candidates(sc);
 }
+__global__ __launch_bounds__(kSelThreads) void oc_select_kernel(int nparts, double tol, Scalars *sc,
+                                                                const double *partials) {
+  oc_select_body(nparts, tol, sc, partials);
+}
+// one block per problem
+__global__ __launch_bounds__(kSelThreads) void oc_select_group_kernel(int nparts, GroupTab<OcArgs> t,
+                                                                      GroupTab<double *> part) {
+  const OcArgs &o = t.v[blockIdx.x];
+  oc_select_body(nparts, o.tol, o.sc, part.v[blockIdx.x]);
+}
 
 template <bool kStored>
-__global__ void oc_final_kernel(int64_t nel, const double *__restrict__ x,
-                                const double *__restrict__ a, const double *__restrict__ dc,
-                                const double *__restrict__ dv, const int8_t *__restrict__ mask,
-                                double move, double eta, double *__restrict__ xnew, Scalars *sc,
-                                double *partials) {
+__device__ __forceinline__ void oc_final_body(int64_t nel, const double *__restrict__ x,
+                                              const double *__restrict__ a, const double *__restrict__ dc,
+                                              const double *__restrict__ dv, const int8_t *__restrict__ mask,
+                                              double move, double eta, double *__restrict__ xnew, Scalars *sc,
+                                              double *partials) {
   const double lam = 0.5 * (sc->l1 + sc->l2);
   const double lp = pow(lam, -eta);
   double chg = 0.0, vol = 0.0;
@@ -178,6 +216,18 @@ __global__ void oc_final_kernel(int64_t nel, const double *__restrict__ x,
   double vs[1] = {vol};
   block_reduce_store<1, false>(vs, partials + 1, blockIdx.x);
   if (blockIdx.x == 0 && threadIdx.x == 0) sc->lambda = lam;
+}
+template <bool kStored>
+__global__ void oc_final_kernel(int64_t nel, const double *__restrict__ x,
+                                const double *__restrict__ a, const double *__restrict__ dc,
+                                const double *__restrict__ dv, const int8_t *__restrict__ mask,
+                                double move, double eta, double *__restrict__ xnew, Scalars *sc,
+                                double *partials) {
+  oc_final_body<kStored>(nel, x, a, dc, dv, mask, move, eta, xnew, sc, partials);
+}
+__global__ void oc_final_group_kernel(int64_t nel, GroupTab<OcArgs> t, GroupTab<double *> part) {
+  const OcArgs &o = t.v[blockIdx.z];
+  oc_final_body<true>(nel, o.x, o.a, o.dc, o.dv, o.mask, o.move, o.eta, o.xnew, o.sc, part.v[blockIdx.z]);
 }
 
 static unsigned oc_blocks(int64_t nel, int cap) {
@@ -227,6 +277,50 @@ hipError_t launch_oc_final(hipStream_t s, int64_t nel, const double *x, const do
   if (e != hipSuccess) return e;
   Reducer r2{red.partials + 1, red.max_blocks};
   return launch_finalize(s, r2, (int)nb, 1, fin_sum(&sc->volume));
+}
+
+
+// ---------------------------------------------------------------------------
+// The same update for G problems with equally many elements: every launch
+// above serves the whole group (stored coefficients only)
+hipError_t launch_oc_update_group(hipStream_t s, int G, int64_t nel, const OcArgs *o, const Reducer *red) {
+  if (!group_ok(G)) return hipErrorInvalidValue;
+  for (int i = 0; i < G; ++i)
+    if (!o[i].a) return hipErrorInvalidValue;
+  const GroupTab<OcArgs> t = group_tab(G, o);
+  const GroupTab<double *> part = group_partials(G, red);
+  const int *noskip[kMaxGroup] = {};
+  Fin fin[kMaxGroup];
+  // prepare: coefficients and the volume of the passive elements
+  const unsigned nr = oc_blocks(nel, kOcReduceBlocks);
+  oc_prepare_group_kernel<<<dim3(nr, 1, G), kBs, 0, s>>>(nel, t, part);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  for (int i = 0; i < G; ++i) fin[i] = fin_sum(&o[i].sc->vconst);
+  e = launch_finalize_group(s, G, red, (int)nr, 1, fin, noskip);
+  if (e != hipSuccess) return e;
+  oc_init_group_kernel<<<1, G, 0, s>>>(t);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  // multisection passes
+  const unsigned np = oc_blocks(nel, kOcPassBlocks);
+  for (int pass = 0; pass < kOcPasses; ++pass) {
+    oc_pass_group_kernel<<<dim3(np, 1, G), kBs, 0, s>>>(nel, t, part);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    oc_select_group_kernel<<<G, kSelThreads, 0, s>>>((int)np, t, part);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  // final: new design, its change and volume
+  oc_final_group_kernel<<<dim3(nr, 1, G), kBs, 0, s>>>(nel, t, part);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  for (int i = 0; i < G; ++i) fin[i] = fin_max(&o[i].sc->change);
+  e = launch_finalize_group(s, G, red, (int)nr, 1, fin, noskip);
+  if (e != hipSuccess) return e;
+  Reducer r2[kMaxGroup];
+  for (int i = 0; i < G; ++i) {
+    r2[i] = Reducer{red[i].partials + 1, red[i].max_blocks};
+    fin[i] = fin_sum(&o[i].sc->volume);
+  }
+  return launch_finalize_group(s, G, r2, (int)nr, 1, fin, noskip);
 }
 
 }  // namespace topo

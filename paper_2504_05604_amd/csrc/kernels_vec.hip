@@ -2,6 +2,7 @@
 // All reductions are deterministic (block partials summed in a fixed order).
 // Kernels of the CG loop take a `skip` flag (device int, may be NULL): once the
 // loop has converged every later kernel of a replayed chunk returns at once.
+#include "group_host.h"
 #include "internal.h"
 #include "reduce_dev.h"
 
@@ -23,13 +24,19 @@ inline unsigned red_blocks(int64_t n, const Reducer &red) {
 __device__ __forceinline__ bool skipped(const int *skip) { return skip != nullptr && *skip != 0; }
 }  // namespace
 
-__global__ void zero_fixed_kernel(int64_t nnodes, const uint8_t *fixed, double *v) {
+__device__ __forceinline__ void zero_fixed_body(int64_t nnodes, const uint8_t *fixed, double *v) {
   const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (n >= nnodes) return;
   const uint8_t f = fixed[n];
   if (f & 1) v[3 * n + 0] = 0.0;
   if (f & 2) v[3 * n + 1] = 0.0;
   if (f & 4) v[3 * n + 2] = 0.0;
+}
+__global__ void zero_fixed_kernel(int64_t nnodes, const uint8_t *fixed, double *v) {
+  zero_fixed_body(nnodes, fixed, v);
+}
+__global__ void zero_fixed_group_kernel(int64_t nnodes, GroupTab<const uint8_t *> fixed, GroupTab<double *> v) {
+  zero_fixed_body(nnodes, fixed.v[blockIdx.z], v.v[blockIdx.z]);
 }
 
 hipError_t launch_zero_fixed(hipStream_t s, int64_t nnodes, const uint8_t *fixed, double *v) {
@@ -95,6 +102,33 @@ hipError_t launch_dot(hipStream_t s, int64_t n, const double *a, const double *b
   return e != hipSuccess ? e : launch_finalize(s, red, (int)nb, 1, fin, skip);
 }
 
+// nv <= kMaxRed dot products a_k . b in one pass; every value is summed in the
+// order of dot_body (the same per-thread chains, block tree and finalize), so
+// each equals the separate dot product bit for bit
+__device__ __forceinline__ void multi_dot_body(int64_t n, const MultiDotArgs &m, double *partials) {
+  double t[kMaxRed] = {};
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const double bi = m.b[i];
+#pragma unroll
+    for (int k = 0; k < kMaxRed; ++k)
+      if (k < m.nv) t[k] = fma(m.a[k][i], bi, t[k]);
+  }
+  block_reduce_store<kMaxRed, false>(t, partials, blockIdx.x);
+}
+__global__ void multi_dot_kernel(int64_t n, MultiDotArgs m, double *partials) { multi_dot_body(n, m, partials); }
+__global__ void multi_dot_group_kernel(int64_t n, GroupTab<MultiDotArgs> t, GroupTab<double *> part) {
+  multi_dot_body(n, t.v[blockIdx.z], part.v[blockIdx.z]);
+}
+
+hipError_t launch_multi_dot(hipStream_t s, int64_t n, const MultiDotArgs &m, const Reducer &red, const Fin &fin) {
+  if (m.nv < 1 || m.nv > kMaxRed) return hipErrorInvalidValue;
+  const unsigned nb = red_blocks(n, red);
+  multi_dot_kernel<<<nb, kBs, 0, s>>>(n, m, red.partials);
+  hipError_t e = hipGetLastError();
+  return e != hipSuccess ? e : launch_finalize(s, red, (int)nb, m.nv, fin);
+}
+
 // r32 (optional): the new residual rounded to FP32 as well, the right-hand side
 // of a single-precision preconditioner
 __device__ __forceinline__ void cg_update_xr_body(int64_t n, const Scalars *sc, double *x, double *r,
@@ -133,13 +167,19 @@ hipError_t launch_cg_update_xr(hipStream_t s, int64_t n, Scalars *sc, double *x,
   return e != hipSuccess ? e : launch_finalize(s, red, (int)nb, 1, fin, skip);
 }
 
-__global__ void cg_start_kernel(Scalars *sc, double rtol2, int max_iters) {
+__device__ __forceinline__ void cg_start_body(Scalars *sc, double rtol2, int max_iters) {
   sc->cg_iters = 0;
   sc->rtol2 = rtol2;
   sc->cg_max = max_iters;
   sc->nn_fallback = 0;
   sc->rz = 1.0;  // the first r.z finalize forms a beta that is never used: keep it finite
   sc->cg_done = !(sc->rr > rtol2 * sc->ff) || max_iters <= 0;
+}
+__global__ void cg_start_kernel(Scalars *sc, double rtol2, int max_iters) { cg_start_body(sc, rtol2, max_iters); }
+// one thread per problem
+__global__ void cg_start_group_kernel(GroupTab<CgStartArgs> t) {
+  const CgStartArgs &a = t.v[threadIdx.x];
+  cg_start_body(a.sc, a.rtol2, a.max_iters);
 }
 
 hipError_t launch_cg_start(hipStream_t s, Scalars *sc, double rtol2, int max_iters) {
@@ -264,10 +304,18 @@ hipError_t launch_cheb_start(hipStream_t s, int64_t n, const float *res, const f
 
 // Precision conversions at the boundary of a single-precision preconditioner.
 template <typename S, typename D>
-__global__ void convert_kernel(int64_t n, const S *in, D *out, const int *skip) {
+__device__ __forceinline__ void convert_body(int64_t n, const S *in, D *out, const int *skip) {
   if (skipped(skip)) return;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) out[i] = (D)in[i];
+}
+template <typename S, typename D>
+__global__ void convert_kernel(int64_t n, const S *in, D *out, const int *skip) {
+  convert_body(n, in, out, skip);
+}
+__global__ void convert_group_kernel(int64_t n, GroupTab<ConvertArgs> t) {
+  const ConvertArgs &a = t.v[blockIdx.z];
+  convert_body(n, a.in, a.out, a.skip);
 }
 
 hipError_t launch_convert(hipStream_t s, int64_t n, const double *in, float *out, const int *skip) {
@@ -322,12 +370,16 @@ hipError_t launch_flex_dot(hipStream_t s, int64_t n, const float *res, const flo
 }
 
 // linear extrapolation of the solution sequence: u_prev <- u, u <- 2 u - u_prev_old
-__global__ void extrapolate_kernel(int64_t n, double *u, double *u_prev) {
+__device__ __forceinline__ void extrapolate_body(int64_t n, double *u, double *u_prev) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const double cur = u[i], old = u_prev[i];
   u_prev[i] = cur;
   u[i] = 2.0 * cur - old;
+}
+__global__ void extrapolate_kernel(int64_t n, double *u, double *u_prev) { extrapolate_body(n, u, u_prev); }
+__global__ void extrapolate_group_kernel(int64_t n, GroupTab<double *> u, GroupTab<double *> u_prev) {
+  extrapolate_body(n, u.v[blockIdx.z], u_prev.v[blockIdx.z]);
 }
 
 hipError_t launch_extrapolate(hipStream_t s, int64_t n, double *u, double *u_prev) {
@@ -335,19 +387,17 @@ hipError_t launch_extrapolate(hipStream_t s, int64_t n, double *u, double *u_pre
   return hipGetLastError();
 }
 
-// u = sum_k alpha_k v_k (up to 4 vectors)
-struct Combo {
-  const double *v[4];
-  double alpha[4];
-  int n;
-};
-
-__global__ void combine_kernel(int64_t n, Combo c, double *u) {
+// u = sum_k alpha_k v_k (up to 4 vectors; Combo in internal.h)
+__device__ __forceinline__ void combine_body(int64_t n, const Combo &c, double *u) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   double t = 0.0;
   for (int k = 0; k < c.n; ++k) t = fma(c.alpha[k], c.v[k][i], t);
   u[i] = t;
+}
+__global__ void combine_kernel(int64_t n, Combo c, double *u) { combine_body(n, c, u); }
+__global__ void combine_group_kernel(int64_t n, GroupTab<Combo> c, GroupTab<double *> u) {
+  combine_body(n, c.v[blockIdx.z], u.v[blockIdx.z]);
 }
 
 hipError_t launch_combine(hipStream_t s, int64_t n, int nv, const double *const *v, const double *alpha, double *u) {
@@ -364,26 +414,6 @@ hipError_t launch_combine(hipStream_t s, int64_t n, int nv, const double *const 
 
 // ---------------------------------------------------------------------------
 // grouped launchers (one launch for G problems of equal size; see internal.h)
-namespace {
-template <class A>
-GroupTab<A> group_tab(int G, const A *a) {
-  GroupTab<A> t{};
-  for (int i = 0; i < G; ++i) t.v[i] = a[i];
-  return t;
-}
-GroupTab<double *> group_partials(int G, const Reducer *red) {
-  GroupTab<double *> t{};
-  for (int i = 0; i < G; ++i) t.v[i] = red[i].partials;
-  return t;
-}
-template <class A>
-GroupTab<const int *> group_skips(int G, const A *a) {
-  GroupTab<const int *> t{};
-  for (int i = 0; i < G; ++i) t.v[i] = a[i].skip;
-  return t;
-}
-bool group_ok(int G) { return G >= 1 && G <= kMaxGroup; }
-}  // namespace
 
 hipError_t launch_dot_group(hipStream_t s, int G, int64_t n, const DotArgs *a, const Reducer *red, const Fin *fin) {
   if (!group_ok(G)) return hipErrorInvalidValue;
@@ -434,5 +464,73 @@ hipError_t launch_cheb_start_group(hipStream_t s, int G, int64_t n, T inv_theta,
 }
 template hipError_t launch_cheb_start_group<double>(hipStream_t, int, int64_t, double, const ChebStartArgs<double> *);
 template hipError_t launch_cheb_start_group<float>(hipStream_t, int, int64_t, float, const ChebStartArgs<float> *);
+
+hipError_t launch_zero_fixed_group(hipStream_t s, int G, int64_t nnodes, const uint8_t *const *fixed,
+                                   double *const *v) {
+  if (!group_ok(G)) return hipErrorInvalidValue;
+  zero_fixed_group_kernel<<<dim3(nblocks(nnodes), 1, G), kBs, 0, s>>>(nnodes, group_tab(G, fixed), group_tab(G, v));
+  return hipGetLastError();
+}
+
+hipError_t launch_cg_start_group(hipStream_t s, int G, const CgStartArgs *a) {
+  if (!group_ok(G)) return hipErrorInvalidValue;
+  cg_start_group_kernel<<<1, G, 0, s>>>(group_tab(G, a));
+  return hipGetLastError();
+}
+
+hipError_t launch_convert_group(hipStream_t s, int G, int64_t n, const ConvertArgs *a) {
+  if (!group_ok(G)) return hipErrorInvalidValue;
+  convert_group_kernel<<<dim3(nblocks(n), 1, G), kBs, 0, s>>>(n, group_tab(G, a));
+  return hipGetLastError();
+}
+
+hipError_t launch_extrapolate_group(hipStream_t s, int G, int64_t n, double *const *u, double *const *u_prev) {
+  if (!group_ok(G)) return hipErrorInvalidValue;
+  extrapolate_group_kernel<<<dim3(nblocks(n), 1, G), kBs, 0, s>>>(n, group_tab(G, u), group_tab(G, u_prev));
+  return hipGetLastError();
+}
+
+hipError_t launch_combine_group(hipStream_t s, int G, int64_t n, const Combo *c, double *const *u) {
+  if (!group_ok(G)) return hipErrorInvalidValue;
+  for (int i = 0; i < G; ++i)
+    if (c[i].n < 1 || c[i].n > 4) return hipErrorInvalidValue;
+  combine_group_kernel<<<dim3(nblocks(n), 1, G), kBs, 0, s>>>(n, group_tab(G, c), group_tab(G, u));
+  return hipGetLastError();
+}
+
+hipError_t launch_multi_dot_group(hipStream_t s, int G, int64_t n, const MultiDotArgs *m, const Reducer *red,
+                                  const Fin *fin) {
+  if (!group_ok(G)) return hipErrorInvalidValue;
+  for (int i = 0; i < G; ++i)
+    if (m[i].nv != m[0].nv || m[i].nv < 1 || m[i].nv > kMaxRed) return hipErrorInvalidValue;
+  const unsigned nb = red_blocks(n, red[0]);
+  multi_dot_group_kernel<<<dim3(nb, 1, G), kBs, 0, s>>>(n, group_tab(G, m), group_partials(G, red));
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int *sk[kMaxGroup] = {};
+  return launch_finalize_group(s, G, red, (int)nb, m[0].nv, fin, sk);
+}
+
+// plain copies and zero fills of G equally long buffers (32-bit words: every
+// buffer here holds doubles or floats)
+__global__ void copy_words_group_kernel(int64_t nw, GroupTab<const uint32_t *> src, GroupTab<uint32_t *> dst) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nw) return;
+  const uint32_t *sp = src.v[blockIdx.z];
+  dst.v[blockIdx.z][i] = sp ? sp[i] : 0u;
+}
+
+hipError_t launch_copy_group(hipStream_t s, int G, int64_t bytes, const void *const *src, void *const *dst) {
+  if (!group_ok(G) || bytes % 4 != 0) return hipErrorInvalidValue;
+  GroupTab<const uint32_t *> a{};
+  GroupTab<uint32_t *> b{};
+  for (int i = 0; i < G; ++i) {
+    a.v[i] = src ? (const uint32_t *)src[i] : nullptr;
+    b.v[i] = (uint32_t *)dst[i];
+  }
+  const int64_t nw = bytes / 4;
+  copy_words_group_kernel<<<dim3(nblocks(nw), 1, G), kBs, 0, s>>>(nw, a, b);
+  return hipGetLastError();
+}
 
 }  // namespace topo

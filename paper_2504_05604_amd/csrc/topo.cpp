@@ -720,29 +720,28 @@ static void sym_eig(std::vector<double> A, int n, std::vector<double> &w, std::v
   for (int i = 0; i < n; ++i) w[i] = A[i * n + i];
 }
 
-static topo_status projected_start(topo_ctx *ctx) {
-  hipStream_t s = ctx->stream;
-  const int nb = ctx->nbasis;
-  Level &L0 = ctx->lv[0];
-  // Gram matrix G_ij = u_i . K u_j (upper triangle) and g_i = u_i . f
-  for (int j = 0; j < nb; ++j) {
-    KuArgs a = ku_args(ctx, L0, ctx->basis[j]);
-    a.y = ctx->tmp;
-    TOPO_HIP(launch_ku(s, KU_STORE, a, ctx->kap, ctx->red, fin_sum(nullptr)));
-    for (int i = 0; i <= j; ++i)
-      TOPO_HIP(launch_dot(s, ctx->ndof, ctx->basis[i], ctx->tmp, ctx->red, fin_sum(&ctx->gram[i * kMaxBasis + j])));
-    TOPO_HIP(launch_dot(s, ctx->ndof, ctx->basis[j], ctx->f, ctx->red, fin_sum(&ctx->gram[kMaxBasis * kMaxBasis + j])));
-  }
-  double h[kMaxBasis * kMaxBasis + kMaxBasis];
-  TOPO_HIP(hipMemcpyAsync(h, ctx->gram, sizeof(h), hipMemcpyDeviceToHost, s));
-  TOPO_HIP(hipStreamSynchronize(s));
+// the dot products of column j of the Gram matrix: basis[0..j] against b
+// (j = nbasis with b = f: the right-hand side g)
+static MultiDotArgs gram_column(const topo_ctx *ctx, int j, const double *b) {
+  MultiDotArgs m{};
+  m.nv = std::min(j + 1, ctx->nbasis);
+  for (int i = 0; i < m.nv; ++i) m.a[i] = ctx->basis[i];
+  m.b = b;
+  return m;
+}
+
+// Coefficients of the Galerkin projection u = sum_i alpha_i u_i of the new
+// solution onto the stored ones: G alpha = g, G solved through its eigenpairs
+// with the (numerically) null directions dropped.  h: the Gram matrix read
+// back from the device (layout above).  False when a coefficient is not finite.
+static bool projection_coefficients(const double *h, int nb, double *alpha) {
   std::vector<double> G(nb * nb), w, V;
-  for (int i = 0; i < nb; ++i)
-    for (int j = i; j < nb; ++j) G[i * nb + j] = G[j * nb + i] = h[i * kMaxBasis + j];
+  for (int j = 0; j < nb; ++j)
+    for (int i = 0; i <= j; ++i) G[i * nb + j] = G[j * nb + i] = h[j * kMaxBasis + i];
   sym_eig(G, nb, w, V);
   double wmax = 0.0;
   for (double v : w) wmax = std::max(wmax, v);
-  double alpha[kMaxBasis] = {0.0, 0.0, 0.0, 0.0};
+  for (int i = 0; i < kMaxBasis; ++i) alpha[i] = 0.0;
   for (int k = 0; k < nb; ++k) {
     if (!(w[k] > 1e-12 * wmax)) continue;
     double qg = 0.0;
@@ -750,7 +749,30 @@ static topo_status projected_start(topo_ctx *ctx) {
     for (int i = 0; i < nb; ++i) alpha[i] += V[i * nb + k] * qg / w[k];
   }
   for (int i = 0; i < nb; ++i)
-    if (!std::isfinite(alpha[i])) return TOPO_OK;  // keep the plain warm start
+    if (!std::isfinite(alpha[i])) return false;
+  return true;
+}
+
+static topo_status projected_start(topo_ctx *ctx) {
+  hipStream_t s = ctx->stream;
+  const int nb = ctx->nbasis;
+  Level &L0 = ctx->lv[0];
+  // Gram matrix G_ij = u_i . K u_j (column j: i <= j, at gram[j kMaxBasis + i])
+  // and g_i = u_i . f (at gram[kMaxBasis^2 + i])
+  for (int j = 0; j < nb; ++j) {
+    KuArgs a = ku_args(ctx, L0, ctx->basis[j]);
+    a.y = ctx->tmp;
+    TOPO_HIP(launch_ku(s, KU_STORE, a, ctx->kap, ctx->red, fin_sum(nullptr)));
+    TOPO_HIP(launch_multi_dot(s, ctx->ndof, gram_column(ctx, j, ctx->tmp), ctx->red,
+                              fin_sum(&ctx->gram[j * kMaxBasis])));
+  }
+  TOPO_HIP(launch_multi_dot(s, ctx->ndof, gram_column(ctx, nb, ctx->f), ctx->red,
+                            fin_sum(&ctx->gram[kMaxBasis * kMaxBasis])));
+  double h[kMaxBasis * kMaxBasis + kMaxBasis];
+  TOPO_HIP(hipMemcpyAsync(h, ctx->gram, sizeof(h), hipMemcpyDeviceToHost, s));
+  TOPO_HIP(hipStreamSynchronize(s));
+  double alpha[kMaxBasis];
+  if (!projection_coefficients(h, nb, alpha)) return TOPO_OK;  // keep the plain warm start
   const double *vs[kMaxBasis];
   for (int i = 0; i < nb; ++i) vs[i] = ctx->basis[i];
   TOPO_HIP(launch_combine(s, ctx->ndof, nb, vs, alpha, ctx->u));
@@ -1600,20 +1622,46 @@ static topo_status group_read_scalars(const Group &G) {
 topo_status group_pcg(Group &G, hipGraph_t *graph_out, hipGraphExec_t *exec, hipStream_t cap_stream,
                       topo_solve_stats *stats) {
   const int n = G.n();
-  for (topo_ctx *c : G.c) {
+  for (topo_ctx *c : G.c)
     if (c->stream != G.s) return set_error("grouped CG: the contexts must use the group's stream"), TOPO_EINVAL;
-    const int64_t nd = c->ndof;
-    Level &L0 = c->lv[0];
-    TOPO_HIP(launch_zero_fixed(G.s, c->nnodes, L0.fixed, c->u));
-    KuArgs a = ku_args(c, L0, c->u);
-    a.y = c->r;
-    a.b = c->f;
-    TOPO_HIP(launch_ku(G.s, KU_RESID, a, c->kap, c->red, fin_sum(&c->sc->rr)));
-    TOPO_HIP(launch_dot(G.s, nd, c->f, c->f, c->red, fin_sum(&c->sc->ff)));
-    TOPO_HIP(launch_cg_start(G.s, c->sc, c->opts.rtol * c->opts.rtol, c->opts.max_iters));
-    if (c->mixed) {
-      TOPO_HIP(hipMemsetAsync(c->z32, 0, nd * sizeof(float), G.s));
-      TOPO_HIP(launch_convert(G.s, nd, c->r, L0.f32.b, &c->sc->cg_done));
+  // r = f - K u, rr, ff and the stopping test of every member (the launches of
+  // pcg_run's start, shared by the group)
+  {
+    topo_ctx *c0 = G.c[0];
+    const int64_t nd = c0->ndof;
+    const std::vector<Reducer> red = group_reds(G);
+    std::vector<const uint8_t *> fx(n);
+    std::vector<double *> uu(n);
+    std::vector<KuArgs> a(n);
+    std::vector<Fin> frr(n), fff(n);
+    std::vector<DotArgs> ff(n);
+    std::vector<CgStartArgs> cs(n);
+    for (int i = 0; i < n; ++i) {
+      topo_ctx *c = G.c[i];
+      fx[i] = c->lv[0].fixed;
+      uu[i] = c->u;
+      a[i] = ku_args(c, c->lv[0], c->u);
+      a[i].y = c->r;
+      a[i].b = c->f;
+      frr[i] = fin_sum(&c->sc->rr);
+      fff[i] = fin_sum(&c->sc->ff);
+      ff[i] = DotArgs{c->f, c->f, nullptr};
+      cs[i] = CgStartArgs{c->sc, c->opts.rtol * c->opts.rtol, c->opts.max_iters};
+    }
+    TOPO_HIP(launch_zero_fixed_group(G.s, n, c0->nnodes, fx.data(), uu.data()));
+    TOPO_HIP(launch_ku_group<double>(G.s, KU_RESID, n, a.data(), c0->kap, red.data(), frr.data(),
+                                     ku_shape_for(c0->g, KU_RESID, TOPO_KU_AUTO, false)));
+    TOPO_HIP(launch_dot_group(G.s, n, nd, ff.data(), red.data(), fff.data()));
+    TOPO_HIP(launch_cg_start_group(G.s, n, cs.data()));
+    if (c0->mixed) {
+      std::vector<void *> z(n);
+      std::vector<ConvertArgs> cv(n);
+      for (int i = 0; i < n; ++i) {
+        z[i] = G.c[i]->z32;
+        cv[i] = ConvertArgs{G.c[i]->r, G.c[i]->lv[0].f32.b, &G.c[i]->sc->cg_done};
+      }
+      TOPO_HIP(launch_copy_group(G.s, n, nd * (int64_t)sizeof(float), nullptr, z.data()));
+      TOPO_HIP(launch_convert_group(G.s, n, nd, cv.data()));
     }
   }
   topo_status st = group_precondition(G);
@@ -1871,24 +1919,308 @@ topo_status iterate_post(topo_ctx *ctx, double *d_x, const topo_solve_stats &ss,
   if (o) {
     st = read_scalars(ctx);
     if (st != TOPO_OK) return st;
-    o->c = ctx->h_sc->comp;
-    o->volume = ctx->h_sc->volume;
-    o->change = ctx->h_sc->change;
-    o->lambda = ctx->h_sc->lambda;
-    o->pcg_iters = ss.iters;
-    o->converged = ss.converged;
-    o->relres = ss.relres;
-    o->fallbacks = ss.fallbacks;
-    o->learned_iters = ss.learned_iters;
-    float t[5];
-    for (int k = 0; k < 5; ++k) (void)hipEventElapsedTime(&t[k], ev[k], ev[k + 1]);
-    float tot = 0.f;
-    (void)hipEventElapsedTime(&tot, ev[0], ev[5]);
-    o->ms_total = tot;
-    o->ms_filter = t[0] + t[3];
-    o->ms_solve = t[1];
-    o->ms_sens = t[2];
-    o->ms_oc = t[4];
+    fill_stats(ctx, ss, ev, o);
+  }
+  return TOPO_OK;
+}
+
+// the stats of one SIMP iteration from the scalars already read back and the
+// six phase events
+void fill_stats(const topo_ctx *ctx, const topo_solve_stats &ss, hipEvent_t *ev, topo_iter_stats *o) {
+  o->c = ctx->h_sc->comp;
+  o->volume = ctx->h_sc->volume;
+  o->change = ctx->h_sc->change;
+  o->lambda = ctx->h_sc->lambda;
+  o->pcg_iters = ss.iters;
+  o->converged = ss.converged;
+  o->relres = ss.relres;
+  o->fallbacks = ss.fallbacks;
+  o->learned_iters = ss.learned_iters;
+  float t[5];
+  for (int k = 0; k < 5; ++k) (void)hipEventElapsedTime(&t[k], ev[k], ev[k + 1]);
+  float tot = 0.f;
+  (void)hipEventElapsedTime(&tot, ev[0], ev[5]);
+  o->ms_total = tot;
+  o->ms_filter = t[0] + t[3];
+  o->ms_solve = t[1];
+  o->ms_sens = t[2];
+  o->ms_oc = t[4];
+}
+
+// ---------------------------------------------------------------------------
+// The rest of a SIMP iteration of a group (iterate_pre / iterate_post of every
+// member, with one launch per step for the whole group).  The members must be
+// in lockstep (the same warm-start history and coarse refresh count), which
+// they are when set up and iterated together; members whose filters differ in
+// reach or mode share the launches of their own kind.
+bool group_lockstep(const Group &G) {
+  const topo_ctx *a = G.c[0];
+  for (const topo_ctx *c : G.c) {
+    if (c->nn || !c->oc_a) return false;
+    if (c->nel != a->nel || c->ndof != a->ndof || c->lv.size() != a->lv.size() || c->ncoarse != a->ncoarse ||
+        c->mixed != a->mixed)
+      return false;
+    if (c->opts.warm_start != a->opts.warm_start || c->have_u != a->have_u || c->n_warm != a->n_warm ||
+        c->nbasis != a->nbasis || c->basis_next != a->basis_next || c->coarse_due != a->coarse_due)
+      return false;
+  }
+  return true;
+}
+
+// op for each member's problem: TOPO_FILTER_* per member (-1: none); members
+// with the same operation and stencil reach share a launch
+static topo_status group_filter(const Group &G, const std::vector<int> &op, const std::vector<FilterCall> &call) {
+  const int n = G.n();
+  std::vector<bool> done(n, false);
+  for (int i = 0; i < n; ++i) {
+    if (done[i] || op[i] < 0) continue;
+    const int R = call[i].f.R;
+    const bool tiled = R >= 1 && R <= kFilterTiledMaxR;
+    std::vector<FilterCall> part;
+    for (int j = i; j < n; ++j) {
+      const int Rj = call[j].f.R;
+      const bool tj = Rj >= 1 && Rj <= kFilterTiledMaxR;
+      if (done[j] || op[j] != op[i] || tj != tiled || (tiled && Rj != R)) continue;
+      part.push_back(call[j]);
+      done[j] = true;
+    }
+    TOPO_HIP(launch_filter_group(G.s, op[i], (int)part.size(), part.data()));
+  }
+  return TOPO_OK;
+}
+
+// prepare_operator for every member
+static topo_status group_prepare_operator(const Group &G, bool refresh) {
+  const int n = G.n();
+  topo_ctx *c0 = G.c[0];
+  hipStream_t s = G.s;
+  std::vector<ModulusArgs> ma(n);
+  for (int i = 0; i < n; ++i) {
+    const topo_problem &P = G.c[i]->prob;
+    ma[i] = ModulusArgs{G.c[i]->xphys, P.E0, P.Emin, P.penal, G.c[i]->lv[0].E};
+  }
+  TOPO_HIP(launch_simp_modulus_group(s, n, c0->nel, ma.data()));
+  for (size_t l = 0; l < c0->lv.size(); ++l) {
+    std::vector<const double *> ef(n);
+    std::vector<double *> ec(n);
+    std::vector<DiagArgs> da(n);
+    for (int i = 0; i < n; ++i) {
+      Level &L = G.c[i]->lv[l];
+      if (l > 0) ef[i] = G.c[i]->lv[l - 1].E, ec[i] = L.E;
+      da[i] = DiagArgs{L.E, G.c[i]->kap, L.fixed, L.dinv};
+    }
+    if (l > 0) TOPO_HIP(launch_coarsen_moduli_group(s, n, c0->lv[l - 1].g, c0->lv[l].g, ef.data(), ec.data()));
+    TOPO_HIP(launch_diag_group(s, n, c0->lv[l].g, da.data()));
+  }
+  if (c0->lv.size() > 1 && refresh) {
+    std::vector<AssembleArgs> aa(n);
+    std::vector<double *> A(n), W(n);
+    for (int i = 0; i < n; ++i) {
+      const Level &C = G.c[i]->lv.back();
+      aa[i] = AssembleArgs{C.E, G.c[i]->kap, C.fixed, G.c[i]->Ainv};
+      A[i] = G.c[i]->Ainv;
+      W[i] = G.c[i]->Awork;
+    }
+    TOPO_HIP(launch_dense_assemble_group(s, n, c0->lv.back().g, aa.data()));
+    TOPO_HIP(launch_dense_invert_group(s, n, c0->ncoarse, A.data(), W.data()));
+  }
+  for (topo_ctx *c : G.c) c->coarse_due = refresh ? c->opts.coarse_refresh : c->coarse_due;
+  if (c0->mixed) {
+    for (size_t l = 0; l < c0->lv.size(); ++l) {
+      std::vector<ConvertArgs> ce(n), cd(n);
+      for (int i = 0; i < n; ++i) {
+        Level &L = G.c[i]->lv[l];
+        ce[i] = ConvertArgs{L.E, L.f32.E, nullptr};
+        cd[i] = ConvertArgs{L.dinv, L.f32.dinv, nullptr};
+      }
+      TOPO_HIP(launch_convert_group(s, n, c0->lv[l].g.nel(), ce.data()));
+      TOPO_HIP(launch_convert_group(s, n, c0->lv[l].g.ndof(), cd.data()));
+    }
+  }
+  return TOPO_OK;
+}
+
+// projected_start for every member: the Gram matrices together, one wait,
+// the combinations of the members whose projection is usable
+static topo_status group_projected_start(const Group &G) {
+  const int n = G.n();
+  topo_ctx *c0 = G.c[0];
+  hipStream_t s = G.s;
+  const int nb = c0->nbasis;
+  const std::vector<Reducer> red = group_reds(G);
+  const int shape = ku_shape_for(c0->g, KU_STORE, TOPO_KU_AUTO, false);
+  std::vector<KuArgs> a(n);
+  std::vector<MultiDotArgs> md(n);
+  std::vector<Fin> fin(n), nofin(n, fin_sum(nullptr));
+  for (int j = 0; j < nb; ++j) {
+    for (int i = 0; i < n; ++i) {
+      topo_ctx *c = G.c[i];
+      a[i] = ku_args(c, c->lv[0], c->basis[j]);
+      a[i].y = c->tmp;
+      md[i] = gram_column(c, j, c->tmp);
+      fin[i] = fin_sum(&c->gram[j * kMaxBasis]);
+    }
+    TOPO_HIP(launch_ku_group<double>(s, KU_STORE, n, a.data(), c0->kap, red.data(), nofin.data(), shape));
+    TOPO_HIP(launch_multi_dot_group(s, n, c0->ndof, md.data(), red.data(), fin.data()));
+  }
+  for (int i = 0; i < n; ++i) {
+    md[i] = gram_column(G.c[i], nb, G.c[i]->f);
+    fin[i] = fin_sum(&G.c[i]->gram[kMaxBasis * kMaxBasis]);
+  }
+  TOPO_HIP(launch_multi_dot_group(s, n, c0->ndof, md.data(), red.data(), fin.data()));
+  constexpr int kGram = kMaxBasis * kMaxBasis + kMaxBasis;
+  std::vector<double> h((size_t)n * kGram);
+  for (int i = 0; i < n; ++i)
+    TOPO_HIP(hipMemcpyAsync(&h[(size_t)i * kGram], G.c[i]->gram, kGram * sizeof(double), hipMemcpyDeviceToHost, s));
+  TOPO_HIP(hipStreamSynchronize(s));
+  std::vector<Combo> cb;
+  std::vector<double *> uu;
+  for (int i = 0; i < n; ++i) {
+    double alpha[kMaxBasis];
+    if (!projection_coefficients(&h[(size_t)i * kGram], nb, alpha)) continue;  // plain warm start
+    Combo c{};
+    c.n = nb;
+    for (int k = 0; k < nb; ++k) {
+      c.v[k] = G.c[i]->basis[k];
+      c.alpha[k] = alpha[k];
+    }
+    cb.push_back(c);
+    uu.push_back(G.c[i]->u);
+  }
+  if (!cb.empty()) TOPO_HIP(launch_combine_group(s, (int)cb.size(), c0->ndof, cb.data(), uu.data()));
+  return TOPO_OK;
+}
+
+topo_status group_pre(const Group &G, double *const *d_x, hipEvent_t *ev) {
+  const int n = G.n();
+  topo_ctx *c0 = G.c[0];
+  hipStream_t s = G.s;
+  (void)hipEventRecord(ev[0], s);
+  // physical densities
+  {
+    std::vector<int> op(n);
+    std::vector<FilterCall> call(n);
+    std::vector<const void *> src;
+    std::vector<void *> dst;
+    for (int i = 0; i < n; ++i) {
+      topo_ctx *c = G.c[i];
+      const bool density = c->prob.filter == TOPO_FILTER_DENSITY;
+      op[i] = density ? TOPO_FILTER_FWD : -1;
+      call[i] = FilterCall{c->filt, d_x[i], nullptr, c->xphys};
+      if (!density) src.push_back(d_x[i]), dst.push_back(c->xphys);
+    }
+    topo_status st = group_filter(G, op, call);
+    if (st != TOPO_OK) return st;
+    if (!src.empty())
+      TOPO_HIP(launch_copy_group(s, (int)src.size(), c0->nel * (int64_t)sizeof(double), src.data(), dst.data()));
+  }
+  (void)hipEventRecord(ev[1], s);
+  // initial guesses
+  std::vector<double *> uu(n), up(n);
+  for (int i = 0; i < n; ++i) uu[i] = G.c[i]->u;
+  if (!c0->opts.warm_start || !c0->have_u) {
+    std::vector<void *> d(uu.begin(), uu.end());
+    TOPO_HIP(launch_copy_group(s, n, c0->ndof * (int64_t)sizeof(double), nullptr, d.data()));
+    for (topo_ctx *c : G.c) c->n_warm = 0, c->nbasis = 0;
+  } else if (c0->opts.warm_start == 2) {
+    for (int i = 0; i < n; ++i) {
+      topo_ctx *ctx = G.c[i];
+      if (!ctx->u_prev) TOPO_ALLOC(ctx->u_prev, ctx->ndof);
+      up[i] = ctx->u_prev;
+    }
+    if (c0->n_warm >= 2) {
+      TOPO_HIP(launch_extrapolate_group(s, n, c0->ndof, uu.data(), up.data()));
+    } else {
+      std::vector<const void *> a(uu.begin(), uu.end());
+      std::vector<void *> b(up.begin(), up.end());
+      TOPO_HIP(launch_copy_group(s, n, c0->ndof * (int64_t)sizeof(double), a.data(), b.data()));
+    }
+  }
+  const bool refresh = c0->coarse_due <= 0;
+  topo_status st = group_prepare_operator(G, refresh);
+  for (topo_ctx *c : G.c) --c->coarse_due;
+  if (st == TOPO_OK && c0->opts.warm_start == 3 && c0->nbasis > 0) st = group_projected_start(G);
+  return st;
+}
+
+topo_status group_post(const Group &G, double *const *d_x, const topo_solve_stats *ss, hipEvent_t *ev,
+                       topo_iter_stats *const *o) {
+  const int n = G.n();
+  topo_ctx *c0 = G.c[0];
+  hipStream_t s = G.s;
+  for (topo_ctx *c : G.c) c->have_u = 1, ++c->n_warm;
+  if (c0->opts.warm_start == 3) {
+    std::vector<const void *> a(n);
+    std::vector<void *> b(n);
+    for (int i = 0; i < n; ++i) {
+      topo_ctx *ctx = G.c[i];
+      if (!ctx->gram) TOPO_ALLOC(ctx->gram, kMaxBasis * kMaxBasis + kMaxBasis);
+      double *&slot = ctx->basis[ctx->basis_next];
+      if (!slot) TOPO_ALLOC(slot, ctx->ndof);
+      a[i] = ctx->u;
+      b[i] = slot;
+      ctx->basis_next = (ctx->basis_next + 1) % kMaxBasis;
+      ctx->nbasis = std::min(ctx->nbasis + 1, kMaxBasis);
+    }
+    TOPO_HIP(launch_copy_group(s, n, c0->ndof * (int64_t)sizeof(double), a.data(), b.data()));
+  }
+  (void)hipEventRecord(ev[2], s);
+  // sensitivities and compliances
+  {
+    std::vector<SensArgs> sa(n);
+    std::vector<DotArgs> fu(n);
+    std::vector<Fin> fin(n);
+    for (int i = 0; i < n; ++i) {
+      topo_ctx *c = G.c[i];
+      const topo_problem &P = c->prob;
+      sa[i] = SensArgs{c->kap, c->u, c->xphys, P.E0, P.Emin, P.penal, c->ce, c->dc};
+      fu[i] = DotArgs{c->f, c->u, nullptr};
+      fin[i] = fin_sum(&c->sc->comp);
+    }
+    TOPO_HIP(launch_sensitivity_group(s, n, c0->g, sa.data()));
+    const std::vector<Reducer> red = group_reds(G);
+    TOPO_HIP(launch_dot_group(s, n, c0->ndof, fu.data(), red.data(), fin.data()));
+  }
+  (void)hipEventRecord(ev[3], s);
+  // filtered sensitivities
+  {
+    std::vector<int> op(n);
+    std::vector<FilterCall> call(n);
+    for (int i = 0; i < n; ++i) {
+      topo_ctx *c = G.c[i];
+      const bool density = c->prob.filter == TOPO_FILTER_DENSITY;
+      op[i] = density ? TOPO_FILTER_ADJ : TOPO_FILTER_SENS;
+      call[i] = FilterCall{c->filt, c->dc, density ? nullptr : d_x[i], c->dcf};
+    }
+    topo_status st = group_filter(G, op, call);
+    if (st != TOPO_OK) return st;
+  }
+  (void)hipEventRecord(ev[4], s);
+  // OC updates into xnew, then the designs
+  {
+    std::vector<OcArgs> oa(n);
+    std::vector<const void *> a(n);
+    std::vector<void *> b(n);
+    for (int i = 0; i < n; ++i) {
+      topo_ctx *c = G.c[i];
+      const topo_problem &P = c->prob;
+      oa[i] = OcArgs{d_x[i], c->dcf, c->volw, c->mask, P.move, P.eta, c->opts.oc_tol, c->target,
+                     c->oc_a, c->xnew, c->sc};
+      a[i] = c->xnew;
+      b[i] = d_x[i];
+    }
+    const std::vector<Reducer> red = group_reds(G);
+    TOPO_HIP(launch_oc_update_group(s, n, c0->nel, oa.data(), red.data()));
+    TOPO_HIP(launch_copy_group(s, n, c0->nel * (int64_t)sizeof(double), a.data(), b.data()));
+  }
+  (void)hipEventRecord(ev[5], s);
+  bool any = false;
+  for (int i = 0; i < n; ++i) any = any || o[i];
+  if (any) {
+    for (topo_ctx *c : G.c) TOPO_HIP(hipMemcpyAsync(c->h_sc, c->sc, sizeof(Scalars), hipMemcpyDeviceToHost, s));
+    TOPO_HIP(hipStreamSynchronize(s));
+    for (int i = 0; i < n; ++i)
+      if (o[i]) fill_stats(G.c[i], ss[i], ev, o[i]);
   }
   return TOPO_OK;
 }

@@ -80,6 +80,38 @@ def test_grouped_launches_equal_separate_streams(precision):
         assert np.array_equal(res[0][0][i], res[1][0][i]), i
         assert [s["c"] for s in res[0][1][i]] == [s["c"] for s in res[1][1][i]], i
         assert [s["pcg_iters"] for s in res[0][1][i]] == [s["pcg_iters"] for s in res[1][1][i]], i
+        assert [s["volume"] for s in res[0][1][i]] == [s["volume"] for s in res[1][1][i]], i
+
+
+@pytest.mark.parametrize("variant", ["extrapolated-sens", "zero-keep-inverse", "last-mixed-reach"])
+def test_grouped_iterations_cover_every_warm_start_and_filter(variant):
+    """Grouped SIMP phases (filter, operator set-up and coarse inverse, warm
+    starts, sensitivities, OC) against per-problem streams, bit for bit, under
+    the other warm starts, the sensitivity filter, a coarse inverse kept for two
+    iterations and stencils of different reach within one group."""
+    ps = [synth.random_problem(300 + s, 16, n_iter=4) for s in range(5)]
+    kw = dict(precision=topo.PREC_FP32)
+    if variant == "extrapolated-sens":
+        kw["warm_start"] = 2
+        for p in ps:
+            p.filter_mode = "sensitivity"
+    elif variant == "zero-keep-inverse":
+        kw.update(warm_start=0, coarse_refresh=2, precision=topo.PREC_FP64)
+    else:
+        kw["warm_start"] = 1
+        for k, p in enumerate(ps):
+            p.rmin = [1.5, 2.5, 3.5, 1.8, 4.5][k]  # reaches 1, 2, 3, 1 and the offset-list kernel
+    res = {}
+    for grouped in (0, 1):
+        with topo.Batch(ps, topo.default_opts(group_launch=grouped, **kw), n_threads=2) as b:
+            xs = [torch.from_numpy(p.initial_design()).to("cuda") for p in ps]
+            st = b.iterate(xs, 4)
+            torch.cuda.synchronize()
+            res[grouped] = ([x.cpu().numpy() for x in xs], st)
+    for i in range(len(ps)):
+        assert np.array_equal(res[0][0][i], res[1][0][i]), i
+        for key in ("c", "pcg_iters", "volume", "change", "lambda"):
+            assert [s[key] for s in res[0][1][i]] == [s[key] for s in res[1][1][i]], (i, key)
 
 
 def test_autotuner_remembers_shapes_per_grid():
