@@ -525,6 +525,50 @@ def lockstep_fp64_error(topo, p, opts, mixed_stats, mixed_ctx):
             "fp64_pcg_iters_mean": round(float(np.mean([s["pcg_iters"] for s in st64])), 2)}
 
 
+def precision_variants(topo, p, opts, args):
+    """The mixed-precision configuration's preconditioner variants on the same
+    160x80x80 workload: FP64 V-cycle (the reference), FP32 on the vector units
+    (the headline mode), FP32 and BF16 operands on the matrix cores.  Each runs
+    1 + variant_steps SIMP iterations from the initial design (the first
+    untimed); compliance and displacement are compared with the FP64 run."""
+    import numpy as np
+    import torch
+
+    from paper_2504_05604_amd._lib import Opts_C
+    n = args.variant_steps
+    modes = (("fp64", topo.PREC_FP64, 0), ("fp32", topo.PREC_FP32, 0), ("fp32_matrix_cores", topo.PREC_FP32, 1),
+             ("bf16_matrix_cores", topo.PREC_BF16, 0))
+    runs = {}
+    for name, prec, mfma in modes:
+        o = Opts_C.from_buffer_copy(opts)
+        o.precision = prec
+        o.mfma_smoothing = mfma
+        with topo.Context(p, o) as ctx:
+            x = torch.from_numpy(p.initial_design()).to("cuda")
+            st = ctx.iterate(x, 1, raise_on_nonconv=False)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st += ctx.iterate(x, n, raise_on_nonconv=False)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            u = torch.empty(p.ndof, dtype=torch.float64, device="cuda")
+            ctx.get_state(u=u)
+        runs[name] = (st, u, 1e3 * dt / n)
+    st64, u64, _ = runs["fp64"]
+    out = {"workload": "cantilever-160x80x80, the headline options with each preconditioner precision",
+           "timed_iterations": n, "untimed_first": 1}
+    for name, (st, u, ms) in runs.items():
+        out[name] = {
+            "ms_per_simp_iteration": round(ms, 3),
+            "pcg_iters_mean": round(float(np.mean([s["pcg_iters"] for s in st])), 2),
+            "compliance_max_rel_diff_vs_fp64": float(max(abs(a["c"] - b["c"]) / abs(b["c"]) for a, b in zip(st, st64))),
+            "displacement_rel_diff_vs_fp64": float(torch.linalg.vector_norm(u - u64) / torch.linalg.vector_norm(u64)),
+        }
+        print(f"# variant {name}: {ms:.2f} ms per SIMP iteration, "
+              f"{out[name]['pcg_iters_mean']} CG iterations", file=sys.stderr, flush=True)
+    return out
+
+
 def batched(topo, synth, args):
     """64 independent random problems (grids 24x12x12 .. 96x48x48, seeds 0-63) with the
     single-precision multigrid preconditioner and autotuned K.u launch shapes:
@@ -613,6 +657,9 @@ def main():
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-vs-multigrid leg")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-problems leg")
     ap.add_argument("--no-paper", action="store_true", help="skip the paper's 32x16x16 workload")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip the preconditioner-precision variants of the 160x80x80 workload")
+    ap.add_argument("--variant-steps", type=int, default=3)
     ap.add_argument("--batch-size", type=int, default=64)
     ap.add_argument("--batch-steps", type=int, default=5)
     ap.add_argument("--batch-warmup", type=int, default=2)
@@ -725,6 +772,7 @@ def main():
             "phase_ms_mean": {k: round(float(np.mean([s[k] for s in stats])), 3)
                               for k in ("ms_filter", "ms_solve", "ms_sens", "ms_oc")},
             "compliance_last": stats[-1]["c"],
+            "precision_variants": None,
             "learned_vs_mg": None,
             "batched": None,
             "paper_benchmark": None,
@@ -732,6 +780,8 @@ def main():
         "roofline": roofline,
     }
     ctx.close()
+    if not args.no_variants:
+        out["config"]["precision_variants"] = precision_variants(topo, p, opts, args)
     if args.copy_probe_mib > 0:
         n = args.copy_probe_mib * (1 << 20) // 8
         src = torch.ones(n, dtype=torch.float64, device="cuda")
