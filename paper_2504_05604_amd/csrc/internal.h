@@ -131,7 +131,12 @@ enum KuEpi {
   KU_RESUPD = 7,       // res -= Au
   KU_RESID_START = 8,  // res = b - Au; dout = res dinv s0 (x not updated: the next
                        // KU_CHEB_ADD adds dout; dout null: not stored)
+  KU_RESID_FLEX = 9,   // the end of a degree-1 post-smoothing handed to flexible CG:
+                       // res = b - Au (not stored), z_new = u + res dinv s0 into zflex
+                       // (u = x), reduce rflex.z_new and rflex.z_old (z_old: zflex before)
 };
+// values an epilogue reduces (0: none)
+inline int ku_ndot(KuEpi epi) { return epi == KU_RESID_FLEX ? 2 : 1; }
 template <typename T>
 struct KuArgsT {
   Grid g;
@@ -147,6 +152,8 @@ struct KuArgsT {
   const int *skip;        // device flag: return at once when non-zero (may be NULL)
   const float *ke32;      // matrix-core shapes: KE as FP32 [32][24] (rows 24.. zero)
   const void *ke16;       // ... and as BF16 [32][32] (zero padded)
+  const double *rflex;    // RESID_FLEX: the conjugate-gradient residual (FP64)
+  T *zflex;               // RESID_FLEX: the preconditioned residual, read and replaced
 };
 using KuArgs = KuArgsT<double>;
 // fin receives the reduction of STORE_DOT / RESID / CHEB with dot_with
@@ -165,6 +172,7 @@ int ku_shape_for(const Grid &g, KuEpi epi, int family, bool single = false);
 // mode), 6..10 the element-column kernel in the sum/difference basis
 constexpr int kKuShapes = 4;
 constexpr int kKuShapeMfma = 4, kKuShapeMfmaBf16 = 5;
+inline bool ku_matrix_core_shape(int shape) { return shape == kKuShapeMfma || shape == kKuShapeMfmaBf16; }
 constexpr int kKuShapeHada = 6, kKuShapesHada = 9;
 hipError_t launch_ku_mfma(hipStream_t s, KuEpi epi, const KuArgsT<float> &a, bool bf16);
 template <typename T>

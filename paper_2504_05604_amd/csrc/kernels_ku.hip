@@ -51,7 +51,7 @@ __global__ __launch_bounds__(BS) void ku_march_kernel(KuArgsT<T> a, KappaT<T> ka
   constexpr bool kScaled = EpiTraits<EPI>::scaled_operand;
   const T *__restrict__ u = kScaled ? a.b : a.u;
   const T *__restrict__ dinv = a.dinv;
-  double dotv = 0.0;
+  double dotv[2] = {0.0, 0.0};
   if (active) {
     T P0[9][3], P1[9][3];
     auto load_plane = [&](int kp, T(&P)[9][3]) {
@@ -181,6 +181,7 @@ static hipError_t launch_ku_shape(hipStream_t s, KuEpi epi, const KuArgsT<T> &a,
     TOPO_KU_CASE(KU_CHEB_ADD)
     TOPO_KU_CASE(KU_RESUPD)
     TOPO_KU_CASE(KU_RESID_START)
+    TOPO_KU_CASE(KU_RESID_FLEX)
     default: return hipErrorInvalidValue;
   }
 #undef TOPO_KU_CASE
@@ -237,7 +238,7 @@ static hipError_t launch_ku_t(hipStream_t s, KuEpi epi, const KuArgsT<T> &a, con
   if (shape >= kKuShapeHada && shape < kKuShapeHada + kKuShapesHada) {
     e = launch_ku_hada<T>(s, epi, a, kap, red, shape - kKuShapeHada, &nparts);
     if (e != hipSuccess) return e;
-    if (ku_reduces(epi, a)) return launch_finalize(s, red, nparts, 1, fin, a.skip);
+    if (ku_reduces(epi, a)) return launch_finalize(s, red, nparts, ku_ndot(epi), fin, a.skip);
     return hipSuccess;
   }
   switch (shape) {
@@ -248,7 +249,7 @@ static hipError_t launch_ku_t(hipStream_t s, KuEpi epi, const KuArgsT<T> &a, con
     default: return hipErrorInvalidValue;
   }
   if (e != hipSuccess) return e;
-  if (ku_reduces(epi, a)) return launch_finalize(s, red, nparts, 1, fin, a.skip);
+  if (ku_reduces(epi, a)) return launch_finalize(s, red, nparts, ku_ndot(epi), fin, a.skip);
   return hipSuccess;
 }
 
@@ -283,7 +284,7 @@ hipError_t launch_ku_group(hipStream_t s, KuEpi epi, int G, const KuArgsT<T> *a,
     f[i] = fin[i];
     sk[i] = a[i].skip;
   }
-  return launch_finalize_group(s, G, red, nparts, 1, f, sk);
+  return launch_finalize_group(s, G, red, nparts, ku_ndot(epi), f, sk);
 }
 template hipError_t launch_ku_group<double>(hipStream_t, KuEpi, int, const KuArgsT<double> *, const KappaT<double> &,
                                             const Reducer *, const Fin *, int);

@@ -112,7 +112,7 @@ __device__ __forceinline__ void ku_hada_body(const KuArgsT<T> &a, const HadaW<T>
   // for one load waits for every older one): first the epilogue inputs of node
   // plane L, then (PF) the next plane and modulus, which stay in flight through
   // this layer's arithmetic and barrier (the barrier waits for LDS traffic only).
-  double dotv = 0.0;
+  double dotv[2] = {0.0, 0.0};
   T Pb[3][4], selfb[3];  // node plane L (xy modes) and the operand at the owned node
   T bdb[2][3];           // scaled epilogues: b and dinv at the owned node of plane L
   T ytp[3][4];           // top face of element layer L-1 (xy modes)
@@ -302,7 +302,7 @@ __device__ __forceinline__ void ku_hada_lds_body(const KuArgsT<T> &a, const Hada
 
   // node plane k0-1+m is staged in stage[m & 1] and loaded into rg[m & 1]
   T rg[2][SL], rd[2][SL];
-  double dotv = 0.0;
+  double dotv[2] = {0.0, 0.0};
   T Pb[3][4], selfb[3], ytp[3][4];
   T Ecur = load_E(k0 - 1), Enx = load_E(k0);
   EpiIn<T> in_nx;  // epilogue inputs of the next node plane, loaded one layer ahead
@@ -446,6 +446,7 @@ static hipError_t launch_hada_shape(hipStream_t s, KuEpi epi, const KuArgsT<T> &
     TOPO_KU_CASE(KU_CHEB_ADD)
     TOPO_KU_CASE(KU_RESUPD)
     TOPO_KU_CASE(KU_RESID_START)
+    TOPO_KU_CASE(KU_RESID_FLEX)
     default: return hipErrorInvalidValue;
   }
 #undef TOPO_KU_CASE
@@ -487,6 +488,7 @@ static hipError_t launch_hada_shape_group(hipStream_t s, KuEpi epi, int G, const
     TOPO_KU_CASE(KU_CHEB_ADD)
     TOPO_KU_CASE(KU_RESUPD)
     TOPO_KU_CASE(KU_RESID_START)
+    TOPO_KU_CASE(KU_RESID_FLEX)
     default: return hipErrorInvalidValue;
   }
 #undef TOPO_KU_CASE

@@ -28,6 +28,8 @@ template <typename T>
 struct EpiIn {
   uint8_t fx;  // fixed-dof bits of the node
   T b[3], r[3], d[3], x[3], w[3];  // rhs, residual, inverse diagonal, iterate, dot_with
+  double rc[3];                    // RESID_FLEX: the CG residual
+  T zo[3];                         // RESID_FLEX: the previous preconditioned residual
 };
 
 // HAVE_BD: the caller already holds b and dinv at the node (the scaled
@@ -36,10 +38,13 @@ template <int EPI, bool HAVE_BD = false, typename T>
 __device__ __forceinline__ void ku_epi_load(const KuArgsT<T> &a, int64_t n, const T *__restrict__ dinv,
                                             EpiIn<T> &in) {
   in.fx = a.fixed[n];
-  constexpr bool kB = !HAVE_BD && (EPI == KU_RESID || EPI == KU_RES0 || EPI == KU_CHEB0 || EPI == KU_RESID_START);
+  constexpr bool kB = !HAVE_BD && (EPI == KU_RESID || EPI == KU_RES0 || EPI == KU_CHEB0 || EPI == KU_RESID_START ||
+                                   EPI == KU_RESID_FLEX);
   constexpr bool kR = EPI == KU_CHEB || EPI == KU_CHEB_ADD || EPI == KU_RESUPD;
-  constexpr bool kD = !HAVE_BD && (EPI == KU_CHEB0 || EPI == KU_CHEB || EPI == KU_CHEB_ADD || EPI == KU_RESID_START);
+  constexpr bool kD = !HAVE_BD && (EPI == KU_CHEB0 || EPI == KU_CHEB || EPI == KU_CHEB_ADD || EPI == KU_RESID_START ||
+                                   EPI == KU_RESID_FLEX);
   constexpr bool kX = EPI == KU_CHEB || EPI == KU_CHEB_ADD;
+  constexpr bool kF = EPI == KU_RESID_FLEX;
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
     const int64_t dof = 3 * n + c;
@@ -50,6 +55,10 @@ __device__ __forceinline__ void ku_epi_load(const KuArgsT<T> &a, int64_t n, cons
       if (EPI != KU_RESID_START || a.dout) in.d[c] = dinv[dof];
     }
     if constexpr (kX) in.x[c] = a.x[dof];
+    if constexpr (kF) {
+      in.rc[c] = a.rflex[dof];
+      in.zo[c] = a.zflex[dof];
+    }
   }
   if constexpr (kX) {
     if (a.dot_with) {
@@ -61,10 +70,11 @@ __device__ __forceinline__ void ku_epi_load(const KuArgsT<T> &a, int64_t n, cons
 
 // self: the operand at the node (u, or b dinv s0 for the scaled epilogues);
 // Au: the operator's product at the node; dotv accumulates the epilogue's dot
-// product (STORE_DOT: u.y, RESID: r.r, CHEB with dot_with: dot_with.x_new).
+// products (STORE_DOT: u.y, RESID: r.r, CHEB with dot_with: dot_with.x_new;
+// RESID_FLEX: r.z_new and r.z_old).
 template <int EPI, typename T>
 __device__ __forceinline__ void ku_epi_finish(const KuArgsT<T> &a, int64_t n, const EpiIn<T> &in,
-                                              const T (&self)[3], const T (&Au)[3], double &dotv) {
+                                              const T (&self)[3], const T (&Au)[3], double (&dotv)[2]) {
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
     const bool isf = (in.fx >> c) & 1;
@@ -75,11 +85,11 @@ __device__ __forceinline__ void ku_epi_finish(const KuArgsT<T> &a, int64_t n, co
     } else if constexpr (EPI == KU_STORE_DOT) {
       const T yv = isf ? self[c] : Au[c];
       a.y[dof] = yv;
-      dotv = fma((double)self[c], (double)yv, dotv);
+      dotv[0] = fma((double)self[c], (double)yv, dotv[0]);
     } else if constexpr (EPI == KU_RESID) {
       const T yv = isf ? T(0) : in.b[c] - Au[c];
       a.y[dof] = yv;
-      dotv = fma((double)yv, (double)yv, dotv);
+      dotv[0] = fma((double)yv, (double)yv, dotv[0]);
     } else if constexpr (EPI == KU_RES0) {  // x = d0, res = b - A d0
       a.res[dof] = in.b[c] - Ac;
       a.x[dof] = self[c];
@@ -99,13 +109,21 @@ __device__ __forceinline__ void ku_epi_finish(const KuArgsT<T> &a, int64_t n, co
         a.dout[dof] = dn;
       }
       a.x[dof] = xn;
-      if (a.dot_with) dotv = fma((double)in.w[c], (double)xn, dotv);
+      if (a.dot_with) dotv[0] = fma((double)in.w[c], (double)xn, dotv[0]);
     } else if constexpr (EPI == KU_RESUPD) {
       a.res[dof] = in.r[c] - Ac;
     } else if constexpr (EPI == KU_RESID_START) {  // res = b - A x; dout = res dinv s0 (unless null)
       const T r = in.b[c] - Ac;
       a.res[dof] = r;
       if (a.dout) a.dout[dof] = r * in.d[c] * a.s0;
+    } else if constexpr (EPI == KU_RESID_FLEX) {
+      // the last update x + res dinv s0 of the smoothing, as the flexible-CG
+      // pass forms it on its own (dinv is 0 on fixed dofs, where x is 0)
+      const T r = in.b[c] - Ac;
+      const T zf = self[c] + r * in.d[c] * a.s0;
+      a.zflex[dof] = zf;
+      dotv[0] = fma(in.rc[c], (double)zf, dotv[0]);
+      dotv[1] = fma(in.rc[c], (double)in.zo[c], dotv[1]);
     }
   }
 }
@@ -114,7 +132,7 @@ __device__ __forceinline__ void ku_epi_finish(const KuArgsT<T> &a, int64_t n, co
 template <int EPI, typename T>
 __device__ __forceinline__ void ku_node_epilogue(const KuArgsT<T> &a, int64_t n, const T (&self)[3],
                                                  const T (&Au)[3], const T *__restrict__ dinv,
-                                                 double &dotv) {
+                                                 double (&dotv)[2]) {
   EpiIn<T> in;
   ku_epi_load<EPI>(a, n, dinv, in);
   ku_epi_finish<EPI>(a, n, in, self, Au, dotv);
@@ -122,21 +140,24 @@ __device__ __forceinline__ void ku_node_epilogue(const KuArgsT<T> &a, int64_t n,
 
 // The block's share of the epilogue's dot product (every thread must call it).
 template <int EPI, typename T>
-__device__ __forceinline__ void ku_block_reduce(const KuArgsT<T> &a, double dotv, double *partials) {
+__device__ __forceinline__ void ku_block_reduce(const KuArgsT<T> &a, const double (&dotv)[2], double *partials) {
   if constexpr (EPI == KU_STORE_DOT || EPI == KU_RESID) {
-    double v[1] = {dotv};
+    double v[1] = {dotv[0]};
     block_reduce_store<1, false>(v, partials, linear_block());
   } else if constexpr (EPI == KU_CHEB || EPI == KU_CHEB_ADD) {
     if (a.dot_with) {
-      double v[1] = {dotv};
+      double v[1] = {dotv[0]};
       block_reduce_store<1, false>(v, partials, linear_block());
     }
+  } else if constexpr (EPI == KU_RESID_FLEX) {
+    double v[2] = {dotv[0], dotv[1]};
+    block_reduce_store<2, false>(v, partials, linear_block());
   }
 }
 
 template <typename T>
 inline bool ku_reduces(KuEpi epi, const KuArgsT<T> &a) {
-  return epi == KU_STORE_DOT || epi == KU_RESID ||
+  return epi == KU_STORE_DOT || epi == KU_RESID || epi == KU_RESID_FLEX ||
          ((epi == KU_CHEB || epi == KU_CHEB_ADD) && a.dot_with != nullptr);
 }
 

@@ -1040,7 +1040,17 @@ static topo_status post_smooth(topo_ctx *ctx, Level &L, const int *skip, const T
   a.skip = skip;
   // degree 1 into flex_dot: it forms the direction from res itself
   bool fused_last = false;
-  if constexpr (std::is_same<T, float>::value) fused_last = deg == 1 && flex;
+  if constexpr (std::is_same<T, float>::value) {
+    fused_last = deg == 1 && flex;
+    if (fused_last && !ku_matrix_core_shape(L.shape)) {
+      // ... or, with the vector kernels, the operator pass forms z and the
+      // flexible-CG dot products itself (res is not needed afterwards)
+      a.rflex = flex->r;
+      a.zflex = flex->z;
+      TOPO_HIP(launch_ku(s, KU_RESID_FLEX, a, kap, ctx->red, flex->fin, L.shape));
+      return TOPO_OK;
+    }
+  }
   if (fused_last) a.dout = nullptr;
   TOPO_HIP(launch_ku(s, KU_RESID_START, a, kap, ctx->red, fin_sum(nullptr), L.shape));
   if (deg == 1) {
@@ -1471,6 +1481,16 @@ static topo_status group_post_smooth(const Group &G, size_t l, bool finest) {
     a[i].dout = fused_last ? nullptr : dcur[i];
     a[i].s0 = (T)(1.0 / ch.theta);
     a[i].skip = &G.c[i]->sc->cg_done;
+  }
+  if constexpr (single) {
+    if (fused_last) {  // the operator pass forms z and the flexible-CG dots (post_smooth)
+      for (int i = 0; i < n; ++i) {
+        a[i].rflex = G.c[i]->r;
+        a[i].zflex = G.c[i]->z32;
+      }
+      TOPO_HIP(launch_ku_group<T>(G.s, KU_RESID_FLEX, n, a.data(), kap, red.data(), flexfin.data(), shape));
+      return TOPO_OK;
+    }
   }
   TOPO_HIP(launch_ku_group<T>(G.s, KU_RESID_START, n, a.data(), kap, red.data(), fin.data(), shape));
   const int64_t nd = c0->lv[l].g.ndof();
