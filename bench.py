@@ -651,6 +651,8 @@ def main():
     ap.add_argument("--ku-kernel", choices=["auto", "node", "element"], default="auto",
                     help="K.u kernel: node columns or element columns in the sum/difference basis")
     ap.add_argument("--ku-shape", type=int, default=-1, help="one K.u launch shape for every level (-1: by grid size)")
+    ap.add_argument("--cheb-upper", type=float, default=0.8,
+                    help="top of the smoothing interval as a fraction of the element bound (1: the bound)")
     ap.add_argument("--coarse-refresh", type=int, default=2,
                     help="recompute the coarsest level's dense inverse every this many SIMP iterations "
                          "(in between the previous one, still SPD, preconditions)")
@@ -701,6 +703,7 @@ def main():
                              ku_kernel={"auto": topo.KU_AUTO, "node": topo.KU_NODE,
                                         "element": topo.KU_ELEMENT}[args.ku_kernel],
                              ku_shape=args.ku_shape, coarse_refresh=args.coarse_refresh,
+                             cheb_upper=args.cheb_upper,
                              precond=topo.PRECOND_MG if args.precond == "mg" else topo.PRECOND_JACOBI)
     ctx = topo.Context(p, opts)
     x = torch.from_numpy(p.initial_design()).to("cuda")
@@ -761,6 +764,7 @@ def main():
             "coarse_dof_cap": args.coarse_dof,
             "check_every": args.check_every, "graphs": not args.no_graphs,
             "coarse_tail_nodes": args.tail_nodes, "autotune": bool(args.autotune),
+            "cheb_upper": args.cheb_upper,
             "ku_kernel": args.ku_kernel, "ku_shape": args.ku_shape, "coarse_refresh": args.coarse_refresh,
             "preconditioner_precision": args.precision,
             "error_vs_fp64": fp64_reference,

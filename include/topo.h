@@ -163,6 +163,15 @@ typedef struct {
                                  pass one launch for the whole group (results identical to
                                  solving each alone with the group's launch shapes);
                                  0 = every problem on its own stream                  */
+  double cheb_upper;          /* the smoothers' Chebyshev interval is [c lb / 30, c lb], c =
+                                 cheb_upper in (0, 1], lb = lambda_max(diag(KE)^-1 KE), which
+                                 bounds lambda_max(D^-1 A) for any densities (c = 1, the
+                                 default, is valid always).  A smaller c smooths the top
+                                 of the spectrum harder and fits while lambda_max(D^-1 A)
+                                 stays below c lb: filtered SIMP designs measure 0.58-0.72,
+                                 unfiltered random densities up to 0.85, an isolated solid
+                                 element in void 1.  Convergence to rtol is checked on the
+                                 true residual whatever c is                           */
 } topo_opts;
 
 typedef struct {
@@ -193,7 +202,7 @@ typedef struct {
  * rtol 1e-8, max_iters 1000, projected warm start (3), oc_tol 1e-12,
  * check_every 4, use_graphs 1, nn_max_iters 200, autotune 0, coarse_tail_nodes 0,
  * mfma_smoothing 0, ku_kernel TOPO_KU_AUTO, ku_shape -1, coarse_refresh 1,
- * cheb_degree_level all 0, group_launch 1. */
+ * cheb_degree_level all 0, group_launch 1, cheb_upper 1. */
 void topo_default_opts(topo_opts *opts);
 
 /* Validates the problem, copies its arrays to the device, builds the element

@@ -21,8 +21,8 @@ checked against a plain implementation.
 * Smoother: Chebyshev polynomial in D^-1 A on the interval
   [lam_max / CHEB_RATIO, lam_max] with lam_max the Jacobi-scaled element bound
   lambda_max(diag(KE)^-1 KE) (an upper bound of lambda_max(D^-1 A) for any
-  non-negative moduli), same polynomial before and after the coarse
-  correction, so the V-cycle is a symmetric operator.
+  non-negative moduli), or a given fraction of it, same polynomial before and
+  after the coarse correction, so the V-cycle is a symmetric operator.
 * Coarsest level: direct solve.
 """
 
@@ -102,18 +102,19 @@ class VCycle:
     """Symmetric V-cycle M ~ A^-1 of the reduced operator with identity rows."""
 
     def __init__(self, p, E, KE, degree=2, max_coarse_dof=800, levels=None, coarse_degree=None,
-                 level_degrees=None):
+                 level_degrees=None, cheb_upper=1.0):
         """degree: Chebyshev steps per pre/post smoothing on the finest level;
         coarse_degree: the same on the coarser levels (None: degree);
         level_degrees: per level, finest first, a degree that replaces those two
-        where it is given and positive."""
+        where it is given and positive; cheb_upper: the smoothing interval's top
+        as a fraction of the element bound (1: the bound itself)."""
         dims = hierarchy(p.nelx, p.nely, p.nelz, max_coarse_dof)
         if levels is not None:
             dims = dims[:levels]
         fixed = np.zeros(p.ndof, dtype=bool)
         fixed[np.asarray(p.fixed_dofs)] = True
         d = np.diag(KE)
-        self.lam_max = float(np.linalg.eigvalsh(KE / np.sqrt(np.outer(d, d))).max())
+        self.lam_max = cheb_upper * float(np.linalg.eigvalsh(KE / np.sqrt(np.outer(d, d))).max())
         self.degree = degree
         self.coarse_degree = degree if coarse_degree is None else coarse_degree
         self.level_degrees = list(level_degrees or [])

@@ -69,6 +69,7 @@ class Opts_C(C.Structure):
         ("autotune", C.c_int32), ("coarse_tail_nodes", C.c_int32), ("mfma_smoothing", C.c_int32),
         ("ku_kernel", C.c_int32), ("ku_shape", C.c_int32), ("coarse_refresh", C.c_int32),
         ("cheb_degree_level", C.c_int32 * 8), ("group_launch", C.c_int32),
+        ("cheb_upper", C.c_double),
     ]
 
 

@@ -181,7 +181,7 @@ struct topo_ctx {
   double target = 0.0;
   // constants
   Kappa kap{};
-  double lam_max = 0.0;
+  double lam_max = 0.0;  // top of the Chebyshev smoothing interval (cheb_upper x the element bound)
   // problem data
   double *f = nullptr;
   int8_t *mask = nullptr;
@@ -284,6 +284,7 @@ extern "C" void topo_default_opts(topo_opts *o) {
   o->coarse_refresh = 1;
   for (int l = 0; l < 8; ++l) o->cheb_degree_level[l] = 0;
   o->group_launch = 1;
+  o->cheb_upper = 1.0;
 }
 
 extern "C" const char *topo_last_error(void) { return g_err; }
@@ -346,6 +347,7 @@ static topo_status validate(const topo_problem *P, const topo_opts *O) {
   if (O->coarse_refresh < 1) return set_error("coarse_refresh must be >= 1"), TOPO_EINVAL;
   if (O->group_launch != 0 && O->group_launch != 1) return set_error("group_launch must be 0 or 1"), TOPO_EINVAL;
   if (O->autotune < 0 || O->autotune > 2) return set_error("autotune must be 0, 1 or 2"), TOPO_EINVAL;
+  if (!(O->cheb_upper > 0.0 && O->cheb_upper <= 1.0)) return set_error("cheb_upper must lie in (0, 1]"), TOPO_EINVAL;
   for (int l = 0; l < 8; ++l)
     if (O->cheb_degree_level[l] < 0 || O->cheb_degree_level[l] > 16)
       return set_error("cheb_degree_level[%d] must lie in [0, 16]", l), TOPO_EINVAL;
@@ -399,7 +401,8 @@ extern "C" topo_status topo_setup(const topo_problem *P, const topo_opts *O, voi
   ctx->nnodes = g.nnodes();
   ctx->ndof = g.ndof();
 
-  // element stiffness and the Jacobi-scaled bound lambda_max(diag(KE)^-1 KE)
+  // element stiffness and the Jacobi-scaled bound lambda_max(diag(KE)^-1 KE),
+  // whose cheb_upper-th part is the top of the smoothers' Chebyshev interval
   double KE[576];
   element_stiffness(P->nu, KE);
   double KEd[24];
@@ -408,7 +411,7 @@ extern "C" topo_status topo_setup(const topo_problem *P, const topo_opts *O, voi
     std::vector<double> S(576);
     for (int i = 0; i < 24; ++i)
       for (int j = 0; j < 24; ++j) S[i * 24 + j] = KE[i * 24 + j] / std::sqrt(KEd[i] * KEd[j]);
-    ctx->lam_max = sym_max_eig(S, 24);
+    ctx->lam_max = O->cheb_upper * sym_max_eig(S, 24);
   }
   // the kernels use the exact compile-time form of KE; check it against the
   // quadrature once (they agree to rounding for every nu)
@@ -1358,7 +1361,8 @@ std::string group_key(const topo_ctx *ctx) {
     return true;
   }();
   if (!is_hada) return "";
-  std::string k = std::to_string(ctx->prob.nu) + "|" + std::to_string(ctx->mixed) + "|" + std::to_string(ctx->shape_cg);
+  std::string k = std::to_string(ctx->prob.nu) + "|" + std::to_string(ctx->mixed) + "|" + std::to_string(ctx->shape_cg) +
+                  "|" + std::to_string(ctx->lam_max);
   for (size_t l = 0; l < ctx->lv.size(); ++l) {
     const Level &L = ctx->lv[l];
     k += "|" + std::to_string(L.g.nx) + "x" + std::to_string(L.g.ny) + "x" + std::to_string(L.g.nz) + "s" +

@@ -33,7 +33,7 @@ def test_default_opts():
     assert o.cheb_degree == 1 and o.cheb_degree_coarse == 4
     assert o.ku_kernel == pkg.KU_AUTO and o.ku_shape == -1 and o.coarse_tail_nodes == 0
     assert o.mg_max_coarse_dof == 1500 and o.coarse_refresh == 1
-    assert o.group_launch == 1 and list(o.cheb_degree_level) == [0] * 8
+    assert o.group_launch == 1 and list(o.cheb_degree_level) == [0] * 8 and o.cheb_upper == 1.0
 
 
 def setup_status(p, vol_mode=0, **opt):
@@ -107,7 +107,8 @@ def test_setup_rejects_bad_options():
                     ({"ku_shape": -2}, "ku_shape"), ({"coarse_refresh": 0}, "coarse_refresh"),
                     ({"cheb_degree_coarse": -1}, "cheb_degree_coarse"), ({"cheb_degree_coarse": 17}, "cheb_degree_coarse"),
                     ({"group_launch": 2}, "group_launch"), ({"group_launch": -1}, "group_launch"),
-                    ({"autotune": 3}, "autotune"), ({"autotune": -1}, "autotune")]:
+                    ({"autotune": 3}, "autotune"), ({"autotune": -1}, "autotune"),
+                    ({"cheb_upper": 0.0}, "cheb_upper"), ({"cheb_upper": 1.5}, "cheb_upper")]:
         st, err, _ = setup_status(p, **kw)
         assert st == _lib.TOPO_EINVAL and msg in err, (kw, err)
 

@@ -121,22 +121,24 @@ def test_preconditioner_matches_oracle(case, precond, kernel):
     assert np.abs(got - ref).max() <= 1e-11 * np.abs(ref).max()
 
 
+@pytest.mark.parametrize("upper", [1.0, 0.8])
 @pytest.mark.parametrize("kernel", list(KERNELS))
 @pytest.mark.parametrize("tail", [0, 1024])
 @pytest.mark.parametrize("lev", [[1, 2, 4, 6], [2, 3, 1, 5]])
-def test_per_level_degrees_on_a_five_level_hierarchy(lev, tail, kernel):
+def test_per_level_degrees_on_a_five_level_hierarchy(lev, tail, kernel, upper):
     """33x17x17 at a 140-dof cap coarsens to 5 levels, so each of the 4 listed
-    degrees smooths a level of its own (the benchmark's 1, 2, 4, 6 among them)."""
+    degrees smooths a level of its own (the benchmark's 1, 2, 4, 6 among them);
+    upper: the top of the smoothing interval as a fraction of the element bound."""
     p = synth.cantilever(33, 17, 17, volfrac=0.3, rmin=1.5, n_iter=1)
     x = synth.random_density(15, p.nel, 0.0, 1.0)
     E = fem.simp_modulus(x, p.E0, p.Emin, p.penal)
     r = synth.random_vector(16, p.ndof)
     r[fixed_mask(p)] = 0.0
-    V = mg.VCycle(p, E, KE, degree=1, coarse_degree=4, max_coarse_dof=140, level_degrees=lev)
+    V = mg.VCycle(p, E, KE, degree=1, coarse_degree=4, max_coarse_dof=140, level_degrees=lev, cheb_upper=upper)
     assert len(V.levels) == len(lev) + 1
     ref = V.apply(r)
     opts = topo.default_opts(mg_max_coarse_dof=140, cheb_degree=1, cheb_degree_coarse=4, cheb_degree_level=lev,
-                             coarse_tail_nodes=tail, ku_kernel=KERNELS[kernel])
+                             coarse_tail_nodes=tail, ku_kernel=KERNELS[kernel], cheb_upper=upper)
     with topo.Context(p, opts) as ctx:
         assert ctx.mg_levels == len(V.levels)
         z = torch.empty(p.ndof, dtype=torch.float64, device="cuda")

@@ -150,3 +150,36 @@ def test_per_level_degrees_reach_each_level():
     np.testing.assert_allclose(got, x0, rtol=0, atol=1e-13 * np.abs(x0).max())
     other = mg.VCycle(p, E, KE, degree=3, coarse_degree=3, max_coarse_dof=300, level_degrees=[a, a]).apply(r)
     assert np.abs(other - got).max() > 1e-3 * np.abs(got).max()
+
+
+def _jacobi_scaled_lambda_max(p, xphys):
+    """lambda_max(D^-1 A) of the finest-level operator (identity rows on fixed
+    dofs), by scipy's Lanczos on D^-1/2 A D^-1/2, relative to the element bound."""
+    import scipy.sparse.linalg as sla
+
+    E = fem.simp_modulus(xphys, p.E0, p.Emin, p.penal)
+    V = mg.VCycle(p, E, KE, degree=1, max_coarse_dof=300)
+    A = V.levels[0].A
+    s = sp.diags(1.0 / np.sqrt(A.diagonal()))
+    lam = sla.eigsh(s @ A @ s, k=1, which="LA", return_eigenvectors=False, tol=1e-8)[0]
+    return lam / V.lam_max
+
+
+def test_smoothing_interval_fractions_of_the_element_bound():
+    """The validity range stated for a smoothing interval below the element
+    bound: a uniform density sits near 0.58 of it, a filtered SIMP design well
+    below 0.8, an isolated solid element in void at the bound itself (its own
+    element matrix is the operator there), and no density exceeds it."""
+    from oracle import simp
+
+    p = synth.cantilever(16, 8, 8, volfrac=0.3, rmin=1.5, n_iter=1)
+    assert abs(_jacobi_scaled_lambda_max(p, np.full(p.nel, 0.3)) - 0.58) < 0.01
+    o = simp.SimpOracle(p)
+    x, _ = o.trajectory(12)
+    assert _jacobi_scaled_lambda_max(p, o.physical(x)) < 0.75
+    x = np.full(p.nel, 1e-3)
+    x[p.nel // 2 + p.nelx // 2] = 1.0
+    ratio = _jacobi_scaled_lambda_max(p, x)
+    assert 0.99 < ratio <= 1.0 + 1e-9
+    rng = np.random.default_rng(3)
+    assert _jacobi_scaled_lambda_max(p, rng.uniform(0.0, 1.0, p.nel)) <= 1.0 + 1e-9
