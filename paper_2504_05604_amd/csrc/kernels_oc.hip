@@ -39,13 +39,11 @@ __device__ __forceinline__ double oc_a_of(const double *__restrict__ a, const do
   else return oc_coef(x, dc[e], dv[e], eta);
 }
 
-__device__ void oc_make_candidates(Scalars *sc) {
-  const double l1 = sc->l1, l2 = sc->l2;
+// candidate c of the bracket [l1, l2] (one lane per candidate)
+__device__ __forceinline__ double oc_candidate(double l1, double l2, int c) {
   const bool geo = l1 > 0.0 && l2 > 2.0 * l1;
-  for (int c = 0; c < kOcCand; ++c) {
-    const double t = (double)(c + 1) / (double)(kOcCand + 1);
-    sc->oc_lam[c] = geo ? l1 * pow(l2 / l1, t) : l1 + (l2 - l1) * t;
-  }
+  const double t = (double)(c + 1) / (double)(kOcCand + 1);
+  return geo ? l1 * pow(l2 / l1, t) : l1 + (l2 - l1) * t;
 }
 
 __device__ __forceinline__ void oc_prepare_body(int64_t nel, const double *__restrict__ x,
@@ -76,18 +74,23 @@ __global__ void oc_prepare_group_kernel(int64_t nel, GroupTab<OcArgs> t, GroupTa
   oc_prepare_body(nel, o.x, o.dc, o.dv, o.mask, o.eta, o.a, part.v[blockIdx.z]);
 }
 
+// one wave: lane 0 the scalars, lane c candidate c
 __device__ __forceinline__ void oc_init_body(Scalars *sc, double target) {
-  sc->target = target;
-  sc->l1 = 1e-40;  // the multiplier is positive; this stands for the lower end 0
-  sc->l2 = 1e40;
-  sc->oc_done = 0;
-  sc->oc_pass = 0;
-  oc_make_candidates(sc);
+  constexpr double l1 = 1e-40, l2 = 1e40;  // the multiplier is positive; l1 stands for the lower end 0
+  const int c = threadIdx.x;
+  if (c == 0) {
+    sc->target = target;
+    sc->l1 = l1;
+    sc->l2 = l2;
+    sc->oc_done = 0;
+    sc->oc_pass = 0;
+  }
+  if (c < kOcCand) sc->oc_lam[c] = oc_candidate(l1, l2, c);
 }
 __global__ void oc_init_kernel(Scalars *sc, double target) { oc_init_body(sc, target); }
-// one thread per problem
+// one wave per problem
 __global__ void oc_init_group_kernel(GroupTab<OcArgs> t) {
-  const OcArgs &o = t.v[threadIdx.x];
+  const OcArgs &o = t.v[blockIdx.x];
   oc_init_body(o.sc, o.target);
 }
 
@@ -164,24 +167,28 @@ __device__ __forceinline__ void oc_select_body(int nparts, double tol, Scalars *
   t += __shfl_down(t, 1, 4);
   if (c < kOcCand && part == 0) V[c] = t + sc->vconst;
   __syncthreads();
-  if (threadIdx.x != 0) return;
+  if (threadIdx.x >= 64) return;
+  // the crossing: V is non-increasing in lambda, and the bracket keeps the last
+  // candidate above the target and the first one at or below it (a scan over
+  // the candidates stopping at the first one not above); one wave, lane = candidate
+  const int lane = threadIdx.x;
   const double target = sc->target;
+  const bool above = lane < kOcCand && V[lane] > target;
+  const unsigned long long m = __ballot(above);
+  const int first_below = __builtin_ctzll(~m);  // lane kOcCand (never above) bounds it
   double l1 = sc->l1, l2 = sc->l2;
-  for (int c = 0; c < kOcCand; ++c) {
-    if (V[c] > target) {
-      l1 = sc->oc_lam[c];
-    } else {
-      l2 = sc->oc_lam[c];
-      break;
-    }
+  if (first_below > 0) l1 = sc->oc_lam[first_below - 1];
+  if (first_below < kOcCand) l2 = sc->oc_lam[first_below];
+  const int pass = sc->oc_pass + 1;
+  const bool done = (l2 - l1) / (l1 + l2) < tol || pass >= 64;
+  // every lane has read what it needs (the new values depend on those reads)
+  if (lane == 0) {
+    sc->l1 = l1;
+    sc->l2 = l2;
+    sc->oc_pass = pass;
+    sc->oc_done = done ? 1 : 0;
   }
-  sc->l1 = l1;
-  sc->l2 = l2;
-  sc->oc_pass += 1;
-  if ((l2 - l1) / (l1 + l2) < tol || sc->oc_pass >= 64)
-    sc->oc_done = 1;
-  else
-    oc_make_candidates(sc);
+  if (!done && lane < kOcCand) sc->oc_lam[lane] = oc_candidate(l1, l2, lane);
 }
 __global__ __launch_bounds__(kSelThreads) void oc_select_kernel(int nparts, double tol, Scalars *sc,
                                                                 const double *partials) {
@@ -245,7 +252,7 @@ hipError_t launch_oc_prepare(hipStream_t s, int64_t nel, const double *x, const 
   if (e != hipSuccess) return e;
   e = launch_finalize(s, red, (int)nb, 1, fin_sum(&sc->vconst));
   if (e != hipSuccess) return e;
-  oc_init_kernel<<<1, 1, 0, s>>>(sc, target);
+  oc_init_kernel<<<1, 64, 0, s>>>(sc, target);
   return hipGetLastError();
 }
 
@@ -299,7 +306,7 @@ hipError_t launch_oc_update_group(hipStream_t s, int G, int64_t nel, const OcArg
   for (int i = 0; i < G; ++i) fin[i] = fin_sum(&o[i].sc->vconst);
   e = launch_finalize_group(s, G, red, (int)nr, 1, fin, noskip);
   if (e != hipSuccess) return e;
-  oc_init_group_kernel<<<1, G, 0, s>>>(t);
+  oc_init_group_kernel<<<G, 64, 0, s>>>(t);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   // multisection passes
   const unsigned np = oc_blocks(nel, kOcPassBlocks);
