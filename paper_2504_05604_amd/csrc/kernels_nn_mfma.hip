@@ -123,38 +123,18 @@ __global__ __launch_bounds__(256) void igemm_mfma_kernel(GemmArgs a, int kchunk)
       *reinterpret_cast<bf16x8 *>(&As[arow * kPitch + ak0]) = v;
     }
     // ---- B slab [TN][32] (column-major: k contiguous)
-    {
+    if (kNMajor) {
       __bf16 vals[KPT];
-      if (kNMajor) {
 #pragma unroll
-        for (int q = 0; q < KPT; ++q) {
-          const int k = k0 + bk0 + q;
-          float v = 0.0f;
-          if (col_ok && k < ke) {
-            if (MODE == GB_PLAIN) v = a.src[(int64_t)k * a.N + n_b];
-            else if (MODE == GB_CONV) v = gat_conv(a.src, g, k / 27, pcol, k % 27);
-            else v = gat_convt(a.src, g, k / 27, pcol, k % 27);
-          }
-          vals[q] = (__bf16)v;
+      for (int q = 0; q < KPT; ++q) {
+        const int k = k0 + bk0 + q;
+        float v = 0.0f;
+        if (col_ok && k < ke) {
+          if (MODE == GB_PLAIN) v = a.src[(int64_t)k * a.N + n_b];
+          else if (MODE == GB_CONV) v = gat_conv(a.src, g, k / 27, pcol, k % 27);
+          else v = gat_convt(a.src, g, k / 27, pcol, k % 27);
         }
-      } else {
-        // k runs over spatial positions (b, o) on go; column n = (ci, t) or ci
-        const int kfirst = k0 + bk0;
-        Pos pk{};
-        if (MODE == GB_WGRAD && kfirst < ke) pk = decode_pos(kfirst, g.go);
-        const int ch = MODE == GB_WGRAD ? n_b / 27 : n_b;
-        const int tap = MODE == GB_WGRAD ? n_b % 27 : 0;
-#pragma unroll
-        for (int q = 0; q < KPT; ++q) {
-          const int k = kfirst + q;
-          float v = 0.0f;
-          if (col_ok && k < ke) {
-            if (MODE == GB_PLAINT) v = a.src[(int64_t)n_b * a.K + k];
-            else v = gat_conv(a.src, g, ch, pk, tap);
-          }
-          if (MODE == GB_WGRAD) advance(pk, g.go);
-          vals[q] = (__bf16)v;
-        }
+        vals[q] = (__bf16)v;
       }
 #pragma unroll
       for (int q = 0; q < KPT; q += 8) {
@@ -163,6 +143,28 @@ __global__ __launch_bounds__(256) void igemm_mfma_kernel(GemmArgs a, int kchunk)
         for (int e = 0; e < 8; ++e) v[e] = vals[q + e];
         *reinterpret_cast<bf16x8 *>(&Bs[bcol * kPitch + bk0 + q]) = v;
       }
+    } else {
+      // k runs over spatial positions (b, o) on go, column n = (ci, t) or ci.
+      // The lanes take consecutive k (one position each, so a column's gather
+      // is one contiguous run), every thread all columns c0 + 8 j of the tile.
+      constexpr int CPT = TN / (256 / kKs);
+      const int kk = tid % kKs, c0 = tid / kKs;
+      const int k = k0 + kk;
+      const bool k_ok = k < ke;
+      Pos pk{};
+      if (MODE == GB_WGRAD && k_ok) pk = decode_pos(k, g.go);
+      float v[CPT];
+#pragma unroll
+      for (int j = 0; j < CPT; ++j) {
+        const int n = n0 + c0 + 8 * j;
+        v[j] = 0.0f;
+        if (k_ok && n < a.N) {
+          if (MODE == GB_PLAINT) v[j] = a.src[(int64_t)n * a.K + k];
+          else v[j] = gat_conv(a.src, g, n / 27, pk, n % 27);
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < CPT; ++j) Bs[(c0 + 8 * j) * kPitch + kk] = (__bf16)v[j];
     }
     __syncthreads();
     // ---- matrix-core products
