@@ -257,6 +257,35 @@ constexpr int kLdsDense = 140;  // n*n doubles + pivot row/column fit in 160 KB 
 constexpr int kGjNb = 64;       // panel width of the blocked elimination
 constexpr int kGjQ = 32;        // inner-dimension chunk staged in LDS by the tile kernels
 
+// One chunk of kGjQ inner indices of a 64 x 64 tile product on the FP64 matrix
+// cores (v_mfma_f64_16x16x4f64): wave w owns the 32 x 32 quadrant (w / 2, w % 2)
+// as 2 x 2 tiles of 16 x 16.  Operand lanes: X[i][k] from lane i + 16 k, Y[k][j]
+// from lane j + 16 k; result row (lane / 16) + 4 r, column lane % 16 in acc[r].
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ void gj_mfma_chunk(const double (*Xs)[kGjQ + 1], const double (*Ys)[kGjNb],
+                                              f64x4 (&acc)[2][2]) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int r0 = (w >> 1) * 32, c0 = (w & 1) * 32, li = lane & 15, lk = lane >> 4;
+#pragma unroll
+  for (int q = 0; q < kGjQ; q += 4) {
+    double a[2], b[2];
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      a[t] = Xs[r0 + 16 * t + li][q + lk];
+      b[t] = Ys[q + lk][c0 + 16 * t + li];
+    }
+#pragma unroll
+    for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+      for (int tj = 0; tj < 2; ++tj) acc[ti][tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[ti], b[tj], acc[ti][tj], 0, 0, 0);
+  }
+}
+// tile row and column of acc[ti][tj][r] of this lane
+__device__ __forceinline__ int gj_acc_row(int ti, int r) {
+  return ((threadIdx.x >> 6) >> 1) * 32 + 16 * ti + ((threadIdx.x & 63) >> 4) + 4 * r;
+}
+__device__ __forceinline__ int gj_acc_col(int tj) { return ((threadIdx.x >> 6) & 1) * 32 + 16 * tj + (threadIdx.x & 15); }
+
 __device__ __forceinline__ double gj_update(double a, int i, int j, int k, double inv,
                                             const double *col, const double *rowk) {
   if (i == k) return (j == k) ? inv : rowk[j] * inv;
@@ -360,7 +389,6 @@ __global__ __launch_bounds__(256) void gj_panel_inv_group_kernel(int n, GroupTab
 // The two roles touch disjoint parts of A.
 __device__ __forceinline__ void gj_panel_rows_body(int n, double *A, int k0, int kb, const double *P, double *C) {
   const int nt = (n + kGjNb - 1) / kGjNb, kt = k0 / kGjNb;
-  const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
   if ((int)blockIdx.x >= nt) {
     const int it = blockIdx.x - nt;
     if (it == kt) return;
@@ -376,30 +404,41 @@ __device__ __forceinline__ void gj_panel_rows_body(int n, double *A, int k0, int
   const int j0 = jt * kGjNb, cols = min(kGjNb, n - j0);
   __shared__ double Ps[kGjNb][kGjQ + 1];
   __shared__ double Bs[kGjQ][kGjNb];
-  double acc[4][4] = {};
+  f64x4 acc[2][2];
+#pragma unroll
+  for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+    for (int tj = 0; tj < 2; ++tj) acc[ti][tj] = f64x4{0.0, 0.0, 0.0, 0.0};
+  constexpr int NL = kGjNb * kGjQ / 256;
   for (int q0 = 0; q0 < kb; q0 += kGjQ) {
-    for (int t = threadIdx.x; t < kGjNb * kGjQ; t += blockDim.x) {
+    double pv[NL], bv[NL];
+#pragma unroll
+    for (int u = 0; u < NL; ++u) {  // every load of the chunk before the first LDS store
+      const int t = threadIdx.x + 256 * u;
       const int r = t / kGjQ, q = t % kGjQ;
-      Ps[r][q] = (r < kb && q0 + q < kb) ? P[r * kb + q0 + q] : 0.0;
+      pv[u] = (r < kb && q0 + q < kb) ? P[r * kb + q0 + q] : 0.0;
       const int qb = t / kGjNb, c = t % kGjNb;
-      Bs[qb][c] = (q0 + qb < kb && c < cols) ? A[(int64_t)(k0 + q0 + qb) * n + j0 + c] : 0.0;
+      bv[u] = (q0 + qb < kb && c < cols) ? A[(int64_t)(k0 + q0 + qb) * n + j0 + c] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < NL; ++u) {
+      const int t = threadIdx.x + 256 * u;
+      Ps[t / kGjQ][t % kGjQ] = pv[u];
+      Bs[t / kGjNb][t % kGjNb] = bv[u];
     }
     __syncthreads();
-#pragma unroll 8
-    for (int q = 0; q < kGjQ; ++q)
-#pragma unroll
-      for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int b = 0; b < 4; ++b) acc[a][b] = fma(Ps[ty + 16 * a][q], Bs[q][tx + 16 * b], acc[a][b]);
+    gj_mfma_chunk(Ps, Bs, acc);
     __syncthreads();
   }
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+  for (int ti = 0; ti < 2; ++ti)
 #pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      const int r = ty + 16 * a, c = tx + 16 * b;
-      if (r < kb && c < cols) A[(int64_t)(k0 + r) * n + j0 + c] = acc[a][b];
-    }
+    for (int tj = 0; tj < 2; ++tj)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int r = gj_acc_row(ti, q), c = gj_acc_col(tj);
+        if (r < kb && c < cols) A[(int64_t)(k0 + r) * n + j0 + c] = acc[ti][tj][q];
+      }
 }
 __global__ __launch_bounds__(256) void gj_panel_rows_kernel(int n, double *A, int k0, int kb,
                                                             const double *P, double *C) {
@@ -425,39 +464,58 @@ __device__ __forceinline__ void gj_update_body(int n, double *A, int k0, int kb,
     return;
   }
   const bool panel = jt == kt;
-  const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
   __shared__ double Cs[kGjNb][kGjQ + 1];
   __shared__ double Bs[kGjQ][kGjNb];
-  double acc[4][4] = {};
+  f64x4 acc[2][2];
+#pragma unroll
+  for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+    for (int tj = 0; tj < 2; ++tj) acc[ti][tj] = f64x4{0.0, 0.0, 0.0, 0.0};
+  // the tile entries this lane updates, loaded first (their latency hides
+  // behind the staging and the products)
+  double old[2][2][4];
+#pragma unroll
+  for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+    for (int tj = 0; tj < 2; ++tj)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int r = gj_acc_row(ti, q), c = gj_acc_col(tj);
+        old[ti][tj][q] = (!panel && r < rows && c < cols) ? A[(int64_t)(i0 + r) * n + j0 + c] : 0.0;
+      }
+  constexpr int NL = kGjNb * kGjQ / 256;
   for (int q0 = 0; q0 < kb; q0 += kGjQ) {
-    for (int t = threadIdx.x; t < kGjNb * kGjQ; t += blockDim.x) {
+    double cv[NL], bv[NL];
+#pragma unroll
+    for (int u = 0; u < NL; ++u) {  // every load of the chunk before the first LDS store
+      const int t = threadIdx.x + 256 * u;
       const int r = t / kGjQ, q = t % kGjQ;
-      Cs[r][q] = (r < rows && q0 + q < kb) ? C[(int64_t)(i0 + r) * kb + q0 + q] : 0.0;
+      cv[u] = (r < rows && q0 + q < kb) ? C[(int64_t)(i0 + r) * kb + q0 + q] : 0.0;
       const int qb = t / kGjNb, c = t % kGjNb;
-      double bv = 0.0;
+      bv[u] = 0.0;
       if (q0 + qb < kb && c < cols)
-        bv = panel ? P[(q0 + qb) * kb + c] : A[(int64_t)(k0 + q0 + qb) * n + j0 + c];
-      Bs[qb][c] = bv;
+        bv[u] = panel ? P[(q0 + qb) * kb + c] : A[(int64_t)(k0 + q0 + qb) * n + j0 + c];
+    }
+#pragma unroll
+    for (int u = 0; u < NL; ++u) {
+      const int t = threadIdx.x + 256 * u;
+      Cs[t / kGjQ][t % kGjQ] = cv[u];
+      Bs[t / kGjNb][t % kGjNb] = bv[u];
     }
     __syncthreads();
-#pragma unroll 8
-    for (int q = 0; q < kGjQ; ++q)
-#pragma unroll
-      for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int b = 0; b < 4; ++b) acc[a][b] = fma(Cs[ty + 16 * a][q], Bs[q][tx + 16 * b], acc[a][b]);
+    gj_mfma_chunk(Cs, Bs, acc);
     __syncthreads();
   }
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+  for (int ti = 0; ti < 2; ++ti)
 #pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      const int r = ty + 16 * a, c = tx + 16 * b;
-      if (r < rows && c < cols) {
-        double *dst = A + (int64_t)(i0 + r) * n + j0 + c;
-        *dst = panel ? -acc[a][b] : *dst - acc[a][b];
+    for (int tj = 0; tj < 2; ++tj)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int r = gj_acc_row(ti, q), c = gj_acc_col(tj);
+        if (r < rows && c < cols)
+          A[(int64_t)(i0 + r) * n + j0 + c] = panel ? -acc[ti][tj][q] : old[ti][tj][q] - acc[ti][tj][q];
       }
-    }
 }
 __global__ __launch_bounds__(256) void gj_update_kernel(int n, double *A, int k0, int kb,
                                                         const double *P, const double *C) {
