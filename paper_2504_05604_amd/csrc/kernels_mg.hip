@@ -341,31 +341,64 @@ __device__ __forceinline__ double read_lane_f64(double v, int lane) {
 
 // P = A_KK^-1 for the panel K = [k0, k0 + kb), the block padded to kGjNb x kGjNb
 // with the identity.  Four waves; lane c of wave w holds column c of rows
-// 16 w .. 16 w + 15 in registers.  Step k: the wave holding row k publishes it
-// through LDS (double-buffered, one four-wave barrier per step), and every lane
-// reads the pivot column entries of its own rows from lane k of its own wave.
+// 16 w .. 16 w + 15 in registers.  Gauss-Jordan steps on a symmetric matrix
+// keep it symmetric within the eliminated indices and within the remaining
+// ones and antisymmetric between the two sets, so the pivot column of step k
+// is the pivot row with the signs of its eliminated entries flipped.  The wave
+// holding row k publishes through LDS the row scaled by the reciprocal pivot,
+// its signed copy (the column) and the reciprocal; after the step's barrier
+// every wave reads them in one batch, and each element update is one product
+// and one fused multiply-add.  The wave holding row k + 1 updates and publishes
+// it before its other rows, so the next division overlaps them; one barrier
+// per step (double-buffered LDS).  Steps past kb (the identity padding) change
+// nothing in the kb x kb block and are skipped by 16s.
+__device__ __forceinline__ void gj_publish(double mk, int k, int c, double *prow, double *pcol, double *pinv) {
+  const double inv = 1.0 / read_lane_f64(mk, k);  // 1 / M[k][k]
+  prow[c] = mk * inv;
+  pcol[c] = c < k ? -mk : mk;  // M[c][k]
+  if (c == 0) *pinv = inv;
+}
+
+// one elimination step on the wave's rows but row `skip`: column k becomes
+// -M[r][k] / M[k][k] (keep 0, coef 1 / M[k][k]), every other column subtracts
+// M[r][k] times the scaled pivot row (keep 1)
+__device__ __forceinline__ void gj_rows(double (&M)[16], const double (&pc)[16], double keep, double coef,
+                                        int skip) {
+#pragma unroll
+  for (int i = 0; i < 16; ++i)
+    if (i != skip) M[i] = fma(-pc[i], coef, keep * M[i]);
+}
+
 __device__ __forceinline__ void gj_panel_inv_body(int n, const double *A, int k0, int kb, double *P) {
-  __shared__ double piv[2][kGjNb];
-  const int c = threadIdx.x % kGjNb, w = threadIdx.x / kGjNb;
+  __shared__ double prow[2][kGjNb], pcol[2][kGjNb], pinv[2];
+  const int c = threadIdx.x % kGjNb;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kGjNb);  // wave-uniform
   double M[16];
 #pragma unroll
   for (int i = 0; i < 16; ++i) {
     const int r = 16 * w + i;
     M[i] = (r < kb && c < kb) ? A[(int64_t)(k0 + r) * n + k0 + c] : (r == c ? 1.0 : 0.0);
   }
+  if (w == 0) gj_publish(M[0], 0, c, prow[0], pcol[0], &pinv[0]);
+  for (int kw = 0; kw < 4 && 16 * kw < kb; ++kw) {
 #pragma unroll
-  for (int k = 0; k < kGjNb; ++k) {
-    double *pv = piv[k & 1];
-    if (w == k / 16) pv[c] = M[k % 16];
-    __syncthreads();
-    const double pk = pv[c];  // M[k][c]
-    const double inv = 1.0 / pv[k];
+    for (int kk = 0; kk < 16; ++kk) {
+      const int k = 16 * kw + kk, b = k & 1;
+      __syncthreads();
+      double pc[16];
 #pragma unroll
-    for (int i = 0; i < 16; ++i) {
-      const int r = 16 * w + i;
-      const double ck = read_lane_f64(M[i], k);  // M[r][k]
-      const double upd = M[i] - ck * pk * inv;
-      M[i] = r == k ? (c == k ? inv : pk * inv) : (c == k ? -ck * inv : upd);
+      for (int i = 0; i < 16; ++i) pc[i] = pcol[b][16 * w + i];
+      const double pr = prow[b][c], inv = pinv[b];
+      const double keep = c == k ? 0.0 : 1.0, coef = c == k ? inv : pr;
+      const int in = (kk + 1) % 16;  // register of row k + 1 in its wave
+      if (k + 1 < kGjNb && w == (k + 1) / 16) {
+        M[in] = fma(-pc[in], coef, keep * M[in]);
+        gj_publish(M[in], k + 1, c, prow[b ^ 1], pcol[b ^ 1], &pinv[b ^ 1]);
+        gj_rows(M, pc, keep, coef, in);
+      } else {
+        gj_rows(M, pc, keep, coef, -1);
+      }
+      if (w == kw) M[kk] = c == k ? inv : pr;  // the pivot row itself
     }
   }
 #pragma unroll
