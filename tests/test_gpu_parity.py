@@ -168,6 +168,27 @@ def test_preconditioner_with_large_coarsest_level_matches_oracle(dims, degrees):
     assert np.abs(got - ref).max() <= 1e-10 * np.abs(ref).max()
 
 
+@pytest.mark.parametrize("dims,cap,ncoarse", [((12, 4, 4), 200, 189), ((24, 12, 12), 2000, 1911)])
+def test_coarse_inverse_panel_edge_sizes(dims, cap, ncoarse):
+    """Coarsest levels just above the one-workgroup inverse (189 dofs: panels of
+    64, 64 and 61 columns) and near the 2048-dof limit (1911 dofs: 30 panels, the
+    last 55 wide) against the oracle's exact coarse solve."""
+    p = synth.cantilever(*dims, volfrac=0.3, rmin=1.5, n_iter=1)
+    x = synth.random_density(25, p.nel, 0.0, 1.0)
+    E = fem.simp_modulus(x, p.E0, p.Emin, p.penal)
+    r = synth.random_vector(26, p.ndof)
+    r[fixed_mask(p)] = 0.0
+    V = mg.VCycle(p, E, KE, degree=1, coarse_degree=4, max_coarse_dof=cap)
+    assert V.levels[-1].A.shape[0] == ncoarse
+    ref = V.apply(r)
+    with topo.Context(p, topo.default_opts(mg_max_coarse_dof=cap, cheb_degree=1, cheb_degree_coarse=4)) as ctx:
+        assert ctx.mg_levels == len(V.levels)
+        z = torch.empty(p.ndof, dtype=torch.float64, device="cuda")
+        ctx.apply_precond(dev(x), dev(r), z)
+        got = host(z)
+    assert np.abs(got - ref).max() <= 1e-10 * np.abs(ref).max()
+
+
 @pytest.mark.parametrize("kernel", list(KERNELS))
 @pytest.mark.parametrize("case", CASES)
 @pytest.mark.parametrize("precond", ["mg", "jacobi"])
