@@ -277,7 +277,7 @@ topo_status topo_oc_update(topo_ctx *ctx, const double *d_x, const double *d_dc,
  * allocate device memory (code under HIP graph capture, tight serving loops,
  * harnesses that forbid allocation): this call allocates nothing.  Its search
  * state and partial sums live in one fixed array of the library per GPU (about
- * 130 KB, held until the process ends; its size does not depend on nel), so
+ * 260 KB, held until the process ends; its size does not depend on nel), so
  * calls that overlap on one GPU (concurrent streams or threads) race and must
  * be serialised by the caller; each call fully rewrites the state it reads.
  * Arguments: nel >= 1 elements; d_x, d_dc, d_dv, d_xnew (nel FP64 each) and

@@ -521,10 +521,20 @@ hipError_t launch_sensitivity_group(hipStream_t s, int G, Grid g, const SensArgs
 // every pass recomputes them from x, dc and dv (the same bits).  Partials: the
 // pass kernels use kOcPassBlocks x kOcStride slots, the prepare and final
 // reductions kOcReduceBlocks x kMaxRed.
-constexpr int kOcPassBlocks = 256, kOcReduceBlocks = 1024, kOcStride = 64;
+constexpr int kOcPassBlocks = 512, kOcReduceBlocks = 1024, kOcStride = 64;
 constexpr int kOcPartials = kOcPassBlocks * kOcStride > kOcReduceBlocks * kMaxRed
                                 ? kOcPassBlocks * kOcStride : kOcReduceBlocks * kMaxRed;
-constexpr int kOcPasses = 16;  // multisection passes (a 1e80 bracket shrinks below 1e-12)
+// Multisection passes launched for a final relative bracket width tol: from the
+// initial 1e80 bracket two geometric passes (each shrinks the log-range 64-fold)
+// leave a bracket within a factor 2, a relative width of at most 1/3, which each
+// linear pass shrinks 64-fold; one pass spare, at most kOcMaxPasses (passes
+// after convergence return at once).  10 for tol = 1e-12.
+constexpr int kOcMaxPasses = 16;
+inline int oc_pass_launches(double tol) {
+  int n = 3;
+  for (double w = 1.0 / 3.0; w >= tol && n < kOcMaxPasses; w /= 64.0) ++n;
+  return n;
+}
 hipError_t launch_oc_prepare(hipStream_t s, int64_t nel, const double *x, const double *dc,
                              const double *dv, const int8_t *mask, double eta, double target,
                              double *a, Scalars *sc, const Reducer &red);
@@ -534,7 +544,7 @@ hipError_t launch_oc_pass(hipStream_t s, int64_t nel, const double *x, const dou
 hipError_t launch_oc_final(hipStream_t s, int64_t nel, const double *x, const double *a,
                            const double *dc, const double *dv, const int8_t *mask, double move,
                            double eta, double *xnew, Scalars *sc, const Reducer &red);
-// prepare, kOcPasses passes and the final update of G problems with nel
+// prepare, the multisection passes and the final update of G problems with nel
 // elements each, every launch shared by the group (a: stored coefficients)
 struct OcArgs {
   const double *x, *dc, *dv;

@@ -8,6 +8,8 @@
 // spacing while the bracket spans more than a factor 2, linear after) and keeps
 // the sub-interval in which V crosses the target; the bracket shrinks by a
 // factor 64 per pass instead of 2 per bisection step, and the host never waits.
+#include <algorithm>
+
 #include "group_host.h"
 #include "internal.h"
 #include "reduce_dev.h"
@@ -94,7 +96,14 @@ __global__ void oc_init_group_kernel(GroupTab<OcArgs> t) {
   oc_init_body(o.sc, o.target);
 }
 
-// Partial volumes of one block for every candidate multiplier.
+// Partial volumes of one block for every candidate multiplier.  A thread takes
+// its elements e0, e0 + S, e0 + 2S, ... (S threads in the grid) in groups of
+// kOcGroup: the loads of the next group are issued before the arithmetic of the
+// current one, and each candidate's lambda^-eta, read once from LDS, serves the
+// whole group.  Elements outside the design (mask) or past nel contribute exact
+// zeros (x_new of x = a = 0 is 0, weighted by 0), so every accumulator adds the
+// same terms in the same order as a plain element-by-element loop.
+constexpr int kOcGroup = 4;
 template <bool kStored>
 __device__ __forceinline__ void oc_pass_body(int64_t nel, const double *__restrict__ x,
                                              const double *__restrict__ a, const double *__restrict__ dc,
@@ -108,19 +117,68 @@ __device__ __forceinline__ void oc_pass_body(int64_t nel, const double *__restri
   double part[kOcCand];
 #pragma unroll
   for (int c = 0; c < kOcCand; ++c) part[c] = 0.0;
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nel;
-       e += (int64_t)gridDim.x * blockDim.x) {
-    if (mask[e] != 0) continue;
-    const double xe = x[e], ae = oc_a_of<kStored>(a, dc, dv, xe, eta, e), we = dv[e];
+  constexpr int U = kOcGroup;
+  const int64_t S = (int64_t)gridDim.x * blockDim.x;
+  // raw loads of a group (clamped index: in bounds, selected at use)
+  struct Grp {
+    double x[U], q[U], w[U];  // q: a (stored) or dc (recomputed)
+    int8_t m[U];
+  };
+  auto fetch = [&](int64_t eb, Grp &g) {
 #pragma unroll
-    for (int c = 0; c < kOcCand; ++c) part[c] = fma(we, oc_value(xe, ae, lampow[c], move), part[c]);
+    for (int u = 0; u < U; ++u) {
+      const int64_t ec = min(eb + u * S, nel - 1);
+      g.x[u] = x[ec];
+      g.q[u] = kStored ? a[ec] : dc[ec];
+      g.w[u] = dv[ec];
+      g.m[u] = mask[ec];
+    }
+  };
+  Grp cur, nxt;
+  int64_t eb = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (eb < nel) fetch(eb, cur);
+  for (; eb < nel; eb += U * S) {
+    if (eb + U * S < nel) fetch(eb + U * S, nxt);
+    double xe[U], ae[U], we[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const bool ok = eb + u * S < nel && cur.m[u] == 0;
+      const double ar = kStored ? cur.q[u] : oc_coef(cur.x[u], cur.q[u], cur.w[u], eta);
+      xe[u] = ok ? cur.x[u] : 0.0;
+      ae[u] = ok ? ar : 0.0;
+      we[u] = ok ? cur.w[u] : 0.0;
+    }
+    // an index the compiler cannot see through: keeps the 63 reads of lampow
+    // inside the loop (hoisted, they would hold 126 more registers)
+    int l0 = 0;
+    asm volatile("" : "+v"(l0));
+#pragma unroll
+    for (int c = 0; c < kOcCand; ++c) {
+      const double lp = lampow[c + l0];
+#pragma unroll
+      for (int u = 0; u < U; ++u) part[c] = fma(we[u], oc_value(xe[u], ae[u], lp, move), part[c]);
+    }
+    cur = nxt;
   }
+  // the wave's sums of the 64 accumulators (the last one zero) by recursive
+  // halving: at distance k a lane keeps half of its current range, adds its
+  // partner's copy of that half and hands the other half over, so lane c ends
+  // with candidate c (63 exchanges instead of 63 separate wave reductions)
   const int lane = threadIdx.x & 63, wid = threadIdx.x / 64;
+  double v[64];
 #pragma unroll
-  for (int c = 0; c < kOcCand; ++c) {
-    const double t = wave_reduce<false>(part[c]);
-    if (lane == 0) sh[c][wid] = t;
+  for (int c = 0; c < 64; ++c) v[c] = c < kOcCand ? part[c] : 0.0;
+#pragma unroll
+  for (int k = 32; k >= 1; k >>= 1) {
+    const bool upper = (lane & k) != 0;
+#pragma unroll
+    for (int i = 0; i < k; ++i) {
+      const double send = upper ? v[i] : v[k + i];
+      const double keep = upper ? v[k + i] : v[i];
+      v[i] = keep + __shfl_xor(send, k, 64);
+    }
   }
+  if (lane < kOcCand) sh[lane][wid] = v[0];
   __syncthreads();
   for (int c = threadIdx.x; c < kOcCand; c += blockDim.x) {
     double t = 0.0;
@@ -144,36 +202,40 @@ __global__ __launch_bounds__(kBs) void oc_pass_group_kernel(int64_t nel, GroupTa
   oc_pass_body<true>(nel, o.x, o.a, o.dc, o.dv, o.mask, o.move, o.eta, o.sc, part.v[blockIdx.z]);
 }
 
-// Sums the pass partials (fixed order: 4 interleaved lanes per candidate, then
-// a fixed pairwise combine), keeps the crossing sub-interval.
-constexpr int kSelThreads = 256;
+// Sums the pass partials and keeps the crossing sub-interval.  Wave w of the
+// 16 reads partial rows w, w + 16, ... with lane = candidate (each load one
+// contiguous row, every load of the lane in flight at once: the loop is
+// unrolled to the largest count), into four running sums (row index / 16 mod
+// 4); the first wave adds the 16 wave sums in a fixed pairwise order.
+// nparts <= kOcPassBlocks.
+constexpr int kSelThreads = 1024;
 __device__ __forceinline__ void oc_select_body(int nparts, double tol, Scalars *sc, const double *partials) {
   if (sc->oc_done) return;
-  __shared__ double V[kOcCand];
-  const int c = threadIdx.x >> 2, part = threadIdx.x & 3;  // 64 candidates x 4 lanes
-  double t = 0.0;
-  if (c < kOcCand) {
-    int b = part;
-    for (; b + 12 < nparts; b += 16) {
-      const double v0 = partials[(size_t)b * kOcStride + c];
-      const double v1 = partials[(size_t)(b + 4) * kOcStride + c];
-      const double v2 = partials[(size_t)(b + 8) * kOcStride + c];
-      const double v3 = partials[(size_t)(b + 12) * kOcStride + c];
-      t += (v0 + v1) + (v2 + v3);
-    }
-    for (; b < nparts; b += 4) t += partials[(size_t)b * kOcStride + c];
+  constexpr int kW = kSelThreads / 64, kPer = (kOcPassBlocks + kW - 1) / kW;
+  __shared__ double Vw[kW][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int j = 0; j < kPer; ++j) {
+    const int b = w + kW * j;
+    acc[j & 3] += (b < nparts && lane < kOcCand) ? partials[(size_t)b * kOcStride + lane] : 0.0;
   }
-  t += __shfl_down(t, 2, 4);
-  t += __shfl_down(t, 1, 4);
-  if (c < kOcCand && part == 0) V[c] = t + sc->vconst;
+  Vw[w][lane] = (acc[0] + acc[1]) + (acc[2] + acc[3]);
   __syncthreads();
   if (threadIdx.x >= 64) return;
+  double t[kW];
+#pragma unroll
+  for (int q = 0; q < kW; ++q) t[q] = Vw[q][lane];
+#pragma unroll
+  for (int h = kW / 2; h >= 1; h /= 2)
+#pragma unroll
+    for (int q = 0; q < h; ++q) t[q] += t[q + h];
+  const double Vc = t[0] + sc->vconst;
   // the crossing: V is non-increasing in lambda, and the bracket keeps the last
   // candidate above the target and the first one at or below it (a scan over
   // the candidates stopping at the first one not above); one wave, lane = candidate
-  const int lane = threadIdx.x;
   const double target = sc->target;
-  const bool above = lane < kOcCand && V[lane] > target;
+  const bool above = lane < kOcCand && Vc > target;
   const unsigned long long m = __ballot(above);
   const int first_below = __builtin_ctzll(~m);  // lane kOcCand (never above) bounds it
   double l1 = sc->l1, l2 = sc->l2;
@@ -310,7 +372,10 @@ hipError_t launch_oc_update_group(hipStream_t s, int G, int64_t nel, const OcArg
   if ((e = hipGetLastError()) != hipSuccess) return e;
   // multisection passes
   const unsigned np = oc_blocks(nel, kOcPassBlocks);
-  for (int pass = 0; pass < kOcPasses; ++pass) {
+  double tol = o[0].tol;  // enough passes for the tightest member
+  for (int i = 1; i < G; ++i) tol = std::min(tol, o[i].tol);
+  const int passes = oc_pass_launches(tol);
+  for (int pass = 0; pass < passes; ++pass) {
     oc_pass_group_kernel<<<dim3(np, 1, G), kBs, 0, s>>>(nel, t, part);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     oc_select_group_kernel<<<G, kSelThreads, 0, s>>>((int)np, t, part);

@@ -17,7 +17,7 @@ constexpr size_t kScratchDoubles = kScalarDoubles + (size_t)kOcPartials;
 static_assert(sizeof(Scalars) <= kScalarDoubles * sizeof(double), "scalar block fits");
 }  // namespace
 
-// The fixed workspace (about 130 KB).  Host code never uses this name as an
+// The fixed workspace (about 260 KB).  Host code never uses this name as an
 // address: it stands for a device symbol, whose address on each GPU comes from
 // hipGetSymbolAddress below.
 static __device__ __align__(256) double scratch[kScratchDoubles];
@@ -69,7 +69,8 @@ extern "C" topo_status topo_oc_update_noalloc(int64_t nel, const double *d_x, co
   // the search state is fully written by the prepare launches (bracket, target,
   // pass count, candidates, the passive elements' volume): nothing to clear
   TOPO_HIP(launch_oc_prepare(s, nel, d_x, d_dc, d_dv, d_mask, eta, target, nullptr, sc, red));
-  for (int pass = 0; pass < kOcPasses; ++pass)
+  const int passes = oc_pass_launches(oc_tol);
+  for (int pass = 0; pass < passes; ++pass)
     TOPO_HIP(launch_oc_pass(s, nel, d_x, nullptr, d_dc, d_dv, d_mask, move, eta, oc_tol, sc, red));
   TOPO_HIP(launch_oc_final(s, nel, d_x, nullptr, d_dc, d_dv, d_mask, move, eta, d_xnew, sc, red));
   if (d_result) {

@@ -1849,8 +1849,8 @@ static topo_status oc_update(topo_ctx *ctx, const double *d_x, const double *d_d
   const topo_problem &P = ctx->prob;
   TOPO_HIP(launch_oc_prepare(s, ctx->nel, d_x, d_dc, d_dv, ctx->mask, P.eta, ctx->target, ctx->oc_a,
                              ctx->sc, ctx->red));
-  // worst case: 1e80 bracket, geometric passes shrink by 64x in log, linear by 64x
-  for (int pass = 0; pass < kOcPasses; ++pass)
+  const int passes = oc_pass_launches(ctx->opts.oc_tol);
+  for (int pass = 0; pass < passes; ++pass)
     TOPO_HIP(launch_oc_pass(s, ctx->nel, d_x, ctx->oc_a, d_dc, d_dv, ctx->mask, P.move, P.eta,
                             ctx->opts.oc_tol, ctx->sc, ctx->red));
   TOPO_HIP(launch_oc_final(s, ctx->nel, d_x, ctx->oc_a, d_dc, d_dv, ctx->mask, P.move, P.eta, d_xnew,
