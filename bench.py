@@ -651,7 +651,7 @@ def main():
     ap.add_argument("--ku-kernel", choices=["auto", "node", "element"], default="auto",
                     help="K.u kernel: node columns or element columns in the sum/difference basis")
     ap.add_argument("--ku-shape", type=int, default=-1, help="one K.u launch shape for every level (-1: by grid size)")
-    ap.add_argument("--cheb-upper", type=float, default=0.8,
+    ap.add_argument("--cheb-upper", type=float, default=0.7,
                     help="top of the smoothing interval as a fraction of the element bound (1: the bound)")
     ap.add_argument("--coarse-refresh", type=int, default=2,
                     help="recompute the coarsest level's dense inverse every this many SIMP iterations "

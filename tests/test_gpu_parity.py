@@ -121,7 +121,7 @@ def test_preconditioner_matches_oracle(case, precond, kernel):
     assert np.abs(got - ref).max() <= 1e-11 * np.abs(ref).max()
 
 
-@pytest.mark.parametrize("upper", [1.0, 0.8])
+@pytest.mark.parametrize("upper", [1.0, 0.8, 0.7])
 @pytest.mark.parametrize("kernel", list(KERNELS))
 @pytest.mark.parametrize("tail", [0, 1024])
 @pytest.mark.parametrize("lev", [[1, 2, 4, 6], [2, 3, 1, 5]])
