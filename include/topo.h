@@ -268,7 +268,10 @@ topo_status topo_filter(topo_ctx *ctx, int32_t op, const double *d_in, const dou
  * volfrac * nel - (number of fixed-solid elements)); dv is therefore the volume weight vector: H(1_D/Hs) for the
  * density filter (TOPO_FILTER_VOLW), 1 on design and 0 on passive elements for
  * the sensitivity filter.  The multiplier bracket is narrowed until its relative
- * width is below oc_tol.  d_x, d_dc, d_dv, d_xnew: nel (d_xnew must not alias).
+ * width is below oc_tol (down to about 1e-16: the number of passes enqueued
+ * grows with -log(oc_tol) and is capped at 16, enough for 1e-16 from the
+ * initial [1e-40, 1e40] bracket).  d_x, d_dc, d_dv, d_xnew: nel (d_xnew must
+ * not alias).
  * h_change = max |x_new - x|, h_lambda (either may be NULL; synchronises if not). */
 topo_status topo_oc_update(topo_ctx *ctx, const double *d_x, const double *d_dc, const double *d_dv,
                            double *d_xnew, double *h_change, double *h_lambda);
