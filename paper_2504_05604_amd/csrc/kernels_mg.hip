@@ -183,21 +183,21 @@ __global__ void zero_group_kernel(int64_t n, GroupTab<AssembleArgs> t) {
   if (i < n) t.v[blockIdx.z].A[i] = 0.0;
 }
 
-__device__ __forceinline__ void dense_assemble_body(Grid g, const double *E, const Kappa &kap,
-                                                    const uint8_t *fixed, double *A) {
-  const int64_t n = g.ndof();
-  const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (row >= n) return;
-  double *Ar = A + row * n;
-  const int64_t node = row / 3;
-  const int comp = (int)(row % 3);
-  if ((fixed[node] >> comp) & 1) {
-    Ar[row] = 1.0;
-    return;
-  }
-  const int i = (int)(node % g.NX());
-  const int j = (int)((node / g.NX()) % g.NY());
-  const int k = (int)(node / ((int64_t)g.NX() * g.NY()));
+// One thread per row.  The row's dof couples with the 3 components of the 27
+// nodes around its node; those 81 entries are summed in registers over the up
+// to 8 elements around the node (element order e = 0..7, so every entry gets
+// the same additions in the same order as an in-place accumulation) and each is
+// written once; the rest of the row stays zero, as do fixed columns.  Threads
+// go component-major (all rows of component 0, then 1, then 2), so a wave has
+// one component and the element matrix entries are compile-time indices.
+template <int C>
+__device__ __forceinline__ void dense_assemble_row(const Grid &g, const double *E, const Kappa &kap,
+                                                   const uint8_t *fixed, double *Ar, int i, int j, int k) {
+  double acc[27][3];
+#pragma unroll
+  for (int o = 0; o < 27; ++o)
+#pragma unroll
+    for (int d = 0; d < 3; ++d) acc[o][d] = 0.0;
 #pragma unroll
   for (int e = 0; e < 8; ++e) {
     const int ex = e & 1, ey = (e >> 1) & 1, ez = e >> 2;
@@ -207,24 +207,46 @@ __device__ __forceinline__ void dense_assemble_body(Grid g, const double *E, con
     const int li = corner_of(1 - ex, 1 - ey, 1 - ez);
 #pragma unroll
     for (int b = 0; b < 8; ++b) {
-      const int64_t nb = (ei + cx(b)) + (int64_t)g.NX() * ((ej + cy(b)) + (int64_t)g.NY() * (ek + cz(b)));
-      const uint8_t fb = fixed[nb];
+      const int o = (ex + cx(b)) + 3 * (ey + cy(b)) + 9 * (ez + cz(b));  // neighbour (di, dj, dk) + 1
 #pragma unroll
-      for (int d = 0; d < 3; ++d) {
-        if ((fb >> d) & 1) continue;
-        const double kv = comp == 0 ? TOPO_KE(kap, 3 * li + 0, 3 * b + d)
-                          : comp == 1 ? TOPO_KE(kap, 3 * li + 1, 3 * b + d)
-                                      : TOPO_KE(kap, 3 * li + 2, 3 * b + d);
-        Ar[3 * nb + d] += Ee * kv;
-      }
+      for (int d = 0; d < 3; ++d) acc[o][d] += Ee * TOPO_KE(kap, 3 * li + C, 3 * b + d);
     }
   }
+#pragma unroll
+  for (int o = 0; o < 27; ++o) {
+    const int ni = i + o % 3 - 1, nj = j + (o / 3) % 3 - 1, nk = k + o / 9 - 1;
+    if (ni < 0 || ni >= g.NX() || nj < 0 || nj >= g.NY() || nk < 0 || nk >= g.NZ()) continue;
+    const int64_t nb = ni + (int64_t)g.NX() * (nj + (int64_t)g.NY() * nk);
+    const uint8_t fb = fixed[nb];
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+      if (!((fb >> d) & 1)) Ar[3 * nb + d] = acc[o][d];
+  }
 }
-__global__ void dense_assemble_kernel(Grid g, const double *E, Kappa kap, const uint8_t *fixed,
+__device__ __forceinline__ void dense_assemble_body(Grid g, const double *E, const Kappa &kap,
+                                                    const uint8_t *fixed, double *A) {
+  const int64_t nn = g.nnodes(), n = g.ndof();
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  const int comp = (int)(t / nn);
+  const int64_t node = t - comp * nn, row = 3 * node + comp;
+  double *Ar = A + row * n;
+  if ((fixed[node] >> comp) & 1) {
+    Ar[row] = 1.0;
+    return;
+  }
+  const int i = (int)(node % g.NX());
+  const int j = (int)((node / g.NX()) % g.NY());
+  const int k = (int)(node / ((int64_t)g.NX() * g.NY()));
+  if (comp == 0) dense_assemble_row<0>(g, E, kap, fixed, Ar, i, j, k);
+  else if (comp == 1) dense_assemble_row<1>(g, E, kap, fixed, Ar, i, j, k);
+  else dense_assemble_row<2>(g, E, kap, fixed, Ar, i, j, k);
+}
+__global__ __launch_bounds__(kBs) void dense_assemble_kernel(Grid g, const double *E, Kappa kap, const uint8_t *fixed,
                                       double *A) {
   dense_assemble_body(g, E, kap, fixed, A);
 }
-__global__ void dense_assemble_group_kernel(Grid g, GroupTab<AssembleArgs> t) {
+__global__ __launch_bounds__(kBs) void dense_assemble_group_kernel(Grid g, GroupTab<AssembleArgs> t) {
   const AssembleArgs &a = t.v[blockIdx.z];
   dense_assemble_body(g, a.E, a.kap, a.fixed, a.A);
 }
