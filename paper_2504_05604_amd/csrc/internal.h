@@ -108,14 +108,17 @@ inline Fin fin_max(double *out) { return Fin{FIN_MAX, out, nullptr}; }
 hipError_t launch_finalize(hipStream_t s, const Reducer &red, int nparts, int n, const Fin &fin,
                            const int *skip = nullptr);
 
-// E_e = Emin + xphys^p (E0 - Emin), times scale
+// E_e = Emin + xphys^p (E0 - Emin), times scale.  The set-up kernels below
+// also write a single-precision copy of their result where one is passed (E32,
+// Ec32, dinv32 may be NULL): the FP64 value rounded once.
 hipError_t launch_simp_modulus(hipStream_t s, int64_t nel, const double *xphys, double E0,
-                               double Emin, double penal, double scale, double *E);
+                               double Emin, double penal, double scale, double *E, float *E32 = nullptr);
 // E_c = 2 * mean of the 8 children (missing children count as 0)
-hipError_t launch_coarsen_moduli(hipStream_t s, Grid gf, Grid gc, const double *Ef, double *Ec);
+hipError_t launch_coarsen_moduli(hipStream_t s, Grid gf, Grid gc, const double *Ef, double *Ec,
+                                 float *Ec32 = nullptr);
 // dinv_i = 1 / sum_{e ni i} E_e KE_{li,li}; 0 on fixed dofs
 hipError_t launch_diag(hipStream_t s, Grid g, const double *E, const Kappa &kap,
-                       const uint8_t *fixed, double *dinv);
+                       const uint8_t *fixed, double *dinv, float *dinv32 = nullptr);
 
 // K.u variants (matrix-free, identity rows on fixed dofs); the input vector must
 // be zero on fixed dofs.
@@ -420,15 +423,17 @@ struct ModulusArgs {
   const double *xphys;
   double E0, Emin, penal;
   double *E;
+  float *E32;  // may be NULL
 };
 hipError_t launch_simp_modulus_group(hipStream_t s, int G, int64_t nel, const ModulusArgs *a);
 hipError_t launch_coarsen_moduli_group(hipStream_t s, int G, Grid gf, Grid gc, const double *const *Ef,
-                                       double *const *Ec);
+                                       double *const *Ec, float *const *Ec32);
 struct DiagArgs {
   const double *E;
   Kappa kap;
   const uint8_t *fixed;
   double *dinv;
+  float *dinv32;  // may be NULL
 };
 hipError_t launch_diag_group(hipStream_t s, int G, Grid g, const DiagArgs *a);
 struct AssembleArgs {

@@ -376,34 +376,37 @@ hipError_t launch_finalize(hipStream_t s, const Reducer &red, int nparts, int n,
 }
 
 // ---------------------------------------------------------------------------
+// E32 (may be NULL): the single-precision copy, rounded from the FP64 value
 __device__ __forceinline__ void simp_modulus_body(int64_t nel, const double *xphys, double E0, double Emin,
-                                                  double penal, double scale, double *E) {
+                                                  double penal, double scale, double *E, float *E32) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= nel) return;
   const double x = xphys[e];
   const double xp = (penal == 3.0) ? x * x * x : pow(x, penal);
-  E[e] = scale * (Emin + xp * (E0 - Emin));
+  const double v = scale * (Emin + xp * (E0 - Emin));
+  E[e] = v;
+  if (E32) E32[e] = (float)v;
 }
 __global__ void simp_modulus_kernel(int64_t nel, const double *xphys, double E0, double Emin,
-                                    double penal, double scale, double *E) {
-  simp_modulus_body(nel, xphys, E0, Emin, penal, scale, E);
+                                    double penal, double scale, double *E, float *E32) {
+  simp_modulus_body(nel, xphys, E0, Emin, penal, scale, E, E32);
 }
 __global__ void simp_modulus_group_kernel(int64_t nel, GroupTab<ModulusArgs> t) {
   const ModulusArgs &a = t.v[blockIdx.z];
-  simp_modulus_body(nel, a.xphys, a.E0, a.Emin, a.penal, 1.0, a.E);
+  simp_modulus_body(nel, a.xphys, a.E0, a.Emin, a.penal, 1.0, a.E, a.E32);
 }
 
 hipError_t launch_simp_modulus(hipStream_t s, int64_t nel, const double *xphys, double E0,
-                               double Emin, double penal, double scale, double *E) {
+                               double Emin, double penal, double scale, double *E, float *E32) {
   const int bs = 256;
   simp_modulus_kernel<<<(unsigned)((nel + bs - 1) / bs), bs, 0, s>>>(nel, xphys, E0, Emin, penal,
-                                                                    scale, E);
+                                                                    scale, E, E32);
   return hipGetLastError();
 }
 
 // Coarse modulus = 2 * mean of the 8 fine children (missing children are 0):
 // the factor 2 is the stiffness scaling of an element of twice the edge length.
-__device__ __forceinline__ void coarsen_moduli_body(Grid gf, Grid gc, const double *Ef, double *Ec) {
+__device__ __forceinline__ void coarsen_moduli_body(Grid gf, Grid gc, const double *Ef, double *Ec, float *Ec32) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= gc.nel()) return;
   const int I = (int)(e % gc.nx);
@@ -416,23 +419,25 @@ __device__ __forceinline__ void coarsen_moduli_body(Grid gf, Grid gc, const doub
     if (i < gf.nx && j < gf.ny && k < gf.nz) s += Ef[i + (int64_t)gf.nx * (j + (int64_t)gf.ny * k)];
   }
   Ec[e] = 0.25 * s;
+  if (Ec32) Ec32[e] = (float)(0.25 * s);
 }
-__global__ void coarsen_moduli_kernel(Grid gf, Grid gc, const double *Ef, double *Ec) {
-  coarsen_moduli_body(gf, gc, Ef, Ec);
+__global__ void coarsen_moduli_kernel(Grid gf, Grid gc, const double *Ef, double *Ec, float *Ec32) {
+  coarsen_moduli_body(gf, gc, Ef, Ec, Ec32);
 }
-__global__ void coarsen_moduli_group_kernel(Grid gf, Grid gc, GroupTab<const double *> Ef, GroupTab<double *> Ec) {
-  coarsen_moduli_body(gf, gc, Ef.v[blockIdx.z], Ec.v[blockIdx.z]);
+__global__ void coarsen_moduli_group_kernel(Grid gf, Grid gc, GroupTab<const double *> Ef, GroupTab<double *> Ec,
+                                            GroupTab<float *> Ec32) {
+  coarsen_moduli_body(gf, gc, Ef.v[blockIdx.z], Ec.v[blockIdx.z], Ec32.v[blockIdx.z]);
 }
 
-hipError_t launch_coarsen_moduli(hipStream_t s, Grid gf, Grid gc, const double *Ef, double *Ec) {
+hipError_t launch_coarsen_moduli(hipStream_t s, Grid gf, Grid gc, const double *Ef, double *Ec, float *Ec32) {
   const int bs = 256;
-  coarsen_moduli_kernel<<<(unsigned)((gc.nel() + bs - 1) / bs), bs, 0, s>>>(gf, gc, Ef, Ec);
+  coarsen_moduli_kernel<<<(unsigned)((gc.nel() + bs - 1) / bs), bs, 0, s>>>(gf, gc, Ef, Ec, Ec32);
   return hipGetLastError();
 }
 
 // inverse Jacobi diagonal: 1 / sum_{e around i} E_e KE[(3 li + c),(3 li + c)]; 0 on fixed dofs
 __device__ __forceinline__ void diag_body(Grid g, const double *E, const Kappa &kap, const uint8_t *fixed,
-                                          double *dinv) {
+                                          double *dinv, float *dinv32) {
   const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (n >= g.nnodes()) return;
   const int i = (int)(n % g.NX());
@@ -451,22 +456,29 @@ __device__ __forceinline__ void diag_body(Grid g, const double *E, const Kappa &
     d2 += Ee * TOPO_KE(kap, 3 * li + 2, 3 * li + 2);
   }
   const uint8_t fx = fixed[n];
-  dinv[3 * n + 0] = (fx & 1) ? 0.0 : 1.0 / d0;
-  dinv[3 * n + 1] = (fx & 2) ? 0.0 : 1.0 / d1;
-  dinv[3 * n + 2] = (fx & 4) ? 0.0 : 1.0 / d2;
+  const double v0 = (fx & 1) ? 0.0 : 1.0 / d0, v1 = (fx & 2) ? 0.0 : 1.0 / d1, v2 = (fx & 4) ? 0.0 : 1.0 / d2;
+  dinv[3 * n + 0] = v0;
+  dinv[3 * n + 1] = v1;
+  dinv[3 * n + 2] = v2;
+  if (dinv32) {
+    dinv32[3 * n + 0] = (float)v0;
+    dinv32[3 * n + 1] = (float)v1;
+    dinv32[3 * n + 2] = (float)v2;
+  }
 }
-__global__ void diag_kernel(Grid g, const double *E, Kappa kap, const uint8_t *fixed, double *dinv) {
-  diag_body(g, E, kap, fixed, dinv);
+__global__ void diag_kernel(Grid g, const double *E, Kappa kap, const uint8_t *fixed, double *dinv,
+                            float *dinv32) {
+  diag_body(g, E, kap, fixed, dinv, dinv32);
 }
 __global__ void diag_group_kernel(Grid g, GroupTab<DiagArgs> t) {
   const DiagArgs &a = t.v[blockIdx.z];
-  diag_body(g, a.E, a.kap, a.fixed, a.dinv);
+  diag_body(g, a.E, a.kap, a.fixed, a.dinv, a.dinv32);
 }
 
 hipError_t launch_diag(hipStream_t s, Grid g, const double *E, const Kappa &kap,
-                       const uint8_t *fixed, double *dinv) {
+                       const uint8_t *fixed, double *dinv, float *dinv32) {
   const int bs = 256;
-  diag_kernel<<<(unsigned)((g.nnodes() + bs - 1) / bs), bs, 0, s>>>(g, E, kap, fixed, dinv);
+  diag_kernel<<<(unsigned)((g.nnodes() + bs - 1) / bs), bs, 0, s>>>(g, E, kap, fixed, dinv, dinv32);
   return hipGetLastError();
 }
 
@@ -479,11 +491,11 @@ hipError_t launch_simp_modulus_group(hipStream_t s, int G, int64_t nel, const Mo
   return hipGetLastError();
 }
 hipError_t launch_coarsen_moduli_group(hipStream_t s, int G, Grid gf, Grid gc, const double *const *Ef,
-                                       double *const *Ec) {
+                                       double *const *Ec, float *const *Ec32) {
   if (!group_ok(G)) return hipErrorInvalidValue;
   const int bs = 256;
   coarsen_moduli_group_kernel<<<dim3((unsigned)((gc.nel() + bs - 1) / bs), 1, G), bs, 0, s>>>(
-      gf, gc, group_tab(G, Ef), group_tab(G, Ec));
+      gf, gc, group_tab(G, Ef), group_tab(G, Ec), group_tab(G, Ec32));
   return hipGetLastError();
 }
 hipError_t launch_diag_group(hipStream_t s, int G, Grid g, const DiagArgs *a) {

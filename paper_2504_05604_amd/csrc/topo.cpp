@@ -908,11 +908,14 @@ static topo_status autotune_timed(topo_ctx *ctx) {
 static topo_status prepare_operator(topo_ctx *ctx, const double *d_xphys, bool refresh_coarse = true) {
   hipStream_t s = ctx->stream;
   const topo_problem &P = ctx->prob;
-  TOPO_HIP(launch_simp_modulus(s, ctx->nel, d_xphys, P.E0, P.Emin, P.penal, 1.0, ctx->lv[0].E));
+  // in mixed precision every kernel also writes the single-precision copy
+  const bool m = ctx->mixed;
+  TOPO_HIP(launch_simp_modulus(s, ctx->nel, d_xphys, P.E0, P.Emin, P.penal, 1.0, ctx->lv[0].E,
+                               m ? ctx->lv[0].f32.E : nullptr));
   for (size_t l = 0; l < ctx->lv.size(); ++l) {
     Level &L = ctx->lv[l];
-    if (l > 0) TOPO_HIP(launch_coarsen_moduli(s, ctx->lv[l - 1].g, L.g, ctx->lv[l - 1].E, L.E));
-    TOPO_HIP(launch_diag(s, L.g, L.E, ctx->kap, L.fixed, L.dinv));
+    if (l > 0) TOPO_HIP(launch_coarsen_moduli(s, ctx->lv[l - 1].g, L.g, ctx->lv[l - 1].E, L.E, m ? L.f32.E : nullptr));
+    TOPO_HIP(launch_diag(s, L.g, L.E, ctx->kap, L.fixed, L.dinv, m ? L.f32.dinv : nullptr));
   }
   if (ctx->lv.size() > 1 && refresh_coarse) {
     const Level &C = ctx->lv.back();
@@ -921,12 +924,6 @@ static topo_status prepare_operator(topo_ctx *ctx, const double *d_xphys, bool r
   }
   // a direct call leaves a fresh inverse; the SIMP loop counts from here
   ctx->coarse_due = refresh_coarse ? ctx->opts.coarse_refresh : ctx->coarse_due;
-  if (ctx->mixed) {
-    for (Level &L : ctx->lv) {
-      TOPO_HIP(launch_convert(s, L.g.nel(), L.E, L.f32.E));
-      TOPO_HIP(launch_convert(s, L.g.ndof(), L.dinv, L.f32.dinv));
-    }
-  }
   // network input channel 0 (node density) is fixed for the whole solve
   if (ctx->nn) TOPO_HIP(launch_node_density(s, ctx->g, d_xphys, ctx->nnw.x));
   return TOPO_OK;
@@ -2021,19 +2018,22 @@ static topo_status group_prepare_operator(const Group &G, bool refresh) {
   std::vector<ModulusArgs> ma(n);
   for (int i = 0; i < n; ++i) {
     const topo_problem &P = G.c[i]->prob;
-    ma[i] = ModulusArgs{G.c[i]->xphys, P.E0, P.Emin, P.penal, G.c[i]->lv[0].E};
+    ma[i] = ModulusArgs{G.c[i]->xphys, P.E0, P.Emin, P.penal, G.c[i]->lv[0].E,
+                        c0->mixed ? G.c[i]->lv[0].f32.E : nullptr};
   }
   TOPO_HIP(launch_simp_modulus_group(s, n, c0->nel, ma.data()));
   for (size_t l = 0; l < c0->lv.size(); ++l) {
     std::vector<const double *> ef(n);
     std::vector<double *> ec(n);
+    std::vector<float *> ec32(n);
     std::vector<DiagArgs> da(n);
     for (int i = 0; i < n; ++i) {
       Level &L = G.c[i]->lv[l];
-      if (l > 0) ef[i] = G.c[i]->lv[l - 1].E, ec[i] = L.E;
-      da[i] = DiagArgs{L.E, G.c[i]->kap, L.fixed, L.dinv};
+      if (l > 0) ef[i] = G.c[i]->lv[l - 1].E, ec[i] = L.E, ec32[i] = c0->mixed ? L.f32.E : nullptr;
+      da[i] = DiagArgs{L.E, G.c[i]->kap, L.fixed, L.dinv, c0->mixed ? L.f32.dinv : nullptr};
     }
-    if (l > 0) TOPO_HIP(launch_coarsen_moduli_group(s, n, c0->lv[l - 1].g, c0->lv[l].g, ef.data(), ec.data()));
+    if (l > 0)
+      TOPO_HIP(launch_coarsen_moduli_group(s, n, c0->lv[l - 1].g, c0->lv[l].g, ef.data(), ec.data(), ec32.data()));
     TOPO_HIP(launch_diag_group(s, n, c0->lv[l].g, da.data()));
   }
   if (c0->lv.size() > 1 && refresh) {
@@ -2049,18 +2049,6 @@ static topo_status group_prepare_operator(const Group &G, bool refresh) {
     TOPO_HIP(launch_dense_invert_group(s, n, c0->ncoarse, A.data(), W.data()));
   }
   for (topo_ctx *c : G.c) c->coarse_due = refresh ? c->opts.coarse_refresh : c->coarse_due;
-  if (c0->mixed) {
-    for (size_t l = 0; l < c0->lv.size(); ++l) {
-      std::vector<ConvertArgs> ce(n), cd(n);
-      for (int i = 0; i < n; ++i) {
-        Level &L = G.c[i]->lv[l];
-        ce[i] = ConvertArgs{L.E, L.f32.E, nullptr};
-        cd[i] = ConvertArgs{L.dinv, L.f32.dinv, nullptr};
-      }
-      TOPO_HIP(launch_convert_group(s, n, c0->lv[l].g.nel(), ce.data()));
-      TOPO_HIP(launch_convert_group(s, n, c0->lv[l].g.ndof(), cd.data()));
-    }
-  }
   return TOPO_OK;
 }
 
