@@ -397,6 +397,22 @@ struct MatvecArgs {
 };
 template <typename T>
 hipError_t launch_dense_matvec_group(hipStream_t s, int G, int n, const MatvecArgs<T> *a);
+// the restriction of r_f onto the coarsest level and x = Ainv of it in one
+// launch (the coarsest right-hand side is not stored); n = gc.ndof()
+template <typename T>
+hipError_t launch_restrict_solve(hipStream_t s, Grid gf, Grid gc, const T *rf, const uint8_t *fixc, int n,
+                                 const double *A, T *y, const int *skip);
+template <typename T>
+struct RestrictSolveArgs {
+  const T *rf;
+  const uint8_t *fixed;  // of the coarsest level
+  const double *A;
+  T *y;
+  const int *skip;
+};
+template <typename T>
+hipError_t launch_restrict_solve_group(hipStream_t s, int G, Grid gf, Grid gc, int n,
+                                       const RestrictSolveArgs<T> *a);
 
 hipError_t launch_zero_fixed_group(hipStream_t s, int G, int64_t nnodes, const uint8_t *const *fixed,
                                    double *const *v);

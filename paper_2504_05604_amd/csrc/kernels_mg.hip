@@ -20,12 +20,8 @@ inline unsigned nblocks(int64_t n) { return (unsigned)((n + kBs - 1) / kBs); }
 // Branch-free: a neighbour outside the fine grid is read at a clamped (valid)
 // index with weight 0, which adds an exact zero.
 template <typename T>
-__device__ __forceinline__ void restrict_body(const Grid &gf, const Grid &gc, const T *__restrict__ rf,
-                                              const uint8_t *__restrict__ fixc, T *__restrict__ rc,
-                                              const int *skip) {
-  if (skip && *skip) return;
-  const int m = (int)(blockIdx.x * blockDim.x + threadIdx.x);
-  if (m >= (int)gc.nnodes()) return;
+__device__ __forceinline__ void restrict_node(const Grid &gf, const Grid &gc, const T *__restrict__ rf,
+                                              const uint8_t *__restrict__ fixc, int m, T (&out)[3]) {
   const int NXc = gc.NX(), NYc = gc.NY(), NXf = gf.NX(), NYf = gf.NY();
   const int I = m % NXc, J = (m / NXc) % NYc, K = m / (NXc * NYc);
   int xi[3], yj[3], zk[3];
@@ -57,9 +53,22 @@ __device__ __forceinline__ void restrict_body(const Grid &gf, const Grid &gc, co
       }
     }
   const uint8_t f = fixc[m];
-  rc[3 * (int64_t)m + 0] = (f & 1) ? T(0) : s0;
-  rc[3 * (int64_t)m + 1] = (f & 2) ? T(0) : s1;
-  rc[3 * (int64_t)m + 2] = (f & 4) ? T(0) : s2;
+  out[0] = (f & 1) ? T(0) : s0;
+  out[1] = (f & 2) ? T(0) : s1;
+  out[2] = (f & 4) ? T(0) : s2;
+}
+template <typename T>
+__device__ __forceinline__ void restrict_body(const Grid &gf, const Grid &gc, const T *__restrict__ rf,
+                                              const uint8_t *__restrict__ fixc, T *__restrict__ rc,
+                                              const int *skip) {
+  if (skip && *skip) return;
+  const int m = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+  if (m >= (int)gc.nnodes()) return;
+  T o[3];
+  restrict_node<T>(gf, gc, rf, fixc, m, o);
+  rc[3 * (int64_t)m + 0] = o[0];
+  rc[3 * (int64_t)m + 1] = o[1];
+  rc[3 * (int64_t)m + 2] = o[2];
 }
 
 template <typename T>
@@ -635,8 +644,7 @@ hipError_t launch_dense_invert_group(hipStream_t s, int G, int n, double *const 
 // the result rounded once): the coarse operator is ill-conditioned, and an FP32
 // copy of its inverse loses percents of accuracy at a thousand dofs
 template <typename T>
-__device__ __forceinline__ void dense_matvec_body(int n, const double *A, const T *x, T *y, const int *skip) {
-  if (skip && *skip) return;
+__device__ __forceinline__ void dense_matvec_rows(int n, const double *A, const T *x, T *y) {
   const int lane = threadIdx.x & 63;
   const int row = blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64;
   if (row >= n) return;
@@ -655,6 +663,47 @@ __device__ __forceinline__ void dense_matvec_body(int n, const double *A, const 
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) t += __shfl_down(t, off, 64);
   if (lane == 0) y[row] = (T)t;
+}
+template <typename T>
+__device__ __forceinline__ void dense_matvec_body(int n, const double *A, const T *x, T *y, const int *skip) {
+  if (skip && *skip) return;
+  dense_matvec_rows<T>(n, A, x, y);
+}
+
+// The coarsest solve fused with the restriction into it: every block forms the
+// whole coarsest right-hand side R r_f in LDS (restrict_node: the values of the
+// transfer kernel) and then its rows of x = Ainv b (the sums of the mat-vec),
+// one launch instead of two; the coarsest b itself is not stored (nothing
+// else reads it).  n = 3 nnodes(gc) <= kMaxDense.
+template <typename T>
+__device__ __forceinline__ void restrict_solve_body(const Grid &gf, const Grid &gc, const T *rf,
+                                                    const uint8_t *fixc, int n, const double *A, T *y,
+                                                    const int *skip) {
+  if (skip && *skip) return;
+  __shared__ T bs[kMaxDense];
+  const int nn = (int)gc.nnodes();
+  for (int m = threadIdx.x; m < nn; m += blockDim.x) {
+    T o[3];
+    restrict_node<T>(gf, gc, rf, fixc, m, o);
+    bs[3 * m + 0] = o[0];
+    bs[3 * m + 1] = o[1];
+    bs[3 * m + 2] = o[2];
+  }
+  __syncthreads();
+  dense_matvec_rows<T>(n, A, bs, y);
+}
+constexpr int kRsThreads = 512;  // the restriction phase covers 512 coarse nodes in one round
+template <typename T>
+__global__ __launch_bounds__(kRsThreads) void restrict_solve_kernel(Grid gf, Grid gc, const T *rf,
+                                                                    const uint8_t *fixc, int n, const double *A,
+                                                                    T *y, const int *skip) {
+  restrict_solve_body<T>(gf, gc, rf, fixc, n, A, y, skip);
+}
+template <typename T>
+__global__ __launch_bounds__(kRsThreads) void restrict_solve_group_kernel(Grid gf, Grid gc, int n,
+                                                                          GroupTab<RestrictSolveArgs<T>> t) {
+  const RestrictSolveArgs<T> &a = t.v[blockIdx.z];
+  restrict_solve_body<T>(gf, gc, a.rf, a.fixed, n, a.A, a.y, a.skip);
 }
 
 template <typename T>
@@ -679,6 +728,36 @@ hipError_t launch_dense_matvec(hipStream_t s, int n, const double *A, const floa
   dense_matvec_kernel<float><<<(unsigned)((n + rows_per_block - 1) / rows_per_block), kBs, 0, s>>>(n, A, x, y, skip);
   return hipGetLastError();
 }
+
+template <typename T>
+hipError_t launch_restrict_solve(hipStream_t s, Grid gf, Grid gc, const T *rf, const uint8_t *fixc, int n,
+                                 const double *A, T *y, const int *skip) {
+  if (n != gc.ndof() || n > kMaxDense || gf.nnodes() >= INT32_MAX) return hipErrorInvalidValue;
+  const int rows_per_block = kRsThreads / 64;
+  restrict_solve_kernel<T><<<(unsigned)((n + rows_per_block - 1) / rows_per_block), kRsThreads, 0, s>>>(
+      gf, gc, rf, fixc, n, A, y, skip);
+  return hipGetLastError();
+}
+template hipError_t launch_restrict_solve<double>(hipStream_t, Grid, Grid, const double *, const uint8_t *, int,
+                                                  const double *, double *, const int *);
+template hipError_t launch_restrict_solve<float>(hipStream_t, Grid, Grid, const float *, const uint8_t *, int,
+                                                 const double *, float *, const int *);
+template <typename T>
+hipError_t launch_restrict_solve_group(hipStream_t s, int G, Grid gf, Grid gc, int n,
+                                       const RestrictSolveArgs<T> *a) {
+  if (G < 1 || G > kMaxGroup || n != gc.ndof() || n > kMaxDense || gf.nnodes() >= INT32_MAX)
+    return hipErrorInvalidValue;
+  GroupTab<RestrictSolveArgs<T>> t{};
+  for (int i = 0; i < G; ++i) t.v[i] = a[i];
+  const int rows_per_block = kRsThreads / 64;
+  restrict_solve_group_kernel<T><<<dim3((unsigned)((n + rows_per_block - 1) / rows_per_block), 1, G), kRsThreads, 0,
+                                   s>>>(gf, gc, n, t);
+  return hipGetLastError();
+}
+template hipError_t launch_restrict_solve_group<double>(hipStream_t, int, Grid, Grid, int,
+                                                        const RestrictSolveArgs<double> *);
+template hipError_t launch_restrict_solve_group<float>(hipStream_t, int, Grid, Grid, int,
+                                                       const RestrictSolveArgs<float> *);
 
 // grouped launchers: one launch for G problems of the same grids
 template <typename T>

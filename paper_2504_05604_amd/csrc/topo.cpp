@@ -1138,9 +1138,14 @@ static topo_status vcycle(topo_ctx *ctx, size_t l, const int *skip, const Fin *d
   if (st != TOPO_OK) return st;
   Level &C = ctx->lv[l + 1];
   const LevelBufs<T> BC = bufs<T>(C);
-  TOPO_HIP(launch_restrict(s, L.g, C.g, B.res, C.fixed, BC.b, skip));
-  st = vcycle<T>(ctx, l + 1, skip, nullptr);
-  if (st != TOPO_OK) return st;
+  if (l + 2 == ctx->lv.size()) {
+    // the next level is the coarsest: restriction and dense solve in one launch
+    TOPO_HIP(launch_restrict_solve<T>(s, L.g, C.g, B.res, C.fixed, ctx->ncoarse, ctx->Ainv, BC.x, skip));
+  } else {
+    TOPO_HIP(launch_restrict(s, L.g, C.g, B.res, C.fixed, BC.b, skip));
+    st = vcycle<T>(ctx, l + 1, skip, nullptr);
+    if (st != TOPO_OK) return st;
+  }
   TOPO_HIP(launch_prolong_add(s, L.g, C.g, BC.x, L.fixed, B.x, skip));
   return post_smooth<T>(ctx, L, skip, dot_fin ? B.b : nullptr, dot_fin ? *dot_fin : fin_sum(nullptr), flex);
 }
@@ -1574,13 +1579,23 @@ static topo_status group_vcycle(const Group &G, size_t l) {
   topo_status st = group_pre_smooth<T>(G, l);
   if (st != TOPO_OK) return st;
   std::vector<TransferArgs<T>> t(n);
-  for (int i = 0; i < n; ++i) {
-    Level &L = G.c[i]->lv[l], &C = G.c[i]->lv[l + 1];
-    t[i] = TransferArgs<T>{bufs<T>(L).res, C.fixed, bufs<T>(C).b, &G.c[i]->sc->cg_done};
+  if (l + 2 == c0->lv.size()) {
+    // the next level is the coarsest: restriction and dense solve in one launch
+    std::vector<RestrictSolveArgs<T>> r(n);
+    for (int i = 0; i < n; ++i) {
+      Level &L = G.c[i]->lv[l], &C = G.c[i]->lv[l + 1];
+      r[i] = RestrictSolveArgs<T>{bufs<T>(L).res, C.fixed, G.c[i]->Ainv, bufs<T>(C).x, &G.c[i]->sc->cg_done};
+    }
+    TOPO_HIP(launch_restrict_solve_group<T>(G.s, n, c0->lv[l].g, c0->lv[l + 1].g, c0->ncoarse, r.data()));
+  } else {
+    for (int i = 0; i < n; ++i) {
+      Level &L = G.c[i]->lv[l], &C = G.c[i]->lv[l + 1];
+      t[i] = TransferArgs<T>{bufs<T>(L).res, C.fixed, bufs<T>(C).b, &G.c[i]->sc->cg_done};
+    }
+    TOPO_HIP(launch_restrict_group<T>(G.s, n, c0->lv[l].g, c0->lv[l + 1].g, t.data()));
+    st = group_vcycle<T>(G, l + 1);
+    if (st != TOPO_OK) return st;
   }
-  TOPO_HIP(launch_restrict_group<T>(G.s, n, c0->lv[l].g, c0->lv[l + 1].g, t.data()));
-  st = group_vcycle<T>(G, l + 1);
-  if (st != TOPO_OK) return st;
   for (int i = 0; i < n; ++i) {
     Level &L = G.c[i]->lv[l], &C = G.c[i]->lv[l + 1];
     t[i] = TransferArgs<T>{bufs<T>(C).x, L.fixed, bufs<T>(L).x, &G.c[i]->sc->cg_done};
