@@ -285,13 +285,15 @@ def test_filter_deep_tiles_match_oracle(rmin):
             assert np.all(np.abs(got - ref) <= tol), (op, np.max(np.abs(got - ref) - tol))
 
 
+@pytest.mark.parametrize("tol,lam_tol", [(1e-12, 1e-10), (1e-15, 1e-13)])
 @pytest.mark.parametrize("vol_mode", ["design", "all"])
 @pytest.mark.parametrize("seed", [0, 1, 2])
 @pytest.mark.parametrize("move", [0.2, 0.05])
-def test_oc_update_matches_exact_multiplier(seed, move, vol_mode):
+def test_oc_update_matches_exact_multiplier(seed, move, vol_mode, tol, lam_tol):
     """The multiplier and design against the oracle's exact breakpoint root, with
     the volume target over design elements or over all elements (fixed solids
-    counted at 1)."""
+    counted at 1); a tighter oc_tol launches more multisection passes and
+    brings the multiplier closer to the root."""
     p = ragged_problem(20 + seed, (23, 11, 9), rmin=2.0)
     p.move = move
     p.vol_mode = vol_mode
@@ -309,11 +311,11 @@ def test_oc_update_matches_exact_multiplier(seed, move, vol_mode):
         assert target == p.volfrac * p.nel - (p.mask == 2).sum()
     xref, lam_ref = oc.oc_exact(x, dc, w, w, target, p.move, p.eta, design)
     assert abs(w @ xref - target) <= 1e-9 * target
-    with topo.Context(p) as ctx:
+    with topo.Context(p, topo.default_opts(oc_tol=tol)) as ctx:
         xn = torch.empty(p.nel, dtype=torch.float64, device="cuda")
         chg, lam = ctx.oc_update(dev(x), dev(dc), dev(w), xn)
         got = host(xn)
-    assert abs(lam - lam_ref) <= 1e-10 * lam_ref
+    assert abs(lam - lam_ref) <= lam_tol * lam_ref
     np.testing.assert_allclose(got, xref, atol=1e-10)
     assert np.array_equal(got[~design], x[~design])
     assert abs(chg - np.abs(xref - x).max()) <= 1e-10
