@@ -139,6 +139,81 @@ __device__ __forceinline__ void prolong_add_body(const Grid &gf, const Grid &gc,
   xn[2] = (f & 4) ? x2 : fma(w, s2, x2);
 }
 
+// The same prolongation per coarse cell (I, J, K), for large fine grids: the
+// up to 8 fine nodes (2I + a, 2J + b, 2K + c) take the sums of prolong_add_body
+// (the same 8 terms in the same order, the same weights: bit for bit) from the
+// cell's 8 coarse values, read once instead of once per fine node.
+constexpr int64_t kProlongCellNodes = 500000;  // fine nodes from which the cell form is used
+template <typename T>
+__device__ __forceinline__ void prolong_cell_body(const Grid &gf, const Grid &gc, const T *__restrict__ ec,
+                                                  const uint8_t *__restrict__ fixf, T *__restrict__ xf,
+                                                  const int *skip) {
+  if (skip && *skip) return;
+  const int NXf = gf.NX(), NYf = gf.NY(), NZf = gf.NZ(), NXc = gc.NX(), NYc = gc.NY();
+  const int CX = (NXf + 1) / 2, CY = (NYf + 1) / 2, CZ = (NZf + 1) / 2;
+  const int t = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+  if (t >= CX * CY * CZ) return;
+  const int I = t % CX, J = (t / CX) % CY, K = t / (CX * CY);
+  const int I1 = min(I + 1, gc.nx), J1 = min(J + 1, gc.ny), K1 = min(K + 1, gc.nz);
+  T v[2][2][2][3];
+#pragma unroll
+  for (int c = 0; c < 2; ++c)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int a = 0; a < 2; ++a) {
+        const T *__restrict__ p = ec + 3 * ((int64_t)((c ? K1 : K) * NYc + (b ? J1 : J)) * NXc + (a ? I1 : I));
+        v[c][b][a][0] = p[0];
+        v[c][b][a][1] = p[1];
+        v[c][b][a][2] = p[2];
+      }
+#pragma unroll
+  for (int fk = 0; fk < 2; ++fk)
+#pragma unroll
+    for (int fj = 0; fj < 2; ++fj)
+#pragma unroll
+      for (int fi = 0; fi < 2; ++fi) {
+        const int i = 2 * I + fi, j = 2 * J + fj, k = 2 * K + fk;
+        if (i >= NXf || j >= NYf || k >= NZf) continue;
+        const T ia = fi ? T(1) : T(0), jb = fj ? T(1) : T(0), kc = fk ? T(1) : T(0);
+        const T w = (fi ? T(0.5) : T(1)) * (fj ? T(0.5) : T(1)) * (fk ? T(0.5) : T(1));
+        T s0 = 0, s1 = 0, s2 = 0;
+#pragma unroll
+        for (int c = 0; c < 2; ++c)
+#pragma unroll
+          for (int b = 0; b < 2; ++b) {
+            const T inc_cb = (c ? kc : T(1)) * (b ? jb : T(1));
+#pragma unroll
+            for (int a = 0; a < 2; ++a) {
+              const T inc = inc_cb * (a ? ia : T(1));
+              s0 = fma(inc, v[c][b][a][0], s0);
+              s1 = fma(inc, v[c][b][a][1], s1);
+              s2 = fma(inc, v[c][b][a][2], s2);
+            }
+          }
+        const int64_t n = i + (int64_t)NXf * (j + (int64_t)NYf * k);
+        const uint8_t f = fixf[n];
+        T *__restrict__ xn = xf + 3 * n;
+        const T x0 = xn[0], x1 = xn[1], x2 = xn[2];
+        xn[0] = (f & 1) ? x0 : fma(w, s0, x0);
+        xn[1] = (f & 2) ? x1 : fma(w, s1, x1);
+        xn[2] = (f & 4) ? x2 : fma(w, s2, x2);
+      }
+}
+template <typename T>
+__global__ void prolong_cell_kernel(Grid gf, Grid gc, const T *__restrict__ ec, const uint8_t *__restrict__ fixf,
+                                    T *__restrict__ xf, const int *skip) {
+  prolong_cell_body<T>(gf, gc, ec, fixf, xf, skip);
+}
+template <typename T>
+__global__ void prolong_cell_group_kernel(Grid gf, Grid gc, GroupTab<TransferArgs<T>> t) {
+  const TransferArgs<T> &a = t.v[blockIdx.z];
+  prolong_cell_body<T>(gf, gc, a.in, a.fixed, a.out, a.skip);
+}
+inline int64_t prolong_cells(const Grid &gf) {
+  return (int64_t)((gf.NX() + 1) / 2) * ((gf.NY() + 1) / 2) * ((gf.NZ() + 1) / 2);
+}
+
 template <typename T>
 __global__ void prolong_add_kernel(Grid gf, Grid gc, const T *__restrict__ ec, const uint8_t *__restrict__ fixf,
                                    T *__restrict__ xf, const int *skip) {
@@ -153,13 +228,19 @@ __global__ void prolong_add_group_kernel(Grid gf, Grid gc, GroupTab<TransferArgs
 hipError_t launch_prolong_add(hipStream_t s, Grid gf, Grid gc, const double *ec,
                               const uint8_t *fixf, double *xf, const int *skip) {
   if (gf.nnodes() >= INT32_MAX) return hipErrorInvalidValue;
-  prolong_add_kernel<double><<<nblocks(gf.nnodes()), kBs, 0, s>>>(gf, gc, ec, fixf, xf, skip);
+  if (gf.nnodes() >= kProlongCellNodes)
+    prolong_cell_kernel<double><<<nblocks(prolong_cells(gf)), kBs, 0, s>>>(gf, gc, ec, fixf, xf, skip);
+  else
+    prolong_add_kernel<double><<<nblocks(gf.nnodes()), kBs, 0, s>>>(gf, gc, ec, fixf, xf, skip);
   return hipGetLastError();
 }
 hipError_t launch_prolong_add(hipStream_t s, Grid gf, Grid gc, const float *ec,
                               const uint8_t *fixf, float *xf, const int *skip) {
   if (gf.nnodes() >= INT32_MAX) return hipErrorInvalidValue;
-  prolong_add_kernel<float><<<nblocks(gf.nnodes()), kBs, 0, s>>>(gf, gc, ec, fixf, xf, skip);
+  if (gf.nnodes() >= kProlongCellNodes)
+    prolong_cell_kernel<float><<<nblocks(prolong_cells(gf)), kBs, 0, s>>>(gf, gc, ec, fixf, xf, skip);
+  else
+    prolong_add_kernel<float><<<nblocks(gf.nnodes()), kBs, 0, s>>>(gf, gc, ec, fixf, xf, skip);
   return hipGetLastError();
 }
 
@@ -773,7 +854,10 @@ hipError_t launch_prolong_add_group(hipStream_t s, int G, Grid gf, Grid gc, cons
   if (G < 1 || G > kMaxGroup || gf.nnodes() >= INT32_MAX) return hipErrorInvalidValue;
   GroupTab<TransferArgs<T>> t{};
   for (int i = 0; i < G; ++i) t.v[i] = a[i];
-  prolong_add_group_kernel<T><<<dim3(nblocks(gf.nnodes()), 1, G), kBs, 0, s>>>(gf, gc, t);
+  if (gf.nnodes() >= kProlongCellNodes)
+    prolong_cell_group_kernel<T><<<dim3(nblocks(prolong_cells(gf)), 1, G), kBs, 0, s>>>(gf, gc, t);
+  else
+    prolong_add_group_kernel<T><<<dim3(nblocks(gf.nnodes()), 1, G), kBs, 0, s>>>(gf, gc, t);
   return hipGetLastError();
 }
 template <typename T>

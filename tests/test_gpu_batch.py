@@ -83,6 +83,23 @@ def test_grouped_launches_equal_separate_streams(precision):
         assert [s["volume"] for s in res[0][1][i]] == [s["volume"] for s in res[1][1][i]], i
 
 
+def test_grouped_launches_equal_separate_streams_on_a_large_grid():
+    """Two problems of 101x71x69 elements (large enough for the per-cell
+    prolongation on the finest level): grouped launches end bit for bit where
+    separate streams do."""
+    ps = [synth.cantilever(101, 71, 69, volfrac=v, rmin=1.5, n_iter=2) for v in (0.3, 0.2)]
+    res = {}
+    for grouped in (0, 1):
+        with topo.Batch(ps, topo.default_opts(precision=topo.PREC_FP32, group_launch=grouped), n_threads=2) as b:
+            xs = [torch.from_numpy(p.initial_design()).to("cuda") for p in ps]
+            st = b.iterate(xs, 2)
+            torch.cuda.synchronize()
+            res[grouped] = ([x.cpu().numpy() for x in xs], st)
+    for i in range(len(ps)):
+        assert np.array_equal(res[0][0][i], res[1][0][i]), i
+        assert [s["pcg_iters"] for s in res[0][1][i]] == [s["pcg_iters"] for s in res[1][1][i]], i
+
+
 @pytest.mark.parametrize("variant", ["extrapolated-sens", "zero-keep-inverse", "last-mixed-reach"])
 def test_grouped_iterations_cover_every_warm_start_and_filter(variant):
     """Grouped SIMP phases (filter, operator set-up and coarse inverse, warm

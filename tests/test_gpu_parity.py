@@ -168,6 +168,32 @@ def test_preconditioner_with_large_coarsest_level_matches_oracle(dims, degrees):
     assert np.abs(got - ref).max() <= 1e-10 * np.abs(ref).max()
 
 
+@functools.lru_cache(maxsize=1)
+def large_vcycle_case():
+    """102x72x70 nodes (above the size from which the finest level prolongs per
+    coarse cell; odd element counts leave ragged cells on every axis)."""
+    p = synth.cantilever(101, 71, 69, volfrac=0.3, rmin=1.5, n_iter=1)
+    x = synth.random_density(5, p.nel, 0.0, 1.0)
+    E = fem.simp_modulus(x, p.E0, p.Emin, p.penal)
+    r = synth.random_vector(6, p.ndof)
+    r[fixed_mask(p)] = 0.0
+    V = mg.VCycle(p, E, KE, degree=1, coarse_degree=4, max_coarse_dof=1500)
+    return p, x, r, V.apply(r), len(V.levels)
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-11), ("fp32", 1e-4)])
+def test_preconditioner_on_a_large_ragged_grid_matches_oracle(precision, tol):
+    p, x, r, ref, nlev = large_vcycle_case()
+    prec = topo.PREC_FP64 if precision == "fp64" else topo.PREC_FP32
+    with topo.Context(p, topo.default_opts(mg_max_coarse_dof=1500, cheb_degree=1, cheb_degree_coarse=4,
+                                           precision=prec)) as ctx:
+        assert ctx.mg_levels == nlev
+        z = torch.empty(p.ndof, dtype=torch.float64, device="cuda")
+        ctx.apply_precond(dev(x), dev(r), z)
+        got = host(z)
+    assert np.abs(got - ref).max() <= tol * np.abs(ref).max()
+
+
 @pytest.mark.parametrize("dims,cap,ncoarse", [((12, 4, 4), 200, 189), ((24, 12, 12), 2000, 1911)])
 def test_coarse_inverse_panel_edge_sizes(dims, cap, ncoarse):
     """Coarsest levels just above the one-workgroup inverse (189 dofs: panels of
