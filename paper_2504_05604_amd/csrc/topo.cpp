@@ -211,6 +211,7 @@ struct topo_ctx {
   hipStream_t cap_stream = nullptr;  // private stream for graph capture
   hipGraph_t cg_graph[3] = {};
   hipGraphExec_t cg_exec[3] = {};    // chunk of CG iterations, per preconditioner kind
+  int cg_prev_iters[3] = {};          // iterations of the last solve, per preconditioner kind
   // learned preconditioner
   int shape_cg = -1;                 // K.u launch shape of the CG product (-1: by grid size)
   size_t tail_start = 0;             // first level of the one-workgroup V-cycle tail (0: none)
@@ -1261,6 +1262,31 @@ static topo_status cg_chunk(topo_ctx *ctx, int kind) {
   return TOPO_OK;
 }
 
+// How many chunks to enqueue before the next host check of the convergence
+// flag.  Each check is a round trip (copy, synchronize, next launch) that leaves
+// the device idle; chunks enqueued past convergence only cost their launches,
+// since every kernel in them returns at once.  From the mean rate at which r.r
+// has fallen so far, the chunks expected to stay short of the tolerance
+// (three quarters of the estimate) go in together.  Before the first check the
+// previous solve with this preconditioner gives the estimate (three fifths of
+// its iterations); without one, or when the residual has not fallen, one chunk.
+// Never more chunks than the iteration cap leaves room for.
+static int chunks_ahead(const topo_ctx *ctx, int kind, int max_iters, double rr0, double goal) {
+  const int chunk = std::max(1, ctx->opts.check_every);
+  const int it = ctx->h_sc->cg_iters;
+  const double rr = ctx->h_sc->rr;
+  const int room = std::max(1, (max_iters - it + chunk - 1) / chunk);
+  int n = 1;
+  if (it == 0) {
+    n = 3 * ctx->cg_prev_iters[kind] / (5 * chunk);
+  } else if (rr0 > 0.0 && rr > 0.0 && rr < rr0 && goal < rr && std::isfinite(rr0)) {
+    const double per_iter = std::log(rr / rr0) / it;     // < 0
+    const double rest = std::log(goal / rr) / per_iter;  // iterations still needed at that rate
+    n = (int)(0.75 * rest / chunk);
+  }
+  return std::max(1, std::min(std::min(n, room), 64));
+}
+
 // One run of (flexible) PCG with preconditioner `kind` and iteration cap
 // max_iters, from ctx->u; the scalars end in ctx->h_sc.
 static topo_status pcg_run(topo_ctx *ctx, int kind, int max_iters) {
@@ -1288,12 +1314,17 @@ static topo_status pcg_run(topo_ctx *ctx, int kind, int max_iters) {
   TOPO_HIP(update_p(ctx, kind, 1, &ctx->sc->cg_done));
   st = read_scalars(ctx);
   if (st != TOPO_OK) return st;
+  const double rr0 = ctx->h_sc->rr, goal = rtol * rtol * ctx->h_sc->ff;
   while (!ctx->h_sc->cg_done) {
-    st = cg_chunk(ctx, kind);
-    if (st != TOPO_OK) return st;
+    const int n = chunks_ahead(ctx, kind, max_iters, rr0, goal);
+    for (int c = 0; c < n; ++c) {
+      st = cg_chunk(ctx, kind);
+      if (st != TOPO_OK) return st;
+    }
     st = read_scalars(ctx);
     if (st != TOPO_OK) return st;
   }
+  ctx->cg_prev_iters[kind] = ctx->h_sc->cg_iters;
   return TOPO_OK;
 }
 

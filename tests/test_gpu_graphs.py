@@ -58,3 +58,28 @@ def test_solve_reports_nonconvergence():
         assert not st["converged"] and st["iters"] == 2
         with pytest.raises(topo.NotConverged):
             ctx.solve(x, torch.zeros_like(u))
+
+
+@pytest.mark.parametrize("graphs", [0, 1])
+def test_chunks_enqueued_past_convergence_change_nothing(graphs):
+    """A long solve makes the next one enqueue several chunks before its first
+    host check; a solve that converges well inside them (from a close initial
+    guess) ends where a fresh context's does, bit for bit, with the same count."""
+    p = synth.config_small()
+    x = torch.from_numpy(synth.random_density(3, p.nel, 0.05, 1.0)).to("cuda")
+    opts = topo.default_opts(rtol=1e-12, check_every=2, use_graphs=graphs)
+    with topo.Context(p, opts) as ctx:
+        u = torch.zeros(p.ndof, dtype=torch.float64, device="cuda")
+        long = ctx.solve(x, u)
+        guess = u * (1.0 + 1e-9 * torch.from_numpy(synth.random_vector(4, p.ndof)).to("cuda"))
+        u2 = guess.clone()
+        short = ctx.solve(x, u2)
+    print("iterations", long["iters"], short["iters"])
+    # the first check of the second solve comes after 3/5 of the first one's
+    # iterations, past its convergence
+    assert 3 * long["iters"] // 5 >= short["iters"] + 2 >= 3
+    with topo.Context(p, opts) as fresh:
+        u3 = guess.clone()
+        ref = fresh.solve(x, u3)
+    assert short["iters"] == ref["iters"]
+    assert torch.equal(u2, u3)
