@@ -1759,21 +1759,36 @@ topo_status group_pcg(Group &G, hipGraph_t *graph_out, hipGraphExec_t *exec, hip
   }
   st = group_read_scalars(G);
   if (st != TOPO_OK) return st;
+  std::vector<double> rr0(n), goal(n);
+  for (int i = 0; i < n; ++i) {
+    const topo_ctx *c = G.c[i];
+    rr0[i] = c->h_sc->rr;
+    goal[i] = c->opts.rtol * c->opts.rtol * c->h_sc->ff;
+  }
   for (;;) {
-    bool all = true;
-    for (topo_ctx *c : G.c) all = all && c->h_sc->cg_done;
-    if (all) break;
-    if (graphs) {
-      TOPO_HIP(hipGraphLaunch(*exec, G.s));
-    } else {
-      for (int k = 0; k < chunk; ++k) {
-        st = group_cg_body(G);
-        if (st != TOPO_OK) return st;
+    // chunks before the next check: the fewest that any unconverged member asks for
+    int ahead = 0;
+    for (int i = 0; i < n; ++i) {
+      const topo_ctx *c = G.c[i];
+      if (c->h_sc->cg_done) continue;
+      const int want = chunks_ahead(c, TOPO_PRECOND_MG, c->opts.max_iters, rr0[i], goal[i]);
+      ahead = ahead ? std::min(ahead, want) : want;
+    }
+    if (!ahead) break;
+    for (int a = 0; a < ahead; ++a) {
+      if (graphs) {
+        TOPO_HIP(hipGraphLaunch(*exec, G.s));
+      } else {
+        for (int k = 0; k < chunk; ++k) {
+          st = group_cg_body(G);
+          if (st != TOPO_OK) return st;
+        }
       }
     }
     st = group_read_scalars(G);
     if (st != TOPO_OK) return st;
   }
+  for (topo_ctx *c : G.c) c->cg_prev_iters[TOPO_PRECOND_MG] = c->h_sc->cg_iters;
   topo_status result = TOPO_OK;
   for (int i = 0; i < n; ++i) {
     topo_ctx *c = G.c[i];
