@@ -67,6 +67,7 @@ struct Scalars {
   int cg_max;             // iteration cap of the running solve
   int nn_fallback;        // learned preconditioner failed its safeguard test
   double rtol2;           // squared relative tolerance of the running solve
+  double rr_start;        // r.r when the running solve started
   double oc_lam[64];
 };
 

@@ -173,6 +173,7 @@ __device__ __forceinline__ void cg_start_body(Scalars *sc, double rtol2, int max
   sc->cg_max = max_iters;
   sc->nn_fallback = 0;
   sc->rz = 1.0;  // the first r.z finalize forms a beta that is never used: keep it finite
+  sc->rr_start = sc->rr;
   sc->cg_done = !(sc->rr > rtol2 * sc->ff) || max_iters <= 0;
 }
 __global__ void cg_start_kernel(Scalars *sc, double rtol2, int max_iters) { cg_start_body(sc, rtol2, max_iters); }

@@ -1266,15 +1266,16 @@ static topo_status cg_chunk(topo_ctx *ctx, int kind) {
 // flag.  Each check is a round trip (copy, synchronize, next launch) that leaves
 // the device idle; chunks enqueued past convergence only cost their launches,
 // since every kernel in them returns at once.  From the mean rate at which r.r
-// has fallen so far, the chunks expected to stay short of the tolerance
-// (three quarters of the estimate) go in together.  Before the first check the
-// previous solve with this preconditioner gives the estimate (three fifths of
-// its iterations); without one, or when the residual has not fallen, one chunk.
-// Never more chunks than the iteration cap leaves room for.
-static int chunks_ahead(const topo_ctx *ctx, int kind, int max_iters, double rr0, double goal) {
+// has fallen since the solve started, the chunks expected to stay short of the
+// tolerance (three quarters of the estimate) go in together; before any
+// iteration, three fifths of the previous solve's iterations with this
+// preconditioner; without either, one chunk.  Never more chunks than the
+// iteration cap leaves room for.
+static int chunks_ahead(const topo_ctx *ctx, int kind, int max_iters) {
   const int chunk = std::max(1, ctx->opts.check_every);
-  const int it = ctx->h_sc->cg_iters;
-  const double rr = ctx->h_sc->rr;
+  const Scalars &h = *ctx->h_sc;
+  const int it = h.cg_iters;
+  const double rr = h.rr, rr0 = h.rr_start, goal = h.rtol2 * h.ff;
   const int room = std::max(1, (max_iters - it + chunk - 1) / chunk);
   int n = 1;
   if (it == 0) {
@@ -1312,15 +1313,25 @@ static topo_status pcg_run(topo_ctx *ctx, int kind, int max_iters) {
   topo_status st = precondition(ctx, kind, &ctx->sc->cg_done);
   if (st != TOPO_OK) return st;
   TOPO_HIP(update_p(ctx, kind, 1, &ctx->sc->cg_done));
-  st = read_scalars(ctx);
-  if (st != TOPO_OK) return st;
-  const double rr0 = ctx->h_sc->rr, goal = rtol * rtol * ctx->h_sc->ff;
-  while (!ctx->h_sc->cg_done) {
-    const int n = chunks_ahead(ctx, kind, max_iters, rr0, goal);
-    for (int c = 0; c < n; ++c) {
+  // with the previous solve's count as a guide the first chunks go in at once
+  // (on an already converged start they return at once); otherwise the state
+  // is read first
+  const int chunk = std::max(1, ctx->opts.check_every);
+  int ahead = std::min(3 * ctx->cg_prev_iters[kind] / (5 * chunk), std::min(64, (max_iters + chunk - 1) / chunk));
+  if (ahead < 1) {
+    st = read_scalars(ctx);
+    if (st != TOPO_OK) return st;
+  }
+  for (;;) {
+    if (ahead < 1) {
+      if (ctx->h_sc->cg_done) break;
+      ahead = chunks_ahead(ctx, kind, max_iters);
+    }
+    for (int c = 0; c < ahead; ++c) {
       st = cg_chunk(ctx, kind);
       if (st != TOPO_OK) return st;
     }
+    ahead = 0;
     st = read_scalars(ctx);
     if (st != TOPO_OK) return st;
   }
@@ -1759,19 +1770,13 @@ topo_status group_pcg(Group &G, hipGraph_t *graph_out, hipGraphExec_t *exec, hip
   }
   st = group_read_scalars(G);
   if (st != TOPO_OK) return st;
-  std::vector<double> rr0(n), goal(n);
-  for (int i = 0; i < n; ++i) {
-    const topo_ctx *c = G.c[i];
-    rr0[i] = c->h_sc->rr;
-    goal[i] = c->opts.rtol * c->opts.rtol * c->h_sc->ff;
-  }
   for (;;) {
     // chunks before the next check: the fewest that any unconverged member asks for
     int ahead = 0;
     for (int i = 0; i < n; ++i) {
       const topo_ctx *c = G.c[i];
       if (c->h_sc->cg_done) continue;
-      const int want = chunks_ahead(c, TOPO_PRECOND_MG, c->opts.max_iters, rr0[i], goal[i]);
+      const int want = chunks_ahead(c, TOPO_PRECOND_MG, c->opts.max_iters);
       ahead = ahead ? std::min(ahead, want) : want;
     }
     if (!ahead) break;
