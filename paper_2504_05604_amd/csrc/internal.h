@@ -162,8 +162,10 @@ struct KuArgsT {
 using KuArgs = KuArgsT<double>;
 // fin receives the reduction of STORE_DOT / RESID / CHEB with dot_with
 // shape: launch shape index (-1 = chosen from the grid size)
+// defer_parts: no finalize launch; the block partials stay in red (value 0 of
+// each slot) for the next kernel to sum, and their count is stored here
 hipError_t launch_ku(hipStream_t s, KuEpi epi, const KuArgs &a, const Kappa &kap, const Reducer &red,
-                     const Fin &fin, int shape = -1);
+                     const Fin &fin, int shape = -1, int *defer_parts = nullptr);
 // single-precision operator (smoothing passes only: no reducing epilogues)
 hipError_t launch_ku(hipStream_t s, KuEpi epi, const KuArgsT<float> &a, const KappaT<float> &kap,
                      const Reducer &red, const Fin &fin, int shape = -1);
@@ -206,6 +208,13 @@ hipError_t launch_dot(hipStream_t s, int64_t n, const double *a, const double *b
 hipError_t launch_cg_update_xr(hipStream_t s, int64_t n, Scalars *sc, double *x, double *r,
                                const double *p, const double *q, const Reducer &red,
                                const Fin &fin, const int *skip = nullptr, float *r32 = nullptr);
+// The same with p.q still as npq block partials in red (left by launch_ku with
+// defer_parts): every block sums them in the finalize kernel's order (so alpha
+// is bit for bit the one of the unfused pair), block 0 stores p.q, and the r.r
+// partials go to value 1 of each slot, apart from the ones being read.
+hipError_t launch_cg_update_xr_pq(hipStream_t s, int64_t n, Scalars *sc, double *x, double *r,
+                                  const double *p, const double *q, const Reducer &red, int npq,
+                                  const Fin &fin, const int *skip = nullptr, float *r32 = nullptr);
 // cg_iters = 0; rtol2, cg_max stored; nn_fallback = 0; cg_done = (rr <= rtol2 ff)
 hipError_t launch_cg_start(hipStream_t s, Scalars *sc, double rtol2, int max_iters);
 // z = r * dinv; fin.out = r.z

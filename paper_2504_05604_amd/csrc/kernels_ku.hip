@@ -228,7 +228,7 @@ std::vector<int> ku_tunable_shapes(bool single, int family) {
 
 template <typename T>
 static hipError_t launch_ku_t(hipStream_t s, KuEpi epi, const KuArgsT<T> &a, const KappaT<T> &kap,
-                              const Reducer &red, const Fin &fin, int shape) {
+                              const Reducer &red, const Fin &fin, int shape, int *defer_parts = nullptr) {
   if (shape < 0) shape = ku_shape_for(a.g, epi, TOPO_KU_AUTO, std::is_same<T, float>::value);
   if constexpr (std::is_same<T, float>::value) {
     if (shape == kKuShapeMfma || shape == kKuShapeMfmaBf16) return launch_ku_mfma(s, epi, a, shape == kKuShapeMfmaBf16);
@@ -238,6 +238,7 @@ static hipError_t launch_ku_t(hipStream_t s, KuEpi epi, const KuArgsT<T> &a, con
   if (shape >= kKuShapeHada && shape < kKuShapeHada + kKuShapesHada) {
     e = launch_ku_hada<T>(s, epi, a, kap, red, shape - kKuShapeHada, &nparts);
     if (e != hipSuccess) return e;
+    if (defer_parts) return *defer_parts = nparts, hipSuccess;
     if (ku_reduces(epi, a)) return launch_finalize(s, red, nparts, ku_ndot(epi), fin, a.skip);
     return hipSuccess;
   }
@@ -249,13 +250,15 @@ static hipError_t launch_ku_t(hipStream_t s, KuEpi epi, const KuArgsT<T> &a, con
     default: return hipErrorInvalidValue;
   }
   if (e != hipSuccess) return e;
+  if (defer_parts) return *defer_parts = nparts, hipSuccess;
   if (ku_reduces(epi, a)) return launch_finalize(s, red, nparts, ku_ndot(epi), fin, a.skip);
   return hipSuccess;
 }
 
 hipError_t launch_ku(hipStream_t s, KuEpi epi, const KuArgs &a, const Kappa &kap, const Reducer &red,
-                     const Fin &fin, int shape) {
-  return launch_ku_t<double>(s, epi, a, kap, red, fin, shape);
+                     const Fin &fin, int shape, int *defer_parts) {
+  if (defer_parts && (epi != KU_STORE_DOT || a.dot_with)) return hipErrorInvalidValue;
+  return launch_ku_t<double>(s, epi, a, kap, red, fin, shape, defer_parts);
 }
 
 hipError_t launch_ku(hipStream_t s, KuEpi epi, const KuArgsT<float> &a, const KappaT<float> &kap,

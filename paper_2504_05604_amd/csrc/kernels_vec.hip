@@ -131,11 +131,20 @@ hipError_t launch_multi_dot(hipStream_t s, int64_t n, const MultiDotArgs &m, con
 
 // r32 (optional): the new residual rounded to FP32 as well, the right-hand side
 // of a single-precision preconditioner
-__device__ __forceinline__ void cg_update_xr_body(int64_t n, const Scalars *sc, double *x, double *r,
+// pq_parts (optional): p.q as npq block partials, summed here by every block
+__device__ __forceinline__ void cg_update_xr_body(int64_t n, Scalars *sc, double *x, double *r,
                                                   const double *p, const double *q, float *r32,
-                                                  double *partials, const int *skip) {
+                                                  double *partials, const int *skip,
+                                                  const double *pq_parts = nullptr, int npq = 0) {
   if (skipped(skip)) return;
-  const double alpha = sc->rz / sc->pq;
+  double pq;
+  if (pq_parts) {
+    pq = block_sum_partials(pq_parts, npq, 0);
+    if (blockIdx.x == 0 && threadIdx.x == 0) sc->pq = pq;
+  } else {
+    pq = sc->pq;
+  }
+  const double alpha = sc->rz / pq;
   double t = 0.0;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x) {
@@ -149,9 +158,14 @@ __device__ __forceinline__ void cg_update_xr_body(int64_t n, const Scalars *sc, 
   block_reduce_store<1, false>(v, partials, blockIdx.x);
 }
 
-__global__ void cg_update_xr_kernel(int64_t n, const Scalars *sc, double *x, double *r, const double *p,
+__global__ void cg_update_xr_kernel(int64_t n, Scalars *sc, double *x, double *r, const double *p,
                                     const double *q, float *r32, double *partials, const int *skip) {
   cg_update_xr_body(n, sc, x, r, p, q, r32, partials, skip);
+}
+__global__ void cg_update_xr_pq_kernel(int64_t n, Scalars *sc, double *x, double *r, const double *p,
+                                       const double *q, float *r32, double *partials, const int *skip,
+                                       const double *pq_parts, int npq) {
+  cg_update_xr_body(n, sc, x, r, p, q, r32, partials, skip, pq_parts, npq);
 }
 __global__ void cg_update_xr_group_kernel(int64_t n, GroupTab<XrArgs> t, GroupTab<double *> part) {
   const XrArgs &a = t.v[blockIdx.z];
@@ -165,6 +179,21 @@ hipError_t launch_cg_update_xr(hipStream_t s, int64_t n, Scalars *sc, double *x,
   cg_update_xr_kernel<<<nb, kBs, 0, s>>>(n, sc, x, r, p, q, r32, red.partials, skip);
   hipError_t e = hipGetLastError();
   return e != hipSuccess ? e : launch_finalize(s, red, (int)nb, 1, fin, skip);
+}
+
+hipError_t launch_cg_update_xr_pq(hipStream_t s, int64_t n, Scalars *sc, double *x, double *r,
+                                  const double *p, const double *q, const Reducer &red, int npq,
+                                  const Fin &fin, const int *skip, float *r32) {
+  static_assert(kBs == 256, "block_sum_partials reproduces the 256-thread finalize");
+  if (npq < 1 || npq > red.max_blocks) return hipErrorInvalidValue;
+  const unsigned nb = red_blocks(n, red);
+  // r.r into value 1 of each slot: the p.q partials (value 0) stay intact while
+  // other blocks still read them
+  Reducer r1 = red;
+  r1.partials = red.partials + 1;
+  cg_update_xr_pq_kernel<<<nb, kBs, 0, s>>>(n, sc, x, r, p, q, r32, r1.partials, skip, red.partials, npq);
+  hipError_t e = hipGetLastError();
+  return e != hipSuccess ? e : launch_finalize(s, r1, (int)nb, 1, fin, skip);
 }
 
 __device__ __forceinline__ void cg_start_body(Scalars *sc, double rtol2, int max_iters) {

@@ -47,6 +47,28 @@ __device__ void block_reduce_store(double (&v)[N], double *partials, int slot) {
   }
 }
 
+// The sum a one-block finalize of 256 threads forms from value k of nparts
+// partials, in its order (per-thread chains over slots t, t + 256, ..., the
+// wave trees, the waves in order), returned to every thread of the calling
+// block, which must have 256 threads and call it uniformly.
+__device__ __forceinline__ double block_sum_partials(const double *partials, int nparts, int k) {
+  __shared__ double sh[16];
+  __shared__ double total;
+  const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave, nw = blockDim.x / kWave;
+  double t = 0.0;
+  for (int b = threadIdx.x; b < nparts; b += blockDim.x) t = t + partials[(size_t)b * kMaxRed + k];
+  t = wave_reduce<false>(t);
+  if (lane == 0) sh[wid] = t;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double v = sh[0];
+    for (int w = 1; w < nw; ++w) v = v + sh[w];
+    total = v;
+  }
+  __syncthreads();
+  return total;
+}
+
 __device__ __forceinline__ int linear_block() { return blockIdx.x + gridDim.x * blockIdx.y; }
 
 // The dispatcher hands the workgroups of a launch to the 8 XCDs round-robin by

@@ -1210,12 +1210,16 @@ static topo_status cg_body(topo_ctx *ctx, int kind) {
   KuArgs a = ku_args(ctx, L0, ctx->p);
   a.y = ctx->q;
   a.skip = skip;
-  TOPO_HIP(launch_ku(s, KU_STORE_DOT, a, ctx->kap, ctx->red, fin_sum(&ctx->sc->pq), ctx->shape_cg));
+  // p.q stays as block partials, summed by every block of the update (no
+  // finalize launch between the two)
+  int npq = 0;
+  TOPO_HIP(launch_ku(s, KU_STORE_DOT, a, ctx->kap, ctx->red, fin_sum(&ctx->sc->pq), ctx->shape_cg, &npq));
   const Fin check{FIN_CG_CHECK, &ctx->sc->rr, ctx->sc};
   // a single-precision multigrid preconditioner takes the residual in FP32, written
   // by the same pass
   float *r32 = z_single(ctx, kind) ? L0.f32.b : nullptr;
-  TOPO_HIP(launch_cg_update_xr(s, ctx->ndof, ctx->sc, ctx->u, ctx->r, ctx->p, ctx->q, ctx->red, check, skip, r32));
+  TOPO_HIP(launch_cg_update_xr_pq(s, ctx->ndof, ctx->sc, ctx->u, ctx->r, ctx->p, ctx->q, ctx->red, npq, check, skip,
+                                  r32));
   topo_status st = precondition(ctx, kind, skip, r32 != nullptr);
   if (st != TOPO_OK) return st;
   TOPO_HIP(update_p(ctx, kind, 0, skip));
