@@ -68,6 +68,7 @@ struct Scalars {
   int nn_fallback;        // learned preconditioner failed its safeguard test
   double rtol2;           // squared relative tolerance of the running solve
   double rr_start;        // r.r when the running solve started
+  double rz_old;          // r.z as the x/r update found it (read by the fused flexible p update)
   double oc_lam[64];
 };
 
@@ -166,9 +167,10 @@ using KuArgs = KuArgsT<double>;
 // each slot) for the next kernel to sum, and their count is stored here
 hipError_t launch_ku(hipStream_t s, KuEpi epi, const KuArgs &a, const Kappa &kap, const Reducer &red,
                      const Fin &fin, int shape = -1, int *defer_parts = nullptr);
-// single-precision operator (smoothing passes only: no reducing epilogues)
+// single-precision operator (smoothing passes only: no reducing epilogues but
+// RESID_FLEX's, which defer_parts can leave as partials as above)
 hipError_t launch_ku(hipStream_t s, KuEpi epi, const KuArgsT<float> &a, const KappaT<float> &kap,
-                     const Reducer &red, const Fin &fin, int shape = -1);
+                     const Reducer &red, const Fin &fin, int shape = -1, int *defer_parts = nullptr);
 // launch shape by grid size within a K.u kernel family (TOPO_KU_*), for the
 // double- or the single-precision operator
 int ku_shape_for(const Grid &g, KuEpi epi, int family, bool single = false);
@@ -226,6 +228,13 @@ hipError_t launch_cg_update_p(hipStream_t s, int64_t n, Scalars *sc, const doubl
                               int first, const int *skip = nullptr);
 hipError_t launch_cg_update_p(hipStream_t s, int64_t n, Scalars *sc, const float *z, double *p,
                               int first, const int *skip = nullptr);
+// The flexible update with r.z_new and r.z_old still as nrz block partials in
+// red (left by RESID_FLEX with defer_parts): every block sums them in the
+// finalize kernel's order and forms beta = (r.z_new - r.z_old) / sc->rz_old as
+// FIN_RZ_FLEX does from sc->rz (sc->rz_old is the copy the x/r update made of
+// it); block 0 stores the sums in sc->red[0..1], beta and sc->rz = r.z_new.
+hipError_t launch_cg_update_p_flex(hipStream_t s, int64_t n, Scalars *sc, const float *z, double *p,
+                                   const Reducer &red, int nrz, const int *skip = nullptr);
 // Chebyshev first step from x = 0: d = r dinv / theta; x = d; res = r
 hipError_t launch_cheb_first(hipStream_t s, int64_t n, const double *r, const double *dinv,
                              double inv_theta, double *d, double *x, double *res,

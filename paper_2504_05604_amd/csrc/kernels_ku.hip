@@ -262,9 +262,11 @@ hipError_t launch_ku(hipStream_t s, KuEpi epi, const KuArgs &a, const Kappa &kap
 }
 
 hipError_t launch_ku(hipStream_t s, KuEpi epi, const KuArgsT<float> &a, const KappaT<float> &kap,
-                     const Reducer &red, const Fin &fin, int shape) {
+                     const Reducer &red, const Fin &fin, int shape, int *defer_parts) {
   if (epi == KU_STORE_DOT || epi == KU_RESID || a.dot_with) return hipErrorInvalidValue;
-  return launch_ku_t<float>(s, epi, a, kap, red, fin, shape);
+  if (defer_parts && (epi != KU_RESID_FLEX || shape == kKuShapeMfma || shape == kKuShapeMfmaBf16))
+    return hipErrorInvalidValue;
+  return launch_ku_t<float>(s, epi, a, kap, red, fin, shape, defer_parts);
 }
 
 // Grouped K.u (element-column shapes only): one launch for G problems of the

@@ -4,6 +4,8 @@
 // loop has converged every later kernel of a replayed chunk returns at once.
 #include "group_host.h"
 #include "internal.h"
+#include <algorithm>
+
 #include "reduce_dev.h"
 
 namespace topo {
@@ -140,7 +142,10 @@ __device__ __forceinline__ void cg_update_xr_body(int64_t n, Scalars *sc, double
   double pq;
   if (pq_parts) {
     pq = block_sum_partials(pq_parts, npq, 0);
-    if (blockIdx.x == 0 && threadIdx.x == 0) sc->pq = pq;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      sc->pq = pq;
+      sc->rz_old = sc->rz;
+    }
   } else {
     pq = sc->pq;
   }
@@ -258,6 +263,22 @@ __global__ void cg_update_p_kernel(int64_t n, const Scalars *sc, const Z *z, dou
                                    const int *skip) {
   cg_update_p_body<Z>(n, sc, z, p, first, skip);
 }
+__global__ void cg_update_p_flex_kernel(int64_t n, Scalars *sc, const float *z, double *p, const double *parts,
+                                        int nrz, const int *skip) {
+  if (skipped(skip)) return;
+  const double rzn = block_sum_partials(parts, nrz, 0);
+  const double rzo = block_sum_partials(parts, nrz, 1);
+  const double beta = (rzn - rzo) / sc->rz_old;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    sc->red[0] = rzn;
+    sc->red[1] = rzo;
+    sc->beta = beta;
+    sc->rz = rzn;
+  }
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = fma(beta, p[i], (double)z[i]);
+}
 template <typename Z>
 __global__ void cg_update_p_group_kernel(int64_t n, GroupTab<PArgs> t, int first) {
   const PArgs &a = t.v[blockIdx.z];
@@ -272,6 +293,14 @@ hipError_t launch_cg_update_p(hipStream_t s, int64_t n, Scalars *sc, const doubl
 hipError_t launch_cg_update_p(hipStream_t s, int64_t n, Scalars *sc, const float *z, double *p,
                               int first, const int *skip) {
   cg_update_p_kernel<float><<<nblocks(n, 4), kBs, 0, s>>>(n, sc, z, p, first, skip);
+  return hipGetLastError();
+}
+hipError_t launch_cg_update_p_flex(hipStream_t s, int64_t n, Scalars *sc, const float *z, double *p,
+                                   const Reducer &red, int nrz, const int *skip) {
+  if (nrz < 1 || nrz > red.max_blocks) return hipErrorInvalidValue;
+  // a bounded grid: every block sums the partials first
+  const unsigned nb = std::min(nblocks(n, 4), 1024u);
+  cg_update_p_flex_kernel<<<nb, kBs, 0, s>>>(n, sc, z, p, red.partials, nrz, skip);
   return hipGetLastError();
 }
 

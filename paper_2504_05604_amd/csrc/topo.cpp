@@ -1017,6 +1017,7 @@ struct FlexOut {
   float *z;
   const double *r;
   Fin fin;
+  int *defer;  // when set, a pass that forms the dots leaves them as partials (their count here)
 };
 
 // Post-smoothing from the current x (cheb_degree steps).  With dot_with set,
@@ -1048,7 +1049,7 @@ static topo_status post_smooth(topo_ctx *ctx, Level &L, const int *skip, const T
       // flexible-CG dot products itself (res is not needed afterwards)
       a.rflex = flex->r;
       a.zflex = flex->z;
-      TOPO_HIP(launch_ku(s, KU_RESID_FLEX, a, kap, ctx->red, flex->fin, L.shape));
+      TOPO_HIP(launch_ku(s, KU_RESID_FLEX, a, kap, ctx->red, flex->fin, L.shape, flex->defer));
       return TOPO_OK;
     }
   }
@@ -1160,7 +1161,8 @@ static topo_status vcycle(topo_ctx *ctx, size_t l, const int *skip, const Fin *d
 // The learned preconditioner (kind TOPO_PRECOND_LEARNED) maps the residual
 // through the network (its rms comes from rr, formed by the caller) and feeds
 // the flexible update with the safeguard test of FIN_RZ_SAFE.
-static topo_status precondition(topo_ctx *ctx, int kind, const int *skip, bool have_r32 = false) {
+static topo_status precondition(topo_ctx *ctx, int kind, const int *skip, bool have_r32 = false,
+                                int *defer = nullptr) {
   hipStream_t s = ctx->stream;
   Level &L0 = ctx->lv[0];
   const Fin fin{FIN_RZ, &ctx->sc->rz_new, ctx->sc};
@@ -1180,7 +1182,7 @@ static topo_status precondition(topo_ctx *ctx, int kind, const int *skip, bool h
   }
   if (!ctx->mixed) return vcycle<double>(ctx, 0, skip, &fin);
   if (!have_r32) TOPO_HIP(launch_convert(s, ctx->ndof, ctx->r, L0.f32.b, skip));
-  const FlexOut flex{ctx->z32, ctx->r, Fin{FIN_RZ_FLEX, &ctx->sc->red[0], ctx->sc}};
+  const FlexOut flex{ctx->z32, ctx->r, Fin{FIN_RZ_FLEX, &ctx->sc->red[0], ctx->sc}, defer};
   return vcycle<float>(ctx, 0, skip, nullptr, &flex);
 }
 
@@ -1220,9 +1222,13 @@ static topo_status cg_body(topo_ctx *ctx, int kind) {
   float *r32 = z_single(ctx, kind) ? L0.f32.b : nullptr;
   TOPO_HIP(launch_cg_update_xr_pq(s, ctx->ndof, ctx->sc, ctx->u, ctx->r, ctx->p, ctx->q, ctx->red, npq, check, skip,
                                   r32));
-  topo_status st = precondition(ctx, kind, skip, r32 != nullptr);
+  // the flexible dots of a single-precision V-cycle stay as partials where its
+  // last pass forms them, summed by every block of the p update
+  int nrz = 0;
+  topo_status st = precondition(ctx, kind, skip, r32 != nullptr, z_single(ctx, kind) ? &nrz : nullptr);
   if (st != TOPO_OK) return st;
-  TOPO_HIP(update_p(ctx, kind, 0, skip));
+  if (nrz > 0) TOPO_HIP(launch_cg_update_p_flex(s, ctx->ndof, ctx->sc, ctx->z32, ctx->p, ctx->red, nrz, skip));
+  else TOPO_HIP(update_p(ctx, kind, 0, skip));
   return TOPO_OK;
 }
 
