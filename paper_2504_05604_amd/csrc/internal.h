@@ -159,8 +159,17 @@ struct KuArgsT {
   const void *ke16;       // ... and as BF16 [32][32] (zero padded)
   const double *rflex;    // RESID_FLEX: the conjugate-gradient residual (FP64)
   T *zflex;               // RESID_FLEX: the preconditioned residual, read and replaced
+  // RES0 on an element-column shape of 256 threads: CG's r.r as chk_n block
+  // partials (value 0 of each slot); every block first takes the stopping test
+  // of FIN_CG_CHECK on their sum (the x/r update has counted the iteration)
+  // and returns when CG has stopped; block 0 stores r.r and raises cg_done
+  const double *chk_parts;
+  int chk_n;
+  Scalars *chk_sc;
 };
 using KuArgs = KuArgsT<double>;
+// threads per block of element-column shape `which` (relative to kKuShapeHada)
+int ku_hada_block_threads(int which);
 // fin receives the reduction of STORE_DOT / RESID / CHEB with dot_with
 // shape: launch shape index (-1 = chosen from the grid size)
 // defer_parts: no finalize launch; the block partials stay in red (value 0 of
@@ -214,9 +223,13 @@ hipError_t launch_cg_update_xr(hipStream_t s, int64_t n, Scalars *sc, double *x,
 // defer_parts): every block sums them in the finalize kernel's order (so alpha
 // is bit for bit the one of the unfused pair), block 0 stores p.q, and the r.r
 // partials go to value 1 of each slot, apart from the ones being read.
+// defer_rr: no finalize launch either; block 0 counts the iteration, the r.r
+// partials stay at red.partials + 1 and their count is stored here, for a
+// RES0 pass with chk_parts to take the stopping test
 hipError_t launch_cg_update_xr_pq(hipStream_t s, int64_t n, Scalars *sc, double *x, double *r,
                                   const double *p, const double *q, const Reducer &red, int npq,
-                                  const Fin &fin, const int *skip = nullptr, float *r32 = nullptr);
+                                  const Fin &fin, const int *skip = nullptr, float *r32 = nullptr,
+                                  int *defer_rr = nullptr);
 // cg_iters = 0; rtol2, cg_max stored; nn_fallback = 0; cg_done = (rr <= rtol2 ff)
 hipError_t launch_cg_start(hipStream_t s, Scalars *sc, double rtol2, int max_iters);
 // z = r * dinv; fin.out = r.z

@@ -258,6 +258,7 @@ static hipError_t launch_ku_t(hipStream_t s, KuEpi epi, const KuArgsT<T> &a, con
 hipError_t launch_ku(hipStream_t s, KuEpi epi, const KuArgs &a, const Kappa &kap, const Reducer &red,
                      const Fin &fin, int shape, int *defer_parts) {
   if (defer_parts && (epi != KU_STORE_DOT || a.dot_with)) return hipErrorInvalidValue;
+  if (a.chk_parts && !(shape >= kKuShapeHada && shape < kKuShapeHada + kKuShapesHada)) return hipErrorInvalidValue;
   return launch_ku_t<double>(s, epi, a, kap, red, fin, shape, defer_parts);
 }
 
@@ -266,6 +267,8 @@ hipError_t launch_ku(hipStream_t s, KuEpi epi, const KuArgsT<float> &a, const Ka
   if (epi == KU_STORE_DOT || epi == KU_RESID || a.dot_with) return hipErrorInvalidValue;
   if (defer_parts && (epi != KU_RESID_FLEX || shape == kKuShapeMfma || shape == kKuShapeMfmaBf16))
     return hipErrorInvalidValue;
+  // the stopping test rides on element-column shapes only
+  if (a.chk_parts && !(shape >= kKuShapeHada && shape < kKuShapeHada + kKuShapesHada)) return hipErrorInvalidValue;
   return launch_ku_t<float>(s, epi, a, kap, red, fin, shape, defer_parts);
 }
 

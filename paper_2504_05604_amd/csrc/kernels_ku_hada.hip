@@ -37,6 +37,9 @@ template <int EPI, int KZ, int TX, int TY, bool PF, typename T>
 __device__ __forceinline__ void ku_hada_body(const KuArgsT<T> &a, const HadaW<T> &hw, int tiles_x, int tiles_xy,
                                              double *partials) {
   if (a.skip && *a.skip) return;
+  if constexpr (EPI == KU_RES0 && TX * TY == 256) {
+    if (a.chk_parts && cg_stop_in_block(a.chk_parts, a.chk_n, a.chk_sc)) return;
+  }
   constexpr int NT = TX * TY;
   // corner contributions (0,0), (1,0), (0,1) of every thread's element column,
   // double-buffered over node planes so one barrier per plane suffices
@@ -236,6 +239,9 @@ template <int EPI, int KZ, int TX, int TY, typename T>
 __device__ __forceinline__ void ku_hada_lds_body(const KuArgsT<T> &a, const HadaW<T> &hw, int tiles_x,
                                                  int tiles_xy, double *partials) {
   if (a.skip && *a.skip) return;
+  if constexpr (EPI == KU_RES0 && TX * TY == 256) {
+    if (a.chk_parts && cg_stop_in_block(a.chk_parts, a.chk_n, a.chk_sc)) return;
+  }
   constexpr int NT = TX * TY;
   constexpr int NX1 = TX + 1;
   constexpr int NV = NX1 * (TY + 1) * 3;  // values of one node plane of the tile
@@ -510,9 +516,21 @@ static hipError_t launch_hada_shape_group(hipStream_t s, KuEpi epi, int G, const
   X(7, 8, 32, 8, 2)         \
   X(8, 8, 16, 16, 2)
 
+int ku_hada_block_threads(int which) {
+  switch (which) {
+#define TOPO_HADA_THREADS(I, KZ, TX, TY, VAR) \
+  case I: return TX * TY;
+    TOPO_HADA_SHAPES(TOPO_HADA_THREADS)
+#undef TOPO_HADA_THREADS
+    default: return 0;
+  }
+}
+
 template <typename T>
 hipError_t launch_ku_hada(hipStream_t s, KuEpi epi, const KuArgsT<T> &a, const KappaT<T> &kap,
                           const Reducer &red, int which, int *nparts) {
+  if (a.chk_parts && (epi != KU_RES0 || ku_hada_block_threads(which) != 256 || a.chk_n < 1 || !a.chk_sc))
+    return hipErrorInvalidValue;
   switch (which) {
 #define TOPO_HADA_LAUNCH(I, KZ, TX, TY, VAR) \
   case I: return launch_hada_shape<KZ, TX, TY, VAR>(s, epi, a, kap, red, nparts);

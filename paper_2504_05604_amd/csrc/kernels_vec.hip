@@ -137,7 +137,8 @@ hipError_t launch_multi_dot(hipStream_t s, int64_t n, const MultiDotArgs &m, con
 __device__ __forceinline__ void cg_update_xr_body(int64_t n, Scalars *sc, double *x, double *r,
                                                   const double *p, const double *q, float *r32,
                                                   double *partials, const int *skip,
-                                                  const double *pq_parts = nullptr, int npq = 0) {
+                                                  const double *pq_parts = nullptr, int npq = 0,
+                                                  int count_iter = 0) {
   if (skipped(skip)) return;
   double pq;
   if (pq_parts) {
@@ -145,6 +146,7 @@ __device__ __forceinline__ void cg_update_xr_body(int64_t n, Scalars *sc, double
     if (blockIdx.x == 0 && threadIdx.x == 0) {
       sc->pq = pq;
       sc->rz_old = sc->rz;
+      if (count_iter) sc->cg_iters += 1;
     }
   } else {
     pq = sc->pq;
@@ -169,8 +171,8 @@ __global__ void cg_update_xr_kernel(int64_t n, Scalars *sc, double *x, double *r
 }
 __global__ void cg_update_xr_pq_kernel(int64_t n, Scalars *sc, double *x, double *r, const double *p,
                                        const double *q, float *r32, double *partials, const int *skip,
-                                       const double *pq_parts, int npq) {
-  cg_update_xr_body(n, sc, x, r, p, q, r32, partials, skip, pq_parts, npq);
+                                       const double *pq_parts, int npq, int count_iter) {
+  cg_update_xr_body(n, sc, x, r, p, q, r32, partials, skip, pq_parts, npq, count_iter);
 }
 __global__ void cg_update_xr_group_kernel(int64_t n, GroupTab<XrArgs> t, GroupTab<double *> part) {
   const XrArgs &a = t.v[blockIdx.z];
@@ -188,17 +190,21 @@ hipError_t launch_cg_update_xr(hipStream_t s, int64_t n, Scalars *sc, double *x,
 
 hipError_t launch_cg_update_xr_pq(hipStream_t s, int64_t n, Scalars *sc, double *x, double *r,
                                   const double *p, const double *q, const Reducer &red, int npq,
-                                  const Fin &fin, const int *skip, float *r32) {
+                                  const Fin &fin, const int *skip, float *r32, int *defer_rr) {
   static_assert(kBs == 256, "block_sum_partials reproduces the 256-thread finalize");
   if (npq < 1 || npq > red.max_blocks) return hipErrorInvalidValue;
+  if (defer_rr && fin.mode != FIN_CG_CHECK) return hipErrorInvalidValue;
   const unsigned nb = red_blocks(n, red);
   // r.r into value 1 of each slot: the p.q partials (value 0) stay intact while
   // other blocks still read them
   Reducer r1 = red;
   r1.partials = red.partials + 1;
-  cg_update_xr_pq_kernel<<<nb, kBs, 0, s>>>(n, sc, x, r, p, q, r32, r1.partials, skip, red.partials, npq);
+  cg_update_xr_pq_kernel<<<nb, kBs, 0, s>>>(n, sc, x, r, p, q, r32, r1.partials, skip, red.partials, npq,
+                                            defer_rr ? 1 : 0);
   hipError_t e = hipGetLastError();
-  return e != hipSuccess ? e : launch_finalize(s, r1, (int)nb, 1, fin, skip);
+  if (e != hipSuccess) return e;
+  if (defer_rr) return *defer_rr = (int)nb, hipSuccess;
+  return launch_finalize(s, r1, (int)nb, 1, fin, skip);
 }
 
 __device__ __forceinline__ void cg_start_body(Scalars *sc, double rtol2, int max_iters) {

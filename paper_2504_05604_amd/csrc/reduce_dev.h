@@ -71,6 +71,20 @@ __device__ __forceinline__ double block_sum_partials(const double *partials, int
 
 __device__ __forceinline__ int linear_block() { return blockIdx.x + gridDim.x * blockIdx.y; }
 
+// CG's stopping test (FIN_CG_CHECK, the iteration already counted) taken by
+// every block of a 256-thread kernel from the n block partials of r.r; block 0
+// stores r.r and raises cg_done.  Every block reaches the same decision, so a
+// block that reads cg_done before block 0 raises it acts as one reading after.
+__device__ __forceinline__ bool cg_stop_in_block(const double *parts, int n, Scalars *sc) {
+  const double rr = block_sum_partials(parts, n, 0);
+  const bool done = !(rr > sc->rtol2 * sc->ff) || sc->cg_iters >= sc->cg_max;
+  if (linear_block() == 0 && threadIdx.x == 0) {
+    sc->rr = rr;
+    if (done) sc->cg_done = 1;
+  }
+  return done;
+}
+
 // The dispatcher hands the workgroups of a launch to the 8 XCDs round-robin by
 // linear id, and each XCD has its own L2.  xcd_tile maps a workgroup to the tile
 // it processes so that every XCD works through runs of kXcdRun consecutive

@@ -212,6 +212,9 @@ struct topo_ctx {
   hipGraph_t cg_graph[3] = {};
   hipGraphExec_t cg_exec[3] = {};    // chunk of CG iterations, per preconditioner kind
   int cg_prev_iters[3] = {};          // iterations of the last solve, per preconditioner kind
+  // CG's stopping test left to the next finest-level RES0 pass: r.r partials
+  const double *chk_parts = nullptr;
+  int chk_n = 0;
   // learned preconditioner
   int shape_cg = -1;                 // K.u launch shape of the CG product (-1: by grid size)
   size_t tail_start = 0;             // first level of the one-workgroup V-cycle tail (0: none)
@@ -968,6 +971,12 @@ static topo_status pre_smooth(topo_ctx *ctx, Level &L, const int *skip) {
   a.s0 = (T)(1.0 / ch.theta);
   a.skip = skip;
   if (deg == 1) {
+    if (&L == &ctx->lv[0] && ctx->chk_n) {
+      a.chk_parts = ctx->chk_parts;
+      a.chk_n = ctx->chk_n;
+      a.chk_sc = ctx->sc;
+      ctx->chk_n = 0;
+    }
     TOPO_HIP(launch_ku(s, KU_RES0, a, kap, ctx->red, fin_sum(nullptr), L.shape));
     return TOPO_OK;
   }
@@ -1220,12 +1229,27 @@ static topo_status cg_body(topo_ctx *ctx, int kind) {
   // a single-precision multigrid preconditioner takes the residual in FP32, written
   // by the same pass
   float *r32 = z_single(ctx, kind) ? L0.f32.b : nullptr;
+  // where the V-cycle starts with a RES0 pass on a 256-thread element-column
+  // shape, that pass takes the stopping test on the r.r partials itself (no
+  // finalize launch); cg_iters is counted by the update then
+  const bool stop_in_pass = r32 && level_degree(ctx, 0) == 1 && L0.shape >= kKuShapeHada &&
+                            L0.shape < kKuShapeHada + kKuShapesHada &&
+                            ku_hada_block_threads(L0.shape - kKuShapeHada) == 256;
+  int nrr = 0;
   TOPO_HIP(launch_cg_update_xr_pq(s, ctx->ndof, ctx->sc, ctx->u, ctx->r, ctx->p, ctx->q, ctx->red, npq, check, skip,
-                                  r32));
+                                  r32, stop_in_pass ? &nrr : nullptr));
+  if (stop_in_pass) {
+    ctx->chk_parts = ctx->red.partials + 1;
+    ctx->chk_n = nrr;
+  }
   // the flexible dots of a single-precision V-cycle stay as partials where its
   // last pass forms them, summed by every block of the p update
   int nrz = 0;
   topo_status st = precondition(ctx, kind, skip, r32 != nullptr, z_single(ctx, kind) ? &nrz : nullptr);
+  if (ctx->chk_n) {
+    ctx->chk_n = 0;
+    return set_error("internal: the CG stopping test was not taken by the first V-cycle pass"), TOPO_EINVAL;
+  }
   if (st != TOPO_OK) return st;
   if (nrz > 0) TOPO_HIP(launch_cg_update_p_flex(s, ctx->ndof, ctx->sc, ctx->z32, ctx->p, ctx->red, nrz, skip));
   else TOPO_HIP(update_p(ctx, kind, 0, skip));
