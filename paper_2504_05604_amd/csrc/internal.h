@@ -248,6 +248,18 @@ hipError_t launch_cg_update_p(hipStream_t s, int64_t n, Scalars *sc, const float
 // it); block 0 stores the sums in sc->red[0..1], beta and sc->rz = r.z_new.
 hipError_t launch_cg_update_p_flex(hipStream_t s, int64_t n, Scalars *sc, const float *z, double *p,
                                    const Reducer &red, int nrz, const int *skip = nullptr);
+// The same for an FP64 preconditioner: r.z as nrz block partials (left by
+// launch_cheb_last_dot), beta = r.z / sc->rz_old as FIN_RZ forms it; block 0
+// stores sc->rz_new, beta and sc->rz = r.z.
+hipError_t launch_cg_update_p_rz(hipStream_t s, int64_t n, Scalars *sc, const double *z, double *p,
+                                 const Reducer &red, int nrz, const int *skip = nullptr);
+// Degree-1 post-smoothing's update with the V-cycle's r.z: x += res dinv
+// inv_theta, and r.x as block partials in red (value 0 of each slot) in
+// launch_dot's order and grid, so that their sum is bit for bit the one of
+// launch_cheb_start + launch_dot; the count goes to *nparts (no finalize).
+hipError_t launch_cheb_last_dot(hipStream_t s, int64_t n, const double *res, const double *dinv, double inv_theta,
+                                double *x, const double *r, const Reducer &red, int *nparts,
+                                const int *skip = nullptr);
 // Chebyshev first step from x = 0: d = r dinv / theta; x = d; res = r
 hipError_t launch_cheb_first(hipStream_t s, int64_t n, const double *r, const double *dinv,
                              double inv_theta, double *d, double *x, double *res,

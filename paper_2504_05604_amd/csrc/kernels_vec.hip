@@ -301,6 +301,51 @@ hipError_t launch_cg_update_p(hipStream_t s, int64_t n, Scalars *sc, const float
   cg_update_p_kernel<float><<<nblocks(n, 4), kBs, 0, s>>>(n, sc, z, p, first, skip);
   return hipGetLastError();
 }
+__global__ void cg_update_p_rz_kernel(int64_t n, Scalars *sc, const double *z, double *p, const double *parts,
+                                      int nrz, const int *skip) {
+  if (skipped(skip)) return;
+  const double rz = block_sum_partials(parts, nrz, 0);
+  const double beta = rz / sc->rz_old;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    sc->rz_new = rz;
+    sc->beta = beta;
+    sc->rz = rz;
+  }
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = fma(beta, p[i], z[i]);
+}
+hipError_t launch_cg_update_p_rz(hipStream_t s, int64_t n, Scalars *sc, const double *z, double *p,
+                                 const Reducer &red, int nrz, const int *skip) {
+  if (nrz < 1 || nrz > red.max_blocks) return hipErrorInvalidValue;
+  const unsigned nb = std::min(nblocks(n, 4), 1024u);
+  cg_update_p_rz_kernel<<<nb, kBs, 0, s>>>(n, sc, z, p, red.partials, nrz, skip);
+  return hipGetLastError();
+}
+
+__global__ void cheb_last_dot_kernel(int64_t n, const double *res, const double *dinv, double inv_theta, double *x,
+                                     const double *r, double *partials, const int *skip) {
+  if (skipped(skip)) return;
+  double t = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    // x + (res dinv) inv_theta as one fused multiply-add: the form the compiler
+    // gives launch_cheb_start's update
+    const double xi = fma(res[i] * dinv[i], inv_theta, x[i]);
+    x[i] = xi;
+    t = fma(r[i], xi, t);
+  }
+  double v[1] = {t};
+  block_reduce_store<1, false>(v, partials, blockIdx.x);
+}
+hipError_t launch_cheb_last_dot(hipStream_t s, int64_t n, const double *res, const double *dinv, double inv_theta,
+                                double *x, const double *r, const Reducer &red, int *nparts, const int *skip) {
+  const unsigned nb = red_blocks(n, red);
+  cheb_last_dot_kernel<<<nb, kBs, 0, s>>>(n, res, dinv, inv_theta, x, r, red.partials, skip);
+  *nparts = (int)nb;
+  return hipGetLastError();
+}
+
 hipError_t launch_cg_update_p_flex(hipStream_t s, int64_t n, Scalars *sc, const float *z, double *p,
                                    const Reducer &red, int nrz, const int *skip) {
   if (nrz < 1 || nrz > red.max_blocks) return hipErrorInvalidValue;

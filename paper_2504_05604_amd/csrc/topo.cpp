@@ -1035,7 +1035,7 @@ struct FlexOut {
 // products, fused into the last update when the degree is 1.
 template <typename T>
 static topo_status post_smooth(topo_ctx *ctx, Level &L, const int *skip, const T *dot_with,
-                               const Fin &fin, const FlexOut *flex = nullptr) {
+                               const Fin &fin, const FlexOut *flex = nullptr, int *defer_dot = nullptr) {
   hipStream_t s = ctx->stream;
   const int deg = level_degree(ctx, L);
   const Cheb ch(ctx->lam_max);
@@ -1069,6 +1069,15 @@ static topo_status post_smooth(topo_ctx *ctx, Level &L, const int *skip, const T
       if (flex) {
         TOPO_HIP(launch_flex_dot(s, L.g.ndof(), B.res, B.dinv, (T)(1.0 / ch.theta), B.x, flex->r, flex->z,
                                  ctx->red, flex->fin, skip));
+        return TOPO_OK;
+      }
+    }
+    if constexpr (std::is_same<T, double>::value) {
+      if (dot_with && defer_dot) {
+        // the last update and the dot product in one pass, its partials left
+        // for the consumer (no finalize; the unused step is not stored)
+        TOPO_HIP(launch_cheb_last_dot(s, L.g.ndof(), B.res, B.dinv, 1.0 / ch.theta, B.x, dot_with, ctx->red,
+                                      defer_dot, skip));
         return TOPO_OK;
       }
     }
@@ -1136,7 +1145,7 @@ static topo_status vcycle_tail(topo_ctx *ctx, const int *skip) {
 
 template <typename T>
 static topo_status vcycle(topo_ctx *ctx, size_t l, const int *skip, const Fin *dot_fin,
-                          const FlexOut *flex = nullptr) {
+                          const FlexOut *flex = nullptr, int *defer_dot = nullptr) {
   hipStream_t s = ctx->stream;
   Level &L = ctx->lv[l];
   const LevelBufs<T> B = bufs<T>(L);
@@ -1158,7 +1167,8 @@ static topo_status vcycle(topo_ctx *ctx, size_t l, const int *skip, const Fin *d
     if (st != TOPO_OK) return st;
   }
   TOPO_HIP(launch_prolong_add(s, L.g, C.g, BC.x, L.fixed, B.x, skip));
-  return post_smooth<T>(ctx, L, skip, dot_fin ? B.b : nullptr, dot_fin ? *dot_fin : fin_sum(nullptr), flex);
+  return post_smooth<T>(ctx, L, skip, dot_fin ? B.b : nullptr, dot_fin ? *dot_fin : fin_sum(nullptr), flex,
+                        defer_dot);
 }
 
 // z = M r; the r.z finalize sets rz_new, beta = rz_new / rz and rz = rz_new.
@@ -1189,7 +1199,7 @@ static topo_status precondition(topo_ctx *ctx, int kind, const int *skip, bool h
     TOPO_HIP(launch_jacobi(s, ctx->ndof, ctx->r, L0.dinv, ctx->z, ctx->red, fin, skip));
     return TOPO_OK;
   }
-  if (!ctx->mixed) return vcycle<double>(ctx, 0, skip, &fin);
+  if (!ctx->mixed) return vcycle<double>(ctx, 0, skip, &fin, nullptr, defer);
   if (!have_r32) TOPO_HIP(launch_convert(s, ctx->ndof, ctx->r, L0.f32.b, skip));
   const FlexOut flex{ctx->z32, ctx->r, Fin{FIN_RZ_FLEX, &ctx->sc->red[0], ctx->sc}, defer};
   return vcycle<float>(ctx, 0, skip, nullptr, &flex);
@@ -1232,7 +1242,8 @@ static topo_status cg_body(topo_ctx *ctx, int kind) {
   // where the V-cycle starts with a RES0 pass on a 256-thread element-column
   // shape, that pass takes the stopping test on the r.r partials itself (no
   // finalize launch); cg_iters is counted by the update then
-  const bool stop_in_pass = r32 && level_degree(ctx, 0) == 1 && L0.shape >= kKuShapeHada &&
+  const bool stop_in_pass = kind == TOPO_PRECOND_MG && ctx->lv.size() > 1 && level_degree(ctx, 0) == 1 &&
+                            L0.shape >= kKuShapeHada &&
                             L0.shape < kKuShapeHada + kKuShapesHada &&
                             ku_hada_block_threads(L0.shape - kKuShapeHada) == 256;
   int nrr = 0;
@@ -1242,17 +1253,21 @@ static topo_status cg_body(topo_ctx *ctx, int kind) {
     ctx->chk_parts = ctx->red.partials + 1;
     ctx->chk_n = nrr;
   }
-  // the flexible dots of a single-precision V-cycle stay as partials where its
-  // last pass forms them, summed by every block of the p update
+  // r.z (or the flexible pair of a single-precision V-cycle) stays as partials
+  // where the V-cycle's last pass forms it, summed by every block of the p update
   int nrz = 0;
-  topo_status st = precondition(ctx, kind, skip, r32 != nullptr, z_single(ctx, kind) ? &nrz : nullptr);
+  topo_status st = precondition(ctx, kind, skip, r32 != nullptr, kind == TOPO_PRECOND_MG ? &nrz : nullptr);
   if (ctx->chk_n) {
     ctx->chk_n = 0;
     return set_error("internal: the CG stopping test was not taken by the first V-cycle pass"), TOPO_EINVAL;
   }
   if (st != TOPO_OK) return st;
-  if (nrz > 0) TOPO_HIP(launch_cg_update_p_flex(s, ctx->ndof, ctx->sc, ctx->z32, ctx->p, ctx->red, nrz, skip));
-  else TOPO_HIP(update_p(ctx, kind, 0, skip));
+  if (nrz > 0 && z_single(ctx, kind))
+    TOPO_HIP(launch_cg_update_p_flex(s, ctx->ndof, ctx->sc, ctx->z32, ctx->p, ctx->red, nrz, skip));
+  else if (nrz > 0)
+    TOPO_HIP(launch_cg_update_p_rz(s, ctx->ndof, ctx->sc, ctx->z, ctx->p, ctx->red, nrz, skip));
+  else
+    TOPO_HIP(update_p(ctx, kind, 0, skip));
   return TOPO_OK;
 }
 
