@@ -632,7 +632,7 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--ku-reps", type=int, default=100)
     ap.add_argument("--coarse-dof", type=int, default=1500, help="coarsest multigrid level size cap")
-    ap.add_argument("--check-every", type=int, default=4)
+    ap.add_argument("--check-every", type=int, default=3)
     ap.add_argument("--no-graphs", action="store_true")
     ap.add_argument("--precision", choices=["fp64", "fp32", "bf16"], default="fp32",
                     help="precision of the multigrid preconditioner (CG stays FP64)")

@@ -122,8 +122,9 @@ typedef struct {
                                  the combination of the last 4 solutions closest to the
                                  new solution in the new operator's energy norm          */
   double oc_tol;              /* relative width of the final multiplier bracket        */
-  int32_t check_every;        /* CG iterations per host convergence check (the device
-                                 stops iterating at convergence within a chunk)         */
+  int32_t check_every;        /* CG iterations per chunk; the host checks convergence
+                                 after one or more chunks (the device stops iterating
+                                 at convergence within a chunk)                        */
   int32_t use_graphs;         /* replay chunks of CG iterations from a captured HIP graph */
   int32_t nn_max_iters;       /* LEARNED: flexible-CG iterations before the solve restarts
                                  on the multigrid preconditioner                       */
@@ -200,7 +201,7 @@ typedef struct {
 /* Fills *opts with defaults: FP64, MG, automatic depth (coarsest <= 1500 dofs),
  * Chebyshev degree 1 on the finest level and 4 below (cheb_degree_coarse),
  * rtol 1e-8, max_iters 1000, projected warm start (3), oc_tol 1e-12,
- * check_every 4, use_graphs 1, nn_max_iters 200, autotune 0, coarse_tail_nodes 0,
+ * check_every 3, use_graphs 1, nn_max_iters 200, autotune 0, coarse_tail_nodes 0,
  * mfma_smoothing 0, ku_kernel TOPO_KU_AUTO, ku_shape -1, coarse_refresh 1,
  * cheb_degree_level all 0, group_launch 1, cheb_upper 1. */
 void topo_default_opts(topo_opts *opts);

@@ -277,7 +277,7 @@ extern "C" void topo_default_opts(topo_opts *o) {
   o->max_iters = 1000;
   o->warm_start = 3;
   o->oc_tol = 1e-12;
-  o->check_every = 4;
+  o->check_every = 3;
   o->use_graphs = 1;
   o->nn_max_iters = 200;
   o->autotune = 0;
