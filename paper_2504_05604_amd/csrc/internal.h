@@ -378,9 +378,10 @@ template <class A>
 struct GroupTab {
   A v[kMaxGroup];
 };
+// defer_parts (STORE_DOT, RESID_FLEX): no finalize, as for launch_ku
 template <typename T>
 hipError_t launch_ku_group(hipStream_t s, KuEpi epi, int G, const KuArgsT<T> *a, const KappaT<T> &kap,
-                           const Reducer *red, const Fin *fin, int shape);
+                           const Reducer *red, const Fin *fin, int shape, int *defer_parts = nullptr);
 // finalize of G reductions of nparts partials each (partials of red[i], skip[i])
 hipError_t launch_finalize_group(hipStream_t s, int G, const Reducer *red, int nparts, int n, const Fin *fin,
                                  const int *const *skip);
@@ -393,13 +394,20 @@ struct XrArgs {
 };
 hipError_t launch_cg_update_xr_group(hipStream_t s, int G, int64_t n, const XrArgs *a, const Reducer *red,
                                      const Fin *fin);
+// launch_cg_update_xr_pq for each problem of a group (p.q as npq partials in
+// red[i], r.r to value 1 of each slot and its finalize)
+hipError_t launch_cg_update_xr_group_pq(hipStream_t s, int G, int64_t n, const XrArgs *a, const Reducer *red,
+                                        int npq, const Fin *fin);
 struct PArgs {
-  const Scalars *sc;
+  Scalars *sc;
   const void *z;  // double, or float when zsingle
   double *p;
   const int *skip;
 };
 hipError_t launch_cg_update_p_group(hipStream_t s, int G, int64_t n, bool zsingle, const PArgs *a, int first);
+// launch_cg_update_p_flex for each problem of a group (z in single precision)
+hipError_t launch_cg_update_p_flex_group(hipStream_t s, int G, int64_t n, const PArgs *a, const Reducer *red,
+                                         int nrz);
 struct FlexArgs {
   const float *res, *dinv, *x;
   const double *r;

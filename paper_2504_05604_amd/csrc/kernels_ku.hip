@@ -276,15 +276,17 @@ hipError_t launch_ku(hipStream_t s, KuEpi epi, const KuArgsT<float> &a, const Ka
 // same grid, each reducing into its own partials and finalize.
 template <typename T>
 hipError_t launch_ku_group(hipStream_t s, KuEpi epi, int G, const KuArgsT<T> *a, const KappaT<T> &kap,
-                           const Reducer *red, const Fin *fin, int shape) {
+                           const Reducer *red, const Fin *fin, int shape, int *defer_parts) {
   if (G < 1 || G > kMaxGroup) return hipErrorInvalidValue;
   if (shape < kKuShapeHada || shape >= kKuShapeHada + kKuShapesHada) return hipErrorInvalidValue;
   if constexpr (std::is_same<T, float>::value) {
     if (epi == KU_STORE_DOT || epi == KU_RESID) return hipErrorInvalidValue;
   }
   int nparts = 0;
+  if (defer_parts && epi != KU_STORE_DOT && epi != KU_RESID_FLEX) return hipErrorInvalidValue;
   hipError_t e = launch_ku_hada_group<T>(s, epi, G, a, kap, red, shape - kKuShapeHada, &nparts);
   if (e != hipSuccess) return e;
+  if (defer_parts) return *defer_parts = nparts, hipSuccess;
   if (!ku_reduces(epi, a[0])) return hipSuccess;
   Fin f[kMaxGroup];
   const int *sk[kMaxGroup];
@@ -295,9 +297,9 @@ hipError_t launch_ku_group(hipStream_t s, KuEpi epi, int G, const KuArgsT<T> *a,
   return launch_finalize_group(s, G, red, nparts, ku_ndot(epi), f, sk);
 }
 template hipError_t launch_ku_group<double>(hipStream_t, KuEpi, int, const KuArgsT<double> *, const KappaT<double> &,
-                                            const Reducer *, const Fin *, int);
+                                            const Reducer *, const Fin *, int, int *);
 template hipError_t launch_ku_group<float>(hipStream_t, KuEpi, int, const KuArgsT<float> *, const KappaT<float> &,
-                                           const Reducer *, const Fin *, int);
+                                           const Reducer *, const Fin *, int, int *);
 
 // ---------------------------------------------------------------------------
 // Sums the block partials in block order.  Besides writing the sum, a finalize

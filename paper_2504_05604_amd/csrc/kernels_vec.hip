@@ -178,6 +178,12 @@ __global__ void cg_update_xr_group_kernel(int64_t n, GroupTab<XrArgs> t, GroupTa
   const XrArgs &a = t.v[blockIdx.z];
   cg_update_xr_body(n, a.sc, a.x, a.r, a.p, a.q, a.r32, part.v[blockIdx.z], a.skip);
 }
+// p.q partials at value 0 of the member's slots, r.r to value 1
+__global__ void cg_update_xr_group_pq_kernel(int64_t n, GroupTab<XrArgs> t, GroupTab<double *> part, int npq) {
+  const XrArgs &a = t.v[blockIdx.z];
+  double *pp = part.v[blockIdx.z];
+  cg_update_xr_body(n, a.sc, a.x, a.r, a.p, a.q, a.r32, pp + 1, a.skip, pp, npq, 0);
+}
 
 hipError_t launch_cg_update_xr(hipStream_t s, int64_t n, Scalars *sc, double *x, double *r,
                                const double *p, const double *q, const Reducer &red, const Fin &fin,
@@ -269,8 +275,8 @@ __global__ void cg_update_p_kernel(int64_t n, const Scalars *sc, const Z *z, dou
                                    const int *skip) {
   cg_update_p_body<Z>(n, sc, z, p, first, skip);
 }
-__global__ void cg_update_p_flex_kernel(int64_t n, Scalars *sc, const float *z, double *p, const double *parts,
-                                        int nrz, const int *skip) {
+__device__ __forceinline__ void cg_update_p_flex_body(int64_t n, Scalars *sc, const float *z, double *p,
+                                                      const double *parts, int nrz, const int *skip) {
   if (skipped(skip)) return;
   const double rzn = block_sum_partials(parts, nrz, 0);
   const double rzo = block_sum_partials(parts, nrz, 1);
@@ -284,6 +290,14 @@ __global__ void cg_update_p_flex_kernel(int64_t n, Scalars *sc, const float *z, 
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x)
     p[i] = fma(beta, p[i], (double)z[i]);
+}
+__global__ void cg_update_p_flex_kernel(int64_t n, Scalars *sc, const float *z, double *p, const double *parts,
+                                        int nrz, const int *skip) {
+  cg_update_p_flex_body(n, sc, z, p, parts, nrz, skip);
+}
+__global__ void cg_update_p_flex_group_kernel(int64_t n, GroupTab<PArgs> t, GroupTab<double *> part, int nrz) {
+  const PArgs &a = t.v[blockIdx.z];
+  cg_update_p_flex_body(n, a.sc, static_cast<const float *>(a.z), a.p, part.v[blockIdx.z], nrz, a.skip);
 }
 template <typename Z>
 __global__ void cg_update_p_group_kernel(int64_t n, GroupTab<PArgs> t, int first) {
@@ -544,6 +558,33 @@ hipError_t launch_cg_update_xr_group(hipStream_t s, int G, int64_t n, const XrAr
   if (e != hipSuccess) return e;
   const GroupTab<const int *> sk = group_skips(G, a);
   return launch_finalize_group(s, G, red, (int)nb, 1, fin, sk.v);
+}
+
+hipError_t launch_cg_update_xr_group_pq(hipStream_t s, int G, int64_t n, const XrArgs *a, const Reducer *red,
+                                        int npq, const Fin *fin) {
+  if (!group_ok(G) || npq < 1) return hipErrorInvalidValue;
+  Reducer r1[kMaxGroup];
+  for (int i = 0; i < G; ++i) {
+    if (npq > red[i].max_blocks) return hipErrorInvalidValue;
+    r1[i] = red[i];
+    r1[i].partials = red[i].partials + 1;
+  }
+  const unsigned nb = red_blocks(n, red[0]);
+  cg_update_xr_group_pq_kernel<<<dim3(nb, 1, G), kBs, 0, s>>>(n, group_tab(G, a), group_partials(G, red), npq);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const GroupTab<const int *> sk = group_skips(G, a);
+  return launch_finalize_group(s, G, r1, (int)nb, 1, fin, sk.v);
+}
+
+hipError_t launch_cg_update_p_flex_group(hipStream_t s, int G, int64_t n, const PArgs *a, const Reducer *red,
+                                         int nrz) {
+  if (!group_ok(G) || nrz < 1) return hipErrorInvalidValue;
+  for (int i = 0; i < G; ++i)
+    if (nrz > red[i].max_blocks) return hipErrorInvalidValue;
+  const unsigned nb = std::min(nblocks(n, 4), 1024u);
+  cg_update_p_flex_group_kernel<<<dim3(nb, 1, G), kBs, 0, s>>>(n, group_tab(G, a), group_partials(G, red), nrz);
+  return hipGetLastError();
 }
 
 hipError_t launch_cg_update_p_group(hipStream_t s, int G, int64_t n, bool zsingle, const PArgs *a, int first) {

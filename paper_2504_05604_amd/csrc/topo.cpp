@@ -1550,7 +1550,7 @@ static topo_status group_pre_smooth(const Group &G, size_t l) {
 // precision through flex_dot into z32 (flexible update), in double with the
 // r.z reduction of the last pass (FIN_RZ)
 template <typename T>
-static topo_status group_post_smooth(const Group &G, size_t l, bool finest) {
+static topo_status group_post_smooth(const Group &G, size_t l, bool finest, int *defer = nullptr) {
   const int n = G.n();
   topo_ctx *c0 = G.c[0];
   const int deg = level_degree(c0, l);
@@ -1585,7 +1585,7 @@ static topo_status group_post_smooth(const Group &G, size_t l, bool finest) {
         a[i].rflex = G.c[i]->r;
         a[i].zflex = G.c[i]->z32;
       }
-      TOPO_HIP(launch_ku_group<T>(G.s, KU_RESID_FLEX, n, a.data(), kap, red.data(), flexfin.data(), shape));
+      TOPO_HIP(launch_ku_group<T>(G.s, KU_RESID_FLEX, n, a.data(), kap, red.data(), flexfin.data(), shape, defer));
       return TOPO_OK;
     }
   }
@@ -1654,8 +1654,10 @@ static topo_status group_post_smooth(const Group &G, size_t l, bool finest) {
   return TOPO_OK;
 }
 
+// defer: where the finest level's last pass forms the flexible-CG dots, they
+// stay as partials (their count there) for the grouped p update
 template <typename T>
-static topo_status group_vcycle(const Group &G, size_t l) {
+static topo_status group_vcycle(const Group &G, size_t l, int *defer = nullptr) {
   const int n = G.n();
   topo_ctx *c0 = G.c[0];
   if (l + 1 == c0->lv.size()) {
@@ -1692,7 +1694,7 @@ static topo_status group_vcycle(const Group &G, size_t l) {
     t[i] = TransferArgs<T>{bufs<T>(C).x, L.fixed, bufs<T>(L).x, &G.c[i]->sc->cg_done};
   }
   TOPO_HIP(launch_prolong_add_group<T>(G.s, n, c0->lv[l].g, c0->lv[l + 1].g, t.data()));
-  return group_post_smooth<T>(G, l, l == 0);
+  return group_post_smooth<T>(G, l, l == 0, l == 0 ? defer : nullptr);
 }
 
 static topo_status group_update_p(const Group &G, int first) {
@@ -1727,11 +1729,25 @@ static topo_status group_cg_body(const Group &G) {
     fchk[i] = Fin{FIN_CG_CHECK, &c->sc->rr, c->sc};
     xr[i] = XrArgs{c->sc, c->u, c->r, c->p, c->q, c->mixed ? c->lv[0].f32.b : nullptr, &c->sc->cg_done};
   }
-  TOPO_HIP(launch_ku_group<double>(G.s, KU_STORE_DOT, n, a.data(), c0->kap, red.data(), fpq.data(), c0->shape_cg));
-  TOPO_HIP(launch_cg_update_xr_group(G.s, n, c0->ndof, xr.data(), red.data(), fchk.data()));
-  topo_status st = group_precondition(G);
+  // p.q summed by every block of the update, and in mixed precision the
+  // flexible dots by every block of the p update (as cg_body does)
+  int npq = 0;
+  TOPO_HIP(launch_ku_group<double>(G.s, KU_STORE_DOT, n, a.data(), c0->kap, red.data(), fpq.data(), c0->shape_cg,
+                                   &npq));
+  TOPO_HIP(launch_cg_update_xr_group_pq(G.s, n, c0->ndof, xr.data(), red.data(), npq, fchk.data()));
+  if (!c0->mixed) {
+    topo_status st = group_vcycle<double>(G, 0);
+    if (st != TOPO_OK) return st;
+    return group_update_p(G, 0);
+  }
+  int nrz = 0;
+  topo_status st = group_vcycle<float>(G, 0, &nrz);
   if (st != TOPO_OK) return st;
-  return group_update_p(G, 0);
+  if (nrz < 1) return group_update_p(G, 0);
+  std::vector<PArgs> pa(n);
+  for (int i = 0; i < n; ++i) pa[i] = PArgs{G.c[i]->sc, G.c[i]->z32, G.c[i]->p, &G.c[i]->sc->cg_done};
+  TOPO_HIP(launch_cg_update_p_flex_group(G.s, n, c0->ndof, pa.data(), red.data(), nrz));
+  return TOPO_OK;
 }
 
 // the scalars of every problem of the group into their pinned mirrors, one wait
