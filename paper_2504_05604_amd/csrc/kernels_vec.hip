@@ -140,17 +140,6 @@ __device__ __forceinline__ void cg_update_xr_body(int64_t n, Scalars *sc, double
                                                   const double *pq_parts = nullptr, int npq = 0,
                                                   int count_iter = 0) {
   if (skipped(skip)) return;
-  // the first element's operands are requested before the scalars are formed,
-  // so that their latency overlaps the partial sums
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  double x0 = 0.0, p0 = 0.0, q0 = 0.0, r0 = 0.0;
-  if (i < n) {
-    x0 = x[i];
-    p0 = p[i];
-    q0 = q[i];
-    r0 = r[i];
-  }
   double pq;
   if (pq_parts) {
     pq = block_sum_partials(pq_parts, npq, 0);
@@ -164,15 +153,8 @@ __device__ __forceinline__ void cg_update_xr_body(int64_t n, Scalars *sc, double
   }
   const double alpha = sc->rz / pq;
   double t = 0.0;
-  if (i < n) {
-    x[i] = fma(alpha, p0, x0);
-    const double ri = fma(-alpha, q0, r0);
-    r[i] = ri;
-    if (r32) r32[i] = (float)ri;
-    t = fma(ri, ri, t);
-    i += stride;
-  }
-  for (; i < n; i += stride) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
     x[i] = fma(alpha, p[i], x[i]);
     const double ri = fma(-alpha, q[i], r[i]);
     r[i] = ri;
@@ -296,15 +278,6 @@ __global__ void cg_update_p_kernel(int64_t n, const Scalars *sc, const Z *z, dou
 __device__ __forceinline__ void cg_update_p_flex_body(int64_t n, Scalars *sc, const float *z, double *p,
                                                       const double *parts, int nrz, const int *skip) {
   if (skipped(skip)) return;
-  // the first element's operands requested before the partial sums (latency overlap)
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  float z0 = 0.f;
-  double p0 = 0.0;
-  if (i < n) {
-    z0 = z[i];
-    p0 = p[i];
-  }
   const double rzn = block_sum_partials(parts, nrz, 0);
   const double rzo = block_sum_partials(parts, nrz, 1);
   const double beta = (rzn - rzo) / sc->rz_old;
@@ -314,11 +287,9 @@ __device__ __forceinline__ void cg_update_p_flex_body(int64_t n, Scalars *sc, co
     sc->beta = beta;
     sc->rz = rzn;
   }
-  if (i < n) {
-    p[i] = fma(beta, p0, (double)z0);
-    i += stride;
-  }
-  for (; i < n; i += stride) p[i] = fma(beta, p[i], (double)z[i]);
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = fma(beta, p[i], (double)z[i]);
 }
 __global__ void cg_update_p_flex_kernel(int64_t n, Scalars *sc, const float *z, double *p, const double *parts,
                                         int nrz, const int *skip) {
@@ -347,14 +318,6 @@ hipError_t launch_cg_update_p(hipStream_t s, int64_t n, Scalars *sc, const float
 __global__ void cg_update_p_rz_kernel(int64_t n, Scalars *sc, const double *z, double *p, const double *parts,
                                       int nrz, const int *skip) {
   if (skipped(skip)) return;
-  // the first element's operands requested before the partial sums (latency overlap)
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  double z0 = 0.0, p0 = 0.0;
-  if (i < n) {
-    z0 = z[i];
-    p0 = p[i];
-  }
   const double rz = block_sum_partials(parts, nrz, 0);
   const double beta = rz / sc->rz_old;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -362,11 +325,9 @@ __global__ void cg_update_p_rz_kernel(int64_t n, Scalars *sc, const double *z, d
     sc->beta = beta;
     sc->rz = rz;
   }
-  if (i < n) {
-    p[i] = fma(beta, p0, z0);
-    i += stride;
-  }
-  for (; i < n; i += stride) p[i] = fma(beta, p[i], z[i]);
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = fma(beta, p[i], z[i]);
 }
 hipError_t launch_cg_update_p_rz(hipStream_t s, int64_t n, Scalars *sc, const double *z, double *p,
                                  const Reducer &red, int nrz, const int *skip) {
