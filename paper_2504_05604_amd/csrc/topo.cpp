@@ -209,6 +209,11 @@ struct topo_ctx {
   Reducer red{};
   int have_u = 0;
   hipStream_t cap_stream = nullptr;  // private stream for graph capture
+  // the coarse inverse of a SIMP iteration, built on a stream of its own while
+  // the warm start and the start of the solve run; joined before the V-cycle
+  hipStream_t side = nullptr;
+  hipEvent_t side_ev[2] = {};
+  bool inv_pending = false;
   hipGraph_t cg_graph[3] = {};
   hipGraphExec_t cg_exec[3] = {};    // chunk of CG iterations, per preconditioner kind
   int cg_prev_iters[3] = {};          // iterations of the last solve, per preconditioner kind
@@ -248,6 +253,12 @@ struct topo_ctx {
     drop_graphs();
     nnw.release();
     if (cap_stream) (void)hipStreamDestroy(cap_stream);
+    if (side) {
+      (void)hipStreamSynchronize(side);
+      (void)hipStreamDestroy(side);
+    }
+    for (hipEvent_t e : side_ev)
+      if (e) (void)hipEventDestroy(e);
     for (void *a : allocs) (void)hipFree(a);
     if (h_sc) (void)hipHostFree(h_sc);
   }
@@ -909,8 +920,21 @@ static topo_status autotune_timed(topo_ctx *ctx) {
 
 // level-0 modulus from xphys, then the coarse moduli, diagonals and (unless the
 // previous one is kept) the coarse inverse
-static topo_status prepare_operator(topo_ctx *ctx, const double *d_xphys, bool refresh_coarse = true) {
+// The context's stream waits for a coarse inverse still being built on the side stream.
+static topo_status join_inverse(topo_ctx *ctx) {
+  if (!ctx->inv_pending) return TOPO_OK;
+  ctx->inv_pending = false;
+  TOPO_HIP(hipStreamWaitEvent(ctx->stream, ctx->side_ev[1], 0));
+  return TOPO_OK;
+}
+
+// overlap_inverse: the coarse inverse goes to the side stream and is joined by
+// join_inverse (pcg_run does so before its first V-cycle)
+static topo_status prepare_operator(topo_ctx *ctx, const double *d_xphys, bool refresh_coarse = true,
+                                    bool overlap_inverse = false) {
   hipStream_t s = ctx->stream;
+  topo_status js = join_inverse(ctx);
+  if (js != TOPO_OK) return js;
   const topo_problem &P = ctx->prob;
   // in mixed precision every kernel also writes the single-precision copy
   const bool m = ctx->mixed;
@@ -923,8 +947,23 @@ static topo_status prepare_operator(topo_ctx *ctx, const double *d_xphys, bool r
   }
   if (ctx->lv.size() > 1 && refresh_coarse) {
     const Level &C = ctx->lv.back();
-    TOPO_HIP(launch_dense_assemble(s, C.g, C.E, ctx->kap, C.fixed, ctx->Ainv));
-    TOPO_HIP(launch_dense_invert(s, ctx->ncoarse, ctx->Ainv, ctx->Awork));
+    hipStream_t si = s;
+    if (overlap_inverse) {
+      if (!ctx->side) {
+        TOPO_HIP(hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking));
+        for (hipEvent_t &e : ctx->side_ev) TOPO_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+      }
+      // after the coarsest moduli (and everything before them on the stream)
+      TOPO_HIP(hipEventRecord(ctx->side_ev[0], s));
+      TOPO_HIP(hipStreamWaitEvent(ctx->side, ctx->side_ev[0], 0));
+      si = ctx->side;
+    }
+    TOPO_HIP(launch_dense_assemble(si, C.g, C.E, ctx->kap, C.fixed, ctx->Ainv));
+    TOPO_HIP(launch_dense_invert(si, ctx->ncoarse, ctx->Ainv, ctx->Awork));
+    if (overlap_inverse) {
+      TOPO_HIP(hipEventRecord(ctx->side_ev[1], ctx->side));
+      ctx->inv_pending = true;
+    }
   }
   // a direct call leaves a fresh inverse; the SIMP loop counts from here
   ctx->coarse_due = refresh_coarse ? ctx->opts.coarse_refresh : ctx->coarse_due;
@@ -1359,7 +1398,10 @@ static topo_status pcg_run(topo_ctx *ctx, int kind, int max_iters) {
   if (z_single(ctx, kind)) TOPO_HIP(hipMemsetAsync(ctx->z32, 0, n * sizeof(float), s));
   else if (kind == TOPO_PRECOND_LEARNED || ctx->mixed) TOPO_HIP(hipMemsetAsync(ctx->z, 0, n * sizeof(double), s));
   // first direction (skipped on the device when already converged)
-  topo_status st = precondition(ctx, kind, &ctx->sc->cg_done);
+  // the coarse inverse of this SIMP iteration may still be in the making
+  topo_status st = join_inverse(ctx);
+  if (st != TOPO_OK) return st;
+  st = precondition(ctx, kind, &ctx->sc->cg_done);
   if (st != TOPO_OK) return st;
   TOPO_HIP(update_p(ctx, kind, 1, &ctx->sc->cg_done));
   // with the previous solve's count as a guide the first chunks go in at once
@@ -1767,6 +1809,11 @@ topo_status group_pcg(Group &G, hipGraph_t *graph_out, hipGraphExec_t *exec, hip
   const int n = G.n();
   for (topo_ctx *c : G.c)
     if (c->stream != G.s) return set_error("grouped CG: the contexts must use the group's stream"), TOPO_EINVAL;
+  // coarse inverses that iterate_pre left on the members' side streams
+  for (topo_ctx *c : G.c) {
+    const topo_status js = join_inverse(c);
+    if (js != TOPO_OK) return js;
+  }
   // r = f - K u, rr, ff and the stopping test of every member (the launches of
   // pcg_run's start, shared by the group)
   {
@@ -2033,7 +2080,7 @@ topo_status iterate_pre(topo_ctx *ctx, double *d_x, hipEvent_t *ev) {
   // the coarse inverse is recomputed every coarse_refresh SIMP iterations; in
   // between the previous one (still SPD) preconditions the coarsest level
   const bool refresh = ctx->coarse_due <= 0;
-  topo_status st = prepare_operator(ctx, ctx->xphys, refresh);
+  topo_status st = prepare_operator(ctx, ctx->xphys, refresh, true);
   --ctx->coarse_due;
   if (st == TOPO_OK && ctx->opts.warm_start == 3 && ctx->nbasis > 0) st = projected_start(ctx);
   return st;
