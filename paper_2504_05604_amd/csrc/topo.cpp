@@ -928,6 +928,25 @@ static topo_status join_inverse(topo_ctx *ctx) {
   return TOPO_OK;
 }
 
+// The side stream of ctx (created on first use) set to start after everything
+// enqueued on s so far; side_end marks the work enqueued on it since as the
+// pending coarse inverse.
+static topo_status side_begin(topo_ctx *ctx, hipStream_t s, hipStream_t *side) {
+  if (!ctx->side) {
+    TOPO_HIP(hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking));
+    for (hipEvent_t &e : ctx->side_ev) TOPO_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  }
+  TOPO_HIP(hipEventRecord(ctx->side_ev[0], s));
+  TOPO_HIP(hipStreamWaitEvent(ctx->side, ctx->side_ev[0], 0));
+  *side = ctx->side;
+  return TOPO_OK;
+}
+static topo_status side_end(topo_ctx *ctx) {
+  TOPO_HIP(hipEventRecord(ctx->side_ev[1], ctx->side));
+  ctx->inv_pending = true;
+  return TOPO_OK;
+}
+
 // overlap_inverse: the coarse inverse goes to the side stream and is joined by
 // join_inverse (pcg_run does so before its first V-cycle)
 static topo_status prepare_operator(topo_ctx *ctx, const double *d_xphys, bool refresh_coarse = true,
@@ -949,20 +968,15 @@ static topo_status prepare_operator(topo_ctx *ctx, const double *d_xphys, bool r
     const Level &C = ctx->lv.back();
     hipStream_t si = s;
     if (overlap_inverse) {
-      if (!ctx->side) {
-        TOPO_HIP(hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking));
-        for (hipEvent_t &e : ctx->side_ev) TOPO_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
-      }
       // after the coarsest moduli (and everything before them on the stream)
-      TOPO_HIP(hipEventRecord(ctx->side_ev[0], s));
-      TOPO_HIP(hipStreamWaitEvent(ctx->side, ctx->side_ev[0], 0));
-      si = ctx->side;
+      const topo_status ss = side_begin(ctx, s, &si);
+      if (ss != TOPO_OK) return ss;
     }
     TOPO_HIP(launch_dense_assemble(si, C.g, C.E, ctx->kap, C.fixed, ctx->Ainv));
     TOPO_HIP(launch_dense_invert(si, ctx->ncoarse, ctx->Ainv, ctx->Awork));
     if (overlap_inverse) {
-      TOPO_HIP(hipEventRecord(ctx->side_ev[1], ctx->side));
-      ctx->inv_pending = true;
+      const topo_status se = side_end(ctx);
+      if (se != TOPO_OK) return se;
     }
   }
   // a direct call leaves a fresh inverse; the SIMP loop counts from here
@@ -2189,10 +2203,16 @@ static topo_status group_filter(const Group &G, const std::vector<int> &op, cons
 }
 
 // prepare_operator for every member
+// The grouped coarse inverse goes to the first member's side stream (joined by
+// group_pcg before the first V-cycle).
 static topo_status group_prepare_operator(const Group &G, bool refresh) {
   const int n = G.n();
   topo_ctx *c0 = G.c[0];
   hipStream_t s = G.s;
+  for (topo_ctx *c : G.c) {
+    const topo_status js = join_inverse(c);
+    if (js != TOPO_OK) return js;
+  }
   std::vector<ModulusArgs> ma(n);
   for (int i = 0; i < n; ++i) {
     const topo_problem &P = G.c[i]->prob;
@@ -2223,8 +2243,13 @@ static topo_status group_prepare_operator(const Group &G, bool refresh) {
       A[i] = G.c[i]->Ainv;
       W[i] = G.c[i]->Awork;
     }
-    TOPO_HIP(launch_dense_assemble_group(s, n, c0->lv.back().g, aa.data()));
-    TOPO_HIP(launch_dense_invert_group(s, n, c0->ncoarse, A.data(), W.data()));
+    hipStream_t si = s;
+    const topo_status ss = side_begin(c0, s, &si);
+    if (ss != TOPO_OK) return ss;
+    TOPO_HIP(launch_dense_assemble_group(si, n, c0->lv.back().g, aa.data()));
+    TOPO_HIP(launch_dense_invert_group(si, n, c0->ncoarse, A.data(), W.data()));
+    const topo_status se = side_end(c0);
+    if (se != TOPO_OK) return se;
   }
   for (topo_ctx *c : G.c) c->coarse_due = refresh ? c->opts.coarse_refresh : c->coarse_due;
   return TOPO_OK;
